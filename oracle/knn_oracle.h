@@ -1,0 +1,98 @@
+/*
+ * knn_oracle.h -- plain, slow, single-threaded CPU oracle for adaptive
+ * k-NN (LeJeune, Baraniuk, Heckel, "Adaptive Estimation for Approximate
+ * k-Nearest-Neighbor Computations", AISTATS 2019).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product
+ * library (libknn) never links, loads or calls it, and it shares no code
+ * with the product: its own Philox, its own confidence bounds, its own
+ * schedule, its own selection, all written from the paper.
+ *
+ * Precision: integer sums in int64, every bound in IEEE double with no
+ * fused multiply-add (built with -ffp-contract=off), natural logarithms.
+ */
+#ifndef KNN_ORACLE_H
+#define KNN_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_U8 = 0, ORC_F32 = 1 };
+
+/* Result-defining parameters of one query (same field order and meaning as
+ * the product's parameter struct, so one Python object can fill both). */
+typedef struct {
+  int64_t  h;           /* slack; < 0 means h = k */
+  double   delta;       /* failure probability, (0,1) */
+  uint64_t seed;        /* Philox key */
+  int32_t  alpha_kind;  /* 0 footnote beta, 1 Lemma-3 beta, 2 experimental C_alpha */
+  double   c_alpha;     /* only for alpha_kind 2 */
+  int32_t  b0;          /* samples per point in round 0 (multiple of 4); 0 -> 64 */
+  float    growth;      /* T grows by max(4, ceil4(T*(g-1))) per round; 0 -> 2 */
+  float    theta_exact; /* go exact once the next target reaches ceil(theta*m); 0 -> 1 */
+  int32_t  c_exact;     /* candidate-exact count (0 = pure round form) */
+} orc_params;
+
+typedef struct {
+  int64_t coord_evals;  /* coordinate evaluations: samples + m per exact point */
+  int32_t rounds;       /* decide steps executed */
+  int32_t count;        /* returned set size */
+  int64_t exact_points; /* points whose distance was computed exactly */
+} orc_stats;
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+ * Philox S-box keyed by a Weyl sequence. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Raw 32-bit draw for sample t of point i under seed: output t mod 4 of
+ * Philox4x32-10 with key = (seed lo, seed hi), counter = (t/4, 0, i, 0). */
+uint32_t orc_draw(uint64_t seed, int64_t i, int64_t t);
+
+/* Coordinate index of that sample: floor(draw * m / 2^32). */
+int64_t orc_index(uint64_t seed, int64_t i, int64_t t, int64_t m);
+
+/* Confidence width alpha(u) of Section 4 (footnote form, kind 0), of
+ * Lemma 3 (kind 1) or of the experiments section (kind 2). Kind 0 falls
+ * back to kind 1 when delta/n >= 0.05.  Returns NaN on invalid input. */
+double orc_alpha(int32_t kind, int64_t u, int64_t n, double delta, double c_alpha);
+
+/* Round schedule: fills T[0..R-1] with the cumulative sample targets of the
+ * sampled rounds; round R is the exact round.  Returns R, or -1 if the
+ * schedule would exceed maxlen rounds or the parameters are invalid. */
+int32_t orc_schedule(int32_t b0, float growth, float theta, int64_t m,
+                     int32_t *T, int32_t maxlen);
+
+/* Fixed-point scaling for float data: W (samples s/W lie in [0,1]) and the
+ * shift F; for u8 W = 255^2 and F = 0.  Returns 0 ok, 1 degenerate (zero
+ * range), <0 invalid. */
+int32_t orc_scaling(const void *X, int64_t n, int64_t m, int32_t dtype,
+                    const void *q, double *W, int32_t *F);
+
+/* Adaptive k-NN, round-synchronous form of Algorithm 1.
+ * out_idx: [k+h] (padded with -1).  stop_after > 0 stops after that many
+ * decide steps without finalising (for state comparison); the per-point
+ * state is then written to S_dump / fl_dump / ri_dump when non-NULL.
+ * Returns 0 ok, <0 invalid arguments. */
+int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
+                     const void *q, int32_t k, const orc_params *p,
+                     int32_t stop_after, int64_t *out_idx, orc_stats *st,
+                     int64_t *S_dump, uint8_t *fl_dump, uint8_t *ri_dump);
+
+/* Naive brute force of Section 3: all distances, k smallest by (d, index).
+ * u8: exact int64 sums; f32: double sums in coordinate order.
+ * out_dist receives the unnormalised squared distances. */
+int32_t orc_naive(const void *X, int64_t n, int64_t m, int32_t dtype,
+                  const void *q, int32_t k, int64_t *out_idx, double *out_dist);
+
+/* Exact squared distance of one point (unnormalised), as the naive scan
+ * computes it. */
+double orc_exact_dist(const void *X, int64_t n, int64_t m, int32_t dtype,
+                      const void *q, int64_t i);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

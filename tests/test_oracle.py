@@ -1,0 +1,380 @@
+"""Pins for the CPU oracle: each test ties it to something other than its
+own code -- published known-answer vectors, an independent RNG library, a
+worked example derived from the paper's bound, brute force, Lemma 3's
+coverage guarantee (with a negative control), Appendix A's explicit sample
+bound, Theorem 1's miss rate and Theorem 2's lower bound."""
+from __future__ import annotations
+
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+from scipy import stats as sps
+
+from knn_inputs import antipodal, coherent, pm_half, tiny, uniform_u8, rng
+from tests.helpers import brute_dists, contains_knn
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- Philox
+
+
+def test_philox_known_answers(orc):
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = orc.philox(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+def test_draw_matches_rocrand_engine(orc):
+    """The draw for sample t of point i is rocRAND's Philox4x32-10
+    engine(seed, subsequence=i, offset=t).next(); compiled from rocRAND's
+    header-only engine as an independent implementation."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand"):
+        pytest.skip("rocRAND headers / hipcc not available")
+    g = rng(11)
+    triples = [(0, 0, 0), (1, 2, 3), (2**64 - 1, 7, 1000001)]
+    for _ in range(200):
+        triples.append((int(g.integers(0, 2**63)), int(g.integers(0, 2**21)),
+                        int(g.integers(0, 2**20))))
+    with tempfile.TemporaryDirectory() as td:
+        exe = os.path.join(td, "probe")
+        subprocess.check_call([hipcc, "-O1", "-I/opt/rocm/include",
+                               os.path.join(GOLDEN, "rocrand_philox_probe.cpp"), "-o", exe],
+                              stderr=subprocess.DEVNULL)
+        inp = "".join(f"{s} {i} {t}\n" for s, i, t in triples)
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    ref = [int(x) for x in out.split()]
+    mine = [orc.draw(s, i, t) for s, i, t in triples]
+    assert mine == ref
+
+
+@pytest.mark.parametrize("m", [256, 3072])
+def test_index_uniform_chi_square(orc, m):
+    counts = np.zeros(m, dtype=np.int64)
+    N = 200 * m if m <= 256 else 100 * m
+    for t in range(N):
+        counts[orc.index(99, t % 97, t, m)] += 1
+    chi2, p = sps.chisquare(counts)
+    assert p > 1e-4, (chi2, p)
+
+
+# ---------------------------------------------------------------- alpha
+
+
+def test_alpha_monotone_and_lil_growth(orc):
+    us = np.arange(1, 4097)
+    a = np.array([orc.alpha(0, int(u), 2000, 0.01) for u in us])
+    assert np.all(np.isfinite(a)) and np.all(a > 0)
+    assert np.all(np.diff(a) < 0), "alpha must shrink with more samples"
+    # sqrt(u) alpha(u) grows like sqrt(log log u): nondecreasing, sublinear.
+    g = a * np.sqrt(us)
+    assert np.all(np.diff(g) >= -1e-12)
+    assert g[-1] / g[0] < 1.5
+
+
+def test_alpha_footnote_falls_back_to_lemma(orc):
+    # delta/n = 0.9 > 1/e would make 3 log log(1/delta') negative; the
+    # Lemma 3 form (valid for all delta) must be used instead.
+    a0 = orc.alpha(0, 100, 1, 0.9)
+    a1 = orc.alpha(1, 100, 1, 0.9)
+    assert a0 == a1 and a0 > 0
+    # far below 0.05 the two forms differ
+    assert orc.alpha(0, 100, 1000, 0.01) != orc.alpha(1, 100, 1000, 0.01)
+    assert math.isnan(orc.alpha(0, 0, 10, 0.1))
+    assert math.isnan(orc.alpha(0, 5, 10, 1.5))
+
+
+@pytest.mark.parametrize("kind,delta,shrink,expect_ok", [
+    (0, 0.04, 1.0, True), (1, 0.2, 1.0, True), (0, 0.04, 0.2, False)])
+def test_alpha_anytime_coverage(orc, kind, delta, shrink, expect_ok):
+    """Lemma 3: for one arm (n = 1, delta' = delta) of i.i.d. [0,1] samples,
+    |d^(t) - d| <= alpha(t) for all t at once with probability >= 1 - delta.
+    A band shrunk by 5x must fail that (negative control: the test has power)."""
+    g = rng(5 + kind)
+    trials, tmax, p = 4000, 1500, 0.3
+    t = np.arange(1, tmax + 1)
+    a = np.array([orc.alpha(kind, int(u), 1, delta) for u in t]) * shrink
+    bad = 0
+    for s in range(0, trials, 500):
+        x = (g.random((500, tmax)) < p).astype(np.float64)
+        est = np.cumsum(x, axis=1) / t
+        bad += int(np.any(np.abs(est - p) > a, axis=1).sum())
+    rate = bad / trials
+    if expect_ok:
+        assert rate <= delta, rate
+    else:
+        assert rate > 5 * delta, rate
+
+
+@pytest.mark.parametrize("gap", [0.9, 0.5, 0.2, 0.05])
+def test_fact6_sample_bound(orc, gap):
+    """Appendix A (proof of Fact 6) with the Lemma 3 constants: the smallest u
+    with alpha(u) <= gap/8 is at most
+      c2 / gap^2 * log(125 (n/delta) log(1.12 * 128 / gap^2)),
+    c2 = c1 + 1, c1 = 128 / (1 - 2 / log(1.12 * 32))."""
+    n, delta = 1000, 0.01
+    c1 = 128.0 / (1.0 - 2.0 / math.log(1.12 * 32.0))
+    bound = (c1 + 1.0) / gap**2 * math.log(125.0 * n / delta * math.log(1.12 * 128.0 / gap**2))
+    # smallest u by doubling then bisection on the monotone alpha
+    hi = 1
+    while orc.alpha(1, hi, n, delta) > gap / 8:
+        hi *= 2
+    lo = hi // 2
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if orc.alpha(1, mid, n, delta) <= gap / 8:
+            hi = mid
+        else:
+            lo = mid
+    assert hi <= bound
+    assert hi >= 0.05 * bound  # same order: the bound is not vacuous
+
+
+# ---------------------------------------------------------------- schedule
+
+
+def test_schedule(orc):
+    assert list(orc.schedule(64, 2.0, 1.0, 3072)) == [64, 128, 256, 512, 1024, 2048]
+    assert list(orc.schedule(64, 2.0, 1.0, 256)) == [64, 128]
+    assert list(orc.schedule(256, 2.0, 1.0, 256)) == []
+    assert list(orc.schedule(8, 1.5, 1.0, 40)) == [8, 12, 20, 32]
+    assert list(orc.schedule(0, 0.0, 0.0, 3072)) == [64, 128, 256, 512, 1024, 2048]
+    assert list(orc.schedule(64, 2.0, 0.5, 3072)) == [64, 128, 256, 512, 1024]
+    with pytest.raises(ValueError):
+        orc.schedule(62, 2.0, 1.0, 3072)
+    with pytest.raises(ValueError):
+        orc.schedule(4, 1.0, 1.0, 1 << 20)  # too many rounds
+
+
+# ---------------------------------------------------------------- estimator
+
+
+def test_exact_at_m_u8(orc):
+    """Algorithm 1: once a point is made exact, d^ = d.  With B0 >= m every
+    point is exact at once; S must equal the brute-force sum."""
+    X, Q = uniform_u8(3, 300, 64)
+    p = orc.make_params(b0=64)
+    _, st, (S, fl, _) = orc.adaptive(X, Q[0], 5, p, stop_after=1, dump=True)
+    assert np.array_equal(S, brute_dists(X, Q[0]))
+    assert np.all(fl & 1)
+    assert st["coord_evals"] == 300 * 64 and st["exact_points"] == 300
+
+
+def test_exact_at_m_f32(orc):
+    g = rng(4)
+    X = g.standard_normal((200, 48)).astype(np.float32)
+    q = g.standard_normal((48,)).astype(np.float32)
+    rc, W, F = orc.scaling(X, q)
+    assert rc == 0 and 30 < F < 62
+    _, _, (S, fl, _) = orc.adaptive(X, q, 3, orc.make_params(b0=48), stop_after=1, dump=True)
+    d = brute_dists(X, q)
+    lo, hi = min(X.min(), q.min()), max(X.max(), q.max())
+    Rp = (float(hi) - float(lo)) ** 2 * (1 + 2**-20)
+    est = S / (48 * W)
+    ref = d / (48 * Rp)
+    # fixed-point truncation and fp32 rounding of (x - q)^2 only
+    assert np.max(np.abs(est - ref) / ref) < 1e-6
+    assert np.all(est <= 1.0)
+
+
+def test_unbiased_estimator(orc):
+    """Lemma 3's premise: E d^(T) = d (uniform draws, Section 4)."""
+    X, Q = uniform_u8(8, 200, 128)
+    d = brute_dists(X, Q[0]) / (128 * 65025.0)
+    est = []
+    for seed in range(300):
+        _, _, (S, _, _) = orc.adaptive(X, Q[0], 5, orc.make_params(seed=seed), stop_after=1, dump=True)
+        est.append(S / (64 * 65025.0))
+    est = np.array(est)
+    se = est.std(axis=0, ddof=1) / np.sqrt(est.shape[0])
+    z = (est.mean(axis=0) - d) / se
+    assert np.max(np.abs(z)) < 5.0
+    assert abs(z.mean() * np.sqrt(len(z))) < 4.0
+
+
+# ---------------------------------------------------------------- algorithm
+
+
+def test_worked_example_pure(orc):
+    """RNG-free example from the paper's bound: 5 copies of the query (every
+    sample 0) among 995 antipodes (every sample 1), n = 1000, m = 1024,
+    delta = 0.01, k = h = 5.  alpha(64) = 0.816 and alpha(128) = 0.580
+    exceed 1/2, so nothing is decided; alpha(256) = 0.411 < 1/2, so at T = 256
+    every antipode has LCB 0.589 > U = 0.411 and is discarded, and the copies
+    (UCB 0.411 <= L2 = 0.589) are accepted: 1000 * 256 evaluations."""
+    X, Q, where = antipodal()
+    assert orc.alpha(0, 64, 1000, 0.01) > 0.5 and orc.alpha(0, 128, 1000, 0.01) > 0.5
+    assert orc.alpha(0, 256, 1000, 0.01) < 0.5
+    idx, st = orc.adaptive(X, Q[0], 5, orc.make_params(h=5, delta=0.01, seed=123))
+    assert sorted(idx.tolist()) == where.tolist()
+    assert st == dict(coord_evals=256_000, rounds=3, count=5, exact_points=0)
+
+
+def test_worked_example_candidate_exact(orc):
+    """Same instance with the 10 smallest estimates made exact after round 0:
+    U = 0 (five exact copies), every antipode has LCB >= 1 - 0.816 > 0 and is
+    discarded at T = 64: 64,000 + 10 * 1024 evaluations."""
+    X, Q, where = antipodal()
+    idx, st = orc.adaptive(X, Q[0], 5, orc.make_params(h=5, delta=0.01, seed=9, c_exact=10))
+    assert sorted(idx.tolist()) == where.tolist()
+    assert st == dict(coord_evals=74_240, rounds=1, count=5, exact_points=10)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_contains_knn_bruteforce(orc, seed):
+    g = rng(100 + seed)
+    n, m = int(g.integers(50, 400)), int(g.choice([16, 64, 200, 256]))
+    k = int(g.integers(1, 8))
+    h = int(g.integers(0, 6))
+    X, Q, _ = tiny(seed=200 + seed, n=n, m=m, planted=max(1, k), noise=int(g.integers(1, 40)))
+    for c_exact in (0, k + h):
+        p = orc.make_params(h=h, delta=0.05, seed=seed, b0=4 * int(g.integers(1, 9)),
+                            growth=float(g.choice([1.5, 2.0, 3.0])), c_exact=c_exact)
+        idx, st = orc.adaptive(X, Q[0], k, p)
+        assert len(idx) <= k + h and len(set(idx.tolist())) == len(idx)
+        assert contains_knn(idx, brute_dists(X, Q[0]), k)
+        assert st["coord_evals"] <= n * (2 * m + 4)
+
+
+def test_ties_everywhere(orc):
+    """All points identical: every distance ties; any k+h points are valid."""
+    X = np.full((100, 32), 7, dtype=np.uint8)
+    q = np.full((32,), 9, dtype=np.uint8)
+    idx, st = orc.adaptive(X, q, 4, orc.make_params(h=2))
+    assert len(idx) == 6 and contains_knn(idx, brute_dists(X, q), 4)
+
+
+def test_small_n_returns_all(orc):
+    X, Q = uniform_u8(1, 7, 16)
+    idx, st = orc.adaptive(X, Q[0], 4, orc.make_params(h=3))
+    assert idx.tolist() == list(range(7)) and st["coord_evals"] == 0
+
+
+def test_invalid_args(orc):
+    X, Q = uniform_u8(1, 20, 16)
+    with pytest.raises(ValueError):
+        orc.adaptive(X, Q[0], 0)
+    with pytest.raises(ValueError):
+        orc.adaptive(X, Q[0], 3, orc.make_params(delta=0.0))
+    with pytest.raises(ValueError):
+        orc.adaptive(X, Q[0], 3, orc.make_params(b0=6))
+    with pytest.raises(ValueError):
+        orc.adaptive(X, Q[0], 3, orc.make_params(alpha_kind=2, c_alpha=0.0))
+
+
+def _miss_instance(seed, n=600, m=1024):
+    g = rng(seed)
+    d = np.concatenate([g.uniform(0.10, 0.14, 5), g.uniform(0.145, 0.25, 30),
+                        g.uniform(0.35, 0.65, n - 35)])
+    X, Q, flips = pm_half(seed, n, m, d)
+    return X, Q, flips
+
+
+def _miss_count(orc, seeds, params_fn, m=1024):
+    misses, evals = 0, []
+    for s in seeds:
+        X, Q, flips = _miss_instance(s, m=m)
+        idx, st = orc.adaptive(X, Q[0], 5, params_fn(s))
+        misses += 0 if contains_knn(idx, flips.astype(np.int64), 5) else 1
+        evals.append(st["coord_evals"])
+    return misses, np.array(evals)
+
+
+def test_miss_rate_within_delta(orc):
+    """Theorem 1: the returned set misses a nearest neighbour with
+    probability <= delta.  Instances are decided before the exact round
+    (candidate-exact on), so the bound is what keeps them right."""
+    delta, N = 0.01, 1000
+    misses, evals = _miss_count(
+        orc, range(N), lambda s: orc.make_params(h=5, delta=delta, seed=10_000 + s, c_exact=10))
+    limit = sps.binom.ppf(0.999, N, delta)
+    assert misses <= limit, misses
+    assert np.median(evals) < 600 * 1024  # decisions really happen before exact
+
+
+def test_miss_rate_negative_control(orc):
+    """A width far below the paper's (experimental form, tiny C_alpha) must
+    produce misses on the same instances: the test above has power."""
+    misses, _ = _miss_count(
+        orc, range(200), lambda s: orc.make_params(h=5, delta=0.01, seed=s, alpha_kind=2,
+                                                   c_alpha=1e-4))
+    assert misses >= 20, misses
+
+
+def test_miss_rate_pure_form(orc):
+    delta, N = 0.05, 150
+    misses, evals = _miss_count(
+        orc, range(N), lambda s: orc.make_params(h=5, delta=delta, seed=s), m=4096)
+    assert misses <= sps.binom.ppf(0.999, N, delta)
+    assert np.median(evals) < 600 * 4096
+
+
+def test_theorem2_lower_bound(orc):
+    """Theorem 2 on +-1/2 data (h < k, delta <= 0.14): expected coordinate
+    evaluations of any correct sampling algorithm are at least
+    c' (sum_{i<=k-h} D_{i,k+1+h}^-2 + sum_{i>=k+1+h} D_{k-h,i}^-2)."""
+    k, h, delta, n, m = 5, 2, 0.05, 300, 1024
+    tot, runs = 0, 40
+    for s in range(runs):
+        g = rng(700 + s)
+        dists = np.sort(np.concatenate([g.uniform(0.05, 0.15, 8), g.uniform(0.3, 0.6, n - 8)]))
+        X, Q, flips = pm_half(700 + s, n, m, dists)
+        d = np.sort(flips / m)
+        idx, st = orc.adaptive(X, Q[0], k, orc.make_params(h=h, delta=delta, seed=s, c_exact=k + h))
+        assert contains_knn(idx, flips.astype(np.int64), k)
+        cprime = math.log(1 / (2 * delta)) * min(d[k - h - 1] * (1 - d[k - h - 1]),
+                                                  d[k + h] * (1 - d[k + h]))
+        nlow = cprime * (sum((d[i] - d[k + h]) ** -2.0 for i in range(k - h)) +
+                         sum((d[k - h - 1] - d[i]) ** -2.0 for i in range(k + h, n)))
+        assert st["coord_evals"] >= nlow
+        tot += st["coord_evals"]
+
+
+def test_coherent_no_savings(orc):
+    """Section 4.2: all mass on one coordinate -- sampling cannot resolve the
+    distances before nearly all coordinates are read."""
+    X, Q = coherent(5, 400, 512)
+    idx, st = orc.adaptive(X, Q[0], 5, orc.make_params(h=5, seed=1))
+    assert contains_knn(idx, brute_dists(X, Q[0]), 5)
+    assert st["coord_evals"] >= 400 * 512
+
+
+# ---------------------------------------------------------------- naive
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_naive_matches_numpy(orc, dtype):
+    g = rng(21)
+    if dtype == "u8":
+        X = g.integers(0, 4, size=(500, 24), dtype=np.uint8)  # many ties
+        q = g.integers(0, 4, size=(24,), dtype=np.uint8)
+    else:
+        X = g.standard_normal((500, 24)).astype(np.float32)
+        q = g.standard_normal((24,)).astype(np.float32)
+    d = brute_dists(X, q)
+    ref = np.lexsort((np.arange(500), d))[:17]
+    idx, dist = orc.naive(X, q, 17)
+    assert idx.tolist() == ref.tolist()
+    if dtype == "u8":
+        assert np.array_equal(dist, d[ref].astype(np.float64))
+    else:  # numpy sums pairwise, the oracle in coordinate order
+        assert np.allclose(dist, d[ref], rtol=1e-12, atol=0)
+
+
+def test_f32_adaptive_contains(orc):
+    g = rng(31)
+    for s in range(6):
+        X = g.standard_normal((300, 40)).astype(np.float32)
+        q = X[g.integers(0, 300)] + 0.05 * g.standard_normal(40).astype(np.float32)
+        idx, _ = orc.adaptive(X, q, 3, orc.make_params(h=3, seed=s, b0=8, c_exact=s % 2 * 6))
+        assert contains_knn(idx, brute_dists(X, q), 3, rtol=1e-6)
