@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark: adaptive k-NN (LeJeune, Baraniuk, Heckel, AISTATS 2019) against
+the naive MFMA scan on one MI355X.
+
+Workload (batched integer): n = 100,000 points, m = 3072 dims, uint8 from a
+32-component Gaussian mixture (centres uniform in [0,255], sigma 30, rounded
+and clipped), 1,024 queries from the same mixture, k = 10, h = 10,
+delta = 0.01, all inputs resident in HBM before the timed region.
+
+One step = one adaptive k-NN pass over the whole batch of 1,024 queries
+(every stage: sampling, bounds, selection, decisions, compaction, output).
+A query counts only when its returned set contains the true k nearest
+neighbours (tie-aware, against the exact int8-MFMA scan computed before the
+timed region).  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "k-NN queries/s adaptive vs naive MFMA (true k-NN contained), p50/p99 latency"
+N, M, NQ, K, H, DELTA = 100_000, 3072, 1024, 10, 10, 0.01
+HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0
+VALU_PEAK_TOPS = 39.3  # 256 CU x 64 lanes x 2.4 GHz, 32-bit VALU ops (one per lane per cycle)
+# algorithmic 32-bit ops per sample: Philox4x32-10 share 20 (10 rounds x (2 mul_lo + 2 mul_hi
+# + 4 xor) / 4 samples), index 1, address 2, difference 1, square 1, 64-bit accumulate 2
+OPS_PER_SAMPLE = 27
+OPS_PER_EXACT_ELEM = 4  # difference, square, 64-bit accumulate
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def load_lib():
+    import paper_1902_09465_amd as P
+    try:
+        P.lib()
+    except ImportError:
+        from paper_1902_09465_amd import build
+        build.build()
+        P.lib()
+    return P
+
+
+def contained(idx, cnt, X_t, Q_t, nidx, ndist, k):
+    """Per query: does the returned set contain a k-NN set (tie-aware)?"""
+    import torch
+    nq = idx.shape[0]
+    dk = ndist[:, k - 1]  # exact k-th distance
+    ok = torch.zeros(nq, dtype=torch.bool, device=idx.device)
+    valid = idx >= 0
+    safe = torch.where(valid, idx, torch.zeros_like(idx))
+    pts = X_t[safe.reshape(-1)].reshape(nq, idx.shape[1], -1).to(torch.int32)
+    d = ((pts - Q_t[:, None, :].to(torch.int32)) ** 2).sum(-1).to(torch.float64)
+    d = torch.where(valid, d, torch.full_like(d, float("inf")))
+    n_le = (d <= dk[:, None]).sum(1)
+    strict = ndist < dk[:, None]  # neighbours strictly closer than d_(k)
+    member = (nidx[:, :, None] == idx[:, None, :]).any(-1)
+    ok = (~strict | member).all(1) & (n_le >= k)
+    return ok
+
+
+def _oracle_worker(args):
+    X, q, k, h, delta, seed = args
+    import oracle
+    t0 = time.perf_counter()
+    idx, st = oracle.adaptive(X, q, k, oracle.make_params(h=h, delta=delta, seed=seed))
+    return time.perf_counter() - t0, st["coord_evals"]
+
+
+def cpu_baseline(X, Q, seconds_hint):
+    """The oracle, untuned, on this host's cores: one query per process."""
+    import oracle
+    oracle.build()
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    nqs = cores
+    jobs = [(X, Q[i], K, H, DELTA, 12345) for i in range(nqs)]
+    t0 = time.perf_counter()
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    per_q = [r[0] for r in res]
+    return {"value": nqs / wall, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nqs} queries of the same workload, one per process ({cores} processes), "
+                      f"single-threaded C oracle each; wall {wall:.1f} s, median per-query "
+                      f"{np.median(per_q):.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures a single MI355X "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py is single-GPU; do not launch it with several ranks", file=sys.stderr)
+        return 2
+    import torch
+    from knn_inputs import gmm_u8
+
+    P = load_lib()
+    lib = P.lib()
+    import ctypes
+
+    log("generating inputs")
+    X, Q = gmm_u8(2000, n=N, m=M, n_centres=32, sigma=30.0, nq=NQ)
+    X_t = torch.from_numpy(X).cuda()
+    Q_t = torch.from_numpy(Q).cuda()
+    db = P.KnnDB(X_t)
+    params = P.default_params(h=H, delta=DELTA, seed=12345)
+    torch.cuda.synchronize()
+
+    log("exact reference (int8 MFMA naive scan)")
+    nidx, ndist = db.naive(Q_t, K)
+    torch.cuda.synchronize()
+
+    # ---------------- adaptive: warmup, then exactly `steps` timed steps
+    for w in range(args.warmup):
+        log(f"adaptive warmup {w + 1}/{args.warmup}")
+        db.adaptive(Q_t, K, params, with_stats=False)
+    torch.cuda.synchronize()
+    P._lib.check(lib.knn_prof_enable(1))
+    step_ms = []
+    ok_counts = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for s in range(args.steps):
+        t0 = time.perf_counter()
+        idx, cnt, _ = db.adaptive(Q_t, K, params, with_stats=False)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+        log(f"adaptive step {s + 1}/{args.steps}: {step_ms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t_all
+    # containment and statistics (outside the timed region)
+    ok = contained(idx, cnt, X_t, Q_t, nidx, ndist, K)
+    n_ok = int(ok.sum().item())
+    prof = {}
+    for kind, name in enumerate(["sample", "cand", "select", "decide", "finish"]):
+        ms, n_l, u = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        P._lib.check(lib.knn_prof_read(kind, ctypes.byref(ms), ctypes.byref(n_l), ctypes.byref(u)))
+        prof[name] = dict(ms=ms.value, launches=n_l.value)
+    cnts = np.zeros(4, dtype=np.uint64)
+    P._lib.check(lib.knn_prof_counters(cnts.ctypes.data_as(ctypes.c_void_p)))
+    P._lib.check(lib.knn_prof_enable(0))
+    _, _, stats = db.adaptive(Q_t, K, params, with_stats=True)
+    torch.cuda.synchronize()
+    evals = stats["coord_evals"].astype(np.float64)
+
+    ms_per_step = total_s * 1e3 / args.steps
+    value = n_ok / (ms_per_step / 1e3)
+
+    # dominant kernel of the step and its roofline (per-launch averages over the timed steps)
+    dom = max(prof, key=lambda k_: prof[k_]["ms"])
+    samp = prof["sample"]
+    samples, exact_elems, alg_bytes = float(cnts[1]), float(cnts[2]), float(cnts[0])
+    ops = samples * OPS_PER_SAMPLE + exact_elems * OPS_PER_EXACT_ELEM
+    avg_s = samp["ms"] / max(1, samp["launches"]) / 1e3
+    ops_per_launch = ops / max(1, samp["launches"])
+    achieved = ops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
+    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_sample",
+                "avg_launch_ms": avg_s * 1e3, "launches": samp["launches"],
+                "alg_bytes_per_launch": alg_bytes / max(1, samp["launches"]),
+                "hbm_frac_alg_bytes": (alg_bytes / max(1, samp["launches"]) / avg_s / 1e9) / HBM_PEAK_GBS
+                if avg_s > 0 else 0.0}
+
+    # ---------------- naive MFMA scan, same batch
+    for w in range(args.warmup):
+        db.naive(Q_t, K, with_dist=False)
+    torch.cuda.synchronize()
+    P._lib.check(lib.knn_prof_enable(1))
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        db.naive(Q_t, K, with_dist=False)
+    torch.cuda.synchronize()
+    naive_s = (time.perf_counter() - t0) / args.steps
+    ms, n_l, u = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    P._lib.check(lib.knn_prof_read(5, ctypes.byref(ms), ctypes.byref(n_l), ctypes.byref(u)))
+    P._lib.check(lib.knn_prof_enable(0))
+    gemm_avg_s = ms.value / max(1, n_l.value) / 1e3
+    naive_tops = (u.value / max(1, n_l.value)) / gemm_avg_s / 1e12 if gemm_avg_s > 0 else 0.0
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "batched_int: n=100000 points x m=3072 uint8, 32-centre Gaussian mixture "
+                               "sigma=30, 1024 queries, k=10 h=10 delta=0.01, footnote width, B0=64, g=2",
+                   "global_batch": NQ, "seq_len": M, "parallelism": "single GPU"},
+        "contained": f"{n_ok}/{NQ}",
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                       "note": "whole-batch latency per step (all 1024 queries finish together)"},
+        "coord_evals_per_query": float(evals.mean()),
+        "fraction_of_naive_evals": float(evals.mean() / (N * M)),
+        "naive": {"queries_per_s": NQ / naive_s, "ms_per_batch": naive_s * 1e3,
+                  "mfma_int8_tops": naive_tops, "mfma_frac": naive_tops / INT8_PEAK_TOPS},
+        "adaptive_vs_naive": (value / (NQ / naive_s)) if naive_s > 0 else None,
+        "kernels_ms_per_step": {k_: v["ms"] / args.steps for k_, v in prof.items()},
+        "dominant_kernel": dom,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on host cores)")
+        out["cpu_baseline"] = cpu_baseline(X, Q, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    db.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,202 @@
+/*
+ * knn.h -- C ABI of libknn: adaptive k-nearest-neighbour search on MI355X
+ * (gfx950), after LeJeune, Baraniuk, Heckel, "Adaptive Estimation for
+ * Approximate k-Nearest-Neighbor Computations" (AISTATS 2019).
+ *
+ * Conventions for every entry point:
+ *  - Plain pointers and sizes only.  "dev_" pointers are device (HBM)
+ *    addresses, "host_" pointers are host addresses.  The caller owns every
+ *    buffer it passes and keeps it alive until the call's work is finished
+ *    (stream-ordered calls: until the stream is synchronised).
+ *  - Matrices are row-major: points are rows ("point-major"), X[i*m + j].
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Return value: KNN_OK (0), KNN_PENDING (1) or a negative KNN_E* code.
+ *    Arguments are checked before any work is enqueued; on error nothing is
+ *    enqueued and knn_last_error() describes the failure (thread-local).
+ *    No C++ exception crosses the ABI.
+ */
+#ifndef KNN_H
+#define KNN_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KNN_OK 0
+#define KNN_PENDING 1
+#define KNN_EINVAL (-1)   /* invalid argument */
+#define KNN_ENOMEM (-2)   /* device or host allocation failed */
+#define KNN_EDEVICE (-3)  /* HIP runtime error */
+#define KNN_EBUSY (-4)    /* object still in use */
+#define KNN_ENOTFOUND (-5)/* unknown ticket / id */
+
+typedef enum { KNN_U8 = 0, KNN_F32 = 1 } knn_dtype;
+
+#define KNN_DB_BORROW 0   /* alias dev_points; caller keeps it alive until destroy */
+#define KNN_DB_COPY 1     /* copy dev_points into library-owned HBM */
+
+#define KNN_MAX_KH 2048   /* largest k + h (adaptive) and k (naive) */
+#define KNN_MAX_ROUNDS 48 /* longest round schedule */
+
+typedef struct knn_db_s *knn_db;
+typedef struct knn_session_s *knn_session;
+
+/* Result-defining parameters of one adaptive query.  Fields marked "0 ->"
+ * take the stated default when zero. */
+typedef struct {
+  int64_t h;           /* slack: returned set has at most k+h points; < 0 means h = k
+                          (Section 4.2 takes h = k) */
+  double delta;        /* failure probability in (0,1) (Theorem 1) */
+  uint64_t seed;       /* Philox key; the same seed gives the same result alone or batched */
+  int32_t alpha_kind;  /* 0: Section 4 footnote width (falls back to 1 when delta/n >= 0.05);
+                          1: Lemma 3 width, valid for any delta;
+                          2: Section 5 width sqrt(c_alpha log(1+(1+log u) n/delta)/u), no guarantee */
+  double c_alpha;      /* only for alpha_kind 2, > 0 */
+  int32_t b0;          /* samples per point in round 0, multiple of 4 (0 -> 64) */
+  float growth;        /* target growth g >= 1: T += max(4, ceil4(ceil(T (g-1)))) (0 -> 2) */
+  float theta_exact;   /* a point goes exact once the next target reaches ceil(theta m) (0 -> 1) */
+  int32_t c_exact;     /* >= 0; the c_exact undecided points with the smallest estimate are
+                          made exact after every sampling step (0 = pure round form) */
+} knn_params;
+
+/* Per-query statistics (24 bytes). */
+typedef struct {
+  int64_t coord_evals;  /* coordinate evaluations: samples + m per exact distance */
+  int32_t rounds;       /* decide steps executed */
+  int32_t count;        /* size of the returned set */
+  int64_t exact_points; /* points whose distance was computed exactly */
+} knn_stats;
+
+/* Fills *p with the defaults: h = -1 (h = k), delta = 0.01, seed = 0,
+ * alpha_kind = 0, c_alpha = 0, b0 = 64, growth = 2, theta_exact = 1, c_exact = 0. */
+void knn_params_default(knn_params *p);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *knn_last_error(void);
+
+/* Library version string. */
+const char *knn_version(void);
+
+/* ---------------------------------------------------------------- DB --- */
+
+/* Registers n points of dimension m (Section 3: the point set X in R^m).
+ * dev_points: device, [n][m] row-major, u8 or f32.  BORROW aliases it; COPY
+ * copies it.  Precomputes row norms (and for f32 a BF16 copy and the value
+ * range) for the naive scan.  Synchronous.  Errors: EINVAL (n < 1, m < 1,
+ * n >= 2^31, bad dtype/flags, NULL), ENOMEM, EDEVICE. */
+int knn_db_create(const void *dev_points, int64_t n, int64_t m, knn_dtype dt,
+                  int32_t flags, knn_db *out);
+
+/* Releases the DB.  EBUSY while a session still holds it or requests on it
+ * are pending.  Waits for the library's own work on it to finish. */
+int knn_db_destroy(knn_db db);
+
+/* n, m and dtype of a DB. */
+int knn_db_info(knn_db db, int64_t *n, int64_t *m, int32_t *dtype);
+
+/* ---------------------------------------------------------- adaptive --- */
+
+/* Round schedule and widths that knn_adaptive uses for one parameter set on
+ * a DB with n points of dimension m (Section 4 footnote / Lemma 3 /
+ * Section 5 widths).  host_T[r], host_alpha[r] for r < *R (cumulative
+ * sample targets of the sampled rounds); round *R is the exact round.
+ * Arrays must hold KNN_MAX_ROUNDS entries.  Host only. */
+int knn_schedule(const knn_params *p, int64_t n, int64_t m, int32_t *host_T,
+                 double *host_alpha, int32_t *R);
+
+/* Adaptive k-NN (Algorithm 1, round-synchronous form) for nq queries.
+ *  dev_queries : device, [nq][m], same dtype as the DB.
+ *  host_k      : host, [nq], k_q >= 1.
+ *  p, np       : host parameter array of length np = 1 (shared) or nq.
+ *  dev_out_idx : device, [nq][out_stride] int64; row q receives the returned
+ *                set (at most k_q + h_q indices, ordered by estimate then index),
+ *                padded with -1.  out_stride >= max_q (k_q + h_q).
+ *  dev_out_count: device, [nq] int32, returned set sizes.
+ *  dev_out_stats: device, [nq] knn_stats, or NULL.
+ * With probability >= 1 - delta (per query) the set contains the k nearest
+ * neighbours (Theorem 1).  If k_q + h_q >= n all n points are returned.
+ * Stream-ordered on `stream`; may synchronise it when the queries do not
+ * all fit in device memory at once.  Errors: EINVAL (k < 1, k+h > KNN_MAX_KH,
+ * delta outside (0,1), b0 not a positive multiple of 4, growth < 1, schedule
+ * longer than KNN_MAX_ROUNDS, c_exact < 0, alpha_kind 2 with c_alpha <= 0,
+ * NULL pointers, out_stride too small), ENOMEM, EDEVICE. */
+int knn_adaptive(knn_db db, const void *dev_queries, int64_t nq, const int32_t *host_k,
+                 const knn_params *p, int64_t np, int64_t *dev_out_idx, int64_t out_stride,
+                 int32_t *dev_out_count, knn_stats *dev_out_stats, void *stream);
+
+/* Debug/parity hook: runs query 0 of the same call as knn_adaptive for
+ * `stop_after` decide steps and copies the per-point state to host arrays
+ * of length n: S (int64 running sums), fl (bit 0 exact, bit 1 accepted,
+ * bit 2 discarded) and ri (round index of the point's last sampled target).
+ * Synchronous. */
+int knn_adaptive_state(knn_db db, const void *dev_query, int32_t k, const knn_params *p,
+                       int32_t stop_after, int64_t *host_S, uint8_t *host_fl,
+                       uint8_t *host_ri, void *stream);
+
+/* ------------------------------------------------------------- naive --- */
+
+/* Naive k-NN (Section 3): all n distances, the k smallest by (distance,
+ * index).  u8: exact integer distances via int8 MFMA; f32: BF16 MFMA
+ * candidates, rescored in FP64 in coordinate order, so the set and the
+ * distances equal an FP64 scan.
+ *  dev_out_idx : device, [nq][k] int64 (ascending distance).
+ *  dev_out_dist: device, [nq][k] double (unnormalised squared distance), or NULL.
+ * Stream-ordered.  Errors: EINVAL (k < 1, k > min(n, KNN_MAX_KH), NULL), ENOMEM,
+ * EDEVICE. */
+int knn_naive(knn_db db, const void *dev_queries, int64_t nq, int32_t k,
+              int64_t *dev_out_idx, double *dev_out_dist, void *stream);
+
+/* ----------------------------------------------------------- session --- */
+
+/* Serving session: resident DBs, a background loop that admits submitted
+ * queries while their state fits hbm_budget_bytes, and runs admitted
+ * queries of different k and delta together (continuous batching: queries
+ * join at round boundaries of queries already running). */
+int knn_session_create(size_t hbm_budget_bytes, knn_session *out);
+
+/* Makes `db` resident in the session; *db_id identifies it in submit. */
+int knn_session_add_db(knn_session s, knn_db db, int32_t *db_id);
+
+/* Enqueues one query (host_query: host, [m] of the DB's dtype; copied
+ * before return).  Never blocks on the GPU.  *ticket identifies the
+ * request.  Errors: EINVAL, ENOTFOUND (db_id). */
+int knn_session_submit(knn_session s, int32_t db_id, const void *host_query, int32_t k,
+                       const knn_params *p, uint64_t *ticket);
+
+/* KNN_PENDING until the request is done; then copies its result
+ * (host_idx: at least k+h entries, -1 padded), frees the ticket and
+ * returns KNN_OK.  ENOTFOUND for unknown tickets. */
+int knn_session_poll(knn_session s, uint64_t ticket, int64_t *host_idx, int32_t *count,
+                     knn_stats *st);
+
+/* Stops the loop, waits for in-flight work, frees session memory. */
+int knn_session_destroy(knn_session s);
+
+/* ------------------------------------------------------- measurement --- */
+
+/* Kernel timing for benchmarks.  knn_prof_enable(1) clears the records and
+ * turns timing on: every launch of a hot kernel class is then bracketed by
+ * HIP events on the stream it is launched on, and the adaptive sampling
+ * kernel adds its algorithmic work to device counters.  Off by default
+ * (no events, no counters).  knn_prof_enable(0) turns it off. */
+int knn_prof_enable(int on);
+
+/* Total event time (ms), launch count and algorithmic work units of one
+ * kernel class since the last enable: 0 adaptive sampling (units: bytes),
+ * 1 candidate-exact, 2 bound selection, 3 decide/compact, 4 finish/admit,
+ * 5 naive MFMA scan (units: integer or floating-point operations, 2 per
+ * multiply-add), 6 naive query prep / merge / rescoring.  Waits for the
+ * recorded events. */
+int knn_prof_read(int32_t kind, double *total_ms, int64_t *launches, double *units);
+
+/* Device work counters since the last enable: [0] algorithmic bytes of the
+ * sampling kernel, [1] samples drawn, [2] exact-distance coordinates,
+ * [3] reserved.  host_out4: host, 4 entries.  Synchronises the device. */
+int knn_prof_counters(uint64_t *host_out4);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

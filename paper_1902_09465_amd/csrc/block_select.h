@@ -1,0 +1,164 @@
+// block_select.h -- exact order statistics of 64-bit keys inside one
+// workgroup, by most-significant-digit radix selection with an LDS
+// histogram (8-bit digits).  Only values matter for the thresholds of the
+// adaptive rule, so keys are selected with multiplicity; where an index
+// tie-break is needed the caller runs a second selection on the indices of
+// the boundary key.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace knn {
+
+constexpr int kWave = 64;
+
+struct SelScratch {
+  uint32_t hist[256];
+  int32_t res[4];
+};
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// One wave: find the bucket b where the running count over hist[0..255]
+// first reaches r (1-based); res[0] = b, res[1] = count in buckets < b.
+__device__ __forceinline__ void scan_find_bucket(SelScratch &s, int r) {
+  const int l = lane_id();
+  const uint32_t c0 = s.hist[4 * l], c1 = s.hist[4 * l + 1], c2 = s.hist[4 * l + 2],
+                 c3 = s.hist[4 * l + 3];
+  const int tot = (int)(c0 + c1 + c2 + c3);
+  int incl = tot;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int t = __shfl_up(incl, d);
+    if (l >= d) incl += t;
+  }
+  const int excl = incl - tot;
+  if (excl < r && r <= incl) {
+    int cum = excl;
+    int b;
+    if (cum + (int)c0 >= r) {
+      b = 4 * l;
+    } else {
+      cum += (int)c0;
+      if (cum + (int)c1 >= r) {
+        b = 4 * l + 1;
+      } else {
+        cum += (int)c1;
+        if (cum + (int)c2 >= r) {
+          b = 4 * l + 2;
+        } else {
+          cum += (int)c2;
+          b = 4 * l + 3;
+        }
+      }
+    }
+    s.res[0] = b;
+    s.res[1] = cum;
+  }
+}
+
+// rank-th smallest (1-based, with multiplicity) of the keys held in
+// registers by the block (E per thread; pad unused entries with
+// UINT64_MAX and count them).  *less = number of keys strictly smaller.
+template <int NT, int E>
+__device__ uint64_t block_kth_regs(const uint64_t (&key)[E], int rank, SelScratch &s, int *less) {
+  uint64_t prefix = 0, mask = 0;
+  int r = rank, lt = 0;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int b = threadIdx.x; b < 256; b += NT) s.hist[b] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if ((key[e] & mask) == prefix) atomicAdd(&s.hist[(uint32_t)(key[e] >> shift) & 255u], 1u);
+    __syncthreads();
+    if (threadIdx.x < kWave) scan_find_bucket(s, r);
+    __syncthreads();
+    const int b = s.res[0], before = s.res[1];
+    r -= before;
+    lt += before;
+    prefix |= (uint64_t)b << shift;
+    mask |= 0xFFull << shift;
+    __syncthreads();
+  }
+  *less = lt;
+  return prefix;
+}
+
+// Same over a generated sequence: getkey(p) for p in [0, N), re-evaluated on
+// each of the 8 passes (the caller pads nothing; rank <= N).
+template <int NT, typename GetKey>
+__device__ uint64_t block_kth_gen(int64_t N, GetKey getkey, int rank, SelScratch &s, int *less) {
+  uint64_t prefix = 0, mask = 0;
+  int r = rank, lt = 0;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int b = threadIdx.x; b < 256; b += NT) s.hist[b] = 0;
+    __syncthreads();
+    for (int64_t p = threadIdx.x; p < N; p += NT) {
+      const uint64_t k = getkey(p);
+      if ((k & mask) == prefix) atomicAdd(&s.hist[(uint32_t)(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) scan_find_bucket(s, r);
+    __syncthreads();
+    const int b = s.res[0], before = s.res[1];
+    r -= before;
+    lt += before;
+    prefix |= (uint64_t)b << shift;
+    mask |= 0xFFull << shift;
+    __syncthreads();
+  }
+  *less = lt;
+  return prefix;
+}
+
+// rank-th smallest 32-bit value among getval(p) for which keep(p) holds.
+template <int NT, typename GetVal, typename Keep>
+__device__ uint32_t block_kth_u32_gen(int64_t N, GetVal getval, Keep keep, int rank, SelScratch &s) {
+  uint32_t prefix = 0, mask = 0;
+  int r = rank;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int b = threadIdx.x; b < 256; b += NT) s.hist[b] = 0;
+    __syncthreads();
+    for (int64_t p = threadIdx.x; p < N; p += NT) {
+      if (!keep(p)) continue;
+      const uint32_t v = getval(p);
+      if ((v & mask) == prefix) atomicAdd(&s.hist[(v >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) scan_find_bucket(s, r);
+    __syncthreads();
+    r -= s.res[1];
+    prefix |= (uint32_t)s.res[0] << shift;
+    mask |= 0xFFu << shift;
+    __syncthreads();
+  }
+  return prefix;
+}
+
+// In-LDS bitonic sort of (key, idx) pairs ascending by (key, idx); len is a
+// power of two; the whole block takes part.
+template <int NT>
+__device__ void block_bitonic_sort(uint64_t *key, int32_t *idx, int len) {
+  for (int size = 2; size <= len; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < (len >> 1); t += NT) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = ((lo & size) == 0);
+        const uint64_t ka = key[lo], kb = key[hi];
+        const int32_t ia = idx[lo], ib = idx[hi];
+        const bool a_gt_b = (ka > kb) || (ka == kb && ia > ib);
+        if (a_gt_b == up) {
+          key[lo] = kb;
+          key[hi] = ka;
+          idx[lo] = ib;
+          idx[hi] = ia;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace knn

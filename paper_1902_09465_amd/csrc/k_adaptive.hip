@@ -1,0 +1,922 @@
+// k_adaptive.hip -- device side of the round-synchronous adaptive k-NN
+// (Algorithm 1 of LeJeune, Baraniuk, Heckel, AISTATS 2019, one round at a
+// time for every in-flight query "slot").
+//
+// One step advances every running slot by one round:
+//   k_sample          draw and accumulate the round's samples (Section 4
+//                     estimator), or the exact distance in the exact round
+//   k_cand_partial/   optional: make the c_exact undecided points with the
+//   k_cand_merge      smallest estimate exact
+//   k_select_partial  per chunk of the kept set P: the k smallest upper and
+//                     k+1 smallest lower bounds (values)
+//   k_select_merge    U, L1, L2 for the slot (eq. d_ind in round form)
+//   k_decide          discard / accept / keep, compacting the undecided list
+//   k_finish          stop rule, output, next round, admission of new queries
+// All decisions use the same IEEE double expressions as the CPU oracle
+// (compiled without FMA contraction); sums are integers, so the result does
+// not depend on launch shape, chunking or atomic order.
+#include "block_select.h"
+#include "knn_internal.h"
+#include "philox.h"
+#include "knn_prof.h"
+
+namespace knn {
+
+constexpr int NT = 256;
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int64_t shfl_xor_i64(int64_t v, int mask) {
+  const int lo = __shfl_xor((int)(uint32_t)v, mask);
+  const int hi = __shfl_xor((int)(uint32_t)((uint64_t)v >> 32), mask);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// floor(v * 2^F) for a finite v >= 0 (the f32 fixed-point sample).
+__device__ __forceinline__ int64_t fixed_of(float v, int F) {
+  const uint32_t b = __float_as_uint(v);
+  const int e = (int)((b >> 23) & 0xFFu);
+  uint32_t mant = b & 0x7FFFFFu;
+  int sh;
+  if (e) {
+    mant |= 0x800000u;
+    sh = e - 150 + F;
+  } else {
+    sh = -149 + F;
+  }
+  if (sh >= 0) return (int64_t)((uint64_t)mant << (sh > 62 ? 62 : sh));
+  return (sh <= -32) ? 0 : (int64_t)(mant >> (-sh));
+}
+
+template <int DT>
+__device__ __forceinline__ int64_t sample_val(const uint8_t *__restrict__ row,
+                                              const uint8_t *__restrict__ q, uint32_t j, int F) {
+  if constexpr (DT == KNN_U8) {
+    const int d = (int)row[j] - (int)q[j];
+    return (int64_t)(d * d);
+  } else {
+    const float d = reinterpret_cast<const float *>(row)[j] - reinterpret_cast<const float *>(q)[j];
+    return fixed_of(d * d, F);
+  }
+}
+
+struct SlotArrays {
+  int64_t *S;
+  uint8_t *fl, *ri;
+  int32_t *act, *xa;      // current halves
+  int32_t *act_n, *xa_n;  // next halves
+  int32_t *acc;
+};
+
+__device__ __forceinline__ SlotArrays slot_arrays(const Bufs &B, int64_t n, int s, int par) {
+  SlotArrays a;
+  a.S = B.S + (int64_t)s * n;
+  a.fl = B.fl + (int64_t)s * n;
+  a.ri = B.ri + (int64_t)s * n;
+  int32_t *act = B.act + (int64_t)s * 2 * n;
+  int32_t *xa = B.xa + (int64_t)s * 2 * n;
+  a.act = act + (int64_t)par * n;
+  a.act_n = act + (int64_t)(par ^ 1) * n;
+  a.xa = xa + (int64_t)par * n;
+  a.xa_n = xa + (int64_t)(par ^ 1) * n;
+  a.acc = B.acc + (int64_t)s * n;
+  return a;
+}
+
+// Estimate and width of point i (Section 4): d^ = S / (T W), alpha(T); an
+// exact point has T = m and width 0 (Algorithm 1).
+__device__ __forceinline__ void point_bounds(const Slot *sl, int64_t m, int64_t S, uint8_t f,
+                                             uint8_t r, double &d, double &a) {
+  if (f & FL_EXACT) {
+    d = (double)S / ((double)m * sl->W);
+    a = 0.0;
+  } else {
+    d = (double)S / ((double)sl->T[r] * sl->W);
+    a = sl->alpha[r];
+  }
+}
+
+// p-th element of the kept set P = [act | xa | acc] (identity while implicit).
+__device__ __forceinline__ int32_t elem_P(const Slot *sl, const SlotArrays &a, int64_t p) {
+  if (sl->implicit) return (int32_t)p;
+  if (p < sl->n_act) return a.act[p];
+  p -= sl->n_act;
+  if (p < sl->n_xa) return a.xa[p];
+  return a.acc[p - sl->n_xa];
+}
+
+// p-th element of the undecided set A = [act | xa].
+__device__ __forceinline__ int32_t elem_A(const Slot *sl, const SlotArrays &a, int64_t p) {
+  if (sl->implicit) return (int32_t)p;
+  if (p < sl->n_act) return a.act[p];
+  return a.xa[p - sl->n_act];
+}
+
+__device__ __forceinline__ int64_t size_P(const Slot *sl, int64_t n) {
+  return sl->implicit ? n : (int64_t)sl->n_act + sl->n_xa + sl->n_acc;
+}
+__device__ __forceinline__ int64_t size_A(const Slot *sl, int64_t n) {
+  return sl->implicit ? n : (int64_t)sl->n_act + sl->n_xa;
+}
+
+// Exact sum over all m coordinates of point i by the whole block
+// (rare paths: candidate-exact and oversized finalisation).
+template <int DT, int BT>
+__device__ int64_t block_exact_sum(const uint8_t *X, int64_t m, int32_t i, const uint8_t *q, int F,
+                                   int64_t *red) {
+  const int elem = DT == KNN_U8 ? 1 : 4;
+  const uint8_t *row = X + (int64_t)i * m * elem;
+  int64_t acc = 0;
+  for (int64_t j = threadIdx.x; j < m; j += BT) acc += sample_val<DT>(row, q, (uint32_t)j, F);
+  for (int o = kWave / 2; o > 0; o >>= 1) acc += shfl_xor_i64(acc, o);
+  __syncthreads();
+  if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  int64_t tot = 0;
+  for (int w = 0; w < BT / kWave; ++w) tot += red[w];
+  __syncthreads();
+  return tot;
+}
+
+// ---------------------------------------------------------------- f32 prep
+
+// Per query: value range of query and points -> W = R' 2^F with
+// R' = (hi - lo)^2 (1 + 2^-20), F = 61 - ceil(log2 m) - ceil(log2 R').
+__device__ __forceinline__ int ceil_log2_pos(double x) {
+  uint64_t b;
+  __builtin_memcpy(&b, &x, 8);
+  const int fe = (int)((b >> 52) & 0x7FF) - 1022;  // x = f 2^fe, f in [0.5, 1)
+  return (b & 0xFFFFFFFFFFFFFull) == 0 ? fe - 1 : fe;
+}
+__device__ __forceinline__ double pow2_d(int e) {
+  const uint64_t b = (uint64_t)(e + 1023) << 52;
+  double x;
+  __builtin_memcpy(&x, &b, 8);
+  return x;
+}
+
+__global__ __launch_bounds__(NT) void k_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m,
+                                                 double db_lo, double db_hi) {
+  const int qi = blockIdx.x;
+  if (qi >= nq) return;
+  const float *q = reinterpret_cast<const float *>(qd[qi].q);
+  float lo = INFINITY, hi = -INFINITY;
+  for (int64_t j = threadIdx.x; j < m; j += NT) {
+    lo = fminf(lo, q[j]);
+    hi = fmaxf(hi, q[j]);
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, o));
+    hi = fmaxf(hi, __shfl_xor(hi, o));
+  }
+  __shared__ float slo[NT / kWave], shi[NT / kWave];
+  if (lane_id() == 0) {
+    slo[threadIdx.x / kWave] = lo;
+    shi[threadIdx.x / kWave] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double l = db_lo, h = db_hi;
+    for (int w = 0; w < NT / kWave; ++w) {
+      if ((double)slo[w] < l) l = (double)slo[w];
+      if ((double)shi[w] > h) h = (double)shi[w];
+    }
+    const double span = h - l;
+    if (!(span > 0.0)) {
+      qd[qi].trivial = 1;
+      qd[qi].W = 0.0;
+      qd[qi].F = 0;
+    } else {
+      const double Rp = span * span * (1.0 + 0x1p-20);
+      const int F = 61 - ceil_log2_pos((double)m) - ceil_log2_pos(Rp);
+      qd[qi].F = F;
+      qd[qi].W = Rp * pow2_d(F);
+      if (qd[qi].kh >= n) qd[qi].trivial = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- sample
+
+// Round `cur` of every running slot: samples t in [T[cur-1], T[cur]) of each
+// point of the sampled list, LPP lanes per point (each lane takes every
+// LPP-th block of four draws); or, in the exact round, the exact distance,
+// one wave per point with coalesced row reads.
+template <int DT, int LPP, bool QLDS>
+__global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const uint8_t *__restrict__ X,
+                                               Bufs B, Geometry G) {
+  const int s = blockIdx.y;
+  const Slot *sl = &slots[s];
+  if (sl->state != 1) return;
+  const int64_t n = G.n, m = G.m;
+  const int implicit = sl->implicit;
+  const int64_t nlist = implicit ? n : sl->n_act;
+  const int64_t base = (int64_t)blockIdx.x * G.ch_sample;
+  if (base >= nlist) return;
+  const int64_t end = min(nlist, base + (int64_t)G.ch_sample);
+  constexpr int elem = DT == KNN_U8 ? 1 : 4;
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint8_t *qg = reinterpret_cast<const uint8_t *>(sl->q);
+  if constexpr (QLDS) {
+    const int64_t qb = m * elem;
+    if ((qb & 3) == 0 && (((uintptr_t)qg) & 3) == 0) {
+      for (int64_t w = threadIdx.x; w < qb / 4; w += NT)
+        reinterpret_cast<uint32_t *>(smem)[w] = reinterpret_cast<const uint32_t *>(qg)[w];
+    } else {
+      for (int64_t w = threadIdx.x; w < qb; w += NT) smem[w] = qg[w];
+    }
+    __syncthreads();
+  }
+  const uint8_t *q = QLDS ? smem : qg;
+  const int cur = sl->cur;
+  const int F = sl->F;
+  const SlotArrays a = slot_arrays(B, n, s, sl->par);
+  if (G.prof && threadIdx.x == 0) {
+    // algorithmic work of this block: per point the sampled values, the
+    // running sum (read + write), the list entry and the round index
+    const uint64_t pts = (uint64_t)(end - base);
+    if (cur >= sl->R) {
+      atomicAdd(&G.prof[0], pts * (uint64_t)(m * elem + 14));
+      atomicAdd(&G.prof[2], pts * (uint64_t)m);
+    } else {
+      const uint64_t B_r = (uint64_t)(sl->T[cur] - (cur ? sl->T[cur - 1] : 0));
+      atomicAdd(&G.prof[0], pts * (B_r * elem + 21));
+      atomicAdd(&G.prof[1], pts * B_r);
+    }
+  }
+  if (cur >= sl->R) {
+    // exact round
+    const int wave = threadIdx.x / kWave, lane = lane_id();
+    for (int64_t p = base + wave; p < end; p += NT / kWave) {
+      const int32_t i = implicit ? (int32_t)p : a.act[p];
+      const uint8_t *row = X + (int64_t)i * m * elem;
+      int64_t acc = 0;
+      if constexpr (DT == KNN_U8) {
+        if ((m & 3) == 0) {
+          const uint32_t *r4 = reinterpret_cast<const uint32_t *>(row);
+          for (int64_t w = lane; w < m / 4; w += kWave) {
+            const uint32_t xv = r4[w];
+            const uint32_t qv = QLDS ? reinterpret_cast<const uint32_t *>(q)[w]
+                                     : (uint32_t)q[4 * w] | ((uint32_t)q[4 * w + 1] << 8) |
+                                           ((uint32_t)q[4 * w + 2] << 16) | ((uint32_t)q[4 * w + 3] << 24);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const int d = (int)((xv >> (8 * b)) & 255u) - (int)((qv >> (8 * b)) & 255u);
+              acc += d * d;
+            }
+          }
+        } else {
+          for (int64_t j = lane; j < m; j += kWave) acc += sample_val<DT>(row, q, (uint32_t)j, F);
+        }
+      } else {
+        for (int64_t j = lane; j < m; j += kWave) acc += sample_val<DT>(row, q, (uint32_t)j, F);
+      }
+      for (int o = kWave / 2; o > 0; o >>= 1) acc += shfl_xor_i64(acc, o);
+      if (lane == 0) {
+        a.S[i] = acc;
+        if (cur == 0) {
+          a.fl[i] = FL_EXACT;
+          a.ri[i] = 0;
+        } else {
+          a.fl[i] = a.fl[i] | FL_EXACT;
+        }
+      }
+    }
+    return;
+  }
+  // sampled round
+  const uint32_t t0 = cur ? (uint32_t)sl->T[cur - 1] : 0u;
+  const uint32_t t1 = (uint32_t)sl->T[cur];
+  const uint32_t blk0 = t0 >> 2, blk1 = t1 >> 2;
+  const uint32_t k0 = (uint32_t)sl->seed, k1 = (uint32_t)(sl->seed >> 32);
+  const uint32_t mm = (uint32_t)m;
+  const int sub = threadIdx.x % LPP;
+  for (int64_t p = base + threadIdx.x / LPP; p < end; p += NT / LPP) {
+    const int32_t i = implicit ? (int32_t)p : a.act[p];
+    const uint8_t *row = X + (int64_t)i * m * elem;
+    int64_t acc = 0;
+    for (uint32_t b = blk0 + sub; b < blk1; b += LPP) {
+      const P4 r = philox10(b, 0u, (uint32_t)i, 0u, k0, k1);
+      acc += sample_val<DT>(row, q, coord_of(r.x, mm), F);
+      acc += sample_val<DT>(row, q, coord_of(r.y, mm), F);
+      acc += sample_val<DT>(row, q, coord_of(r.z, mm), F);
+      acc += sample_val<DT>(row, q, coord_of(r.w, mm), F);
+    }
+#pragma unroll
+    for (int o = LPP / 2; o > 0; o >>= 1) acc += shfl_xor_i64(acc, o);
+    if (sub == 0) {
+      if (cur == 0) {
+        a.S[i] = acc;
+        a.fl[i] = 0;
+      } else {
+        a.S[i] += acc;
+      }
+      a.ri[i] = (uint8_t)cur;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- selection
+
+// Writes the K smallest keys of the block (with multiplicity) to out[0..K).
+template <int E>
+__device__ void emit_smallest(const uint64_t (&key)[E], int K, uint64_t *out, SelScratch &ss, int &cnt) {
+  int less;
+  const uint64_t v = block_kth_regs<NT, E>(key, K, ss, &less);
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (key[e] < v) out[atomicAdd(&cnt, 1)] = key[e];
+  for (int j = less + (int)threadIdx.x; j < K; j += NT) out[j] = v;
+  __syncthreads();
+}
+
+constexpr int SEL_E = 16;
+constexpr int SEL_CH = NT * SEL_E;
+
+// Per chunk of P: the k smallest upper bounds and the k+1 smallest lower
+// bounds (values).  U, L1, L2 of the whole set are order statistics of the
+// union of these lists.
+__global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots, Bufs B, Geometry G) {
+  const int s = blockIdx.y;
+  const Slot *sl = &slots[s];
+  if (sl->state != 1) return;
+  const int64_t n = G.n, m = G.m;
+  const int64_t nP = size_P(sl, n);
+  const int64_t base = (int64_t)blockIdx.x * SEL_CH;
+  if (base >= nP) return;
+  const SlotArrays a = slot_arrays(B, n, s, sl->par);
+  __shared__ SelScratch ss;
+  __shared__ int cnt;
+  uint64_t ku[SEL_E], kl[SEL_E];
+#pragma unroll
+  for (int e = 0; e < SEL_E; ++e) {
+    const int64_t p = base + (int64_t)e * NT + threadIdx.x;
+    if (p < nP) {
+      const int32_t i = elem_P(sl, a, p);
+      double d, al;
+      point_bounds(sl, m, a.S[i], a.fl[i], a.ri[i], d, al);
+      ku[e] = dkey(d + al);
+      kl[e] = dkey(d - al);
+    } else {
+      ku[e] = ~0ull;
+      kl[e] = ~0ull;
+    }
+  }
+  const int k = sl->k;
+  uint64_t *out = B.part + (int64_t)s * B.part_stride + (int64_t)blockIdx.x * (2 * k + 1);
+  emit_smallest<SEL_E>(ku, k, out, ss, cnt);
+  emit_smallest<SEL_E>(kl, k + 1, out + k, ss, cnt);
+}
+
+constexpr int MT = 1024;  // merge / finish block size
+
+__global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, Bufs B, Geometry G) {
+  const int s = blockIdx.x;
+  Slot *sl = &slots[s];
+  if (sl->state != 1) return;
+  const int64_t nP = size_P(sl, G.n);
+  const int64_t nch = (nP + SEL_CH - 1) / SEL_CH;
+  const int k = sl->k;
+  const int64_t w = 2 * k + 1;
+  const uint64_t *part = B.part + (int64_t)s * B.part_stride;
+  __shared__ SelScratch ss;
+  int less;
+  auto gu = [&](int64_t p) -> uint64_t { return part[(p / k) * w + (p % k)]; };
+  auto gl = [&](int64_t p) -> uint64_t { return part[(p / (k + 1)) * w + k + (p % (k + 1))]; };
+  const uint64_t U = block_kth_gen<MT>(nch * k, gu, k, ss, &less);
+  const uint64_t L1 = block_kth_gen<MT>(nch * (k + 1), gl, k, ss, &less);
+  const uint64_t L2 = block_kth_gen<MT>(nch * (k + 1), gl, k + 1, ss, &less);
+  if (threadIdx.x == 0) {
+    sl->U = dkey_inv(U);
+    sl->L1 = dkey_inv(L1);
+    sl->L2 = dkey_inv(L2);
+  }
+}
+
+// ---------------------------------------------------------------- decide
+
+constexpr int DEC_CH = NT * 8;
+
+// Discard if LCB > U (k kept points are surely closer); accept if fewer
+// than k other points can be closer (UCB <= L2, or for an exact point
+// d <= L1); otherwise keep undecided.  Survivors are compacted into the
+// next lists; order within a list is irrelevant to the result.
+__global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B, Geometry G) {
+  const int s = blockIdx.y;
+  Slot *sl = &slots[s];
+  if (sl->state != 1) return;
+  const int64_t n = G.n, m = G.m;
+  const int64_t nA = size_A(sl, n);
+  const int64_t base = (int64_t)blockIdx.x * DEC_CH;
+  if (base >= nA) return;
+  const int64_t end = min(nA, base + (int64_t)DEC_CH);
+  const SlotArrays a = slot_arrays(B, n, s, sl->par);
+  const double U = sl->U, L1 = sl->L1, L2 = sl->L2;
+  __shared__ int wcnt[NT / kWave][3];
+  __shared__ int bbase[3];
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  for (int64_t p0 = base; p0 < end; p0 += NT) {
+    const int64_t p = p0 + threadIdx.x;
+    int cat = -1;  // 0 act, 1 xa, 2 acc, -1 none
+    int32_t i = 0;
+    if (p < end) {
+      i = elem_A(sl, a, p);
+      const uint8_t f = a.fl[i];
+      double d, al;
+      point_bounds(sl, m, a.S[i], f, a.ri[i], d, al);
+      const double ucb = d + al, lcb = d - al;
+      const bool exact = (f & FL_EXACT) != 0;
+      if (lcb > U) {
+        a.fl[i] = f | FL_DISC;
+      } else if (exact ? (ucb <= L1) : (ucb <= L2)) {
+        a.fl[i] = f | FL_ACC;
+        cat = 2;
+      } else {
+        cat = exact ? 1 : 0;
+      }
+    }
+    uint64_t mk[3];
+    int off[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      mk[c] = __ballot(cat == c);
+      off[c] = __popcll(mk[c] & lt_mask);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) wcnt[wave][c] = __popcll(mk[c]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const int c = threadIdx.x;
+      int tot = 0;
+      for (int w = 0; w < NT / kWave; ++w) {
+        const int t = wcnt[w][c];
+        wcnt[w][c] = tot;  // exclusive prefix over waves
+        tot += t;
+      }
+      int *ctr = c == 0 ? &sl->nn_act : (c == 1 ? &sl->nn_xa : &sl->nn_acc);
+      bbase[c] = tot ? atomicAdd(ctr, tot) : 0;
+    }
+    __syncthreads();
+    if (cat >= 0) {
+      const int pos = bbase[cat] + wcnt[wave][cat] + off[cat];
+      int32_t *dst = cat == 0 ? a.act_n : (cat == 1 ? a.xa_n : a.acc);
+      dst[pos] = i;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- candidate-exact
+
+constexpr int CAND_E = 16;
+constexpr int CAND_CH = NT * CAND_E;
+
+// Per chunk of the undecided set: the c_exact smallest (estimate, index).
+__global__ __launch_bounds__(NT) void k_cand_partial(Slot *__restrict__ slots, Bufs B, Geometry G) {
+  const int s = blockIdx.y;
+  const Slot *sl = &slots[s];
+  if (sl->state != 1 || sl->c_exact <= 0) return;
+  const int64_t n = G.n, m = G.m;
+  const int64_t nA = size_A(sl, n);
+  const int64_t base = (int64_t)blockIdx.x * CAND_CH;
+  if (base >= nA) return;
+  const SlotArrays a = slot_arrays(B, n, s, sl->par);
+  const int c = min(sl->c_exact, CAND_CH);
+  __shared__ SelScratch ss;
+  __shared__ int cnt;
+  uint64_t key[CAND_E];
+  uint32_t id[CAND_E];
+#pragma unroll
+  for (int e = 0; e < CAND_E; ++e) {
+    const int64_t p = base + (int64_t)e * NT + threadIdx.x;
+    if (p < nA) {
+      const int32_t i = elem_A(sl, a, p);
+      double d, al;
+      point_bounds(sl, m, a.S[i], a.fl[i], a.ri[i], d, al);
+      key[e] = dkey(d);
+      id[e] = (uint32_t)i;
+    } else {
+      key[e] = ~0ull;
+      id[e] = 0xFFFFFFFFu;
+    }
+  }
+  int less;
+  const uint64_t v = block_kth_regs<NT, CAND_E>(key, c, ss, &less);
+  const int need = c - less;
+  // index tie-break among keys equal to v
+  uint32_t prefix = 0, mask = 0;
+  int r = need;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int b = threadIdx.x; b < 256; b += NT) ss.hist[b] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < CAND_E; ++e)
+      if (key[e] == v && (id[e] & mask) == prefix) atomicAdd(&ss.hist[(id[e] >> shift) & 255u], 1u);
+    __syncthreads();
+    if (threadIdx.x < kWave) scan_find_bucket(ss, r);
+    __syncthreads();
+    r -= ss.res[1];
+    prefix |= (uint32_t)ss.res[0] << shift;
+    mask |= 0xFFu << shift;
+    __syncthreads();
+  }
+  const uint32_t idthr = prefix;
+  uint64_t *ok = B.part + (int64_t)s * B.part_stride + (int64_t)blockIdx.x * c;
+  const int64_t nchA = (nA + CAND_CH - 1) / CAND_CH;
+  uint32_t *oi = reinterpret_cast<uint32_t *>(B.part + (int64_t)s * B.part_stride + nchA * c) +
+                 (int64_t)blockIdx.x * c;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < CAND_E; ++e) {
+    if (key[e] < v || (key[e] == v && id[e] <= idthr)) {
+      const int pos = atomicAdd(&cnt, 1);
+      if (pos < c) {
+        ok[pos] = key[e];
+        oi[pos] = id[e];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int DT>
+__global__ __launch_bounds__(MT) void k_cand_merge(Slot *__restrict__ slots, const uint8_t *__restrict__ X,
+                                                   Bufs B, Geometry G) {
+  const int s = blockIdx.x;
+  Slot *sl = &slots[s];
+  if (sl->state != 1 || sl->c_exact <= 0) return;
+  const int64_t n = G.n, m = G.m;
+  const int64_t nA = size_A(sl, n);
+  const int64_t nchA = (nA + CAND_CH - 1) / CAND_CH;
+  const int c = min(sl->c_exact, CAND_CH);
+  const int64_t N = nchA * c;
+  const uint64_t *pk = B.part + (int64_t)s * B.part_stride;
+  const uint32_t *pi = reinterpret_cast<const uint32_t *>(pk + nchA * c);
+  const SlotArrays a = slot_arrays(B, n, s, sl->par);
+  __shared__ SelScratch ss;
+  __shared__ int cnt;
+  __shared__ int32_t pick[kMaxKH];
+  __shared__ int64_t red[MT / kWave];
+  const int take = (int)min((int64_t)c, nA);
+  int less;
+  const uint64_t v = block_kth_gen<MT>(N, [&](int64_t p) { return pk[p]; }, take, ss, &less);
+  const uint32_t thr = block_kth_u32_gen<MT>(
+      N, [&](int64_t p) { return pi[p]; }, [&](int64_t p) { return pk[p] == v; }, take - less, ss);
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int64_t p = threadIdx.x; p < N; p += MT) {
+    const uint64_t kk = pk[p];
+    if (kk == ~0ull) continue;
+    if (kk < v || (kk == v && pi[p] <= thr)) {
+      const int pos = atomicAdd(&cnt, 1);
+      if (pos < kMaxKH) pick[pos] = (int32_t)pi[p];
+    }
+  }
+  __syncthreads();
+  const int np = min(cnt, take);
+  const int F = sl->F;
+  const uint8_t *q = reinterpret_cast<const uint8_t *>(sl->q);
+  int64_t made = 0;
+  for (int t = 0; t < np; ++t) {
+    const int32_t i = pick[t];
+    if (a.fl[i] & FL_EXACT) continue;
+    const int64_t tot = block_exact_sum<DT, MT>(X, m, i, q, F, red);
+    if (threadIdx.x == 0) {
+      a.S[i] = tot;
+      a.fl[i] = a.fl[i] | FL_EXACT;
+    }
+    ++made;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && made) {
+    sl->exact_points += made;
+    sl->coord_evals += made * m;
+  }
+}
+
+// ---------------------------------------------------------------- finish
+
+__device__ void write_trivial(const QDesc &qd, int64_t n) {
+  const int64_t cnt = qd.kh < n ? qd.kh : n;
+  for (int64_t j = threadIdx.x; j < qd.out_stride; j += blockDim.x) qd.out_idx[j] = j < cnt ? j : -1;
+  if (threadIdx.x == 0) {
+    *qd.out_count = (int32_t)cnt;
+    if (qd.out_stats) {
+      qd.out_stats->coord_evals = 0;
+      qd.out_stats->rounds = 0;
+      qd.out_stats->count = (int32_t)cnt;
+      qd.out_stats->exact_points = 0;
+    }
+  }
+}
+
+// Output: the kept set ordered by (estimate, index), at most k+h entries.
+// An oversized stop (no undecided point left to sample, |P| > k+h) first
+// makes the remaining estimated points exact, then keeps the k+h smallest
+// by (distance, index), which contain a k-NN set also under ties.
+template <int DT>
+__device__ void finalize(Slot *sl, int s, const QDesc &qd, const uint8_t *X, const Bufs &B,
+                         const Geometry &G) {
+  const int64_t n = G.n, m = G.m;
+  const SlotArrays a = slot_arrays(B, n, s, sl->par);
+  const int kh = sl->kh;
+  __shared__ SelScratch ss;
+  __shared__ uint64_t skey[kMaxKH];
+  __shared__ int32_t sidx[kMaxKH];
+  __shared__ int cnt;
+  __shared__ int64_t red[MT / kWave];
+  const int n_act = sl->n_act, n_xa = sl->n_xa, n_acc = sl->n_acc;
+  const int64_t nP = (int64_t)n_act + n_xa + n_acc;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  if (nP > kh) {
+    const uint8_t *q = reinterpret_cast<const uint8_t *>(sl->q);
+    int64_t made = 0;
+    for (int t = 0; t < n_acc; ++t) {
+      const int32_t i = a.acc[t];
+      if (a.fl[i] & FL_EXACT) continue;
+      const int64_t tot = block_exact_sum<DT, MT>(X, m, i, q, sl->F, red);
+      if (threadIdx.x == 0) {
+        a.S[i] = tot;
+        a.fl[i] = a.fl[i] | FL_EXACT;
+      }
+      ++made;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && made) {
+      sl->exact_points += made;
+      sl->coord_evals += made * m;
+    }
+    __syncthreads();
+    // P = [xa | acc] (n_act == 0 here), every point exact
+    const double denom = (double)m * sl->W;
+    auto elem = [&](int64_t p) -> int32_t { return p < n_xa ? a.xa[p] : a.acc[p - n_xa]; };
+    auto gk = [&](int64_t p) -> uint64_t { return dkey((double)a.S[elem(p)] / denom); };
+    const int64_t N = (int64_t)n_xa + n_acc;
+    int less;
+    const uint64_t v = block_kth_gen<MT>(N, gk, kh, ss, &less);
+    const uint32_t thr = block_kth_u32_gen<MT>(
+        N, [&](int64_t p) { return (uint32_t)elem(p); }, [&](int64_t p) { return gk(p) == v; },
+        kh - less, ss);
+    for (int64_t p = threadIdx.x; p < N; p += MT) {
+      const int32_t i = elem(p);
+      const uint64_t kk = gk(p);
+      if (kk < v || (kk == v && (uint32_t)i <= thr)) {
+        const int pos = atomicAdd(&cnt, 1);
+        if (pos < kMaxKH) {
+          skey[pos] = kk;
+          sidx[pos] = i;
+        }
+      }
+    }
+  } else {
+    for (int64_t p = threadIdx.x; p < nP; p += MT) {
+      const int32_t i = elem_P(sl, a, p);
+      double d, al;
+      point_bounds(sl, m, a.S[i], a.fl[i], a.ri[i], d, al);
+      skey[p] = dkey(d);
+      sidx[p] = i;
+    }
+    if (threadIdx.x == 0) cnt = (int)nP;
+  }
+  __syncthreads();
+  const int c = min(cnt, kh);
+  int len = 1;
+  while (len < c) len <<= 1;
+  for (int p = c + (int)threadIdx.x; p < len; p += MT) {
+    skey[p] = ~0ull;
+    sidx[p] = 0x7FFFFFFF;
+  }
+  block_bitonic_sort<MT>(skey, sidx, len);
+  for (int64_t j = threadIdx.x; j < qd.out_stride; j += MT) qd.out_idx[j] = j < c ? (int64_t)sidx[j] : -1;
+  if (threadIdx.x == 0) {
+    *qd.out_count = c;
+    if (qd.out_stats) {
+      qd.out_stats->coord_evals = sl->coord_evals;
+      qd.out_stats->rounds = sl->rounds;
+      qd.out_stats->count = c;
+      qd.out_stats->exact_points = sl->exact_points;
+    }
+  }
+  __syncthreads();
+}
+
+// Claims at most one query for an idle slot and initialises it.  A trivial
+// query (k+h >= n, or a zero value range) is answered on the spot and the
+// slot stays idle until the next step.  There is deliberately no loop here:
+// a loop whose head and back-edge both hold thread-0-only work around
+// barriers can be restructured so that lane 0 leaves the loop nest while the
+// rest of its wave keeps iterating.
+__device__ void admit(Slot *sl, const QDesc *qd, const Sched *sched, Ctl *ctl, int64_t n, int64_t m) {
+  __shared__ int claimed;
+  if (threadIdx.x == 0) {
+    const int nq = __atomic_load_n(&ctl->nq, __ATOMIC_RELAXED);
+    int cur = __atomic_load_n(&ctl->next_query, __ATOMIC_RELAXED);
+    int got = -1;
+    while (cur < nq) {
+      const int prev = atomicCAS(&ctl->next_query, cur, cur + 1);
+      if (prev == cur) {
+        got = cur;
+        break;
+      }
+      cur = prev;
+    }
+    claimed = got;
+  }
+  __syncthreads();
+  const int qseq = claimed;
+  if (qseq < 0) return;
+  const int qi = ctl->qcap > 0 ? qseq % ctl->qcap : qseq;  // ring slot of the query
+  const QDesc &d = qd[qi];
+  if (d.trivial) {
+    write_trivial(d, n);
+    if (threadIdx.x == 0) {
+      __threadfence();
+      atomicAdd(&ctl->done, 1);
+    }
+    return;
+  }
+  const Sched &sc = sched[d.sched];
+  for (int r = threadIdx.x; r < kMaxRounds; r += blockDim.x) {
+    sl->T[r] = sc.T[r];
+    sl->alpha[r] = sc.alpha[r];
+  }
+  if (threadIdx.x == 0) {
+    sl->qi = qi;
+    sl->cur = 0;
+    sl->par = 0;
+    sl->implicit = 1;
+    sl->n_act = (int32_t)n;
+    sl->n_xa = 0;
+    sl->n_acc = 0;
+    sl->nn_act = 0;
+    sl->nn_xa = 0;
+    sl->nn_acc = 0;
+    sl->k = d.k;
+    sl->kh = d.kh;
+    sl->R = sc.R;
+    sl->c_exact = d.c_exact;
+    sl->F = d.F;
+    sl->seed = d.seed;
+    sl->W = d.W;
+    sl->q = d.q;
+    sl->rounds = 0;
+    sl->coord_evals = sc.R == 0 ? n * m : n * (int64_t)sc.T[0];
+    sl->exact_points = sc.R == 0 ? n : 0;
+    sl->state = 1;
+  }
+}
+
+template <int DT>
+__global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const QDesc *__restrict__ qd,
+                                               const Sched *__restrict__ sched, Ctl *ctl,
+                                               const uint8_t *__restrict__ X, Bufs B, Geometry G,
+                                               int admit_only) {
+  const int s = blockIdx.x;
+  Slot *sl = &slots[s];
+  const int64_t n = G.n, m = G.m;
+  if (sl->state == 1 && !admit_only) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      sl->n_act = sl->nn_act;
+      sl->n_xa = sl->nn_xa;
+      sl->n_acc = sl->nn_acc;
+      sl->rounds += 1;
+      sl->implicit = 0;
+      sl->par ^= 1;
+    }
+    __syncthreads();
+    const int64_t nP = (int64_t)sl->n_act + sl->n_xa + sl->n_acc;
+    if (ctl->stop_after > 0 && sl->rounds >= ctl->stop_after) {
+      if (threadIdx.x == 0) {
+        sl->state = 2;  // frozen for inspection
+        atomicAdd(&ctl->done, 1);
+      }
+      return;
+    }
+    if (nP <= sl->kh || sl->n_act == 0) {
+      finalize<DT>(sl, s, qd[sl->qi], X, B, G);
+      if (threadIdx.x == 0) {
+        sl->state = 0;
+        atomicAdd(&ctl->done, 1);
+      }
+      __syncthreads();
+    } else {
+      if (threadIdx.x == 0) {
+        const int cur = sl->cur + 1;
+        sl->cur = cur;
+        const int64_t per = cur < sl->R ? (int64_t)(sl->T[cur] - sl->T[cur - 1]) : m;
+        sl->coord_evals += per * sl->n_act;
+        if (cur >= sl->R) sl->exact_points += sl->n_act;
+        sl->nn_act = 0;
+        sl->nn_xa = 0;
+        sl->nn_acc = sl->n_acc;
+      }
+      return;
+    }
+  }
+  if (sl->state == 0) admit(sl, qd, sched, ctl, n, m);
+}
+
+// ---------------------------------------------------------------- launch table
+
+#define KNN_INST_SAMPLE(DT, LPP)                                                                  \
+  template __global__ void k_sample<DT, LPP, true>(Slot *, const uint8_t *, Bufs, Geometry);  \
+  template __global__ void k_sample<DT, LPP, false>(Slot *, const uint8_t *, Bufs, Geometry);
+
+}  // namespace knn
+
+// Host-side launchers (called from the runtime).
+namespace knn {
+
+template <int DT, int LPP>
+static void launch_sample_t(Slot *slots, const uint8_t *X, const Bufs &B, const Geometry &G, bool qlds,
+                            size_t qbytes, hipStream_t st) {
+  dim3 grid((unsigned)((G.n + G.ch_sample - 1) / G.ch_sample), (unsigned)G.nslots);
+  if (qlds)
+    hipLaunchKernelGGL((k_sample<DT, LPP, true>), grid, dim3(NT), qbytes, st, slots, X, B, G);
+  else
+    hipLaunchKernelGGL((k_sample<DT, LPP, false>), grid, dim3(NT), 0, st, slots, X, B, G);
+}
+
+template <int DT>
+static void launch_sample_dt(Slot *slots, const uint8_t *X, const Bufs &B, const Geometry &G, bool qlds,
+                             size_t qbytes, hipStream_t st) {
+  switch (G.lpp) {
+    case 1: launch_sample_t<DT, 1>(slots, X, B, G, qlds, qbytes, st); break;
+    case 2: launch_sample_t<DT, 2>(slots, X, B, G, qlds, qbytes, st); break;
+    case 4: launch_sample_t<DT, 4>(slots, X, B, G, qlds, qbytes, st); break;
+    case 8: launch_sample_t<DT, 8>(slots, X, B, G, qlds, qbytes, st); break;
+    default: launch_sample_t<DT, 16>(slots, X, B, G, qlds, qbytes, st); break;
+  }
+}
+
+void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, double hi, hipStream_t st) {
+  hipLaunchKernelGGL(k_prep_f32, dim3((unsigned)nq), dim3(NT), 0, st, qd, nq, n, m, lo, hi);
+}
+
+void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
+                 const Bufs &B, const Geometry &G0, bool any_cexact, hipStream_t st) {
+  Geometry G = G0;
+  G.prof = prof_device_counters();
+  const int elem = G.dtype == KNN_U8 ? 1 : 4;
+  const size_t qbytes = (size_t)G.m * elem;
+  const bool qlds = qbytes <= 48 * 1024;
+  int tok = prof_begin(PROF_SAMPLE, st);
+  if (G.dtype == KNN_U8)
+    launch_sample_dt<KNN_U8>(slots, X, B, G, qlds, qbytes, st);
+  else
+    launch_sample_dt<KNN_F32>(slots, X, B, G, qlds, qbytes, st);
+  prof_end(tok, st, 0.0);
+  const unsigned ns = (unsigned)G.nslots;
+  if (any_cexact) {
+    tok = prof_begin(PROF_CAND, st);
+    hipLaunchKernelGGL(k_cand_partial, dim3((unsigned)((G.n + CAND_CH - 1) / CAND_CH), ns), dim3(NT), 0, st,
+                       slots, B, G);
+    if (G.dtype == KNN_U8)
+      hipLaunchKernelGGL(k_cand_merge<KNN_U8>, dim3(ns), dim3(MT), 0, st, slots, X, B, G);
+    else
+      hipLaunchKernelGGL(k_cand_merge<KNN_F32>, dim3(ns), dim3(MT), 0, st, slots, X, B, G);
+    prof_end(tok, st, 0.0);
+  }
+  tok = prof_begin(PROF_SELECT, st);
+  hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((G.n + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st,
+                     slots, B, G);
+  hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G);
+  prof_end(tok, st, 0.0);
+  tok = prof_begin(PROF_DECIDE, st);
+  hipLaunchKernelGGL(k_decide, dim3((unsigned)((G.n + DEC_CH - 1) / DEC_CH), ns), dim3(NT), 0, st, slots,
+                     B, G);
+  prof_end(tok, st, 0.0);
+  tok = prof_begin(PROF_FINISH, st);
+  if (G.dtype == KNN_U8)
+    hipLaunchKernelGGL(k_finish<KNN_U8>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, 0);
+  else
+    hipLaunchKernelGGL(k_finish<KNN_F32>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, 0);
+  prof_end(tok, st, 0.0);
+}
+
+void launch_admit(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X, const Bufs &B,
+                  const Geometry &G, hipStream_t st) {
+  const unsigned ns = (unsigned)G.nslots;
+  if (G.dtype == KNN_U8)
+    hipLaunchKernelGGL(k_finish<KNN_U8>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, 1);
+  else
+    hipLaunchKernelGGL(k_finish<KNN_F32>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, 1);
+}
+
+int64_t part_words(int64_t n, int32_t kmax, int32_t cmax) {
+  const int64_t nsel = (n + SEL_CH - 1) / SEL_CH;
+  const int64_t ncand = (n + CAND_CH - 1) / CAND_CH;
+  const int64_t a = nsel * (2 * (int64_t)kmax + 1);
+  const int64_t c = cmax > 0 ? ncand * (int64_t)min(cmax, CAND_CH) * 2 : 0;  // keys + packed ids
+  return (a > c ? a : c) + 8;
+}
+
+}  // namespace knn

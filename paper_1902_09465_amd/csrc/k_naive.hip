@@ -1,0 +1,368 @@
+// k_naive.hip -- the naive scan of Section 3 (all distances, keep the k
+// smallest) as a dense contraction on the gfx950 matrix cores.
+//
+// u8: with x' = x - 128 and q' = q - 128 (int8),
+//       ||x - q||^2 = ||x'||^2 + ||q'||^2 - 2 x'.q',
+//     x'.q' by v_mfma_i32_16x16x64_i8 (exact int32 for m <= 65536), so
+//     distances are exact integers.  The k smallest (distance, index) per
+//     query are kept in LDS while the tile loop streams the points
+//     (fused epilogue, the n-by-nq distance matrix is never stored).
+// f32: (see the f32 section below).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "block_select.h"
+#include "knn_host.h"
+#include "knn_prof.h"
+
+namespace knn {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- DB prep
+
+// u8: int8 copy x - 128 padded with zeros to mp (multiple of 64), and
+// per-row sum of (x - 128)^2.
+__global__ __launch_bounds__(256) void k_prep_u8_rows(const uint8_t *__restrict__ X, int64_t n, int64_t m,
+                                                      int64_t mp, int8_t *__restrict__ xs, int32_t *__restrict__ nrm) {
+  const int64_t i = blockIdx.x;
+  if (i >= n) return;
+  int acc = 0;
+  for (int64_t j = threadIdx.x; j < mp; j += 256) {
+    int v = 0;
+    if (j < m) v = (int)X[i * m + j] - 128;
+    xs[i * mp + j] = (int8_t)v;
+    acc += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ int red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) nrm[i] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_minmax_f32(const float *__restrict__ X, int64_t count, float *out) {
+  float lo = INFINITY, hi = -INFINITY;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < count; p += (int64_t)gridDim.x * 256) {
+    lo = fminf(lo, X[p]);
+    hi = fmaxf(hi, X[p]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, o));
+    hi = fmaxf(hi, __shfl_xor(hi, o));
+  }
+  __shared__ float sl[4], sh[4];
+  if ((threadIdx.x & 63) == 0) {
+    sl[threadIdx.x >> 6] = lo;
+    sh[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = fminf(fminf(sl[0], sl[1]), fminf(sl[2], sl[3]));
+    out[2 * blockIdx.x + 1] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+  }
+}
+
+int db_range_f32(const float *X, int64_t count, double *lo, double *hi, hipStream_t st) {
+  const int nb = 1024;
+  float *d = nullptr;
+  HIP_TRY(hipMalloc(&d, sizeof(float) * 2 * nb));
+  hipLaunchKernelGGL(k_minmax_f32, dim3(nb), dim3(256), 0, st, X, count, d);
+  std::vector<float> h(2 * nb);
+  hipError_t e = hipMemcpy(h.data(), d, sizeof(float) * 2 * nb, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(KNN_EDEVICE, std::string("range: ") + hipGetErrorString(e));
+  float l = INFINITY, u = -INFINITY;
+  for (int b = 0; b < nb; ++b) {
+    l = std::min(l, h[2 * b]);
+    u = std::max(u, h[2 * b + 1]);
+  }
+  *lo = (double)l;
+  *hi = (double)u;
+  return KNN_OK;
+}
+
+int naive_prepare_db(knn_db_s *db, hipStream_t st) {
+  db->mp = (db->m + 63) / 64 * 64;
+  if (db->dtype == KNN_U8) {
+    HIP_TRY(hipMalloc(&db->xs8, (size_t)db->n * db->mp));
+    HIP_TRY(hipMalloc(&db->norm_i, sizeof(int32_t) * db->n));
+    hipLaunchKernelGGL(k_prep_u8_rows, dim3((unsigned)db->n), dim3(256), 0, st, db->X, db->n, db->m, db->mp,
+                       db->xs8, db->norm_i);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return KNN_OK;
+}
+
+void naive_free_db(knn_db_s *db) {
+  if (db->xs8) (void)hipFree(db->xs8);
+  if (db->norm_i) (void)hipFree(db->norm_i);
+  if (db->xbf) (void)hipFree(db->xbf);
+  if (db->norm_f) (void)hipFree(db->norm_f);
+  if (db->rownorm) (void)hipFree(db->rownorm);
+  db->xs8 = nullptr;
+  db->norm_i = nullptr;
+  db->xbf = nullptr;
+  db->norm_f = nullptr;
+  db->rownorm = nullptr;
+}
+
+// ---------------------------------------------------------------- u8 queries
+
+__global__ __launch_bounds__(256) void k_prep_u8_queries(const uint8_t *__restrict__ Q, int64_t m, int64_t mp,
+                                                         int8_t *__restrict__ qs, int32_t *__restrict__ qn) {
+  const int64_t q = blockIdx.x;
+  int acc = 0;
+  for (int64_t j = threadIdx.x; j < mp; j += 256) {
+    int v = 0;
+    if (j < m) v = (int)Q[q * m + j] - 128;
+    qs[q * mp + j] = (int8_t)v;
+    acc += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ int red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) qn[q] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ---------------------------------------------------------------- u8 scan
+
+constexpr int NBQ = 64;    // queries per block tile
+constexpr int NBP = 128;   // points per block tile
+constexpr int NKS = 64;    // k-step (bytes of K per MFMA)
+constexpr int ROWB = 80;   // LDS row stride in bytes (64 + 16 pad)
+constexpr int DSTR = NBP + 4;
+
+// Per-query running top-k (k <= KC, keys (dist << 32 | index)), one wave per
+// query: candidates below the current maximum replace it.
+template <int KC>
+__device__ __forceinline__ void topk_insert(uint64_t *list, int k, uint64_t &tau, uint64_t c0, uint64_t c1) {
+  const int lane = lane_id();
+  bool p0 = c0 < tau, p1 = c1 < tau;
+  uint64_t act = __ballot(p0 || p1);
+  while (act) {
+    const int src = __ffsll((long long)act) - 1;
+    const bool use0 = __shfl((int)p0, src) != 0;
+    const uint64_t cs = use0 ? c0 : c1;
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)cs, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(cs >> 32), src);
+    const uint64_t cand = ((uint64_t)hi << 32) | lo;
+    if (lane == src) {
+      if (use0) p0 = false;
+      else p1 = false;
+    }
+    // replace the slot holding tau (keys are unique)
+#pragma unroll
+    for (int e = 0; e < KC / 64; ++e) {
+      const int j = e * 64 + lane;
+      if (j < k && list[j] == tau) list[j] = cand;
+    }
+    // new maximum
+    uint64_t mx = 0;
+#pragma unroll
+    for (int e = 0; e < KC / 64; ++e) {
+      const int j = e * 64 + lane;
+      if (j < k) mx = list[j] > mx ? list[j] : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t l2 = (uint32_t)__shfl_xor((int)(uint32_t)mx, o);
+      const uint32_t h2 = (uint32_t)__shfl_xor((int)(uint32_t)(mx >> 32), o);
+      const uint64_t v = ((uint64_t)h2 << 32) | l2;
+      mx = v > mx ? v : mx;
+    }
+    tau = mx;
+    p0 = p0 && (c0 < tau);
+    p1 = p1 && (c1 < tau);
+    act = __ballot(p0 || p1);
+  }
+}
+
+template <int KC>
+__global__ __launch_bounds__(256) void k_naive_u8(const int8_t *__restrict__ Q8, const int32_t *__restrict__ qn,
+                                                  const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
+                                                  int64_t nq, int64_t n, int64_t mp, int k, int64_t prange,
+                                                  uint64_t *__restrict__ part, int64_t nranges) {
+  // the GEMM tiles and the distance tile are never live at the same time
+  __shared__ __align__(16) uint8_t tiles[NBQ * DSTR * 4];
+  static_assert((NBQ + NBP) * ROWB <= NBQ * DSTR * 4, "tile union too small");
+  int8_t *As = reinterpret_cast<int8_t *>(tiles);
+  int8_t *Bs = As + NBQ * ROWB;
+  uint32_t *Ds = reinterpret_cast<uint32_t *>(tiles);
+  __shared__ uint64_t L[NBQ * KC];
+  __shared__ uint64_t Tau[NBQ];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int64_t q0 = (int64_t)blockIdx.y * NBQ;
+  const int64_t pr0 = (int64_t)blockIdx.x * prange;
+  const int64_t pr1 = std::min(n, pr0 + prange);
+  // sentinel list entries: unique keys above every real key
+  for (int j = tid; j < NBQ * KC; j += 256) L[j] = ~0ull - (uint64_t)(j % KC);
+  const int wq = wave >> 1, wp = wave & 1;
+  for (int j = tid; j < NBQ; j += 256) Tau[j] = ~0ull;
+  __syncthreads();
+  for (int64_t p0 = pr0; p0 < pr1; p0 += NBP) {
+    v4i acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+    for (int64_t k0 = 0; k0 < mp; k0 += NKS) {
+      {  // A: 64 rows x 64 B, one 16 B piece per thread
+        const int r = tid >> 2, c = (tid & 3) * 16;
+        v4i v = v4i{0, 0, 0, 0};
+        if (q0 + r < nq) v = *reinterpret_cast<const v4i *>(Q8 + (q0 + r) * mp + k0 + c);
+        *reinterpret_cast<v4i *>(As + r * ROWB + c) = v;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {  // B: 128 rows x 64 B
+        const int r = (tid >> 2) + 64 * h, c = (tid & 3) * 16;
+        v4i v = v4i{0, 0, 0, 0};
+        if (p0 + r < pr1) v = *reinterpret_cast<const v4i *>(X8 + (p0 + r) * mp + k0 + c);
+        *reinterpret_cast<v4i *>(Bs + r * ROWB + c) = v;
+      }
+      __syncthreads();
+      v4i af[2], bf[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        af[a] = *reinterpret_cast<const v4i *>(As + (32 * wq + 16 * a + (lane & 15)) * ROWB + 16 * (lane >> 4));
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        bf[b] = *reinterpret_cast<const v4i *>(Bs + (64 * wp + 16 * b + (lane & 15)) * ROWB + 16 * (lane >> 4));
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
+      __syncthreads();
+    }
+    // epilogue: distances of the tile into LDS
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+          const int pl = 64 * wp + 16 * b + (lane & 15);
+          uint32_t d = 0xFFFFFFFFu;
+          if (p0 + pl < pr1 && q0 + ql < nq) {
+            const int64_t dd = (int64_t)qn[q0 + ql] + (int64_t)xn[p0 + pl] - 2 * (int64_t)acc[a][b][v];
+            d = (uint32_t)dd;
+          }
+          Ds[ql * DSTR + pl] = d;
+        }
+    __syncthreads();
+    // per-query top-k, wave `wave` owns queries [16 wave, 16 wave + 16)
+#pragma unroll 1
+    for (int t = 0; t < NBQ / 4; ++t) {
+      const int ql = wave * (NBQ / 4) + t;
+      if (q0 + ql >= nq) break;
+      const uint32_t d0 = Ds[ql * DSTR + lane], d1 = Ds[ql * DSTR + lane + 64];
+      const uint64_t c0 = d0 == 0xFFFFFFFFu ? ~0ull : (((uint64_t)d0 << 32) | (uint64_t)(p0 + lane));
+      const uint64_t c1 = d1 == 0xFFFFFFFFu ? ~0ull : (((uint64_t)d1 << 32) | (uint64_t)(p0 + lane + 64));
+      uint64_t tau = Tau[ql];
+      topk_insert<KC>(L + ql * KC, k, tau, c0, c1);
+      if (lane == 0) Tau[ql] = tau;
+    }
+    __syncthreads();
+  }
+  // the block's k smallest per query -> part[q][range][k]
+  for (int t = 0; t < NBQ / 4; ++t) {
+    const int ql = wave * (NBQ / 4) + t;
+    if (q0 + ql >= nq) break;
+    uint64_t *dst = part + ((q0 + ql) * nranges + blockIdx.x) * (int64_t)k;
+    for (int j = lane; j < k; j += 64) dst[j] = L[ql * KC + j];
+  }
+}
+
+// Merge per query: the k smallest keys over all ranges, sorted; index and
+// distance out.
+__global__ __launch_bounds__(1024) void k_naive_merge(const uint64_t *__restrict__ part, int64_t nranges, int k,
+                                                      int64_t *__restrict__ out_idx, double *__restrict__ out_dist) {
+  const int64_t q = blockIdx.x;
+  const uint64_t *p = part + q * nranges * k;
+  const int64_t N = nranges * k;
+  __shared__ SelScratch ss;
+  __shared__ uint64_t key[kMaxKH];
+  __shared__ int32_t id[kMaxKH];
+  __shared__ int cnt;
+  int less;
+  const uint64_t v = block_kth_gen<1024>(N, [&](int64_t t) { return p[t]; }, k, ss, &less);
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < N; t += 1024) {
+    const uint64_t kk = p[t];
+    if (kk <= v) {  // keys are unique
+      const int pos = atomicAdd(&cnt, 1);
+      if (pos < kMaxKH) {
+        key[pos] = kk;
+        id[pos] = (int32_t)(kk & 0xFFFFFFFFu);
+      }
+    }
+  }
+  __syncthreads();
+  int len = 1;
+  while (len < k) len <<= 1;
+  for (int t = k + (int)threadIdx.x; t < len; t += 1024) {
+    key[t] = ~0ull;
+    id[t] = 0x7FFFFFFF;
+  }
+  block_bitonic_sort<1024>(key, id, len);
+  for (int t = threadIdx.x; t < k; t += 1024) {
+    out_idx[q * k + t] = (int64_t)(key[t] & 0xFFFFFFFFu);
+    if (out_dist) out_dist[q * k + t] = (double)(key[t] >> 32);
+  }
+}
+
+template <int KC>
+static void launch_naive_u8(const int8_t *Q8, const int32_t *qn, const knn_db_s *db, int64_t nq, int k,
+                            int64_t prange, uint64_t *part, int64_t nranges, hipStream_t st) {
+  dim3 grid((unsigned)nranges, (unsigned)((nq + NBQ - 1) / NBQ));
+  hipLaunchKernelGGL(k_naive_u8<KC>, grid, dim3(256), 0, st, Q8, qn, db->xs8, db->norm_i, nq, db->n, db->mp, k,
+                     prange, part, nranges);
+}
+
+static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
+                    hipStream_t st) {
+  if (db->m > 65536) return fail(KNN_EINVAL, "naive u8 scan supports m <= 65536");
+  if (k > 128) return fail(KNN_EINVAL, "naive u8 scan supports k <= 128");
+  const int64_t n = db->n, mp = db->mp;
+  const int64_t qt = (nq + NBQ - 1) / NBQ;
+  // enough blocks to fill 256 CUs a few times over
+  int64_t prange = (n * qt + 1023) / 1024;
+  prange = std::max<int64_t>(NBP, (prange + NBP - 1) / NBP * NBP);
+  const int64_t nranges = (n + prange - 1) / prange;
+  const size_t bytes_q = (size_t)nq * mp + 256, bytes_qn = sizeof(int32_t) * nq + 256,
+               bytes_part = sizeof(uint64_t) * nq * nranges * k;
+  void *ws = nullptr;
+  HIP_TRY(hipMallocAsync(&ws, bytes_q + bytes_qn + bytes_part, st));
+  int8_t *Q8 = (int8_t *)ws;
+  int32_t *qn = (int32_t *)((uint8_t *)ws + bytes_q);
+  uint64_t *part = (uint64_t *)((uint8_t *)ws + bytes_q + bytes_qn);
+  int tok = prof_begin(PROF_NAIVE_REST, st);
+  hipLaunchKernelGGL(k_prep_u8_queries, dim3((unsigned)nq), dim3(256), 0, st, dq, db->m, mp, Q8, qn);
+  prof_end(tok, st, 0.0);
+  tok = prof_begin(PROF_NAIVE_GEMM, st);
+  if (k <= 64)
+    launch_naive_u8<64>(Q8, qn, db, nq, k, prange, part, nranges, st);
+  else
+    launch_naive_u8<128>(Q8, qn, db, nq, k, prange, part, nranges, st);
+  prof_end(tok, st, 2.0 * (double)nq * (double)n * (double)db->m);
+  tok = prof_begin(PROF_NAIVE_REST, st);
+  hipLaunchKernelGGL(k_naive_merge, dim3((unsigned)nq), dim3(1024), 0, st, part, nranges, k, out_idx, out_dist);
+  prof_end(tok, st, 0.0);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipFreeAsync(ws, st));
+  return KNN_OK;
+}
+
+int naive_run(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
+              hipStream_t st) {
+  if (db->dtype == KNN_U8) return naive_u8(db, (const uint8_t *)dq, nq, k, out_idx, out_dist, st);
+  return fail(KNN_EINVAL, "naive f32 scan not available in this build");
+}
+
+}  // namespace knn

@@ -1,0 +1,445 @@
+// knn_api.cpp -- host runtime of libknn: the C ABI of include/knn.h, the DB
+// registry, the host-side schedule and confidence widths, and the slot
+// engine that drives the adaptive kernels round by round.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "knn_host.h"
+
+namespace knn {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+// ------------------------------------------------------------ widths
+
+// Section 4 footnote: beta(u, d') = log(1/d') + 3 log log(1/d') + 1.5 log(1 + log u).
+// Lemma 3 (valid for every delta): beta(u, d') = 2 log(125 log(1.12 u) / d').
+// Section 5: alpha(u) = sqrt(C log(1 + (1 + log u) n / delta) / u).
+// alpha(u) = sqrt(2 beta(u, delta/n) / u) for the first two.
+static double width(int32_t kind, int64_t u, int64_t n, double delta, double c_alpha) {
+  const double du = (double)u;
+  if (kind == 2) return std::sqrt(c_alpha * std::log(1.0 + (1.0 + std::log(du)) * (double)n / delta) / du);
+  const double dp = delta / (double)n;
+  double beta;
+  if (kind == 0 && dp < 0.05) {
+    const double L = std::log(1.0 / dp);
+    beta = L + 3.0 * std::log(L) + 1.5 * std::log(1.0 + std::log(du));
+  } else {
+    beta = 2.0 * std::log(125.0 * std::log(1.12 * du) / dp);
+  }
+  return std::sqrt(2.0 * beta / du);
+}
+
+bool host_schedule(const knn_params &p, int64_t n, int64_t m, Sched &out, std::string &why) {
+  std::memset(&out, 0, sizeof(out));
+  const int32_t b0 = p.b0 == 0 ? 64 : p.b0;
+  const float g = p.growth == 0.0f ? 2.0f : p.growth;
+  const float th = p.theta_exact == 0.0f ? 1.0f : p.theta_exact;
+  if (b0 < 4 || b0 % 4) return why = "b0 must be a positive multiple of 4", false;
+  if (!(g >= 1.0f)) return why = "growth must be >= 1", false;
+  if (!(th > 0.0f)) return why = "theta_exact must be > 0", false;
+  if (!(p.delta > 0.0 && p.delta < 1.0)) return why = "delta must lie in (0,1)", false;
+  if (p.alpha_kind < 0 || p.alpha_kind > 2) return why = "alpha_kind must be 0, 1 or 2", false;
+  if (p.alpha_kind == 2 && !(p.c_alpha > 0.0)) return why = "alpha_kind 2 needs c_alpha > 0", false;
+  if (p.c_exact < 0 || p.c_exact > KNN_MAX_KH) return why = "c_exact out of range", false;
+  // exact threshold ceil(theta m), clipped to [1, m]
+  const double thr_d = std::ceil((double)th * (double)m);
+  int64_t thr = thr_d >= (double)m ? m : (int64_t)thr_d;
+  if (thr < 1) thr = 1;
+  int32_t R = 0;
+  for (int64_t t = b0; t < thr;) {
+    if (R >= kMaxRounds) return why = "round schedule longer than KNN_MAX_ROUNDS", false;
+    out.T[R] = (int32_t)t;
+    out.alpha[R] = width(p.alpha_kind, t, n, p.delta, p.c_alpha);
+    if (!(out.alpha[R] >= 0.0)) return why = "confidence width is not a number", false;
+    ++R;
+    int64_t b = (int64_t)std::ceil((double)t * ((double)g - 1.0));
+    b = (b + 3) / 4 * 4;
+    t += b < 4 ? 4 : b;
+  }
+  out.R = R;
+  return true;
+}
+
+// ------------------------------------------------------------ engine
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static int env_int(const char *name, int dflt) {
+  const char *v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax) {
+  const int64_t pw = part_words(n, kmax, cmax);
+  return (size_t)n * (8 + 1 + 1 + 4 * 2 + 4 * 2 + 4) + (size_t)pw * 8 + sizeof(Slot) + 12 * 256;
+}
+
+int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cmax, int64_t qcap, int64_t nsched,
+                  hipStream_t st, bool async_alloc) {
+  const int64_t n = db->n;
+  const int64_t pw = part_words(n, kmax, cmax);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const size_t o_slots = take(sizeof(Slot) * ns);
+  const size_t o_ctl = take(sizeof(Ctl));
+  const size_t o_qd = take(sizeof(QDesc) * qcap);
+  const size_t o_sched = take(sizeof(Sched) * nsched);
+  const size_t o_S = take((size_t)ns * n * 8);
+  const size_t o_fl = take((size_t)ns * n);
+  const size_t o_ri = take((size_t)ns * n);
+  const size_t o_act = take((size_t)ns * n * 8);
+  const size_t o_xa = take((size_t)ns * n * 8);
+  const size_t o_acc = take((size_t)ns * n * 4);
+  const size_t o_part = take((size_t)ns * pw * 8);
+  void *base = nullptr;
+  if (async_alloc)
+    HIP_TRY(hipMallocAsync(&base, off, st));
+  else
+    HIP_TRY(hipMalloc(&base, off));
+  auto at = [&](size_t o) { return (uint8_t *)base + o; };
+  E.db = db;
+  E.st = st;
+  E.base = base;
+  E.async_alloc = async_alloc;
+  E.slots = (Slot *)at(o_slots);
+  E.ctl = (Ctl *)at(o_ctl);
+  E.qd = (QDesc *)at(o_qd);
+  E.sched = (Sched *)at(o_sched);
+  E.B.S = (int64_t *)at(o_S);
+  E.B.fl = at(o_fl);
+  E.B.ri = at(o_ri);
+  E.B.act = (int32_t *)at(o_act);
+  E.B.xa = (int32_t *)at(o_xa);
+  E.B.acc = (int32_t *)at(o_acc);
+  E.B.part = (uint64_t *)at(o_part);
+  E.B.part_stride = pw;
+  E.B.cand = nullptr;
+  E.G.n = n;
+  E.G.m = db->m;
+  E.G.dtype = db->dtype;
+  E.G.nslots = (int32_t)ns;
+  E.G.ch_sample = std::max(1, env_int("KNN_CH_SAMPLE", 1024));
+  E.G.ch_select = 0;
+  E.G.ch_decide = 0;
+  E.G.lpp = env_int("KNN_LPP", 1);
+  E.ns = ns;
+  E.qcap = qcap;
+  E.nsched = nsched;
+  HIP_TRY(hipMemsetAsync(E.slots, 0, sizeof(Slot) * ns, st));
+  HIP_TRY(hipMemsetAsync(E.ctl, 0, sizeof(Ctl), st));
+  return KNN_OK;
+}
+
+int engine_destroy(Engine &E) {
+  if (!E.base) return KNN_OK;
+  hipError_t e = E.async_alloc ? hipFreeAsync(E.base, E.st) : hipFree(E.base);
+  E.base = nullptr;
+  if (e != hipSuccess) return fail(KNN_EDEVICE, std::string("engine free: ") + hipGetErrorString(e));
+  return KNN_OK;
+}
+
+void engine_step(Engine &E, bool any_cexact) {
+  launch_step(E.slots, E.qd, E.sched, E.ctl, E.db->X, E.B, E.G, any_cexact, E.st);
+}
+
+int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &pp, QDesc &d, Sched &sc) {
+  if (k < 1) return fail(KNN_EINVAL, "k must be >= 1");
+  const int64_t h = pp.h < 0 ? k : pp.h;
+  const int64_t kh = k + h;
+  if (kh > KNN_MAX_KH) return fail(KNN_EINVAL, "k + h exceeds KNN_MAX_KH");
+  std::string why;
+  if (!host_schedule(pp, db->n, db->m, sc, why)) return fail(KNN_EINVAL, why);
+  std::memset(&d, 0, sizeof(d));
+  d.seed = pp.seed;
+  d.k = k;
+  d.kh = (int32_t)kh;
+  d.c_exact = pp.c_exact;
+  d.W = db->dtype == KNN_U8 ? 65025.0 : 0.0;
+  d.F = 0;
+  d.trivial = kh >= db->n ? 1 : 0;
+  return KNN_OK;
+}
+
+struct Prepared {
+  std::vector<QDesc> qd;
+  std::vector<Sched> sched;
+  int32_t kmax = 1, cmax = 0, rmax = 0;
+  bool any_cexact = false;
+};
+
+static int prepare(knn_db_s *db, const void *dq, int64_t nq, const int32_t *host_k, const knn_params *p,
+                   int64_t np, int64_t *out_idx, int64_t out_stride, int32_t *out_count, knn_stats *out_stats,
+                   Prepared &P) {
+  const int64_t n = db->n, m = db->m;
+  const int elem = db->dtype == KNN_U8 ? 1 : 4;
+  std::map<std::string, int> seen;
+  P.qd.resize(nq);
+  for (int64_t q = 0; q < nq; ++q) {
+    const knn_params &pp = p[np == 1 ? 0 : q];
+    QDesc &d = P.qd[q];
+    Sched sc;
+    int rc = make_qdesc(db, host_k[q], pp, d, sc);
+    if (rc != KNN_OK) return rc;
+    if (out_stride < std::min<int64_t>(d.kh, n)) return fail(KNN_EINVAL, "out_stride smaller than k + h");
+    std::string key((const char *)&sc, sizeof(Sched));
+    auto it = seen.find(key);
+    if (it == seen.end()) {
+      d.sched = (int32_t)P.sched.size();
+      P.sched.push_back(sc);
+      seen.emplace(key, d.sched);
+      P.rmax = std::max(P.rmax, sc.R);
+    } else {
+      d.sched = it->second;
+    }
+    d.q = (const uint8_t *)dq + q * m * elem;
+    d.out_idx = out_idx + q * out_stride;
+    d.out_count = out_count + q;
+    d.out_stats = out_stats ? out_stats + q : nullptr;
+    d.out_stride = out_stride;
+    P.kmax = std::max(P.kmax, d.k);
+    P.cmax = std::max(P.cmax, d.c_exact);
+    if (d.c_exact > 0) P.any_cexact = true;
+  }
+  return KNN_OK;
+}
+
+// Runs the slot engine over the prepared queries.  stop_after > 0 freezes
+// slot 0 after that many decide steps (debug state dump) and leaves the
+// engine allocated in *keep.
+static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int32_t stop_after, Engine *keep) {
+  const int64_t n = db->n, m = db->m;
+  const size_t per_slot = engine_slot_bytes(n, P.kmax, P.cmax);
+  size_t freeb = 0, totb = 0;
+  HIP_TRY(hipMemGetInfo(&freeb, &totb));
+  size_t budget = (size_t)(freeb * 0.5);
+  const size_t cap = (size_t)env_int("KNN_SLOT_BUDGET_MB", 65536) << 20;
+  budget = std::min(budget, cap);
+  int64_t ns = (int64_t)(budget / per_slot);
+  ns = std::min<int64_t>(ns, nq);
+  ns = std::min<int64_t>(ns, env_int("KNN_MAX_SLOTS", 65535));
+  if (stop_after > 0) ns = 1;
+  if (ns < 1) return fail(KNN_ENOMEM, "not enough device memory for one query slot");
+  Engine E;
+  int rc = engine_create(E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, true);
+  if (rc != KNN_OK) return rc;
+  Ctl ctl;
+  std::memset(&ctl, 0, sizeof(ctl));
+  ctl.nq = (int32_t)nq;
+  ctl.qcap = (int32_t)nq;
+  ctl.stop_after = stop_after;
+  auto chk = [&](hipError_t e, const char *what) {
+    if (e != hipSuccess && rc == KNN_OK)
+      rc = fail(e == hipErrorOutOfMemory ? KNN_ENOMEM : KNN_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  chk(hipMemcpyAsync(E.ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice, st), "copy ctl");
+  chk(hipMemcpyAsync(E.qd, P.qd.data(), sizeof(QDesc) * nq, hipMemcpyHostToDevice, st), "copy queries");
+  chk(hipMemcpyAsync(E.sched, P.sched.data(), sizeof(Sched) * P.sched.size(), hipMemcpyHostToDevice, st),
+      "copy schedules");
+  if (rc == KNN_OK) {
+    if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, st);
+    launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st);
+    chk(hipGetLastError(), "launch");
+  }
+  const int steps_gen = P.rmax + 1;
+  if (rc == KNN_OK) {
+    if (nq <= ns || stop_after > 0) {
+      for (int t = 0; t < steps_gen; ++t) engine_step(E, P.any_cexact);
+      chk(hipGetLastError(), "launch");
+    } else {
+      // slots are recycled on the device; poll until every query is done
+      const int64_t max_gen = ((nq + ns - 1) / ns + 1) * (P.rmax + 2);
+      int64_t gen = 0;
+      for (;;) {
+        for (int t = 0; t < steps_gen; ++t) engine_step(E, P.any_cexact);
+        chk(hipGetLastError(), "launch");
+        int32_t done = 0;
+        chk(hipMemcpyAsync(&done, &E.ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, st), "poll");
+        chk(hipStreamSynchronize(st), "poll sync");
+        if (rc != KNN_OK || done >= nq) break;
+        if (++gen > max_gen) {
+          rc = fail(KNN_EDEVICE, "adaptive engine made no progress");
+          break;
+        }
+      }
+    }
+  }
+  if (keep && rc == KNN_OK) {
+    *keep = E;
+    return KNN_OK;  // caller frees
+  }
+  const int rc2 = engine_destroy(E);
+  chk(hipStreamSynchronize(st), "hipStreamSynchronize");
+  return rc != KNN_OK ? rc : rc2;
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace knn
+
+using namespace knn;
+
+extern "C" {
+
+void knn_params_default(knn_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->h = -1;
+  p->delta = 0.01;
+  p->seed = 0;
+  p->alpha_kind = 0;
+  p->c_alpha = 0.0;
+  p->b0 = 64;
+  p->growth = 2.0f;
+  p->theta_exact = 1.0f;
+  p->c_exact = 0;
+}
+
+const char *knn_last_error(void) { return g_err.c_str(); }
+
+const char *knn_version(void) { return "libknn 0.1 (gfx950)"; }
+
+int knn_db_create(const void *dev_points, int64_t n, int64_t m, knn_dtype dt, int32_t flags, knn_db *out) {
+  if (!out || !dev_points) return fail(KNN_EINVAL, "NULL argument");
+  if (n < 1 || m < 1 || n >= (int64_t)1 << 31 || m >= (int64_t)1 << 31)
+    return fail(KNN_EINVAL, "n and m must lie in [1, 2^31)");
+  if (dt != KNN_U8 && dt != KNN_F32) return fail(KNN_EINVAL, "bad dtype");
+  if (flags != KNN_DB_BORROW && flags != KNN_DB_COPY) return fail(KNN_EINVAL, "bad flags");
+  knn_db_s *db = new knn_db_s();
+  db->n = n;
+  db->m = m;
+  db->dtype = dt;
+  const size_t bytes = (size_t)n * m * (dt == KNN_U8 ? 1 : 4);
+  hipStream_t st = nullptr;
+  int rc = KNN_OK;
+  if (flags == KNN_DB_COPY || !aligned16(dev_points)) {
+    hipError_t e = hipMalloc(&db->owned, bytes);
+    if (e == hipSuccess) e = hipMemcpy(db->owned, dev_points, bytes, hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+      rc = fail(e == hipErrorOutOfMemory ? KNN_ENOMEM : KNN_EDEVICE, std::string("copy DB: ") + hipGetErrorString(e));
+    }
+    db->X = (const uint8_t *)db->owned;
+  } else {
+    db->X = (const uint8_t *)dev_points;
+  }
+  if (rc == KNN_OK && dt == KNN_F32) rc = db_range_f32((const float *)db->X, n * m, &db->lo, &db->hi, st);
+  if (rc == KNN_OK) rc = naive_prepare_db(db, st);
+  if (rc != KNN_OK) {
+    naive_free_db(db);
+    if (db->owned) (void)hipFree(db->owned);
+    delete db;
+    return rc;
+  }
+  *out = db;
+  return KNN_OK;
+}
+
+int knn_db_destroy(knn_db db) {
+  if (!db) return fail(KNN_EINVAL, "NULL db");
+  if (db->users.load() > 0) return fail(KNN_EBUSY, "DB is held by a session");
+  (void)hipDeviceSynchronize();
+  naive_free_db(db);
+  if (db->owned) (void)hipFree(db->owned);
+  delete db;
+  return KNN_OK;
+}
+
+int knn_db_info(knn_db db, int64_t *n, int64_t *m, int32_t *dtype) {
+  if (!db) return fail(KNN_EINVAL, "NULL db");
+  if (n) *n = db->n;
+  if (m) *m = db->m;
+  if (dtype) *dtype = db->dtype;
+  return KNN_OK;
+}
+
+int knn_schedule(const knn_params *p, int64_t n, int64_t m, int32_t *host_T, double *host_alpha, int32_t *R) {
+  if (!p || !host_T || !host_alpha || !R) return fail(KNN_EINVAL, "NULL argument");
+  if (n < 1 || m < 1) return fail(KNN_EINVAL, "n and m must be >= 1");
+  Sched sc;
+  std::string why;
+  if (!host_schedule(*p, n, m, sc, why)) return fail(KNN_EINVAL, why);
+  for (int r = 0; r < kMaxRounds; ++r) {
+    host_T[r] = sc.T[r];
+    host_alpha[r] = sc.alpha[r];
+  }
+  *R = sc.R;
+  return KNN_OK;
+}
+
+int knn_adaptive(knn_db db, const void *dev_queries, int64_t nq, const int32_t *host_k, const knn_params *p,
+                 int64_t np, int64_t *dev_out_idx, int64_t out_stride, int32_t *dev_out_count,
+                 knn_stats *dev_out_stats, void *stream) {
+  if (!db || !host_k || !p || !dev_out_idx || !dev_out_count) return fail(KNN_EINVAL, "NULL argument");
+  if (nq < 0 || nq >= (int64_t)1 << 31) return fail(KNN_EINVAL, "bad nq");
+  if (nq == 0) return KNN_OK;
+  if (!dev_queries) return fail(KNN_EINVAL, "NULL queries");
+  if (np != 1 && np != nq) return fail(KNN_EINVAL, "np must be 1 or nq");
+  Prepared P;
+  int rc = prepare(db, dev_queries, nq, host_k, p, np, dev_out_idx, out_stride, dev_out_count, dev_out_stats, P);
+  if (rc != KNN_OK) return rc;
+  std::lock_guard<std::mutex> lk(db->mu);
+  return run_engine(db, P, nq, (hipStream_t)stream, 0, nullptr);
+}
+
+int knn_adaptive_state(knn_db db, const void *dev_query, int32_t k, const knn_params *p, int32_t stop_after,
+                       int64_t *host_S, uint8_t *host_fl, uint8_t *host_ri, void *stream) {
+  if (!db || !dev_query || !p || !host_S || !host_fl || !host_ri) return fail(KNN_EINVAL, "NULL argument");
+  if (stop_after < 1) return fail(KNN_EINVAL, "stop_after must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t kh = k + (p->h < 0 ? k : p->h);
+  int64_t *d_idx = nullptr;
+  int32_t *d_cnt = nullptr;
+  HIP_TRY(hipMalloc(&d_idx, sizeof(int64_t) * std::max<int64_t>(kh, 1)));
+  HIP_TRY(hipMalloc(&d_cnt, sizeof(int32_t)));
+  Prepared P;
+  int rc = prepare(db, dev_query, 1, &k, p, 1, d_idx, std::max<int64_t>(kh, 1), d_cnt, nullptr, P);
+  if (rc == KNN_OK && P.qd[0].trivial) rc = fail(KNN_EINVAL, "trivial query (k + h >= n) has no state");
+  Engine E;
+  if (rc == KNN_OK) {
+    std::lock_guard<std::mutex> lk(db->mu);
+    rc = run_engine(db, P, 1, st, stop_after, &E);
+    if (rc == KNN_OK) {
+      const int64_t n = db->n;
+      hipError_t e = hipMemcpyAsync(host_S, E.B.S, n * 8, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(host_fl, E.B.fl, n, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(host_ri, E.B.ri, n, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      const int rc2 = engine_destroy(E);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) rc = fail(KNN_EDEVICE, std::string("state copy: ") + hipGetErrorString(e));
+      else if (rc2 != KNN_OK) rc = rc2;
+    }
+  }
+  (void)hipFree(d_idx);
+  (void)hipFree(d_cnt);
+  return rc;
+}
+
+int knn_naive(knn_db db, const void *dev_queries, int64_t nq, int32_t k, int64_t *dev_out_idx,
+              double *dev_out_dist, void *stream) {
+  if (!db || !dev_out_idx) return fail(KNN_EINVAL, "NULL argument");
+  if (nq < 0 || nq >= (int64_t)1 << 31) return fail(KNN_EINVAL, "bad nq");
+  if (k < 1 || k > KNN_MAX_KH || k > db->n) return fail(KNN_EINVAL, "k must lie in [1, min(n, KNN_MAX_KH)]");
+  if (nq == 0) return KNN_OK;
+  if (!dev_queries) return fail(KNN_EINVAL, "NULL queries");
+  return naive_run(db, dev_queries, nq, k, dev_out_idx, dev_out_dist, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// knn_host.h -- host runtime internals of libknn (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <mutex>
+#include <string>
+
+#include "knn_internal.h"
+
+struct knn_db_s {
+  const uint8_t *X = nullptr;  // [n][m] point-major (u8 or f32 bytes)
+  void *owned = nullptr;       // library allocation when copied
+  int64_t n = 0, m = 0;
+  int32_t dtype = KNN_U8;
+  double lo = 0.0, hi = 0.0;   // f32 value range over all points
+  // naive-scan auxiliaries
+  int8_t *xs8 = nullptr;       // u8: x - 128 as int8, [n][mp] (mp = m padded to 64)
+  int64_t mp = 0;
+  int32_t *norm_i = nullptr;   // u8: sum (x-128)^2 per row
+  uint16_t *xbf = nullptr;     // f32: bf16 copy [n][mp]
+  float *norm_f = nullptr;     // f32: sum x^2 (fp32) per row
+  float *rownorm = nullptr;    // f32: ||x|| per row (for the BF16 error bound)
+  std::atomic<int> users{0};   // sessions holding the DB
+  std::mutex mu;
+};
+
+namespace knn {
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+// Host computation of the round schedule and widths (Section 4 footnote,
+// Lemma 3, Section 5); returns false on invalid parameters.
+bool host_schedule(const knn_params &p, int64_t n, int64_t m, Sched &out, std::string &why);
+
+// A slot engine: device state for `ns` in-flight queries on one DB, plus
+// QDesc/Sched rings of qcap entries.  Used by knn_adaptive (ring = the whole
+// query table) and by the serving session (ring refilled while running).
+struct Engine {
+  knn_db_s *db = nullptr;
+  hipStream_t st = nullptr;
+  void *base = nullptr;
+  bool async_alloc = false;
+  Slot *slots = nullptr;
+  Ctl *ctl = nullptr;
+  QDesc *qd = nullptr;
+  Sched *sched = nullptr;
+  Bufs B{};
+  Geometry G{};
+  int64_t ns = 0, qcap = 0, nsched = 0;
+};
+size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax);
+int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cmax, int64_t qcap, int64_t nsched,
+                  hipStream_t st, bool async_alloc);
+int engine_destroy(Engine &E);
+void engine_step(Engine &E, bool any_cexact);
+// Host-side parameter check + per-query descriptor (no device pointers for the
+// query/outputs are filled here).
+int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &p, QDesc &d, Sched &sc);
+
+// kernels (k_adaptive.hip)
+void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, double hi, hipStream_t st);
+void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
+                 const Bufs &B, const Geometry &G, bool any_cexact, hipStream_t st);
+void launch_admit(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
+                  const Bufs &B, const Geometry &G, hipStream_t st);
+int64_t part_words(int64_t n, int32_t kmax, int32_t cmax);
+
+// kernels (k_naive.hip)
+int naive_prepare_db(knn_db_s *db, hipStream_t st);
+int naive_run(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
+              hipStream_t st);
+void naive_free_db(knn_db_s *db);
+int db_range_f32(const float *X, int64_t count, double *lo, double *hi, hipStream_t st);
+
+}  // namespace knn
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return knn::fail(_e == hipErrorOutOfMemory ? KNN_ENOMEM : KNN_EDEVICE,           \
+                       std::string(#expr) + ": " + hipGetErrorString(_e));             \
+  } while (0)

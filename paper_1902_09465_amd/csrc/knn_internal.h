@@ -1,0 +1,114 @@
+// knn_internal.h -- structures shared by the host runtime and the kernels of
+// libknn.  Device-resident structs are plain data (no pointers to host memory).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/knn.h"
+
+namespace knn {
+
+constexpr int kMaxRounds = KNN_MAX_ROUNDS;
+constexpr int kMaxKH = KNN_MAX_KH;
+
+// Point flags (per query, per point).  The dump format of
+// knn_adaptive_state uses the same bits.
+constexpr uint8_t FL_EXACT = 1;
+constexpr uint8_t FL_ACC = 2;
+constexpr uint8_t FL_DISC = 4;
+
+// Round schedule and widths of one parameter set (host-computed).
+struct Sched {
+  int32_t R;                      // number of sampled rounds; round R is exact
+  int32_t pad;
+  int32_t T[kMaxRounds];          // cumulative sample target of round r
+  double alpha[kMaxRounds];       // confidence width at T[r]
+};
+
+// One query as submitted (device table, filled by the host and, for the
+// f32 range scaling, by k_prep_queries).
+struct QDesc {
+  const void *q;        // [m] query vector
+  uint64_t seed;
+  int32_t k, kh;        // k and k+h
+  int32_t c_exact;
+  int32_t sched;        // index into the Sched table
+  double W;             // sample normaliser: samples s/W lie in [0,1]
+  int32_t F;            // f32 fixed-point shift (0 for u8)
+  int32_t trivial;      // 1: k+h >= n or zero range -> return the first min(n,k+h) indices
+  int64_t *out_idx;     // row of out_stride int64
+  int32_t *out_count;
+  knn_stats *out_stats;
+  int64_t out_stride;
+};
+
+// One in-flight query (a "slot").  All slots advance one round per step.
+struct Slot {
+  int32_t state;        // 0 idle, 1 running
+  int32_t qi;           // query index in the QDesc table
+  int32_t cur;          // current round index (0..R); round R is exact
+  int32_t par;          // which half of the double-buffered lists is current
+  int32_t implicit;     // 1 while the undecided list is the identity 0..n-1
+  int32_t n_act, n_xa, n_acc;   // current list sizes
+  int32_t nn_act, nn_xa, nn_acc; // sizes being built by k_decide
+  int32_t k, kh, R, c_exact;
+  int32_t F, pad0;
+  uint64_t seed;
+  double W;
+  const void *q;
+  double U, L1, L2;     // thresholds of the current snapshot
+  int64_t coord_evals, exact_points;
+  int32_t rounds, pad1;
+  int32_t T[kMaxRounds];
+  double alpha[kMaxRounds];
+};
+
+// Engine control block (device).
+struct Ctl {
+  int32_t next_query;   // admission cursor (monotone)
+  int32_t done;         // finished queries
+  int32_t nq;           // queries submitted so far (the host may raise it between steps)
+  int32_t stop_after;   // > 0: debug stop after that many decide steps (no output)
+  int32_t qcap;         // QDesc/Sched tables are rings of qcap entries (query qi at qi % qcap)
+  int32_t pad[3];
+};
+
+// Device buffers of one engine instance (per-slot arrays are [nslots][n]).
+struct Bufs {
+  int64_t *S;           // running sums
+  uint8_t *fl;          // flags
+  uint8_t *ri;          // round index of last sampled target
+  int32_t *act;         // [nslots][2][n] undecided, still sampled
+  int32_t *xa;          // [nslots][2][n] undecided, exact
+  int32_t *acc;         // [nslots][n] accepted
+  uint64_t *part;       // [nslots][part_stride] per-chunk selection candidates
+  int64_t part_stride;
+  int32_t *cand;        // [nslots][kMaxKH] candidate-exact picks
+};
+
+struct Geometry {
+  int64_t n, m;
+  int32_t dtype;        // KNN_U8 / KNN_F32
+  int32_t nslots;
+  int32_t ch_sample;    // points per sample block
+  int32_t ch_select;    // elements per selection block
+  int32_t ch_decide;    // elements per decide block
+  int32_t lpp;          // lanes per point in sampled rounds
+  uint64_t *prof;       // NULL, or work counters: [0] algorithmic bytes, [1] samples, [2] exact elements
+};
+
+// Order-preserving map of a non-NaN double to uint64 (and back).
+__host__ __device__ inline uint64_t dkey(double x) {
+  if (x == 0.0) x = 0.0;  // canonical +0
+  uint64_t b;
+  __builtin_memcpy(&b, &x, 8);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ inline double dkey_inv(uint64_t k) {
+  uint64_t b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+  double x;
+  __builtin_memcpy(&x, &b, 8);
+  return x;
+}
+
+}  // namespace knn

@@ -1,0 +1,27 @@
+// knn_prof.h -- optional kernel timing for measurement.  When enabled
+// (knn_prof_enable), launchers bracket their hot kernels with HIP events on
+// the stream they launch on, and kernels add their algorithmic work to
+// device counters.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace knn {
+
+enum ProfKind {
+  PROF_SAMPLE = 0,     // k_sample
+  PROF_CAND = 1,       // k_cand_partial + k_cand_merge
+  PROF_SELECT = 2,     // k_select_partial + k_select_merge
+  PROF_DECIDE = 3,     // k_decide
+  PROF_FINISH = 4,     // k_finish
+  PROF_NAIVE_GEMM = 5, // naive MFMA scan with fused top-k
+  PROF_NAIVE_REST = 6, // naive query prep + merge (+ f32 rescoring)
+  PROF_KINDS = 8
+};
+
+bool prof_enabled();
+uint64_t *prof_device_counters();  // NULL unless enabled
+int prof_begin(int kind, hipStream_t st);               // returns a token (or -1)
+void prof_end(int token, hipStream_t st, double units); // units: algorithmic work known on the host
+
+}  // namespace knn

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP adaptive path (through the C ABI) against the CPU
+oracle -- returned sets, statistics and per-round state, bit-exact."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from knn_inputs import antipodal, coherent, gmm_f32, gmm_u8, rng, tiny, uniform_u8
+from tests.helpers import brute_dists, contains_knn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1902_09465_amd as P
+    P.lib()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return P
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def oparams(orc, **kw):
+    return orc.make_params(**kw)
+
+
+def check_query(P, orc, db, X, q, k, **kw):
+    idx, cnt, st = db.adaptive(dev(q[None]), k, P.default_params(**kw))
+    ref, rst = orc.adaptive(X, q, k, oparams(orc, **kw))
+    c = int(cnt.cpu()[0])
+    got = idx.cpu().numpy()[0]
+    assert c == len(ref), (c, len(ref))
+    assert got[:c].tolist() == ref.tolist()
+    assert np.all(got[c:] == -1)
+    s = st[0]
+    assert (int(s["coord_evals"]), int(s["rounds"]), int(s["count"]), int(s["exact_points"])) == \
+        (rst["coord_evals"], rst["rounds"], rst["count"], rst["exact_points"])
+    return ref, rst
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_tiny_config_parity(P, orc, seed):
+    X, Q, planted = tiny(seed=1000 + seed)
+    db = P.KnnDB(dev(X))
+    for c_exact in (0, 10):
+        ref, _ = check_query(P, orc, db, X, Q[0], 5, h=5, delta=0.01, seed=seed, c_exact=c_exact)
+        assert set(planted.tolist()) <= set(ref.tolist())
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_per_round_state_parity(P, orc, dtype):
+    """After every decide step the per-point (S, flags, round) equal the oracle's."""
+    g = rng(77)
+    if dtype == "u8":
+        X, Q = gmm_u8(77, n=5003, m=202, n_centres=6, sigma=25.0, nq=1)
+    else:
+        X, Q = gmm_f32(77, n=5003, m=101, n_centres=6, sigma=0.3, nq=1)
+    db = P.KnnDB(dev(X))
+    kw = dict(h=4, delta=0.05, seed=int(g.integers(1 << 40)), b0=8, growth=1.5, c_exact=3)
+    T = orc.schedule(8, 1.5, 1.0, X.shape[1])
+    for r in range(1, len(T) + 2):
+        S, fl, ri = db.adaptive_state(dev(Q), 6, P.default_params(**kw), r)
+        _, _, (So, flo, rio) = orc.adaptive(X, Q[0], 6, oparams(orc, **kw), stop_after=r, dump=True)
+        assert np.array_equal(fl, flo), f"round {r}: flags differ"
+        assert np.array_equal(S, So), f"round {r}: sums differ"
+        assert np.array_equal(ri, rio), f"round {r}: round index differs"
+
+
+@pytest.mark.parametrize("variant", ["pure", "cexact", "b0_4", "lemma", "calpha", "theta"])
+def test_variants_parity(P, orc, variant):
+    X, Q = gmm_u8(5, n=3000, m=300, n_centres=4, sigma=20.0, nq=3)
+    db = P.KnnDB(dev(X))
+    kw = dict(pure=dict(), cexact=dict(c_exact=8), b0_4=dict(b0=4, growth=3.0),
+              lemma=dict(alpha_kind=1), calpha=dict(alpha_kind=2, c_alpha=0.01),
+              theta=dict(theta_exact=0.4, c_exact=2))[variant]
+    for qi in range(3):
+        check_query(P, orc, db, X, Q[qi], 7, h=3, delta=0.02, seed=qi, **kw)
+
+
+def test_batched_mixed_k_and_params(P, orc):
+    """One call, queries of different k, h, delta and seed: each equals the
+    oracle run alone (the slot engine shares nothing between queries)."""
+    X, Q = gmm_u8(9, n=4097, m=128, n_centres=8, sigma=30.0, nq=40)
+    db = P.KnnDB(dev(X))
+    g = rng(9)
+    ks = g.integers(1, 20, size=40).astype(np.int32)
+    plist = [P.default_params(h=int(g.integers(0, 8)), delta=float(g.choice([0.01, 0.05, 0.2])),
+                              seed=int(g.integers(1 << 62)), c_exact=int(g.choice([0, 0, 5])))
+             for _ in range(40)]
+    idx, cnt, st = db.adaptive(dev(Q), ks, plist)
+    idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
+    for q in range(40):
+        p = plist[q]
+        ref, rst = orc.adaptive(X, Q[q], int(ks[q]), oparams(
+            orc, h=p.h, delta=p.delta, seed=p.seed, c_exact=p.c_exact))
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert int(st[q]["coord_evals"]) == rst["coord_evals"]
+
+
+def test_more_queries_than_slots(P, orc):
+    """Slots are recycled on the device when the queries do not fit at once."""
+    X, Q = gmm_u8(11, n=2500, m=96, n_centres=5, sigma=30.0, nq=23)
+    db = P.KnnDB(dev(X))
+    os.environ["KNN_MAX_SLOTS"] = "4"
+    try:
+        idx, cnt, _ = db.adaptive(dev(Q), 5, P.default_params(h=5, seed=3))
+    finally:
+        del os.environ["KNN_MAX_SLOTS"]
+    idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
+    for q in range(23):
+        ref, _ = orc.adaptive(X, Q[q], 5, oparams(orc, h=5, seed=3))
+        assert idx[q, :cnt[q]].tolist() == ref.tolist()
+
+
+@pytest.mark.parametrize("knob", [("KNN_LPP", v) for v in ("1", "2", "4", "8", "16")] +
+                         [("KNN_CH_SAMPLE", v) for v in ("64", "256", "4096")])
+def test_performance_knobs_do_not_change_results(P, orc, knob):
+    X, Q = gmm_u8(13, n=3001, m=256, n_centres=5, sigma=20.0, nq=4)
+    db = P.KnnDB(dev(X))
+    base = db.adaptive(dev(Q), 6, P.default_params(seed=1, c_exact=4))
+    os.environ[knob[0]] = knob[1]
+    try:
+        alt = db.adaptive(dev(Q), 6, P.default_params(seed=1, c_exact=4))
+    finally:
+        del os.environ[knob[0]]
+    assert torch.equal(base[0], alt[0]) and torch.equal(base[1], alt[1])
+    assert np.array_equal(base[2], alt[2])
+
+
+def test_f32_parity(P, orc):
+    X, Q = gmm_f32(21, n=3000, m=100, n_centres=10, sigma=0.2, nq=4)
+    db = P.KnnDB(dev(X))
+    for qi in range(4):
+        ref, _ = check_query(P, orc, db, X, Q[qi], 5, h=5, delta=0.05, seed=qi, c_exact=(qi % 2) * 10)
+        assert contains_knn(ref, brute_dists(X, Q[qi]), 5, rtol=1e-6)
+
+
+def test_worked_example(P, orc):
+    X, Q, where = antipodal()
+    db = P.KnnDB(dev(X))
+    idx, cnt, st = db.adaptive(dev(Q), 5, P.default_params(h=5, delta=0.01, seed=123))
+    assert sorted(idx.cpu().numpy()[0, :int(cnt[0])].tolist()) == where.tolist()
+    assert int(st[0]["coord_evals"]) == 256_000 and int(st[0]["rounds"]) == 3
+    idx, cnt, st = db.adaptive(dev(Q), 5, P.default_params(h=5, delta=0.01, seed=9, c_exact=10))
+    assert int(st[0]["coord_evals"]) == 74_240
+
+
+def test_edge_cases(P, orc):
+    # n <= k + h: everything, no evaluations
+    X, Q = uniform_u8(1, 7, 16)
+    db = P.KnnDB(dev(X))
+    idx, cnt, st = db.adaptive(dev(Q), 4, P.default_params(h=3))
+    assert int(cnt[0]) == 7 and idx.cpu().numpy()[0].tolist() == list(range(7))
+    # all points identical: every distance ties (oversized stop path)
+    X = np.full((300, 40), 7, dtype=np.uint8)
+    q = np.full((40,), 9, dtype=np.uint8)
+    db = P.KnnDB(dev(X))
+    check_query(P, orc, db, X, q, 4, h=2, seed=1)
+    # coherent data, k = 1, h = 0
+    X, Q = coherent(5, 1500, 100)
+    db = P.KnnDB(dev(X))
+    check_query(P, orc, db, X, Q[0], 1, h=0, seed=2)
+    # f32 with zero range: first k + h indices
+    Xf = np.zeros((50, 8), dtype=np.float32)
+    dbf = P.KnnDB(dev(Xf))
+    idx, cnt, _ = dbf.adaptive(dev(Xf[:1]), 3, P.default_params(h=2))
+    assert idx.cpu().numpy()[0, :5].tolist() == list(range(5))
+
+
+def test_invalid_arguments_raise(P):
+    from paper_1902_09465_amd import KnnError
+    X, Q = uniform_u8(1, 100, 16)
+    db = P.KnnDB(dev(X))
+    with pytest.raises(KnnError):
+        db.adaptive(dev(Q), 0)
+    with pytest.raises(KnnError):
+        db.adaptive(dev(Q), 3, P.default_params(b0=6))
+    with pytest.raises(KnnError):
+        db.adaptive(dev(Q), 3, P.default_params(h=5000))
+
+
+def test_containment_many_seeds(P, orc):
+    """Theorem 1 on the GPU path: over many seeds every returned set contains
+    the k nearest neighbours (tie-aware) and has at most k+h points."""
+    X, Q, _ = tiny(seed=1500, n=1200, m=256)
+    d = brute_dists(X, Q[0])
+    db = P.KnnDB(dev(X))
+    plist = [P.default_params(h=5, delta=0.01, seed=s, c_exact=(s % 2) * 10) for s in range(200)]
+    Qs = np.repeat(Q, 200, axis=0)
+    idx, cnt, _ = db.adaptive(dev(Qs), 5, plist)
+    idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
+    for s in range(200):
+        assert cnt[s] <= 10 and contains_knn(idx[s, :cnt[s]], d, 5)
