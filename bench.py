@@ -31,11 +31,13 @@ METRIC = "k-NN queries/s adaptive vs naive MFMA (true k-NN contained), p50/p99 l
 N, M, NQ, K, H, DELTA = 100_000, 3072, 1024, 10, 10, 0.01
 HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0
-VALU_PEAK_TOPS = 39.3  # 256 CU x 64 lanes x 2.4 GHz, 32-bit VALU ops (one per lane per cycle)
-# algorithmic 32-bit ops per sample: Philox4x32-10 share 20 (10 rounds x (2 mul_lo + 2 mul_hi
-# + 4 xor) / 4 samples), index 1, address 2, difference 1, square 1, 64-bit accumulate 2
-OPS_PER_SAMPLE = 27
-OPS_PER_EXACT_ELEM = 4  # difference, square, 64-bit accumulate
+VALU_PEAK_TOPS = 39.3  # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit VALU lane-ops per second
+# Algorithmic 32-bit ops of the sampled rounds.  Per coordinate draw (shared by
+# all queries with the same seed): Philox4x32-10 share 20 (10 rounds x (2 mul_lo
+# + 2 mul_hi + 4 xor) / 4 draws), index 1, gather address 1.  Per (query, sample):
+# difference, square, accumulate.
+OPS_PER_DRAW = 22
+OPS_PER_PAIR = 3
 
 
 def log(msg):
@@ -154,7 +156,8 @@ def main():
     ok = contained(idx, cnt, X_t, Q_t, nidx, ndist, K)
     n_ok = int(ok.sum().item())
     prof = {}
-    for kind, name in enumerate(["sample", "cand", "select", "decide", "finish"]):
+    for kind, name in ((0, "sample"), (7, "sample_exact_round"), (1, "cand"), (2, "select"), (3, "decide"),
+                       (4, "finish")):
         ms, n_l, u = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         P._lib.check(lib.knn_prof_read(kind, ctypes.byref(ms), ctypes.byref(n_l), ctypes.byref(u)))
         prof[name] = dict(ms=ms.value, launches=n_l.value)
@@ -168,20 +171,26 @@ def main():
     ms_per_step = total_s * 1e3 / args.steps
     value = n_ok / (ms_per_step / 1e3)
 
-    # dominant kernel of the step and its roofline (per-launch averages over the timed steps)
+    # dominant kernel class of the step and its roofline (averages over the timed steps)
     dom = max(prof, key=lambda k_: prof[k_]["ms"])
-    samp = prof["sample"]
-    samples, exact_elems, alg_bytes = float(cnts[1]), float(cnts[2]), float(cnts[0])
-    ops = samples * OPS_PER_SAMPLE + exact_elems * OPS_PER_EXACT_ELEM
-    avg_s = samp["ms"] / max(1, samp["launches"]) / 1e3
-    ops_per_launch = ops / max(1, samp["launches"])
-    achieved = ops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
-    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_sample",
-                "avg_launch_ms": avg_s * 1e3, "launches": samp["launches"],
-                "alg_bytes_per_launch": alg_bytes / max(1, samp["launches"]),
-                "hbm_frac_alg_bytes": (alg_bytes / max(1, samp["launches"]) / avg_s / 1e9) / HBM_PEAK_GBS
-                if avg_s > 0 else 0.0}
+    alg_bytes, pairs, exact_elems, draws = (float(c) for c in cnts)
+    samp, exr = prof["sample"], prof["sample_exact_round"]
+    s_avg = samp["ms"] / max(1, samp["launches"]) / 1e3
+    e_avg = exr["ms"] / max(1, exr["launches"]) / 1e3
+    s_ops = (draws * OPS_PER_DRAW + pairs * OPS_PER_PAIR) / max(1, samp["launches"])
+    e_ops = 2.0 * exact_elems / max(1, exr["launches"])
+    rl_sample = {"bound": "alu", "achieved": s_ops / s_avg / 1e12 if s_avg > 0 else 0.0,
+                 "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
+                 "kernel": "k_sample_grp_u8 (sampled rounds)", "avg_launch_ms": s_avg * 1e3,
+                 "launches": samp["launches"], "ops_per_launch": s_ops,
+                 "alg_bytes_per_launch": alg_bytes / max(1, samp["launches"] + exr["launches"])}
+    rl_sample["frac"] = rl_sample["achieved"] / VALU_PEAK_TOPS
+    rl_exact = {"bound": "mfma", "achieved": e_ops / e_avg / 1e12 if e_avg > 0 else 0.0,
+                "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
+                "kernel": "k_sample_grp_u8 (exact round, int8 MFMA)", "avg_launch_ms": e_avg * 1e3,
+                "launches": exr["launches"], "ops_per_launch": e_ops}
+    rl_exact["frac"] = rl_exact["achieved"] / INT8_PEAK_TOPS
+    roofline = rl_exact if dom == "sample_exact_round" else rl_sample
 
     # ---------------- naive MFMA scan, same batch
     for w in range(args.warmup):
@@ -226,6 +235,9 @@ def main():
         "kernels_ms_per_step": {k_: v["ms"] / args.steps for k_, v in prof.items()},
         "dominant_kernel": dom,
         "roofline": roofline,
+        "roofline_exact_round": rl_exact,
+        "work": {"draws": draws, "query_samples": pairs, "exact_elements": exact_elems,
+                 "alg_bytes": alg_bytes},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on host cores)")

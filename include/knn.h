@@ -187,8 +187,10 @@ int knn_prof_enable(int on);
  * kernel class since the last enable: 0 adaptive sampling (units: bytes),
  * 1 candidate-exact, 2 bound selection, 3 decide/compact, 4 finish/admit,
  * 5 naive MFMA scan (units: integer or floating-point operations, 2 per
- * multiply-add), 6 naive query prep / merge / rescoring.  Waits for the
- * recorded events. */
+ * multiply-add), 6 naive query prep / merge / rescoring, 7 adaptive sampling
+ * launches that run the exact round of a batch whose queries all share one
+ * schedule (such launches are counted here instead of under 0).  Waits for
+ * the recorded events. */
 int knn_prof_read(int32_t kind, double *total_ms, int64_t *launches, double *units);
 
 /* Device work counters since the last enable: [0] algorithmic bytes of the

@@ -15,6 +15,8 @@
 // All decisions use the same IEEE double expressions as the CPU oracle
 // (compiled without FMA contraction); sums are integers, so the result does
 // not depend on launch shape, chunking or atomic order.
+#include <algorithm>
+
 #include "block_select.h"
 #include "knn_internal.h"
 #include "philox.h"
@@ -202,28 +204,24 @@ __global__ __launch_bounds__(NT) void k_prep_f32(QDesc *qd, int32_t nq, int64_t 
 // point of the sampled list, LPP lanes per point (each lane takes every
 // LPP-th block of four draws); or, in the exact round, the exact distance,
 // one wave per point with coalesced row reads.
-template <int DT, int LPP, bool QLDS>
-__global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const uint8_t *__restrict__ X,
-                                               Bufs B, Geometry G) {
-  const int s = blockIdx.y;
-  const Slot *sl = &slots[s];
-  if (sl->state != 1) return;
+template <int DT, bool QLDS, int BT = NT>
+__device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const uint8_t *__restrict__ X,
+                                  const Bufs &B, const Geometry &G, uint8_t *smem) {
   const int64_t n = G.n, m = G.m;
   const int implicit = sl->implicit;
   const int64_t nlist = implicit ? n : sl->n_act;
-  const int64_t base = (int64_t)blockIdx.x * G.ch_sample;
+  const int64_t base = chunk * G.ch_sample;
   if (base >= nlist) return;
   const int64_t end = min(nlist, base + (int64_t)G.ch_sample);
   constexpr int elem = DT == KNN_U8 ? 1 : 4;
-  extern __shared__ __align__(16) uint8_t smem[];
   const uint8_t *qg = reinterpret_cast<const uint8_t *>(sl->q);
   if constexpr (QLDS) {
     const int64_t qb = m * elem;
     if ((qb & 3) == 0 && (((uintptr_t)qg) & 3) == 0) {
-      for (int64_t w = threadIdx.x; w < qb / 4; w += NT)
+      for (int64_t w = threadIdx.x; w < qb / 4; w += BT)
         reinterpret_cast<uint32_t *>(smem)[w] = reinterpret_cast<const uint32_t *>(qg)[w];
     } else {
-      for (int64_t w = threadIdx.x; w < qb; w += NT) smem[w] = qg[w];
+      for (int64_t w = threadIdx.x; w < qb; w += BT) smem[w] = qg[w];
     }
     __syncthreads();
   }
@@ -242,12 +240,13 @@ __global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const u
       const uint64_t B_r = (uint64_t)(sl->T[cur] - (cur ? sl->T[cur - 1] : 0));
       atomicAdd(&G.prof[0], pts * (B_r * elem + 21));
       atomicAdd(&G.prof[1], pts * B_r);
+      atomicAdd(&G.prof[3], pts * B_r);  // every sample is its own draw here
     }
   }
   if (cur >= sl->R) {
     // exact round
     const int wave = threadIdx.x / kWave, lane = lane_id();
-    for (int64_t p = base + wave; p < end; p += NT / kWave) {
+    for (int64_t p = base + wave; p < end; p += BT / kWave) {
       const int32_t i = implicit ? (int32_t)p : a.act[p];
       const uint8_t *row = X + (int64_t)i * m * elem;
       int64_t acc = 0;
@@ -282,6 +281,7 @@ __global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const u
         }
       }
     }
+    __syncthreads();  // smem (the staged query) may be reused by the caller
     return;
   }
   // sampled round
@@ -290,20 +290,27 @@ __global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const u
   const uint32_t blk0 = t0 >> 2, blk1 = t1 >> 2;
   const uint32_t k0 = (uint32_t)sl->seed, k1 = (uint32_t)(sl->seed >> 32);
   const uint32_t mm = (uint32_t)m;
-  const int sub = threadIdx.x % LPP;
-  for (int64_t p = base + threadIdx.x / LPP; p < end; p += NT / LPP) {
+  // lanes per point: enough that every lane draws at least one block of four
+  // samples, up to a whole wave, so a wave's gathers hit one or a few rows
+  int lpp = G.lpp;
+  if (lpp <= 0) {
+    const uint32_t nb = blk1 - blk0;
+    lpp = 1;
+    while (lpp < kWave && (uint32_t)(2 * lpp) <= nb) lpp <<= 1;
+  }
+  const int sub = threadIdx.x % lpp;
+  for (int64_t p = base + threadIdx.x / lpp; p < end; p += BT / lpp) {
     const int32_t i = implicit ? (int32_t)p : a.act[p];
     const uint8_t *row = X + (int64_t)i * m * elem;
     int64_t acc = 0;
-    for (uint32_t b = blk0 + sub; b < blk1; b += LPP) {
+    for (uint32_t b = blk0 + sub; b < blk1; b += lpp) {
       const P4 r = philox10(b, 0u, (uint32_t)i, 0u, k0, k1);
       acc += sample_val<DT>(row, q, coord_of(r.x, mm), F);
       acc += sample_val<DT>(row, q, coord_of(r.y, mm), F);
       acc += sample_val<DT>(row, q, coord_of(r.z, mm), F);
       acc += sample_val<DT>(row, q, coord_of(r.w, mm), F);
     }
-#pragma unroll
-    for (int o = LPP / 2; o > 0; o >>= 1) acc += shfl_xor_i64(acc, o);
+    for (int o = lpp / 2; o > 0; o >>= 1) acc += shfl_xor_i64(acc, o);
     if (sub == 0) {
       if (cur == 0) {
         a.S[i] = acc;
@@ -313,6 +320,346 @@ __global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const u
       }
       a.ri[i] = (uint8_t)cur;
     }
+  }
+  __syncthreads();  // smem (the staged query) may be reused by the caller
+}
+
+template <int DT, bool QLDS>
+__global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const uint8_t *__restrict__ X,
+                                               Bufs B, Geometry G) {
+  // slot-fastest grid: blocks that run together cover the same points for
+  // many queries, so the point rows they gather stay in L2
+  const int s = blockIdx.x;
+  const Slot *sl = &slots[s];
+  if (sl->state != 1) return;
+  extern __shared__ __align__(16) uint8_t smem[];
+  sample_slot_chunk<DT, QLDS>(sl, s, (int64_t)blockIdx.y, X, B, G, smem);
+}
+
+// ---------------------------------------------------------------- grouped sample (u8)
+
+// Sixteen slots that share the seed and the round draw the same coordinates
+// for a point (the draw depends on (seed, point, sample) only), so one block
+// serves all of them: one Philox draw and one gather of x_ij per sample,
+// reused for every query of the group from a transposed query tile in LDS
+// (one 16-byte read gives the sixteen query values at coordinate j).  In the
+// exact round the group computes its sixteen rows of distances on the matrix
+// cores: sum_j (x_ij - q_j)^2 = |x'|^2 + |q'|^2 - 2 x'.q' with x' = x - 128,
+// q' = q - 128, exact in integers (int8 MFMA, int32 accumulation).  Groups
+// whose slots differ in seed or round fall back to the per-slot path.
+// Points are taken in index order; a slot's undecided-and-sampled points
+// are exactly those with no flag set (all points in round 0).
+constexpr int GRP = 16;
+constexpr int GBT = 512;  // threads per block of the grouped kernel
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
+// Sums v[0..GRP) over the LPP lanes of a point (LPP a power of two <= 64)
+// by halving exchanges: at each step a lane keeps one half of its values
+// and receives the partner's copy of that half, so GRP values need about GRP
+// shuffles in total instead of GRP log2(LPP).  Afterwards each lane holds the
+// totals of GRP / min(LPP, GRP) consecutive slots; of the lanes holding the
+// same slots (when LPP > GRP) the one with the low bits clear stores them.
+// Everything is indexed with compile-time constants (no register spills).
+template <int LPP>
+__device__ __forceinline__ void reduce_store(uint32_t (&v)[GRP], int lane, uint32_t act, int g0, int64_t n,
+                                             int32_t i, int cur, const Bufs &B) {
+  constexpr int HALVINGS = (LPP >= GRP) ? 4 : (LPP == 8 ? 3 : LPP == 4 ? 2 : LPP == 2 ? 1 : 0);
+  constexpr int NV = GRP >> HALVINGS;
+  int base = 0;
+#pragma unroll
+  for (int st = 0; st < HALVINGS; ++st) {
+    const int d = LPP >> (st + 1);
+    const int half = GRP >> (st + 1);
+    const bool up = (lane & d) != 0;
+#pragma unroll
+    for (int k = 0; k < half; ++k) {
+      const uint32_t send = up ? v[k] : v[k + half];
+      const uint32_t recv = (uint32_t)__shfl_xor((int)send, d);
+      v[k] = (up ? v[k + half] : v[k]) + recv;
+    }
+    if (up) base += half;
+  }
+  int dup = 0;
+#pragma unroll
+  for (int d = (LPP >> (HALVINGS + 1)); d > 0; d >>= 1) {
+    v[0] += (uint32_t)__shfl_xor((int)v[0], d);
+    dup |= d;
+  }
+  if (lane & dup) return;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int g = base + k;
+    if (!(act & (1u << g))) continue;
+    const int64_t off = (int64_t)(g0 + g) * n + i;
+    if (cur == 0) {
+      B.S[off] = (int64_t)v[k];
+      B.fl[off] = 0;
+    } else {
+      B.S[off] += (int64_t)v[k];
+    }
+    B.ri[off] = (uint8_t)cur;
+  }
+}
+
+__global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k_sample_grp_u8(Slot *__restrict__ slots, const uint8_t *__restrict__ X,
+                                                      const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
+                                                      int64_t mp, Bufs B, Geometry G) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ int s_mode, s_cur, s_impl;
+  __shared__ uint32_t s_run;
+  __shared__ uint64_t s_seed;
+  __shared__ uint32_t s_t0, s_t1;
+  __shared__ int64_t s_qn[GBT / kWave];
+  const int g0 = blockIdx.x * GRP;
+  const int64_t n = G.n, m = G.m;
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    int mode = 1, cur = 0, impl = 0;
+    uint64_t seed = 0;
+    uint32_t t0 = 0, t1 = 0;
+    for (int g = 0; g < GRP; ++g) {
+      const int s = g0 + g;
+      if (s >= G.nslots || slots[s].state != 1) continue;
+      const Slot *sl = &slots[s];
+      const int c = sl->cur;
+      const bool exact = c >= sl->R;
+      const uint32_t a0 = exact ? 0u : (c ? (uint32_t)sl->T[c - 1] : 0u);
+      const uint32_t a1 = exact ? 0u : (uint32_t)sl->T[c];
+      if (run == 0) {
+        cur = c;
+        seed = sl->seed;
+        impl = sl->implicit;
+        t0 = a0;
+        t1 = a1;
+        mode = exact ? 2 : 1;
+      } else if (c != cur || (exact ? 2 : 1) != mode || sl->implicit != impl ||
+                 (!exact && (sl->seed != seed || a0 != t0 || a1 != t1))) {
+        mode = 0;
+      }
+      run |= 1u << g;
+    }
+    s_run = run;
+    s_mode = run ? mode : -1;
+    s_cur = cur;
+    s_impl = impl;
+    s_seed = seed;
+    s_t0 = t0;
+    s_t1 = t1;
+  }
+  __syncthreads();
+  const int mode = s_mode;
+  if (mode < 0) return;
+  const uint32_t run = s_run;
+  if (mode == 0 || (mode == 2 && m > 65536)) {
+    for (int g = 0; g < GRP; ++g)
+      if (run & (1u << g))
+        sample_slot_chunk<KNN_U8, true, GBT>(&slots[g0 + g], g0 + g, (int64_t)blockIdx.y, X, B, G, smem);
+    return;
+  }
+  const int64_t base = (int64_t)blockIdx.y * G.ch_sample;
+  if (base >= n) return;
+  const int64_t end = min(n, base + (int64_t)G.ch_sample);
+  const int cur = s_cur;
+  const int impl = s_impl;
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  if (mode == 1) {
+    // queries transposed into LDS: qT[j * GRP + g]
+    for (int g = 0; g < GRP; ++g) {
+      const uint8_t *qg = (run & (1u << g)) ? reinterpret_cast<const uint8_t *>(slots[g0 + g].q) : nullptr;
+      for (int64_t j = threadIdx.x; j < m; j += GBT) smem[j * GRP + g] = qg ? qg[j] : 0;
+    }
+    __syncthreads();
+    const uint32_t blk0 = s_t0 >> 2, blk1 = s_t1 >> 2;
+    const uint64_t seed = s_seed;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t mm = (uint32_t)m;
+    int lpp = G.lpp;
+    if (lpp <= 0) {  // about sixteen blocks of draws per lane amortise the per-point work
+      const uint32_t nb = blk1 - blk0;
+      lpp = 1;
+      while (lpp < kWave && (uint32_t)(32 * lpp) <= nb) lpp <<= 1;
+    }
+    const int sub = threadIdx.x % lpp;
+    // per-lane sums stay 32-bit; so does the per-point total of a round as
+    // long as B * 255^2 < 2^32
+    const bool narrow = (uint64_t)(s_t1 - s_t0) * 65025ull < (1ull << 32);
+    uint64_t my_pairs = 0, my_pts = 0;
+    for (int64_t p = base + threadIdx.x / lpp; p < end; p += GBT / lpp) {
+      const int32_t i = (int32_t)p;
+      uint32_t act = 0;
+      if (impl) {
+        act = run;
+      } else {
+        const uint8_t *f = B.fl + (int64_t)g0 * n + i;
+#pragma unroll 1
+        for (int g = 0; g < GRP; ++g, f += n)
+          if ((run & (1u << g)) && *f == 0) act |= 1u << g;
+      }
+      if (act == 0) continue;  // uniform within the lanes of this point
+      const uint8_t *row = X + (int64_t)i * m;
+      uint32_t acc[GRP];
+#pragma unroll
+      for (int g = 0; g < GRP; ++g) acc[g] = 0;
+      // software pipelined: the next block's draws, gathers and LDS reads
+      // are in flight while the current block is accumulated
+      uint32_t b = blk0 + sub;
+      int xc[4];
+      uint4 qc[4];
+      if (b < blk1) {
+        const P4 r = philox10(b, 0u, (uint32_t)i, 0u, k0, k1);
+        const uint32_t js[4] = {coord_of(r.x, mm), coord_of(r.y, mm), coord_of(r.z, mm), coord_of(r.w, mm)};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          xc[e] = (int)row[js[e]];
+          qc[e] = *reinterpret_cast<const uint4 *>(smem + (size_t)js[e] * GRP);
+        }
+      }
+      for (; b < blk1; b += lpp) {
+        int xn_[4];
+        uint4 qn_[4];
+        const uint32_t bn = b + lpp;
+        if (bn < blk1) {
+          const P4 r = philox10(bn, 0u, (uint32_t)i, 0u, k0, k1);
+          const uint32_t js[4] = {coord_of(r.x, mm), coord_of(r.y, mm), coord_of(r.z, mm), coord_of(r.w, mm)};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            xn_[e] = (int)row[js[e]];
+            qn_[e] = *reinterpret_cast<const uint4 *>(smem + (size_t)js[e] * GRP);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t w4[4] = {qc[e].x, qc[e].y, qc[e].z, qc[e].w};
+#pragma unroll
+          for (int g = 0; g < GRP; ++g) {
+            const int d = xc[e] - (int)((w4[g >> 2] >> (8 * (g & 3))) & 255u);
+            acc[g] += (uint32_t)(d * d);
+          }
+        }
+        if (bn < blk1) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            xc[e] = xn_[e];
+            qc[e] = qn_[e];
+          }
+        }
+      }
+      if (narrow) {
+        switch (lpp) {
+          case 1: reduce_store<1>(acc, lane, act, g0, n, i, cur, B); break;
+          case 2: reduce_store<2>(acc, lane, act, g0, n, i, cur, B); break;
+          case 4: reduce_store<4>(acc, lane, act, g0, n, i, cur, B); break;
+          case 8: reduce_store<8>(acc, lane, act, g0, n, i, cur, B); break;
+          case 16: reduce_store<16>(acc, lane, act, g0, n, i, cur, B); break;
+          case 32: reduce_store<32>(acc, lane, act, g0, n, i, cur, B); break;
+          default: reduce_store<64>(acc, lane, act, g0, n, i, cur, B); break;
+        }
+        if (sub == 0) {
+          my_pts += 1;
+          my_pairs += (uint64_t)__popc(act);
+        }
+      } else {
+        // rounds long enough to overflow 32 bits: 64-bit totals, lane 0 writes
+        uint64_t tot[GRP];
+#pragma unroll
+        for (int g = 0; g < GRP; ++g) {
+          tot[g] = acc[g];
+          for (int o = lpp / 2; o > 0; o >>= 1) tot[g] += (uint64_t)shfl_xor_i64((int64_t)tot[g], o);
+        }
+        if (sub == 0) {
+          my_pts += 1;
+          for (int g = 0; g < GRP; ++g) {
+            if (!(act & (1u << g))) continue;
+            const int64_t off = (int64_t)(g0 + g) * n + i;
+            if (cur == 0) {
+              B.S[off] = (int64_t)tot[g];
+              B.fl[off] = 0;
+            } else {
+              B.S[off] += (int64_t)tot[g];
+            }
+            B.ri[off] = (uint8_t)cur;
+            my_pairs += 1;
+          }
+        }
+      }
+    }
+    if (G.prof) {
+      const uint64_t B_r = (uint64_t)(s_t1 - s_t0);
+      if (my_pairs) {
+        atomicAdd(&G.prof[0], my_pairs * (B_r + 21));
+        atomicAdd(&G.prof[1], my_pairs * B_r);
+      }
+      if (my_pts) atomicAdd(&G.prof[3], my_pts * B_r);
+    }
+    return;
+  }
+  // mode 2: exact round on the matrix cores.  Shifted int8 queries,
+  // row-major [GRP][mp] in LDS (zero rows for idle slots, zero padding).
+  int8_t *Qs = reinterpret_cast<int8_t *>(smem);
+  int64_t *qn_s = reinterpret_cast<int64_t *>(smem + (size_t)GRP * mp);
+  for (int g = 0; g < GRP; ++g) {
+    const uint8_t *qg = (run & (1u << g)) ? reinterpret_cast<const uint8_t *>(slots[g0 + g].q) : nullptr;
+    int64_t part = 0;
+    for (int64_t j = threadIdx.x; j < mp; j += GBT) {
+      const int v = (qg && j < m) ? (int)qg[j] - 128 : 0;
+      Qs[(int64_t)g * mp + j] = (int8_t)v;
+      part += v * v;
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) part += shfl_xor_i64(part, o);
+    if (lane == 0) s_qn[wave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t t = 0;
+      for (int w = 0; w < GBT / kWave; ++w) t += s_qn[w];
+      qn_s[g] = t;
+    }
+    __syncthreads();
+  }
+  uint64_t my_pairs = 0;
+  const int64_t ntile = (end - base + 15) / 16;
+  for (int64_t t = wave; t < ntile; t += GBT / kWave) {
+    const int64_t p0 = base + 16 * t;
+    const int64_t prow = p0 + (lane & 15);
+    const bool pin = prow < end;
+    v4i_t acc = v4i_t{0, 0, 0, 0};
+    const int8_t *qrow = Qs + (int64_t)(lane & 15) * mp + 16 * (lane >> 4);
+    const int8_t *xrow = X8 + (pin ? prow : 0) * mp + 16 * (lane >> 4);
+    int64_t k0 = 0;
+    for (; k0 + 256 <= mp; k0 += 256) {  // four k-steps per batch of loads
+      v4i_t b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        b[u] = pin ? *reinterpret_cast<const v4i_t *>(xrow + k0 + 64 * u) : v4i_t{0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(*reinterpret_cast<const v4i_t *>(qrow + k0 + 64 * u), b[u],
+                                                    acc, 0, 0, 0);
+    }
+    for (; k0 < mp; k0 += 64) {
+      const v4i_t a = *reinterpret_cast<const v4i_t *>(qrow + k0);
+      const v4i_t b = pin ? *reinterpret_cast<const v4i_t *>(xrow + k0) : v4i_t{0, 0, 0, 0};
+      acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc, 0, 0, 0);
+    }
+    // lane holds D[g = 4 (lane / 16) + v][point p0 + lane % 16]
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int g = 4 * (lane >> 4) + v;
+      if (!pin || !(run & (1u << g))) continue;
+      const int64_t off = (int64_t)(g0 + g) * n + prow;
+      if (!impl && B.fl[off] != 0) continue;  // not an undecided sampled point of slot g
+      B.S[off] = qn_s[g] + (int64_t)xn[prow] - 2 * (int64_t)acc[v];
+      if (cur == 0) {
+        B.fl[off] = FL_EXACT;
+        B.ri[off] = 0;
+      } else {
+        B.fl[off] = FL_EXACT;
+      }
+      my_pairs += 1;
+    }
+  }
+  if (G.prof && my_pairs) {
+    atomicAdd(&G.prof[0], my_pairs * (uint64_t)(m + 14));
+    atomicAdd(&G.prof[2], my_pairs * (uint64_t)m);
   }
 }
 
@@ -826,35 +1173,19 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
 
 // ---------------------------------------------------------------- launch table
 
-#define KNN_INST_SAMPLE(DT, LPP)                                                                  \
-  template __global__ void k_sample<DT, LPP, true>(Slot *, const uint8_t *, Bufs, Geometry);  \
-  template __global__ void k_sample<DT, LPP, false>(Slot *, const uint8_t *, Bufs, Geometry);
-
 }  // namespace knn
 
 // Host-side launchers (called from the runtime).
 namespace knn {
 
-template <int DT, int LPP>
-static void launch_sample_t(Slot *slots, const uint8_t *X, const Bufs &B, const Geometry &G, bool qlds,
-                            size_t qbytes, hipStream_t st) {
-  dim3 grid((unsigned)((G.n + G.ch_sample - 1) / G.ch_sample), (unsigned)G.nslots);
-  if (qlds)
-    hipLaunchKernelGGL((k_sample<DT, LPP, true>), grid, dim3(NT), qbytes, st, slots, X, B, G);
-  else
-    hipLaunchKernelGGL((k_sample<DT, LPP, false>), grid, dim3(NT), 0, st, slots, X, B, G);
-}
-
 template <int DT>
 static void launch_sample_dt(Slot *slots, const uint8_t *X, const Bufs &B, const Geometry &G, bool qlds,
                              size_t qbytes, hipStream_t st) {
-  switch (G.lpp) {
-    case 1: launch_sample_t<DT, 1>(slots, X, B, G, qlds, qbytes, st); break;
-    case 2: launch_sample_t<DT, 2>(slots, X, B, G, qlds, qbytes, st); break;
-    case 4: launch_sample_t<DT, 4>(slots, X, B, G, qlds, qbytes, st); break;
-    case 8: launch_sample_t<DT, 8>(slots, X, B, G, qlds, qbytes, st); break;
-    default: launch_sample_t<DT, 16>(slots, X, B, G, qlds, qbytes, st); break;
-  }
+  dim3 grid((unsigned)G.nslots, (unsigned)((G.n + G.ch_sample - 1) / G.ch_sample));
+  if (qlds)
+    hipLaunchKernelGGL((k_sample<DT, true>), grid, dim3(NT), qbytes, st, slots, X, B, G);
+  else
+    hipLaunchKernelGGL((k_sample<DT, false>), grid, dim3(NT), 0, st, slots, X, B, G);
 }
 
 void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, double hi, hipStream_t st) {
@@ -862,17 +1193,22 @@ void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, dou
 }
 
 void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
-                 const Bufs &B, const Geometry &G0, bool any_cexact, hipStream_t st) {
+                 const Bufs &B, const Geometry &G0, bool any_cexact, hipStream_t st, int sample_kind) {
   Geometry G = G0;
   G.prof = prof_device_counters();
   const int elem = G.dtype == KNN_U8 ? 1 : 4;
   const size_t qbytes = (size_t)G.m * elem;
   const bool qlds = qbytes <= 48 * 1024;
-  int tok = prof_begin(PROF_SAMPLE, st);
-  if (G.dtype == KNN_U8)
+  int tok = prof_begin(sample_kind == 1 ? PROF_EXACT : PROF_SAMPLE, st);
+  if (G.dtype == KNN_U8 && G.grouped) {
+    const size_t gbytes = std::max<size_t>((size_t)GRP * G.mp + 8 * GRP, qbytes);
+    dim3 grid((unsigned)((G.nslots + GRP - 1) / GRP), (unsigned)((G.n + G.ch_sample - 1) / G.ch_sample));
+    hipLaunchKernelGGL(k_sample_grp_u8, grid, dim3(GBT), gbytes, st, slots, X, G.x8, G.xn, G.mp, B, G);
+  } else if (G.dtype == KNN_U8) {
     launch_sample_dt<KNN_U8>(slots, X, B, G, qlds, qbytes, st);
-  else
+  } else {
     launch_sample_dt<KNN_F32>(slots, X, B, G, qlds, qbytes, st);
+  }
   prof_end(tok, st, 0.0);
   const unsigned ns = (unsigned)G.nslots;
   if (any_cexact) {

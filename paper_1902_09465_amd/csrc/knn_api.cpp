@@ -89,7 +89,7 @@ size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax) {
 }
 
 int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cmax, int64_t qcap, int64_t nsched,
-                  hipStream_t st, bool async_alloc) {
+                  hipStream_t st, bool async_alloc, bool grouped) {
   const int64_t n = db->n;
   const int64_t pw = part_words(n, kmax, cmax);
   size_t off = 0;
@@ -136,10 +136,18 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.G.m = db->m;
   E.G.dtype = db->dtype;
   E.G.nslots = (int32_t)ns;
-  E.G.ch_sample = std::max(1, env_int("KNN_CH_SAMPLE", 1024));
+  E.G.ch_sample = std::max(1, env_int("KNN_CH_SAMPLE", 2048));
   E.G.ch_select = 0;
   E.G.ch_decide = 0;
-  E.G.lpp = env_int("KNN_LPP", 1);
+  E.G.lpp = env_int("KNN_LPP", 0);  // 0: chosen per round from its sample count
+  if (E.G.lpp < 0 || E.G.lpp > 64 || (E.G.lpp & (E.G.lpp - 1)) != 0) E.G.lpp = 0;
+  E.G.prof = nullptr;
+  E.G.x8 = db->xs8;
+  E.G.xn = db->norm_i;
+  E.G.mp = db->mp;
+  // grouped sampling needs the shared query tile (16 rows of mp bytes) in LDS
+  E.G.grouped = (grouped && db->dtype == KNN_U8 && db->xs8 && 16 * db->mp + 128 <= 65536 &&
+                 env_int("KNN_GROUP", 1) != 0) ? 1 : 0;
   E.ns = ns;
   E.qcap = qcap;
   E.nsched = nsched;
@@ -156,8 +164,8 @@ int engine_destroy(Engine &E) {
   return KNN_OK;
 }
 
-void engine_step(Engine &E, bool any_cexact) {
-  launch_step(E.slots, E.qd, E.sched, E.ctl, E.db->X, E.B, E.G, any_cexact, E.st);
+void engine_step(Engine &E, bool any_cexact, int sample_kind) {
+  launch_step(E.slots, E.qd, E.sched, E.ctl, E.db->X, E.B, E.G, any_cexact, E.st, sample_kind);
 }
 
 int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &pp, QDesc &d, Sched &sc) {
@@ -238,7 +246,12 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
   if (stop_after > 0) ns = 1;
   if (ns < 1) return fail(KNN_ENOMEM, "not enough device memory for one query slot");
   Engine E;
-  int rc = engine_create(E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, true);
+  // queries that share seed and schedule draw identical coordinates: let
+  // the sampling kernel serve them in groups
+  bool same = true;
+  for (int64_t q = 1; q < nq && same; ++q)
+    same = P.qd[q].seed == P.qd[0].seed && P.qd[q].sched == P.qd[0].sched;
+  int rc = engine_create(E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, true, same);
   if (rc != KNN_OK) return rc;
   Ctl ctl;
   std::memset(&ctl, 0, sizeof(ctl));
@@ -261,7 +274,11 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
   const int steps_gen = P.rmax + 1;
   if (rc == KNN_OK) {
     if (nq <= ns || stop_after > 0) {
-      for (int t = 0; t < steps_gen; ++t) engine_step(E, P.any_cexact);
+      // every query starts together: with one shared schedule, step t runs
+      // round t for all of them (timing label only)
+      const bool lockstep = P.sched.size() == 1;
+      for (int t = 0; t < steps_gen; ++t)
+        engine_step(E, P.any_cexact, (lockstep && t == P.rmax) ? 1 : 0);
       chk(hipGetLastError(), "launch");
     } else {
       // slots are recycled on the device; poll until every query is done

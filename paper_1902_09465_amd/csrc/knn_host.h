@@ -52,9 +52,9 @@ struct Engine {
 };
 size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax);
 int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cmax, int64_t qcap, int64_t nsched,
-                  hipStream_t st, bool async_alloc);
+                  hipStream_t st, bool async_alloc, bool grouped);
 int engine_destroy(Engine &E);
-void engine_step(Engine &E, bool any_cexact);
+void engine_step(Engine &E, bool any_cexact, int sample_kind = 0);
 // Host-side parameter check + per-query descriptor (no device pointers for the
 // query/outputs are filled here).
 int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &p, QDesc &d, Sched &sc);
@@ -62,7 +62,7 @@ int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &p, QDesc &d, Sch
 // kernels (k_adaptive.hip)
 void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, double hi, hipStream_t st);
 void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
-                 const Bufs &B, const Geometry &G, bool any_cexact, hipStream_t st);
+                 const Bufs &B, const Geometry &G, bool any_cexact, hipStream_t st, int sample_kind = 0);
 void launch_admit(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
                   const Bufs &B, const Geometry &G, hipStream_t st);
 int64_t part_words(int64_t n, int32_t kmax, int32_t cmax);

@@ -94,7 +94,13 @@ struct Geometry {
   int32_t ch_select;    // elements per selection block
   int32_t ch_decide;    // elements per decide block
   int32_t lpp;          // lanes per point in sampled rounds
-  uint64_t *prof;       // NULL, or work counters: [0] algorithmic bytes, [1] samples, [2] exact elements
+  uint64_t *prof;       // NULL, or work counters: [0] algorithmic bytes, [1] samples, [2] exact
+                        // elements, [3] distinct Philox draws x 4
+  const int8_t *x8;     // u8 DB: x - 128 as int8, [n][mp] (exact round on the matrix cores)
+  const int32_t *xn;    // u8 DB: sum (x - 128)^2 per row
+  int64_t mp;           // m padded to a multiple of 64
+  int32_t grouped;      // 1: sample GRP slots per block when they share seed and round
+  int32_t pad0;
 };
 
 // Order-preserving map of a non-NaN double to uint64 (and back).

@@ -16,6 +16,7 @@ enum ProfKind {
   PROF_FINISH = 4,     // k_finish
   PROF_NAIVE_GEMM = 5, // naive MFMA scan with fused top-k
   PROF_NAIVE_REST = 6, // naive query prep + merge (+ f32 rescoring)
+  PROF_EXACT = 7,      // k_sample launches of a lock-step batch's exact round
   PROF_KINDS = 8
 };
 

@@ -227,7 +227,8 @@ int knn_session_add_db(knn_session S, knn_db db, int32_t *db_id) {
   ns = std::max<int64_t>(1, std::min<int64_t>(ns, kSessionMaxSlots));
   D->qcap = 2 * ns;
   HIP_TRY(hipStreamCreateWithFlags(&D->st, hipStreamNonBlocking));
-  int rc = engine_create(D->E, db, ns, (int32_t)kSessionMaxKH, (int32_t)kSessionMaxKH, D->qcap, D->qcap, D->st, false);
+  int rc = engine_create(D->E, db, ns, (int32_t)kSessionMaxKH, (int32_t)kSessionMaxKH, D->qcap, D->qcap, D->st, false,
+                         false);
   if (rc != KNN_OK) {
     (void)hipStreamDestroy(D->st);
     return rc;

@@ -118,8 +118,8 @@ def test_more_queries_than_slots(P, orc):
         assert idx[q, :cnt[q]].tolist() == ref.tolist()
 
 
-@pytest.mark.parametrize("knob", [("KNN_LPP", v) for v in ("1", "2", "4", "8", "16")] +
-                         [("KNN_CH_SAMPLE", v) for v in ("64", "256", "4096")])
+@pytest.mark.parametrize("knob", [("KNN_LPP", v) for v in ("1", "2", "4", "8", "16", "32", "64")] +
+                         [("KNN_CH_SAMPLE", v) for v in ("64", "256", "4096")] + [("KNN_GROUP", "0")])
 def test_performance_knobs_do_not_change_results(P, orc, knob):
     X, Q = gmm_u8(13, n=3001, m=256, n_centres=5, sigma=20.0, nq=4)
     db = P.KnnDB(dev(X))
@@ -197,3 +197,24 @@ def test_containment_many_seeds(P, orc):
     idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
     for s in range(200):
         assert cnt[s] <= 10 and contains_knn(idx[s, :cnt[s]], d, 5)
+
+
+def test_grouped_shared_seed_batch(P, orc):
+    """64 queries with one seed: the sampling kernel serves them sixteen at a
+    time (shared draws and gathers; exact round on the matrix cores).  Every
+    query equals the oracle, and equals the ungrouped path."""
+    X, Q = gmm_u8(61, n=20011, m=1000, n_centres=12, sigma=30.0, nq=64)
+    db = P.KnnDB(dev(X))
+    p = P.default_params(h=10, delta=0.01, seed=99, c_exact=0)
+    idx, cnt, st = db.adaptive(dev(Q), 10, p)
+    os.environ["KNN_GROUP"] = "0"
+    try:
+        idx2, cnt2, st2 = db.adaptive(dev(Q), 10, p)
+    finally:
+        del os.environ["KNN_GROUP"]
+    assert torch.equal(idx, idx2) and np.array_equal(st, st2)
+    idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
+    for q in range(0, 64, 9):
+        ref, rst = orc.adaptive(X, Q[q], 10, oparams(orc, h=10, delta=0.01, seed=99))
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert int(st[q]["coord_evals"]) == rst["coord_evals"]
