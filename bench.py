@@ -161,7 +161,7 @@ def main():
         ms, n_l, u = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         P._lib.check(lib.knn_prof_read(kind, ctypes.byref(ms), ctypes.byref(n_l), ctypes.byref(u)))
         prof[name] = dict(ms=ms.value, launches=n_l.value)
-    cnts = np.zeros(4, dtype=np.uint64)
+    cnts = np.zeros(8, dtype=np.uint64)
     P._lib.check(lib.knn_prof_counters(cnts.ctypes.data_as(ctypes.c_void_p)))
     P._lib.check(lib.knn_prof_enable(0))
     _, _, stats = db.adaptive(Q_t, K, params, with_stats=True)
@@ -173,7 +173,7 @@ def main():
 
     # dominant kernel class of the step and its roofline (averages over the timed steps)
     dom = max(prof, key=lambda k_: prof[k_]["ms"])
-    alg_bytes, pairs, exact_elems, draws = (float(c) for c in cnts)
+    alg_bytes, pairs, exact_elems, draws = (float(c) for c in cnts[:4])
     samp, exr = prof["sample"], prof["sample_exact_round"]
     s_avg = samp["ms"] / max(1, samp["launches"]) / 1e3
     e_avg = exr["ms"] / max(1, exr["launches"]) / 1e3

@@ -193,10 +193,12 @@ int knn_prof_enable(int on);
  * the recorded events. */
 int knn_prof_read(int32_t kind, double *total_ms, int64_t *launches, double *units);
 
-/* Device work counters since the last enable: [0] algorithmic bytes of the
- * sampling kernel, [1] samples drawn, [2] exact-distance coordinates,
- * [3] reserved.  host_out4: host, 4 entries.  Synchronises the device. */
-int knn_prof_counters(uint64_t *host_out4);
+/* Work counters since the last enable: [0] algorithmic bytes of the
+ * adaptive sampling kernel, [1] (query, sample) pairs drawn, [2] exact-distance
+ * (query, coordinate) pairs, [3] distinct coordinate draws (queries sharing a
+ * seed share them), [4] float naive queries that fell back to an exact rescan,
+ * [5..7] reserved.  host_out8: host, 8 entries.  Synchronises the device. */
+int knn_prof_counters(uint64_t *host_out8);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libknn.so")
 OBJ = os.path.join(HERE, "_build")
 
-SOURCES = ["k_adaptive.hip", "k_naive.hip", "knn_api.cpp", "knn_session.cpp", "knn_prof.cpp"]
+SOURCES = ["k_adaptive.hip", "k_naive.hip", "k_naive_f32.hip", "knn_api.cpp", "knn_session.cpp", "knn_prof.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
           "-Wall", "-Wno-unused-function", "-Wno-unused-result"]

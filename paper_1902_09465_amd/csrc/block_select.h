@@ -161,4 +161,51 @@ __device__ void block_bitonic_sort(uint64_t *key, int32_t *idx, int len) {
   __syncthreads();
 }
 
+// Running k smallest of unique 64-bit keys held by one wave in `list`
+// (k <= KC entries, LDS), with tau = the current maximum: each candidate
+// below tau replaces the maximum, which is then recomputed.  c0, c1 are this
+// lane's two candidates.
+template <int KC>
+__device__ __forceinline__ void topk_insert(uint64_t *list, int k, uint64_t &tau, uint64_t c0, uint64_t c1) {
+  const int lane = lane_id();
+  bool p0 = c0 < tau, p1 = c1 < tau;
+  uint64_t act = __ballot(p0 || p1);
+  while (act) {
+    const int src = __ffsll((long long)act) - 1;
+    const bool use0 = __shfl((int)p0, src) != 0;
+    const uint64_t cs = use0 ? c0 : c1;
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)cs, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(cs >> 32), src);
+    const uint64_t cand = ((uint64_t)hi << 32) | lo;
+    if (lane == src) {
+      if (use0) p0 = false;
+      else p1 = false;
+    }
+    // replace the slot holding tau (keys are unique)
+#pragma unroll
+    for (int e = 0; e < KC / 64; ++e) {
+      const int j = e * 64 + lane;
+      if (j < k && list[j] == tau) list[j] = cand;
+    }
+    // new maximum
+    uint64_t mx = 0;
+#pragma unroll
+    for (int e = 0; e < KC / 64; ++e) {
+      const int j = e * 64 + lane;
+      if (j < k) mx = list[j] > mx ? list[j] : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t l2 = (uint32_t)__shfl_xor((int)(uint32_t)mx, o);
+      const uint32_t h2 = (uint32_t)__shfl_xor((int)(uint32_t)(mx >> 32), o);
+      const uint64_t v = ((uint64_t)h2 << 32) | l2;
+      mx = v > mx ? v : mx;
+    }
+    tau = mx;
+    p0 = p0 && (c0 < tau);
+    p1 = p1 && (c1 < tau);
+    act = __ballot(p0 || p1);
+  }
+}
+
 }  // namespace knn

@@ -7,7 +7,7 @@
 //     distances are exact integers.  The k smallest (distance, index) per
 //     query are kept in LDS while the tile loop streams the points
 //     (fused epilogue, the n-by-nq distance matrix is never stored).
-// f32: (see the f32 section below).
+// f32: split-BF16 MFMA with an error bound and FP64 rescoring (k_naive_f32.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -93,8 +93,9 @@ int naive_prepare_db(knn_db_s *db, hipStream_t st) {
                        db->xs8, db->norm_i);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
+    return KNN_OK;
   }
-  return KNN_OK;
+  return naive_prepare_db_f32(db, st);
 }
 
 void naive_free_db(knn_db_s *db) {
@@ -136,51 +137,6 @@ constexpr int NBP = 128;   // points per block tile
 constexpr int NKS = 64;    // k-step (bytes of K per MFMA)
 constexpr int ROWB = 80;   // LDS row stride in bytes (64 + 16 pad)
 constexpr int DSTR = NBP + 4;
-
-// Per-query running top-k (k <= KC, keys (dist << 32 | index)), one wave per
-// query: candidates below the current maximum replace it.
-template <int KC>
-__device__ __forceinline__ void topk_insert(uint64_t *list, int k, uint64_t &tau, uint64_t c0, uint64_t c1) {
-  const int lane = lane_id();
-  bool p0 = c0 < tau, p1 = c1 < tau;
-  uint64_t act = __ballot(p0 || p1);
-  while (act) {
-    const int src = __ffsll((long long)act) - 1;
-    const bool use0 = __shfl((int)p0, src) != 0;
-    const uint64_t cs = use0 ? c0 : c1;
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)cs, src);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(cs >> 32), src);
-    const uint64_t cand = ((uint64_t)hi << 32) | lo;
-    if (lane == src) {
-      if (use0) p0 = false;
-      else p1 = false;
-    }
-    // replace the slot holding tau (keys are unique)
-#pragma unroll
-    for (int e = 0; e < KC / 64; ++e) {
-      const int j = e * 64 + lane;
-      if (j < k && list[j] == tau) list[j] = cand;
-    }
-    // new maximum
-    uint64_t mx = 0;
-#pragma unroll
-    for (int e = 0; e < KC / 64; ++e) {
-      const int j = e * 64 + lane;
-      if (j < k) mx = list[j] > mx ? list[j] : mx;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const uint32_t l2 = (uint32_t)__shfl_xor((int)(uint32_t)mx, o);
-      const uint32_t h2 = (uint32_t)__shfl_xor((int)(uint32_t)(mx >> 32), o);
-      const uint64_t v = ((uint64_t)h2 << 32) | l2;
-      mx = v > mx ? v : mx;
-    }
-    tau = mx;
-    p0 = p0 && (c0 < tau);
-    p1 = p1 && (c1 < tau);
-    act = __ballot(p0 || p1);
-  }
-}
 
 template <int KC>
 __global__ __launch_bounds__(256) void k_naive_u8(const int8_t *__restrict__ Q8, const int32_t *__restrict__ qn,
@@ -362,7 +318,7 @@ static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int6
 int naive_run(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
               hipStream_t st) {
   if (db->dtype == KNN_U8) return naive_u8(db, (const uint8_t *)dq, nq, k, out_idx, out_dist, st);
-  return fail(KNN_EINVAL, "naive f32 scan not available in this build");
+  return naive_f32(db, (const float *)dq, nq, k, out_idx, out_dist, st);
 }
 
 }  // namespace knn

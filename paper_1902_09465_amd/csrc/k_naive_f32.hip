@@ -1,0 +1,411 @@
+// k_naive_f32.hip -- the naive scan of Section 3 for float data on the
+// matrix cores, returning exactly the set (and distances) of an FP64 scan.
+//
+// 1. Split BF16: every value v is stored as hi = bf16(v), lo = bf16(v - hi),
+//    so |v - hi - lo| <= 2^-16 |v|.  The dot product q.x is taken as
+//    hi.hi + hi.lo + lo.hi with v_mfma_f32_16x16x32_bf16 (three MFMAs per
+//    k-step, fp32 accumulation), and the distance as |q|^2 + |x|^2 - 2 q.x.
+// 2. Error bound per pair: |d~ - d| <= E = c1 |q| |x| + c2 (|q|^2 + |x|^2),
+//    c1 covering the split (3.01 2^-16 per product) and fp32 accumulation of
+//    3m terms (3m 2^-24), doubled for safety; c2 the fp32 epilogue roundings.
+// 3. Each block keeps, per query, the k smallest upper bounds u = d~ + E and
+//    the KL smallest lower bounds l = d~ - E over its range of points.  The
+//    k-th smallest upper bound tau over all ranges bounds d_(k) from above;
+//    every true k-NN point has l <= d <= tau.  A range whose lower-bound list
+//    is full with its largest entry still <= tau may have dropped a candidate:
+//    that query is rescanned exactly.
+// 4. Candidates (l <= tau) are rescored in FP64, summing (x_j - q_j)^2 in
+//    coordinate order like the CPU reference, and the k smallest by
+//    (distance, index) are returned.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "block_select.h"
+#include "knn_host.h"
+#include "knn_prof.h"
+
+namespace knn {
+
+typedef int v4i_f __attribute__((ext_vector_type(4)));
+typedef float v4f_f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf_f __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t bf16_rne(float v) {
+  const uint32_t b = __float_as_uint(v);
+  return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// order-preserving 32-bit key of a float
+__device__ __forceinline__ uint32_t fkey(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float fkey_inv(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// Rows of a float matrix -> split BF16 (hi, lo) padded to mp, |row|^2 (fp64
+// sum rounded to fp32) and |row|.
+__global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ A, int64_t rows, int64_t m,
+                                                    int64_t mp, uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
+                                                    float *__restrict__ nrm, float *__restrict__ rn) {
+  const int64_t r = blockIdx.x;
+  if (r >= rows) return;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < mp; j += 256) {
+    const float v = j < m ? A[r * m + j] : 0.0f;
+    const uint16_t h = bf16_rne(v);
+    const uint16_t l = bf16_rne(v - bf16_to_f(h));
+    hi[r * mp + j] = h;
+    lo[r * mp + j] = l;
+    acc += (double)v * (double)v;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = red[0] + red[1] + red[2] + red[3];
+    nrm[r] = (float)t;
+    rn[r] = (float)sqrt(t);
+  }
+}
+
+constexpr int FBQ = 64, FBP = 128, FROWB = 80, FDSTR = FBP + 4;
+constexpr int KCU = 64;  // upper-bound list capacity (k <= 64)
+constexpr int KCL = 64;  // lower-bound list capacity per range
+
+__global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ Qh, const uint16_t *__restrict__ Ql,
+                                                   const float *__restrict__ qn, const float *__restrict__ qr,
+                                                   const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xl,
+                                                   const float *__restrict__ xn, const float *__restrict__ xr,
+                                                   int64_t nq, int64_t n, int64_t mp, int k, int64_t prange,
+                                                   float c1, float c2, uint64_t *__restrict__ part, int64_t nranges) {
+  __shared__ __align__(16) uint8_t tiles[FBQ * FDSTR * 4];
+  static_assert(2 * (FBQ + FBP) * FROWB <= FBQ * FDSTR * 4, "tile union too small");
+  uint8_t *Ah = tiles, *Al = tiles + FBQ * FROWB;
+  uint8_t *Bh = tiles + 2 * FBQ * FROWB, *Bl = Bh + FBP * FROWB;
+  float *Ds = reinterpret_cast<float *>(tiles);
+  __shared__ uint64_t LU[FBQ * KCU];
+  __shared__ uint64_t LL[FBQ * KCL];
+  __shared__ uint64_t TU[FBQ], TL[FBQ];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int64_t q0 = (int64_t)blockIdx.y * FBQ;
+  const int64_t pr0 = (int64_t)blockIdx.x * prange;
+  const int64_t pr1 = std::min(n, pr0 + prange);
+  for (int j = tid; j < FBQ * KCU; j += 256) LU[j] = ~0ull - (uint64_t)(j % KCU);
+  for (int j = tid; j < FBQ * KCL; j += 256) LL[j] = ~0ull - (uint64_t)(j % KCL);
+  for (int j = tid; j < FBQ; j += 256) {
+    TU[j] = ~0ull;
+    TL[j] = ~0ull;
+  }
+  const int wq = wave >> 1, wp = wave & 1;
+  __syncthreads();
+  for (int64_t p0 = pr0; p0 < pr1; p0 += FBP) {
+    v4f_f acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = v4f_f{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = 0; k0 < mp; k0 += 32) {  // 32 bf16 = 64 bytes per row per step
+      {
+        const int r = tid >> 2, c = (tid & 3) * 16;
+        v4i_f vh = v4i_f{0, 0, 0, 0}, vl = v4i_f{0, 0, 0, 0};
+        if (q0 + r < nq) {
+          vh = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Qh + (q0 + r) * mp + k0) + c);
+          vl = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Ql + (q0 + r) * mp + k0) + c);
+        }
+        *reinterpret_cast<v4i_f *>(Ah + r * FROWB + c) = vh;
+        *reinterpret_cast<v4i_f *>(Al + r * FROWB + c) = vl;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = (tid >> 2) + 64 * h, c = (tid & 3) * 16;
+        v4i_f vh = v4i_f{0, 0, 0, 0}, vl = v4i_f{0, 0, 0, 0};
+        if (p0 + r < pr1) {
+          vh = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Xh + (p0 + r) * mp + k0) + c);
+          vl = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Xl + (p0 + r) * mp + k0) + c);
+        }
+        *reinterpret_cast<v4i_f *>(Bh + r * FROWB + c) = vh;
+        *reinterpret_cast<v4i_f *>(Bl + r * FROWB + c) = vl;
+      }
+      __syncthreads();
+      v8bf_f ah[2], al[2], bh[4], bl[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int off = (32 * wq + 16 * a + (lane & 15)) * FROWB + 16 * (lane >> 4);
+        ah[a] = *reinterpret_cast<const v8bf_f *>(Ah + off);
+        al[a] = *reinterpret_cast<const v8bf_f *>(Al + off);
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int off = (64 * wp + 16 * b + (lane & 15)) * FROWB + 16 * (lane >> 4);
+        bh[b] = *reinterpret_cast<const v8bf_f *>(Bh + off);
+        bl[b] = *reinterpret_cast<const v8bf_f *>(Bl + off);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+        }
+      __syncthreads();
+    }
+    // approximate distances of the tile
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+          const int pl = 64 * wp + 16 * b + (lane & 15);
+          float d = 0.0f;
+          if (p0 + pl < pr1 && q0 + ql < nq) d = (qn[q0 + ql] + xn[p0 + pl]) - 2.0f * acc[a][b][v];
+          Ds[ql * FDSTR + pl] = d;
+        }
+    __syncthreads();
+#pragma unroll 1
+    for (int t = 0; t < FBQ / 4; ++t) {
+      const int ql = wave * (FBQ / 4) + t;
+      if (q0 + ql >= nq) break;
+      const float qnv = qn[q0 + ql], qrv = qr[q0 + ql];
+      uint64_t cu[2], cl[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int pl = lane + 64 * h;
+        const int64_t p = p0 + pl;
+        if (p < pr1) {
+          const float d = Ds[ql * FDSTR + pl];
+          const float E = c1 * qrv * xr[p] + c2 * (qnv + xn[p]);
+          cu[h] = ((uint64_t)fkey(d + E) << 32) | (uint64_t)p;
+          cl[h] = ((uint64_t)fkey(d - E) << 32) | (uint64_t)p;
+        } else {
+          cu[h] = ~0ull;
+          cl[h] = ~0ull;
+        }
+      }
+      uint64_t tu = TU[ql], tl = TL[ql];
+      topk_insert<KCU>(LU + ql * KCU, k, tu, cu[0], cu[1]);
+      topk_insert<KCL>(LL + ql * KCL, KCL, tl, cl[0], cl[1]);
+      if (lane == 0) {
+        TU[ql] = tu;
+        TL[ql] = tl;
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = 0; t < FBQ / 4; ++t) {
+    const int ql = wave * (FBQ / 4) + t;
+    if (q0 + ql >= nq) break;
+    uint64_t *dst = part + ((q0 + ql) * nranges + blockIdx.x) * (int64_t)(k + KCL);
+    for (int j = lane; j < k; j += 64) dst[j] = LU[ql * KCU + j];
+    for (int j = lane; j < KCL; j += 64) dst[k + j] = LL[ql * KCL + j];
+  }
+}
+
+// Exact FP64 distance of point i, coordinates in order (no FMA contraction).
+__device__ __forceinline__ double exact_f64(const float *__restrict__ X, const float *__restrict__ q, int64_t m,
+                                            int64_t i) {
+  const float *row = X + i * m;
+  double s = 0.0;
+  for (int64_t j = 0; j < m; ++j) {
+    const double d = (double)row[j] - (double)q[j];
+    s += d * d;
+  }
+  return s;
+}
+
+constexpr int FCAP = 2048;  // candidate capacity per query in the merge
+
+__global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__restrict__ part, int64_t nranges, int k,
+                                                          const float *__restrict__ X, const float *__restrict__ Q,
+                                                          int64_t m, int64_t *__restrict__ out_idx,
+                                                          double *__restrict__ out_dist, int32_t *__restrict__ flag) {
+  const int64_t q = blockIdx.x;
+  const int64_t w = k + KCL;
+  const uint64_t *pq = part + q * nranges * w;
+  __shared__ SelScratch ss;
+  __shared__ uint64_t key[FCAP];
+  __shared__ int32_t id[FCAP];
+  __shared__ int cnt, bad;
+  int less;
+  const uint64_t tk =
+      block_kth_gen<1024>(nranges * k, [&](int64_t t) { return pq[(t / k) * w + (t % k)]; }, k, ss, &less);
+  const float tau = fkey_inv((uint32_t)(tk >> 32));
+  const uint32_t tau_key = fkey(tau + fabsf(tau) * 1e-6f + 1e-30f);  // tiny margin over fp32 rounding
+  if (threadIdx.x == 0) {
+    cnt = 0;
+    bad = 0;
+  }
+  __syncthreads();
+  // completeness: a full lower-bound list whose largest entry is <= tau may have dropped candidates
+  for (int64_t r = threadIdx.x; r < nranges; r += 1024) {
+    const uint64_t *L = pq + r * w + k;
+    uint64_t mx = 0;
+    bool full = true;
+    for (int j = 0; j < KCL; ++j) {
+      if (L[j] >= 0xFFFFFFFF00000000ull) full = false;  // a sentinel: the range had fewer points
+      mx = L[j] > mx ? L[j] : mx;
+    }
+    if (full && (uint32_t)(mx >> 32) <= tau_key) atomicOr(&bad, 1);
+  }
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < nranges * KCL; t += 1024) {
+    const uint64_t e = pq[(t / KCL) * w + k + (t % KCL)];
+    if (e >= 0xFFFFFFFF00000000ull) continue;
+    if ((uint32_t)(e >> 32) <= tau_key) {
+      const int pos = atomicAdd(&cnt, 1);
+      if (pos < FCAP) id[pos] = (int32_t)(e & 0xFFFFFFFFu);
+      else atomicOr(&bad, 1);
+    }
+  }
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) flag[q] = 1;
+    return;
+  }
+  const int c = cnt;
+  const float *qv = Q + q * m;
+  for (int t = threadIdx.x; t < c; t += 1024) key[t] = dkey(exact_f64(X, qv, m, id[t]));
+  __syncthreads();
+  int len = 1;
+  while (len < c) len <<= 1;
+  for (int t = c + (int)threadIdx.x; t < len; t += 1024) {
+    key[t] = ~0ull;
+    id[t] = 0x7FFFFFFF;
+  }
+  block_bitonic_sort<1024>(key, id, len);
+  for (int t = threadIdx.x; t < k; t += 1024) {
+    out_idx[q * k + t] = t < c ? (int64_t)id[t] : -1;
+    if (out_dist) out_dist[q * k + t] = t < c ? dkey_inv(key[t]) : INFINITY;
+  }
+  if (threadIdx.x == 0) flag[q] = 0;
+}
+
+// Exact FP64 scan of one query (used when a candidate list may be incomplete).
+__global__ __launch_bounds__(1024) void k_naive_f32_full(const float *__restrict__ X, const float *__restrict__ Q,
+                                                         int64_t n, int64_t m, int k, const int32_t *__restrict__ qids,
+                                                         double *__restrict__ scratch, int64_t *__restrict__ out_idx,
+                                                         double *__restrict__ out_dist) {
+  const int64_t q = qids[blockIdx.x];
+  double *dd = scratch + (int64_t)blockIdx.x * n;
+  const float *qv = Q + q * m;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) dd[i] = exact_f64(X, qv, m, i);
+  __syncthreads();
+  __shared__ SelScratch ss;
+  __shared__ uint64_t key[kMaxKH];
+  __shared__ int32_t id[kMaxKH];
+  __shared__ int cnt;
+  int less;
+  const uint64_t v = block_kth_gen<1024>(n, [&](int64_t i) { return dkey(dd[i]); }, k, ss, &less);
+  const uint32_t thr = block_kth_u32_gen<1024>(
+      n, [&](int64_t i) { return (uint32_t)i; }, [&](int64_t i) { return dkey(dd[i]) == v; }, k - less, ss);
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const uint64_t kk = dkey(dd[i]);
+    if (kk < v || (kk == v && (uint32_t)i <= thr)) {
+      const int pos = atomicAdd(&cnt, 1);
+      if (pos < kMaxKH) {
+        key[pos] = kk;
+        id[pos] = (int32_t)i;
+      }
+    }
+  }
+  __syncthreads();
+  int len = 1;
+  while (len < k) len <<= 1;
+  for (int t = k + (int)threadIdx.x; t < len; t += 1024) {
+    key[t] = ~0ull;
+    id[t] = 0x7FFFFFFF;
+  }
+  block_bitonic_sort<1024>(key, id, len);
+  for (int t = threadIdx.x; t < k; t += 1024) {
+    out_idx[q * k + t] = (int64_t)id[t];
+    if (out_dist) out_dist[q * k + t] = dkey_inv(key[t]);
+  }
+}
+
+int naive_prepare_db_f32(knn_db_s *db, hipStream_t st) {
+  const size_t cells = (size_t)db->n * db->mp;
+  HIP_TRY(hipMalloc(&db->xbf, cells * 2 * sizeof(uint16_t)));  // hi, then lo
+  HIP_TRY(hipMalloc(&db->norm_f, sizeof(float) * db->n));
+  HIP_TRY(hipMalloc(&db->rownorm, sizeof(float) * db->n));
+  hipLaunchKernelGGL(k_split_rows, dim3((unsigned)db->n), dim3(256), 0, st, (const float *)db->X, db->n, db->m,
+                     db->mp, db->xbf, db->xbf + cells, db->norm_f, db->rownorm);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return KNN_OK;
+}
+
+int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
+              hipStream_t st) {
+  if (k > KCU) return fail(KNN_EINVAL, "naive f32 scan supports k <= 64");
+  const int64_t n = db->n, m = db->m, mp = db->mp;
+  const size_t cells = (size_t)n * mp;
+  const int64_t qt = (nq + FBQ - 1) / FBQ;
+  int64_t prange = (n * qt + 1023) / 1024;
+  prange = std::max<int64_t>(FBP, (prange + FBP - 1) / FBP * FBP);
+  const int64_t nranges = (n + prange - 1) / prange;
+  // error-bound constants (doubled for safety, see the file header)
+  const double u16 = 1.0 / 65536.0, u24 = 1.0 / 16777216.0;
+  const float c1 = (float)(2.0 * 2.0 * (3.01 * u16 + 3.1 * (double)m * u24));
+  const float c2 = (float)(8.0 * u24);
+  const size_t b_qs = (size_t)nq * mp * 2 * 2, b_qn = sizeof(float) * nq * 2 + 512,
+               b_part = sizeof(uint64_t) * nq * nranges * (k + KCL), b_flag = sizeof(int32_t) * nq + 256;
+  void *ws = nullptr;
+  HIP_TRY(hipMallocAsync(&ws, b_qs + b_qn + b_part + b_flag, st));
+  uint16_t *Qh = (uint16_t *)ws, *Ql = Qh + (size_t)nq * mp;
+  float *qn = (float *)((uint8_t *)ws + b_qs), *qr = qn + nq;
+  uint64_t *part = (uint64_t *)((uint8_t *)ws + b_qs + b_qn);
+  int32_t *flag = (int32_t *)((uint8_t *)ws + b_qs + b_qn + b_part);
+  int tok = prof_begin(PROF_NAIVE_REST, st);
+  hipLaunchKernelGGL(k_split_rows, dim3((unsigned)nq), dim3(256), 0, st, dq, nq, m, mp, Qh, Ql, qn, qr);
+  prof_end(tok, st, 0.0);
+  tok = prof_begin(PROF_NAIVE_GEMM, st);
+  hipLaunchKernelGGL(k_naive_f32, dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st, Qh, Ql, qn, qr,
+                     db->xbf, db->xbf + cells, db->norm_f, db->rownorm, nq, n, mp, k, prange, c1, c2, part, nranges);
+  prof_end(tok, st, 3.0 * 2.0 * (double)nq * (double)n * (double)m);
+  tok = prof_begin(PROF_NAIVE_REST, st);
+  hipLaunchKernelGGL(k_naive_f32_merge, dim3((unsigned)nq), dim3(1024), 0, st, part, nranges, k,
+                     (const float *)db->X, dq, m, out_idx, out_dist, flag);
+  prof_end(tok, st, 0.0);
+  HIP_TRY(hipGetLastError());
+  // queries whose candidate list may be incomplete are rescanned exactly
+  std::vector<int32_t> hflag(nq);
+  HIP_TRY(hipMemcpyAsync(hflag.data(), flag, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<int32_t> redo;
+  for (int64_t q = 0; q < nq; ++q)
+    if (hflag[q]) redo.push_back((int32_t)q);
+  prof_add_host(0, (uint64_t)redo.size());
+  if (!redo.empty()) {
+    const int64_t batch = std::max<int64_t>(1, std::min<int64_t>((int64_t)redo.size(), (1ll << 30) / (n * 8)));
+    int32_t *dq_ids = nullptr;
+    double *scratch = nullptr;
+    HIP_TRY(hipMallocAsync(&dq_ids, sizeof(int32_t) * redo.size(), st));
+    HIP_TRY(hipMallocAsync(&scratch, sizeof(double) * n * batch, st));
+    HIP_TRY(hipMemcpyAsync(dq_ids, redo.data(), sizeof(int32_t) * redo.size(), hipMemcpyHostToDevice, st));
+    for (int64_t b0 = 0; b0 < (int64_t)redo.size(); b0 += batch) {
+      const int64_t cnt = std::min<int64_t>(batch, (int64_t)redo.size() - b0);
+      hipLaunchKernelGGL(k_naive_f32_full, dim3((unsigned)cnt), dim3(1024), 0, st, (const float *)db->X, dq, n, m, k,
+                         dq_ids + b0, scratch, out_idx, out_dist);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipFreeAsync(scratch, st));
+    HIP_TRY(hipFreeAsync(dq_ids, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  HIP_TRY(hipFreeAsync(ws, st));
+  return KNN_OK;
+}
+
+
+}  // namespace knn

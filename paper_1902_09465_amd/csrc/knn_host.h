@@ -18,9 +18,9 @@ struct knn_db_s {
   int8_t *xs8 = nullptr;       // u8: x - 128 as int8, [n][mp] (mp = m padded to 64)
   int64_t mp = 0;
   int32_t *norm_i = nullptr;   // u8: sum (x-128)^2 per row
-  uint16_t *xbf = nullptr;     // f32: bf16 copy [n][mp]
-  float *norm_f = nullptr;     // f32: sum x^2 (fp32) per row
-  float *rownorm = nullptr;    // f32: ||x|| per row (for the BF16 error bound)
+  uint16_t *xbf = nullptr;     // f32: split BF16 copy, hi [n][mp] then lo [n][mp]
+  float *norm_f = nullptr;     // f32: |x|^2 per row (fp64 sum rounded to fp32)
+  float *rownorm = nullptr;    // f32: |x| per row (for the error bound)
   std::atomic<int> users{0};   // sessions holding the DB
   std::mutex mu;
 };
@@ -72,6 +72,10 @@ int naive_prepare_db(knn_db_s *db, hipStream_t st);
 int naive_run(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
               hipStream_t st);
 void naive_free_db(knn_db_s *db);
+// k_naive_f32.hip
+int naive_prepare_db_f32(knn_db_s *db, hipStream_t st);
+int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
+              hipStream_t st);
 int db_range_f32(const float *X, int64_t count, double *lo, double *hi, hipStream_t st);
 
 }  // namespace knn

@@ -21,6 +21,7 @@ struct ProfState {
   std::mutex mu;
   bool on = false;
   uint64_t *dcnt = nullptr;
+  uint64_t host_cnt[4] = {0, 0, 0, 0};  // counters kept on the host ([4..7] of the ABI)
   std::vector<ProfRec> recs;
 };
 
@@ -30,6 +31,13 @@ static ProfState &P() {
 }
 
 bool prof_enabled() { return P().on; }
+
+void prof_add_host(int idx, uint64_t v) {
+  ProfState &s = P();
+  if (!s.on || idx < 0 || idx > 3) return;
+  std::lock_guard<std::mutex> lk(s.mu);
+  s.host_cnt[idx] += v;
+}
 uint64_t *prof_device_counters() { return P().on ? P().dcnt : nullptr; }
 
 int prof_begin(int kind, hipStream_t st) {
@@ -73,6 +81,7 @@ int knn_prof_enable(int on) {
   clear_locked(s);
   if (on && !s.dcnt) HIP_TRY(hipMalloc(&s.dcnt, sizeof(uint64_t) * 8));
   if (s.dcnt) HIP_TRY(hipMemset(s.dcnt, 0, sizeof(uint64_t) * 8));
+  s.host_cnt[0] = s.host_cnt[1] = s.host_cnt[2] = s.host_cnt[3] = 0;
   s.on = on != 0;
   return KNN_OK;
 }
@@ -97,13 +106,15 @@ int knn_prof_read(int32_t kind, double *total_ms, int64_t *launches, double *uni
   return KNN_OK;
 }
 
-int knn_prof_counters(uint64_t *host_out4) {
+int knn_prof_counters(uint64_t *host_out8) {
   ProfState &s = P();
-  if (!host_out4) return fail(KNN_EINVAL, "NULL argument");
-  for (int i = 0; i < 4; ++i) host_out4[i] = 0;
+  if (!host_out8) return fail(KNN_EINVAL, "NULL argument");
+  for (int i = 0; i < 8; ++i) host_out8[i] = 0;
   if (!s.dcnt) return KNN_OK;
   HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(host_out4, s.dcnt, sizeof(uint64_t) * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(host_out8, s.dcnt, sizeof(uint64_t) * 4, hipMemcpyDeviceToHost));
+  std::lock_guard<std::mutex> lk(s.mu);
+  for (int i = 0; i < 4; ++i) host_out8[4 + i] = s.host_cnt[i];
   return KNN_OK;
 }
 

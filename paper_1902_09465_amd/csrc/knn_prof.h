@@ -24,5 +24,6 @@ bool prof_enabled();
 uint64_t *prof_device_counters();  // NULL unless enabled
 int prof_begin(int kind, hipStream_t st);               // returns a token (or -1)
 void prof_end(int token, hipStream_t st, double units); // units: algorithmic work known on the host
+void prof_add_host(int idx, uint64_t v);                // host-side counter idx (0..3) += v
 
 }  // namespace knn

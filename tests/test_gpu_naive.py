@@ -59,3 +59,48 @@ def test_naive_u8_batched_config_sampled(P, orc):
         ri, rd = orc.naive(X, Q[q], 10)
         assert idx[q].tolist() == ri.tolist(), q
         assert np.array_equal(dist[q], rd)
+
+
+@pytest.mark.parametrize("n,m,nq,k", [(5003, 100, 70, 10), (3000, 128, 65, 64), (777, 3, 5, 1),
+                                      (2049, 300, 17, 33)])
+def test_naive_f32_parity(P, orc, n, m, nq, k):
+    """Split-BF16 MFMA candidates rescored in FP64: the set and the
+    distances equal the FP64 oracle exactly."""
+    g = rng(7 * n + m)
+    X = g.standard_normal((n, m)).astype(np.float32)
+    Q = (X[g.integers(0, n, size=nq)] + 0.05 * g.standard_normal((nq, m))).astype(np.float32)
+    db = P.KnnDB(dev(X))
+    idx, dist = db.naive(dev(Q), k)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    for q in range(nq):
+        ri, rd = orc.naive(X, Q[q], k)
+        assert idx[q].tolist() == ri.tolist(), q
+        assert np.array_equal(dist[q], rd)
+
+
+def test_naive_f32_clustered_and_ties(P, orc):
+    from knn_inputs import gmm_f32
+    X, Q = gmm_f32(3100, n=50_000, m=128, n_centres=50, sigma=0.1, nq=40)
+    X[100:120] = X[99]  # exact duplicates: equal distances, index order decides
+    Q[0] = X[99]
+    db = P.KnnDB(dev(X))
+    idx, dist = db.naive(dev(Q), 25)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    for q in range(40):
+        ri, rd = orc.naive(X, Q[q], 25)
+        assert idx[q].tolist() == ri.tolist(), q
+        assert np.array_equal(dist[q], rd)
+
+
+def test_naive_f32_float_config_sampled(P, orc):
+    """The float workload (n = 1,000,000 x 128, 10,000 queries from a
+    1,000-cluster mixture); eight sampled queries against the oracle."""
+    from knn_inputs import gmm_f32
+    X, Q = gmm_f32(3000, n=1_000_000, m=128, n_centres=1000, sigma=0.1, nq=10_000)
+    db = P.KnnDB(dev(X))
+    idx, dist = db.naive(dev(Q), 10)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    for q in (0, 1, 63, 64, 4999, 9998, 9999, 1234):
+        ri, rd = orc.naive(X, Q[q], 10)
+        assert idx[q].tolist() == ri.tolist(), q
+        assert np.array_equal(dist[q], rd)
