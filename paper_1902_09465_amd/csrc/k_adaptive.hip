@@ -55,7 +55,7 @@ __device__ __forceinline__ int64_t sample_val(const uint8_t *__restrict__ row,
                                               const uint8_t *__restrict__ q, uint32_t j, int F) {
   if constexpr (DT == KNN_U8) {
     const int d = (int)row[j] - (int)q[j];
-    return (int64_t)(d * d);
+    return (int64_t)__mul24(d, d);  // |d| < 2^8: the full-rate 24-bit multiply is exact
   } else {
     const float d = reinterpret_cast<const float *>(row)[j] - reinterpret_cast<const float *>(q)[j];
     return fixed_of(d * d, F);
@@ -258,11 +258,10 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
             const uint32_t qv = QLDS ? reinterpret_cast<const uint32_t *>(q)[w]
                                      : (uint32_t)q[4 * w] | ((uint32_t)q[4 * w + 1] << 8) |
                                            ((uint32_t)q[4 * w + 2] << 16) | ((uint32_t)q[4 * w + 3] << 24);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              const int d = (int)((xv >> (8 * b)) & 255u) - (int)((qv >> (8 * b)) & 255u);
-              acc += d * d;
-            }
+            // four squared differences as x.x + q.q - 2 x.q (at most 4 * 255^2)
+            const uint32_t sq = __builtin_amdgcn_udot4(xv, xv, 0u, false) + __builtin_amdgcn_udot4(qv, qv, 0u, false) -
+                                2u * __builtin_amdgcn_udot4(xv, qv, 0u, false);
+            acc += (int64_t)sq;
           }
         } else {
           for (int64_t j = lane; j < m; j += kWave) acc += sample_val<DT>(row, q, (uint32_t)j, F);
@@ -497,53 +496,65 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
       if (act == 0) continue;  // uniform within the lanes of this point
       const uint8_t *row = X + (int64_t)i * m;
-      uint32_t acc[GRP];
+      // (x - q)^2 summed over four draws is x.x - 2 x.q + q.q on four-byte
+      // vectors: the draws' query bytes are transposed so that one dword
+      // holds one query's four draws, and each product is one dot4.
+      uint32_t qq[GRP], xq[GRP], xx = 0;
 #pragma unroll
-      for (int g = 0; g < GRP; ++g) acc[g] = 0;
-      // software pipelined: the next block's draws, gathers and LDS reads
-      // are in flight while the current block is accumulated
-      uint32_t b = blk0 + sub;
-      int xc[4];
-      uint4 qc[4];
-      if (b < blk1) {
-        const P4 r = philox10(b, 0u, (uint32_t)i, 0u, k0, k1);
+      for (int g = 0; g < GRP; ++g) qq[g] = xq[g] = 0;
+      auto fetch = [&](uint32_t blk, uint32_t (&xv)[4], uint4 (&qv)[4]) {
+        const P4 r = philox10(blk, 0u, (uint32_t)i, 0u, k0, k1);
         const uint32_t js[4] = {coord_of(r.x, mm), coord_of(r.y, mm), coord_of(r.z, mm), coord_of(r.w, mm)};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          xc[e] = (int)row[js[e]];
-          qc[e] = *reinterpret_cast<const uint4 *>(smem + (size_t)js[e] * GRP);
+          xv[e] = row[js[e]];
+          qv[e] = *reinterpret_cast<const uint4 *>(smem + (size_t)js[e] * GRP);
         }
+      };
+      auto consume = [&](const uint32_t (&xv)[4], const uint4 (&qv)[4]) {
+        const uint32_t x4 = xv[0] | (xv[1] << 8) | (xv[2] << 16) | (xv[3] << 24);
+        xx = __builtin_amdgcn_udot4(x4, x4, xx, false);
+        const uint32_t r[4][4] = {{qv[0].x, qv[1].x, qv[2].x, qv[3].x},
+                                  {qv[0].y, qv[1].y, qv[2].y, qv[3].y},
+                                  {qv[0].z, qv[1].z, qv[2].z, qv[3].z},
+                                  {qv[0].w, qv[1].w, qv[2].w, qv[3].w}};
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          // 4x4 byte transpose: c[u] = byte u of r[w][0..3]
+          const uint32_t t0 = __builtin_amdgcn_perm(r[w][1], r[w][0], 0x05010400u);
+          const uint32_t t1 = __builtin_amdgcn_perm(r[w][1], r[w][0], 0x07030602u);
+          const uint32_t t2 = __builtin_amdgcn_perm(r[w][3], r[w][2], 0x05010400u);
+          const uint32_t t3 = __builtin_amdgcn_perm(r[w][3], r[w][2], 0x07030602u);
+          const uint32_t c[4] = {__builtin_amdgcn_perm(t2, t0, 0x05040100u), __builtin_amdgcn_perm(t2, t0, 0x07060302u),
+                                 __builtin_amdgcn_perm(t3, t1, 0x05040100u), __builtin_amdgcn_perm(t3, t1, 0x07060302u)};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            qq[4 * w + u] = __builtin_amdgcn_udot4(c[u], c[u], qq[4 * w + u], false);
+            xq[4 * w + u] = __builtin_amdgcn_udot4(x4, c[u], xq[4 * w + u], false);
+          }
+        }
+      };
+      // software pipelined over two register stages: the next block's
+      // draws, gathers and LDS reads are in flight while one is summed
+      uint32_t xa[4], xb[4];
+      uint4 qa[4], qb[4];
+      uint32_t b = blk0 + sub;
+      if (b < blk1) fetch(b, xa, qa);
+      while (b < blk1) {
+        const uint32_t b1 = b + lpp;
+        if (b1 < blk1) fetch(b1, xb, qb);
+        consume(xa, qa);
+        if (b1 >= blk1) break;
+        const uint32_t b2 = b1 + lpp;
+        if (b2 < blk1) fetch(b2, xa, qa);
+        consume(xb, qb);
+        b = b2;
       }
-      for (; b < blk1; b += lpp) {
-        int xn_[4];
-        uint4 qn_[4];
-        const uint32_t bn = b + lpp;
-        if (bn < blk1) {
-          const P4 r = philox10(bn, 0u, (uint32_t)i, 0u, k0, k1);
-          const uint32_t js[4] = {coord_of(r.x, mm), coord_of(r.y, mm), coord_of(r.z, mm), coord_of(r.w, mm)};
+      // per-lane totals are below 2^32 (at most m draws of 255^2 with
+      // m < 4096 here), so the modular combination is exact
+      uint32_t acc[GRP];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            xn_[e] = (int)row[js[e]];
-            qn_[e] = *reinterpret_cast<const uint4 *>(smem + (size_t)js[e] * GRP);
-          }
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t w4[4] = {qc[e].x, qc[e].y, qc[e].z, qc[e].w};
-#pragma unroll
-          for (int g = 0; g < GRP; ++g) {
-            const int d = xc[e] - (int)((w4[g >> 2] >> (8 * (g & 3))) & 255u);
-            acc[g] += (uint32_t)(d * d);
-          }
-        }
-        if (bn < blk1) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            xc[e] = xn_[e];
-            qc[e] = qn_[e];
-          }
-        }
-      }
+      for (int g = 0; g < GRP; ++g) acc[g] = xx + qq[g] - 2u * xq[g];
       if (narrow) {
         switch (lpp) {
           case 1: reduce_store<1>(acc, lane, act, g0, n, i, cur, B); break;
@@ -666,15 +677,52 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
 // ---------------------------------------------------------------- selection
 
 // Writes the K smallest keys of the block (with multiplicity) to out[0..K).
+// Fast path: the K-th smallest of the per-thread minima bounds the block's
+// K-th smallest key from above, so only the keys at or below it (at most
+// K E of them, usually about K) need an exact selection.  The full radix
+// selection over all keys is the fallback when they do not fit in `cand`.
+constexpr int CAND_CAP = 2048;
+
 template <int E>
-__device__ void emit_smallest(const uint64_t (&key)[E], int K, uint64_t *out, SelScratch &ss, int &cnt) {
+__device__ void emit_smallest(const uint64_t (&key)[E], int K, uint64_t *out, SelScratch &ss, int &cnt,
+                              uint64_t *cand) {
   int less;
-  const uint64_t v = block_kth_regs<NT, E>(key, K, ss, &less);
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
+  uint64_t v;
+  bool done = false;
+  if (K <= NT) {
+    uint64_t mn[1] = {key[0]};
 #pragma unroll
-  for (int e = 0; e < E; ++e)
-    if (key[e] < v) out[atomicAdd(&cnt, 1)] = key[e];
+    for (int e = 1; e < E; ++e) mn[0] = key[e] < mn[0] ? key[e] : mn[0];
+    const uint64_t tau = block_kth_regs<NT, 1>(mn, K, ss, &less);
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (key[e] <= tau) {
+        const int pos = atomicAdd(&cnt, 1);
+        if (pos < CAND_CAP) cand[pos] = key[e];
+      }
+    }
+    __syncthreads();
+    const int c = cnt;
+    __syncthreads();
+    if (c <= CAND_CAP) {
+      v = block_kth_gen<NT>(c, [&](int64_t p) { return cand[p]; }, K, ss, &less);
+      if (threadIdx.x == 0) cnt = 0;
+      __syncthreads();
+      for (int p = threadIdx.x; p < c; p += NT)
+        if (cand[p] < v) out[atomicAdd(&cnt, 1)] = cand[p];
+      done = true;
+    }
+  }
+  if (!done) {
+    v = block_kth_regs<NT, E>(key, K, ss, &less);
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (key[e] < v) out[atomicAdd(&cnt, 1)] = key[e];
+  }
   for (int j = less + (int)threadIdx.x; j < K; j += NT) out[j] = v;
   __syncthreads();
 }
@@ -696,6 +744,7 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
   const SlotArrays a = slot_arrays(B, n, s, sl->par);
   __shared__ SelScratch ss;
   __shared__ int cnt;
+  __shared__ uint64_t cand[CAND_CAP];
   uint64_t ku[SEL_E], kl[SEL_E];
 #pragma unroll
   for (int e = 0; e < SEL_E; ++e) {
@@ -713,8 +762,8 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
   }
   const int k = sl->k;
   uint64_t *out = B.part + (int64_t)s * B.part_stride + (int64_t)blockIdx.x * (2 * k + 1);
-  emit_smallest<SEL_E>(ku, k, out, ss, cnt);
-  emit_smallest<SEL_E>(kl, k + 1, out + k, ss, cnt);
+  emit_smallest<SEL_E>(ku, k, out, ss, cnt, cand);
+  emit_smallest<SEL_E>(kl, k + 1, out + k, ss, cnt, cand);
 }
 
 constexpr int MT = 1024;  // merge / finish block size
