@@ -31,13 +31,18 @@ METRIC = "k-NN queries/s adaptive vs naive MFMA (true k-NN contained), p50/p99 l
 N, M, NQ, K, H, DELTA = 100_000, 3072, 1024, 10, 10, 0.01
 HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0
-VALU_PEAK_TOPS = 39.3  # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit VALU lane-ops per second
-# Algorithmic 32-bit ops of the sampled rounds.  Per coordinate draw (shared by
-# all queries with the same seed): Philox4x32-10 share 20 (10 rounds x (2 mul_lo
-# + 2 mul_hi + 4 xor) / 4 draws), index 1, gather address 1.  Per (query, sample):
-# difference, square, accumulate.
-OPS_PER_DRAW = 22
-OPS_PER_PAIR = 3
+# Sampled rounds are bound by the vector ALU.  Its int8 dot-product peak:
+# 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s, each a
+# v_dot4 of four multiply-adds (8 ops): 314.6 TOP/s.  Algorithmic ops per
+# (query, sample) pair: the two multiply-adds x.q and q.q of
+# (x - q)^2 = x^2 - 2 x.q + q^2 (x^2 is shared by all queries of a point).
+# Per distinct coordinate draw (shared by every query with the same seed):
+# Philox4x32-10 share 20 32-bit ops (10 rounds x (2 mul_lo + 2 mul_hi + 4 xor)
+# / 4 draws), index 1, gather 1 = 22 lane-instructions, i.e. 22 x 8 op slots.
+VALU_LANE_INSTR_PEAK = 39.3e12
+DOT4_PEAK_TOPS = 314.6
+OPS_PER_PAIR = 4
+OPS_PER_DRAW = 22 * 8
 
 
 def log(msg):
@@ -156,8 +161,8 @@ def main():
     ok = contained(idx, cnt, X_t, Q_t, nidx, ndist, K)
     n_ok = int(ok.sum().item())
     prof = {}
-    for kind, name in ((0, "sample"), (7, "sample_exact_round"), (1, "cand"), (2, "select"), (3, "decide"),
-                       (4, "finish")):
+    for kind, name in ((0, "sample"), (7, "sample_exact_round"), (8, "sample_transposes"), (1, "cand"),
+                       (2, "select"), (3, "decide"), (4, "finish")):
         ms, n_l, u = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         P._lib.check(lib.knn_prof_read(kind, ctypes.byref(ms), ctypes.byref(n_l), ctypes.byref(u)))
         prof[name] = dict(ms=ms.value, launches=n_l.value)
@@ -180,11 +185,11 @@ def main():
     s_ops = (draws * OPS_PER_DRAW + pairs * OPS_PER_PAIR) / max(1, samp["launches"])
     e_ops = 2.0 * exact_elems / max(1, exr["launches"])
     rl_sample = {"bound": "alu", "achieved": s_ops / s_avg / 1e12 if s_avg > 0 else 0.0,
-                 "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
-                 "kernel": "k_sample_grp_u8 (sampled rounds)", "avg_launch_ms": s_avg * 1e3,
+                 "peak": DOT4_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
+                 "kernel": "k_sample_ql_u8 (sampled rounds, query-lane)", "avg_launch_ms": s_avg * 1e3,
                  "launches": samp["launches"], "ops_per_launch": s_ops,
                  "alg_bytes_per_launch": alg_bytes / max(1, samp["launches"] + exr["launches"])}
-    rl_sample["frac"] = rl_sample["achieved"] / VALU_PEAK_TOPS
+    rl_sample["frac"] = rl_sample["achieved"] / DOT4_PEAK_TOPS
     rl_exact = {"bound": "mfma", "achieved": e_ops / e_avg / 1e12 if e_avg > 0 else 0.0,
                 "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
                 "kernel": "k_sample_grp_u8 (exact round, int8 MFMA)", "avg_launch_ms": e_avg * 1e3,

@@ -189,7 +189,9 @@ int knn_prof_enable(int on);
  * 5 naive MFMA scan (units: integer or floating-point operations, 2 per
  * multiply-add), 6 naive query prep / merge / rescoring, 7 adaptive sampling
  * launches that run the exact round of a batch whose queries all share one
- * schedule (such launches are counted here instead of under 0).  Waits for
+ * schedule (such launches are counted here instead of under 0), 8 the
+ * point-major / slot-major transposes around query-lane sampling (flags in,
+ * round totals out; under 0 is then the sampling kernel alone).  Waits for
  * the recorded events. */
 int knn_prof_read(int32_t kind, double *total_ms, int64_t *launches, double *units);
 

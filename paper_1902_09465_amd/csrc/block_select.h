@@ -135,6 +135,30 @@ __device__ uint32_t block_kth_u32_gen(int64_t N, GetVal getval, Keep keep, int r
   return prefix;
 }
 
+// Bitonic sort of one 64-bit key per lane across the wave (ascending with
+// the lane index), by exchanges between lanes: 21 compare-exchange steps.
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, j);
+      const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j);
+      const uint64_t o = ((uint64_t)hi << 32) | lo;
+      const bool keep_min = (((l & j) == 0) == ((l & k) == 0));
+      v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+    }
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_bcast_u64(uint64_t v, int src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // In-LDS bitonic sort of (key, idx) pairs ascending by (key, idx); len is a
 // power of two; the whole block takes part.
 template <int NT>

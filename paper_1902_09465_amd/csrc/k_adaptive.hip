@@ -351,6 +351,7 @@ __global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const u
 constexpr int GRP = 16;
 constexpr int GBT = 512;  // threads per block of the grouped kernel
 typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
 
 // Sums v[0..GRP) over the LPP lanes of a point (LPP a power of two <= 64)
 // by halving exchanges: at each step a lane keeps one half of its values
@@ -397,6 +398,101 @@ __device__ __forceinline__ void reduce_store(uint32_t (&v)[GRP], int lane, uint3
       B.S[off] += (int64_t)v[k];
     }
     B.ri[off] = (uint8_t)cur;
+  }
+}
+
+// Sum over this lane's share of the draws of one point, for the GRP queries
+// of a group: blocks of four draws b = b_first, b_first + step, ... < blk1.
+// (x - q)^2 over four draws is x.x - 2 x.q + q.q on four-byte vectors: the
+// four draws' query bytes are transposed so that one dword holds one query's
+// four values, and each product is one dot4.  `row` is the point's row, in
+// global memory or staged in LDS; qT is the transposed query tile in LDS.
+// The per-lane results are below 2^32 (at most m < 4096 draws of 255^2),
+// so the modular combination at the end is exact.
+__device__ __forceinline__ void point_sums(const uint8_t *row, const uint8_t *qT, uint32_t i, uint32_t b_first,
+                                           uint32_t step, uint32_t blk1, uint32_t k0, uint32_t k1, uint32_t mm,
+                                           uint32_t (&acc)[GRP]) {
+  uint32_t qq[GRP], xq[GRP], xx = 0;
+#pragma unroll
+  for (int g = 0; g < GRP; ++g) qq[g] = xq[g] = 0;
+  auto fetch = [&](uint32_t blk, uint32_t (&xv)[4], uint4 (&qv)[4]) {
+    const P4 r = philox10(blk, 0u, i, 0u, k0, k1);
+    const uint32_t js[4] = {coord_of(r.x, mm), coord_of(r.y, mm), coord_of(r.z, mm), coord_of(r.w, mm)};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      xv[e] = row[js[e]];
+      qv[e] = *reinterpret_cast<const uint4 *>(qT + (size_t)js[e] * GRP);
+    }
+  };
+  auto consume = [&](const uint32_t (&xv)[4], const uint4 (&qv)[4]) {
+    const uint32_t x4 = xv[0] | (xv[1] << 8) | (xv[2] << 16) | (xv[3] << 24);
+    xx = __builtin_amdgcn_udot4(x4, x4, xx, false);
+    const uint32_t r[4][4] = {{qv[0].x, qv[1].x, qv[2].x, qv[3].x},
+                              {qv[0].y, qv[1].y, qv[2].y, qv[3].y},
+                              {qv[0].z, qv[1].z, qv[2].z, qv[3].z},
+                              {qv[0].w, qv[1].w, qv[2].w, qv[3].w}};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      // 4x4 byte transpose: c[u] = byte u of r[w][0..3]
+      const uint32_t t0 = __builtin_amdgcn_perm(r[w][1], r[w][0], 0x05010400u);
+      const uint32_t t1 = __builtin_amdgcn_perm(r[w][1], r[w][0], 0x07030602u);
+      const uint32_t t2 = __builtin_amdgcn_perm(r[w][3], r[w][2], 0x05010400u);
+      const uint32_t t3 = __builtin_amdgcn_perm(r[w][3], r[w][2], 0x07030602u);
+      const uint32_t c[4] = {__builtin_amdgcn_perm(t2, t0, 0x05040100u), __builtin_amdgcn_perm(t2, t0, 0x07060302u),
+                             __builtin_amdgcn_perm(t3, t1, 0x05040100u), __builtin_amdgcn_perm(t3, t1, 0x07060302u)};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        qq[4 * w + u] = __builtin_amdgcn_udot4(c[u], c[u], qq[4 * w + u], false);
+        xq[4 * w + u] = __builtin_amdgcn_udot4(x4, c[u], xq[4 * w + u], false);
+      }
+    }
+  };
+  // software pipelined over two register stages: the next block's draws,
+  // gathers and LDS reads are in flight while one is summed
+  uint32_t xa[4], xb[4];
+  uint4 qa[4], qb[4];
+  uint32_t b = b_first;
+  if (b < blk1) fetch(b, xa, qa);
+  while (b < blk1) {
+    const uint32_t b1 = b + step;
+    if (b1 < blk1) fetch(b1, xb, qb);
+    consume(xa, qa);
+    if (b1 >= blk1) break;
+    const uint32_t b2 = b1 + step;
+    if (b2 < blk1) fetch(b2, xa, qa);
+    consume(xb, qb);
+    b = b2;
+  }
+#pragma unroll
+  for (int g = 0; g < GRP; ++g) acc[g] = xx + qq[g] - 2u * xq[g];
+}
+
+// Flags of the point for the running slots of the group: bit g set when slot
+// g0 + g still samples point i (in round 0 and with implicit lists: all).
+__device__ __forceinline__ uint32_t group_active(const Bufs &B, int g0, int64_t n, int32_t i, uint32_t run,
+                                                 int impl) {
+  if (impl) return run;
+  // sixteen independent loads in flight at once (run is uniform)
+  const uint8_t *f = B.fl + (int64_t)g0 * n + i;
+  uint32_t v[GRP];
+#pragma unroll
+  for (int g = 0; g < GRP; ++g) v[g] = (run & (1u << g)) ? (uint32_t)f[(int64_t)g * n] : 1u;
+  uint32_t act = 0;
+#pragma unroll
+  for (int g = 0; g < GRP; ++g) act |= (v[g] == 0 ? 1u : 0u) << g;
+  return act;
+}
+
+__device__ __forceinline__ void reduce_store_lpp(int lpp, uint32_t (&acc)[GRP], int lane, uint32_t act, int g0,
+                                                 int64_t n, int32_t i, int cur, const Bufs &B) {
+  switch (lpp) {
+    case 1: reduce_store<1>(acc, lane, act, g0, n, i, cur, B); break;
+    case 2: reduce_store<2>(acc, lane, act, g0, n, i, cur, B); break;
+    case 4: reduce_store<4>(acc, lane, act, g0, n, i, cur, B); break;
+    case 8: reduce_store<8>(acc, lane, act, g0, n, i, cur, B); break;
+    case 16: reduce_store<16>(acc, lane, act, g0, n, i, cur, B); break;
+    case 32: reduce_store<32>(acc, lane, act, g0, n, i, cur, B); break;
+    default: reduce_store<64>(acc, lane, act, g0, n, i, cur, B); break;
   }
 }
 
@@ -472,125 +568,61 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
     const uint64_t seed = s_seed;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t mm = (uint32_t)m;
-    int lpp = G.lpp;
-    if (lpp <= 0) {  // about sixteen blocks of draws per lane amortise the per-point work
-      const uint32_t nb = blk1 - blk0;
-      lpp = 1;
-      while (lpp < kWave && (uint32_t)(32 * lpp) <= nb) lpp <<= 1;
-    }
-    const int sub = threadIdx.x % lpp;
-    // per-lane sums stay 32-bit; so does the per-point total of a round as
-    // long as B * 255^2 < 2^32
-    const bool narrow = (uint64_t)(s_t1 - s_t0) * 65025ull < (1ull << 32);
+    // the grouped kernel runs only for m < 4096, so a round's total per
+    // point (B * 255^2) fits in 32 bits
     uint64_t my_pairs = 0, my_pts = 0;
-    for (int64_t p = base + threadIdx.x / lpp; p < end; p += GBT / lpp) {
-      const int32_t i = (int32_t)p;
-      uint32_t act = 0;
-      if (impl) {
-        act = run;
-      } else {
-        const uint8_t *f = B.fl + (int64_t)g0 * n + i;
-#pragma unroll 1
-        for (int g = 0; g < GRP; ++g, f += n)
-          if ((run & (1u << g)) && *f == 0) act |= 1u << g;
-      }
-      if (act == 0) continue;  // uniform within the lanes of this point
-      const uint8_t *row = X + (int64_t)i * m;
-      // (x - q)^2 summed over four draws is x.x - 2 x.q + q.q on four-byte
-      // vectors: the draws' query bytes are transposed so that one dword
-      // holds one query's four draws, and each product is one dot4.
-      uint32_t qq[GRP], xq[GRP], xx = 0;
-#pragma unroll
-      for (int g = 0; g < GRP; ++g) qq[g] = xq[g] = 0;
-      auto fetch = [&](uint32_t blk, uint32_t (&xv)[4], uint4 (&qv)[4]) {
-        const P4 r = philox10(blk, 0u, (uint32_t)i, 0u, k0, k1);
-        const uint32_t js[4] = {coord_of(r.x, mm), coord_of(r.y, mm), coord_of(r.z, mm), coord_of(r.w, mm)};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          xv[e] = row[js[e]];
-          qv[e] = *reinterpret_cast<const uint4 *>(smem + (size_t)js[e] * GRP);
+    if (G.stage > 0) {
+      // long rounds: tiles of G.stage point rows are copied into LDS with
+      // coalesced 16-byte loads and the draws gather from there, so the
+      // gathers no longer cost one cache line each in the vector memory
+      // path; GBT / G.stage lanes serve one point
+      const int TP = G.stage, lpp = GBT / TP;
+      const int pt = threadIdx.x / lpp, sub = threadIdx.x % lpp;
+      uint8_t *xt = smem + (size_t)GRP * mp;
+      for (int64_t tile = base; tile < end; tile += TP) {
+        const int rows = (int)min((int64_t)TP, end - tile);
+        const uint8_t *src = X + tile * m;
+        const int64_t bytes = (int64_t)rows * m;
+        if ((m & 15) == 0) {
+          for (int64_t v = threadIdx.x; v < bytes / 16; v += GBT)
+            reinterpret_cast<uint4 *>(xt)[v] = reinterpret_cast<const uint4 *>(src)[v];
+        } else {
+          for (int64_t v = threadIdx.x; v < bytes; v += GBT) xt[v] = src[v];
         }
-      };
-      auto consume = [&](const uint32_t (&xv)[4], const uint4 (&qv)[4]) {
-        const uint32_t x4 = xv[0] | (xv[1] << 8) | (xv[2] << 16) | (xv[3] << 24);
-        xx = __builtin_amdgcn_udot4(x4, x4, xx, false);
-        const uint32_t r[4][4] = {{qv[0].x, qv[1].x, qv[2].x, qv[3].x},
-                                  {qv[0].y, qv[1].y, qv[2].y, qv[3].y},
-                                  {qv[0].z, qv[1].z, qv[2].z, qv[3].z},
-                                  {qv[0].w, qv[1].w, qv[2].w, qv[3].w}};
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          // 4x4 byte transpose: c[u] = byte u of r[w][0..3]
-          const uint32_t t0 = __builtin_amdgcn_perm(r[w][1], r[w][0], 0x05010400u);
-          const uint32_t t1 = __builtin_amdgcn_perm(r[w][1], r[w][0], 0x07030602u);
-          const uint32_t t2 = __builtin_amdgcn_perm(r[w][3], r[w][2], 0x05010400u);
-          const uint32_t t3 = __builtin_amdgcn_perm(r[w][3], r[w][2], 0x07030602u);
-          const uint32_t c[4] = {__builtin_amdgcn_perm(t2, t0, 0x05040100u), __builtin_amdgcn_perm(t2, t0, 0x07060302u),
-                                 __builtin_amdgcn_perm(t3, t1, 0x05040100u), __builtin_amdgcn_perm(t3, t1, 0x07060302u)};
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            qq[4 * w + u] = __builtin_amdgcn_udot4(c[u], c[u], qq[4 * w + u], false);
-            xq[4 * w + u] = __builtin_amdgcn_udot4(x4, c[u], xq[4 * w + u], false);
+        __syncthreads();
+        if (pt < rows) {
+          const int32_t i = (int32_t)(tile + pt);
+          const uint32_t act = group_active(B, g0, n, i, run, impl);
+          if (act) {  // uniform within the lanes of this point
+            uint32_t acc[GRP];
+            point_sums(xt + (size_t)pt * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, acc);
+            reduce_store_lpp(lpp, acc, lane, act, g0, n, i, cur, B);
+            if (sub == 0) {
+              my_pts += 1;
+              my_pairs += (uint64_t)__popc(act);
+            }
           }
         }
-      };
-      // software pipelined over two register stages: the next block's
-      // draws, gathers and LDS reads are in flight while one is summed
-      uint32_t xa[4], xb[4];
-      uint4 qa[4], qb[4];
-      uint32_t b = blk0 + sub;
-      if (b < blk1) fetch(b, xa, qa);
-      while (b < blk1) {
-        const uint32_t b1 = b + lpp;
-        if (b1 < blk1) fetch(b1, xb, qb);
-        consume(xa, qa);
-        if (b1 >= blk1) break;
-        const uint32_t b2 = b1 + lpp;
-        if (b2 < blk1) fetch(b2, xa, qa);
-        consume(xb, qb);
-        b = b2;
+        __syncthreads();
       }
-      // per-lane totals are below 2^32 (at most m draws of 255^2 with
-      // m < 4096 here), so the modular combination is exact
-      uint32_t acc[GRP];
-#pragma unroll
-      for (int g = 0; g < GRP; ++g) acc[g] = xx + qq[g] - 2u * xq[g];
-      if (narrow) {
-        switch (lpp) {
-          case 1: reduce_store<1>(acc, lane, act, g0, n, i, cur, B); break;
-          case 2: reduce_store<2>(acc, lane, act, g0, n, i, cur, B); break;
-          case 4: reduce_store<4>(acc, lane, act, g0, n, i, cur, B); break;
-          case 8: reduce_store<8>(acc, lane, act, g0, n, i, cur, B); break;
-          case 16: reduce_store<16>(acc, lane, act, g0, n, i, cur, B); break;
-          case 32: reduce_store<32>(acc, lane, act, g0, n, i, cur, B); break;
-          default: reduce_store<64>(acc, lane, act, g0, n, i, cur, B); break;
-        }
+    } else {
+      int lpp = G.lpp;
+      if (lpp <= 0) {  // about sixteen blocks of draws per lane amortise the per-point work
+        const uint32_t nb = blk1 - blk0;
+        lpp = 1;
+        while (lpp < kWave && (uint32_t)(32 * lpp) <= nb) lpp <<= 1;
+      }
+      const int sub = threadIdx.x % lpp;
+      for (int64_t p = base + threadIdx.x / lpp; p < end; p += GBT / lpp) {
+        const int32_t i = (int32_t)p;
+        const uint32_t act = group_active(B, g0, n, i, run, impl);
+        if (act == 0) continue;  // uniform within the lanes of this point
+        uint32_t acc[GRP];
+        point_sums(X + (int64_t)i * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, acc);
+        reduce_store_lpp(lpp, acc, lane, act, g0, n, i, cur, B);
         if (sub == 0) {
           my_pts += 1;
           my_pairs += (uint64_t)__popc(act);
-        }
-      } else {
-        // rounds long enough to overflow 32 bits: 64-bit totals, lane 0 writes
-        uint64_t tot[GRP];
-#pragma unroll
-        for (int g = 0; g < GRP; ++g) {
-          tot[g] = acc[g];
-          for (int o = lpp / 2; o > 0; o >>= 1) tot[g] += (uint64_t)shfl_xor_i64((int64_t)tot[g], o);
-        }
-        if (sub == 0) {
-          my_pts += 1;
-          for (int g = 0; g < GRP; ++g) {
-            if (!(act & (1u << g))) continue;
-            const int64_t off = (int64_t)(g0 + g) * n + i;
-            if (cur == 0) {
-              B.S[off] = (int64_t)tot[g];
-              B.fl[off] = 0;
-            } else {
-              B.S[off] += (int64_t)tot[g];
-            }
-            B.ri[off] = (uint8_t)cur;
-            my_pairs += 1;
-          }
         }
       }
     }
@@ -674,31 +706,265 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
+// ---------------------------------------------------------------- query-lane sample (u8)
+
+// In a sampled round shared by every running slot (one seed, one round:
+// the draws of a point are then the same for all of them), one wave serves
+// one point for up to 1024 slots, sixteen per lane.  The lanes draw 64
+// blocks of four coordinates in parallel (one Philox call each) and the
+// gathered x_ij; then, block by block, the coordinates are read back as
+// wave-uniform values and every lane loads the sixteen query bytes of its
+// slots at each coordinate from the transposed query matrix QT[j][slot]
+// (one coalesced 16-byte load per lane; the matrix stays in L2).  Per lane
+// the sums use the same x.x - 2 x.q + q.q dot4 form as the grouped kernel.
+constexpr int QL_BT = 256;
+constexpr int QL_NW = QL_BT / kWave;
+constexpr int QL_SLOTS = 16 * kWave;  // slots served by one wave
+constexpr uint32_t QL_NONE = 0xFFFFFFFFu;  // D entry of a pair not sampled this round
+constexpr int FT = 64;                     // tile edge of the point-major / slot-major transposes
+
+// A[i][s] = fl[s][i] for the slots running round cur, 1 for the others (a
+// nonzero byte means "not sampled"): the point-major copy of the flags that
+// the query-lane kernel reads with one 16-byte load per lane.
+__global__ __launch_bounds__(NT) void k_flags_ql(const Slot *__restrict__ slots, uint8_t *__restrict__ A, int32_t nqp,
+                                                 Bufs B, Geometry G, int32_t cur) {
+  __shared__ uint8_t t[FT][FT + 4];
+  const int64_t n = G.n;
+  const int ns = G.nslots;
+  const int64_t i0 = (int64_t)blockIdx.x * FT;
+  const int s0 = (int)blockIdx.y * FT;
+  const int c = threadIdx.x % FT, r0 = threadIdx.x / FT;
+  for (int r = r0; r < FT; r += NT / FT) {  // row r: slot s0 + r, column c: point i0 + c
+    const int sl = s0 + r;
+    const int64_t i = i0 + c;
+    uint8_t v = 1;
+    if (sl < ns && i < n && slots[sl].state == 1 && slots[sl].cur == cur) v = B.fl[(int64_t)sl * n + i];
+    t[r][c] = v;
+  }
+  __syncthreads();
+  for (int r = r0; r < FT; r += NT / FT) {  // row r: point i0 + r, column c: slot s0 + c
+    const int64_t i = i0 + r;
+    const int sl = s0 + c;
+    if (i < n && sl < nqp) A[i * nqp + sl] = t[c][r];
+  }
+}
+
+// S[s][i] += D[i][s] (S = D in round 0, with flags cleared), round index
+// cur, for the sampled pairs (D != QL_NONE): 64 x 64 tiles transposed through
+// LDS so that both the point-major reads and the slot-major writes are
+// coalesced.
+__global__ __launch_bounds__(NT) void k_fold_ql(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
+                                                int32_t nqp, Bufs B, Geometry G, int32_t cur) {
+  __shared__ uint32_t t[FT][FT + 1];
+  const int64_t n = G.n;
+  const int ns = G.nslots;
+  const int64_t i0 = (int64_t)blockIdx.x * FT;
+  const int s0 = (int)blockIdx.y * FT;
+  const int c = threadIdx.x % FT, r0 = threadIdx.x / FT;
+  for (int r = r0; r < FT; r += NT / FT) {
+    const int64_t i = i0 + r;
+    const int sl = s0 + c;
+    t[r][c] = (i < n && sl < nqp) ? D[i * nqp + sl] : QL_NONE;
+  }
+  __syncthreads();
+  for (int r = r0; r < FT; r += NT / FT) {
+    const int sl = s0 + r;
+    const int64_t i = i0 + c;
+    if (sl >= ns || i >= n) continue;
+    if (slots[sl].state != 1 || slots[sl].cur != cur) continue;  // D holds nothing of this round for it
+    const uint32_t v = t[c][r];
+    if (v == QL_NONE) continue;
+    const int64_t off = (int64_t)sl * n + i;
+    if (cur == 0) {
+      B.S[off] = (int64_t)v;
+      B.fl[off] = 0;
+    } else {
+      B.S[off] += (int64_t)v;
+    }
+    B.ri[off] = (uint8_t)cur;
+  }
+}
+
+// QT[j * nqp + s] = q_s[j] for the running slots s < ns, 0 elsewhere.
+__global__ __launch_bounds__(NT) void k_build_qt(const Slot *__restrict__ slots, int32_t ns, int64_t m, int32_t nqp,
+                                                 uint8_t *__restrict__ QT) {
+  const int64_t total = m * (int64_t)nqp;
+  for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
+    const int64_t j = idx / nqp;
+    const int s = (int)(idx - j * nqp);
+    uint8_t v = 0;
+    if (s < ns && slots[s].state == 1) v = reinterpret_cast<const uint8_t *>(slots[s].q)[j];
+    QT[idx] = v;
+  }
+}
+
+__global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__ slots, const uint8_t *__restrict__ X,
+                                                        const uint8_t *__restrict__ QT, int32_t nqp,
+                                                        const uint8_t *__restrict__ A, uint32_t *__restrict__ D,
+                                                        Bufs B, Geometry G, QlRound R) {
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  const int64_t n = G.n, m = G.m;
+  const int ns = G.nslots;
+  const int s0 = (int)blockIdx.y * QL_SLOTS + 16 * lane;
+  const bool has_q = s0 < nqp;  // nqp is a multiple of 16; other lanes read column 0 and store nothing
+  uint32_t run = 0;
+  for (int g = 0; g < GRP; ++g) {
+    const int s = s0 + g;
+    if (s < ns && slots[s].state == 1 && slots[s].cur == R.cur) run |= 1u << g;
+  }
+  if (__ballot(run != 0) == 0) return;  // no running slot in this wave's range
+  const uint32_t blk0 = R.t0 >> 2, blk1 = R.t1 >> 2;
+  const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
+  const uint32_t mm = (uint32_t)m;
+  // QT through a buffer descriptor: the row offset j * nqp is a wave-uniform
+  // scalar and the lane's column a fixed vector offset, so a load costs no
+  // address arithmetic (and reads past the matrix return zeros)
+  const __amdgpu_buffer_rsrc_t qrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(QT), 0, (int)(m * nqp), 0x00020000);
+  const int qcol = has_q ? s0 : 0;  // this lane's sixteen columns
+  uint64_t my_pairs = 0, my_pts = 0;
+  // each block walks a contiguous range of points, its waves interleaved, so
+  // that the per-slot rows of S, flags and rounds it updates (one 128-byte
+  // line holds 16 consecutive points) are written from one L2 in a short time
+  const int64_t per_block = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i_end = min(n, ((int64_t)blockIdx.x + 1) * per_block);
+  for (int64_t i = (int64_t)blockIdx.x * per_block + wave; i < i_end; i += QL_NW) {
+    // undecided sampled pairs: zero bytes of the point-major flag copy
+    uint32_t act = run;
+    if (!R.impl) {
+      const uint4 a = *reinterpret_cast<const uint4 *>(A + i * (int64_t)nqp + qcol);
+      const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+      act = 0;
+#pragma unroll
+      for (int g = 0; g < GRP; ++g) act |= (((w[g >> 2] >> (8 * (g & 3))) & 255u) == 0 ? 1u : 0u) << g;
+      act &= run;
+    }
+    uint4 *drow = reinterpret_cast<uint4 *>(D + i * (int64_t)nqp + qcol);
+    if (__ballot(act != 0) == 0) {  // wave-uniform: nothing to sample at this point
+      if (has_q) {
+        const uint4 none = make_uint4(QL_NONE, QL_NONE, QL_NONE, QL_NONE);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) drow[c] = none;
+      }
+      continue;
+    }
+    const uint8_t *row = X + i * m;
+    uint32_t qq[GRP], xq[GRP], xx = 0;
+#pragma unroll
+    for (int g = 0; g < GRP; ++g) qq[g] = xq[g] = 0;
+    for (uint32_t bb = blk0; bb < blk1; bb += kWave) {
+      // lane l draws block bb + l
+      uint32_t jv[4] = {0u, 0u, 0u, 0u}, xv = 0;
+      if (bb + lane < blk1) {
+        const P4 r = philox10(bb + lane, 0u, (uint32_t)i, 0u, k0, k1);
+        jv[0] = coord_of(r.x, mm);
+        jv[1] = coord_of(r.y, mm);
+        jv[2] = coord_of(r.z, mm);
+        jv[3] = coord_of(r.w, mm);
+        xv = (uint32_t)row[jv[0]] | ((uint32_t)row[jv[1]] << 8) | ((uint32_t)row[jv[2]] << 16) |
+             ((uint32_t)row[jv[3]] << 24);
+      }
+      const int nb = (int)min((uint32_t)kWave, blk1 - bb);
+      auto fetch = [&](int d, uint4 (&qv)[4]) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t j = (uint32_t)__builtin_amdgcn_readlane((int)jv[e], d);
+          const v4u_t w = __builtin_amdgcn_raw_buffer_load_b128(qrs, qcol, (int)(j * (uint32_t)nqp), 0);
+          qv[e] = make_uint4(w.x, w.y, w.z, w.w);
+        }
+      };
+      auto consume = [&](int d, const uint4 (&qv)[4]) {
+        const uint32_t x4 = (uint32_t)__builtin_amdgcn_readlane((int)xv, d);
+        xx = __builtin_amdgcn_udot4(x4, x4, xx, false);
+        const uint32_t r[4][4] = {{qv[0].x, qv[1].x, qv[2].x, qv[3].x},
+                                  {qv[0].y, qv[1].y, qv[2].y, qv[3].y},
+                                  {qv[0].z, qv[1].z, qv[2].z, qv[3].z},
+                                  {qv[0].w, qv[1].w, qv[2].w, qv[3].w}};
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t t0 = __builtin_amdgcn_perm(r[w][1], r[w][0], 0x05010400u);
+          const uint32_t t1 = __builtin_amdgcn_perm(r[w][1], r[w][0], 0x07030602u);
+          const uint32_t t2 = __builtin_amdgcn_perm(r[w][3], r[w][2], 0x05010400u);
+          const uint32_t t3 = __builtin_amdgcn_perm(r[w][3], r[w][2], 0x07030602u);
+          const uint32_t c[4] = {__builtin_amdgcn_perm(t2, t0, 0x05040100u), __builtin_amdgcn_perm(t2, t0, 0x07060302u),
+                                 __builtin_amdgcn_perm(t3, t1, 0x05040100u), __builtin_amdgcn_perm(t3, t1, 0x07060302u)};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            qq[4 * w + u] = __builtin_amdgcn_udot4(c[u], c[u], qq[4 * w + u], false);
+            xq[4 * w + u] = __builtin_amdgcn_udot4(x4, c[u], xq[4 * w + u], false);
+          }
+        }
+      };
+      // two register stages: the loads of block d + 1 are in flight while d
+      // is summed (issued unconditionally, the last block once more, so that
+      // the wait before each sum covers only the older stage)
+      uint4 qa[4], qb[4];
+      fetch(0, qa);
+      int d = 0;
+      for (;;) {
+        fetch(min(d + 1, nb - 1), qb);
+        consume(d, qa);
+        if (++d >= nb) break;
+        fetch(min(d + 1, nb - 1), qa);
+        consume(d, qb);
+        if (++d >= nb) break;
+      }
+    }
+    // totals of this round per slot (below 2^32 - 1 because m < 66052), in
+    // the point-major buffer D (one coalesced 64-byte store per lane); the
+    // fold kernel adds them to the slot-major running sums
+    if (has_q) {
+      uint32_t t[GRP];
+#pragma unroll
+      for (int g = 0; g < GRP; ++g) t[g] = (act & (1u << g)) ? xx + qq[g] - 2u * xq[g] : QL_NONE;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) drow[c] = make_uint4(t[4 * c], t[4 * c + 1], t[4 * c + 2], t[4 * c + 3]);
+    }
+    my_pairs += (uint64_t)__popc(act);
+    if (lane == 0) my_pts += 1;
+  }
+  if (G.prof) {
+    const uint64_t B_r = (uint64_t)(R.t1 - R.t0);
+    if (my_pairs) {
+      atomicAdd(&G.prof[0], my_pairs * (B_r + 21));
+      atomicAdd(&G.prof[1], my_pairs * B_r);
+    }
+    if (my_pts) atomicAdd(&G.prof[3], my_pts * B_r);
+  }
+}
+
 // ---------------------------------------------------------------- selection
 
-// Writes the K smallest keys of the block (with multiplicity) to out[0..K).
-// Fast path: the K-th smallest of the per-thread minima bounds the block's
-// K-th smallest key from above, so only the keys at or below it (at most
-// K E of them, usually about K) need an exact selection.  The full radix
-// selection over all keys is the fallback when they do not fit in `cand`.
+// Writes the K smallest keys of the block (with multiplicity) to out[0..K);
+// UINT64_MAX marks padding.  Fast path (K <= 64): the K-th smallest of a
+// wave's per-lane minima bounds the block's K-th smallest key from above,
+// and so does the least such bound over the waves (tau).  Only the real keys
+// at or below tau (usually a few times K) are then ordered, by one wave when
+// they fit in it.  The radix selections are the fallbacks.
 constexpr int CAND_CAP = 2048;
 
 template <int E>
 __device__ void emit_smallest(const uint64_t (&key)[E], int K, uint64_t *out, SelScratch &ss, int &cnt,
-                              uint64_t *cand) {
+                              uint64_t *cand, uint64_t *wtau) {
+  constexpr uint64_t PAD = ~0ull;
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
   int less;
   uint64_t v;
   bool done = false;
-  if (K <= NT) {
-    uint64_t mn[1] = {key[0]};
+  if (K <= kWave) {
+    uint64_t mn = key[0];
 #pragma unroll
-    for (int e = 1; e < E; ++e) mn[0] = key[e] < mn[0] ? key[e] : mn[0];
-    const uint64_t tau = block_kth_regs<NT, 1>(mn, K, ss, &less);
+    for (int e = 1; e < E; ++e) mn = key[e] < mn ? key[e] : mn;
+    const uint64_t tw = wave_bcast_u64(wave_sort_u64(mn), K - 1);
+    if (lane == 0) wtau[wave] = tw;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
+    uint64_t tau = wtau[0];
+#pragma unroll
+    for (int w = 1; w < NT / kWave; ++w) tau = wtau[w] < tau ? wtau[w] : tau;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      if (key[e] <= tau) {
+      if (key[e] <= tau && key[e] != PAD) {
         const int pos = atomicAdd(&cnt, 1);
         if (pos < CAND_CAP) cand[pos] = key[e];
       }
@@ -706,6 +972,14 @@ __device__ void emit_smallest(const uint64_t (&key)[E], int K, uint64_t *out, Se
     __syncthreads();
     const int c = cnt;
     __syncthreads();
+    if (c <= kWave) {
+      if (wave == 0) {
+        const uint64_t sv = wave_sort_u64(lane < c ? cand[lane] : PAD);
+        if (lane < K) out[lane] = sv;  // PAD beyond the real keys
+      }
+      __syncthreads();
+      return;
+    }
     if (c <= CAND_CAP) {
       v = block_kth_gen<NT>(c, [&](int64_t p) { return cand[p]; }, K, ss, &less);
       if (threadIdx.x == 0) cnt = 0;
@@ -745,6 +1019,7 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
   __shared__ SelScratch ss;
   __shared__ int cnt;
   __shared__ uint64_t cand[CAND_CAP];
+  __shared__ uint64_t wtau[NT / kWave];
   uint64_t ku[SEL_E], kl[SEL_E];
 #pragma unroll
   for (int e = 0; e < SEL_E; ++e) {
@@ -762,8 +1037,8 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
   }
   const int k = sl->k;
   uint64_t *out = B.part + (int64_t)s * B.part_stride + (int64_t)blockIdx.x * (2 * k + 1);
-  emit_smallest<SEL_E>(ku, k, out, ss, cnt, cand);
-  emit_smallest<SEL_E>(kl, k + 1, out + k, ss, cnt, cand);
+  emit_smallest<SEL_E>(ku, k, out, ss, cnt, cand, wtau);
+  emit_smallest<SEL_E>(kl, k + 1, out + k, ss, cnt, cand, wtau);
 }
 
 constexpr int MT = 1024;  // merge / finish block size
@@ -793,12 +1068,14 @@ __global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, B
 
 // ---------------------------------------------------------------- decide
 
-constexpr int DEC_CH = NT * 8;
+constexpr int DEC_E = 8;
+constexpr int DEC_CH = NT * DEC_E;
 
 // Discard if LCB > U (k kept points are surely closer); accept if fewer
 // than k other points can be closer (UCB <= L2, or for an exact point
 // d <= L1); otherwise keep undecided.  Survivors are compacted into the
-// next lists; order within a list is irrelevant to the result.
+// next lists with one atomic per list and block (ballots give each lane its
+// place); order within a list is irrelevant to the result.
 __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B, Geometry G) {
   const int s = blockIdx.y;
   Slot *sl = &slots[s];
@@ -807,19 +1084,23 @@ __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B,
   const int64_t nA = size_A(sl, n);
   const int64_t base = (int64_t)blockIdx.x * DEC_CH;
   if (base >= nA) return;
-  const int64_t end = min(nA, base + (int64_t)DEC_CH);
   const SlotArrays a = slot_arrays(B, n, s, sl->par);
   const double U = sl->U, L1 = sl->L1, L2 = sl->L2;
-  __shared__ int wcnt[NT / kWave][3];
+  constexpr int NW = NT / kWave;
+  __shared__ int wcnt[DEC_E][NW][3];
   __shared__ int bbase[3];
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  for (int64_t p0 = base; p0 < end; p0 += NT) {
-    const int64_t p = p0 + threadIdx.x;
-    int cat = -1;  // 0 act, 1 xa, 2 acc, -1 none
-    int32_t i = 0;
-    if (p < end) {
-      i = elem_A(sl, a, p);
+  int cat[DEC_E];  // 0 act, 1 xa, 2 acc, -1 none
+  int32_t id[DEC_E];
+#pragma unroll
+  for (int e = 0; e < DEC_E; ++e) {
+    const int64_t p = base + (int64_t)e * NT + threadIdx.x;
+    cat[e] = -1;
+    id[e] = 0;
+    if (p < nA) {
+      const int32_t i = elem_A(sl, a, p);
+      id[e] = i;
       const uint8_t f = a.fl[i];
       double d, al;
       point_bounds(sl, m, a.S[i], f, a.ri[i], d, al);
@@ -829,41 +1110,45 @@ __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B,
         a.fl[i] = f | FL_DISC;
       } else if (exact ? (ucb <= L1) : (ucb <= L2)) {
         a.fl[i] = f | FL_ACC;
-        cat = 2;
+        cat[e] = 2;
       } else {
-        cat = exact ? 1 : 0;
+        cat[e] = exact ? 1 : 0;
       }
     }
-    uint64_t mk[3];
-    int off[3];
+  }
+#pragma unroll
+  for (int e = 0; e < DEC_E; ++e) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      mk[c] = __ballot(cat == c);
-      off[c] = __popcll(mk[c] & lt_mask);
+      const uint64_t mk = __ballot(cat[e] == c);
+      if (lane == 0) wcnt[e][wave][c] = __popcll(mk);
     }
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) wcnt[wave][c] = __popcll(mk[c]);
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-      const int c = threadIdx.x;
-      int tot = 0;
-      for (int w = 0; w < NT / kWave; ++w) {
-        const int t = wcnt[w][c];
-        wcnt[w][c] = tot;  // exclusive prefix over waves
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int c = threadIdx.x;
+    int tot = 0;
+    for (int e = 0; e < DEC_E; ++e)
+      for (int w = 0; w < NW; ++w) {
+        const int t = wcnt[e][w][c];
+        wcnt[e][w][c] = tot;  // exclusive prefix in (e, wave) order
         tot += t;
       }
-      int *ctr = c == 0 ? &sl->nn_act : (c == 1 ? &sl->nn_xa : &sl->nn_acc);
-      bbase[c] = tot ? atomicAdd(ctr, tot) : 0;
+    int *ctr = c == 0 ? &sl->nn_act : (c == 1 ? &sl->nn_xa : &sl->nn_acc);
+    bbase[c] = tot ? atomicAdd(ctr, tot) : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < DEC_E; ++e) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const uint64_t mk = __ballot(cat[e] == c);
+      if (cat[e] == c) {
+        const int pos = bbase[c] + wcnt[e][wave][c] + __popcll(mk & lt_mask);
+        int32_t *dst = c == 0 ? a.act_n : (c == 1 ? a.xa_n : a.acc);
+        dst[pos] = id[e];
+      }
     }
-    __syncthreads();
-    if (cat >= 0) {
-      const int pos = bbase[cat] + wcnt[wave][cat] + off[cat];
-      int32_t *dst = cat == 0 ? a.act_n : (cat == 1 ? a.xa_n : a.acc);
-      dst[pos] = i;
-    }
-    __syncthreads();
   }
 }
 
@@ -1109,9 +1394,15 @@ __device__ void finalize(Slot *sl, int s, const QDesc &qd, const uint8_t *X, con
 // a loop whose head and back-edge both hold thread-0-only work around
 // barriers can be restructured so that lane 0 leaves the loop nest while the
 // rest of its wave keeps iterating.
-__device__ void admit(Slot *sl, const QDesc *qd, const Sched *sched, Ctl *ctl, int64_t n, int64_t m) {
+// direct: slot s takes query s (s < nq) without touching the shared counter,
+// which the host has already set past those queries (first admission of a
+// batch: one compare-and-swap per slot on one counter would serialise them).
+__device__ void admit(Slot *sl, const QDesc *qd, const Sched *sched, Ctl *ctl, int64_t n, int64_t m,
+                      bool direct) {
   __shared__ int claimed;
-  if (threadIdx.x == 0) {
+  if (direct) {
+    if (threadIdx.x == 0) claimed = (int)blockIdx.x < ctl->nq ? (int)blockIdx.x : -1;
+  } else if (threadIdx.x == 0) {
     const int nq = __atomic_load_n(&ctl->nq, __ATOMIC_RELAXED);
     int cur = __atomic_load_n(&ctl->next_query, __ATOMIC_RELAXED);
     int got = -1;
@@ -1217,7 +1508,7 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
       return;
     }
   }
-  if (sl->state == 0) admit(sl, qd, sched, ctl, n, m);
+  if (sl->state == 0) admit(sl, qd, sched, ctl, n, m, admit_only == 2);
 }
 
 // ---------------------------------------------------------------- launch table
@@ -1241,16 +1532,57 @@ void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, dou
   hipLaunchKernelGGL(k_prep_f32, dim3((unsigned)nq), dim3(NT), 0, st, qd, nq, n, m, lo, hi);
 }
 
+int stage_rows_for(int64_t m, int64_t mp, int want) {
+  // LDS: the transposed query tile (GRP x mp) plus the row tile (rows x m)
+  constexpr int64_t kLds = 160 * 1024 - 4096;  // static shared memory of the kernel stays below 4 KB
+  int rows = 64;
+  while (rows > want || (rows >= 8 && GRP * mp + rows * m > kLds)) rows >>= 1;
+  return rows >= 8 ? rows : 0;
+}
+
+void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint8_t *qt, hipStream_t st) {
+  const int64_t total = m * (int64_t)nqp;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + NT - 1) / NT, 4096);
+  hipLaunchKernelGGL(k_build_qt, dim3(blocks), dim3(NT), 0, st, slots, ns, m, nqp, qt);
+}
+
 void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
-                 const Bufs &B, const Geometry &G0, bool any_cexact, hipStream_t st, int sample_kind) {
+                 const Bufs &B, const Geometry &G0, bool any_cexact, hipStream_t st, int sample_kind,
+                 int stage_rows, const QlRound *ql, const uint8_t *qt, int32_t nqp, uint32_t *qd_buf) {
   Geometry G = G0;
   G.prof = prof_device_counters();
+  G.stage = (G.dtype == KNN_U8 && G.grouped) ? stage_rows : 0;
   const int elem = G.dtype == KNN_U8 ? 1 : 4;
   const size_t qbytes = (size_t)G.m * elem;
   const bool qlds = qbytes <= 48 * 1024;
-  int tok = prof_begin(sample_kind == 1 ? PROF_EXACT : PROF_SAMPLE, st);
-  if (G.dtype == KNN_U8 && G.grouped) {
-    const size_t gbytes = std::max<size_t>((size_t)GRP * G.mp + 8 * GRP, qbytes);
+  const bool use_ql = ql && qt && qd_buf && G.dtype == KNN_U8;
+  int tok = use_ql ? -1 : prof_begin(sample_kind == 1 ? PROF_EXACT : PROF_SAMPLE, st);
+  if (use_ql) {
+    const unsigned bx = (unsigned)std::min<int64_t>((G.n + QL_NW - 1) / QL_NW, 2048);
+    const unsigned by = (unsigned)((nqp + QL_SLOTS - 1) / QL_SLOTS);
+    uint8_t *A = reinterpret_cast<uint8_t *>(qd_buf + G.n * (int64_t)nqp);  // follows D in the arena
+    const dim3 tiles((unsigned)((G.n + FT - 1) / FT), (unsigned)((nqp + FT - 1) / FT));
+    if (!ql->impl) {
+      tok = prof_begin(PROF_QL_AUX, st);
+      hipLaunchKernelGGL(k_flags_ql, tiles, dim3(NT), 0, st, slots, A, nqp, B, G, ql->cur);
+      prof_end(tok, st, 0.0);
+    }
+    tok = prof_begin(PROF_SAMPLE, st);
+    hipLaunchKernelGGL(k_sample_ql_u8, dim3(bx, by), dim3(QL_BT), 0, st, slots, X, qt, nqp, A, qd_buf, B, G, *ql);
+    prof_end(tok, st, 0.0);
+    tok = prof_begin(PROF_QL_AUX, st);
+    hipLaunchKernelGGL(k_fold_ql, tiles, dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur);
+  } else if (G.dtype == KNN_U8 && G.grouped) {
+    size_t gbytes = std::max<size_t>((size_t)GRP * G.mp + 8 * GRP, qbytes);
+    if (G.stage > 0) {
+      gbytes = std::max<size_t>(gbytes, (size_t)GRP * G.mp + (size_t)G.stage * G.m);
+      static bool attr_set = false;
+      if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sample_grp_u8),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+        attr_set = true;
+      }
+    }
     dim3 grid((unsigned)((G.nslots + GRP - 1) / GRP), (unsigned)((G.n + G.ch_sample - 1) / G.ch_sample));
     hipLaunchKernelGGL(k_sample_grp_u8, grid, dim3(GBT), gbytes, st, slots, X, G.x8, G.xn, G.mp, B, G);
   } else if (G.dtype == KNN_U8) {
@@ -1288,12 +1620,13 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
 }
 
 void launch_admit(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X, const Bufs &B,
-                  const Geometry &G, hipStream_t st) {
+                  const Geometry &G, hipStream_t st, bool direct) {
   const unsigned ns = (unsigned)G.nslots;
+  const int mode = direct ? 2 : 1;
   if (G.dtype == KNN_U8)
-    hipLaunchKernelGGL(k_finish<KNN_U8>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, 1);
+    hipLaunchKernelGGL(k_finish<KNN_U8>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, mode);
   else
-    hipLaunchKernelGGL(k_finish<KNN_F32>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, 1);
+    hipLaunchKernelGGL(k_finish<KNN_F32>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, mode);
 }
 
 int64_t part_words(int64_t n, int32_t kmax, int32_t cmax) {

@@ -89,7 +89,7 @@ size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax) {
 }
 
 int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cmax, int64_t qcap, int64_t nsched,
-                  hipStream_t st, bool async_alloc, bool grouped) {
+                  hipStream_t st, bool async_alloc, bool grouped, bool query_lane) {
   const int64_t n = db->n;
   const int64_t pw = part_words(n, kmax, cmax);
   size_t off = 0;
@@ -109,6 +109,9 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   const size_t o_xa = take((size_t)ns * n * 8);
   const size_t o_acc = take((size_t)ns * n * 4);
   const size_t o_part = take((size_t)ns * pw * 8);
+  const int32_t nqp = query_lane ? (int32_t)((ns + 15) / 16 * 16) : 0;
+  const size_t o_qt = take((size_t)nqp * (size_t)db->m);
+  const size_t o_qdl = take((size_t)nqp * (size_t)n * 5);  // round totals [n][nqp] u32, then flags [n][nqp] u8
   void *base = nullptr;
   if (async_alloc)
     HIP_TRY(hipMallocAsync(&base, off, st));
@@ -131,6 +134,9 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.B.acc = (int32_t *)at(o_acc);
   E.B.part = (uint64_t *)at(o_part);
   E.B.part_stride = pw;
+  E.qt = query_lane ? at(o_qt) : nullptr;
+  E.qsum = query_lane ? (uint32_t *)at(o_qdl) : nullptr;
+  E.nqp = nqp;
   E.B.cand = nullptr;
   E.G.n = n;
   E.G.m = db->m;
@@ -164,8 +170,9 @@ int engine_destroy(Engine &E) {
   return KNN_OK;
 }
 
-void engine_step(Engine &E, bool any_cexact, int sample_kind) {
-  launch_step(E.slots, E.qd, E.sched, E.ctl, E.db->X, E.B, E.G, any_cexact, E.st, sample_kind);
+void engine_step(Engine &E, bool any_cexact, int sample_kind, int stage_rows, const QlRound *ql) {
+  launch_step(E.slots, E.qd, E.sched, E.ctl, E.db->X, E.B, E.G, any_cexact, E.st, sample_kind, stage_rows, ql, E.qt,
+              E.nqp, E.qsum);
 }
 
 int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &pp, QDesc &d, Sched &sc) {
@@ -251,13 +258,20 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
   bool same = true;
   for (int64_t q = 1; q < nq && same; ++q)
     same = P.qd[q].seed == P.qd[0].seed && P.qd[q].sched == P.qd[0].sched;
-  int rc = engine_create(E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, true, same);
+  // Query-lane sampling: with every query in flight at once (nq <= ns) and
+  // one seed and schedule, all slots run the same round at each step, so a
+  // wave can serve one point for many slots at a time.
+  const bool query_lane = same && db->dtype == KNN_U8 && m < 65536 && (nq <= ns || stop_after > 0) &&
+                          P.sched.size() == 1 &&
+                          ns >= env_int("KNN_QL_MIN", 64) && env_int("KNN_QL", 1) != 0;
+  int rc = engine_create(E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, true, same, query_lane);
   if (rc != KNN_OK) return rc;
   Ctl ctl;
   std::memset(&ctl, 0, sizeof(ctl));
   ctl.nq = (int32_t)nq;
   ctl.qcap = (int32_t)nq;
   ctl.stop_after = stop_after;
+  ctl.next_query = (int32_t)std::min<int64_t>(ns, nq);  // the first admission hands query s to slot s
   auto chk = [&](hipError_t e, const char *what) {
     if (e != hipSuccess && rc == KNN_OK)
       rc = fail(e == hipErrorOutOfMemory ? KNN_ENOMEM : KNN_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -268,7 +282,8 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
       "copy schedules");
   if (rc == KNN_OK) {
     if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, st);
-    launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st);
+    launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st, true);
+    if (E.qt) launch_build_qt(E.slots, (int32_t)E.ns, m, E.nqp, E.qt, st);
     chk(hipGetLastError(), "launch");
   }
   const int steps_gen = P.rmax + 1;
@@ -277,8 +292,26 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
       // every query starts together: with one shared schedule, step t runs
       // round t for all of them (timing label only)
       const bool lockstep = P.sched.size() == 1;
-      for (int t = 0; t < steps_gen; ++t)
-        engine_step(E, P.any_cexact, (lockstep && t == P.rmax) ? 1 : 0);
+      // long rounds of grouped sampling read whole point rows into LDS
+      const int stage_min = env_int("KNN_STAGE_MIN", 1 << 30);  // off unless asked for: slower than HBM gathers so far
+      const int stage_rows = E.G.grouped ? stage_rows_for(m, db->mp, env_int("KNN_STAGE_ROWS", 8)) : 0;
+      for (int t = 0; t < steps_gen; ++t) {
+        int stage = 0;
+        if (lockstep && stage_rows > 0 && t < P.sched[0].R) {
+          const int64_t b_r = P.sched[0].T[t] - (t ? P.sched[0].T[t - 1] : 0);
+          if (b_r >= stage_min) stage = stage_rows;
+        }
+        QlRound qr{};
+        const bool ql = E.qt && t < P.sched[0].R;
+        if (ql) {
+          qr.seed = P.qd[0].seed;
+          qr.t0 = t ? (uint32_t)P.sched[0].T[t - 1] : 0u;
+          qr.t1 = (uint32_t)P.sched[0].T[t];
+          qr.cur = t;
+          qr.impl = t == 0;
+        }
+        engine_step(E, P.any_cexact, (lockstep && t == P.rmax) ? 1 : 0, stage, ql ? &qr : nullptr);
+      }
       chk(hipGetLastError(), "launch");
     } else {
       // slots are recycled on the device; poll until every query is done

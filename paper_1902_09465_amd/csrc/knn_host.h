@@ -49,12 +49,17 @@ struct Engine {
   Bufs B{};
   Geometry G{};
   int64_t ns = 0, qcap = 0, nsched = 0;
+  uint8_t *qt = nullptr;  // query-lane sampling: transposed queries [m][nqp] (nullptr: not used)
+  uint32_t *qsum = nullptr;  // query-lane sampling: round totals [n][nqp] u32, then flags [n][nqp] u8
+  int32_t nqp = 0;
 };
 size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax);
 int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cmax, int64_t qcap, int64_t nsched,
-                  hipStream_t st, bool async_alloc, bool grouped);
+                  hipStream_t st, bool async_alloc, bool grouped, bool query_lane = false);
 int engine_destroy(Engine &E);
-void engine_step(Engine &E, bool any_cexact, int sample_kind = 0);
+void engine_step(Engine &E, bool any_cexact, int sample_kind = 0, int stage_rows = 0, const QlRound *ql = nullptr);
+// rows per LDS tile for grouped sampled rounds of an m-dimensional DB (0: none fits)
+int stage_rows_for(int64_t m, int64_t mp, int want);
 // Host-side parameter check + per-query descriptor (no device pointers for the
 // query/outputs are filled here).
 int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &p, QDesc &d, Sched &sc);
@@ -62,9 +67,12 @@ int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &p, QDesc &d, Sch
 // kernels (k_adaptive.hip)
 void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, double hi, hipStream_t st);
 void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
-                 const Bufs &B, const Geometry &G, bool any_cexact, hipStream_t st, int sample_kind = 0);
+                 const Bufs &B, const Geometry &G, bool any_cexact, hipStream_t st, int sample_kind = 0,
+                 int stage_rows = 0, const QlRound *ql = nullptr, const uint8_t *qt = nullptr, int32_t nqp = 0,
+                 uint32_t *qd_buf = nullptr);
+void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint8_t *qt, hipStream_t st);
 void launch_admit(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
-                  const Bufs &B, const Geometry &G, hipStream_t st);
+                  const Bufs &B, const Geometry &G, hipStream_t st, bool direct = false);
 int64_t part_words(int64_t n, int32_t kmax, int32_t cmax);
 
 // kernels (k_naive.hip)

@@ -63,6 +63,15 @@ struct Slot {
   double alpha[kMaxRounds];
 };
 
+// A sampled round that every running slot of a launch shares (query-lane
+// sampling): the common seed, the round's sample range [t0, t1) and index.
+struct QlRound {
+  uint64_t seed;
+  uint32_t t0, t1;
+  int32_t cur;
+  int32_t impl;         // 1: round 0, every point undecided
+};
+
 // Engine control block (device).
 struct Ctl {
   int32_t next_query;   // admission cursor (monotone)
@@ -100,7 +109,7 @@ struct Geometry {
   const int32_t *xn;    // u8 DB: sum (x - 128)^2 per row
   int64_t mp;           // m padded to a multiple of 64
   int32_t grouped;      // 1: sample GRP slots per block when they share seed and round
-  int32_t pad0;
+  int32_t stage;        // grouped sampled rounds: point rows per LDS tile (0: gather from HBM)
 };
 
 // Order-preserving map of a non-NaN double to uint64 (and back).

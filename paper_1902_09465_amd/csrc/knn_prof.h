@@ -17,7 +17,8 @@ enum ProfKind {
   PROF_NAIVE_GEMM = 5, // naive MFMA scan with fused top-k
   PROF_NAIVE_REST = 6, // naive query prep + merge (+ f32 rescoring)
   PROF_EXACT = 7,      // k_sample launches of a lock-step batch's exact round
-  PROF_KINDS = 8
+  PROF_QL_AUX = 8,     // query-lane sampling: flag transpose + fold of the round totals
+  PROF_KINDS = 9
 };
 
 bool prof_enabled();

@@ -53,11 +53,16 @@ def test_tiny_config_parity(P, orc, seed):
         assert set(planted.tolist()) <= set(ref.tolist())
 
 
-@pytest.mark.parametrize("dtype", ["u8", "f32"])
-def test_per_round_state_parity(P, orc, dtype):
+@pytest.mark.parametrize("dtype", ["u8", "u8_staged", "u8_qlane", "f32"])
+def test_per_round_state_parity(P, orc, dtype, monkeypatch):
     """After every decide step the per-point (S, flags, round) equal the oracle's."""
     g = rng(77)
-    if dtype == "u8":
+    if dtype == "u8_staged":  # every sampled round reads the point rows from LDS tiles
+        monkeypatch.setenv("KNN_STAGE_MIN", "4")
+        monkeypatch.setenv("KNN_STAGE_ROWS", "16")
+    if dtype == "u8_qlane":  # query-lane sampling even for a single slot
+        monkeypatch.setenv("KNN_QL_MIN", "1")
+    if dtype.startswith("u8"):
         X, Q = gmm_u8(77, n=5003, m=202, n_centres=6, sigma=25.0, nq=1)
     else:
         X, Q = gmm_f32(77, n=5003, m=101, n_centres=6, sigma=0.3, nq=1)
@@ -118,17 +123,26 @@ def test_more_queries_than_slots(P, orc):
         assert idx[q, :cnt[q]].tolist() == ref.tolist()
 
 
-@pytest.mark.parametrize("knob", [("KNN_LPP", v) for v in ("1", "2", "4", "8", "16", "32", "64")] +
-                         [("KNN_CH_SAMPLE", v) for v in ("64", "256", "4096")] + [("KNN_GROUP", "0")])
-def test_performance_knobs_do_not_change_results(P, orc, knob):
-    X, Q = gmm_u8(13, n=3001, m=256, n_centres=5, sigma=20.0, nq=4)
+KNOBS = ([{"KNN_LPP": v} for v in ("1", "2", "4", "8", "16", "32", "64")] +
+         [{"KNN_QL_MIN": "1"}, {"KNN_QL_MIN": "1", "KNN_GROUP": "0"}] +
+         [{"KNN_CH_SAMPLE": v} for v in ("64", "256", "4096")] + [{"KNN_GROUP": "0"}] +
+         # every sampled round from point rows staged in LDS, at each tile height
+         [{"KNN_STAGE_MIN": "4", "KNN_STAGE_ROWS": v} for v in ("8", "16", "32", "64")] +
+         [{"KNN_STAGE_MIN": "4", "KNN_STAGE_ROWS": "8", "KNN_CH_SAMPLE": "100"}])
+
+
+@pytest.mark.parametrize("knob", KNOBS, ids=lambda k: ",".join(f"{a}={b}" for a, b in k.items()))
+@pytest.mark.parametrize("m", [256, 200])
+def test_performance_knobs_do_not_change_results(P, orc, knob, m):
+    X, Q = gmm_u8(13, n=3001, m=m, n_centres=5, sigma=20.0, nq=4)
     db = P.KnnDB(dev(X))
     base = db.adaptive(dev(Q), 6, P.default_params(seed=1, c_exact=4))
-    os.environ[knob[0]] = knob[1]
+    os.environ.update(knob)
     try:
         alt = db.adaptive(dev(Q), 6, P.default_params(seed=1, c_exact=4))
     finally:
-        del os.environ[knob[0]]
+        for k in knob:
+            del os.environ[k]
     assert torch.equal(base[0], alt[0]) and torch.equal(base[1], alt[1])
     assert np.array_equal(base[2], alt[2])
 
@@ -213,6 +227,18 @@ def test_grouped_shared_seed_batch(P, orc):
     finally:
         del os.environ["KNN_GROUP"]
     assert torch.equal(idx, idx2) and np.array_equal(st, st2)
+    os.environ["KNN_STAGE_MIN"] = "4"  # rows staged in LDS in every sampled round (m = 1000: byte copies)
+    try:
+        idx3, cnt3, st3 = db.adaptive(dev(Q), 10, p)
+    finally:
+        del os.environ["KNN_STAGE_MIN"]
+    assert torch.equal(idx, idx3) and np.array_equal(st, st3)
+    os.environ["KNN_QL"] = "0"  # the default here is query-lane sampling (64 slots); compare with it off
+    try:
+        idx4, cnt4, st4 = db.adaptive(dev(Q), 10, p)
+    finally:
+        del os.environ["KNN_QL"]
+    assert torch.equal(idx, idx4) and np.array_equal(st, st4)
     idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
     for q in range(0, 64, 9):
         ref, rst = orc.adaptive(X, Q[q], 10, oparams(orc, h=10, delta=0.01, seed=99))
