@@ -153,6 +153,14 @@ __device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v) {
   return v;
 }
 
+// Lane l receives lane (63 - l)'s value.
+__device__ __forceinline__ uint64_t wave_bcast_rev_u64(uint64_t v) {
+  const int src = kWave - 1 - lane_id();
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t wave_bcast_u64(uint64_t v, int src) {
   const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
   const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);

@@ -1041,14 +1041,136 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
   emit_smallest<SEL_E>(kl, k + 1, out + k, ss, cnt, cand, wtau);
 }
 
+// Fold + selection for query-lane rounds without candidate-exact: one block
+// takes a tile of FS_SL slots x FS_PT points of the point-major round totals
+// (transposed through LDS), adds them to the slot-major running sums, and
+// then - since the kept set P is exactly the points without a discard flag -
+// computes every kept point's bounds and emits the tile's k smallest UCB and
+// k+1 smallest LCB per slot, as k_select_partial does per chunk of P.
+// One wave handles one slot row at a time, eight points per lane.  Needs
+// k + 1 <= 64 (the wave selection below).
+constexpr int FS_SL = 4, FS_PT = 512;  // 4 slots: one slot row per wave, ~10 KB LDS (highest occupancy of those measured)
+constexpr int FS_E = FS_PT / kWave;
+
+// The K (<= 64) smallest of the wave's E keys per lane (PAD = none), written
+// ascending to out[0..K) (PAD beyond the real keys).  The K-th smallest of
+// the lanes' minima bounds the K-th smallest key; the keys at or below it are
+// ordered by one wave sort when they fit, else by sorting each key column and
+// merging the sorted columns (keeping the 64 smallest).
+template <int E>
+__device__ void wave_smallest(const uint64_t (&key)[E], int K, uint64_t *out, uint64_t *cbuf) {
+  constexpr uint64_t PAD = ~0ull;
+  const int lane = lane_id();
+  uint64_t mn = key[0];
+#pragma unroll
+  for (int e = 1; e < E; ++e) mn = key[e] < mn ? key[e] : mn;
+  const uint64_t tau = wave_bcast_u64(wave_sort_u64(mn), K - 1);
+  int cnt = 0;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const bool c = key[e] <= tau && key[e] != PAD;
+    const uint64_t mk = __ballot(c);
+    const int pos = cnt + __popcll(mk & lt);
+    if (c && pos < kWave) cbuf[pos] = key[e];
+    cnt += __popcll(mk);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint64_t best;
+  if (cnt <= kWave) {
+    best = wave_sort_u64(lane < cnt ? cbuf[lane] : PAD);
+  } else {
+    best = wave_sort_u64(key[0]);
+#pragma unroll
+    for (int e = 1; e < E; ++e) {
+      const uint64_t c = wave_sort_u64(key[e]);
+      const uint64_t r = wave_bcast_rev_u64(c);  // descending
+      uint64_t v = best < r ? best : r;          // bitonic: the 64 smallest of both
+#pragma unroll
+      for (int j = kWave / 2; j > 0; j >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, j);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
+      }
+      best = v;
+    }
+  }
+  if (lane < K) out[lane] = best;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();  // cbuf is reused by the next call
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(NT) void k_fold_select_ql(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
+                                                       int32_t nqp, Bufs B, Geometry G, int32_t cur) {
+  __shared__ uint32_t t[FS_SL][FS_PT + 1];
+  __shared__ uint64_t cbuf[NT / kWave][kWave];
+  const int64_t n = G.n, m = G.m;
+  const int ns = G.nslots;
+  const int64_t i0 = (int64_t)blockIdx.x * FS_PT;
+  const int s0 = (int)blockIdx.y * FS_SL;
+  for (int idx = threadIdx.x; idx < FS_PT * FS_SL; idx += NT) {
+    const int p = idx / FS_SL, c = idx % FS_SL;
+    const int64_t i = i0 + p;
+    t[c][p] = (i < n && s0 + c < nqp) ? D[i * nqp + s0 + c] : QL_NONE;
+  }
+  __syncthreads();
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  for (int r = wave; r < FS_SL; r += NT / kWave) {
+    const int sl = s0 + r;
+    if (sl >= ns) break;
+    const Slot *slp = &slots[sl];
+    if (slp->state != 1 || slp->cur != cur) continue;  // wave-uniform
+    const int k = slp->k;
+    uint64_t ku[FS_E], kl[FS_E];
+#pragma unroll
+    for (int e = 0; e < FS_E; ++e) {
+      const int p = e * kWave + lane;
+      const int64_t i = i0 + p;
+      ku[e] = kl[e] = ~0ull;
+      if (i >= n) continue;
+      const int64_t off = (int64_t)sl * n + i;
+      const uint32_t v = t[r][p];
+      uint8_t f, ri;
+      int64_t S;
+      if (v != QL_NONE) {
+        S = cur == 0 ? (int64_t)v : B.S[off] + (int64_t)v;
+        B.S[off] = S;
+        B.ri[off] = (uint8_t)cur;
+        if (cur == 0) B.fl[off] = 0;
+        f = cur == 0 ? 0 : B.fl[off];
+        ri = (uint8_t)cur;
+      } else {
+        f = B.fl[off];
+        if (f & FL_DISC) continue;
+        S = B.S[off];
+        ri = B.ri[off];
+      }
+      if (f & FL_DISC) continue;
+      double d, al;
+      point_bounds(slp, m, S, f, ri, d, al);
+      ku[e] = dkey(d + al);
+      kl[e] = dkey(d - al);
+    }
+    uint64_t *out = B.part + (int64_t)sl * B.part_stride + (int64_t)blockIdx.x * (2 * k + 1);
+    wave_smallest<FS_E>(ku, k, out, cbuf[wave]);
+    wave_smallest<FS_E>(kl, k + 1, out + k, cbuf[wave]);
+  }
+}
+
 constexpr int MT = 1024;  // merge / finish block size
 
-__global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, Bufs B, Geometry G) {
+// fs_chunk > 0: the partials came from k_fold_select_ql, one per fs_chunk
+// points of [0, n); otherwise from k_select_partial, one per SEL_CH of P.
+__global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, Bufs B, Geometry G, int32_t fs_chunk) {
   const int s = blockIdx.x;
   Slot *sl = &slots[s];
   if (sl->state != 1) return;
   const int64_t nP = size_P(sl, G.n);
-  const int64_t nch = (nP + SEL_CH - 1) / SEL_CH;
+  const int64_t nch = fs_chunk > 0 ? (G.n + fs_chunk - 1) / fs_chunk : (nP + SEL_CH - 1) / SEL_CH;
   const int k = sl->k;
   const int64_t w = 2 * k + 1;
   const uint64_t *part = B.part + (int64_t)s * B.part_stride;
@@ -1556,6 +1678,8 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
   const size_t qbytes = (size_t)G.m * elem;
   const bool qlds = qbytes <= 48 * 1024;
   const bool use_ql = ql && qt && qd_buf && G.dtype == KNN_U8;
+  // fold and selection in one pass (candidate-exact must run between them)
+  const bool fused_sel = use_ql && !any_cexact && G.kmax + 1 <= kWave;
   int tok = use_ql ? -1 : prof_begin(sample_kind == 1 ? PROF_EXACT : PROF_SAMPLE, st);
   if (use_ql) {
     const unsigned bx = (unsigned)std::min<int64_t>((G.n + QL_NW - 1) / QL_NW, 2048);
@@ -1570,8 +1694,14 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     tok = prof_begin(PROF_SAMPLE, st);
     hipLaunchKernelGGL(k_sample_ql_u8, dim3(bx, by), dim3(QL_BT), 0, st, slots, X, qt, nqp, A, qd_buf, B, G, *ql);
     prof_end(tok, st, 0.0);
-    tok = prof_begin(PROF_QL_AUX, st);
-    hipLaunchKernelGGL(k_fold_ql, tiles, dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur);
+    if (fused_sel) {
+      tok = prof_begin(PROF_SELECT, st);
+      hipLaunchKernelGGL(k_fold_select_ql, dim3((unsigned)((G.n + FS_PT - 1) / FS_PT), (unsigned)((nqp + FS_SL - 1) / FS_SL)),
+                         dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur);
+    } else {
+      tok = prof_begin(PROF_QL_AUX, st);
+      hipLaunchKernelGGL(k_fold_ql, tiles, dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur);
+    }
   } else if (G.dtype == KNN_U8 && G.grouped) {
     size_t gbytes = std::max<size_t>((size_t)GRP * G.mp + 8 * GRP, qbytes);
     if (G.stage > 0) {
@@ -1602,10 +1732,14 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
       hipLaunchKernelGGL(k_cand_merge<KNN_F32>, dim3(ns), dim3(MT), 0, st, slots, X, B, G);
     prof_end(tok, st, 0.0);
   }
-  tok = prof_begin(PROF_SELECT, st);
-  hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((G.n + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st,
-                     slots, B, G);
-  hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G);
+  if (fused_sel) {
+    hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, FS_PT);
+  } else {
+    tok = prof_begin(PROF_SELECT, st);
+    hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((G.n + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st,
+                       slots, B, G);
+    hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, 0);
+  }
   prof_end(tok, st, 0.0);
   tok = prof_begin(PROF_DECIDE, st);
   hipLaunchKernelGGL(k_decide, dim3((unsigned)((G.n + DEC_CH - 1) / DEC_CH), ns), dim3(NT), 0, st, slots,
@@ -1630,7 +1764,8 @@ void launch_admit(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, co
 }
 
 int64_t part_words(int64_t n, int32_t kmax, int32_t cmax) {
-  const int64_t nsel = (n + SEL_CH - 1) / SEL_CH;
+  int64_t nsel = (n + SEL_CH - 1) / SEL_CH;
+  if (kmax + 1 <= kWave) nsel = std::max<int64_t>(nsel, (n + FS_PT - 1) / FS_PT);  // fused query-lane selection
   const int64_t ncand = (n + CAND_CH - 1) / CAND_CH;
   const int64_t a = nsel * (2 * (int64_t)kmax + 1);
   const int64_t c = cmax > 0 ? ncand * (int64_t)min(cmax, CAND_CH) * 2 : 0;  // keys + packed ids

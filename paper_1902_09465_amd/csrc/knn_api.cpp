@@ -151,6 +151,7 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.G.x8 = db->xs8;
   E.G.xn = db->norm_i;
   E.G.mp = db->mp;
+  E.G.kmax = kmax;
   // grouped sampling needs the shared query tile (16 rows of mp bytes) in LDS
   E.G.grouped = (grouped && db->dtype == KNN_U8 && db->xs8 && 16 * db->mp + 128 <= 65536 &&
                  env_int("KNN_GROUP", 1) != 0) ? 1 : 0;

@@ -110,6 +110,8 @@ struct Geometry {
   int64_t mp;           // m padded to a multiple of 64
   int32_t grouped;      // 1: sample GRP slots per block when they share seed and round
   int32_t stage;        // grouped sampled rounds: point rows per LDS tile (0: gather from HBM)
+  int32_t kmax;         // largest k of the slots' queries
+  int32_t pad1;
 };
 
 // Order-preserving map of a non-NaN double to uint64 (and back).

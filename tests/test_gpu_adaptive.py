@@ -53,21 +53,23 @@ def test_tiny_config_parity(P, orc, seed):
         assert set(planted.tolist()) <= set(ref.tolist())
 
 
-@pytest.mark.parametrize("dtype", ["u8", "u8_staged", "u8_qlane", "f32"])
+@pytest.mark.parametrize("dtype", ["u8", "u8_staged", "u8_qlane", "u8_qlane_pure", "f32"])
 def test_per_round_state_parity(P, orc, dtype, monkeypatch):
     """After every decide step the per-point (S, flags, round) equal the oracle's."""
     g = rng(77)
     if dtype == "u8_staged":  # every sampled round reads the point rows from LDS tiles
         monkeypatch.setenv("KNN_STAGE_MIN", "4")
         monkeypatch.setenv("KNN_STAGE_ROWS", "16")
-    if dtype == "u8_qlane":  # query-lane sampling even for a single slot
+    if dtype.startswith("u8_qlane"):  # query-lane sampling even for a single slot
         monkeypatch.setenv("KNN_QL_MIN", "1")
     if dtype.startswith("u8"):
         X, Q = gmm_u8(77, n=5003, m=202, n_centres=6, sigma=25.0, nq=1)
     else:
         X, Q = gmm_f32(77, n=5003, m=101, n_centres=6, sigma=0.3, nq=1)
     db = P.KnnDB(dev(X))
-    kw = dict(h=4, delta=0.05, seed=int(g.integers(1 << 40)), b0=8, growth=1.5, c_exact=3)
+    # candidate-exact on, except in the pure variant (fused fold + selection)
+    kw = dict(h=4, delta=0.05, seed=int(g.integers(1 << 40)), b0=8, growth=1.5,
+              c_exact=0 if dtype.endswith("pure") else 3)
     T = orc.schedule(8, 1.5, 1.0, X.shape[1])
     for r in range(1, len(T) + 2):
         S, fl, ri = db.adaptive_state(dev(Q), 6, P.default_params(**kw), r)
