@@ -105,6 +105,125 @@ def cpu_baseline(X, Q, seconds_hint):
                       f"{np.median(per_q):.1f} s"}
 
 
+def serving(args):
+    """Serving workload: three resident DBs in one session, requests with
+    k ~ U{1..50}, delta in {0.01, 0.05} and their own seeds.  First the
+    closed-loop saturation rate (every request submitted at once), then
+    Poisson arrivals at 0.3, 0.6 and 0.9 of it; latency = completion - arrival
+    on the host clock, completion seen by a poller thread."""
+    import threading
+    import torch
+    from knn_inputs import serving_dbs, rng
+
+    P = load_lib()
+    log("generating the three serving databases")
+    data = serving_dbs(5000, scale=args.serving_scale)
+    dbs, qpools = [], []
+    for X, Q in data:
+        dbs.append(P.KnnDB(torch.from_numpy(X).cuda()))
+        qpools.append(Q)
+    torch.cuda.synchronize()
+    free = torch.cuda.mem_get_info()[0]
+    sess = P.Session(int(min(free * 0.6, args.serving_budget_gb * (1 << 30))))
+    ids = [sess.add_db(db) for db in dbs]
+    g = rng(5100)
+
+    def make_requests(count):
+        reqs = []
+        for _ in range(count):
+            d = int(g.integers(0, 3))
+            q = qpools[d][int(g.integers(0, qpools[d].shape[0]))]
+            k = int(g.integers(1, 51))
+            delta = 0.01 if g.integers(0, 2) == 0 else 0.05
+            reqs.append((d, q, k, P.default_params(h=k, delta=delta, seed=int(g.integers(1 << 40)))))
+        return reqs
+
+    def run(reqs, arrivals):
+        """Submits reqs at the given arrival offsets (seconds; None = all at
+        once) and returns (latencies, completion results, wall seconds)."""
+        n = len(reqs)
+        t_sub = [0.0] * n
+        tickets = [None] * n
+        lat = [None] * n
+        res = [None] * n
+        done_sub = threading.Event()
+        t0 = time.perf_counter()
+
+        def submitter():
+            for i, (d, q, k, p) in enumerate(reqs):
+                if arrivals is not None:
+                    wait = t0 + arrivals[i] - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                t_sub[i] = time.perf_counter() if arrivals is None else t0 + arrivals[i]
+                tickets[i] = sess.submit(ids[d], q, k, p)
+            done_sub.set()
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        pending = set()
+        nxt = 0
+        finished = 0
+        while finished < n:
+            while nxt < n and tickets[nxt] is not None:
+                pending.add(nxt)
+                nxt += 1
+            for i in list(pending):
+                r = sess.poll(tickets[i], reqs[i][2] * 2)
+                if r is not None:
+                    lat[i] = time.perf_counter() - t_sub[i]
+                    res[i] = r
+                    pending.discard(i)
+                    finished += 1
+            time.sleep(0.0002)
+        th.join()
+        return lat, res, time.perf_counter() - t0
+
+    log("warm-up")
+    run(make_requests(args.serving_warmup), None)
+    log("closed-loop saturation")
+    sat_reqs = make_requests(args.serving_requests)
+    _, _, wall = run(sat_reqs, None)
+    sat_rate = len(sat_reqs) / wall
+    out_rates = []
+    for frac in (0.3, 0.6, 0.9):
+        rate = frac * sat_rate
+        reqs = make_requests(args.serving_requests)
+        arrivals = np.cumsum(g.exponential(1.0 / rate, size=len(reqs)))
+        log(f"Poisson arrivals at {rate:.1f} req/s ({frac} x saturation)")
+        lat, res, wall = run(reqs, arrivals)
+        lat_ms = np.array(lat) * 1e3
+        # containment of a sample of the answers, against the exact scan
+        ok = tot = 0
+        for i in range(0, len(reqs), max(1, len(reqs) // 64)):
+            d, q, k, _ = reqs[i]
+            qd = torch.from_numpy(np.ascontiguousarray(q[None])).cuda()
+            nidx, ndist = dbs[d].naive(qd, k)
+            got = set(res[i][0].tolist())
+            X = data[d][0]
+            dk = float(ndist[0, k - 1])
+            need = [int(j) for j, dj in zip(nidx[0].tolist(), ndist[0].tolist()) if dj < dk]
+            dist_got = [float(((X[j].astype(np.float64) - q.astype(np.float64)) ** 2).sum()) for j in got]
+            n_le = sum(1 for v in dist_got if v <= dk * (1 + 1e-12))
+            ok += int(all(j in got for j in need) and n_le >= k)
+            tot += 1
+        out_rates.append({"offered_per_s": rate, "fraction_of_saturation": frac, "requests": len(reqs),
+                          "achieved_per_s": len(reqs) / wall, "p50_ms": float(np.percentile(lat_ms, 50)),
+                          "p99_ms": float(np.percentile(lat_ms, 99)), "mean_ms": float(lat_ms.mean()),
+                          "contained_sampled": f"{ok}/{tot}"})
+    sess.close()
+    out = {"metric": "serving queries/s and p50/p99 latency (continuous batching, three resident DBs)",
+           "value": sat_rate, "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "u8+f32", "data": "synthetic",
+           "config": {"workload": "serving: DB A 50,000x784 u8 (10-centre mixture, sigma 30), DB B 500,000x256 "
+                                  "f32 and DB C 2,000,000x96 f32 (1,000-cluster mixtures, sigma 0.1), sizes x "
+                                  f"{args.serving_scale}; k ~ U(1..50), h = k, delta in (0.01, 0.05), "
+                                  "DB uniform, per-request seeds"},
+           "saturation_per_s": sat_rate, "rates": out_rates}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +231,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--serving", action="store_true", help="serving workload instead of the batch line")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-warmup", type=int, default=200)
+    ap.add_argument("--serving-scale", type=float, default=1.0)
+    ap.add_argument("--serving-budget-gb", type=float, default=96.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures a single MI355X "
@@ -120,6 +244,8 @@ def main():
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py is single-GPU; do not launch it with several ranks", file=sys.stderr)
         return 2
+    if args.serving:
+        return serving(args)
     import torch
     from knn_inputs import gmm_u8
 

@@ -3,14 +3,16 @@
 //
 // Each DB added to a session gets a slot engine (device state for a fixed
 // number of in-flight queries, sized from the session's HBM budget) on its
-// own HIP stream, plus device rings for query vectors, descriptors and
-// results.  A background thread loops:
-//   1. moves submitted requests into free ring entries (uploads the query,
-//      its descriptor and schedule, then raises the engine's query count);
-//   2. launches one round ("step") on every engine with work -- queries
-//      admitted on the device join at this round boundary while the others
-//      continue where they are;
-//   3. synchronises the streams and collects finished queries.
+// own HIP stream, device rings for query vectors, descriptors and results,
+// and its own worker thread, so that DBs progress independently.  A worker
+// loops:
+//   1. moves submitted requests into free ring entries (uploads the queries,
+//      descriptors and schedules of the whole batch, then raises the
+//      engine's query count);
+//   2. launches one round ("step") on the engine -- queries admitted on the
+//      device join at this round boundary while the others continue where
+//      they are;
+//   3. synchronises its stream and collects finished queries.
 // Requests therefore overlap on the device and are admitted as slots and
 // memory free up; each result depends only on (query, DB, k, params).
 #include <hip/hip_runtime.h>
@@ -40,6 +42,7 @@ struct Request {
   int32_t db_id = 0;
   std::vector<uint8_t> q;
   QDesc d{};
+  QDesc dd{};           // the descriptor as uploaded (device pointers filled in)
   Sched sc{};
   bool done = false;
   int err = KNN_OK;
@@ -62,6 +65,9 @@ struct DbEngine {
   int64_t inflight = 0;
   std::deque<Request *> pending;
   std::vector<int32_t> hcnt;
+  int32_t nq_host = 0;         // source of the query-count upload
+  std::condition_variable cv;  // new requests for this DB
+  std::thread worker;
 };
 
 }  // namespace knn
@@ -69,11 +75,9 @@ struct DbEngine {
 struct knn_session_s {
   size_t budget = 0, reserved = 0;
   std::mutex mu;
-  std::condition_variable cv;
   std::vector<std::unique_ptr<knn::DbEngine>> dbs;
   std::unordered_map<uint64_t, knn::Request *> reqs;
   uint64_t next_ticket = 1;
-  std::thread loop;
   std::atomic<bool> stop{false};
   std::atomic<int> failed{0};
   std::string fail_msg;
@@ -88,110 +92,105 @@ static int upload(DbEngine &D, std::vector<Request *> &batch, std::string &err) 
     if (e != hipSuccess) err = std::string(what) + ": " + hipGetErrorString(e);
     return e == hipSuccess;
   };
+  static const int32_t minus1 = -1;
+  // every host source below (the request's query and descriptor, nq_host)
+  // stays valid until the single synchronisation at the end of the batch
   for (Request *r : batch) {
     const int64_t slot = D.submitted % D.qcap;
-    QDesc d = r->d;
+    QDesc &d = r->dd;
+    d = r->d;
     d.q = D.dq + slot * m * elem;
     d.sched = (int32_t)slot;
     d.out_idx = D.didx + slot * kSessionMaxKH;
     d.out_stride = kSessionMaxKH;
     d.out_count = D.dcnt + slot;
     d.out_stats = D.dstats + slot;
-    const int32_t minus1 = -1;
     if (!ok(hipMemcpyAsync((void *)d.q, r->q.data(), m * elem, hipMemcpyHostToDevice, D.st), "upload query") ||
         !ok(hipMemcpyAsync(D.E.qd + slot, &d, sizeof(QDesc), hipMemcpyHostToDevice, D.st), "upload desc") ||
         !ok(hipMemcpyAsync(D.E.sched + slot, &r->sc, sizeof(Sched), hipMemcpyHostToDevice, D.st), "upload sched") ||
         !ok(hipMemcpyAsync(D.dcnt + slot, &minus1, sizeof(int32_t), hipMemcpyHostToDevice, D.st), "reset count"))
       return KNN_EDEVICE;
-    // the host buffers above must stay valid until the copies ran
-    if (!ok(hipStreamSynchronize(D.st), "upload sync")) return KNN_EDEVICE;
     if (D.db->dtype == KNN_F32) launch_prep_f32(D.E.qd + slot, 1, D.db->n, m, D.db->lo, D.db->hi, D.st);
     D.ring[slot] = r;
     D.inflight++;
     D.submitted++;
   }
-  const int32_t nq = D.submitted;
-  if (!ok(hipMemcpyAsync(&D.E.ctl->nq, &nq, sizeof(int32_t), hipMemcpyHostToDevice, D.st), "raise nq") ||
-      !ok(hipStreamSynchronize(D.st), "raise sync"))
+  D.nq_host = D.submitted;
+  if (!ok(hipMemcpyAsync(&D.E.ctl->nq, &D.nq_host, sizeof(int32_t), hipMemcpyHostToDevice, D.st), "raise nq") ||
+      !ok(hipStreamSynchronize(D.st), "upload sync"))
     return KNN_EDEVICE;
   return KNN_OK;
 }
 
-static void session_loop(knn_session_s *S) {
+static void fail_all(knn_session_s *S, DbEngine &D, const std::string &msg) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->fail_msg = msg;
+  S->failed = 1;
+  for (int64_t s = 0; s < D.qcap; ++s)
+    if (D.ring[s]) {
+      D.ring[s]->done = true;
+      D.ring[s]->err = KNN_EDEVICE;
+      D.ring[s] = nullptr;
+    }
+  D.inflight = 0;
+}
+
+static void db_loop(knn_session_s *S, DbEngine *Dp) {
+  DbEngine &D = *Dp;
   std::string err;
   while (!S->stop.load()) {
     // 1. admission: move pending requests into free ring entries
-    std::vector<std::pair<DbEngine *, std::vector<Request *>>> work;
-    bool any = false;
+    std::vector<Request *> batch;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      for (auto &up : S->dbs) {
-        DbEngine &D = *up;
-        std::vector<Request *> batch;
-        int32_t next = D.submitted;
-        while (!D.pending.empty() && D.ring[next % D.qcap] == nullptr &&
-               D.inflight + (int64_t)batch.size() < D.qcap) {
-          batch.push_back(D.pending.front());
-          D.pending.pop_front();
-          ++next;
-        }
-        if (!batch.empty()) work.emplace_back(&D, std::move(batch));
-        if (D.inflight > 0 || !work.empty()) any = true;
+      int32_t next = D.submitted;
+      while (!D.pending.empty() && D.ring[next % D.qcap] == nullptr &&
+             D.inflight + (int64_t)batch.size() < D.qcap) {
+        batch.push_back(D.pending.front());
+        D.pending.pop_front();
+        ++next;
       }
-      if (!any) {
-        S->cv.wait_for(lk, std::chrono::microseconds(500));
+      if (batch.empty() && D.inflight == 0) {
+        D.cv.wait_for(lk, std::chrono::microseconds(500));
         continue;
       }
     }
-    for (auto &w : work) {
-      if (upload(*w.first, w.second, err) != KNN_OK) {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->fail_msg = err;
-        S->failed = 1;
-        for (Request *r : w.second) {
-          r->done = true;
-          r->err = KNN_EDEVICE;
-        }
-      }
-    }
-    // 2. one round on every engine with work
-    for (auto &up : S->dbs) {
-      DbEngine &D = *up;
-      if (D.inflight > 0) engine_step(D.E, true);
-    }
-    // 3. collect finished queries
-    for (auto &up : S->dbs) {
-      DbEngine &D = *up;
-      if (D.inflight == 0) continue;
-      hipError_t e = hipMemcpyAsync(D.hcnt.data(), D.dcnt, sizeof(int32_t) * D.qcap, hipMemcpyDeviceToHost, D.st);
-      if (e == hipSuccess) e = hipStreamSynchronize(D.st);
-      if (e != hipSuccess) {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->fail_msg = std::string("session step: ") + hipGetErrorString(e);
-        S->failed = 1;
-        for (int64_t s = 0; s < D.qcap; ++s)
-          if (D.ring[s]) {
-            D.ring[s]->done = true;
-            D.ring[s]->err = KNN_EDEVICE;
-            D.ring[s] = nullptr;
-          }
-        D.inflight = 0;
-        continue;
-      }
-      for (int64_t s = 0; s < D.qcap; ++s) {
-        Request *r = D.ring[s];
-        if (!r || D.hcnt[s] < 0) continue;
-        r->count = D.hcnt[s];
-        r->idx.assign(std::max<int64_t>(r->d.kh, 1), -1);
-        e = hipMemcpy(r->idx.data(), D.didx + s * kSessionMaxKH, sizeof(int64_t) * std::min<int64_t>(r->d.kh, kSessionMaxKH),
-                      hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMemcpy(&r->st, D.dstats + s, sizeof(knn_stats), hipMemcpyDeviceToHost);
-        std::lock_guard<std::mutex> lk(S->mu);
-        if (e != hipSuccess) r->err = KNN_EDEVICE;
+    if (!batch.empty() && upload(D, batch, err) != KNN_OK) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->fail_msg = err;
+      S->failed = 1;
+      for (Request *r : batch) {
         r->done = true;
-        D.ring[s] = nullptr;
-        D.inflight--;
+        r->err = KNN_EDEVICE;
       }
+      continue;
+    }
+    // 2. one round
+    engine_step(D.E, true);
+    // 3. collect finished queries
+    hipError_t e = hipMemcpyAsync(D.hcnt.data(), D.dcnt, sizeof(int32_t) * D.qcap, hipMemcpyDeviceToHost, D.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(D.st);
+    if (e != hipSuccess) {
+      fail_all(S, D, std::string("session step: ") + hipGetErrorString(e));
+      continue;
+    }
+    for (int64_t s = 0; s < D.qcap; ++s) {
+      Request *r = D.ring[s];
+      if (!r || D.hcnt[s] < 0) continue;
+      r->count = D.hcnt[s];
+      std::vector<int64_t> idx(std::max<int64_t>(r->d.kh, 1), -1);
+      knn_stats st{};
+      e = hipMemcpyAsync(idx.data(), D.didx + s * kSessionMaxKH, sizeof(int64_t) * std::min<int64_t>(r->d.kh, kSessionMaxKH),
+                         hipMemcpyDeviceToHost, D.st);
+      if (e == hipSuccess) e = hipMemcpyAsync(&st, D.dstats + s, sizeof(knn_stats), hipMemcpyDeviceToHost, D.st);
+      if (e == hipSuccess) e = hipStreamSynchronize(D.st);
+      std::lock_guard<std::mutex> lk(S->mu);
+      r->idx.swap(idx);
+      r->st = st;
+      if (e != hipSuccess) r->err = KNN_EDEVICE;
+      r->done = true;
+      D.ring[s] = nullptr;
+      D.inflight--;
     }
   }
 }
@@ -207,7 +206,6 @@ int knn_session_create(size_t hbm_budget_bytes, knn_session *out) {
   if (hbm_budget_bytes < ((size_t)1 << 20)) return fail(KNN_EINVAL, "budget below 1 MiB");
   knn_session_s *S = new knn_session_s();
   S->budget = hbm_budget_bytes;
-  S->loop = std::thread(session_loop, S);
   *out = S;
   return KNN_OK;
 }
@@ -257,7 +255,9 @@ int knn_session_add_db(knn_session S, knn_db db, int32_t *db_id) {
   std::lock_guard<std::mutex> lk(S->mu);
   S->reserved += (size_t)ns * per_slot + (size_t)D->qcap * per_ring;
   *db_id = (int32_t)S->dbs.size();
+  DbEngine *Dp = D.get();
   S->dbs.push_back(std::move(D));
+  Dp->worker = std::thread(db_loop, S, Dp);
   return KNN_OK;
 }
 
@@ -286,7 +286,7 @@ int knn_session_submit(knn_session S, int32_t db_id, const void *host_query, int
     S->reqs.emplace(r->ticket, r.get());
     r.release();
   }
-  S->cv.notify_one();
+  S->dbs[db_id]->cv.notify_one();
   return KNN_OK;
 }
 
@@ -313,8 +313,10 @@ int knn_session_poll(knn_session S, uint64_t ticket, int64_t *host_idx, int32_t 
 int knn_session_destroy(knn_session S) {
   if (!S) return fail(KNN_EINVAL, "NULL session");
   S->stop = true;
-  S->cv.notify_all();
-  if (S->loop.joinable()) S->loop.join();
+  for (auto &up : S->dbs) {
+    up->cv.notify_all();
+    if (up->worker.joinable()) up->worker.join();
+  }
   for (auto &up : S->dbs) {
     DbEngine &D = *up;
     (void)hipStreamSynchronize(D.st);
