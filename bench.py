@@ -301,6 +301,16 @@ def main():
 
     ms_per_step = total_s * 1e3 / args.steps
     value = n_ok / (ms_per_step / 1e3)
+    # the same batch replayed through the cached engine's captured graph
+    # (timing events off: the graph path is taken only then)
+    db.adaptive(Q_t, K, params, with_stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        idx_g, cnt_g, _ = db.adaptive(Q_t, K, params, with_stats=False)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    same_graph = bool(torch.equal(idx_g, idx) and torch.equal(cnt_g, cnt))
 
     # dominant kernel class of the step and its roofline (averages over the timed steps)
     dom = max(prof, key=lambda k_: prof[k_]["ms"])
@@ -364,6 +374,9 @@ def main():
                   "mfma_int8_tops": naive_tops, "mfma_frac": naive_tops / INT8_PEAK_TOPS},
         "adaptive_vs_naive": (value / (NQ / naive_s)) if naive_s > 0 else None,
         "kernels_ms_per_step": {k_: v["ms"] / args.steps for k_, v in prof.items()},
+        "graph_replay": {"ms_per_step": graph_ms, "same_result": same_graph,
+                         "note": "timed region above runs eagerly with per-kernel HIP events; this is the "
+                                 "cached engine replaying its captured launch graph, events off"},
         "dominant_kernel": dom,
         "roofline": roofline,
         "roofline_exact_round": rl_exact,

@@ -135,6 +135,26 @@ int knn_adaptive_state(knn_db db, const void *dev_query, int32_t k, const knn_pa
                        int32_t stop_after, int64_t *host_S, uint8_t *host_fl,
                        uint8_t *host_ri, void *stream);
 
+/* Autotuner for the performance knobs of the adaptive path (none of them
+ * changes a result): runs knn_adaptive on these queries (same k for all,
+ * params shared) once per candidate -- query-lane vs grouped vs per-query
+ * sampling, points per sampling block, lanes per point, graph replay --
+ * times each on `stream` with HIP events (one untimed warm-up, then the
+ * mean of `reps` runs), checks that every candidate returns the same
+ * indices, counts and statistics as the first, and keeps the fastest for
+ * this DB (used by later calls; KNN_* environment variables still
+ * override).  The result-defining schedule (B0, growth g of the round
+ * targets, Section 4) is never changed; when `schedule_report` is nonzero
+ * the times of B0 in {16, 64, 256} x g in {1.5, 2} are measured and
+ * reported too, as a recommendation only.
+ *  report: host buffer (nullable) receiving one line per measurement,
+ *          "name ms" (truncated to report_len, NUL-terminated).
+ * Synchronous; not to be called concurrently with other calls on the same
+ * DB.  Errors: EINVAL, ENOMEM, EDEVICE (also when a candidate's output
+ * differs from the first one's). */
+int knn_autotune(knn_db db, const void *dev_queries, int64_t nq, int32_t k, const knn_params *p,
+                 int32_t reps, int32_t schedule_report, char *report, size_t report_len, void *stream);
+
 /* ------------------------------------------------------------- naive --- */
 
 /* Naive k-NN (Section 3): all n distances, the k smallest by (distance,

@@ -100,6 +100,21 @@ class KnnDB:
             stats = st.cpu().numpy().view(STATS_DTYPE).reshape(nq)
         return idx, cnt, stats
 
+    def autotune(self, Q: torch.Tensor, k: int, params: Params | None = None, reps: int = 2,
+                 schedule_report: bool = False, stream=None) -> dict:
+        """Times the performance knobs on these queries and keeps the fastest
+        for this DB; returns {candidate: ms}."""
+        Q = self._queries(Q)
+        buf = ctypes.create_string_buffer(8192)
+        check(lib().knn_autotune(self.handle, ctypes.c_void_p(Q.data_ptr()), Q.shape[0], k,
+                                 ctypes.byref(params or default_params()), reps, int(schedule_report), buf,
+                                 len(buf), _stream_handle(stream)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, ms = line.rsplit(" ", 1)
+            out[name] = float(ms)
+        return out
+
     def adaptive_state(self, q: torch.Tensor, k: int, params: Params, stop_after: int, stream=None):
         """Per-point state (S, fl, ri) of query q after `stop_after` decide steps."""
         q = self._queries(q)

@@ -5,13 +5,16 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "knn_host.h"
+#include "knn_prof.h"
 
 namespace knn {
 
@@ -83,6 +86,23 @@ static int env_int(const char *name, int dflt) {
   return v ? std::atoi(v) : dflt;
 }
 
+// Performance knobs (never result-defining): the DB's autotuned values when
+// it has them, else the defaults, then KNN_* environment overrides.
+Knobs knobs_for(const knn_db_s *db) {
+  Knobs k;
+  if (db && db->tune.valid) k = db->tune;
+  k.ql = env_int("KNN_QL", k.ql);
+  k.ql_min = env_int("KNN_QL_MIN", k.ql_min);
+  k.group = env_int("KNN_GROUP", k.group);
+  k.lpp = env_int("KNN_LPP", k.lpp);
+  if (k.lpp < 0 || k.lpp > 64 || (k.lpp & (k.lpp - 1)) != 0) k.lpp = 0;
+  k.ch_sample = std::max(1, env_int("KNN_CH_SAMPLE", k.ch_sample));
+  k.stage_min = env_int("KNN_STAGE_MIN", k.stage_min);
+  k.stage_rows = env_int("KNN_STAGE_ROWS", k.stage_rows);
+  k.graph = env_int("KNN_GRAPH", k.graph);
+  return k;
+}
+
 size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax) {
   const int64_t pw = part_words(n, kmax, cmax);
   return (size_t)n * (8 + 1 + 1 + 4 * 2 + 4 * 2 + 4) + (size_t)pw * 8 + sizeof(Slot) + 12 * 256;
@@ -90,6 +110,7 @@ size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax) {
 
 int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cmax, int64_t qcap, int64_t nsched,
                   hipStream_t st, bool async_alloc, bool grouped, bool query_lane) {
+  const Knobs K = knobs_for(db);
   const int64_t n = db->n;
   const int64_t pw = part_words(n, kmax, cmax);
   size_t off = 0;
@@ -142,19 +163,17 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.G.m = db->m;
   E.G.dtype = db->dtype;
   E.G.nslots = (int32_t)ns;
-  E.G.ch_sample = std::max(1, env_int("KNN_CH_SAMPLE", 2048));
+  E.G.ch_sample = K.ch_sample;
   E.G.ch_select = 0;
   E.G.ch_decide = 0;
-  E.G.lpp = env_int("KNN_LPP", 0);  // 0: chosen per round from its sample count
-  if (E.G.lpp < 0 || E.G.lpp > 64 || (E.G.lpp & (E.G.lpp - 1)) != 0) E.G.lpp = 0;
+  E.G.lpp = K.lpp;  // 0: chosen per round from its sample count
   E.G.prof = nullptr;
   E.G.x8 = db->xs8;
   E.G.xn = db->norm_i;
   E.G.mp = db->mp;
   E.G.kmax = kmax;
   // grouped sampling needs the shared query tile (16 rows of mp bytes) in LDS
-  E.G.grouped = (grouped && db->dtype == KNN_U8 && db->xs8 && 16 * db->mp + 128 <= 65536 &&
-                 env_int("KNN_GROUP", 1) != 0) ? 1 : 0;
+  E.G.grouped = (grouped && db->dtype == KNN_U8 && db->xs8 && 16 * db->mp + 128 <= 65536 && K.group != 0) ? 1 : 0;
   E.ns = ns;
   E.qcap = qcap;
   E.nsched = nsched;
@@ -237,11 +256,134 @@ static int prepare(knn_db_s *db, const void *dq, int64_t nq, const int32_t *host
   return KNN_OK;
 }
 
+// The launches of a batch whose queries all start together: (float
+// query prep,) first admission, (query-lane transposed queries,) then one
+// step per round.  With one shared schedule, step t runs round t for all
+// of them.  Used eagerly and under graph capture.
+static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knobs &K, hipStream_t st) {
+  knn_db_s *db = E.db;
+  const int64_t n = db->n, m = db->m;
+  if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, st);
+  launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st, true);
+  if (E.qt) launch_build_qt(E.slots, (int32_t)E.ns, m, E.nqp, E.qt, st);
+  const bool lockstep = P.sched.size() == 1;
+  // long rounds of grouped sampling read whole point rows into LDS
+  const int stage_rows = E.G.grouped ? stage_rows_for(m, db->mp, K.stage_rows) : 0;
+  for (int t = 0; t < P.rmax + 1; ++t) {
+    int stage = 0;
+    if (lockstep && stage_rows > 0 && t < P.sched[0].R) {
+      const int64_t b_r = P.sched[0].T[t] - (t ? P.sched[0].T[t - 1] : 0);
+      if (b_r >= K.stage_min) stage = stage_rows;
+    }
+    QlRound qr{};
+    const bool ql = E.qt && t < P.sched[0].R;
+    if (ql) {
+      qr.seed = P.qd[0].seed;
+      qr.t0 = t ? (uint32_t)P.sched[0].T[t - 1] : 0u;
+      qr.t1 = (uint32_t)P.sched[0].T[t];
+      qr.cur = t;
+      qr.impl = t == 0;
+    }
+    engine_step(E, P.any_cexact, (lockstep && t == P.rmax) ? 1 : 0, stage, ql ? &qr : nullptr);
+  }
+}
+
+// Resets the slots and the control block of a cached engine at the start of
+// a graph replay (a kernel, not a memset node).
+__global__ void k_reset_engine(uint32_t *slots_words, int64_t nwords, Ctl *ctl, const Ctl *ctl_init) {
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += (int64_t)gridDim.x * blockDim.x)
+    slots_words[w] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ctl = *ctl_init;
+}
+
+// A cached engine for repeated batches of one shape, with its launch
+// sequence captured once in a hipGraph and replayed per call.
+struct Plan {
+  std::string key;
+  Engine E;
+  Ctl *ctl_init = nullptr;     // device copy of the control block at the start of a batch
+  QDesc *qd_host = nullptr;    // pinned staging of the per-call query table
+  hipEvent_t staged = nullptr; // the previous call's upload has left qd_host
+  hipEvent_t done = nullptr;   // the previous replay has finished with the engine
+  hipStream_t cap = nullptr;   // capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~Plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (E.base) (void)hipDeviceSynchronize();
+    engine_destroy(E);
+    if (ctl_init) (void)hipFree(ctl_init);
+    if (qd_host) (void)hipHostFree(qd_host);
+    if (staged) (void)hipEventDestroy(staged);
+    if (done) (void)hipEventDestroy(done);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+void plan_free(Plan *p) { delete p; }
+
+static int run_graph(knn_db_s *db, const Prepared &P, int64_t nq, int64_t ns, bool same, bool query_lane,
+                     const Knobs &K, hipStream_t st) {
+  std::string key;
+  auto put = [&](const void *v, size_t b) { key.append((const char *)v, b); };
+  const int32_t hdr[8] = {(int32_t)nq, (int32_t)ns, P.kmax, P.cmax, P.rmax, (int32_t)P.any_cexact, (int32_t)same,
+                          (int32_t)query_lane};
+  put(hdr, sizeof(hdr));
+  put(&K, sizeof(K));
+  put(P.sched.data(), sizeof(Sched) * P.sched.size());
+  Plan *pl = db->plan;
+  if (!pl || pl->key != key) {
+    if (pl) {
+      plan_free(pl);
+      db->plan = nullptr;
+    }
+    std::unique_ptr<Plan> np(new Plan());
+    np->key = key;
+    int rc = engine_create(np->E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, false, same, query_lane);
+    if (rc != KNN_OK) return rc;
+    Ctl ctl;
+    std::memset(&ctl, 0, sizeof(ctl));
+    ctl.nq = (int32_t)nq;
+    ctl.qcap = (int32_t)nq;
+    ctl.next_query = (int32_t)std::min<int64_t>(ns, nq);  // the first admission hands query s to slot s
+    HIP_TRY(hipMalloc(&np->ctl_init, sizeof(Ctl)));
+    HIP_TRY(hipHostMalloc(&np->qd_host, sizeof(QDesc) * nq));
+    HIP_TRY(hipEventCreateWithFlags(&np->staged, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&np->done, hipEventDisableTiming));
+    HIP_TRY(hipStreamCreateWithFlags(&np->cap, hipStreamNonBlocking));
+    HIP_TRY(hipMemcpyAsync(np->ctl_init, &ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(np->E.sched, P.sched.data(), sizeof(Sched) * P.sched.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    Engine &E = np->E;
+    E.st = np->cap;
+    HIP_TRY(hipStreamBeginCapture(np->cap, hipStreamCaptureModeThreadLocal));
+    const int64_t nwords = (int64_t)sizeof(Slot) * ns / 4;
+    hipLaunchKernelGGL(k_reset_engine, dim3((unsigned)std::min<int64_t>((nwords + 255) / 256, 1024)), dim3(256), 0,
+                       np->cap, reinterpret_cast<uint32_t *>(E.slots), nwords, E.ctl, np->ctl_init);
+    launch_lockstep(E, P, nq, K, np->cap);
+    hipError_t e = hipStreamEndCapture(np->cap, &np->graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&np->exec, np->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(KNN_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    pl = np.release();
+    db->plan = pl;
+  }
+  HIP_TRY(hipEventSynchronize(pl->staged));  // the staging buffer is free again
+  std::memcpy(pl->qd_host, P.qd.data(), sizeof(QDesc) * nq);
+  HIP_TRY(hipStreamWaitEvent(st, pl->done, 0));  // a replay on another stream must finish first
+  HIP_TRY(hipMemcpyAsync(pl->E.qd, pl->qd_host, sizeof(QDesc) * nq, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(pl->staged, st));
+  HIP_TRY(hipGraphLaunch(pl->exec, st));
+  HIP_TRY(hipEventRecord(pl->done, st));
+  return KNN_OK;
+}
+
 // Runs the slot engine over the prepared queries.  stop_after > 0 freezes
 // slot 0 after that many decide steps (debug state dump) and leaves the
 // engine allocated in *keep.
 static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int32_t stop_after, Engine *keep) {
   const int64_t n = db->n, m = db->m;
+  const Knobs K = knobs_for(db);
   const size_t per_slot = engine_slot_bytes(n, P.kmax, P.cmax);
   size_t freeb = 0, totb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totb));
@@ -253,7 +395,6 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
   ns = std::min<int64_t>(ns, env_int("KNN_MAX_SLOTS", 65535));
   if (stop_after > 0) ns = 1;
   if (ns < 1) return fail(KNN_ENOMEM, "not enough device memory for one query slot");
-  Engine E;
   // queries that share seed and schedule draw identical coordinates: let
   // the sampling kernel serve them in groups
   bool same = true;
@@ -263,8 +404,13 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
   // one seed and schedule, all slots run the same round at each step, so a
   // wave can serve one point for many slots at a time.
   const bool query_lane = same && db->dtype == KNN_U8 && m < 65536 && (nq <= ns || stop_after > 0) &&
-                          P.sched.size() == 1 &&
-                          ns >= env_int("KNN_QL_MIN", 64) && env_int("KNN_QL", 1) != 0;
+                          P.sched.size() == 1 && ns >= K.ql_min && K.ql != 0;
+  // Repeated batches of one shape replay a captured launch sequence on a
+  // cached engine (not with timing on, and not for LDS-staged rounds).
+  if (K.graph != 0 && stop_after == 0 && !keep && nq <= ns && P.sched.size() == 1 && !prof_enabled() &&
+      K.stage_min >= (1 << 30))
+    return run_graph(db, P, nq, ns, same, query_lane, K, st);
+  Engine E;
   int rc = engine_create(E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, true, same, query_lane);
   if (rc != KNN_OK) return rc;
   Ctl ctl;
@@ -282,40 +428,15 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
   chk(hipMemcpyAsync(E.sched, P.sched.data(), sizeof(Sched) * P.sched.size(), hipMemcpyHostToDevice, st),
       "copy schedules");
   if (rc == KNN_OK) {
-    if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, st);
-    launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st, true);
-    if (E.qt) launch_build_qt(E.slots, (int32_t)E.ns, m, E.nqp, E.qt, st);
-    chk(hipGetLastError(), "launch");
-  }
-  const int steps_gen = P.rmax + 1;
-  if (rc == KNN_OK) {
     if (nq <= ns || stop_after > 0) {
-      // every query starts together: with one shared schedule, step t runs
-      // round t for all of them (timing label only)
-      const bool lockstep = P.sched.size() == 1;
-      // long rounds of grouped sampling read whole point rows into LDS
-      const int stage_min = env_int("KNN_STAGE_MIN", 1 << 30);  // off unless asked for: slower than HBM gathers so far
-      const int stage_rows = E.G.grouped ? stage_rows_for(m, db->mp, env_int("KNN_STAGE_ROWS", 8)) : 0;
-      for (int t = 0; t < steps_gen; ++t) {
-        int stage = 0;
-        if (lockstep && stage_rows > 0 && t < P.sched[0].R) {
-          const int64_t b_r = P.sched[0].T[t] - (t ? P.sched[0].T[t - 1] : 0);
-          if (b_r >= stage_min) stage = stage_rows;
-        }
-        QlRound qr{};
-        const bool ql = E.qt && t < P.sched[0].R;
-        if (ql) {
-          qr.seed = P.qd[0].seed;
-          qr.t0 = t ? (uint32_t)P.sched[0].T[t - 1] : 0u;
-          qr.t1 = (uint32_t)P.sched[0].T[t];
-          qr.cur = t;
-          qr.impl = t == 0;
-        }
-        engine_step(E, P.any_cexact, (lockstep && t == P.rmax) ? 1 : 0, stage, ql ? &qr : nullptr);
-      }
+      launch_lockstep(E, P, nq, K, st);
       chk(hipGetLastError(), "launch");
     } else {
+      if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, st);
+      launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st, true);
+      chk(hipGetLastError(), "launch");
       // slots are recycled on the device; poll until every query is done
+      const int steps_gen = P.rmax + 1;
       const int64_t max_gen = ((nq + ns - 1) / ns + 1) * (P.rmax + 2);
       int64_t gen = 0;
       for (;;) {
@@ -406,6 +527,7 @@ int knn_db_destroy(knn_db db) {
   if (!db) return fail(KNN_EINVAL, "NULL db");
   if (db->users.load() > 0) return fail(KNN_EBUSY, "DB is held by a session");
   (void)hipDeviceSynchronize();
+  if (db->plan) plan_free(db->plan);
   naive_free_db(db);
   if (db->owned) (void)hipFree(db->owned);
   delete db;
@@ -447,6 +569,131 @@ int knn_adaptive(knn_db db, const void *dev_queries, int64_t nq, const int32_t *
   if (rc != KNN_OK) return rc;
   std::lock_guard<std::mutex> lk(db->mu);
   return run_engine(db, P, nq, (hipStream_t)stream, 0, nullptr);
+}
+
+int knn_autotune(knn_db db, const void *dev_queries, int64_t nq, int32_t k, const knn_params *p, int32_t reps,
+                 int32_t schedule_report, char *report, size_t report_len, void *stream) {
+  if (!db || !dev_queries || !p || nq < 1 || k < 1) return fail(KNN_EINVAL, "bad autotune arguments");
+  if (reps < 1) reps = 1;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t kh = k + (p->h < 0 ? k : p->h);
+  const int64_t stride = std::max<int64_t>(1, std::min<int64_t>(kh, db->n));
+  int64_t *d_idx = nullptr;
+  int32_t *d_cnt = nullptr;
+  knn_stats *d_st = nullptr;
+  HIP_TRY(hipMalloc(&d_idx, sizeof(int64_t) * stride * nq));
+  HIP_TRY(hipMalloc(&d_cnt, sizeof(int32_t) * nq));
+  HIP_TRY(hipMalloc(&d_st, sizeof(knn_stats) * nq));
+  std::vector<int32_t> ks(nq, k);
+  std::vector<int64_t> ref_idx, got_idx(stride * nq);
+  std::vector<int32_t> ref_cnt, got_cnt(nq);
+  std::vector<knn_stats> ref_st, got_st(nq);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  std::string rep;
+  int rc = KNN_OK;
+  // one candidate: warm-up, check the output, then the mean of reps timed runs
+  auto measure = [&](const knn_params &pp, double *ms, bool check) -> int {
+    int r = knn_adaptive(db, dev_queries, nq, ks.data(), &pp, 1, d_idx, stride, d_cnt, d_st, st);
+    if (r != KNN_OK) return r;
+    HIP_TRY(hipMemcpyAsync(got_idx.data(), d_idx, sizeof(int64_t) * stride * nq, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(got_cnt.data(), d_cnt, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(got_st.data(), d_st, sizeof(knn_stats) * nq, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (check) {
+      if (ref_idx.empty()) {
+        ref_idx = got_idx;
+        ref_cnt = got_cnt;
+        ref_st = got_st;
+      } else if (ref_idx != got_idx || ref_cnt != got_cnt ||
+                 std::memcmp(ref_st.data(), got_st.data(), sizeof(knn_stats) * nq) != 0) {
+        return fail(KNN_EDEVICE, "autotune: a performance knob changed the result");
+      }
+    }
+    HIP_TRY(hipEventRecord(e0, st));
+    for (int i = 0; i < reps; ++i) {
+      r = knn_adaptive(db, dev_queries, nq, ks.data(), &pp, 1, d_idx, stride, d_cnt, d_st, st);
+      if (r != KNN_OK) return r;
+    }
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / reps;
+    return KNN_OK;
+  };
+  struct Cand {
+    const char *name;
+    Knobs k;
+  };
+  std::vector<Cand> cands;
+  Knobs base;
+  base.valid = 1;
+  cands.push_back({"default", base});
+  {
+    Knobs c = base;
+    c.ql = 0;
+    cands.push_back({"grouped", c});
+    c.group = 0;
+    cands.push_back({"per-query", c});
+    c = base;
+    c.ql = 0;
+    c.ch_sample = 1024;
+    cands.push_back({"grouped ch1024", c});
+    c.ch_sample = 4096;
+    cands.push_back({"grouped ch4096", c});
+    c = base;
+    c.ql = 0;
+    c.lpp = 16;
+    cands.push_back({"grouped lpp16", c});
+    c = base;
+    c.graph = 0;
+    cands.push_back({"default no-graph", c});
+  }
+  const Knobs saved = db->tune;
+  double best_ms = 1e300;
+  Knobs best = base;
+  char line[160];
+  for (const Cand &c : cands) {
+    db->tune = c.k;
+    double ms = 0.0;
+    rc = measure(*p, &ms, true);
+    if (rc != KNN_OK) break;
+    std::snprintf(line, sizeof(line), "%s %.4f\n", c.name, ms);
+    rep += line;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c.k;
+    }
+  }
+  db->tune = rc == KNN_OK ? best : saved;
+  if (rc == KNN_OK && schedule_report) {
+    const int b0s[3] = {16, 64, 256};
+    const float gs[2] = {1.5f, 2.0f};
+    for (int b : b0s)
+      for (float g : gs) {
+        knn_params pp = *p;
+        pp.b0 = b;
+        pp.growth = g;
+        double ms = 0.0;
+        rc = measure(pp, &ms, false);
+        if (rc != KNN_OK) break;
+        std::snprintf(line, sizeof(line), "schedule b0=%d g=%.1f %.4f\n", b, (double)g, ms);
+        rep += line;
+      }
+  }
+  if (report && report_len) {
+    const size_t c = std::min(report_len - 1, rep.size());
+    std::memcpy(report, rep.data(), c);
+    report[c] = 0;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d_idx);
+  (void)hipFree(d_cnt);
+  (void)hipFree(d_st);
+  return rc;
 }
 
 int knn_adaptive_state(knn_db db, const void *dev_query, int32_t k, const knn_params *p, int32_t stop_after,

@@ -8,6 +8,23 @@
 
 #include "knn_internal.h"
 
+namespace knn {
+struct Plan;
+void plan_free(Plan *p);
+// Performance knobs (never result-defining); see knobs_for.
+struct Knobs {
+  int32_t valid = 0;        // set by the autotuner
+  int32_t ql = 1;           // query-lane sampling allowed
+  int32_t ql_min = 64;      // ... from this many slots
+  int32_t group = 1;        // 16-slot grouped sampling allowed
+  int32_t lpp = 0;          // lanes per point of the grouped kernel (0: per round)
+  int32_t ch_sample = 2048; // points per sampling block
+  int32_t stage_min = 1 << 30;  // LDS-staged rows from this round size (off)
+  int32_t stage_rows = 8;
+  int32_t graph = 1;        // capture and replay repeated batches
+};
+}  // namespace knn
+
 struct knn_db_s {
   const uint8_t *X = nullptr;  // [n][m] point-major (u8 or f32 bytes)
   void *owned = nullptr;       // library allocation when copied
@@ -23,6 +40,8 @@ struct knn_db_s {
   float *rownorm = nullptr;    // f32: |x| per row (for the error bound)
   std::atomic<int> users{0};   // sessions holding the DB
   std::mutex mu;
+  knn::Plan *plan = nullptr;   // cached engine + captured graph of the last batch shape
+  knn::Knobs tune;             // autotuned knobs (tune.valid)
 };
 
 namespace knn {
@@ -60,6 +79,7 @@ int engine_destroy(Engine &E);
 void engine_step(Engine &E, bool any_cexact, int sample_kind = 0, int stage_rows = 0, const QlRound *ql = nullptr);
 // rows per LDS tile for grouped sampled rounds of an m-dimensional DB (0: none fits)
 int stage_rows_for(int64_t m, int64_t mp, int want);
+Knobs knobs_for(const knn_db_s *db);
 // Host-side parameter check + per-query descriptor (no device pointers for the
 // query/outputs are filled here).
 int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &p, QDesc &d, Sched &sc);

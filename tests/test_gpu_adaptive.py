@@ -246,3 +246,48 @@ def test_grouped_shared_seed_batch(P, orc):
         ref, rst = orc.adaptive(X, Q[q], 10, oparams(orc, h=10, delta=0.01, seed=99))
         assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
         assert int(st[q]["coord_evals"]) == rst["coord_evals"]
+
+
+def test_graph_replays_equal_eager(P, orc):
+    """Repeated batches of one shape replay a captured launch sequence on a
+    cached engine.  Several replays with different queries, with eager work
+    in between, each equal the eager (uncaptured) result."""
+    X, Q = gmm_u8(71, n=6007, m=300, n_centres=6, sigma=25.0, nq=192)
+    db = P.KnnDB(dev(X))
+    p = P.default_params(h=6, delta=0.05, seed=5)
+    batches = [dev(Q[:96]), dev(Q[96:]), dev(Q[:96][::-1].copy())]
+    os.environ["KNN_GRAPH"] = "0"
+    try:
+        eager = [db.adaptive(b, 6, p) for b in batches]
+    finally:
+        del os.environ["KNN_GRAPH"]
+    for rep in range(3):
+        for b, ref in zip(batches, eager):
+            got = db.adaptive(b, 6, p)
+            torch.cuda.synchronize()
+            assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+            _ = db.naive(b, 3)  # eager work between replays
+    # a batch of another shape rebuilds the plan, then the first shape again
+    other = db.adaptive(dev(Q[:50]), 6, p)
+    ref50 = orc.adaptive(X, Q[3], 6, oparams(orc, h=6, delta=0.05, seed=5))[0]
+    assert other[0][3, :other[1][3]].cpu().tolist() == ref50.tolist()
+    got = db.adaptive(batches[0], 6, p)
+    assert torch.equal(got[0], eager[0][0])
+
+
+def test_autotune_keeps_results(P, orc):
+    """The autotuner times every knob candidate, checks that all of them give
+    the same output, keeps the fastest, and later calls still equal the oracle."""
+    X, Q = gmm_u8(73, n=5003, m=256, n_centres=5, sigma=25.0, nq=80)
+    db = P.KnnDB(dev(X))
+    p = P.default_params(h=5, seed=9)
+    rep = db.autotune(dev(Q), 5, p, reps=1, schedule_report=True)
+    assert {"default", "grouped", "per-query", "default no-graph"} <= set(rep)
+    assert any(k.startswith("schedule b0=16") for k in rep)
+    assert all(v > 0 for v in rep.values())
+    idx, cnt, st = db.adaptive(dev(Q), 5, p)
+    idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
+    for q in (0, 41, 79):
+        ref, rst = orc.adaptive(X, Q[q], 5, oparams(orc, h=5, seed=9))
+        assert idx[q, :cnt[q]].tolist() == ref.tolist()
+        assert int(st[q]["coord_evals"]) == rst["coord_evals"]
