@@ -1654,6 +1654,10 @@ void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, dou
   hipLaunchKernelGGL(k_prep_f32, dim3((unsigned)nq), dim3(NT), 0, st, qd, nq, n, m, lo, hi);
 }
 
+// the exact round of query-lane batches (k_naive.hip: shares the scan's GEMM tile)
+void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, const int8_t *X8, const int32_t *xn,
+                        const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, hipStream_t st);
+
 int stage_rows_for(int64_t m, int64_t mp, int want) {
   // LDS: the transposed query tile (GRP x mp) plus the row tile (rows x m)
   constexpr int64_t kLds = 160 * 1024 - 4096;  // static shared memory of the kernel stays below 4 KB
@@ -1670,18 +1674,29 @@ void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint
 
 void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
                  const Bufs &B, const Geometry &G0, bool any_cexact, hipStream_t st, int sample_kind,
-                 int stage_rows, const QlRound *ql, const uint8_t *qt, int32_t nqp, uint32_t *qd_buf) {
+                 int stage_rows, const QlRound *ql, const uint8_t *qt, int32_t nqp, uint32_t *qd_buf,
+                 const int8_t *q8, const int32_t *q8n) {
   Geometry G = G0;
   G.prof = prof_device_counters();
   G.stage = (G.dtype == KNN_U8 && G.grouped) ? stage_rows : 0;
   const int elem = G.dtype == KNN_U8 ? 1 : 4;
   const size_t qbytes = (size_t)G.m * elem;
   const bool qlds = qbytes <= 48 * 1024;
+  // exact round of a query-lane batch: one GEMM over (slots x points)
+  const bool ql_exact = ql && ql->exact && q8 && q8n && G.dtype == KNN_U8;
+  if (ql_exact) {
+    const int tk = prof_begin(PROF_EXACT, st);
+    launch_exact_ql_u8(slots, q8, q8n, G.x8, G.xn, B, G, ql->cur, ql->impl, st);
+    prof_end(tk, st, 0.0);
+    ql = nullptr;  // the rest of the step as usual
+  }
   const bool use_ql = ql && qt && qd_buf && G.dtype == KNN_U8;
   // fold and selection in one pass (candidate-exact must run between them)
   const bool fused_sel = use_ql && !any_cexact && G.kmax + 1 <= kWave;
-  int tok = use_ql ? -1 : prof_begin(sample_kind == 1 ? PROF_EXACT : PROF_SAMPLE, st);
-  if (use_ql) {
+  int tok = (use_ql || ql_exact) ? -1 : prof_begin(sample_kind == 1 ? PROF_EXACT : PROF_SAMPLE, st);
+  if (ql_exact) {
+    // sampling done above
+  } else if (use_ql) {
     const unsigned bx = (unsigned)std::min<int64_t>((G.n + QL_NW - 1) / QL_NW, 2048);
     const unsigned by = (unsigned)((nqp + QL_SLOTS - 1) / QL_SLOTS);
     uint8_t *A = reinterpret_cast<uint8_t *>(qd_buf + G.n * (int64_t)nqp);  // follows D in the arena

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <string>
 
 #include "block_select.h"
@@ -234,6 +235,277 @@ __global__ __launch_bounds__(256) void k_naive_u8(const int8_t *__restrict__ Q8,
   }
 }
 
+// Same scan for k <= 64, restructured for throughput:
+//  * the K loop is double-buffered: the next 128-byte slice of the query
+//    and point tiles is loaded into registers while the matrix cores work
+//    on the current one from LDS (one barrier per slice);
+//  * the per-query k smallest live in registers, one sorted list per query
+//    spread over the lanes of the wave that owns it (lane j holds the j-th
+//    smallest).  A tile's distances are filtered against the list's k-th
+//    key and the few that pass are appended to a per-query LDS buffer; the
+//    buffer is merged into the list by a wave sort when it would overflow
+//    and at the end of the block (sort, reverse, take the smaller of each
+//    pair, bitonic clean-up: the 64 smallest of both, sorted).
+constexpr int BK = 128;                 // bytes of K per pipeline stage
+constexpr int BROW = BK + 16;           // LDS row stride of a stage
+constexpr int STAGE = (NBQ + NBP) * BROW;
+constexpr int CB = 32;                  // candidate buffer per query (<= 64)
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int j) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, j);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// list: sorted ascending over the lanes; cand: one key per lane (PAD = none).
+// Returns the 64 smallest of both, sorted ascending over the lanes.
+__device__ __forceinline__ uint64_t merge_sorted64(uint64_t list, uint64_t cand) {
+  const int lane = lane_id();
+  uint64_t c = wave_sort_u64(cand);
+  c = wave_bcast_rev_u64(c);  // descending
+  uint64_t v = list < c ? list : c;
+#pragma unroll
+  for (int j = kWave / 2; j > 0; j >>= 1) {
+    const uint64_t o = shfl_xor_u64(v, j);
+    v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
+  }
+  return v;
+}
+
+// One block's 64 x 128 tile of x'.q' (queries q0.., points p0..) over
+// the whole K range, into the MFMA accumulators: the K loop is
+// double-buffered (the next 128-byte slice is loaded into registers while the
+// matrix cores work on the current one from LDS; one barrier per slice).
+// Rows beyond nq / pend read as zeros.  smem: 2 x STAGE bytes.
+__device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int64_t nq, const int8_t *__restrict__ X8,
+                                             int64_t q0, int64_t p0, int64_t pr1, int64_t mp, uint8_t *smem,
+                                             v4i (&acc)[2][4]) {
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int wq = wave >> 1, wp = wave & 1;
+  const int nks = (int)(mp / BK), tail = (int)(mp % BK);  // tail: 0 or 64
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+  // slice s covers K bytes [s BK, s BK + width): A 64 x width, B 128 x width
+  auto load = [&](int64_t k0, int width, v4i (&ra)[2], v4i (&rb)[4]) {
+    const int per_row = width / 16;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + 256 * h, r = e / 8, c = (e % 8) * 16;
+      ra[h] = v4i{0, 0, 0, 0};
+      if (c / 16 < per_row && q0 + r < nq) ra[h] = *reinterpret_cast<const v4i *>(Q8 + (q0 + r) * mp + k0 + c);
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int e = tid + 256 * h, r = e / 8, c = (e % 8) * 16;
+      rb[h] = v4i{0, 0, 0, 0};
+      if (c / 16 < per_row && p0 + r < pr1) rb[h] = *reinterpret_cast<const v4i *>(X8 + (p0 + r) * mp + k0 + c);
+    }
+  };
+  auto store = [&](int buf, const v4i (&ra)[2], const v4i (&rb)[4]) {
+    int8_t *As = reinterpret_cast<int8_t *>(smem) + buf * STAGE;
+    int8_t *Bs = As + NBQ * BROW;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + 256 * h, r = e / 8, c = (e % 8) * 16;
+      *reinterpret_cast<v4i *>(As + r * BROW + c) = ra[h];
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int e = tid + 256 * h, r = e / 8, c = (e % 8) * 16;
+      *reinterpret_cast<v4i *>(Bs + r * BROW + c) = rb[h];
+    }
+  };
+  auto compute = [&](int buf, int width) {
+    const int8_t *As = reinterpret_cast<const int8_t *>(smem) + buf * STAGE;
+    const int8_t *Bs = As + NBQ * BROW;
+    for (int kk = 0; kk < width; kk += 64) {
+      v4i af[2], bf[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        af[a] = *reinterpret_cast<const v4i *>(As + (32 * wq + 16 * a + (lane & 15)) * BROW + kk + 16 * (lane >> 4));
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        bf[b] = *reinterpret_cast<const v4i *>(Bs + (64 * wp + 16 * b + (lane & 15)) * BROW + kk + 16 * (lane >> 4));
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+  };
+  const int nsl = nks + (tail ? 1 : 0);
+  v4i ra[2], rb[4];
+  load(0, nks ? BK : tail, ra, rb);
+  store(0, ra, rb);
+  __syncthreads();
+  for (int sl = 0; sl < nsl; ++sl) {
+    const int buf = sl & 1;
+    const bool more = sl + 1 < nsl;
+    const int wnext = (sl + 1 < nks) ? BK : tail;
+    if (more) load((int64_t)(sl + 1) * BK, wnext, ra, rb);
+    compute(buf, sl < nks ? BK : tail);
+    if (more) store(buf ^ 1, ra, rb);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_naive_u8_k64(const int8_t *__restrict__ Q8, const int32_t *__restrict__ qn,
+                                                      const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
+                                                      int64_t nq, int64_t n, int64_t mp, int k, int64_t prange,
+                                                      uint64_t *__restrict__ part, int64_t nranges) {
+  constexpr uint64_t PAD = ~0ull;
+  constexpr int QPW = NBQ / 4;  // queries owned by one wave in the epilogue
+  __shared__ __align__(16) uint8_t smem[2 * STAGE > NBQ * DSTR * 4 ? 2 * STAGE : NBQ * DSTR * 4];
+  __shared__ uint64_t Cb[NBQ][CB];
+  uint32_t *Ds = reinterpret_cast<uint32_t *>(smem);
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int64_t q0 = (int64_t)blockIdx.y * NBQ;
+  const int64_t pr0 = (int64_t)blockIdx.x * prange;
+  const int64_t pr1 = std::min(n, pr0 + prange);
+  const int wq = wave >> 1, wp = wave & 1;
+  uint64_t L[QPW];   // lane j: j-th smallest of query wave*QPW + t
+  uint64_t tau[QPW]; // k-th smallest (PAD while fewer than k)
+  int cnt[QPW];      // keys in the query's buffer
+#pragma unroll
+  for (int t = 0; t < QPW; ++t) {
+    L[t] = PAD;
+    tau[t] = PAD;
+    cnt[t] = 0;
+  }
+  for (int64_t p0 = pr0; p0 < pr1; p0 += NBP) {
+    v4i acc[2][4];
+    gemm_u8_tile(Q8, nq, X8, q0, p0, pr1, mp, smem, acc);
+    // distances of the tile into LDS (the stage buffers are free now)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+          const int pl = 64 * wp + 16 * b + (lane & 15);
+          uint32_t d = 0xFFFFFFFFu;
+          if (p0 + pl < pr1 && q0 + ql < nq) {
+            const int64_t dd = (int64_t)qn[q0 + ql] + (int64_t)xn[p0 + pl] - 2 * (int64_t)acc[a][b][v];
+            d = (uint32_t)dd;
+          }
+          Ds[ql * DSTR + pl] = d;
+        }
+    __syncthreads();
+    // filter against the k-th key, append to the buffer, merge when full
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+#pragma unroll
+    for (int t = 0; t < QPW; ++t) {
+      const int ql = wave * QPW + t;
+      const uint32_t d0 = Ds[ql * DSTR + lane], d1 = Ds[ql * DSTR + lane + 64];
+      const uint64_t c0 = d0 == 0xFFFFFFFFu ? PAD : (((uint64_t)d0 << 32) | (uint64_t)(p0 + lane));
+      const uint64_t c1 = d1 == 0xFFFFFFFFu ? PAD : (((uint64_t)d1 << 32) | (uint64_t)(p0 + lane + 64));
+      const bool a0 = c0 < tau[t], a1 = c1 < tau[t];
+      const uint64_t m0 = __ballot(a0), m1 = __ballot(a1);
+      if ((m0 | m1) == 0) continue;  // wave-uniform
+      const int n0 = __popcll(m0), n1 = __popcll(m1);
+      if (cnt[t] + n0 + n1 > CB) {
+        // does not fit: merge the buffer (written in earlier tiles, before
+        // the last barrier) and this tile's candidates into the list
+        if (cnt[t] > 0) L[t] = merge_sorted64(L[t], lane < cnt[t] ? Cb[ql][lane] : PAD);
+        L[t] = merge_sorted64(L[t], a0 ? c0 : PAD);
+        L[t] = merge_sorted64(L[t], a1 ? c1 : PAD);
+        tau[t] = wave_bcast_u64(L[t], k - 1);
+        cnt[t] = 0;
+        continue;
+      }
+      if (a0) Cb[ql][cnt[t] + __popcll(m0 & lt)] = c0;
+      if (a1) Cb[ql][cnt[t] + n0 + __popcll(m1 & lt)] = c1;
+      cnt[t] += n0 + n1;
+    }
+    __syncthreads();
+  }
+  // final merge and the block's k smallest per query -> part[q][range][k]
+#pragma unroll
+  for (int t = 0; t < QPW; ++t) {
+    const int ql = wave * QPW + t;  // its buffer was written before the last barrier
+    if (cnt[t] > 0) L[t] = merge_sorted64(L[t], lane < cnt[t] ? Cb[ql][lane] : PAD);
+    if (q0 + ql < nq && lane < k) part[((q0 + ql) * nranges + blockIdx.x) * (int64_t)k + lane] = L[t];
+  }
+}
+
+// ---------------------------------------------------------------- exact round, query-lane batches
+
+// Shifted int8 copies of the running slots' queries, padded to mp, and their
+// squared norms (zero rows for idle slots): the A operand of the exact round.
+__global__ __launch_bounds__(256) void k_build_q8(const Slot *__restrict__ slots, int32_t ns, int64_t m, int64_t mp,
+                                                  int8_t *__restrict__ Q8, int32_t *__restrict__ qn) {
+  const int s = blockIdx.x;
+  const bool run = s < ns && slots[s].state == 1;
+  const uint8_t *q = run ? reinterpret_cast<const uint8_t *>(slots[s].q) : nullptr;
+  int acc = 0;
+  for (int64_t j = threadIdx.x; j < mp; j += 256) {
+    const int v = (run && j < m) ? (int)q[j] - 128 : 0;
+    Q8[(int64_t)s * mp + j] = (int8_t)v;
+    acc += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ int red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) qn[s] = red[0] + red[1] + red[2] + red[3];
+}
+
+// The exact round of a batch whose slots all run it together, as one GEMM
+// over (slots x points): S = |q'|^2 + |x'|^2 - 2 q'.x' for every undecided
+// sampled pair (flag 0; every pair when the round is round 0), flag exact.
+// Exact in integers (int8 MFMA, int32 accumulation, m <= 65536).
+__global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ slots, const int8_t *__restrict__ Q8,
+                                                     const int32_t *__restrict__ qn, const int8_t *__restrict__ X8,
+                                                     const int32_t *__restrict__ xn, Bufs B, Geometry G, int32_t cur,
+                                                     int32_t impl) {
+  __shared__ __align__(16) uint8_t smem[2 * STAGE];
+  const int64_t n = G.n, mp = G.mp;
+  const int ns = G.nslots;
+  const int64_t p0 = (int64_t)blockIdx.x * NBP;
+  const int64_t q0 = (int64_t)blockIdx.y * NBQ;
+  const int64_t pend = std::min(n, p0 + NBP);
+  v4i acc[2][4];
+  gemm_u8_tile(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);
+  const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
+  uint64_t my_pairs = 0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t s = q0 + 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+      if (s >= ns || slots[s].state != 1 || slots[s].cur != cur) continue;
+      const int64_t qs = qn[s];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
+        if (i >= n) continue;
+        const int64_t off = s * n + i;
+        if (!impl && B.fl[off] != 0) continue;  // not an undecided sampled pair
+        B.S[off] = qs + (int64_t)xn[i] - 2 * (int64_t)acc[a][b][v];
+        B.fl[off] = FL_EXACT;
+        if (impl) B.ri[off] = 0;
+        ++my_pairs;
+      }
+    }
+  if (G.prof && my_pairs) {
+    atomicAdd(&G.prof[0], my_pairs * (uint64_t)(G.m + 14));
+    atomicAdd(&G.prof[2], my_pairs * (uint64_t)G.m);
+  }
+}
+
+void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_t *Q8, int32_t *qn, hipStream_t st) {
+  hipLaunchKernelGGL(k_build_q8, dim3((unsigned)ns), dim3(256), 0, st, slots, ns, m, mp, Q8, qn);
+}
+
+void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, const int8_t *X8, const int32_t *xn,
+                        const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, hipStream_t st) {
+  dim3 grid((unsigned)((G.n + NBP - 1) / NBP), (unsigned)((G.nslots + NBQ - 1) / NBQ));
+  hipLaunchKernelGGL(k_exact_ql_u8, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl);
+}
+
 // Merge per query: the k smallest keys over all ranges, sorted; index and
 // distance out.
 __global__ __launch_bounds__(1024) void k_naive_merge(const uint64_t *__restrict__ part, int64_t nranges, int k,
@@ -287,8 +559,12 @@ static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int6
   if (k > 128) return fail(KNN_EINVAL, "naive u8 scan supports k <= 128");
   const int64_t n = db->n, mp = db->mp;
   const int64_t qt = (nq + NBQ - 1) / NBQ;
-  // enough blocks to fill 256 CUs a few times over
-  int64_t prange = (n * qt + 1023) / 1024;
+  // about KNN_NAIVE_BLOCKS blocks in all (default 512: two per CU, one
+  // wave of blocks); longer point ranges amortise each block's first tiles,
+  // where every distance still enters the running lists
+  const char *nb_env = std::getenv("KNN_NAIVE_BLOCKS");
+  const int64_t nblk = std::max<int64_t>(1, nb_env ? std::atoll(nb_env) : 512);
+  int64_t prange = (n * qt + nblk - 1) / nblk;
   prange = std::max<int64_t>(NBP, (prange + NBP - 1) / NBP * NBP);
   const int64_t nranges = (n + prange - 1) / prange;
   const size_t bytes_q = (size_t)nq * mp + 256, bytes_qn = sizeof(int32_t) * nq + 256,
@@ -302,9 +578,11 @@ static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int6
   hipLaunchKernelGGL(k_prep_u8_queries, dim3((unsigned)nq), dim3(256), 0, st, dq, db->m, mp, Q8, qn);
   prof_end(tok, st, 0.0);
   tok = prof_begin(PROF_NAIVE_GEMM, st);
-  if (k <= 64)
-    launch_naive_u8<64>(Q8, qn, db, nq, k, prange, part, nranges, st);
-  else
+  if (k <= 64) {
+    dim3 grid((unsigned)nranges, (unsigned)((nq + NBQ - 1) / NBQ));
+    hipLaunchKernelGGL(k_naive_u8_k64, grid, dim3(256), 0, st, Q8, qn, db->xs8, db->norm_i, nq, n, mp, k, prange,
+                       part, nranges);
+  } else
     launch_naive_u8<128>(Q8, qn, db, nq, k, prange, part, nranges, st);
   prof_end(tok, st, 2.0 * (double)nq * (double)n * (double)db->m);
   tok = prof_begin(PROF_NAIVE_REST, st);

@@ -133,6 +133,9 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   const int32_t nqp = query_lane ? (int32_t)((ns + 15) / 16 * 16) : 0;
   const size_t o_qt = take((size_t)nqp * (size_t)db->m);
   const size_t o_qdl = take((size_t)nqp * (size_t)n * 5);  // round totals [n][nqp] u32, then flags [n][nqp] u8
+  const bool q8x = query_lane && db->dtype == KNN_U8 && db->xs8 && db->m <= 65536;
+  const size_t o_q8 = take(q8x ? (size_t)nqp * (size_t)db->mp : 0);
+  const size_t o_q8n = take(q8x ? (size_t)nqp * 4 : 0);
   void *base = nullptr;
   if (async_alloc)
     HIP_TRY(hipMallocAsync(&base, off, st));
@@ -157,6 +160,8 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.B.part_stride = pw;
   E.qt = query_lane ? at(o_qt) : nullptr;
   E.qsum = query_lane ? (uint32_t *)at(o_qdl) : nullptr;
+  E.q8 = q8x ? (int8_t *)at(o_q8) : nullptr;
+  E.q8n = q8x ? (int32_t *)at(o_q8n) : nullptr;
   E.nqp = nqp;
   E.B.cand = nullptr;
   E.G.n = n;
@@ -192,7 +197,7 @@ int engine_destroy(Engine &E) {
 
 void engine_step(Engine &E, bool any_cexact, int sample_kind, int stage_rows, const QlRound *ql) {
   launch_step(E.slots, E.qd, E.sched, E.ctl, E.db->X, E.B, E.G, any_cexact, E.st, sample_kind, stage_rows, ql, E.qt,
-              E.nqp, E.qsum);
+              E.nqp, E.qsum, E.q8, E.q8n);
 }
 
 int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &pp, QDesc &d, Sched &sc) {
@@ -266,6 +271,7 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, st);
   launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st, true);
   if (E.qt) launch_build_qt(E.slots, (int32_t)E.ns, m, E.nqp, E.qt, st);
+  if (E.q8) launch_build_q8(E.slots, (int32_t)E.ns, m, db->mp, E.q8, E.q8n, st);
   const bool lockstep = P.sched.size() == 1;
   // long rounds of grouped sampling read whole point rows into LDS
   const int stage_rows = E.G.grouped ? stage_rows_for(m, db->mp, K.stage_rows) : 0;
@@ -276,11 +282,12 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
       if (b_r >= K.stage_min) stage = stage_rows;
     }
     QlRound qr{};
-    const bool ql = E.qt && t < P.sched[0].R;
+    const bool ql = E.qt && (t < P.sched[0].R || (t == P.sched[0].R && E.q8));
     if (ql) {
       qr.seed = P.qd[0].seed;
-      qr.t0 = t ? (uint32_t)P.sched[0].T[t - 1] : 0u;
-      qr.t1 = (uint32_t)P.sched[0].T[t];
+      qr.exact = t >= P.sched[0].R;
+      qr.t0 = (t && !qr.exact) ? (uint32_t)P.sched[0].T[t - 1] : 0u;
+      qr.t1 = qr.exact ? 0u : (uint32_t)P.sched[0].T[t];
       qr.cur = t;
       qr.impl = t == 0;
     }

@@ -70,6 +70,8 @@ struct QlRound {
   uint32_t t0, t1;
   int32_t cur;
   int32_t impl;         // 1: round 0, every point undecided
+  int32_t exact;        // 1: the exact round (t0, t1, seed unused)
+  int32_t pad;
 };
 
 // Engine control block (device).
