@@ -328,7 +328,7 @@ def main():
     rl_sample["frac"] = rl_sample["achieved"] / DOT4_PEAK_TOPS
     rl_exact = {"bound": "mfma", "achieved": e_ops / e_avg / 1e12 if e_avg > 0 else 0.0,
                 "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
-                "kernel": "k_sample_grp_u8 (exact round, int8 MFMA)", "avg_launch_ms": e_avg * 1e3,
+                "kernel": "k_exact_ql_u8 (exact round, int8 MFMA GEMM)", "avg_launch_ms": e_avg * 1e3,
                 "launches": exr["launches"], "ops_per_launch": e_ops}
     rl_exact["frac"] = rl_exact["achieved"] / INT8_PEAK_TOPS
     roofline = rl_exact if dom == "sample_exact_round" else rl_sample
