@@ -72,6 +72,10 @@ def lib():
                                    ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int32,
                                    P, ctypes.POINTER(Stats), P, P, P]
         L.orc_adaptive.restype = ctypes.c_int32
+        L.orc_alg1.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P,
+                               ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int64,
+                               P, ctypes.POINTER(Stats), P]
+        L.orc_alg1.restype = ctypes.c_int32
         L.orc_naive.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P,
                                 ctypes.c_int32, P, P]
         L.orc_naive.restype = ctypes.c_int32
@@ -163,6 +167,30 @@ def adaptive(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
     if dump:
         return idx, stats, (S, fl, ri)
     return idx, stats
+
+
+def alg1(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
+         max_iter: int = 1 << 40):
+    """Algorithm 1, sequential as published.  Returns (idx[k+h], stats dict,
+    final sample counts T[n])."""
+    X = np.ascontiguousarray(X)
+    q = np.ascontiguousarray(q, dtype=X.dtype)
+    n, m = X.shape
+    if params is None:
+        params = make_params()
+    h = params.h if params.h >= 0 else k
+    out = np.full(k + h, -1, dtype=np.int64)
+    T = np.zeros(n, dtype=np.int64)
+    st = Stats()
+    rc = lib().orc_alg1(_ptr(X), n, m, _dtype_code(X), _ptr(q), k, ctypes.byref(params), max_iter,
+                        _ptr(out), ctypes.byref(st), _ptr(T))
+    if rc == -2:
+        raise RuntimeError("Algorithm 1 did not terminate within max_iter iterations")
+    if rc != 0:
+        raise ValueError(f"oracle alg1 rejected arguments (rc={rc})")
+    stats = dict(coord_evals=st.coord_evals, iterations=st.rounds, count=st.count,
+                 exact_points=st.exact_points)
+    return out[:st.count].copy(), stats, T
 
 
 def naive(X: np.ndarray, q: np.ndarray, k: int):

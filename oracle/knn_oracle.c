@@ -469,6 +469,155 @@ double orc_exact_dist(const void *X, int64_t n, int64_t m, int32_t dtype,
   return s;
 }
 
+/* ------------------------------------------------------------------ */
+/* Algorithm 1, sequential, as published (Section 4).                   */
+/* The order of the points by (d^, index) is kept in an array and fixed  */
+/* up after each of the (at most two) updates of an iteration: O(n) per */
+/* iteration instead of the paper's heaps (Section 4.1), same decisions. */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int64_t *S, *T;
+  uint8_t *ex;
+  double *dh, *al;
+} alg1_state_t;
+
+static int before(const alg1_state_t *A, int64_t a, int64_t b) {
+  if (A->dh[a] != A->dh[b]) return A->dh[a] < A->dh[b];
+  return a < b;
+}
+
+/* moves point i (whose d^ changed) to its place in ord[], pos[] the inverse */
+static void reposition(const alg1_state_t *A, int64_t *ord, int64_t *pos, int64_t n, int64_t i) {
+  int64_t p = pos[i];
+  while (p > 0 && before(A, i, ord[p - 1])) {
+    ord[p] = ord[p - 1];
+    pos[ord[p]] = p;
+    --p;
+  }
+  while (p + 1 < n && before(A, ord[p + 1], i)) {
+    ord[p] = ord[p + 1];
+    pos[ord[p]] = p;
+    ++p;
+  }
+  ord[p] = i;
+  pos[i] = p;
+}
+
+int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype,
+                 const void *q, int32_t k, const orc_params *p, int64_t max_iter,
+                 int64_t *out_idx, orc_stats *st, int64_t *T_out) {
+  if (!X || !q || !p || !out_idx || !st || n < 1 || m < 1 || k < 1) return -1;
+  if (dtype != ORC_U8 && dtype != ORC_F32) return -1;
+  if (!(p->delta > 0.0 && p->delta < 1.0)) return -1;
+  if (p->alpha_kind < 0 || p->alpha_kind > 2) return -1;
+  if (p->alpha_kind == 2 && !(p->c_alpha > 0.0)) return -1;
+  const double theta = p->theta_exact == 0.0f ? 1.0 : (double)p->theta_exact;
+  if (!(theta > 0.0)) return -1;
+  const int64_t h = p->h < 0 ? (int64_t)k : p->h;
+  const int64_t kh = (int64_t)k + h;
+  memset(st, 0, sizeof(*st));
+  for (int64_t a = 0; a < kh; ++a) out_idx[a] = -1;
+  if (n <= kh) {
+    for (int64_t i = 0; i < n; ++i) {
+      out_idx[i] = i;
+      if (T_out) T_out[i] = 0;
+    }
+    st->count = (int32_t)n;
+    return 0;
+  }
+  inst_t I;
+  memset(&I, 0, sizeof(I));
+  I.n = n; I.m = m; I.dtype = dtype;
+  if (dtype == ORC_U8) { I.xu = (const uint8_t *)X; I.qu = (const uint8_t *)q; }
+  else { I.xf = (const float *)X; I.qf = (const float *)q; }
+  int32_t F;
+  int sc = orc_scaling(X, n, m, dtype, q, &I.W, &F);
+  if (sc < 0) return -1;
+  if (sc == 1) {  /* zero range: every distance is 0 */
+    for (int64_t a = 0; a < kh; ++a) out_idx[a] = a;
+    st->count = (int32_t)kh;
+    return 0;
+  }
+  I.scale = ldexp(1.0, F);
+  double thr_d = ceil(theta * (double)m);
+  const int64_t thr = thr_d >= (double)m ? m : (thr_d < 1.0 ? 1 : (int64_t)thr_d);
+  alg1_state_t A;
+  A.S = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+  A.T = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+  A.ex = (uint8_t *)calloc((size_t)n, 1);
+  A.dh = (double *)calloc((size_t)n, sizeof(double));
+  A.al = (double *)calloc((size_t)n, sizeof(double));
+  int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  keyidx_t *tmp = (keyidx_t *)malloc(sizeof(keyidx_t) * (size_t)n);
+  int64_t evals = 0, exact_pts = 0;
+  /* one more sample of point i (or its exact distance at the threshold) */
+  #define ALG1_SAMPLE(i) do {                                                   \
+    int64_t i_ = (i);                                                           \
+    A.T[i_] += 1;                                                               \
+    A.S[i_] += sample_value(&I, i_, orc_index(p->seed, i_, A.T[i_] - 1, m));     \
+    evals += 1;                                                                 \
+    if (A.T[i_] >= thr) {                                                       \
+      A.S[i_] = exact_sum(&I, i_);                                              \
+      A.ex[i_] = 1;                                                             \
+      evals += m;                                                               \
+      exact_pts += 1;                                                           \
+      A.dh[i_] = dhat_of(&I, A.S[i_], m);                                       \
+      A.al[i_] = 0.0;                                                           \
+    } else {                                                                    \
+      A.dh[i_] = dhat_of(&I, A.S[i_], A.T[i_]);                                 \
+      A.al[i_] = orc_alpha(p->alpha_kind, A.T[i_], n, p->delta, p->c_alpha);    \
+    }                                                                           \
+  } while (0)
+  for (int64_t i = 0; i < n; ++i) ALG1_SAMPLE(i);
+  for (int64_t i = 0; i < n; ++i) { tmp[i].key = A.dh[i]; tmp[i].idx = i; }
+  qsort(tmp, (size_t)n, sizeof(keyidx_t), cmp_keyidx);
+  for (int64_t a = 0; a < n; ++a) { ord[a] = tmp[a].idx; pos[ord[a]] = a; }
+  int32_t rc = 0;
+  int64_t it = 0;
+  for (;;) {
+    /* eq. d_ind */
+    int64_t q1 = ord[0];
+    for (int64_t a = 1; a < k; ++a) {
+      int64_t i = ord[a];
+      double v = A.dh[i] + A.al[i], w = A.dh[q1] + A.al[q1];
+      if (v > w || (v == w && i < q1)) q1 = i;
+    }
+    int64_t q2 = ord[kh];
+    for (int64_t a = kh + 1; a < n; ++a) {
+      int64_t i = ord[a];
+      double v = A.dh[i] - A.al[i], w = A.dh[q2] - A.al[q2];
+      if (v < w || (v == w && i < q2)) q2 = i;
+    }
+    /* eq. termination */
+    if (A.dh[q1] + A.al[q1] <= A.dh[q2] - A.al[q2]) break;
+    /* eq. blowbupdef: q2 first, then the middle positions in order */
+    int64_t b2 = q2;
+    for (int64_t a = k; a < kh; ++a) {
+      int64_t i = ord[a];
+      if (A.al[i] > A.al[b2]) b2 = i;
+    }
+    if (++it > max_iter) { rc = -2; break; }
+    const int64_t pick[2] = {q1, b2};
+    for (int c = 0; c < 2; ++c) {
+      const int64_t i = pick[c];
+      if (A.ex[i]) continue;  /* its distance is exact already */
+      ALG1_SAMPLE(i);
+      reposition(&A, ord, pos, n, i);
+    }
+  }
+  #undef ALG1_SAMPLE
+  for (int64_t a = 0; a < kh; ++a) out_idx[a] = ord[a];
+  st->coord_evals = evals;
+  st->rounds = it > INT32_MAX ? INT32_MAX : (int32_t)it;
+  st->count = (int32_t)kh;
+  st->exact_points = exact_pts;
+  if (T_out) for (int64_t i = 0; i < n; ++i) T_out[i] = A.ex[i] ? m : A.T[i];
+  free(A.S); free(A.T); free(A.ex); free(A.dh); free(A.al);
+  free(ord); free(pos); free(tmp);
+  return rc;
+}
+
 int32_t orc_naive(const void *X, int64_t n, int64_t m, int32_t dtype,
                   const void *q, int32_t k, int64_t *out_idx, double *out_dist) {
   if (!X || !q || !out_idx || n < 1 || m < 1 || k < 1) return -1;

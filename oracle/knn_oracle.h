@@ -81,6 +81,23 @@ int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
                      int32_t stop_after, int64_t *out_idx, orc_stats *st,
                      int64_t *S_dump, uint8_t *fl_dump, uint8_t *ri_dump);
 
+/* Algorithm 1 exactly as published (Section 4): sequential LUCB.  One
+ * sample per point to start; then, per iteration, with the points ordered
+ * by (d^, index): q1 = argmax of d^ + alpha over the first k, q2 = argmin
+ * of d^ - alpha over positions k+h+1..n, b2 = argmax of alpha over q2 and
+ * positions k+1..k+h (eq. d_ind, eq. blowbupdef; ties to the first listed,
+ * then the smaller index).  Stops when d^_q1 + alpha_q1 <= d^_q2 - alpha_q2
+ * (eq. termination); otherwise q1 and b2 take one more sample each; a point
+ * whose count reaches ceil(theta m) gets its exact distance and alpha = 0.
+ * The t-th sample of point i uses the same Philox draw as the round form.
+ * out_idx: [k+h], the first k+h by (d^, index).  st: coord_evals (samples
+ * + m per exact point), rounds = iterations, count, exact_points.
+ * T_out (nullable): [n] final sample counts.  Returns 0 ok, -1 invalid
+ * arguments, -2 when max_iter iterations did not terminate. */
+int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype,
+                 const void *q, int32_t k, const orc_params *p, int64_t max_iter,
+                 int64_t *out_idx, orc_stats *st, int64_t *T_out);
+
 /* Naive brute force of Section 3: all distances, k smallest by (d, index).
  * u8: exact int64 sums; f32: double sums in coordinate order.
  * out_dist receives the unnormalised squared distances. */

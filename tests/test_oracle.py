@@ -378,3 +378,90 @@ def test_f32_adaptive_contains(orc):
         q = X[g.integers(0, 300)] + 0.05 * g.standard_normal(40).astype(np.float32)
         idx, _ = orc.adaptive(X, q, 3, orc.make_params(h=3, seed=s, b0=8, c_exact=s % 2 * 6))
         assert contains_knn(idx, brute_dists(X, q), 3, rtol=1e-6)
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 as published (sequential LUCB, Section 4)
+
+
+def _tbar(orc, delta_i, n, delta, m):
+    """Smallest u with alpha(u) <= Delta_i / 8 (Theorem 1's proof), capped at m."""
+    if delta_i <= 0:
+        return m
+    lo, hi = 1, m
+    if orc.alpha(0, m, n, delta) > delta_i / 8:
+        return m
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if orc.alpha(0, mid, n, delta) <= delta_i / 8:
+            hi = mid
+        else:
+            lo = mid + 1
+    return lo
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_alg1_contains_knn(orc, seed):
+    from knn_inputs import gap_family
+    X, q = gap_family(200 + seed, n=400, m=256, k=5, near=5, mid=20)
+    idx, st, T = orc.alg1(X, q, 5, orc.make_params(h=5, delta=0.05, seed=seed))
+    assert len(idx) == 10 and len(set(idx.tolist())) == 10
+    assert contains_knn(idx, brute_dists(X, q), 5)
+    # bookkeeping: evaluations = samples drawn (T_i each) + m per exact point
+    assert st["coord_evals"] == int(T.sum()) + 256 * st["exact_points"]
+    assert (T >= 1).all() and (T <= 256).all()
+
+
+def test_alg1_planted_and_antipodal(orc):
+    X, q, where = tiny(1000)
+    idx, st, _ = orc.alg1(X, q[0], 5, orc.make_params(h=5, delta=0.01, seed=1))
+    assert set(where.tolist()) <= set(idx.tolist())
+    Xa, qa, wa = antipodal(7, n=1000, m=1024, copies=5)
+    idx, st, T = orc.alg1(Xa, qa[0], 5, orc.make_params(h=5, delta=0.01, seed=1))
+    assert set(wa.tolist()) <= set(idx.tolist())
+    # every sample of a far point is the exact distance 1: it leaves the
+    # running after few samples, while the round form samples every point to
+    # the first round whose width separates 0 from 1 (256,000 evaluations)
+    far = np.setdiff1d(np.arange(1000), wa)
+    assert T[far].max() < 64
+    _, rst = orc.adaptive(Xa, qa[0], 5, orc.make_params(h=5, delta=0.01, seed=1))
+    assert st["coord_evals"] < rst["coord_evals"] / 2
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_alg1_sample_bound(orc, seed):
+    """Theorem 1's count: on the confidence event every iteration that does not
+    terminate selects a 'bad' point (Lemma 4), and point i can be bad only
+    while T_i <= Tbar_i, the first u with alpha(u) <= Delta_i / 8; an exact point
+    (alpha = 0) is never bad.  So iterations <= sum_i min(Tbar_i, m) and the
+    samples drawn in them <= twice that."""
+    from knn_inputs import gap_family
+    k, h, m, n, delta = 5, 5, 256, 300, 0.05
+    X, q = gap_family(300 + seed, n=n, m=m, k=k, near=5, mid=15)
+    idx, st, T = orc.alg1(X, q, k, orc.make_params(h=h, delta=delta, seed=seed))
+    d = brute_dists(X, q) / (m * 65025.0)
+    order = np.argsort(d, kind="stable")
+    ds = d[order]
+    rank = np.empty(n, dtype=np.int64)
+    rank[order] = np.arange(n)
+    bound = 0
+    for i in range(n):
+        r = rank[i]
+        if r < k:
+            gap = ds[k + h] - d[i]
+        elif r >= k + h:
+            gap = d[i] - ds[k - 1]
+        else:
+            gap = ds[k + h] - ds[k - 1]
+        bound += _tbar(orc, gap, n, delta, m)
+    updates = st["coord_evals"] - n - m * st["exact_points"]
+    assert st["iterations"] <= bound
+    assert updates <= 2 * bound
+
+
+def test_alg1_small_n_and_invalid(orc):
+    X, _ = uniform_u8(5, n=8, m=16)
+    idx, st, _ = orc.alg1(X, X[0], 3, orc.make_params(h=5))
+    assert idx.tolist() == list(range(8))
+    with pytest.raises(ValueError):
+        orc.alg1(X, X[0], 3, orc.make_params(h=1, delta=0.0))
