@@ -224,6 +224,68 @@ def serving(args):
     return 0
 
 
+def paper_sweep(args):
+    """Section 5's experiment on its synthetic data: x = c Q y (subspace
+    dimension p in {10, 100, 1000}), n = 1000, m = 12288, k = h = 10,
+    delta = 0.001, the C_alpha width (alpha_kind 2), several trials (data and
+    seed per trial).  Reports, per (p, C_alpha), the median and interquartile
+    range of recall (true 10-NN found among the 20 returned) and of the
+    fraction of coordinate evaluations of the naive scan, plus the median
+    single-query latency of adaptive and of the naive scan."""
+    import torch
+    from knn_inputs import subspace
+
+    P = load_lib()
+    n, m, k = 1000, 12288, 10
+    cs = [0.001, 0.003, 0.01, 0.03, 0.1, 0.3, 1.0]
+    rows = []
+    for pdim in (10, 100, 1000):
+        per_c = {c: {"recall": [], "frac": [], "ms": []} for c in cs}
+        naive_ms = []
+        for trial in range(args.trials):
+            X, Q = subspace(10_000 + 97 * pdim + trial, n=n, m=m, p=pdim, nq=1)
+            db = P.KnnDB(torch.from_numpy(X).cuda())
+            qd = torch.from_numpy(Q).cuda()
+            nidx, _ = db.naive(qd, k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nidx, _ = db.naive(qd, k)
+            torch.cuda.synchronize()
+            naive_ms.append((time.perf_counter() - t0) * 1e3)
+            true = set(nidx[0].tolist())
+            for c in cs:
+                prm = P.default_params(h=k, delta=0.001, seed=trial + 1, alpha_kind=2, c_alpha=c)
+                db.adaptive(qd, k, prm)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                idx, cnt, st = db.adaptive(qd, k, prm)
+                torch.cuda.synchronize()
+                per_c[c]["ms"].append((time.perf_counter() - t0) * 1e3)
+                got = set(idx[0, :int(cnt[0])].tolist())
+                per_c[c]["recall"].append(len(true & got) / k)
+                per_c[c]["frac"].append(float(st[0]["coord_evals"]) / (n * m))
+            db.close()
+        for c in cs:
+            r, f, t = (np.array(per_c[c][x]) for x in ("recall", "frac", "ms"))
+            rows.append({"p": pdim, "c_alpha": c,
+                         "recall_median": float(np.median(r)),
+                         "recall_iqr": [float(np.percentile(r, 25)), float(np.percentile(r, 75))],
+                         "eval_fraction_median": float(np.median(f)),
+                         "eval_fraction_iqr": [float(np.percentile(f, 25)), float(np.percentile(f, 75))],
+                         "adaptive_ms_median": float(np.median(t)),
+                         "naive_ms_median": float(np.median(naive_ms))})
+            log(f"p={pdim} C={c}: recall {rows[-1]['recall_median']:.2f} "
+                f"fraction {rows[-1]['eval_fraction_median']:.3f} "
+                f"adaptive {rows[-1]['adaptive_ms_median']:.2f} ms naive {rows[-1]['naive_ms_median']:.2f} ms")
+    out = {"metric": "Section 5 sweep: recall and fraction of naive coordinate evaluations vs C_alpha",
+           "unit": "fraction", "n_gpus": 1, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": f"subspace x = cQy, n = {n}, m = {m}, k = h = {k}, delta = 0.001, "
+                                  f"{args.trials} trials per p, one query each"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +298,8 @@ def main():
     ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--serving-scale", type=float, default=1.0)
     ap.add_argument("--serving-budget-gb", type=float, default=96.0)
+    ap.add_argument("--paper-sweep", action="store_true", help="Section 5 C_alpha sweep instead of the batch line")
+    ap.add_argument("--trials", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures a single MI355X "
@@ -246,6 +310,8 @@ def main():
         return 2
     if args.serving:
         return serving(args)
+    if args.paper_sweep:
+        return paper_sweep(args)
     import torch
     from knn_inputs import gmm_u8
 

@@ -168,7 +168,14 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.G.m = db->m;
   E.G.dtype = db->dtype;
   E.G.nslots = (int32_t)ns;
-  E.G.ch_sample = K.ch_sample;
+  // points per sampling block: about 1024 blocks per step over all slots
+  // (single queries on small DBs still spread over the GPU), at most the
+  // knob's value, at least 16
+  {
+    int64_t want = (n * ns + 1023) / 1024;
+    want = (want + 15) / 16 * 16;
+    E.G.ch_sample = (int32_t)std::max<int64_t>(16, std::min<int64_t>(K.ch_sample, want));
+  }
   E.G.ch_select = 0;
   E.G.ch_decide = 0;
   E.G.lpp = K.lpp;  // 0: chosen per round from its sample count

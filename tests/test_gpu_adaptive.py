@@ -291,3 +291,19 @@ def test_autotune_keeps_results(P, orc):
         ref, rst = orc.adaptive(X, Q[q], 5, oparams(orc, h=5, seed=9))
         assert idx[q, :cnt[q]].tolist() == ref.tolist()
         assert int(st[q]["coord_evals"]) == rst["coord_evals"]
+
+
+@pytest.mark.parametrize("c_alpha", [0.01, 0.3])
+def test_subspace_calpha_parity(P, orc, c_alpha):
+    """Section 5's synthetic data (x = cQy, float) with the C_alpha width: the
+    returned set and the evaluation count equal the oracle's."""
+    from knn_inputs import subspace
+    X, Q = subspace(4242, n=300, m=2048, p=10, nq=3)
+    db = P.KnnDB(dev(X))
+    kw = dict(h=10, delta=0.001, seed=17, alpha_kind=2, c_alpha=c_alpha)
+    idx, cnt, st = db.adaptive(dev(Q), 10, P.default_params(**kw))
+    idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
+    for q in range(3):
+        ref, rst = orc.adaptive(X, Q[q], 10, oparams(orc, **kw))
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert int(st[q]["coord_evals"]) == rst["coord_evals"]
