@@ -286,6 +286,66 @@ def paper_sweep(args):
     return 0
 
 
+def uneven_bench(args):
+    """The uneven workload (n = 250,000 x m = 1024 u8; 4,096 queries, half
+    easy -- k planted points at a small gap, the rest far -- and half hard,
+    near-equal distances; k cycling over 1, 10, 100; delta = 0.01; one seed):
+    adaptive on the whole batch, on the easy half and on the hard half, each
+    against the naive int8-MFMA scan of the same queries (one call per k)."""
+    import torch
+    from knn_inputs import uneven
+
+    P = load_lib()
+    log("generating the uneven workload")
+    X, Q, ks = uneven(4000)
+    db = P.KnnDB(torch.from_numpy(X).cuda())
+    Qd = torch.from_numpy(Q).cuda()
+    n_easy = Q.shape[0] // 2
+    parts = {"all": np.arange(Q.shape[0]), "easy": np.arange(n_easy), "hard": np.arange(n_easy, Q.shape[0])}
+    res = {}
+    for variant, (name, sel) in [(v, pn) for v in ("pure", "candidate_exact") for pn in parts.items()]:
+        qs = Qd[torch.from_numpy(sel).cuda()].contiguous()
+        kk = ks[sel]
+        # pure round form, or with the 2k smallest estimates made exact each round
+        if variant == "pure":
+            p = P.default_params(h=-1, delta=0.01, seed=4001)
+        else:
+            p = [P.default_params(h=-1, delta=0.01, seed=4001, c_exact=int(2 * kv)) for kv in kk]
+        name = f"{variant}_{name}"
+        db.adaptive(qs, kk, p, with_stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            idx, cnt, _ = db.adaptive(qs, kk, p, with_stats=False)
+        torch.cuda.synchronize()
+        ad_s = (time.perf_counter() - t0) / args.steps
+        _, _, st = db.adaptive(qs, kk, p)
+        evals = st["coord_evals"].astype(np.float64)
+        # naive: one call per k
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for kv in (1, 10, 100):
+                sub = torch.from_numpy(np.nonzero(kk == kv)[0]).cuda()
+                if sub.numel():
+                    db.naive(qs[sub].contiguous(), kv, with_dist=False)
+        torch.cuda.synchronize()
+        nv_s = (time.perf_counter() - t0) / args.steps
+        res[name] = {"queries": int(len(sel)), "adaptive_queries_per_s": len(sel) / ad_s,
+                     "naive_queries_per_s": len(sel) / nv_s, "adaptive_vs_naive": nv_s / ad_s,
+                     "evals_fraction_of_naive": float(evals.mean() / (X.shape[0] * X.shape[1]))}
+        log(f"{name}: adaptive {len(sel) / ad_s:.0f} q/s, naive {len(sel) / nv_s:.0f} q/s, "
+            f"evaluations {res[name]['evals_fraction_of_naive']:.3f} of naive")
+    out = {"metric": "uneven workload: queries/s adaptive vs naive MFMA (whole batch, easy half, hard half)",
+           "value": res["pure_all"]["adaptive_queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "uneven: n=250000 x m=1024 uint8 binary corners, 4096 queries (2048 easy with k "
+                                  "planted points, 2048 hard), k in (1, 10, 100), h = k, delta = 0.01"},
+           "parts": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +360,7 @@ def main():
     ap.add_argument("--serving-budget-gb", type=float, default=96.0)
     ap.add_argument("--paper-sweep", action="store_true", help="Section 5 C_alpha sweep instead of the batch line")
     ap.add_argument("--trials", type=int, default=20)
+    ap.add_argument("--uneven", action="store_true", help="uneven workload instead of the batch line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures a single MI355X "
@@ -312,6 +373,8 @@ def main():
         return serving(args)
     if args.paper_sweep:
         return paper_sweep(args)
+    if args.uneven:
+        return uneven_bench(args)
     import torch
     from knn_inputs import gmm_u8
 

@@ -307,3 +307,34 @@ def test_subspace_calpha_parity(P, orc, c_alpha):
         ref, rst = orc.adaptive(X, Q[q], 10, oparams(orc, **kw))
         assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
         assert int(st[q]["coord_evals"]) == rst["coord_evals"]
+
+
+def test_uneven_config_sampled(P, orc):
+    """The uneven workload at full size (n = 250,000 x m = 1024, 4,096 queries,
+    half easy / half hard, k cycling over 1, 10, 100, one seed): every query's
+    set contains its true k-NN (against the exact scan, tie-aware), and sampled
+    easy and hard queries of each k equal the oracle exactly."""
+    from knn_inputs import uneven
+    X, Q, ks = uneven(4000)
+    db = P.KnnDB(dev(X))
+    Qd = dev(Q)
+    p = P.default_params(h=-1, delta=0.01, seed=4001)
+    idx, cnt, st = db.adaptive(Qd, ks, p)
+    idx_c, cnt_c = idx.cpu().numpy(), cnt.cpu().numpy()
+    # containment for all queries, per k, against the int8-MFMA exact scan
+    for kk in (1, 10, 100):
+        sel = np.nonzero(ks == kk)[0]
+        nidx, ndist = db.naive(Qd[torch.from_numpy(sel).cuda()], kk)
+        nidx, ndist = nidx.cpu().numpy(), ndist.cpu().numpy()
+        for row, qi in enumerate(sel):
+            got = idx_c[qi, :cnt_c[qi]]
+            dk = ndist[row, kk - 1]
+            strict = set(nidx[row][ndist[row] < dk].tolist())
+            assert strict <= set(got.tolist()), (qi, kk)
+            dg = ((X[got].astype(np.int64) - Q[qi].astype(np.int64)) ** 2).sum(1)
+            assert (dg <= dk).sum() >= kk, (qi, kk)
+    n_easy = Q.shape[0] // 2
+    for qi in (0, 1, 2, n_easy, n_easy + 1, n_easy + 2):
+        ref, rst = orc.adaptive(X, Q[qi], int(ks[qi]), oparams(orc, h=-1, delta=0.01, seed=4001))
+        assert idx_c[qi, :cnt_c[qi]].tolist() == ref.tolist(), qi
+        assert int(st[qi]["coord_evals"]) == rst["coord_evals"], qi
