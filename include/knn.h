@@ -59,18 +59,28 @@ typedef struct {
   float theta_exact;   /* a point goes exact once the next target reaches ceil(theta m) (0 -> 1) */
   int32_t c_exact;     /* >= 0; the c_exact undecided points with the smallest estimate are
                           made exact after every sampling step (0 = pure round form) */
+  int32_t sampling;    /* 0: coordinates drawn with replacement (Section 4);
+                          1: without replacement (Section 4 footnote): sample t < m of point i
+                          is pi(t) for a per-(seed, point) permutation pi of [0, m) -- a
+                          four-round Feistel network on 2h bits (2^2h >= m, h >= 1) with
+                          round keys Philox4x32-10(seed, counter (0, 0, i, 1)) and round
+                          function F(k, v) = lowbias32(v xor k) mod 2^h, cycle-walked into
+                          [0, m) (Black & Rogaway); d^ at T = m is then the exact distance,
+                          and an exact distance costs the m - T coordinates not yet seen */
 } knn_params;
 
 /* Per-query statistics (24 bytes). */
 typedef struct {
-  int64_t coord_evals;  /* coordinate evaluations: samples + m per exact distance */
+  int64_t coord_evals;  /* coordinate evaluations: samples + m per exact distance (without
+                           replacement: + the m - T coordinates not yet sampled) */
   int32_t rounds;       /* decide steps executed */
   int32_t count;        /* size of the returned set */
   int64_t exact_points; /* points whose distance was computed exactly */
 } knn_stats;
 
 /* Fills *p with the defaults: h = -1 (h = k), delta = 0.01, seed = 0,
- * alpha_kind = 0, c_alpha = 0, b0 = 64, growth = 2, theta_exact = 1, c_exact = 0. */
+ * alpha_kind = 0, c_alpha = 0, b0 = 64, growth = 2, theta_exact = 1, c_exact = 0,
+ * sampling = 0. */
 void knn_params_default(knn_params *p);
 
 /* Thread-local description of the last error on this thread ("" if none). */

@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("alpha_kind", ctypes.c_int32),
                 ("c_alpha", ctypes.c_double), ("b0", ctypes.c_int32),
                 ("growth", ctypes.c_float), ("theta_exact", ctypes.c_float),
-                ("c_exact", ctypes.c_int32)]
+                ("c_exact", ctypes.c_int32), ("sampling", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -59,6 +59,8 @@ def lib():
         L.orc_draw.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
         L.orc_draw.restype = ctypes.c_uint32
         L.orc_index.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+        L.orc_perm_index.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+        L.orc_perm_index.restype = ctypes.c_int64
         L.orc_index.restype = ctypes.c_int64
         L.orc_alpha.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                 ctypes.c_double, ctypes.c_double]
@@ -99,8 +101,8 @@ def _dtype_code(X: np.ndarray) -> int:
 
 
 def make_params(h=-1, delta=0.01, seed=0, alpha_kind=0, c_alpha=0.0, b0=64,
-                growth=2.0, theta_exact=1.0, c_exact=0) -> Params:
-    return Params(h, delta, seed, alpha_kind, c_alpha, b0, growth, theta_exact, c_exact)
+                growth=2.0, theta_exact=1.0, c_exact=0, sampling=0) -> Params:
+    return Params(h, delta, seed, alpha_kind, c_alpha, b0, growth, theta_exact, c_exact, sampling)
 
 
 def philox(ctr, key):
@@ -109,6 +111,10 @@ def philox(ctr, key):
     out = np.zeros(4, dtype=np.uint32)
     lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
     return out
+
+
+def perm_index(seed: int, i: int, t: int, m: int) -> int:
+    return int(lib().orc_perm_index(seed, i, t, m))
 
 
 def draw(seed: int, i: int, t: int) -> int:

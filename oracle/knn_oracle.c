@@ -104,6 +104,43 @@ double orc_alpha(int32_t kind, int64_t u, int64_t n, double delta, double c_alph
 }
 
 /* ------------------------------------------------------------------ */
+/* Sampling without replacement: a keyed permutation of [0, m) (Section  */
+/* 4 footnote; Black & Rogaway's cycle-walking cipher on a Feistel       */
+/* network).                                                             */
+/* ------------------------------------------------------------------ */
+static uint32_t lowbias32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+int64_t orc_perm_index(uint64_t seed, int64_t i, int64_t t, int64_t m) {
+  uint32_t ctr[4] = {0u, 0u, (uint32_t)i, 1u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t rk[4];
+  orc_philox4x32_10(ctr, key, rk);
+  int bits = 0;
+  while (((int64_t)1 << bits) < m) ++bits;  /* ceil(log2 m) */
+  int h = (bits + 1) / 2;
+  if (h < 1) h = 1;
+  const uint32_t mask = (h >= 32) ? 0xFFFFFFFFu : ((1u << h) - 1u);
+  uint64_t x = (uint64_t)t;
+  do {
+    uint32_t L = (uint32_t)(x >> h) & mask, R = (uint32_t)x & mask;
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t nr = L ^ (lowbias32(R ^ rk[r]) & mask);
+      L = R;
+      R = nr;
+    }
+    x = ((uint64_t)L << h) | R;
+  } while ((int64_t)x >= m);
+  return (int64_t)x;
+}
+
+/* ------------------------------------------------------------------ */
 /* Round schedule (round-synchronous reading; Algorithm 1 takes one     */
 /* sample per iteration, here a round takes B samples per point).      */
 /* ------------------------------------------------------------------ */
@@ -149,6 +186,7 @@ typedef struct {
   int32_t dtype;
   double W;
   double scale; /* 2^F */
+  int32_t norepl; /* sampling without replacement */
 } inst_t;
 
 static int ceil_log2(double x) {
@@ -202,8 +240,15 @@ static int64_t exact_sum(const inst_t *I, int64_t i) {
 /* Section 4 estimator: sum of samples t0..t1-1 of point i. */
 static int64_t sampled_sum(const inst_t *I, uint64_t seed, int64_t i, int64_t t0, int64_t t1) {
   int64_t s = 0;
-  for (int64_t t = t0; t < t1; ++t) s += sample_value(I, i, orc_index(seed, i, t, I->m));
+  for (int64_t t = t0; t < t1; ++t)
+    s += sample_value(I, i, I->norepl ? orc_perm_index(seed, i, t, I->m) : orc_index(seed, i, t, I->m));
   return s;
+}
+
+/* Coordinates an exact distance costs on top of T samples already drawn:
+ * all m with replacement, the m - T not yet seen without. */
+static int64_t exact_cost(const inst_t *I, int64_t T) {
+  return I->norepl ? I->m - T : I->m;
 }
 
 /* d^_i(T) = S / (T W): the Section 4 estimate in the [0,1] normalisation. */
@@ -282,6 +327,8 @@ int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
     return 0;
   }
   I.scale = ldexp(1.0, F);
+  if (p->sampling < 0 || p->sampling > 1) return -1;
+  I.norepl = p->sampling;
 
   double alpha_r[MAX_ROUNDS];
   for (int32_t r = 0; r < R; ++r) {
@@ -340,7 +387,7 @@ int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
         if (fl[i] & FL_EXACT) continue;
         S[i] = exact_sum(&I, i);
         fl[i] |= FL_EXACT;
-        st->coord_evals += m;
+        st->coord_evals += exact_cost(&I, T[ri[i]]);
         st->exact_points += 1;
       }
     }
@@ -398,7 +445,7 @@ int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
       if (cur >= R) {
         S[i] = exact_sum(&I, i);
         fl[i] |= FL_EXACT;
-        st->coord_evals += m;
+        st->coord_evals += exact_cost(&I, T[cur - 1]);
         st->exact_points += 1;
       } else {
         S[i] += sampled_sum(&I, p->seed, i, T[cur - 1], T[cur]);
@@ -420,7 +467,7 @@ int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
         if ((fl[i] & FL_DISC) || (fl[i] & FL_EXACT)) continue;
         S[i] = exact_sum(&I, i);
         fl[i] |= FL_EXACT;
-        st->coord_evals += m;
+        st->coord_evals += exact_cost(&I, T[ri[i]]);
         st->exact_points += 1;
       }
     }
@@ -539,6 +586,8 @@ int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype,
     return 0;
   }
   I.scale = ldexp(1.0, F);
+  if (p->sampling < 0 || p->sampling > 1) return -1;
+  I.norepl = p->sampling;
   double thr_d = ceil(theta * (double)m);
   const int64_t thr = thr_d >= (double)m ? m : (thr_d < 1.0 ? 1 : (int64_t)thr_d);
   alg1_state_t A;
@@ -555,12 +604,13 @@ int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype,
   #define ALG1_SAMPLE(i) do {                                                   \
     int64_t i_ = (i);                                                           \
     A.T[i_] += 1;                                                               \
-    A.S[i_] += sample_value(&I, i_, orc_index(p->seed, i_, A.T[i_] - 1, m));     \
+    A.S[i_] += sample_value(&I, i_, I.norepl ? orc_perm_index(p->seed, i_, A.T[i_] - 1, m)  \
+                                             : orc_index(p->seed, i_, A.T[i_] - 1, m));      \
     evals += 1;                                                                 \
     if (A.T[i_] >= thr) {                                                       \
       A.S[i_] = exact_sum(&I, i_);                                              \
       A.ex[i_] = 1;                                                             \
-      evals += m;                                                               \
+      evals += exact_cost(&I, A.T[i_]);                                         \
       exact_pts += 1;                                                           \
       A.dh[i_] = dhat_of(&I, A.S[i_], m);                                       \
       A.al[i_] = 0.0;                                                           \

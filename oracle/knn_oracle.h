@@ -34,6 +34,7 @@ typedef struct {
   float    growth;      /* T grows by max(4, ceil4(T*(g-1))) per round; 0 -> 2 */
   float    theta_exact; /* go exact once the next target reaches ceil(theta*m); 0 -> 1 */
   int32_t  c_exact;     /* candidate-exact count (0 = pure round form) */
+  int32_t  sampling;    /* 0 with replacement, 1 without (orc_perm_index) */
 } orc_params;
 
 typedef struct {
@@ -58,6 +59,16 @@ int64_t orc_index(uint64_t seed, int64_t i, int64_t t, int64_t m);
  * Lemma 3 (kind 1) or of the experiments section (kind 2). Kind 0 falls
  * back to kind 1 when delta/n >= 0.05.  Returns NaN on invalid input. */
 double orc_alpha(int32_t kind, int64_t u, int64_t n, double delta, double c_alpha);
+
+/* Sampling without replacement (Section 4 footnote): sample t (< m) of
+ * point i is pi(t), pi a permutation of [0, m): a four-round Feistel
+ * network on 2h bits, h = max(1, ceil(ceil(log2 m) / 2)), halves of h
+ * bits, (L, R) -> (R, L xor F(k_r, R)) with F(k, v) = lowbias32(v xor k)
+ * mod 2^h, round keys k_0..k_3 = Philox4x32-10(key = seed, counter =
+ * (0, 0, i, 1)); values >= m are enciphered again until they fall in
+ * [0, m) (cycle walking, Black & Rogaway 2002).  lowbias32(x): x ^= x >> 16;
+ * x *= 0x7feb352d; x ^= x >> 15; x *= 0x846ca68b; x ^= x >> 16. */
+int64_t orc_perm_index(uint64_t seed, int64_t i, int64_t t, int64_t m);
 
 /* Round schedule: fills T[0..R-1] with the cumulative sample targets of the
  * sampled rounds; round R is the exact round.  Returns R, or -1 if the

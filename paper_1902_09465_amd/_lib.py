@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("alpha_kind", ctypes.c_int32),
                 ("c_alpha", ctypes.c_double), ("b0", ctypes.c_int32),
                 ("growth", ctypes.c_float), ("theta_exact", ctypes.c_float),
-                ("c_exact", ctypes.c_int32)]
+                ("c_exact", ctypes.c_int32), ("sampling", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -298,16 +298,18 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
     while (lpp < kWave && (uint32_t)(2 * lpp) <= nb) lpp <<= 1;
   }
   const int sub = threadIdx.x % lpp;
+  const bool norepl = sl->norepl != 0;
+  const int ph = perm_half_bits(mm);
   for (int64_t p = base + threadIdx.x / lpp; p < end; p += BT / lpp) {
     const int32_t i = implicit ? (int32_t)p : a.act[p];
     const uint8_t *row = X + (int64_t)i * m * elem;
+    const PermKey pk = norepl ? perm_key((uint32_t)i, k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
     int64_t acc = 0;
     for (uint32_t b = blk0 + sub; b < blk1; b += lpp) {
-      const P4 r = philox10(b, 0u, (uint32_t)i, 0u, k0, k1);
-      acc += sample_val<DT>(row, q, coord_of(r.x, mm), F);
-      acc += sample_val<DT>(row, q, coord_of(r.y, mm), F);
-      acc += sample_val<DT>(row, q, coord_of(r.z, mm), F);
-      acc += sample_val<DT>(row, q, coord_of(r.w, mm), F);
+      uint32_t js[4];
+      draw_block(b, (uint32_t)i, k0, k1, mm, norepl, ph, pk, js);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc += sample_val<DT>(row, q, js[e], F);
     }
     for (int o = lpp / 2; o > 0; o >>= 1) acc += shfl_xor_i64(acc, o);
     if (sub == 0) {
@@ -411,13 +413,15 @@ __device__ __forceinline__ void reduce_store(uint32_t (&v)[GRP], int lane, uint3
 // so the modular combination at the end is exact.
 __device__ __forceinline__ void point_sums(const uint8_t *row, const uint8_t *qT, uint32_t i, uint32_t b_first,
                                            uint32_t step, uint32_t blk1, uint32_t k0, uint32_t k1, uint32_t mm,
-                                           uint32_t (&acc)[GRP]) {
+                                           bool norepl, uint32_t (&acc)[GRP]) {
   uint32_t qq[GRP], xq[GRP], xx = 0;
 #pragma unroll
   for (int g = 0; g < GRP; ++g) qq[g] = xq[g] = 0;
+  const int ph = perm_half_bits(mm);
+  const PermKey pk = norepl ? perm_key(i, k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
   auto fetch = [&](uint32_t blk, uint32_t (&xv)[4], uint4 (&qv)[4]) {
-    const P4 r = philox10(blk, 0u, i, 0u, k0, k1);
-    const uint32_t js[4] = {coord_of(r.x, mm), coord_of(r.y, mm), coord_of(r.z, mm), coord_of(r.w, mm)};
+    uint32_t js[4];
+    draw_block(blk, i, k0, k1, mm, norepl, ph, pk, js);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       xv[e] = row[js[e]];
@@ -500,7 +504,7 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                       const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
                                                       int64_t mp, Bufs B, Geometry G) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ int s_mode, s_cur, s_impl;
+  __shared__ int s_mode, s_cur, s_impl, s_norepl;
   __shared__ uint32_t s_run;
   __shared__ uint64_t s_seed;
   __shared__ uint32_t s_t0, s_t1;
@@ -509,7 +513,7 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int64_t n = G.n, m = G.m;
   if (threadIdx.x == 0) {
     uint32_t run = 0;
-    int mode = 1, cur = 0, impl = 0;
+    int mode = 1, cur = 0, impl = 0, norepl = 0;
     uint64_t seed = 0;
     uint32_t t0 = 0, t1 = 0;
     for (int g = 0; g < GRP; ++g) {
@@ -524,16 +528,18 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
         cur = c;
         seed = sl->seed;
         impl = sl->implicit;
+        norepl = sl->norepl;
         t0 = a0;
         t1 = a1;
         mode = exact ? 2 : 1;
       } else if (c != cur || (exact ? 2 : 1) != mode || sl->implicit != impl ||
-                 (!exact && (sl->seed != seed || a0 != t0 || a1 != t1))) {
+                 (!exact && (sl->seed != seed || sl->norepl != norepl || a0 != t0 || a1 != t1))) {
         mode = 0;
       }
       run |= 1u << g;
     }
     s_run = run;
+    s_norepl = norepl;
     s_mode = run ? mode : -1;
     s_cur = cur;
     s_impl = impl;
@@ -595,7 +601,8 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
           const uint32_t act = group_active(B, g0, n, i, run, impl);
           if (act) {  // uniform within the lanes of this point
             uint32_t acc[GRP];
-            point_sums(xt + (size_t)pt * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, acc);
+            point_sums(xt + (size_t)pt * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, s_norepl,
+                       acc);
             reduce_store_lpp(lpp, acc, lane, act, g0, n, i, cur, B);
             if (sub == 0) {
               my_pts += 1;
@@ -618,7 +625,8 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
         const uint32_t act = group_active(B, g0, n, i, run, impl);
         if (act == 0) continue;  // uniform within the lanes of this point
         uint32_t acc[GRP];
-        point_sums(X + (int64_t)i * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, acc);
+        point_sums(X + (int64_t)i * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, s_norepl,
+                   acc);
         reduce_store_lpp(lpp, acc, lane, act, g0, n, i, cur, B);
         if (sub == 0) {
           my_pts += 1;
@@ -816,6 +824,8 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
   const uint32_t blk0 = R.t0 >> 2, blk1 = R.t1 >> 2;
   const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
   const uint32_t mm = (uint32_t)m;
+  const bool norepl = R.norepl != 0;
+  const int ph = perm_half_bits(mm);
   // QT through a buffer descriptor: the row offset j * nqp is a wave-uniform
   // scalar and the lane's column a fixed vector offset, so a load costs no
   // address arithmetic (and reads past the matrix return zeros)
@@ -849,6 +859,7 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
       continue;
     }
     const uint8_t *row = X + i * m;
+    const PermKey pk = norepl ? perm_key((uint32_t)i, k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
     uint32_t qq[GRP], xq[GRP], xx = 0;
 #pragma unroll
     for (int g = 0; g < GRP; ++g) qq[g] = xq[g] = 0;
@@ -856,11 +867,7 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
       // lane l draws block bb + l
       uint32_t jv[4] = {0u, 0u, 0u, 0u}, xv = 0;
       if (bb + lane < blk1) {
-        const P4 r = philox10(bb + lane, 0u, (uint32_t)i, 0u, k0, k1);
-        jv[0] = coord_of(r.x, mm);
-        jv[1] = coord_of(r.y, mm);
-        jv[2] = coord_of(r.z, mm);
-        jv[3] = coord_of(r.w, mm);
+        draw_block(bb + lane, (uint32_t)i, k0, k1, mm, norepl, ph, pk, jv);
         xv = (uint32_t)row[jv[0]] | ((uint32_t)row[jv[1]] << 8) | ((uint32_t)row[jv[2]] << 16) |
              ((uint32_t)row[jv[3]] << 24);
       }
@@ -1385,10 +1392,12 @@ __global__ __launch_bounds__(MT) void k_cand_merge(Slot *__restrict__ slots, con
   const int np = min(cnt, take);
   const int F = sl->F;
   const uint8_t *q = reinterpret_cast<const uint8_t *>(sl->q);
-  int64_t made = 0;
+  int64_t made = 0, cost = 0;
   for (int t = 0; t < np; ++t) {
     const int32_t i = pick[t];
     if (a.fl[i] & FL_EXACT) continue;
+    // m coordinates, or the m - T not yet sampled without replacement
+    cost += sl->norepl ? m - (int64_t)sl->T[a.ri[i]] : m;
     const int64_t tot = block_exact_sum<DT, MT>(X, m, i, q, F, red);
     if (threadIdx.x == 0) {
       a.S[i] = tot;
@@ -1399,7 +1408,7 @@ __global__ __launch_bounds__(MT) void k_cand_merge(Slot *__restrict__ slots, con
   }
   if (threadIdx.x == 0 && made) {
     sl->exact_points += made;
-    sl->coord_evals += made * m;
+    sl->coord_evals += cost;
   }
 }
 
@@ -1440,10 +1449,11 @@ __device__ void finalize(Slot *sl, int s, const QDesc &qd, const uint8_t *X, con
   __syncthreads();
   if (nP > kh) {
     const uint8_t *q = reinterpret_cast<const uint8_t *>(sl->q);
-    int64_t made = 0;
+    int64_t made = 0, cost = 0;
     for (int t = 0; t < n_acc; ++t) {
       const int32_t i = a.acc[t];
       if (a.fl[i] & FL_EXACT) continue;
+      cost += sl->norepl ? m - (int64_t)sl->T[a.ri[i]] : m;
       const int64_t tot = block_exact_sum<DT, MT>(X, m, i, q, sl->F, red);
       if (threadIdx.x == 0) {
         a.S[i] = tot;
@@ -1454,7 +1464,7 @@ __device__ void finalize(Slot *sl, int s, const QDesc &qd, const uint8_t *X, con
     }
     if (threadIdx.x == 0 && made) {
       sl->exact_points += made;
-      sl->coord_evals += made * m;
+      sl->coord_evals += cost;
     }
     __syncthreads();
     // P = [xa | acc] (n_act == 0 here), every point exact
@@ -1572,6 +1582,7 @@ __device__ void admit(Slot *sl, const QDesc *qd, const Sched *sched, Ctl *ctl, i
     sl->R = sc.R;
     sl->c_exact = d.c_exact;
     sl->F = d.F;
+    sl->norepl = d.norepl;
     sl->seed = d.seed;
     sl->W = d.W;
     sl->q = d.q;
@@ -1620,7 +1631,9 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
       if (threadIdx.x == 0) {
         const int cur = sl->cur + 1;
         sl->cur = cur;
-        const int64_t per = cur < sl->R ? (int64_t)(sl->T[cur] - sl->T[cur - 1]) : m;
+        // the exact round costs m per point, or the m - T not yet seen without replacement
+        const int64_t per = cur < sl->R ? (int64_t)(sl->T[cur] - sl->T[cur - 1])
+                                        : (sl->norepl ? m - (int64_t)sl->T[cur - 1] : m);
         sl->coord_evals += per * sl->n_act;
         if (cur >= sl->R) sl->exact_points += sl->n_act;
         sl->nn_act = 0;

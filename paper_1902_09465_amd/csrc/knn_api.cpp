@@ -222,6 +222,8 @@ int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &pp, QDesc &d, Sc
   d.W = db->dtype == KNN_U8 ? 65025.0 : 0.0;
   d.F = 0;
   d.trivial = kh >= db->n ? 1 : 0;
+  if (pp.sampling < 0 || pp.sampling > 1) return fail(KNN_EINVAL, "sampling must be 0 or 1");
+  d.norepl = pp.sampling;
   return KNN_OK;
 }
 
@@ -292,6 +294,7 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
     const bool ql = E.qt && (t < P.sched[0].R || (t == P.sched[0].R && E.q8));
     if (ql) {
       qr.seed = P.qd[0].seed;
+      qr.norepl = P.qd[0].norepl;
       qr.exact = t >= P.sched[0].R;
       qr.t0 = (t && !qr.exact) ? (uint32_t)P.sched[0].T[t - 1] : 0u;
       qr.t1 = qr.exact ? 0u : (uint32_t)P.sched[0].T[t];
@@ -413,7 +416,7 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
   // the sampling kernel serve them in groups
   bool same = true;
   for (int64_t q = 1; q < nq && same; ++q)
-    same = P.qd[q].seed == P.qd[0].seed && P.qd[q].sched == P.qd[0].sched;
+    same = P.qd[q].seed == P.qd[0].seed && P.qd[q].sched == P.qd[0].sched && P.qd[q].norepl == P.qd[0].norepl;
   // Query-lane sampling: with every query in flight at once (nq <= ns) and
   // one seed and schedule, all slots run the same round at each step, so a
   // wave can serve one point for many slots at a time.
@@ -496,6 +499,7 @@ void knn_params_default(knn_params *p) {
   p->growth = 2.0f;
   p->theta_exact = 1.0f;
   p->c_exact = 0;
+  p->sampling = 0;
 }
 
 const char *knn_last_error(void) { return g_err.c_str(); }

@@ -36,6 +36,7 @@ struct QDesc {
   double W;             // sample normaliser: samples s/W lie in [0,1]
   int32_t F;            // f32 fixed-point shift (0 for u8)
   int32_t trivial;      // 1: k+h >= n or zero range -> return the first min(n,k+h) indices
+  int32_t norepl;       // 1: coordinates drawn without replacement
   int64_t *out_idx;     // row of out_stride int64
   int32_t *out_count;
   knn_stats *out_stats;
@@ -52,7 +53,7 @@ struct Slot {
   int32_t n_act, n_xa, n_acc;   // current list sizes
   int32_t nn_act, nn_xa, nn_acc; // sizes being built by k_decide
   int32_t k, kh, R, c_exact;
-  int32_t F, pad0;
+  int32_t F, norepl;
   uint64_t seed;
   double W;
   const void *q;
@@ -71,7 +72,7 @@ struct QlRound {
   int32_t cur;
   int32_t impl;         // 1: round 0, every point undecided
   int32_t exact;        // 1: the exact round (t0, t1, seed unused)
-  int32_t pad;
+  int32_t norepl;       // 1: coordinates drawn without replacement
 };
 
 // Engine control block (device).

@@ -43,4 +43,66 @@ __device__ __forceinline__ uint32_t coord_of(uint32_t r, uint32_t m) {
   return __umulhi(r, m);
 }
 
+// Sampling without replacement (Section 4 footnote): sample t < m of point i
+// is pi(t) for a permutation pi of [0, m) keyed by (seed, i): a four-round
+// Feistel network on 2h bits (h = max(1, ceil(ceil(log2 m) / 2)), halves of h
+// bits, (L, R) -> (R, L xor F(k_r, R)), F(k, v) = lowbias32(v xor k) mod
+// 2^h), with round keys Philox4x32-10(seed, counter (0, 0, i, 1)) and cycle
+// walking into [0, m) (Black & Rogaway 2002).  lowbias32 is C. Wellons'
+// 32-bit integer hash (hash-prospector).
+struct PermKey {
+  uint32_t k[4];
+};
+
+__device__ __forceinline__ PermKey perm_key(uint32_t i, uint32_t s0, uint32_t s1) {
+  const P4 r = philox10(0u, 0u, i, 1u, s0, s1);
+  return PermKey{{r.x, r.y, r.z, r.w}};
+}
+
+__device__ __forceinline__ int perm_half_bits(uint32_t m) {
+  const int bits = m <= 1u ? 0 : 32 - __clz(m - 1u);  // ceil(log2 m)
+  const int h = (bits + 1) / 2;
+  return h < 1 ? 1 : h;
+}
+
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t perm_coord(uint32_t t, uint32_t m, int h, const PermKey &pk) {
+  const uint32_t mask = (1u << h) - 1u;  // h <= 16 for m < 2^32
+  uint32_t x = t;
+  do {
+    uint32_t L = (x >> h) & mask, R = x & mask;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t nr = L ^ (lowbias32(R ^ pk.k[r]) & mask);
+      L = R;
+      R = nr;
+    }
+    x = (L << h) | R;
+  } while (x >= m);
+  return x;
+}
+
+// The four coordinates of draw block b (samples 4b .. 4b + 3) of point i.
+__device__ __forceinline__ void draw_block(uint32_t b, uint32_t i, uint32_t s0, uint32_t s1, uint32_t m, bool norepl,
+                                           int h, const PermKey &pk, uint32_t (&js)[4]) {
+  if (norepl) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) js[e] = perm_coord(4u * b + (uint32_t)e, m, h, pk);
+  } else {
+    const P4 r = philox10(b, 0u, i, 0u, s0, s1);
+    js[0] = coord_of(r.x, m);
+    js[1] = coord_of(r.y, m);
+    js[2] = coord_of(r.z, m);
+    js[3] = coord_of(r.w, m);
+  }
+}
+
 }  // namespace knn

@@ -53,7 +53,8 @@ def test_tiny_config_parity(P, orc, seed):
         assert set(planted.tolist()) <= set(ref.tolist())
 
 
-@pytest.mark.parametrize("dtype", ["u8", "u8_staged", "u8_qlane", "u8_qlane_pure", "f32"])
+@pytest.mark.parametrize("dtype", ["u8", "u8_staged", "u8_qlane", "u8_qlane_pure", "f32",
+                                   "u8_norepl", "u8_qlane_norepl", "u8_ungrouped_norepl", "f32_norepl"])
 def test_per_round_state_parity(P, orc, dtype, monkeypatch):
     """After every decide step the per-point (S, flags, round) equal the oracle's."""
     g = rng(77)
@@ -62,6 +63,8 @@ def test_per_round_state_parity(P, orc, dtype, monkeypatch):
         monkeypatch.setenv("KNN_STAGE_ROWS", "16")
     if dtype.startswith("u8_qlane"):  # query-lane sampling even for a single slot
         monkeypatch.setenv("KNN_QL_MIN", "1")
+    if dtype.startswith("u8_ungrouped"):  # the per-query sampling kernel
+        monkeypatch.setenv("KNN_GROUP", "0")
     if dtype.startswith("u8"):
         X, Q = gmm_u8(77, n=5003, m=202, n_centres=6, sigma=25.0, nq=1)
     else:
@@ -69,7 +72,7 @@ def test_per_round_state_parity(P, orc, dtype, monkeypatch):
     db = P.KnnDB(dev(X))
     # candidate-exact on, except in the pure variant (fused fold + selection)
     kw = dict(h=4, delta=0.05, seed=int(g.integers(1 << 40)), b0=8, growth=1.5,
-              c_exact=0 if dtype.endswith("pure") else 3)
+              c_exact=0 if dtype.endswith("pure") else 3, sampling=1 if dtype.endswith("norepl") else 0)
     T = orc.schedule(8, 1.5, 1.0, X.shape[1])
     for r in range(1, len(T) + 2):
         S, fl, ri = db.adaptive_state(dev(Q), 6, P.default_params(**kw), r)
@@ -338,3 +341,26 @@ def test_uneven_config_sampled(P, orc):
         ref, rst = orc.adaptive(X, Q[qi], int(ks[qi]), oparams(orc, h=-1, delta=0.01, seed=4001))
         assert idx_c[qi, :cnt_c[qi]].tolist() == ref.tolist(), qi
         assert int(st[qi]["coord_evals"]) == rst["coord_evals"], qi
+
+
+def test_without_replacement_batched(P, orc):
+    """Sampling without replacement, 64 queries with one seed (query-lane
+    sampling and the exact-round GEMM), against the oracle and the per-query
+    path; knob invariance."""
+    X, Q = gmm_u8(81, n=9001, m=500, n_centres=8, sigma=30.0, nq=64)
+    db = P.KnnDB(dev(X))
+    kw = dict(h=10, delta=0.01, seed=77, sampling=1)
+    base = db.adaptive(dev(Q), 10, P.default_params(**kw))
+    for env in ({"KNN_QL": "0"}, {"KNN_QL": "0", "KNN_GROUP": "0"}, {"KNN_QL_MIN": "1", "KNN_CH_SAMPLE": "64"}):
+        os.environ.update(env)
+        try:
+            alt = db.adaptive(dev(Q), 10, P.default_params(**kw))
+        finally:
+            for e in env:
+                del os.environ[e]
+        assert torch.equal(base[0], alt[0]) and torch.equal(base[1], alt[1]) and np.array_equal(base[2], alt[2])
+    idx, cnt = base[0].cpu().numpy(), base[1].cpu().numpy()
+    for q in (0, 31, 63):
+        ref, rst = orc.adaptive(X, Q[q], 10, oparams(orc, **kw))
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert int(base[2][q]["coord_evals"]) == rst["coord_evals"]

@@ -465,3 +465,55 @@ def test_alg1_small_n_and_invalid(orc):
     assert idx.tolist() == list(range(8))
     with pytest.raises(ValueError):
         orc.alg1(X, X[0], 3, orc.make_params(h=1, delta=0.0))
+
+
+# ----------------------------------------------------------------------------
+# Sampling without replacement (Section 4 footnote)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 64, 100, 1000, 3072, 4097])
+def test_perm_is_bijection(orc, m):
+    for seed, i in ((0, 0), (12345, 7), (2**40 + 3, 99999)):
+        vals = [orc.perm_index(seed, i, t, m) for t in range(m)]
+        assert sorted(vals) == list(range(m)), (m, seed, i)
+
+
+def test_perm_uniform_and_point_specific(orc):
+    m = 97
+    counts = np.zeros(m)
+    firsts = set()
+    for i in range(3000):
+        v = orc.perm_index(5, i, 0, m)
+        counts[v] += 1
+        firsts.add(tuple(orc.perm_index(5, i, t, m) for t in range(4)))
+    chi2 = ((counts - counts.mean()) ** 2 / counts.mean()).sum()
+    assert sps.chi2.sf(chi2, m - 1) > 1e-3
+    assert len(firsts) > 2900  # different points, different permutations
+
+
+def test_without_replacement_exact_at_m_and_cost(orc):
+    """Uniform data, where no point is decided before the exact round: with
+    replacement each point costs T_{R-1} samples + m exact coordinates, without
+    it the exact distance completes the permutation, m in all per point."""
+    X, Q = uniform_u8(21, n=600, m=256)
+    kw = dict(h=5, delta=0.01, seed=4)
+    r1, s1 = orc.adaptive(X, Q[0], 5, orc.make_params(**kw, sampling=1))
+    r0, s0 = orc.adaptive(X, Q[0], 5, orc.make_params(**kw, sampling=0))
+    d = brute_dists(X, Q[0])
+    assert contains_knn(r1, d, 5) and contains_knn(r0, d, 5)
+    T = orc.schedule(64, 2.0, 1.0, 256)
+    assert s0["exact_points"] == 600 and s1["exact_points"] == 600
+    assert s0["coord_evals"] == 600 * (T[-1] + 256)
+    assert s1["coord_evals"] == 600 * 256
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_without_replacement_contains(orc, seed):
+    from knn_inputs import gap_family
+    X, q = gap_family(400 + seed, n=500, m=256, k=5, near=5, mid=20)
+    for ce in (0, 10):
+        idx, st = orc.adaptive(X, q, 5, orc.make_params(h=5, delta=0.05, seed=seed, sampling=1, c_exact=ce))
+        assert contains_knn(idx, brute_dists(X, q), 5)
+    idx, st, T = orc.alg1(X, q, 5, orc.make_params(h=5, delta=0.05, seed=seed, sampling=1))
+    assert contains_knn(idx, brute_dists(X, q), 5)
+    assert st["coord_evals"] == int(T.sum())  # exact at T = m costs nothing more
