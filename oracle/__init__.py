@@ -21,6 +21,7 @@ _SRC = os.path.join(_HERE, "knn_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 U8, F32 = 0, 1
+L2, L1 = 0, 1  # distance: squared l2, or l1 (samples |x_ij - x_j|)
 
 
 def build(force: bool = False) -> str:
@@ -68,20 +69,20 @@ def lib():
         L.orc_schedule.argtypes = [ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_int64, P, ctypes.c_int32]
         L.orc_schedule.restype = ctypes.c_int32
-        L.orc_scaling.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P, P, P]
+        L.orc_scaling.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P, P]
         L.orc_scaling.restype = ctypes.c_int32
-        L.orc_adaptive.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P,
+        L.orc_adaptive.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
                                    ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int32,
                                    P, ctypes.POINTER(Stats), P, P, P]
         L.orc_adaptive.restype = ctypes.c_int32
-        L.orc_alg1.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P,
+        L.orc_alg1.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
                                ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int64,
                                P, ctypes.POINTER(Stats), P]
         L.orc_alg1.restype = ctypes.c_int32
-        L.orc_naive.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P,
+        L.orc_naive.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
                                 ctypes.c_int32, P, P]
         L.orc_naive.restype = ctypes.c_int32
-        L.orc_exact_dist.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P,
+        L.orc_exact_dist.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
                                      ctypes.c_int64]
         L.orc_exact_dist.restype = ctypes.c_double
         _lib = L
@@ -137,18 +138,18 @@ def schedule(b0=64, growth=2.0, theta=1.0, m=256, maxlen=64):
     return T[:R].copy()
 
 
-def scaling(X: np.ndarray, q: np.ndarray):
+def scaling(X: np.ndarray, q: np.ndarray, metric: int = 0):
     X = np.ascontiguousarray(X)
     q = np.ascontiguousarray(q)
     W = ctypes.c_double()
     F = ctypes.c_int32()
-    rc = lib().orc_scaling(_ptr(X), X.shape[0], X.shape[1], _dtype_code(X), _ptr(q),
+    rc = lib().orc_scaling(_ptr(X), X.shape[0], X.shape[1], _dtype_code(X), metric, _ptr(q),
                            ctypes.byref(W), ctypes.byref(F))
     return rc, W.value, F.value
 
 
 def adaptive(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
-             stop_after: int = 0, dump: bool = False):
+             stop_after: int = 0, dump: bool = False, metric: int = 0):
     """Returns (idx[count], stats dict[, (S, fl, ri)])."""
     X = np.ascontiguousarray(X)
     q = np.ascontiguousarray(q, dtype=X.dtype)
@@ -161,7 +162,7 @@ def adaptive(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
     S = np.zeros(n, dtype=np.int64) if dump else None
     fl = np.zeros(n, dtype=np.uint8) if dump else None
     ri = np.zeros(n, dtype=np.uint8) if dump else None
-    rc = lib().orc_adaptive(_ptr(X), n, m, _dtype_code(X), _ptr(q), k, ctypes.byref(params),
+    rc = lib().orc_adaptive(_ptr(X), n, m, _dtype_code(X), metric, _ptr(q), k, ctypes.byref(params),
                             stop_after, _ptr(out), ctypes.byref(st),
                             _ptr(S) if dump else None, _ptr(fl) if dump else None,
                             _ptr(ri) if dump else None)
@@ -176,7 +177,7 @@ def adaptive(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
 
 
 def alg1(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
-         max_iter: int = 1 << 40):
+         max_iter: int = 1 << 40, metric: int = 0):
     """Algorithm 1, sequential as published.  Returns (idx[k+h], stats dict,
     final sample counts T[n])."""
     X = np.ascontiguousarray(X)
@@ -188,7 +189,7 @@ def alg1(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
     out = np.full(k + h, -1, dtype=np.int64)
     T = np.zeros(n, dtype=np.int64)
     st = Stats()
-    rc = lib().orc_alg1(_ptr(X), n, m, _dtype_code(X), _ptr(q), k, ctypes.byref(params), max_iter,
+    rc = lib().orc_alg1(_ptr(X), n, m, _dtype_code(X), metric, _ptr(q), k, ctypes.byref(params), max_iter,
                         _ptr(out), ctypes.byref(st), _ptr(T))
     if rc == -2:
         raise RuntimeError("Algorithm 1 did not terminate within max_iter iterations")
@@ -199,20 +200,20 @@ def alg1(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
     return out[:st.count].copy(), stats, T
 
 
-def naive(X: np.ndarray, q: np.ndarray, k: int):
+def naive(X: np.ndarray, q: np.ndarray, k: int, metric: int = 0):
     X = np.ascontiguousarray(X)
     q = np.ascontiguousarray(q, dtype=X.dtype)
     n, m = X.shape
     out = np.full(k, -1, dtype=np.int64)
     dist = np.zeros(k, dtype=np.float64)
-    rc = lib().orc_naive(_ptr(X), n, m, _dtype_code(X), _ptr(q), k, _ptr(out), _ptr(dist))
+    rc = lib().orc_naive(_ptr(X), n, m, _dtype_code(X), metric, _ptr(q), k, _ptr(out), _ptr(dist))
     if rc != 0:
         raise ValueError(f"oracle naive rejected arguments (rc={rc})")
     return out, dist
 
 
-def exact_dist(X: np.ndarray, q: np.ndarray, i: int) -> float:
+def exact_dist(X: np.ndarray, q: np.ndarray, i: int, metric: int = 0) -> float:
     X = np.ascontiguousarray(X)
     q = np.ascontiguousarray(q, dtype=X.dtype)
     return float(lib().orc_exact_dist(_ptr(X), X.shape[0], X.shape[1], _dtype_code(X),
-                                      _ptr(q), i))
+                                      metric, _ptr(q), i))

@@ -176,6 +176,12 @@ int32_t orc_schedule(int32_t b0, float growth, float theta, int64_t m,
 /*   u8:  s = (x_ij - x_j)^2,            W = 255^2;                      */
 /*   f32: s = trunc(fl32(fl32(x_ij - x_j)^2) * 2^F),  W = R' 2^F, where  */
 /*        R' = (hi - lo)^2 (1 + 2^-20) over the points and the query.    */
+/* The l1 distance (Section 3 remarks that the results carry over to it)  */
+/* samples |x_ij - x_j| instead, which lies in [0,1] under the same      */
+/* normalisation, so the same estimator and widths apply:                */
+/*   u8:  s = |x_ij - x_j|,              W = 255;                        */
+/*   f32: s = trunc(|fl32(x_ij - x_j)| * 2^F),  W = R' 2^F with          */
+/*        R' = (hi - lo) (1 + 2^-20).                                    */
 /* ------------------------------------------------------------------ */
 typedef struct {
   const uint8_t *xu;
@@ -184,6 +190,7 @@ typedef struct {
   const float *qf;
   int64_t n, m;
   int32_t dtype;
+  int32_t metric; /* ORC_L2 or ORC_L1 */
   double W;
   double scale; /* 2^F */
   int32_t norepl; /* sampling without replacement */
@@ -195,9 +202,10 @@ static int ceil_log2(double x) {
   return (f == 0.5) ? e - 1 : e;
 }
 
-int32_t orc_scaling(const void *X, int64_t n, int64_t m, int32_t dtype,
+int32_t orc_scaling(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                     const void *q, double *W, int32_t *F) {
-  if (dtype == ORC_U8) { *W = 65025.0; *F = 0; return 0; }
+  if (metric != ORC_L2 && metric != ORC_L1) return -1;
+  if (dtype == ORC_U8) { *W = metric == ORC_L1 ? 255.0 : 65025.0; *F = 0; return 0; }
   if (dtype != ORC_F32) return -1;
   const float *xf = (const float *)X, *qf = (const float *)q;
   double lo = INFINITY, hi = -INFINITY;
@@ -213,7 +221,7 @@ int32_t orc_scaling(const void *X, int64_t n, int64_t m, int32_t dtype,
   }
   double span = hi - lo;
   if (!(span > 0.0)) { *W = 0.0; *F = 0; return 1; }
-  double Rp = span * span * (1.0 + 0x1p-20);
+  double Rp = (metric == ORC_L1 ? span : span * span) * (1.0 + 0x1p-20);
   int f = 61 - ceil_log2((double)m) - ceil_log2(Rp);
   *F = f;
   *W = ldexp(Rp, f);
@@ -223,10 +231,11 @@ int32_t orc_scaling(const void *X, int64_t n, int64_t m, int32_t dtype,
 static int64_t sample_value(const inst_t *I, int64_t i, int64_t j) {
   if (I->dtype == ORC_U8) {
     int64_t d = (int64_t)I->xu[i * I->m + j] - (int64_t)I->qu[j];
+    if (I->metric == ORC_L1) return d < 0 ? -d : d;
     return d * d;
   }
   float d = I->xf[i * I->m + j] - I->qf[j];
-  float v = d * d;
+  float v = I->metric == ORC_L1 ? fabsf(d) : d * d;
   return (int64_t)((double)v * I->scale);
 }
 
@@ -287,7 +296,7 @@ static double kth_smallest(double *v, int64_t len, int64_t r) {
 #define FL_DISC 4u
 #define MAX_ROUNDS 64
 
-int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
+int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                      const void *q, int32_t k, const orc_params *p,
                      int32_t stop_after, int64_t *out_idx, orc_stats *st,
                      int64_t *S_dump, uint8_t *fl_dump, uint8_t *ri_dump) {
@@ -314,11 +323,11 @@ int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
 
   inst_t I;
   memset(&I, 0, sizeof(I));
-  I.n = n; I.m = m; I.dtype = dtype;
+  I.n = n; I.m = m; I.dtype = dtype; I.metric = metric;
   if (dtype == ORC_U8) { I.xu = (const uint8_t *)X; I.qu = (const uint8_t *)q; }
   else { I.xf = (const float *)X; I.qf = (const float *)q; }
   int32_t F;
-  int32_t sc = orc_scaling(X, n, m, dtype, q, &I.W, &F);
+  int32_t sc = orc_scaling(X, n, m, dtype, metric, q, &I.W, &F);
   if (sc < 0) return -1;
   if (sc == 1) {
     /* zero range: every distance is 0, any k+h points are an answer */
@@ -495,7 +504,7 @@ int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
 /* ------------------------------------------------------------------ */
 /* Naive brute force (Section 3): all distances, then sort.             */
 /* ------------------------------------------------------------------ */
-double orc_exact_dist(const void *X, int64_t n, int64_t m, int32_t dtype,
+double orc_exact_dist(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                       const void *q, int64_t i) {
   (void)n;
   if (dtype == ORC_U8) {
@@ -503,7 +512,7 @@ double orc_exact_dist(const void *X, int64_t n, int64_t m, int32_t dtype,
     int64_t s = 0;
     for (int64_t j = 0; j < m; ++j) {
       int64_t d = (int64_t)xu[i * m + j] - (int64_t)qu[j];
-      s += d * d;
+      s += metric == ORC_L1 ? (d < 0 ? -d : d) : d * d;
     }
     return (double)s;
   }
@@ -511,7 +520,7 @@ double orc_exact_dist(const void *X, int64_t n, int64_t m, int32_t dtype,
   double s = 0.0;
   for (int64_t j = 0; j < m; ++j) {
     double d = (double)xf[i * m + j] - (double)qf[j];
-    s += d * d;
+    s += metric == ORC_L1 ? fabs(d) : d * d;
   }
   return s;
 }
@@ -550,7 +559,7 @@ static void reposition(const alg1_state_t *A, int64_t *ord, int64_t *pos, int64_
   pos[i] = p;
 }
 
-int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype,
+int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                  const void *q, int32_t k, const orc_params *p, int64_t max_iter,
                  int64_t *out_idx, orc_stats *st, int64_t *T_out) {
   if (!X || !q || !p || !out_idx || !st || n < 1 || m < 1 || k < 1) return -1;
@@ -574,11 +583,11 @@ int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype,
   }
   inst_t I;
   memset(&I, 0, sizeof(I));
-  I.n = n; I.m = m; I.dtype = dtype;
+  I.n = n; I.m = m; I.dtype = dtype; I.metric = metric;
   if (dtype == ORC_U8) { I.xu = (const uint8_t *)X; I.qu = (const uint8_t *)q; }
   else { I.xf = (const float *)X; I.qf = (const float *)q; }
   int32_t F;
-  int sc = orc_scaling(X, n, m, dtype, q, &I.W, &F);
+  int sc = orc_scaling(X, n, m, dtype, metric, q, &I.W, &F);
   if (sc < 0) return -1;
   if (sc == 1) {  /* zero range: every distance is 0 */
     for (int64_t a = 0; a < kh; ++a) out_idx[a] = a;
@@ -668,14 +677,15 @@ int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype,
   return rc;
 }
 
-int32_t orc_naive(const void *X, int64_t n, int64_t m, int32_t dtype,
+int32_t orc_naive(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                   const void *q, int32_t k, int64_t *out_idx, double *out_dist) {
   if (!X || !q || !out_idx || n < 1 || m < 1 || k < 1) return -1;
   if (dtype != ORC_U8 && dtype != ORC_F32) return -1;
+  if (metric != ORC_L2 && metric != ORC_L1) return -1;
   keyidx_t *ki = (keyidx_t *)malloc((size_t)n * sizeof(keyidx_t));
   if (!ki) return -2;
   for (int64_t i = 0; i < n; ++i) {
-    ki[i].key = orc_exact_dist(X, n, m, dtype, q, i);
+    ki[i].key = orc_exact_dist(X, n, m, dtype, metric, q, i);
     ki[i].idx = i;
   }
   qsort(ki, (size_t)n, sizeof(keyidx_t), cmp_keyidx);

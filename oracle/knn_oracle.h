@@ -21,6 +21,9 @@ extern "C" {
 #endif
 
 enum { ORC_U8 = 0, ORC_F32 = 1 };
+/* Distance: squared l2 (the paper's), or l1 (Section 3: the results carry
+ * over to it), whose samples are |x_ij - x_j| instead of (x_ij - x_j)^2. */
+enum { ORC_L2 = 0, ORC_L1 = 1 };
 
 /* Result-defining parameters of one query (same field order and meaning as
  * the product's parameter struct, so one Python object can fill both). */
@@ -77,9 +80,11 @@ int32_t orc_schedule(int32_t b0, float growth, float theta, int64_t m,
                      int32_t *T, int32_t maxlen);
 
 /* Fixed-point scaling for float data: W (samples s/W lie in [0,1]) and the
- * shift F; for u8 W = 255^2 and F = 0.  Returns 0 ok, 1 degenerate (zero
- * range), <0 invalid. */
-int32_t orc_scaling(const void *X, int64_t n, int64_t m, int32_t dtype,
+ * shift F; for u8 W = 255^2 (l1: 255) and F = 0.  For f32, with R = hi - lo
+ * over the points and the query, R' = R^2 (1 + 2^-20) (l1: R (1 + 2^-20)),
+ * F = 61 - ceil(log2 m) - ceil(log2 R') and W = R' 2^F.  Returns 0 ok,
+ * 1 degenerate (zero range), <0 invalid. */
+int32_t orc_scaling(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                     const void *q, double *W, int32_t *F);
 
 /* Adaptive k-NN, round-synchronous form of Algorithm 1.
@@ -87,7 +92,7 @@ int32_t orc_scaling(const void *X, int64_t n, int64_t m, int32_t dtype,
  * decide steps without finalising (for state comparison); the per-point
  * state is then written to S_dump / fl_dump / ri_dump when non-NULL.
  * Returns 0 ok, <0 invalid arguments. */
-int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
+int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                      const void *q, int32_t k, const orc_params *p,
                      int32_t stop_after, int64_t *out_idx, orc_stats *st,
                      int64_t *S_dump, uint8_t *fl_dump, uint8_t *ri_dump);
@@ -105,19 +110,19 @@ int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype,
  * + m per exact point), rounds = iterations, count, exact_points.
  * T_out (nullable): [n] final sample counts.  Returns 0 ok, -1 invalid
  * arguments, -2 when max_iter iterations did not terminate. */
-int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype,
+int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                  const void *q, int32_t k, const orc_params *p, int64_t max_iter,
                  int64_t *out_idx, orc_stats *st, int64_t *T_out);
 
 /* Naive brute force of Section 3: all distances, k smallest by (d, index).
  * u8: exact int64 sums; f32: double sums in coordinate order.
- * out_dist receives the unnormalised squared distances. */
-int32_t orc_naive(const void *X, int64_t n, int64_t m, int32_t dtype,
+ * out_dist receives the unnormalised distances (squared l2, or l1). */
+int32_t orc_naive(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                   const void *q, int32_t k, int64_t *out_idx, double *out_dist);
 
-/* Exact squared distance of one point (unnormalised), as the naive scan
- * computes it. */
-double orc_exact_dist(const void *X, int64_t n, int64_t m, int32_t dtype,
+/* Exact distance of one point (unnormalised squared l2, or l1), as the
+ * naive scan computes it. */
+double orc_exact_dist(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                       const void *q, int64_t i);
 
 #ifdef __cplusplus

@@ -14,6 +14,14 @@ def brute_dists(X: np.ndarray, q: np.ndarray) -> np.ndarray:
     return (d * d).sum(axis=1)
 
 
+def brute_l1(X: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Exact l1 distances by numpy (int64 for u8, float64 for f32)."""
+    q = np.asarray(q).reshape(-1)
+    if X.dtype == np.uint8:
+        return np.abs(X.astype(np.int64) - q.astype(np.int64)[None, :]).sum(axis=1)
+    return np.abs(X.astype(np.float64) - q.astype(np.float64)[None, :]).sum(axis=1)
+
+
 def knn_sets(dists: np.ndarray, k: int, rtol: float = 0.0):
     """(strictly-closer set, boundary-tie set, d_(k)) for tie-aware checks."""
     dk = np.sort(dists)[k - 1]
