@@ -36,6 +36,12 @@ typedef enum { KNN_U8 = 0, KNN_F32 = 1 } knn_dtype;
 
 #define KNN_DB_BORROW 0   /* alias dev_points; caller keeps it alive until destroy */
 #define KNN_DB_COPY 1     /* copy dev_points into library-owned HBM */
+#define KNN_DB_L1 2       /* flag bit: the DB's distance is l1, sum_j |x_j - y_j| (Section 3
+                             notes that the results carry over to it); without it the
+                             distance is the squared l2 of Section 3 */
+
+/* Distance of a DB (knn_db_metric). */
+typedef enum { KNN_METRIC_L2 = 0, KNN_METRIC_L1 = 1 } knn_metric;
 
 #define KNN_MAX_KH 2048   /* largest k + h (adaptive) and k (naive) */
 #define KNN_MAX_ROUNDS 48 /* longest round schedule */
@@ -92,10 +98,15 @@ const char *knn_version(void);
 /* ---------------------------------------------------------------- DB --- */
 
 /* Registers n points of dimension m (Section 3: the point set X in R^m).
- * dev_points: device, [n][m] row-major, u8 or f32.  BORROW aliases it; COPY
- * copies it.  Precomputes row norms (and for f32 a BF16 copy and the value
- * range) for the naive scan.  Synchronous.  Errors: EINVAL (n < 1, m < 1,
- * n >= 2^31, bad dtype/flags, NULL), ENOMEM, EDEVICE. */
+ * dev_points: device, [n][m] row-major, u8 or f32.  flags: KNN_DB_BORROW
+ * aliases it, KNN_DB_COPY copies it; or-ing in KNN_DB_L1 makes every search
+ * on the DB use the l1 distance (adaptive samples |x_ij - x_j|, normalised
+ * by 255 for u8 and by the value range for f32; the naive scan sums
+ * |x_j - q_j|).  Precomputes for the naive scan: squared l2 -- row norms,
+ * shifted int8 (u8) or split BF16 (f32) copies; l1 -- a copy with rows
+ * zero-padded to a multiple of 64 elements.  For f32 also the value range.
+ * Synchronous.  Errors: EINVAL (n < 1, m < 1, n >= 2^31, bad dtype/flags,
+ * NULL), ENOMEM, EDEVICE. */
 int knn_db_create(const void *dev_points, int64_t n, int64_t m, knn_dtype dt,
                   int32_t flags, knn_db *out);
 
@@ -105,6 +116,9 @@ int knn_db_destroy(knn_db db);
 
 /* n, m and dtype of a DB. */
 int knn_db_info(knn_db db, int64_t *n, int64_t *m, int32_t *dtype);
+
+/* The DB's distance: KNN_METRIC_L2 (squared l2) or KNN_METRIC_L1. */
+int knn_db_metric(knn_db db, int32_t *metric);
 
 /* ---------------------------------------------------------- adaptive --- */
 
@@ -168,13 +182,16 @@ int knn_autotune(knn_db db, const void *dev_queries, int64_t nq, int32_t k, cons
 /* ------------------------------------------------------------- naive --- */
 
 /* Naive k-NN (Section 3): all n distances, the k smallest by (distance,
- * index).  u8: exact integer distances via int8 MFMA; f32: BF16 MFMA
- * candidates, rescored in FP64 in coordinate order, so the set and the
- * distances equal an FP64 scan.
+ * index).  Squared l2 -- u8: exact integer distances via int8 MFMA; f32:
+ * BF16 MFMA candidates, rescored in FP64 in coordinate order, so the set and
+ * the distances equal an FP64 scan.  l1 (no matrix-core form) -- u8: exact
+ * integer sums of absolute differences (v_sad_u8); f32: fp32 sums with an
+ * error bound, candidates rescored in FP64 in coordinate order.
  *  dev_out_idx : device, [nq][k] int64 (ascending distance).
- *  dev_out_dist: device, [nq][k] double (unnormalised squared distance), or NULL.
- * Stream-ordered.  Errors: EINVAL (k < 1, k > min(n, KNN_MAX_KH), NULL), ENOMEM,
- * EDEVICE. */
+ *  dev_out_dist: device, [nq][k] double (unnormalised squared l2 or l1
+ *                distance), or NULL.
+ * Stream-ordered.  Errors: EINVAL (k < 1, k > min(n, KNN_MAX_KH), u8 k > 128,
+ * f32 k > 64, NULL), ENOMEM, EDEVICE. */
 int knn_naive(knn_db db, const void *dev_queries, int64_t nq, int32_t k,
               int64_t *dev_out_idx, double *dev_out_dist, void *stream);
 

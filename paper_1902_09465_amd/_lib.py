@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libknn.so")
 KNN_OK, KNN_PENDING = 0, 1
 KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_EBUSY, KNN_ENOTFOUND = -1, -2, -3, -4, -5
 KNN_U8, KNN_F32 = 0, 1
-KNN_DB_BORROW, KNN_DB_COPY = 0, 1
+KNN_DB_BORROW, KNN_DB_COPY, KNN_DB_L1 = 0, 1, 2
+KNN_METRIC_L2, KNN_METRIC_L1 = 0, 1
 KNN_MAX_KH = 2048
 KNN_MAX_ROUNDS = 48
 
@@ -55,6 +56,7 @@ EXPORTS = [
     ("knn_db_create", ctypes.c_int, [_P, _I64, _I64, ctypes.c_int, _I32, ctypes.POINTER(_P)]),
     ("knn_db_destroy", ctypes.c_int, [_P]),
     ("knn_db_info", ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
+    ("knn_db_metric", ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
     ("knn_schedule", ctypes.c_int, [ctypes.POINTER(Params), _I64, _I64, _P, _P, ctypes.POINTER(_I32)]),
     ("knn_adaptive", ctypes.c_int, [_P, _P, _I64, _P, ctypes.POINTER(Params), _I64, _P, _I64, _P, _P, _P]),
     ("knn_adaptive_state", ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(Params), _I32, _P, _P, _P, _P]),

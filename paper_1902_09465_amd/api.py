@@ -41,16 +41,24 @@ def schedule(params: Params, n: int, m: int):
 class KnnDB:
     """A registered point set (Section 3: X = {x_1..x_n} in R^m), device resident."""
 
-    def __init__(self, X: torch.Tensor, copy: bool = False):
+    def __init__(self, X: torch.Tensor, copy: bool = False, metric: str = "l2"):
+        """metric: "l2" (squared Euclidean, the paper's) or "l1" (sum of
+        absolute differences); every search on the DB uses it."""
         if not X.is_cuda or X.dim() != 2:
             raise ValueError("X must be a 2-D CUDA tensor")
+        if metric not in ("l2", "l1"):
+            raise ValueError('metric must be "l2" or "l1"')
         X = X.contiguous()
         self.X = X  # keeps a borrowed buffer alive
         self.n, self.m = X.shape
         self.dtype = X.dtype
+        self.metric = metric
+        flags = _lib.KNN_DB_COPY if copy else _lib.KNN_DB_BORROW
+        if metric == "l1":
+            flags |= _lib.KNN_DB_L1
         h = ctypes.c_void_p()
-        check(lib().knn_db_create(ctypes.c_void_p(X.data_ptr()), self.n, self.m, _dtype_code(X),
-                                  _lib.KNN_DB_COPY if copy else _lib.KNN_DB_BORROW, ctypes.byref(h)))
+        check(lib().knn_db_create(ctypes.c_void_p(X.data_ptr()), self.n, self.m, _dtype_code(X), flags,
+                                  ctypes.byref(h)))
         self.handle = h
 
     def close(self):

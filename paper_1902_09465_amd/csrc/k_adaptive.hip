@@ -50,14 +50,18 @@ __device__ __forceinline__ int64_t fixed_of(float v, int F) {
   return (sh <= -32) ? 0 : (int64_t)(mant >> (-sh));
 }
 
-template <int DT>
+// One sample of coordinate j: (x_ij - x_j)^2, or |x_ij - x_j| for the l1
+// distance (f32: in fixed point, floor(v 2^F)).
+template <int DT, int MET>
 __device__ __forceinline__ int64_t sample_val(const uint8_t *__restrict__ row,
                                               const uint8_t *__restrict__ q, uint32_t j, int F) {
   if constexpr (DT == KNN_U8) {
     const int d = (int)row[j] - (int)q[j];
+    if constexpr (MET == KNN_METRIC_L1) return (int64_t)(d < 0 ? -d : d);
     return (int64_t)__mul24(d, d);  // |d| < 2^8: the full-rate 24-bit multiply is exact
   } else {
     const float d = reinterpret_cast<const float *>(row)[j] - reinterpret_cast<const float *>(q)[j];
+    if constexpr (MET == KNN_METRIC_L1) return fixed_of(fabsf(d), F);
     return fixed_of(d * d, F);
   }
 }
@@ -124,12 +128,16 @@ __device__ __forceinline__ int64_t size_A(const Slot *sl, int64_t n) {
 // Exact sum over all m coordinates of point i by the whole block
 // (rare paths: candidate-exact and oversized finalisation).
 template <int DT, int BT>
-__device__ int64_t block_exact_sum(const uint8_t *X, int64_t m, int32_t i, const uint8_t *q, int F,
+__device__ int64_t block_exact_sum(const uint8_t *X, int64_t m, int32_t i, const uint8_t *q, int F, int met,
                                    int64_t *red) {
   const int elem = DT == KNN_U8 ? 1 : 4;
   const uint8_t *row = X + (int64_t)i * m * elem;
   int64_t acc = 0;
-  for (int64_t j = threadIdx.x; j < m; j += BT) acc += sample_val<DT>(row, q, (uint32_t)j, F);
+  if (met == KNN_METRIC_L1) {
+    for (int64_t j = threadIdx.x; j < m; j += BT) acc += sample_val<DT, KNN_METRIC_L1>(row, q, (uint32_t)j, F);
+  } else {
+    for (int64_t j = threadIdx.x; j < m; j += BT) acc += sample_val<DT, KNN_METRIC_L2>(row, q, (uint32_t)j, F);
+  }
   for (int o = kWave / 2; o > 0; o >>= 1) acc += shfl_xor_i64(acc, o);
   __syncthreads();
   if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
@@ -143,7 +151,8 @@ __device__ int64_t block_exact_sum(const uint8_t *X, int64_t m, int32_t i, const
 // ---------------------------------------------------------------- f32 prep
 
 // Per query: value range of query and points -> W = R' 2^F with
-// R' = (hi - lo)^2 (1 + 2^-20), F = 61 - ceil(log2 m) - ceil(log2 R').
+// R' = (hi - lo)^2 (1 + 2^-20) (l1: (hi - lo)(1 + 2^-20)),
+// F = 61 - ceil(log2 m) - ceil(log2 R').
 __device__ __forceinline__ int ceil_log2_pos(double x) {
   uint64_t b;
   __builtin_memcpy(&b, &x, 8);
@@ -158,7 +167,7 @@ __device__ __forceinline__ double pow2_d(int e) {
 }
 
 __global__ __launch_bounds__(NT) void k_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m,
-                                                 double db_lo, double db_hi) {
+                                                 double db_lo, double db_hi, int32_t metric) {
   const int qi = blockIdx.x;
   if (qi >= nq) return;
   const float *q = reinterpret_cast<const float *>(qd[qi].q);
@@ -189,7 +198,8 @@ __global__ __launch_bounds__(NT) void k_prep_f32(QDesc *qd, int32_t nq, int64_t 
       qd[qi].W = 0.0;
       qd[qi].F = 0;
     } else {
-      const double Rp = span * span * (1.0 + 0x1p-20);
+      // the largest sample, (hi - lo)^2 or (l1) hi - lo, with room for fp32 rounding
+      const double Rp = (metric == KNN_METRIC_L1 ? span : span * span) * (1.0 + 0x1p-20);
       const int F = 61 - ceil_log2_pos((double)m) - ceil_log2_pos(Rp);
       qd[qi].F = F;
       qd[qi].W = Rp * pow2_d(F);
@@ -204,7 +214,7 @@ __global__ __launch_bounds__(NT) void k_prep_f32(QDesc *qd, int32_t nq, int64_t 
 // point of the sampled list, LPP lanes per point (each lane takes every
 // LPP-th block of four draws); or, in the exact round, the exact distance,
 // one wave per point with coalesced row reads.
-template <int DT, bool QLDS, int BT = NT>
+template <int DT, int MET, bool QLDS, int BT = NT>
 __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const uint8_t *__restrict__ X,
                                   const Bufs &B, const Geometry &G, uint8_t *smem) {
   const int64_t n = G.n, m = G.m;
@@ -258,16 +268,21 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
             const uint32_t qv = QLDS ? reinterpret_cast<const uint32_t *>(q)[w]
                                      : (uint32_t)q[4 * w] | ((uint32_t)q[4 * w + 1] << 8) |
                                            ((uint32_t)q[4 * w + 2] << 16) | ((uint32_t)q[4 * w + 3] << 24);
-            // four squared differences as x.x + q.q - 2 x.q (at most 4 * 255^2)
-            const uint32_t sq = __builtin_amdgcn_udot4(xv, xv, 0u, false) + __builtin_amdgcn_udot4(qv, qv, 0u, false) -
-                                2u * __builtin_amdgcn_udot4(xv, qv, 0u, false);
-            acc += (int64_t)sq;
+            if constexpr (MET == KNN_METRIC_L1) {
+              // four absolute differences in one sum-of-absolute-differences
+              acc += (int64_t)__builtin_amdgcn_sad_u8(xv, qv, 0u);
+            } else {
+              // four squared differences as x.x + q.q - 2 x.q (at most 4 * 255^2)
+              const uint32_t sq = __builtin_amdgcn_udot4(xv, xv, 0u, false) +
+                                  __builtin_amdgcn_udot4(qv, qv, 0u, false) - 2u * __builtin_amdgcn_udot4(xv, qv, 0u, false);
+              acc += (int64_t)sq;
+            }
           }
         } else {
-          for (int64_t j = lane; j < m; j += kWave) acc += sample_val<DT>(row, q, (uint32_t)j, F);
+          for (int64_t j = lane; j < m; j += kWave) acc += sample_val<DT, MET>(row, q, (uint32_t)j, F);
         }
       } else {
-        for (int64_t j = lane; j < m; j += kWave) acc += sample_val<DT>(row, q, (uint32_t)j, F);
+        for (int64_t j = lane; j < m; j += kWave) acc += sample_val<DT, MET>(row, q, (uint32_t)j, F);
       }
       for (int o = kWave / 2; o > 0; o >>= 1) acc += shfl_xor_i64(acc, o);
       if (lane == 0) {
@@ -309,7 +324,7 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
       uint32_t js[4];
       draw_block(b, (uint32_t)i, k0, k1, mm, norepl, ph, pk, js);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc += sample_val<DT>(row, q, js[e], F);
+      for (int e = 0; e < 4; ++e) acc += sample_val<DT, MET>(row, q, js[e], F);
     }
     for (int o = lpp / 2; o > 0; o >>= 1) acc += shfl_xor_i64(acc, o);
     if (sub == 0) {
@@ -325,7 +340,7 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
   __syncthreads();  // smem (the staged query) may be reused by the caller
 }
 
-template <int DT, bool QLDS>
+template <int DT, int MET, bool QLDS>
 __global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const uint8_t *__restrict__ X,
                                                Bufs B, Geometry G) {
   // slot-fastest grid: blocks that run together cover the same points for
@@ -334,7 +349,7 @@ __global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const u
   const Slot *sl = &slots[s];
   if (sl->state != 1) return;
   extern __shared__ __align__(16) uint8_t smem[];
-  sample_slot_chunk<DT, QLDS>(sl, s, (int64_t)blockIdx.y, X, B, G, smem);
+  sample_slot_chunk<DT, MET, QLDS>(sl, s, (int64_t)blockIdx.y, X, B, G, smem);
 }
 
 // ---------------------------------------------------------------- grouped sample (u8)
@@ -410,7 +425,9 @@ __device__ __forceinline__ void reduce_store(uint32_t (&v)[GRP], int lane, uint3
 // four values, and each product is one dot4.  `row` is the point's row, in
 // global memory or staged in LDS; qT is the transposed query tile in LDS.
 // The per-lane results are below 2^32 (at most m < 4096 draws of 255^2),
-// so the modular combination at the end is exact.
+// so the modular combination at the end is exact.  For the l1 distance each
+// query's four |x - q| are one v_sad_u8 on the same transposed dwords.
+template <int MET>
 __device__ __forceinline__ void point_sums(const uint8_t *row, const uint8_t *qT, uint32_t i, uint32_t b_first,
                                            uint32_t step, uint32_t blk1, uint32_t k0, uint32_t k1, uint32_t mm,
                                            bool norepl, uint32_t (&acc)[GRP]) {
@@ -430,7 +447,7 @@ __device__ __forceinline__ void point_sums(const uint8_t *row, const uint8_t *qT
   };
   auto consume = [&](const uint32_t (&xv)[4], const uint4 (&qv)[4]) {
     const uint32_t x4 = xv[0] | (xv[1] << 8) | (xv[2] << 16) | (xv[3] << 24);
-    xx = __builtin_amdgcn_udot4(x4, x4, xx, false);
+    if constexpr (MET == KNN_METRIC_L2) xx = __builtin_amdgcn_udot4(x4, x4, xx, false);
     const uint32_t r[4][4] = {{qv[0].x, qv[1].x, qv[2].x, qv[3].x},
                               {qv[0].y, qv[1].y, qv[2].y, qv[3].y},
                               {qv[0].z, qv[1].z, qv[2].z, qv[3].z},
@@ -446,8 +463,12 @@ __device__ __forceinline__ void point_sums(const uint8_t *row, const uint8_t *qT
                              __builtin_amdgcn_perm(t3, t1, 0x05040100u), __builtin_amdgcn_perm(t3, t1, 0x07060302u)};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        qq[4 * w + u] = __builtin_amdgcn_udot4(c[u], c[u], qq[4 * w + u], false);
-        xq[4 * w + u] = __builtin_amdgcn_udot4(x4, c[u], xq[4 * w + u], false);
+        if constexpr (MET == KNN_METRIC_L1) {
+          xq[4 * w + u] = __builtin_amdgcn_sad_u8(x4, c[u], xq[4 * w + u]);
+        } else {
+          qq[4 * w + u] = __builtin_amdgcn_udot4(c[u], c[u], qq[4 * w + u], false);
+          xq[4 * w + u] = __builtin_amdgcn_udot4(x4, c[u], xq[4 * w + u], false);
+        }
       }
     }
   };
@@ -468,7 +489,7 @@ __device__ __forceinline__ void point_sums(const uint8_t *row, const uint8_t *qT
     b = b2;
   }
 #pragma unroll
-  for (int g = 0; g < GRP; ++g) acc[g] = xx + qq[g] - 2u * xq[g];
+  for (int g = 0; g < GRP; ++g) acc[g] = MET == KNN_METRIC_L1 ? xq[g] : xx + qq[g] - 2u * xq[g];
 }
 
 // Flags of the point for the running slots of the group: bit g set when slot
@@ -500,6 +521,7 @@ __device__ __forceinline__ void reduce_store_lpp(int lpp, uint32_t (&acc)[GRP], 
   }
 }
 
+template <int MET>
 __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k_sample_grp_u8(Slot *__restrict__ slots, const uint8_t *__restrict__ X,
                                                       const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
                                                       int64_t mp, Bufs B, Geometry G) {
@@ -551,10 +573,11 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int mode = s_mode;
   if (mode < 0) return;
   const uint32_t run = s_run;
-  if (mode == 0 || (mode == 2 && m > 65536)) {
+  // (the exact round on the matrix cores is squared l2 only)
+  if (mode == 0 || (mode == 2 && (m > 65536 || MET == KNN_METRIC_L1))) {
     for (int g = 0; g < GRP; ++g)
       if (run & (1u << g))
-        sample_slot_chunk<KNN_U8, true, GBT>(&slots[g0 + g], g0 + g, (int64_t)blockIdx.y, X, B, G, smem);
+        sample_slot_chunk<KNN_U8, MET, true, GBT>(&slots[g0 + g], g0 + g, (int64_t)blockIdx.y, X, B, G, smem);
     return;
   }
   const int64_t base = (int64_t)blockIdx.y * G.ch_sample;
@@ -601,7 +624,7 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
           const uint32_t act = group_active(B, g0, n, i, run, impl);
           if (act) {  // uniform within the lanes of this point
             uint32_t acc[GRP];
-            point_sums(xt + (size_t)pt * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, s_norepl,
+            point_sums<MET>(xt + (size_t)pt * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, s_norepl,
                        acc);
             reduce_store_lpp(lpp, acc, lane, act, g0, n, i, cur, B);
             if (sub == 0) {
@@ -625,7 +648,7 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
         const uint32_t act = group_active(B, g0, n, i, run, impl);
         if (act == 0) continue;  // uniform within the lanes of this point
         uint32_t acc[GRP];
-        point_sums(X + (int64_t)i * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, s_norepl,
+        point_sums<MET>(X + (int64_t)i * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, s_norepl,
                    acc);
         reduce_store_lpp(lpp, acc, lane, act, g0, n, i, cur, B);
         if (sub == 0) {
@@ -724,7 +747,8 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
 // wave-uniform values and every lane loads the sixteen query bytes of its
 // slots at each coordinate from the transposed query matrix QT[j][slot]
 // (one coalesced 16-byte load per lane; the matrix stays in L2).  Per lane
-// the sums use the same x.x - 2 x.q + q.q dot4 form as the grouped kernel.
+// the sums use the same x.x - 2 x.q + q.q dot4 form as the grouped kernel
+// (for the l1 distance one v_sad_u8 per query and four draws).
 constexpr int QL_BT = 256;
 constexpr int QL_NW = QL_BT / kWave;
 constexpr int QL_SLOTS = 16 * kWave;  // slots served by one wave
@@ -806,6 +830,7 @@ __global__ __launch_bounds__(NT) void k_build_qt(const Slot *__restrict__ slots,
   }
 }
 
+template <int MET>
 __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__ slots, const uint8_t *__restrict__ X,
                                                         const uint8_t *__restrict__ QT, int32_t nqp,
                                                         const uint8_t *__restrict__ A, uint32_t *__restrict__ D,
@@ -882,7 +907,7 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
       };
       auto consume = [&](int d, const uint4 (&qv)[4]) {
         const uint32_t x4 = (uint32_t)__builtin_amdgcn_readlane((int)xv, d);
-        xx = __builtin_amdgcn_udot4(x4, x4, xx, false);
+        if constexpr (MET == KNN_METRIC_L2) xx = __builtin_amdgcn_udot4(x4, x4, xx, false);
         const uint32_t r[4][4] = {{qv[0].x, qv[1].x, qv[2].x, qv[3].x},
                                   {qv[0].y, qv[1].y, qv[2].y, qv[3].y},
                                   {qv[0].z, qv[1].z, qv[2].z, qv[3].z},
@@ -897,8 +922,12 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
                                  __builtin_amdgcn_perm(t3, t1, 0x05040100u), __builtin_amdgcn_perm(t3, t1, 0x07060302u)};
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            qq[4 * w + u] = __builtin_amdgcn_udot4(c[u], c[u], qq[4 * w + u], false);
-            xq[4 * w + u] = __builtin_amdgcn_udot4(x4, c[u], xq[4 * w + u], false);
+            if constexpr (MET == KNN_METRIC_L1) {
+              xq[4 * w + u] = __builtin_amdgcn_sad_u8(x4, c[u], xq[4 * w + u]);
+            } else {
+              qq[4 * w + u] = __builtin_amdgcn_udot4(c[u], c[u], qq[4 * w + u], false);
+              xq[4 * w + u] = __builtin_amdgcn_udot4(x4, c[u], xq[4 * w + u], false);
+            }
           }
         }
       };
@@ -923,7 +952,8 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
     if (has_q) {
       uint32_t t[GRP];
 #pragma unroll
-      for (int g = 0; g < GRP; ++g) t[g] = (act & (1u << g)) ? xx + qq[g] - 2u * xq[g] : QL_NONE;
+      for (int g = 0; g < GRP; ++g)
+        t[g] = (act & (1u << g)) ? (MET == KNN_METRIC_L1 ? xq[g] : xx + qq[g] - 2u * xq[g]) : QL_NONE;
 #pragma unroll
       for (int c = 0; c < 4; ++c) drow[c] = make_uint4(t[4 * c], t[4 * c + 1], t[4 * c + 2], t[4 * c + 3]);
     }
@@ -1398,7 +1428,7 @@ __global__ __launch_bounds__(MT) void k_cand_merge(Slot *__restrict__ slots, con
     if (a.fl[i] & FL_EXACT) continue;
     // m coordinates, or the m - T not yet sampled without replacement
     cost += sl->norepl ? m - (int64_t)sl->T[a.ri[i]] : m;
-    const int64_t tot = block_exact_sum<DT, MT>(X, m, i, q, F, red);
+    const int64_t tot = block_exact_sum<DT, MT>(X, m, i, q, F, G.metric, red);
     if (threadIdx.x == 0) {
       a.S[i] = tot;
       a.fl[i] = a.fl[i] | FL_EXACT;
@@ -1454,7 +1484,7 @@ __device__ void finalize(Slot *sl, int s, const QDesc &qd, const uint8_t *X, con
       const int32_t i = a.acc[t];
       if (a.fl[i] & FL_EXACT) continue;
       cost += sl->norepl ? m - (int64_t)sl->T[a.ri[i]] : m;
-      const int64_t tot = block_exact_sum<DT, MT>(X, m, i, q, sl->F, red);
+      const int64_t tot = block_exact_sum<DT, MT>(X, m, i, q, sl->F, G.metric, red);
       if (threadIdx.x == 0) {
         a.S[i] = tot;
         a.fl[i] = a.fl[i] | FL_EXACT;
@@ -1653,18 +1683,28 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
 // Host-side launchers (called from the runtime).
 namespace knn {
 
-template <int DT>
+template <int DT, int MET>
 static void launch_sample_dt(Slot *slots, const uint8_t *X, const Bufs &B, const Geometry &G, bool qlds,
                              size_t qbytes, hipStream_t st) {
   dim3 grid((unsigned)G.nslots, (unsigned)((G.n + G.ch_sample - 1) / G.ch_sample));
   if (qlds)
-    hipLaunchKernelGGL((k_sample<DT, true>), grid, dim3(NT), qbytes, st, slots, X, B, G);
+    hipLaunchKernelGGL((k_sample<DT, MET, true>), grid, dim3(NT), qbytes, st, slots, X, B, G);
   else
-    hipLaunchKernelGGL((k_sample<DT, false>), grid, dim3(NT), 0, st, slots, X, B, G);
+    hipLaunchKernelGGL((k_sample<DT, MET, false>), grid, dim3(NT), 0, st, slots, X, B, G);
 }
 
-void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, double hi, hipStream_t st) {
-  hipLaunchKernelGGL(k_prep_f32, dim3((unsigned)nq), dim3(NT), 0, st, qd, nq, n, m, lo, hi);
+template <int DT>
+static void launch_sample_met(Slot *slots, const uint8_t *X, const Bufs &B, const Geometry &G, bool qlds,
+                              size_t qbytes, hipStream_t st) {
+  if (G.metric == KNN_METRIC_L1)
+    launch_sample_dt<DT, KNN_METRIC_L1>(slots, X, B, G, qlds, qbytes, st);
+  else
+    launch_sample_dt<DT, KNN_METRIC_L2>(slots, X, B, G, qlds, qbytes, st);
+}
+
+void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, double hi, int32_t metric,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_prep_f32, dim3((unsigned)nq), dim3(NT), 0, st, qd, nq, n, m, lo, hi, metric);
 }
 
 // the exact round of query-lane batches (k_naive.hip: shares the scan's GEMM tile)
@@ -1696,14 +1736,14 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
   const size_t qbytes = (size_t)G.m * elem;
   const bool qlds = qbytes <= 48 * 1024;
   // exact round of a query-lane batch: one GEMM over (slots x points)
-  const bool ql_exact = ql && ql->exact && q8 && q8n && G.dtype == KNN_U8;
+  const bool ql_exact = ql && ql->exact && q8 && q8n && G.dtype == KNN_U8 && G.metric == KNN_METRIC_L2;
   if (ql_exact) {
     const int tk = prof_begin(PROF_EXACT, st);
     launch_exact_ql_u8(slots, q8, q8n, G.x8, G.xn, B, G, ql->cur, ql->impl, st);
     prof_end(tk, st, 0.0);
     ql = nullptr;  // the rest of the step as usual
   }
-  const bool use_ql = ql && qt && qd_buf && G.dtype == KNN_U8;
+  const bool use_ql = ql && !ql->exact && qt && qd_buf && G.dtype == KNN_U8;
   // fold and selection in one pass (candidate-exact must run between them)
   const bool fused_sel = use_ql && !any_cexact && G.kmax + 1 <= kWave;
   int tok = (use_ql || ql_exact) ? -1 : prof_begin(sample_kind == 1 ? PROF_EXACT : PROF_SAMPLE, st);
@@ -1720,7 +1760,12 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
       prof_end(tok, st, 0.0);
     }
     tok = prof_begin(PROF_SAMPLE, st);
-    hipLaunchKernelGGL(k_sample_ql_u8, dim3(bx, by), dim3(QL_BT), 0, st, slots, X, qt, nqp, A, qd_buf, B, G, *ql);
+    if (G.metric == KNN_METRIC_L1)
+      hipLaunchKernelGGL(k_sample_ql_u8<KNN_METRIC_L1>, dim3(bx, by), dim3(QL_BT), 0, st, slots, X, qt, nqp, A, qd_buf,
+                         B, G, *ql);
+    else
+      hipLaunchKernelGGL(k_sample_ql_u8<KNN_METRIC_L2>, dim3(bx, by), dim3(QL_BT), 0, st, slots, X, qt, nqp, A, qd_buf,
+                         B, G, *ql);
     prof_end(tok, st, 0.0);
     if (fused_sel) {
       tok = prof_begin(PROF_SELECT, st);
@@ -1736,17 +1781,22 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
       gbytes = std::max<size_t>(gbytes, (size_t)GRP * G.mp + (size_t)G.stage * G.m);
       static bool attr_set = false;
       if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sample_grp_u8),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sample_grp_u8<KNN_METRIC_L2>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sample_grp_u8<KNN_METRIC_L1>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
         attr_set = true;
       }
     }
     dim3 grid((unsigned)((G.nslots + GRP - 1) / GRP), (unsigned)((G.n + G.ch_sample - 1) / G.ch_sample));
-    hipLaunchKernelGGL(k_sample_grp_u8, grid, dim3(GBT), gbytes, st, slots, X, G.x8, G.xn, G.mp, B, G);
+    if (G.metric == KNN_METRIC_L1)
+      hipLaunchKernelGGL(k_sample_grp_u8<KNN_METRIC_L1>, grid, dim3(GBT), gbytes, st, slots, X, G.x8, G.xn, G.mp, B, G);
+    else
+      hipLaunchKernelGGL(k_sample_grp_u8<KNN_METRIC_L2>, grid, dim3(GBT), gbytes, st, slots, X, G.x8, G.xn, G.mp, B, G);
   } else if (G.dtype == KNN_U8) {
-    launch_sample_dt<KNN_U8>(slots, X, B, G, qlds, qbytes, st);
+    launch_sample_met<KNN_U8>(slots, X, B, G, qlds, qbytes, st);
   } else {
-    launch_sample_dt<KNN_F32>(slots, X, B, G, qlds, qbytes, st);
+    launch_sample_met<KNN_F32>(slots, X, B, G, qlds, qbytes, st);
   }
   prof_end(tok, st, 0.0);
   const unsigned ns = (unsigned)G.nslots;

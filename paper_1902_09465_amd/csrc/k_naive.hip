@@ -8,6 +8,10 @@
 //     query are kept in LDS while the tile loop streams the points
 //     (fused epilogue, the n-by-nq distance matrix is never stored).
 // f32: split-BF16 MFMA with an error bound and FP64 rescoring (k_naive_f32.hip).
+// l1 distance (sum_j |x_j - q_j|; no product form, so no matrix cores): the
+//     same tiles and top-k epilogue, with the tile's distances summed by
+//     v_sad_u8 (four absolute differences and their sum per instruction) from
+//     zero-padded u8 rows; exact in integers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -85,8 +89,31 @@ int db_range_f32(const float *X, int64_t count, double *lo, double *hi, hipStrea
   return KNN_OK;
 }
 
+// l1: rows copied with zero padding to mp elements (elem bytes each); the
+// padding adds |0 - 0| = 0 to every distance.
+__global__ __launch_bounds__(256) void k_pad_rows(const uint8_t *__restrict__ X, int64_t rows, int64_t m,
+                                                  int64_t mp, int elem, uint8_t *__restrict__ out) {
+  const int64_t r = blockIdx.x;
+  if (r >= rows) return;
+  const int64_t rb = m * elem, pb = mp * elem;
+  for (int64_t b = threadIdx.x; b < pb; b += 256) out[r * pb + b] = b < rb ? X[r * rb + b] : (uint8_t)0;
+}
+
+void launch_pad_rows(const uint8_t *X, int64_t rows, int64_t m, int64_t mp, int elem, uint8_t *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)rows), dim3(256), 0, st, X, rows, m, mp, elem, out);
+}
+
 int naive_prepare_db(knn_db_s *db, hipStream_t st) {
   db->mp = (db->m + 63) / 64 * 64;
+  if (db->metric == KNN_METRIC_L1) {
+    const int elem = db->dtype == KNN_U8 ? 1 : 4;
+    HIP_TRY(hipMalloc(&db->xpad, (size_t)db->n * db->mp * elem));
+    hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)db->n), dim3(256), 0, st, db->X, db->n, db->m, db->mp, elem,
+                       (uint8_t *)db->xpad);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return KNN_OK;
+  }
   if (db->dtype == KNN_U8) {
     HIP_TRY(hipMalloc(&db->xs8, (size_t)db->n * db->mp));
     HIP_TRY(hipMalloc(&db->norm_i, sizeof(int32_t) * db->n));
@@ -105,6 +132,8 @@ void naive_free_db(knn_db_s *db) {
   if (db->xbf) (void)hipFree(db->xbf);
   if (db->norm_f) (void)hipFree(db->norm_f);
   if (db->rownorm) (void)hipFree(db->rownorm);
+  if (db->xpad) (void)hipFree(db->xpad);
+  db->xpad = nullptr;
   db->xs8 = nullptr;
   db->norm_i = nullptr;
   db->xbf = nullptr;
@@ -135,117 +164,17 @@ __global__ __launch_bounds__(256) void k_prep_u8_queries(const uint8_t *__restri
 
 constexpr int NBQ = 64;    // queries per block tile
 constexpr int NBP = 128;   // points per block tile
-constexpr int NKS = 64;    // k-step (bytes of K per MFMA)
-constexpr int ROWB = 80;   // LDS row stride in bytes (64 + 16 pad)
-constexpr int DSTR = NBP + 4;
+constexpr int DSTR = NBP + 4;  // row stride (4-byte words) of a tile's distances in LDS
 
-template <int KC>
-__global__ __launch_bounds__(256) void k_naive_u8(const int8_t *__restrict__ Q8, const int32_t *__restrict__ qn,
-                                                  const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
-                                                  int64_t nq, int64_t n, int64_t mp, int k, int64_t prange,
-                                                  uint64_t *__restrict__ part, int64_t nranges) {
-  // the GEMM tiles and the distance tile are never live at the same time
-  __shared__ __align__(16) uint8_t tiles[NBQ * DSTR * 4];
-  static_assert((NBQ + NBP) * ROWB <= NBQ * DSTR * 4, "tile union too small");
-  int8_t *As = reinterpret_cast<int8_t *>(tiles);
-  int8_t *Bs = As + NBQ * ROWB;
-  uint32_t *Ds = reinterpret_cast<uint32_t *>(tiles);
-  __shared__ uint64_t L[NBQ * KC];
-  __shared__ uint64_t Tau[NBQ];
-  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-  const int64_t q0 = (int64_t)blockIdx.y * NBQ;
-  const int64_t pr0 = (int64_t)blockIdx.x * prange;
-  const int64_t pr1 = std::min(n, pr0 + prange);
-  // sentinel list entries: unique keys above every real key
-  for (int j = tid; j < NBQ * KC; j += 256) L[j] = ~0ull - (uint64_t)(j % KC);
-  const int wq = wave >> 1, wp = wave & 1;
-  for (int j = tid; j < NBQ; j += 256) Tau[j] = ~0ull;
-  __syncthreads();
-  for (int64_t p0 = pr0; p0 < pr1; p0 += NBP) {
-    v4i acc[2][4];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
-    for (int64_t k0 = 0; k0 < mp; k0 += NKS) {
-      {  // A: 64 rows x 64 B, one 16 B piece per thread
-        const int r = tid >> 2, c = (tid & 3) * 16;
-        v4i v = v4i{0, 0, 0, 0};
-        if (q0 + r < nq) v = *reinterpret_cast<const v4i *>(Q8 + (q0 + r) * mp + k0 + c);
-        *reinterpret_cast<v4i *>(As + r * ROWB + c) = v;
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {  // B: 128 rows x 64 B
-        const int r = (tid >> 2) + 64 * h, c = (tid & 3) * 16;
-        v4i v = v4i{0, 0, 0, 0};
-        if (p0 + r < pr1) v = *reinterpret_cast<const v4i *>(X8 + (p0 + r) * mp + k0 + c);
-        *reinterpret_cast<v4i *>(Bs + r * ROWB + c) = v;
-      }
-      __syncthreads();
-      v4i af[2], bf[4];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-        af[a] = *reinterpret_cast<const v4i *>(As + (32 * wq + 16 * a + (lane & 15)) * ROWB + 16 * (lane >> 4));
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        bf[b] = *reinterpret_cast<const v4i *>(Bs + (64 * wp + 16 * b + (lane & 15)) * ROWB + 16 * (lane >> 4));
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
-      __syncthreads();
-    }
-    // epilogue: distances of the tile into LDS
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
-          const int pl = 64 * wp + 16 * b + (lane & 15);
-          uint32_t d = 0xFFFFFFFFu;
-          if (p0 + pl < pr1 && q0 + ql < nq) {
-            const int64_t dd = (int64_t)qn[q0 + ql] + (int64_t)xn[p0 + pl] - 2 * (int64_t)acc[a][b][v];
-            d = (uint32_t)dd;
-          }
-          Ds[ql * DSTR + pl] = d;
-        }
-    __syncthreads();
-    // per-query top-k, wave `wave` owns queries [16 wave, 16 wave + 16)
-#pragma unroll 1
-    for (int t = 0; t < NBQ / 4; ++t) {
-      const int ql = wave * (NBQ / 4) + t;
-      if (q0 + ql >= nq) break;
-      const uint32_t d0 = Ds[ql * DSTR + lane], d1 = Ds[ql * DSTR + lane + 64];
-      const uint64_t c0 = d0 == 0xFFFFFFFFu ? ~0ull : (((uint64_t)d0 << 32) | (uint64_t)(p0 + lane));
-      const uint64_t c1 = d1 == 0xFFFFFFFFu ? ~0ull : (((uint64_t)d1 << 32) | (uint64_t)(p0 + lane + 64));
-      uint64_t tau = Tau[ql];
-      topk_insert<KC>(L + ql * KC, k, tau, c0, c1);
-      if (lane == 0) Tau[ql] = tau;
-    }
-    __syncthreads();
-  }
-  // the block's k smallest per query -> part[q][range][k]
-  for (int t = 0; t < NBQ / 4; ++t) {
-    const int ql = wave * (NBQ / 4) + t;
-    if (q0 + ql >= nq) break;
-    uint64_t *dst = part + ((q0 + ql) * nranges + blockIdx.x) * (int64_t)k;
-    for (int j = lane; j < k; j += 64) dst[j] = L[ql * KC + j];
-  }
+
+// Distance of one tile entry: |q'|^2 + |x'|^2 - 2 x'.q' (squared l2; below
+// 2^32 for m <= 65536) or the l1 sum itself.
+template <int MET>
+__device__ __forceinline__ uint32_t tile_dist(const int32_t *qn, const int32_t *xn, int64_t q, int64_t p, int acc) {
+  if constexpr (MET == KNN_METRIC_L1) return (uint32_t)acc;
+  return (uint32_t)((int64_t)qn[q] + (int64_t)xn[p] - 2 * (int64_t)acc);
 }
 
-// Same scan for k <= 64, restructured for throughput:
-//  * the K loop is double-buffered: the next 128-byte slice of the query
-//    and point tiles is loaded into registers while the matrix cores work
-//    on the current one from LDS (one barrier per slice);
-//  * the per-query k smallest live in registers, one sorted list per query
-//    spread over the lanes of the wave that owns it (lane j holds the j-th
-//    smallest).  A tile's distances are filtered against the list's k-th
-//    key and the few that pass are appended to a per-query LDS buffer; the
-//    buffer is merged into the list by a wave sort when it would overflow
-//    and at the end of the block (sort, reverse, take the smaller of each
-//    pair, bitonic clean-up: the 64 smallest of both, sorted).
 constexpr int BK = 128;                 // bytes of K per pipeline stage
 constexpr int BROW = BK + 16;           // LDS row stride of a stage
 constexpr int STAGE = (NBQ + NBP) * BROW;
@@ -272,11 +201,16 @@ __device__ __forceinline__ uint64_t merge_sorted64(uint64_t list, uint64_t cand)
   return v;
 }
 
-// One block's 64 x 128 tile of x'.q' (queries q0.., points p0..) over
-// the whole K range, into the MFMA accumulators: the K loop is
-// double-buffered (the next 128-byte slice is loaded into registers while the
-// matrix cores work on the current one from LDS; one barrier per slice).
-// Rows beyond nq / pend read as zeros.  smem: 2 x STAGE bytes.
+// One block's 64 x 128 tile (queries q0.., points p0..) over the whole K
+// range: x'.q' on the matrix cores (MET = squared l2, shifted int8 rows), or
+// the l1 distance sum_j |x_j - q_j| by v_sad_u8 (MET = l1, zero-padded u8
+// rows).  Either way lane l of wave w = 2 wq + wp ends with the value of
+// query 32 wq + 16 a + 4 (l / 16) + v and point 64 wp + 16 b + l % 16 in
+// acc[a][b][v] (the MFMA output layout).  The K loop is double-buffered: the
+// next 128-byte slice is loaded into registers while the current one is
+// consumed from LDS (one barrier per slice).  Rows beyond nq / pend read as
+// zeros.  smem: 2 x STAGE bytes.
+template <int MET>
 __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int64_t nq, const int8_t *__restrict__ X8,
                                              int64_t q0, int64_t p0, int64_t pr1, int64_t mp, uint8_t *smem,
                                              v4i (&acc)[2][4]) {
@@ -320,6 +254,33 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
   auto compute = [&](int buf, int width) {
     const int8_t *As = reinterpret_cast<const int8_t *>(smem) + buf * STAGE;
     const int8_t *Bs = As + NBQ * BROW;
+    if constexpr (MET == KNN_METRIC_L1) {
+      // 16 bytes of K at a time: the lane's 8 query rows and 4 point rows,
+      // then 8 x 4 x 4 sums of absolute differences
+      for (int kk = 0; kk < width; kk += 16) {
+        v4i qv[2][4], pv[4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            qv[a][v] = *reinterpret_cast<const v4i *>(As + (32 * wq + 16 * a + 4 * (lane >> 4) + v) * BROW + kk);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          pv[b] = *reinterpret_cast<const v4i *>(Bs + (64 * wp + 16 * b + (lane & 15)) * BROW + kk);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              uint32_t t = (uint32_t)acc[a][b][v];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) t = __builtin_amdgcn_sad_u8((uint32_t)qv[a][v][e], (uint32_t)pv[b][e], t);
+              acc[a][b][v] = (int)t;
+            }
+      }
+      return;
+    }
     for (int kk = 0; kk < width; kk += 64) {
       v4i af[2], bf[4];
 #pragma unroll
@@ -351,6 +312,18 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
   }
 }
 
+// The scan for k <= 64:
+//  * the K loop is double-buffered: the next 128-byte slice of the query
+//    and point tiles is loaded into registers while the current one is
+//    consumed from LDS (one barrier per slice);
+//  * the per-query k smallest live in registers, one sorted list per query
+//    spread over the lanes of the wave that owns it (lane j holds the j-th
+//    smallest).  A tile's distances are filtered against the list's k-th
+//    key and the few that pass are appended to a per-query LDS buffer; the
+//    buffer is merged into the list by a wave sort when it would overflow
+//    and at the end of the block (sort, reverse, take the smaller of each
+//    pair, bitonic clean-up: the 64 smallest of both, sorted).
+template <int MET>
 __global__ __launch_bounds__(256) void k_naive_u8_k64(const int8_t *__restrict__ Q8, const int32_t *__restrict__ qn,
                                                       const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
                                                       int64_t nq, int64_t n, int64_t mp, int k, int64_t prange,
@@ -376,7 +349,7 @@ __global__ __launch_bounds__(256) void k_naive_u8_k64(const int8_t *__restrict__
   }
   for (int64_t p0 = pr0; p0 < pr1; p0 += NBP) {
     v4i acc[2][4];
-    gemm_u8_tile(Q8, nq, X8, q0, p0, pr1, mp, smem, acc);
+    gemm_u8_tile<MET>(Q8, nq, X8, q0, p0, pr1, mp, smem, acc);
     // distances of the tile into LDS (the stage buffers are free now)
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -387,10 +360,7 @@ __global__ __launch_bounds__(256) void k_naive_u8_k64(const int8_t *__restrict__
           const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
           const int pl = 64 * wp + 16 * b + (lane & 15);
           uint32_t d = 0xFFFFFFFFu;
-          if (p0 + pl < pr1 && q0 + ql < nq) {
-            const int64_t dd = (int64_t)qn[q0 + ql] + (int64_t)xn[p0 + pl] - 2 * (int64_t)acc[a][b][v];
-            d = (uint32_t)dd;
-          }
+          if (p0 + pl < pr1 && q0 + ql < nq) d = tile_dist<MET>(qn, xn, q0 + ql, p0 + pl, acc[a][b][v]);
           Ds[ql * DSTR + pl] = d;
         }
     __syncthreads();
@@ -431,6 +401,66 @@ __global__ __launch_bounds__(256) void k_naive_u8_k64(const int8_t *__restrict__
   }
 }
 
+// The scan for 64 < k <= KC: per-query sorted lists of KC keys in LDS,
+// filled by topk_insert from each tile's distances.
+template <int KC, int MET>
+__global__ __launch_bounds__(256) void k_naive_u8(const int8_t *__restrict__ Q8, const int32_t *__restrict__ qn,
+                                                  const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
+                                                  int64_t nq, int64_t n, int64_t mp, int k, int64_t prange,
+                                                  uint64_t *__restrict__ part, int64_t nranges) {
+  // the pipeline stages and the distance tile are never live at the same time
+  __shared__ __align__(16) uint8_t smem[2 * STAGE > NBQ * DSTR * 4 ? 2 * STAGE : NBQ * DSTR * 4];
+  uint32_t *Ds = reinterpret_cast<uint32_t *>(smem);
+  __shared__ uint64_t L[NBQ * KC];
+  __shared__ uint64_t Tau[NBQ];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int64_t q0 = (int64_t)blockIdx.y * NBQ;
+  const int64_t pr0 = (int64_t)blockIdx.x * prange;
+  const int64_t pr1 = std::min(n, pr0 + prange);
+  // sentinel list entries: unique keys above every real key
+  for (int j = tid; j < NBQ * KC; j += 256) L[j] = ~0ull - (uint64_t)(j % KC);
+  const int wq = wave >> 1, wp = wave & 1;
+  for (int j = tid; j < NBQ; j += 256) Tau[j] = ~0ull;
+  __syncthreads();
+  for (int64_t p0 = pr0; p0 < pr1; p0 += NBP) {
+    v4i acc[2][4];
+    gemm_u8_tile<MET>(Q8, nq, X8, q0, p0, pr1, mp, smem, acc);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+          const int pl = 64 * wp + 16 * b + (lane & 15);
+          uint32_t d = 0xFFFFFFFFu;
+          if (p0 + pl < pr1 && q0 + ql < nq) d = tile_dist<MET>(qn, xn, q0 + ql, p0 + pl, acc[a][b][v]);
+          Ds[ql * DSTR + pl] = d;
+        }
+    __syncthreads();
+    // per-query top-k, wave `wave` owns queries [16 wave, 16 wave + 16)
+#pragma unroll 1
+    for (int t = 0; t < NBQ / 4; ++t) {
+      const int ql = wave * (NBQ / 4) + t;
+      if (q0 + ql >= nq) break;
+      const uint32_t d0 = Ds[ql * DSTR + lane], d1 = Ds[ql * DSTR + lane + 64];
+      const uint64_t c0 = d0 == 0xFFFFFFFFu ? ~0ull : (((uint64_t)d0 << 32) | (uint64_t)(p0 + lane));
+      const uint64_t c1 = d1 == 0xFFFFFFFFu ? ~0ull : (((uint64_t)d1 << 32) | (uint64_t)(p0 + lane + 64));
+      uint64_t tau = Tau[ql];
+      topk_insert<KC>(L + ql * KC, k, tau, c0, c1);
+      if (lane == 0) Tau[ql] = tau;
+    }
+    __syncthreads();
+  }
+  // the block's k smallest per query -> part[q][range][k]
+  for (int t = 0; t < NBQ / 4; ++t) {
+    const int ql = wave * (NBQ / 4) + t;
+    if (q0 + ql >= nq) break;
+    uint64_t *dst = part + ((q0 + ql) * nranges + blockIdx.x) * (int64_t)k;
+    for (int j = lane; j < k; j += 64) dst[j] = L[ql * KC + j];
+  }
+}
+
 // ---------------------------------------------------------------- exact round, query-lane batches
 
 // Shifted int8 copies of the running slots' queries, padded to mp, and their
@@ -468,7 +498,7 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
   const int64_t q0 = (int64_t)blockIdx.y * NBQ;
   const int64_t pend = std::min(n, p0 + NBP);
   v4i acc[2][4];
-  gemm_u8_tile(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);
+  gemm_u8_tile<KNN_METRIC_L2>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);
   const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
   uint64_t my_pairs = 0;
 #pragma unroll
@@ -545,17 +575,25 @@ __global__ __launch_bounds__(1024) void k_naive_merge(const uint64_t *__restrict
   }
 }
 
-template <int KC>
-static void launch_naive_u8(const int8_t *Q8, const int32_t *qn, const knn_db_s *db, int64_t nq, int k,
-                            int64_t prange, uint64_t *part, int64_t nranges, hipStream_t st) {
+template <int KC, int MET>
+static void launch_naive_u8(const int8_t *Q8, const int32_t *qn, const int8_t *X8, const int32_t *xn,
+                            const knn_db_s *db, int64_t nq, int k, int64_t prange, uint64_t *part, int64_t nranges,
+                            hipStream_t st) {
   dim3 grid((unsigned)nranges, (unsigned)((nq + NBQ - 1) / NBQ));
-  hipLaunchKernelGGL(k_naive_u8<KC>, grid, dim3(256), 0, st, Q8, qn, db->xs8, db->norm_i, nq, db->n, db->mp, k,
-                     prange, part, nranges);
+  if (k <= 64)
+    hipLaunchKernelGGL(k_naive_u8_k64<MET>, grid, dim3(256), 0, st, Q8, qn, X8, xn, nq, db->n, db->mp, k, prange, part,
+                       nranges);
+  else
+    hipLaunchKernelGGL((k_naive_u8<KC, MET>), grid, dim3(256), 0, st, Q8, qn, X8, xn, nq, db->n, db->mp, k, prange,
+                       part, nranges);
 }
 
 static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
                     hipStream_t st) {
-  if (db->m > 65536) return fail(KNN_EINVAL, "naive u8 scan supports m <= 65536");
+  const bool l1 = db->metric == KNN_METRIC_L1;
+  // squared l2 distances below 2^32 (and exact int32 MFMA sums); l1 sums below 2^32
+  if (!l1 && db->m > 65536) return fail(KNN_EINVAL, "naive u8 scan supports m <= 65536");
+  if (l1 && db->m > 16777216) return fail(KNN_EINVAL, "naive u8 l1 scan supports m <= 2^24");
   if (k > 128) return fail(KNN_EINVAL, "naive u8 scan supports k <= 128");
   const int64_t n = db->n, mp = db->mp;
   const int64_t qt = (nq + NBQ - 1) / NBQ;
@@ -575,15 +613,19 @@ static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int6
   int32_t *qn = (int32_t *)((uint8_t *)ws + bytes_q);
   uint64_t *part = (uint64_t *)((uint8_t *)ws + bytes_q + bytes_qn);
   int tok = prof_begin(PROF_NAIVE_REST, st);
-  hipLaunchKernelGGL(k_prep_u8_queries, dim3((unsigned)nq), dim3(256), 0, st, dq, db->m, mp, Q8, qn);
+  if (l1)  // zero-padded u8 query rows
+    hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)nq), dim3(256), 0, st, dq, nq, db->m, mp, 1, (uint8_t *)Q8);
+  else
+    hipLaunchKernelGGL(k_prep_u8_queries, dim3((unsigned)nq), dim3(256), 0, st, dq, db->m, mp, Q8, qn);
   prof_end(tok, st, 0.0);
   tok = prof_begin(PROF_NAIVE_GEMM, st);
-  if (k <= 64) {
-    dim3 grid((unsigned)nranges, (unsigned)((nq + NBQ - 1) / NBQ));
-    hipLaunchKernelGGL(k_naive_u8_k64, grid, dim3(256), 0, st, Q8, qn, db->xs8, db->norm_i, nq, n, mp, k, prange,
-                       part, nranges);
-  } else
-    launch_naive_u8<128>(Q8, qn, db, nq, k, prange, part, nranges, st);
+  if (l1)
+    launch_naive_u8<128, KNN_METRIC_L1>(Q8, nullptr, (const int8_t *)db->xpad, nullptr, db, nq, k, prange, part,
+                                        nranges, st);
+  else
+    launch_naive_u8<128, KNN_METRIC_L2>(Q8, qn, db->xs8, db->norm_i, db, nq, k, prange, part, nranges, st);
+  // work units: 2 operations per (query, point, coordinate) -- a multiply-add,
+  // or an absolute difference and its addition
   prof_end(tok, st, 2.0 * (double)nq * (double)n * (double)db->m);
   tok = prof_begin(PROF_NAIVE_REST, st);
   hipLaunchKernelGGL(k_naive_merge, dim3((unsigned)nq), dim3(1024), 0, st, part, nranges, k, out_idx, out_dist);

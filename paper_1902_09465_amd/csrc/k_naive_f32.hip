@@ -17,6 +17,11 @@
 // 4. Candidates (l <= tau) are rescored in FP64, summing (x_j - q_j)^2 in
 //    coordinate order like the CPU reference, and the k smallest by
 //    (distance, index) are returned.
+// The l1 distance has no product form: its tile sums |x_j - q_j| in fp32 on
+// the vector ALUs from zero-padded rows (each lane adds its pairs' terms in
+// coordinate order), with the relative bound |d~ - d| <= c1 d~ (m terms,
+// each rounded twice: c1 = 2 (m + 2) 2^-24, doubled for safety), and the same
+// candidate lists, completeness check and FP64 rescoring (sum of |x_j - q_j|).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -79,6 +84,7 @@ constexpr int FBQ = 64, FBP = 128, FROWB = 80, FDSTR = FBP + 4;
 constexpr int KCU = 64;  // upper-bound list capacity (k <= 64)
 constexpr int KCL = 64;  // lower-bound list capacity per range
 
+template <int MET>
 __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ Qh, const uint16_t *__restrict__ Ql,
                                                    const float *__restrict__ qn, const float *__restrict__ qr,
                                                    const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xl,
@@ -111,6 +117,50 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = v4f_f{0.f, 0.f, 0.f, 0.f};
+    if constexpr (MET == KNN_METRIC_L1) {
+      // Qh / Xh hold zero-padded f32 rows here; 16 floats = 64 bytes per row per step
+      const float *Qf = reinterpret_cast<const float *>(Qh), *Xf = reinterpret_cast<const float *>(Xh);
+      for (int64_t k0 = 0; k0 < mp; k0 += 16) {
+        {
+          const int r = tid >> 2, c = (tid & 3) * 4;
+          v4f_f v = v4f_f{0.f, 0.f, 0.f, 0.f};
+          if (q0 + r < nq) v = *reinterpret_cast<const v4f_f *>(Qf + (q0 + r) * mp + k0 + c);
+          *reinterpret_cast<v4f_f *>(Ah + r * FROWB + 4 * c) = v;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = (tid >> 2) + 64 * h, c = (tid & 3) * 4;
+          v4f_f v = v4f_f{0.f, 0.f, 0.f, 0.f};
+          if (p0 + r < pr1) v = *reinterpret_cast<const v4f_f *>(Xf + (p0 + r) * mp + k0 + c);
+          *reinterpret_cast<v4f_f *>(Bh + r * FROWB + 4 * c) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          v4f_f qv[2][4], pv[4];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              qv[a][v] = *reinterpret_cast<const v4f_f *>(Ah + (32 * wq + 16 * a + 4 * (lane >> 4) + v) * FROWB + 4 * kk);
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            pv[b] = *reinterpret_cast<const v4f_f *>(Bh + (64 * wp + 16 * b + (lane & 15)) * FROWB + 4 * kk);
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                float t = acc[a][b][v];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) t += fabsf(qv[a][v][e] - pv[b][e]);
+                acc[a][b][v] = t;
+              }
+        }
+        __syncthreads();
+      }
+    } else
     for (int64_t k0 = 0; k0 < mp; k0 += 32) {  // 32 bf16 = 64 bytes per row per step
       {
         const int r = tid >> 2, c = (tid & 3) * 16;
@@ -167,7 +217,8 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
           const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
           const int pl = 64 * wp + 16 * b + (lane & 15);
           float d = 0.0f;
-          if (p0 + pl < pr1 && q0 + ql < nq) d = (qn[q0 + ql] + xn[p0 + pl]) - 2.0f * acc[a][b][v];
+          if (p0 + pl < pr1 && q0 + ql < nq)
+            d = MET == KNN_METRIC_L1 ? acc[a][b][v] : (qn[q0 + ql] + xn[p0 + pl]) - 2.0f * acc[a][b][v];
           Ds[ql * FDSTR + pl] = d;
         }
     __syncthreads();
@@ -175,7 +226,7 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
     for (int t = 0; t < FBQ / 4; ++t) {
       const int ql = wave * (FBQ / 4) + t;
       if (q0 + ql >= nq) break;
-      const float qnv = qn[q0 + ql], qrv = qr[q0 + ql];
+      const float qnv = MET == KNN_METRIC_L1 ? 0.0f : qn[q0 + ql], qrv = MET == KNN_METRIC_L1 ? 0.0f : qr[q0 + ql];
       uint64_t cu[2], cl[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -183,7 +234,7 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
         const int64_t p = p0 + pl;
         if (p < pr1) {
           const float d = Ds[ql * FDSTR + pl];
-          const float E = c1 * qrv * xr[p] + c2 * (qnv + xn[p]);
+          const float E = MET == KNN_METRIC_L1 ? c1 * d : c1 * qrv * xr[p] + c2 * (qnv + xn[p]);
           cu[h] = ((uint64_t)fkey(d + E) << 32) | (uint64_t)p;
           cl[h] = ((uint64_t)fkey(d - E) << 32) | (uint64_t)p;
         } else {
@@ -210,11 +261,16 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
   }
 }
 
-// Exact FP64 distance of point i, coordinates in order (no FMA contraction).
+// Exact FP64 distance of point i (squared l2 or l1), coordinates in order
+// (no FMA contraction).
 __device__ __forceinline__ double exact_f64(const float *__restrict__ X, const float *__restrict__ q, int64_t m,
-                                            int64_t i) {
+                                            int64_t i, int met) {
   const float *row = X + i * m;
   double s = 0.0;
+  if (met == KNN_METRIC_L1) {
+    for (int64_t j = 0; j < m; ++j) s += fabs((double)row[j] - (double)q[j]);
+    return s;
+  }
   for (int64_t j = 0; j < m; ++j) {
     const double d = (double)row[j] - (double)q[j];
     s += d * d;
@@ -226,7 +282,7 @@ constexpr int FCAP = 2048;  // candidate capacity per query in the merge
 
 __global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__restrict__ part, int64_t nranges, int k,
                                                           const float *__restrict__ X, const float *__restrict__ Q,
-                                                          int64_t m, int64_t *__restrict__ out_idx,
+                                                          int64_t m, int met, int64_t *__restrict__ out_idx,
                                                           double *__restrict__ out_dist, int32_t *__restrict__ flag) {
   const int64_t q = blockIdx.x;
   const int64_t w = k + KCL;
@@ -273,7 +329,7 @@ __global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__rest
   }
   const int c = cnt;
   const float *qv = Q + q * m;
-  for (int t = threadIdx.x; t < c; t += 1024) key[t] = dkey(exact_f64(X, qv, m, id[t]));
+  for (int t = threadIdx.x; t < c; t += 1024) key[t] = dkey(exact_f64(X, qv, m, id[t], met));
   __syncthreads();
   int len = 1;
   while (len < c) len <<= 1;
@@ -291,13 +347,14 @@ __global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__rest
 
 // Exact FP64 scan of one query (used when a candidate list may be incomplete).
 __global__ __launch_bounds__(1024) void k_naive_f32_full(const float *__restrict__ X, const float *__restrict__ Q,
-                                                         int64_t n, int64_t m, int k, const int32_t *__restrict__ qids,
+                                                         int64_t n, int64_t m, int met, int k,
+                                                         const int32_t *__restrict__ qids,
                                                          double *__restrict__ scratch, int64_t *__restrict__ out_idx,
                                                          double *__restrict__ out_dist) {
   const int64_t q = qids[blockIdx.x];
   double *dd = scratch + (int64_t)blockIdx.x * n;
   const float *qv = Q + q * m;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) dd[i] = exact_f64(X, qv, m, i);
+  for (int64_t i = threadIdx.x; i < n; i += 1024) dd[i] = exact_f64(X, qv, m, i, met);
   __syncthreads();
   __shared__ SelScratch ss;
   __shared__ uint64_t key[kMaxKH];
@@ -348,6 +405,7 @@ int naive_prepare_db_f32(knn_db_s *db, hipStream_t st) {
 int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
               hipStream_t st) {
   if (k > KCU) return fail(KNN_EINVAL, "naive f32 scan supports k <= 64");
+  const bool l1 = db->metric == KNN_METRIC_L1;
   const int64_t n = db->n, m = db->m, mp = db->mp;
   const size_t cells = (size_t)n * mp;
   const int64_t qt = (nq + FBQ - 1) / FBQ;
@@ -356,7 +414,7 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
   const int64_t nranges = (n + prange - 1) / prange;
   // error-bound constants (doubled for safety, see the file header)
   const double u16 = 1.0 / 65536.0, u24 = 1.0 / 16777216.0;
-  const float c1 = (float)(2.0 * 2.0 * (3.01 * u16 + 3.1 * (double)m * u24));
+  const float c1 = l1 ? (float)(2.0 * ((double)m + 2.0) * u24) : (float)(2.0 * 2.0 * (3.01 * u16 + 3.1 * (double)m * u24));
   const float c2 = (float)(8.0 * u24);
   const size_t b_qs = (size_t)nq * mp * 2 * 2, b_qn = sizeof(float) * nq * 2 + 512,
                b_part = sizeof(uint64_t) * nq * nranges * (k + KCL), b_flag = sizeof(int32_t) * nq + 256;
@@ -367,15 +425,25 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
   uint64_t *part = (uint64_t *)((uint8_t *)ws + b_qs + b_qn);
   int32_t *flag = (int32_t *)((uint8_t *)ws + b_qs + b_qn + b_part);
   int tok = prof_begin(PROF_NAIVE_REST, st);
-  hipLaunchKernelGGL(k_split_rows, dim3((unsigned)nq), dim3(256), 0, st, dq, nq, m, mp, Qh, Ql, qn, qr);
+  if (l1)  // zero-padded f32 query rows (nq x mp x 4 bytes, the size of the split pair)
+    launch_pad_rows(reinterpret_cast<const uint8_t *>(dq), nq, m, mp, 4, reinterpret_cast<uint8_t *>(Qh), st);
+  else
+    hipLaunchKernelGGL(k_split_rows, dim3((unsigned)nq), dim3(256), 0, st, dq, nq, m, mp, Qh, Ql, qn, qr);
   prof_end(tok, st, 0.0);
   tok = prof_begin(PROF_NAIVE_GEMM, st);
-  hipLaunchKernelGGL(k_naive_f32, dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st, Qh, Ql, qn, qr,
-                     db->xbf, db->xbf + cells, db->norm_f, db->rownorm, nq, n, mp, k, prange, c1, c2, part, nranges);
-  prof_end(tok, st, 3.0 * 2.0 * (double)nq * (double)n * (double)m);
+  if (l1)
+    hipLaunchKernelGGL(k_naive_f32<KNN_METRIC_L1>, dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st, Qh,
+                       nullptr, nullptr, nullptr, reinterpret_cast<const uint16_t *>(db->xpad), nullptr, nullptr,
+                       nullptr, nq, n, mp, k, prange, c1, c2, part, nranges);
+  else
+    hipLaunchKernelGGL(k_naive_f32<KNN_METRIC_L2>, dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st, Qh, Ql,
+                       qn, qr, db->xbf, db->xbf + cells, db->norm_f, db->rownorm, nq, n, mp, k, prange, c1, c2, part,
+                       nranges);
+  // work units: l2 three BF16 products of 2 operations; l1 a difference and an addition
+  prof_end(tok, st, (l1 ? 2.0 : 3.0 * 2.0) * (double)nq * (double)n * (double)m);
   tok = prof_begin(PROF_NAIVE_REST, st);
   hipLaunchKernelGGL(k_naive_f32_merge, dim3((unsigned)nq), dim3(1024), 0, st, part, nranges, k,
-                     (const float *)db->X, dq, m, out_idx, out_dist, flag);
+                     (const float *)db->X, dq, m, db->metric, out_idx, out_dist, flag);
   prof_end(tok, st, 0.0);
   HIP_TRY(hipGetLastError());
   // queries whose candidate list may be incomplete are rescanned exactly
@@ -395,8 +463,8 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
     HIP_TRY(hipMemcpyAsync(dq_ids, redo.data(), sizeof(int32_t) * redo.size(), hipMemcpyHostToDevice, st));
     for (int64_t b0 = 0; b0 < (int64_t)redo.size(); b0 += batch) {
       const int64_t cnt = std::min<int64_t>(batch, (int64_t)redo.size() - b0);
-      hipLaunchKernelGGL(k_naive_f32_full, dim3((unsigned)cnt), dim3(1024), 0, st, (const float *)db->X, dq, n, m, k,
-                         dq_ids + b0, scratch, out_idx, out_dist);
+      hipLaunchKernelGGL(k_naive_f32_full, dim3((unsigned)cnt), dim3(1024), 0, st, (const float *)db->X, dq, n, m,
+                         db->metric, k, dq_ids + b0, scratch, out_idx, out_dist);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipFreeAsync(scratch, st));
@@ -406,6 +474,5 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
   HIP_TRY(hipFreeAsync(ws, st));
   return KNN_OK;
 }
-
 
 }  // namespace knn

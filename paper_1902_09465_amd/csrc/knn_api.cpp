@@ -133,7 +133,8 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   const int32_t nqp = query_lane ? (int32_t)((ns + 15) / 16 * 16) : 0;
   const size_t o_qt = take((size_t)nqp * (size_t)db->m);
   const size_t o_qdl = take((size_t)nqp * (size_t)n * 5);  // round totals [n][nqp] u32, then flags [n][nqp] u8
-  const bool q8x = query_lane && db->dtype == KNN_U8 && db->xs8 && db->m <= 65536;
+  // the exact round of a query-lane batch as a GEMM (squared l2 only: l1 has no product form)
+  const bool q8x = query_lane && db->dtype == KNN_U8 && db->metric == KNN_METRIC_L2 && db->xs8 && db->m <= 65536;
   const size_t o_q8 = take(q8x ? (size_t)nqp * (size_t)db->mp : 0);
   const size_t o_q8n = take(q8x ? (size_t)nqp * 4 : 0);
   void *base = nullptr;
@@ -184,8 +185,14 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.G.xn = db->norm_i;
   E.G.mp = db->mp;
   E.G.kmax = kmax;
+  E.G.metric = db->metric;
   // grouped sampling needs the shared query tile (16 rows of mp bytes) in LDS
-  E.G.grouped = (grouped && db->dtype == KNN_U8 && db->xs8 && 16 * db->mp + 128 <= 65536 && K.group != 0) ? 1 : 0;
+  // (its exact rounds use the shifted int8 copy for squared l2, and fall back to
+  // per-slot sums for l1)
+  E.G.grouped = (grouped && db->dtype == KNN_U8 && (db->xs8 || db->metric == KNN_METRIC_L1) &&
+                 16 * db->mp + 128 <= 65536 && K.group != 0)
+                    ? 1
+                    : 0;
   E.ns = ns;
   E.qcap = qcap;
   E.nsched = nsched;
@@ -219,7 +226,8 @@ int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &pp, QDesc &d, Sc
   d.k = k;
   d.kh = (int32_t)kh;
   d.c_exact = pp.c_exact;
-  d.W = db->dtype == KNN_U8 ? 65025.0 : 0.0;
+  // samples s / W lie in [0,1]: u8 (x - q)^2 <= 255^2, |x - q| <= 255; f32: k_prep_f32
+  d.W = db->dtype == KNN_U8 ? (db->metric == KNN_METRIC_L1 ? 255.0 : 65025.0) : 0.0;
   d.F = 0;
   d.trivial = kh >= db->n ? 1 : 0;
   if (pp.sampling < 0 || pp.sampling > 1) return fail(KNN_EINVAL, "sampling must be 0 or 1");
@@ -277,7 +285,7 @@ static int prepare(knn_db_s *db, const void *dq, int64_t nq, const int32_t *host
 static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knobs &K, hipStream_t st) {
   knn_db_s *db = E.db;
   const int64_t n = db->n, m = db->m;
-  if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, st);
+  if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, db->metric, st);
   launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st, true);
   if (E.qt) launch_build_qt(E.slots, (int32_t)E.ns, m, E.nqp, E.qt, st);
   if (E.q8) launch_build_q8(E.slots, (int32_t)E.ns, m, db->mp, E.q8, E.q8n, st);
@@ -449,7 +457,7 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
       launch_lockstep(E, P, nq, K, st);
       chk(hipGetLastError(), "launch");
     } else {
-      if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, st);
+      if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, db->metric, st);
       launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st, true);
       chk(hipGetLastError(), "launch");
       // slots are recycled on the device; poll until every query is done
@@ -511,15 +519,16 @@ int knn_db_create(const void *dev_points, int64_t n, int64_t m, knn_dtype dt, in
   if (n < 1 || m < 1 || n >= (int64_t)1 << 31 || m >= (int64_t)1 << 31)
     return fail(KNN_EINVAL, "n and m must lie in [1, 2^31)");
   if (dt != KNN_U8 && dt != KNN_F32) return fail(KNN_EINVAL, "bad dtype");
-  if (flags != KNN_DB_BORROW && flags != KNN_DB_COPY) return fail(KNN_EINVAL, "bad flags");
+  if (flags & ~(KNN_DB_COPY | KNN_DB_L1)) return fail(KNN_EINVAL, "bad flags");
   knn_db_s *db = new knn_db_s();
   db->n = n;
   db->m = m;
   db->dtype = dt;
+  db->metric = (flags & KNN_DB_L1) ? KNN_METRIC_L1 : KNN_METRIC_L2;
   const size_t bytes = (size_t)n * m * (dt == KNN_U8 ? 1 : 4);
   hipStream_t st = nullptr;
   int rc = KNN_OK;
-  if (flags == KNN_DB_COPY || !aligned16(dev_points)) {
+  if ((flags & KNN_DB_COPY) || !aligned16(dev_points)) {
     hipError_t e = hipMalloc(&db->owned, bytes);
     if (e == hipSuccess) e = hipMemcpy(db->owned, dev_points, bytes, hipMemcpyDeviceToDevice);
     if (e != hipSuccess) {
@@ -557,6 +566,12 @@ int knn_db_info(knn_db db, int64_t *n, int64_t *m, int32_t *dtype) {
   if (n) *n = db->n;
   if (m) *m = db->m;
   if (dtype) *dtype = db->dtype;
+  return KNN_OK;
+}
+
+int knn_db_metric(knn_db db, int32_t *metric) {
+  if (!db || !metric) return fail(KNN_EINVAL, "NULL argument");
+  *metric = db->metric;
   return KNN_OK;
 }
 

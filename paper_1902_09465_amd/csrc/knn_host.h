@@ -30,6 +30,7 @@ struct knn_db_s {
   void *owned = nullptr;       // library allocation when copied
   int64_t n = 0, m = 0;
   int32_t dtype = KNN_U8;
+  int32_t metric = KNN_METRIC_L2;
   double lo = 0.0, hi = 0.0;   // f32 value range over all points
   // naive-scan auxiliaries
   int8_t *xs8 = nullptr;       // u8: x - 128 as int8, [n][mp] (mp = m padded to 64)
@@ -38,6 +39,7 @@ struct knn_db_s {
   uint16_t *xbf = nullptr;     // f32: split BF16 copy, hi [n][mp] then lo [n][mp]
   float *norm_f = nullptr;     // f32: |x|^2 per row (fp64 sum rounded to fp32)
   float *rownorm = nullptr;    // f32: |x| per row (for the error bound)
+  void *xpad = nullptr;        // l1: the points with rows zero-padded to mp (u8 or f32)
   std::atomic<int> users{0};   // sessions holding the DB
   std::mutex mu;
   knn::Plan *plan = nullptr;   // cached engine + captured graph of the last batch shape
@@ -87,7 +89,8 @@ Knobs knobs_for(const knn_db_s *db);
 int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &p, QDesc &d, Sched &sc);
 
 // kernels (k_adaptive.hip)
-void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, double hi, hipStream_t st);
+void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, double hi, int32_t metric,
+                     hipStream_t st);
 void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
                  const Bufs &B, const Geometry &G, bool any_cexact, hipStream_t st, int sample_kind = 0,
                  int stage_rows = 0, const QlRound *ql = nullptr, const uint8_t *qt = nullptr, int32_t nqp = 0,
@@ -105,6 +108,8 @@ int naive_prepare_db(knn_db_s *db, hipStream_t st);
 int naive_run(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
               hipStream_t st);
 void naive_free_db(knn_db_s *db);
+// rows of elem-byte values copied with zero padding from m to mp elements (the l1 scans' operands)
+void launch_pad_rows(const uint8_t *X, int64_t rows, int64_t m, int64_t mp, int elem, uint8_t *out, hipStream_t st);
 // k_naive_f32.hip
 int naive_prepare_db_f32(knn_db_s *db, hipStream_t st);
 int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,

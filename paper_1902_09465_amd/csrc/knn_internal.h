@@ -114,7 +114,7 @@ struct Geometry {
   int32_t grouped;      // 1: sample GRP slots per block when they share seed and round
   int32_t stage;        // grouped sampled rounds: point rows per LDS tile (0: gather from HBM)
   int32_t kmax;         // largest k of the slots' queries
-  int32_t pad1;
+  int32_t metric;       // KNN_METRIC_L2 (samples (x_ij - x_j)^2) or KNN_METRIC_L1 (|x_ij - x_j|)
 };
 
 // Order-preserving map of a non-NaN double to uint64 (and back).

@@ -110,7 +110,7 @@ static int upload(DbEngine &D, std::vector<Request *> &batch, std::string &err) 
         !ok(hipMemcpyAsync(D.E.sched + slot, &r->sc, sizeof(Sched), hipMemcpyHostToDevice, D.st), "upload sched") ||
         !ok(hipMemcpyAsync(D.dcnt + slot, &minus1, sizeof(int32_t), hipMemcpyHostToDevice, D.st), "reset count"))
       return KNN_EDEVICE;
-    if (D.db->dtype == KNN_F32) launch_prep_f32(D.E.qd + slot, 1, D.db->n, m, D.db->lo, D.db->hi, D.st);
+    if (D.db->dtype == KNN_F32) launch_prep_f32(D.E.qd + slot, 1, D.db->n, m, D.db->lo, D.db->hi, D.db->metric, D.st);
     D.ring[slot] = r;
     D.inflight++;
     D.submitted++;
