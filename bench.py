@@ -43,6 +43,12 @@ VALU_LANE_INSTR_PEAK = 39.3e12
 DOT4_PEAK_TOPS = 314.6
 OPS_PER_PAIR = 4
 OPS_PER_DRAW = 22 * 8
+# l1 distance: one v_sad_u8 (four absolute differences and four additions,
+# 8 op slots, the same 314.6 TOP/s peak) per query and four coordinates, so
+# 2 ops per (query, coordinate) pair -- in the sampled rounds, the exact
+# round and the naive scan alike.
+OPS_PER_PAIR_L1 = 2
+METRIC_L1 = "l1 distance: k-NN queries/s adaptive vs naive v_sad_u8 scan (true k-NN contained)"
 
 
 def log(msg):
@@ -60,7 +66,7 @@ def load_lib():
     return P
 
 
-def contained(idx, cnt, X_t, Q_t, nidx, ndist, k):
+def contained(idx, cnt, X_t, Q_t, nidx, ndist, k, metric="l2"):
     """Per query: does the returned set contain a k-NN set (tie-aware)?"""
     import torch
     nq = idx.shape[0]
@@ -69,7 +75,8 @@ def contained(idx, cnt, X_t, Q_t, nidx, ndist, k):
     valid = idx >= 0
     safe = torch.where(valid, idx, torch.zeros_like(idx))
     pts = X_t[safe.reshape(-1)].reshape(nq, idx.shape[1], -1).to(torch.int32)
-    d = ((pts - Q_t[:, None, :].to(torch.int32)) ** 2).sum(-1).to(torch.float64)
+    diff = pts - Q_t[:, None, :].to(torch.int32)
+    d = (diff.abs() if metric == "l1" else diff ** 2).sum(-1).to(torch.float64)
     d = torch.where(valid, d, torch.full_like(d, float("inf")))
     n_le = (d <= dk[:, None]).sum(1)
     strict = ndist < dk[:, None]  # neighbours strictly closer than d_(k)
@@ -79,20 +86,20 @@ def contained(idx, cnt, X_t, Q_t, nidx, ndist, k):
 
 
 def _oracle_worker(args):
-    X, q, k, h, delta, seed = args
+    X, q, k, h, delta, seed, metric = args
     import oracle
     t0 = time.perf_counter()
-    idx, st = oracle.adaptive(X, q, k, oracle.make_params(h=h, delta=delta, seed=seed))
+    idx, st = oracle.adaptive(X, q, k, oracle.make_params(h=h, delta=delta, seed=seed), metric=metric)
     return time.perf_counter() - t0, st["coord_evals"]
 
 
-def cpu_baseline(X, Q, seconds_hint):
+def cpu_baseline(X, Q, seconds_hint, metric=0):
     """The oracle, untuned, on this host's cores: one query per process."""
     import oracle
     oracle.build()
     cores = max(1, min(os.cpu_count() or 1, 16))
     nqs = cores
-    jobs = [(X, Q[i], K, H, DELTA, 12345) for i in range(nqs)]
+    jobs = [(X, Q[i], K, H, DELTA, 12345, metric) for i in range(nqs)]
     t0 = time.perf_counter()
     ctx = mp.get_context("fork")
     with ctx.Pool(cores) as pool:
@@ -361,6 +368,8 @@ def main():
     ap.add_argument("--paper-sweep", action="store_true", help="Section 5 C_alpha sweep instead of the batch line")
     ap.add_argument("--trials", type=int, default=20)
     ap.add_argument("--uneven", action="store_true", help="uneven workload instead of the batch line")
+    ap.add_argument("--metric", choices=("l2", "l1"), default="l2",
+                    help="distance of the batch line (l1: the same workload on an l1 DB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures a single MI355X "
@@ -386,11 +395,12 @@ def main():
     X, Q = gmm_u8(2000, n=N, m=M, n_centres=32, sigma=30.0, nq=NQ)
     X_t = torch.from_numpy(X).cuda()
     Q_t = torch.from_numpy(Q).cuda()
-    db = P.KnnDB(X_t)
+    l1 = args.metric == "l1"
+    db = P.KnnDB(X_t, metric=args.metric)
     params = P.default_params(h=H, delta=DELTA, seed=12345)
     torch.cuda.synchronize()
 
-    log("exact reference (int8 MFMA naive scan)")
+    log("exact reference (naive scan: int8 MFMA, or v_sad_u8 for l1)")
     nidx, ndist = db.naive(Q_t, K)
     torch.cuda.synchronize()
 
@@ -413,7 +423,7 @@ def main():
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t_all
     # containment and statistics (outside the timed region)
-    ok = contained(idx, cnt, X_t, Q_t, nidx, ndist, K)
+    ok = contained(idx, cnt, X_t, Q_t, nidx, ndist, K, args.metric)
     n_ok = int(ok.sum().item())
     prof = {}
     for kind, name in ((0, "sample"), (7, "sample_exact_round"), (8, "sample_transposes"), (1, "cand"),
@@ -447,7 +457,7 @@ def main():
     samp, exr = prof["sample"], prof["sample_exact_round"]
     s_avg = samp["ms"] / max(1, samp["launches"]) / 1e3
     e_avg = exr["ms"] / max(1, exr["launches"]) / 1e3
-    s_ops = (draws * OPS_PER_DRAW + pairs * OPS_PER_PAIR) / max(1, samp["launches"])
+    s_ops = (draws * OPS_PER_DRAW + pairs * (OPS_PER_PAIR_L1 if l1 else OPS_PER_PAIR)) / max(1, samp["launches"])
     e_ops = 2.0 * exact_elems / max(1, exr["launches"])
     rl_sample = {"bound": "alu", "achieved": s_ops / s_avg / 1e12 if s_avg > 0 else 0.0,
                  "peak": DOT4_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
@@ -455,11 +465,15 @@ def main():
                  "launches": samp["launches"], "ops_per_launch": s_ops,
                  "alg_bytes_per_launch": alg_bytes / max(1, samp["launches"] + exr["launches"])}
     rl_sample["frac"] = rl_sample["achieved"] / DOT4_PEAK_TOPS
-    rl_exact = {"bound": "mfma", "achieved": e_ops / e_avg / 1e12 if e_avg > 0 else 0.0,
-                "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
-                "kernel": "k_exact_ql_u8 (exact round, int8 MFMA GEMM)", "avg_launch_ms": e_avg * 1e3,
-                "launches": exr["launches"], "ops_per_launch": e_ops}
-    rl_exact["frac"] = rl_exact["achieved"] / INT8_PEAK_TOPS
+    # exact round: one tiled pass over (queries x points), a GEMM on the
+    # matrix cores for squared l2, v_sad_u8 sums on the vector ALU for l1
+    e_peak = DOT4_PEAK_TOPS if l1 else INT8_PEAK_TOPS
+    rl_exact = {"bound": "alu" if l1 else "mfma", "achieved": e_ops / e_avg / 1e12 if e_avg > 0 else 0.0,
+                "peak": e_peak, "unit": "TOP/s", "traffic": None,
+                "kernel": ("k_exact_ql_u8<l1> (exact round, v_sad_u8 tiles)" if l1 else
+                           "k_exact_ql_u8<l2> (exact round, int8 MFMA GEMM)"),
+                "avg_launch_ms": e_avg * 1e3, "launches": exr["launches"], "ops_per_launch": e_ops}
+    rl_exact["frac"] = rl_exact["achieved"] / e_peak
     roofline = rl_exact if dom == "sample_exact_round" else rl_sample
 
     # ---------------- naive MFMA scan, same batch
@@ -477,9 +491,17 @@ def main():
     P._lib.check(lib.knn_prof_enable(0))
     gemm_avg_s = ms.value / max(1, n_l.value) / 1e3
     naive_tops = (u.value / max(1, n_l.value)) / gemm_avg_s / 1e12 if gemm_avg_s > 0 else 0.0
+    naive_peak = DOT4_PEAK_TOPS if l1 else INT8_PEAK_TOPS
+    if l1:
+        naive_info = {"queries_per_s": NQ / naive_s, "ms_per_batch": naive_s * 1e3,
+                      "kernel": "k_naive_u8_k64<l1> (v_sad_u8 tiles)", "valu_sad_tops": naive_tops,
+                      "valu_frac": naive_tops / naive_peak}
+    else:
+        naive_info = {"queries_per_s": NQ / naive_s, "ms_per_batch": naive_s * 1e3,
+                      "mfma_int8_tops": naive_tops, "mfma_frac": naive_tops / naive_peak}
 
     out = {
-        "metric": METRIC,
+        "metric": METRIC_L1 if l1 else METRIC,
         "value": value,
         "unit": "queries/s",
         "n_gpus": 1,
@@ -491,16 +513,17 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": "batched_int: n=100000 points x m=3072 uint8, 32-centre Gaussian mixture "
-                               "sigma=30, 1024 queries, k=10 h=10 delta=0.01, footnote width, B0=64, g=2",
+        "config": {"workload": ("batched_int_l1" if l1 else "batched_int") +
+                               ": n=100000 points x m=3072 uint8, 32-centre Gaussian mixture "
+                               "sigma=30, 1024 queries, k=10 h=10 delta=0.01, footnote width, B0=64, g=2" +
+                               (", l1 distance" if l1 else ""),
                    "global_batch": NQ, "seq_len": M, "parallelism": "single GPU"},
         "contained": f"{n_ok}/{NQ}",
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "note": "whole-batch latency per step (all 1024 queries finish together)"},
         "coord_evals_per_query": float(evals.mean()),
         "fraction_of_naive_evals": float(evals.mean() / (N * M)),
-        "naive": {"queries_per_s": NQ / naive_s, "ms_per_batch": naive_s * 1e3,
-                  "mfma_int8_tops": naive_tops, "mfma_frac": naive_tops / INT8_PEAK_TOPS},
+        "naive": naive_info,
         "adaptive_vs_naive": (value / (NQ / naive_s)) if naive_s > 0 else None,
         "kernels_ms_per_step": {k_: v["ms"] / args.steps for k_, v in prof.items()},
         "graph_replay": {"ms_per_step": graph_ms, "same_result": same_graph,
@@ -514,7 +537,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on host cores)")
-        out["cpu_baseline"] = cpu_baseline(X, Q, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(X, Q, args.cpu_seconds, 1 if l1 else 0)
     print(json.dumps(out), flush=True)
     db.close()
     return 0

@@ -1736,7 +1736,7 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
   const size_t qbytes = (size_t)G.m * elem;
   const bool qlds = qbytes <= 48 * 1024;
   // exact round of a query-lane batch: one GEMM over (slots x points)
-  const bool ql_exact = ql && ql->exact && q8 && q8n && G.dtype == KNN_U8 && G.metric == KNN_METRIC_L2;
+  const bool ql_exact = ql && ql->exact && q8 && q8n && G.dtype == KNN_U8;
   if (ql_exact) {
     const int tk = prof_begin(PROF_EXACT, st);
     launch_exact_ql_u8(slots, q8, q8n, G.x8, G.xn, B, G, ql->cur, ql->impl, st);

@@ -465,11 +465,18 @@ __global__ __launch_bounds__(256) void k_naive_u8(const int8_t *__restrict__ Q8,
 
 // Shifted int8 copies of the running slots' queries, padded to mp, and their
 // squared norms (zero rows for idle slots): the A operand of the exact round.
+// For the l1 distance the rows are the queries' own bytes, zero-padded.
+template <int MET>
 __global__ __launch_bounds__(256) void k_build_q8(const Slot *__restrict__ slots, int32_t ns, int64_t m, int64_t mp,
                                                   int8_t *__restrict__ Q8, int32_t *__restrict__ qn) {
   const int s = blockIdx.x;
   const bool run = s < ns && slots[s].state == 1;
   const uint8_t *q = run ? reinterpret_cast<const uint8_t *>(slots[s].q) : nullptr;
+  if constexpr (MET == KNN_METRIC_L1) {
+    for (int64_t j = threadIdx.x; j < mp; j += 256)
+      reinterpret_cast<uint8_t *>(Q8)[(int64_t)s * mp + j] = (run && j < m) ? q[j] : (uint8_t)0;
+    return;
+  }
   int acc = 0;
   for (int64_t j = threadIdx.x; j < mp; j += 256) {
     const int v = (run && j < m) ? (int)q[j] - 128 : 0;
@@ -486,7 +493,9 @@ __global__ __launch_bounds__(256) void k_build_q8(const Slot *__restrict__ slots
 // The exact round of a batch whose slots all run it together, as one GEMM
 // over (slots x points): S = |q'|^2 + |x'|^2 - 2 q'.x' for every undecided
 // sampled pair (flag 0; every pair when the round is round 0), flag exact.
-// Exact in integers (int8 MFMA, int32 accumulation, m <= 65536).
+// Exact in integers (int8 MFMA, int32 accumulation, m <= 65536).  For the l1
+// distance the same tiles sum |x_j - q_j| with v_sad_u8 on zero-padded rows.
+template <int MET>
 __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ slots, const int8_t *__restrict__ Q8,
                                                      const int32_t *__restrict__ qn, const int8_t *__restrict__ X8,
                                                      const int32_t *__restrict__ xn, Bufs B, Geometry G, int32_t cur,
@@ -498,7 +507,7 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
   const int64_t q0 = (int64_t)blockIdx.y * NBQ;
   const int64_t pend = std::min(n, p0 + NBP);
   v4i acc[2][4];
-  gemm_u8_tile<KNN_METRIC_L2>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);
+  gemm_u8_tile<MET>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);
   const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
   uint64_t my_pairs = 0;
 #pragma unroll
@@ -507,14 +516,15 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
     for (int v = 0; v < 4; ++v) {
       const int64_t s = q0 + 32 * wq + 16 * a + 4 * (lane >> 4) + v;
       if (s >= ns || slots[s].state != 1 || slots[s].cur != cur) continue;
-      const int64_t qs = qn[s];
+      const int64_t qs = MET == KNN_METRIC_L1 ? 0 : qn[s];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
         if (i >= n) continue;
         const int64_t off = s * n + i;
         if (!impl && B.fl[off] != 0) continue;  // not an undecided sampled pair
-        B.S[off] = qs + (int64_t)xn[i] - 2 * (int64_t)acc[a][b][v];
+        B.S[off] = MET == KNN_METRIC_L1 ? (int64_t)(uint32_t)acc[a][b][v]
+                                        : qs + (int64_t)xn[i] - 2 * (int64_t)acc[a][b][v];
         B.fl[off] = FL_EXACT;
         if (impl) B.ri[off] = 0;
         ++my_pairs;
@@ -526,14 +536,21 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
   }
 }
 
-void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_t *Q8, int32_t *qn, hipStream_t st) {
-  hipLaunchKernelGGL(k_build_q8, dim3((unsigned)ns), dim3(256), 0, st, slots, ns, m, mp, Q8, qn);
+void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_t *Q8, int32_t *qn, int32_t metric,
+                     hipStream_t st) {
+  if (metric == KNN_METRIC_L1)
+    hipLaunchKernelGGL(k_build_q8<KNN_METRIC_L1>, dim3((unsigned)ns), dim3(256), 0, st, slots, ns, m, mp, Q8, qn);
+  else
+    hipLaunchKernelGGL(k_build_q8<KNN_METRIC_L2>, dim3((unsigned)ns), dim3(256), 0, st, slots, ns, m, mp, Q8, qn);
 }
 
 void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, const int8_t *X8, const int32_t *xn,
                         const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, hipStream_t st) {
   dim3 grid((unsigned)((G.n + NBP - 1) / NBP), (unsigned)((G.nslots + NBQ - 1) / NBQ));
-  hipLaunchKernelGGL(k_exact_ql_u8, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl);
+  if (G.metric == KNN_METRIC_L1)
+    hipLaunchKernelGGL(k_exact_ql_u8<KNN_METRIC_L1>, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl);
+  else
+    hipLaunchKernelGGL(k_exact_ql_u8<KNN_METRIC_L2>, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl);
 }
 
 // Merge per query: the k smallest keys over all ranges, sorted; index and

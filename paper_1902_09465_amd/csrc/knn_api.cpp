@@ -133,8 +133,11 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   const int32_t nqp = query_lane ? (int32_t)((ns + 15) / 16 * 16) : 0;
   const size_t o_qt = take((size_t)nqp * (size_t)db->m);
   const size_t o_qdl = take((size_t)nqp * (size_t)n * 5);  // round totals [n][nqp] u32, then flags [n][nqp] u8
-  // the exact round of a query-lane batch as a GEMM (squared l2 only: l1 has no product form)
-  const bool q8x = query_lane && db->dtype == KNN_U8 && db->metric == KNN_METRIC_L2 && db->xs8 && db->m <= 65536;
+  // the exact round of a query-lane batch as one tiled pass over (slots x points): an int8
+  // GEMM for squared l2, v_sad_u8 tiles for l1
+  const bool l1 = db->metric == KNN_METRIC_L1;
+  const bool q8x = query_lane && db->dtype == KNN_U8 && (l1 ? db->xpad != nullptr : db->xs8 != nullptr) &&
+                   db->m <= 65536;
   const size_t o_q8 = take(q8x ? (size_t)nqp * (size_t)db->mp : 0);
   const size_t o_q8n = take(q8x ? (size_t)nqp * 4 : 0);
   void *base = nullptr;
@@ -181,7 +184,7 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.G.ch_decide = 0;
   E.G.lpp = K.lpp;  // 0: chosen per round from its sample count
   E.G.prof = nullptr;
-  E.G.x8 = db->xs8;
+  E.G.x8 = l1 ? (const int8_t *)db->xpad : db->xs8;  // (u8 DBs; f32 DBs never read it)
   E.G.xn = db->norm_i;
   E.G.mp = db->mp;
   E.G.kmax = kmax;
@@ -288,7 +291,7 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, db->metric, st);
   launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st, true);
   if (E.qt) launch_build_qt(E.slots, (int32_t)E.ns, m, E.nqp, E.qt, st);
-  if (E.q8) launch_build_q8(E.slots, (int32_t)E.ns, m, db->mp, E.q8, E.q8n, st);
+  if (E.q8) launch_build_q8(E.slots, (int32_t)E.ns, m, db->mp, E.q8, E.q8n, db->metric, st);
   const bool lockstep = P.sched.size() == 1;
   // long rounds of grouped sampling read whole point rows into LDS
   const int stage_rows = E.G.grouped ? stage_rows_for(m, db->mp, K.stage_rows) : 0;

@@ -72,8 +72,9 @@ struct Engine {
   int64_t ns = 0, qcap = 0, nsched = 0;
   uint8_t *qt = nullptr;  // query-lane sampling: transposed queries [m][nqp] (nullptr: not used)
   uint32_t *qsum = nullptr;  // query-lane sampling: round totals [n][nqp] u32, then flags [n][nqp] u8
-  int8_t *q8 = nullptr;      // query-lane exact round: shifted int8 queries [nqp][mp] (u8 DBs)
-  int32_t *q8n = nullptr;    // ... and their squared norms [nqp]
+  int8_t *q8 = nullptr;      // query-lane exact round: shifted int8 queries [nqp][mp] (u8 DBs; l1: the
+                             // queries' bytes, zero-padded)
+  int32_t *q8n = nullptr;    // ... and their squared norms [nqp] (squared l2)
   int32_t nqp = 0;
 };
 size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax);
@@ -96,7 +97,8 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
                  int stage_rows = 0, const QlRound *ql = nullptr, const uint8_t *qt = nullptr, int32_t nqp = 0,
                  uint32_t *qd_buf = nullptr, const int8_t *q8 = nullptr, const int32_t *q8n = nullptr);
 void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint8_t *qt, hipStream_t st);
-void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_t *Q8, int32_t *qn, hipStream_t st);
+void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_t *Q8, int32_t *qn, int32_t metric,
+                     hipStream_t st);
 void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, const int8_t *X8, const int32_t *xn,
                         const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, hipStream_t st);
 void launch_admit(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,

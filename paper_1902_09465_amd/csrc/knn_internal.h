@@ -108,7 +108,8 @@ struct Geometry {
   int32_t lpp;          // lanes per point in sampled rounds
   uint64_t *prof;       // NULL, or work counters: [0] algorithmic bytes, [1] samples, [2] exact
                         // elements, [3] distinct Philox draws x 4
-  const int8_t *x8;     // u8 DB: x - 128 as int8, [n][mp] (exact round on the matrix cores)
+  const int8_t *x8;     // u8 DB: x - 128 as int8, [n][mp] (exact round on the matrix cores);
+                        // l1: the points' bytes zero-padded to [n][mp] (exact round by v_sad_u8 tiles)
   const int32_t *xn;    // u8 DB: sum (x - 128)^2 per row
   int64_t mp;           // m padded to a multiple of 64
   int32_t grouped;      // 1: sample GRP slots per block when they share seed and round
