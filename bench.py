@@ -55,6 +55,61 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# HBM traffic of the dominant kernel: measured by two rocprofv3 --pmc passes
+# over `bench.py --profile-pass` (FETCH_SIZE, then WRITE_SIZE), each scaled
+# by what the counter reads for a plain copy of known size in the same run,
+# and stored with the hash of the kernel's source; reported only while the
+# source is unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sample_ql_u8_batched_int_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1902_09465_amd", "csrc", "k_adaptive.hip")
+COPY_BYTES = 1 << 30
+
+
+def source_hash(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic():
+    """Bytes per launch of k_sample_ql_u8 from the committed counter summary,
+    or None when the summary is missing or was taken on other source."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith(" "):
+                a, b = line.split(":", 1)
+                kv[a.strip()] = b.strip()
+        if kv.get("source_sha256_16") != source_hash(KERNEL_SRC):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def profile_pass():
+    """The workload of the counter passes: a plain device copy of COPY_BYTES
+    (calibrates FETCH_SIZE / WRITE_SIZE), then one adaptive batch of the
+    batched-integer workload, launched eagerly (no graph)."""
+    os.environ["KNN_GRAPH"] = "0"
+    import torch
+    from knn_inputs import gmm_u8
+    P = load_lib()
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda").fill_(7)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    X, Q = gmm_u8(2000, n=N, m=M, n_centres=32, sigma=30.0, nq=NQ)
+    db = P.KnnDB(torch.from_numpy(X).cuda())
+    Qd = torch.from_numpy(Q).cuda()
+    idx, cnt, _ = db.adaptive(Qd, K, P.default_params(h=H, delta=DELTA, seed=12345), with_stats=False)
+    torch.cuda.synchronize()
+    log(f"profile pass done: {int((cnt > 0).sum())} queries answered")
+    return 0
+
+
 def load_lib():
     import paper_1902_09465_amd as P
     try:
@@ -370,6 +425,8 @@ def main():
     ap.add_argument("--uneven", action="store_true", help="uneven workload instead of the batch line")
     ap.add_argument("--metric", choices=("l2", "l1"), default="l2",
                     help="distance of the batch line (l1: the same workload on an l1 DB)")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="one copy of known size and one adaptive batch, for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures a single MI355X "
@@ -384,6 +441,8 @@ def main():
         return paper_sweep(args)
     if args.uneven:
         return uneven_bench(args)
+    if args.profile_pass:
+        return profile_pass()
     import torch
     from knn_inputs import gmm_u8
 
@@ -463,8 +522,17 @@ def main():
                  "peak": DOT4_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
                  "kernel": "k_sample_ql_u8 (sampled rounds, query-lane)", "avg_launch_ms": s_avg * 1e3,
                  "launches": samp["launches"], "ops_per_launch": s_ops,
-                 "alg_bytes_per_launch": alg_bytes / max(1, samp["launches"] + exr["launches"])}
+                 # bytes per launch if every query read its own samples (no sharing)
+                 "alg_bytes_per_launch_unshared": alg_bytes / max(1, samp["launches"] + exr["launches"])}
+    # with the draws shared by all queries of the batch: the round totals D
+    # [n][1024] u32 written, the point-major flags A [n][1024] read in every
+    # round but the first, and one byte per distinct draw
+    r_per_step = samp["launches"] / max(1, args.steps)
+    rl_sample["alg_bytes_per_launch"] = (N * NQ * 4 + N * NQ * (r_per_step - 1) / max(1.0, r_per_step)
+                                         + draws / max(1, samp["launches"]))
     rl_sample["frac"] = rl_sample["achieved"] / DOT4_PEAK_TOPS
+    if not l1:
+        rl_sample["traffic"] = stored_traffic()
     # exact round: one tiled pass over (queries x points), a GEMM on the
     # matrix cores for squared l2, v_sad_u8 sums on the vector ALU for l1
     e_peak = DOT4_PEAK_TOPS if l1 else INT8_PEAK_TOPS
