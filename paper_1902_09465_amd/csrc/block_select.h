@@ -19,6 +19,19 @@ struct SelScratch {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Work item of this block for a 1-D grid of 8 * ceil(nwork / 8) blocks.
+// Consecutive blocks are dispatched round-robin over the 8 XCDs, each with
+// its own L2; this mapping gives every XCD one contiguous range of work
+// items instead, so items that read the same lines (neighbours in the work
+// order) run on the same XCD at nearly the same time.  Items >= nwork are
+// padding (the block has nothing to do).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_work_item(int64_t nwork) {
+  const int64_t per = (nwork + kXcds - 1) / kXcds;
+  return (int64_t)(blockIdx.x % kXcds) * per + (int64_t)(blockIdx.x / kXcds);
+}
+inline int64_t xcd_grid(int64_t nwork) { return (nwork + kXcds - 1) / kXcds * kXcds; }
+
 // One wave: find the bucket b where the running count over hist[0..255]
 // first reaches r (1-based); res[0] = b, res[1] = count in buckets < b.
 __device__ __forceinline__ void scan_find_bucket(SelScratch &s, int r) {

@@ -102,7 +102,8 @@ __device__ __forceinline__ void point_bounds(const Slot *sl, int64_t m, int64_t 
   }
 }
 
-// p-th element of the kept set P = [act | xa | acc] (identity while implicit).
+// p-th element of the kept set P = [act | xa | acc] (identity while implicit;
+// with implicit 2 the caller skips points flagged discarded).
 __device__ __forceinline__ int32_t elem_P(const Slot *sl, const SlotArrays &a, int64_t p) {
   if (sl->implicit) return (int32_t)p;
   if (p < sl->n_act) return a.act[p];
@@ -111,7 +112,8 @@ __device__ __forceinline__ int32_t elem_P(const Slot *sl, const SlotArrays &a, i
   return a.acc[p - sl->n_xa];
 }
 
-// p-th element of the undecided set A = [act | xa].
+// p-th element of the undecided set A = [act | xa] (with implicit 2 the
+// caller skips points flagged accepted or discarded).
 __device__ __forceinline__ int32_t elem_A(const Slot *sl, const SlotArrays &a, int64_t p) {
   if (sl->implicit) return (int32_t)p;
   if (p < sl->n_act) return a.act[p];
@@ -258,6 +260,7 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
     const int wave = threadIdx.x / kWave, lane = lane_id();
     for (int64_t p = base + wave; p < end; p += BT / kWave) {
       const int32_t i = implicit ? (int32_t)p : a.act[p];
+      if (implicit == 2 && a.fl[i] != 0) continue;  // not an undecided sampled point
       const uint8_t *row = X + (int64_t)i * m * elem;
       int64_t acc = 0;
       if constexpr (DT == KNN_U8) {
@@ -317,6 +320,7 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
   const int ph = perm_half_bits(mm);
   for (int64_t p = base + threadIdx.x / lpp; p < end; p += BT / lpp) {
     const int32_t i = implicit ? (int32_t)p : a.act[p];
+    if (implicit == 2 && a.fl[i] != 0) continue;  // (uniform over the point's lanes)
     const uint8_t *row = X + (int64_t)i * m * elem;
     const PermKey pk = norepl ? perm_key((uint32_t)i, k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
     int64_t acc = 0;
@@ -549,12 +553,12 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
       if (run == 0) {
         cur = c;
         seed = sl->seed;
-        impl = sl->implicit;
+        impl = sl->implicit == 1;
         norepl = sl->norepl;
         t0 = a0;
         t1 = a1;
         mode = exact ? 2 : 1;
-      } else if (c != cur || (exact ? 2 : 1) != mode || sl->implicit != impl ||
+      } else if (c != cur || (exact ? 2 : 1) != mode || (sl->implicit == 1) != (impl != 0) ||
                  (!exact && (sl->seed != seed || sl->norepl != norepl || a0 != t0 || a1 != t1))) {
         mode = 0;
       }
@@ -1061,7 +1065,7 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
 #pragma unroll
   for (int e = 0; e < SEL_E; ++e) {
     const int64_t p = base + (int64_t)e * NT + threadIdx.x;
-    if (p < nP) {
+    if (p < nP && !(sl->implicit == 2 && (a.fl[elem_P(sl, a, p)] & FL_DISC))) {
       const int32_t i = elem_P(sl, a, p);
       double d, al;
       point_bounds(sl, m, a.S[i], a.fl[i], a.ri[i], d, al);
@@ -1147,8 +1151,15 @@ __global__ __launch_bounds__(NT) void k_fold_select_ql(const Slot *__restrict__ 
   __shared__ uint64_t cbuf[NT / kWave][kWave];
   const int64_t n = G.n, m = G.m;
   const int ns = G.nslots;
-  const int64_t i0 = (int64_t)blockIdx.x * FS_PT;
-  const int s0 = (int)blockIdx.y * FS_SL;
+  // work item (point tile, slot group), slot group fastest: the groups that
+  // share a point tile read the same lines of D (a 128-byte line holds 32
+  // slots), so they run back to back on one XCD
+  const int64_t ngroups = (nqp + FS_SL - 1) / FS_SL;
+  const int64_t w = xcd_work_item(ngroups * ((n + FS_PT - 1) / FS_PT));
+  if (w >= ngroups * ((n + FS_PT - 1) / FS_PT)) return;
+  const int64_t i0 = (w / ngroups) * FS_PT;
+  const int s0 = (int)(w % ngroups) * FS_SL;
+  const int64_t tile = w / ngroups;  // index of the partial lists of this tile
   for (int idx = threadIdx.x; idx < FS_PT * FS_SL; idx += NT) {
     const int p = idx / FS_SL, c = idx % FS_SL;
     const int64_t i = i0 + p;
@@ -1192,7 +1203,7 @@ __global__ __launch_bounds__(NT) void k_fold_select_ql(const Slot *__restrict__ 
       ku[e] = dkey(d + al);
       kl[e] = dkey(d - al);
     }
-    uint64_t *out = B.part + (int64_t)sl * B.part_stride + (int64_t)blockIdx.x * (2 * k + 1);
+    uint64_t *out = B.part + (int64_t)sl * B.part_stride + tile * (2 * k + 1);
     wave_smallest<FS_E>(ku, k, out, cbuf[wave]);
     wave_smallest<FS_E>(kl, k + 1, out + k, cbuf[wave]);
   }
@@ -1261,6 +1272,7 @@ __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B,
       const int32_t i = elem_A(sl, a, p);
       id[e] = i;
       const uint8_t f = a.fl[i];
+      if (sl->implicit == 2 && (f & (FL_DISC | FL_ACC))) continue;  // decided earlier
       double d, al;
       point_bounds(sl, m, a.S[i], f, a.ri[i], d, al);
       const double ucb = d + al, lcb = d - al;
@@ -1297,6 +1309,7 @@ __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B,
     bbase[c] = tot ? atomicAdd(ctr, tot) : 0;
   }
   __syncthreads();
+  if (G.flagsets) return;  // the counts are all the next round needs: no lists
 #pragma unroll
   for (int e = 0; e < DEC_E; ++e) {
 #pragma unroll
@@ -1462,6 +1475,56 @@ __device__ void write_trivial(const QDesc &qd, int64_t n) {
 // An oversized stop (no undecided point left to sample, |P| > k+h) first
 // makes the remaining estimated points exact, then keeps the k+h smallest
 // by (distance, index), which contain a k-NN set also under ties.
+// Slots that keep no lists (implicit 2): builds act / xa / acc from the
+// flags (undecided sampled, undecided exact, accepted; discarded points
+// dropped), in index order, and switches the slot to list mode.
+__device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry &G) {
+  const int64_t n = G.n;
+  const SlotArrays a = slot_arrays(B, n, s, sl->par);
+  constexpr int NW = MT / kWave;
+  __shared__ int wc[NW][3];
+  __shared__ int run[3];
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  if (threadIdx.x < 3) run[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t b = 0; b < n; b += MT) {
+    const int64_t i = b + threadIdx.x;
+    int c = -1;
+    if (i < n) {
+      const uint8_t f = a.fl[i];
+      c = (f & FL_DISC) ? -1 : (f & FL_ACC) ? 2 : (f & FL_EXACT) ? 1 : 0;
+    }
+    uint64_t mk[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      mk[k] = __ballot(c == k);
+      if (lane == 0) wc[wave][k] = __popcll(mk[k]);
+    }
+    __syncthreads();
+    if (c >= 0) {
+      int pos = run[c] + __popcll(mk[c] & lt);
+      for (int w = 0; w < wave; ++w) pos += wc[w][c];
+      int32_t *dst = c == 0 ? a.act : (c == 1 ? a.xa : a.acc);
+      dst[pos] = (int32_t)i;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      int t = 0;
+      for (int w = 0; w < NW; ++w) t += wc[w][threadIdx.x];
+      run[threadIdx.x] += t;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sl->n_act = run[0];
+    sl->n_xa = run[1];
+    sl->n_acc = run[2];
+    sl->implicit = 0;
+  }
+  __syncthreads();
+}
+
 template <int DT>
 __device__ void finalize(Slot *sl, int s, const QDesc &qd, const uint8_t *X, const Bufs &B,
                          const Geometry &G) {
@@ -1638,7 +1701,7 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
       sl->n_xa = sl->nn_xa;
       sl->n_acc = sl->nn_acc;
       sl->rounds += 1;
-      sl->implicit = 0;
+      sl->implicit = G.flagsets ? 2 : 0;
       sl->par ^= 1;
     }
     __syncthreads();
@@ -1651,6 +1714,7 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
       return;
     }
     if (nP <= sl->kh || sl->n_act == 0) {
+      if (sl->implicit == 2) lists_from_flags(sl, s, B, G);
       finalize<DT>(sl, s, qd[sl->qi], X, B, G);
       if (threadIdx.x == 0) {
         sl->state = 0;
@@ -1769,8 +1833,9 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     prof_end(tok, st, 0.0);
     if (fused_sel) {
       tok = prof_begin(PROF_SELECT, st);
-      hipLaunchKernelGGL(k_fold_select_ql, dim3((unsigned)((G.n + FS_PT - 1) / FS_PT), (unsigned)((nqp + FS_SL - 1) / FS_SL)),
-                         dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur);
+      const int64_t nwork = ((G.n + FS_PT - 1) / FS_PT) * ((nqp + FS_SL - 1) / FS_SL);
+      hipLaunchKernelGGL(k_fold_select_ql, dim3((unsigned)xcd_grid(nwork)), dim3(NT), 0, st, slots, qd_buf, nqp, B, G,
+                         ql->cur);
     } else {
       tok = prof_begin(PROF_QL_AUX, st);
       hipLaunchKernelGGL(k_fold_ql, tiles, dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur);

@@ -503,8 +503,14 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
   __shared__ __align__(16) uint8_t smem[2 * STAGE];
   const int64_t n = G.n, mp = G.mp;
   const int ns = G.nslots;
-  const int64_t p0 = (int64_t)blockIdx.x * NBP;
-  const int64_t q0 = (int64_t)blockIdx.y * NBQ;
+  // work item (point tile, query tile), query tile fastest: the query tiles
+  // of one point tile read the same point rows, so they run back to back on
+  // one XCD and the rows come from its L2
+  const int64_t nqt = (ns + NBQ - 1) / NBQ, nwork = nqt * ((n + NBP - 1) / NBP);
+  const int64_t w = xcd_work_item(nwork);
+  if (w >= nwork) return;
+  const int64_t p0 = (w / nqt) * NBP;
+  const int64_t q0 = (w % nqt) * NBQ;
   const int64_t pend = std::min(n, p0 + NBP);
   v4i acc[2][4];
   gemm_u8_tile<MET>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);
@@ -546,7 +552,8 @@ void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_
 
 void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, const int8_t *X8, const int32_t *xn,
                         const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, hipStream_t st) {
-  dim3 grid((unsigned)((G.n + NBP - 1) / NBP), (unsigned)((G.nslots + NBQ - 1) / NBQ));
+  const int64_t nwork = ((G.n + NBP - 1) / NBP) * ((G.nslots + NBQ - 1) / NBQ);
+  const dim3 grid((unsigned)xcd_grid(nwork));
   if (G.metric == KNN_METRIC_L1)
     hipLaunchKernelGGL(k_exact_ql_u8<KNN_METRIC_L1>, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl);
   else

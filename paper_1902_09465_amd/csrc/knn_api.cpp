@@ -293,6 +293,10 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   if (E.qt) launch_build_qt(E.slots, (int32_t)E.ns, m, E.nqp, E.qt, st);
   if (E.q8) launch_build_q8(E.slots, (int32_t)E.ns, m, db->mp, E.q8, E.q8n, db->metric, st);
   const bool lockstep = P.sched.size() == 1;
+  // Query-lane batches whose every round runs the fused fold + selection (no
+  // candidate-exact, k + 1 <= 64) and whose exact round is one tiled pass
+  // read the sets from the flags alone: no per-slot point lists are built
+  E.G.flagsets = (E.qt && E.q8 && lockstep && !P.any_cexact && P.kmax + 1 <= 64) ? 1 : 0;
   // long rounds of grouped sampling read whole point rows into LDS
   const int stage_rows = E.G.grouped ? stage_rows_for(m, db->mp, K.stage_rows) : 0;
   for (int t = 0; t < P.rmax + 1; ++t) {

@@ -49,7 +49,9 @@ struct Slot {
   int32_t qi;           // query index in the QDesc table
   int32_t cur;          // current round index (0..R); round R is exact
   int32_t par;          // which half of the double-buffered lists is current
-  int32_t implicit;     // 1 while the undecided list is the identity 0..n-1
+  int32_t implicit;     // 0: the sets are the lists act/xa/acc; 1: round 0, every point
+                        // undecided (identity); 2: the sets are given by the flags alone
+                        // (points 0..n-1 filtered by flag; no lists kept)
   int32_t n_act, n_xa, n_acc;   // current list sizes
   int32_t nn_act, nn_xa, nn_acc; // sizes being built by k_decide
   int32_t k, kh, R, c_exact;
@@ -116,6 +118,9 @@ struct Geometry {
   int32_t stage;        // grouped sampled rounds: point rows per LDS tile (0: gather from HBM)
   int32_t kmax;         // largest k of the slots' queries
   int32_t metric;       // KNN_METRIC_L2 (samples (x_ij - x_j)^2) or KNN_METRIC_L1 (|x_ij - x_j|)
+  int32_t flagsets;     // 1: slots keep no point lists (implicit 2 after round 0): every
+                        // kernel of the batch reads the sets from the flags
+  int32_t pad2;
 };
 
 // Order-preserving map of a non-NaN double to uint64 (and back).
