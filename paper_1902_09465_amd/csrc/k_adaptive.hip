@@ -1287,6 +1287,27 @@ __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B,
       }
     }
   }
+  if (G.flagsets) {
+    // no lists: only the per-slot counts, added without waiting for the
+    // atomics' results
+    int tot[3] = {0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < DEC_E; ++e)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tot[c] += __popcll(__ballot(cat[e] == c));
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) wcnt[0][wave][c] = tot[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const int c = threadIdx.x;
+      int t = 0;
+      for (int w = 0; w < NW; ++w) t += wcnt[0][w][c];
+      if (t) atomicAdd(c == 0 ? &sl->nn_act : (c == 1 ? &sl->nn_xa : &sl->nn_acc), t);
+    }
+    return;
+  }
 #pragma unroll
   for (int e = 0; e < DEC_E; ++e) {
 #pragma unroll
@@ -1309,7 +1330,6 @@ __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B,
     bbase[c] = tot ? atomicAdd(ctr, tot) : 0;
   }
   __syncthreads();
-  if (G.flagsets) return;  // the counts are all the next round needs: no lists
 #pragma unroll
   for (int e = 0; e < DEC_E; ++e) {
 #pragma unroll
