@@ -880,7 +880,7 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
     }
     uint4 *drow = reinterpret_cast<uint4 *>(D + i * (int64_t)nqp + qcol);
     if (__ballot(act != 0) == 0) {  // wave-uniform: nothing to sample at this point
-      if (has_q) {
+      if (has_q && !G.flagsets) {
         const uint4 none = make_uint4(QL_NONE, QL_NONE, QL_NONE, QL_NONE);
 #pragma unroll
         for (int c = 0; c < 4; ++c) drow[c] = none;
@@ -951,13 +951,30 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
       }
     }
     // totals of this round per slot (below 2^32 - 1 because m < 66052), in
-    // the point-major buffer D (one coalesced 64-byte store per lane); the
-    // fold kernel adds them to the slot-major running sums
+    // the point-major buffer D (one coalesced 64-byte store per lane): as
+    // this round's totals, which the fold kernel adds to the slot-major
+    // running sums; or, in batches that keep their sums point-major
+    // (G.flagsets), added to D itself, which then holds the running sums
     if (has_q) {
-      uint32_t t[GRP];
+      uint32_t t[GRP], old[GRP];
+      if (G.flagsets && !R.impl) {
 #pragma unroll
-      for (int g = 0; g < GRP; ++g)
-        t[g] = (act & (1u << g)) ? (MET == KNN_METRIC_L1 ? xq[g] : xx + qq[g] - 2u * xq[g]) : QL_NONE;
+        for (int c = 0; c < 4; ++c) {
+          const uint4 o = drow[c];
+          old[4 * c] = o.x;
+          old[4 * c + 1] = o.y;
+          old[4 * c + 2] = o.z;
+          old[4 * c + 3] = o.w;
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < GRP; ++g) old[g] = G.flagsets ? 0u : QL_NONE;
+      }
+#pragma unroll
+      for (int g = 0; g < GRP; ++g) {
+        const uint32_t tot = MET == KNN_METRIC_L1 ? xq[g] : xx + qq[g] - 2u * xq[g];
+        t[g] = (act & (1u << g)) ? (G.flagsets ? old[g] + tot : tot) : old[g];
+      }
 #pragma unroll
       for (int c = 0; c < 4; ++c) drow[c] = make_uint4(t[4 * c], t[4 * c + 1], t[4 * c + 2], t[4 * c + 3]);
     }
@@ -1206,6 +1223,256 @@ __global__ __launch_bounds__(NT) void k_fold_select_ql(const Slot *__restrict__ 
     uint64_t *out = B.part + (int64_t)sl * B.part_stride + tile * (2 * k + 1);
     wave_smallest<FS_E>(ku, k, out, cbuf[wave]);
     wave_smallest<FS_E>(kl, k + 1, out + k, cbuf[wave]);
+  }
+}
+
+// Batches that keep their sums point-major (G.flagsets): D[i][s] is the
+// running sum S of pair (s, i) (the exact distance once the pair is exact),
+// the flags stay slot-major, and the round index is stored only for decided
+// and exact pairs -- an undecided sampled pair was sampled up to T[cur].
+__device__ __forceinline__ uint8_t pm_round(uint8_t f, uint8_t ri_stored, int cur) {
+  return (f & (FL_ACC | FL_DISC | FL_EXACT)) ? ri_stored : (uint8_t)cur;
+}
+
+// A slot's round constants, read once into registers (the byte stores of
+// the kernels below may alias any object, so the slot would otherwise be
+// re-read after each of them).  The bounds are the same expressions as
+// point_bounds: d = S / (T W) with T W rounded once, width alpha(T).
+struct RoundConsts {
+  double TW, a, mW;  // T[cur] W, alpha[cur], m W
+};
+__device__ __forceinline__ RoundConsts round_consts(const Slot *sl, int64_t m, int cur) {
+  RoundConsts rc;
+  rc.TW = (double)sl->T[cur] * sl->W;
+  rc.a = sl->alpha[cur];
+  rc.mW = (double)m * sl->W;
+  return rc;
+}
+// Bounds of a pair: exact (width 0), accepted earlier at round ri, or
+// sampled up to T[cur].
+__device__ __forceinline__ void pair_bounds(const Slot *sl, const RoundConsts &rc, int64_t S, uint8_t f, uint8_t ri,
+                                            bool at_cur, double &d, double &a) {
+  if (f & FL_EXACT) {
+    d = (double)S / rc.mW;
+    a = 0.0;
+  } else if (at_cur) {
+    d = (double)S / rc.TW;
+    a = rc.a;
+  } else {
+    d = (double)S / ((double)sl->T[ri] * sl->W);
+    a = sl->alpha[ri];
+  }
+}
+
+// Selection for such batches: one block per tile of FS_SL slots x FS_PT
+// points (D transposed through LDS), the tile's k smallest UCB and k+1
+// smallest LCB per slot over the kept points, as k_fold_select_ql emits
+// them.  In a sampled round 0 every pair is undecided: its flag and round
+// index are initialised here.
+__global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
+                                                  int32_t nqp, Bufs B, Geometry G, int32_t cur, int32_t init) {
+  __shared__ uint32_t t[FS_SL][FS_PT + 1];
+  __shared__ uint64_t cbuf[NT / kWave][kWave];
+  const int64_t n = G.n, m = G.m;
+  const int ns = G.nslots;
+  const int64_t ngroups = (nqp + FS_SL - 1) / FS_SL;
+  const int64_t nwork = ngroups * ((n + FS_PT - 1) / FS_PT);
+  const int64_t w = xcd_work_item(nwork);
+  if (w >= nwork) return;
+  const int64_t tile = w / ngroups;
+  const int64_t i0 = tile * FS_PT;
+  const int s0 = (int)(w % ngroups) * FS_SL;
+  for (int idx = threadIdx.x; idx < FS_PT * FS_SL; idx += NT) {
+    const int p = idx / FS_SL, c = idx % FS_SL;
+    const int64_t i = i0 + p;
+    t[c][p] = (i < n && s0 + c < nqp) ? D[i * nqp + s0 + c] : 0u;
+  }
+  __syncthreads();
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  for (int r = wave; r < FS_SL; r += NT / kWave) {
+    const int sl = s0 + r;
+    if (sl >= ns) break;
+    const Slot *slp = &slots[sl];
+    if (slp->state != 1 || slp->cur != cur) continue;  // wave-uniform
+    const int k = slp->k;
+    const RoundConsts rc = round_consts(slp, m, cur);
+    const uint8_t *flr = B.fl + (int64_t)sl * n + i0;
+    uint8_t fv[FS_E];
+#pragma unroll
+    for (int e = 0; e < FS_E; ++e) {  // every flag load in flight at once
+      const int p = e * kWave + lane;
+      fv[e] = init ? (uint8_t)0 : (i0 + p < n ? flr[p] : (uint8_t)FL_DISC);
+    }
+    uint64_t ku[FS_E], kl[FS_E];
+#pragma unroll
+    for (int e = 0; e < FS_E; ++e) {
+      const int p = e * kWave + lane;
+      const int64_t i = i0 + p;
+      ku[e] = kl[e] = ~0ull;
+      const uint8_t f = fv[e];
+      if (i >= n || (f & FL_DISC)) continue;
+      const bool late = (f & FL_ACC) && !(f & FL_EXACT);  // accepted before this round
+      double d, al;
+      pair_bounds(slp, rc, (int64_t)t[r][p], f, late ? B.ri[(int64_t)sl * n + i] : (uint8_t)0, !late, d, al);
+      ku[e] = dkey(d + al);
+      kl[e] = dkey(d - al);
+    }
+    if (init) {  // round 0: every pair of the slot is undecided, sampled at round 0
+#pragma unroll
+      for (int e = 0; e < FS_E; ++e) {
+        const int64_t i = i0 + e * kWave + lane;
+        if (i < n) {
+          B.fl[(int64_t)sl * n + i] = 0;
+          B.ri[(int64_t)sl * n + i] = 0;
+        }
+      }
+    }
+    uint64_t *out = B.part + (int64_t)sl * B.part_stride + tile * (2 * k + 1);
+    wave_smallest<FS_E>(ku, k, out, cbuf[wave]);
+    wave_smallest<FS_E>(kl, k + 1, out + k, cbuf[wave]);
+  }
+}
+
+// Decide for such batches, per tile of DQ_SL slots x DQ_PT points: the
+// slot-major flags are staged in LDS, each thread keeps one slot's
+// thresholds in registers and decides its pairs from D read point-major,
+// writes the next round's point-major "not sampled" bytes A, and the
+// changed flags (and the round index of pairs decided while sampled) go
+// back slot-major.  Per slot the tile's counts of undecided sampled,
+// undecided exact and newly accepted pairs go to the slot's partial-list
+// area (consumed by k_finish), so no atomics are needed.
+constexpr int DQ_SL = 64, DQ_PT = 512;
+__global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, const uint32_t *__restrict__ D,
+                                                  uint8_t *__restrict__ A, int32_t nqp, Bufs B, Geometry G,
+                                                  int32_t cur) {
+  // rows padded to an odd number of 4-byte words: the 64 lanes of a wave
+  // read 64 different rows at one column without bank conflicts
+  __shared__ __align__(16) uint8_t ft[DQ_SL][DQ_PT + 4];
+  __shared__ int cnt[NT / DQ_SL][DQ_SL][3];
+  const int64_t n = G.n, m = G.m;
+  const int ns = G.nslots;
+  const int64_t ngroups = (nqp + DQ_SL - 1) / DQ_SL;
+  const int64_t nwork = ngroups * ((n + DQ_PT - 1) / DQ_PT);
+  const int64_t w = xcd_work_item(nwork);
+  if (w >= nwork) return;
+  const int64_t tile = w / ngroups;
+  const int64_t i0 = tile * DQ_PT;
+  const int s0 = (int)(w % ngroups) * DQ_SL;
+  const int pts = (int)min((int64_t)DQ_PT, n - i0);
+  // which slots of the tile run this round (one read per slot, in parallel)
+  __shared__ uint8_t srun[DQ_SL];
+  if (threadIdx.x < DQ_SL) {
+    const int sl = s0 + threadIdx.x;
+    srun[threadIdx.x] = (sl < ns && slots[sl].state == 1 && slots[sl].cur == cur) ? 1 : 0;
+  }
+  __syncthreads();
+  // stage the flags of the running slots (others: "not sampled"), four
+  // bytes per lane when the rows allow 4-byte loads
+  if ((n & 3) == 0 && pts == DQ_PT) {
+    // whole tile, 4-byte words: each wave loads its rows' words together
+    constexpr int RW = DQ_SL / (NT / kWave), WPR = DQ_PT / 4 / kWave;  // rows per wave, words per lane and row
+    uint32_t wv[RW][WPR];
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const int r = threadIdx.x / kWave + j * (NT / kWave);
+      const uint32_t *src = reinterpret_cast<const uint32_t *>(B.fl + (int64_t)(srun[r] ? s0 + r : 0) * n + i0);
+      static_assert(FL_DISC == 4, "four FL_DISC bytes");
+#pragma unroll
+      for (int q = 0; q < WPR; ++q) wv[j][q] = srun[r] ? src[lane_id() + q * kWave] : 0x04040404u;
+    }
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const int r = threadIdx.x / kWave + j * (NT / kWave);
+#pragma unroll
+      for (int q = 0; q < WPR; ++q) *reinterpret_cast<uint32_t *>(&ft[r][4 * (lane_id() + q * kWave)]) = wv[j][q];
+    }
+  } else {
+    for (int r = threadIdx.x / kWave; r < DQ_SL; r += NT / kWave) {
+      const bool run = srun[r] != 0;
+      const uint8_t *src = B.fl + (int64_t)(run ? s0 + r : 0) * n + i0;
+      for (int p = lane_id(); p < DQ_PT; p += kWave) ft[r][p] = (run && p < pts) ? src[p] : (uint8_t)FL_DISC;
+    }
+  }
+  __syncthreads();
+  const int c = threadIdx.x % DQ_SL;  // this thread's slot within the tile
+  const int sl = s0 + c;
+  const bool run = srun[c] != 0;
+  int c_act = 0, c_xa = 0, c_acc = 0;
+  if (sl < nqp) {
+    double U = 0, L1 = 0, L2 = 0;
+    const Slot *slp = &slots[run ? sl : 0];
+    RoundConsts rc{1.0, 0.0, 1.0};
+    if (run) {
+      U = slp->U;
+      L1 = slp->L1;
+      L2 = slp->L2;
+      rc = round_consts(slp, m, cur);
+    }
+    // DQ_B points per batch: their sums are loaded together, so the loads'
+    // latency is paid once per batch
+    constexpr int DQ_B = 8, STEP = NT / DQ_SL;
+    for (int pb = threadIdx.x / DQ_SL; pb < pts; pb += STEP * DQ_B) {
+      uint32_t sv[DQ_B];
+#pragma unroll
+      for (int b = 0; b < DQ_B; ++b) {  // unconditional loads (clamped to the tile): all in flight at once
+        const int p = min(pb + b * STEP, pts - 1);
+        sv[b] = D[(i0 + p) * nqp + sl];
+      }
+#pragma unroll
+      for (int b = 0; b < DQ_B; ++b) {
+        const int p = pb + b * STEP;
+        if (p >= pts) break;
+        uint8_t f = ft[c][p];
+        if (run && !(f & (FL_ACC | FL_DISC))) {
+          double d, al;
+          pair_bounds(slp, rc, (int64_t)sv[b], f, (uint8_t)cur, true, d, al);
+          const double ucb = d + al, lcb = d - al;
+          const bool exact = (f & FL_EXACT) != 0;
+          if (lcb > U) {
+            f |= FL_DISC | 0x80;
+          } else if (exact ? (ucb <= L1) : (ucb <= L2)) {
+            f |= FL_ACC | 0x80;
+            ++c_acc;
+          } else if (exact) {
+            ++c_xa;
+          } else {
+            ++c_act;
+          }
+          ft[c][p] = f;
+        }
+        A[(i0 + p) * nqp + sl] = (run && (f & 0x7F) == 0) ? (uint8_t)0 : (uint8_t)1;
+      }
+    }
+  }
+  cnt[threadIdx.x / DQ_SL][c][0] = c_act;
+  cnt[threadIdx.x / DQ_SL][c][1] = c_xa;
+  cnt[threadIdx.x / DQ_SL][c][2] = c_acc;
+  __syncthreads();
+  if (threadIdx.x < DQ_SL && srun[threadIdx.x]) {
+    const int cs = threadIdx.x;
+    const int s = s0 + cs;
+    {
+      int tot[3] = {0, 0, 0};
+      for (int q = 0; q < NT / DQ_SL; ++q)
+        for (int k = 0; k < 3; ++k) tot[k] += cnt[q][cs][k];
+      uint32_t *rec = reinterpret_cast<uint32_t *>(B.part + (int64_t)s * B.part_stride) + 3 * tile;
+      rec[0] = (uint32_t)tot[0];
+      rec[1] = (uint32_t)tot[1];
+      rec[2] = (uint32_t)tot[2];
+    }
+  }
+  // changed flags back, slot-major; a pair decided while still sampled
+  // records the round of its last samples
+  for (int r = threadIdx.x / kWave; r < DQ_SL; r += NT / kWave) {
+    const int s = s0 + r;
+    if (s >= ns) break;
+    for (int p = lane_id(); p < pts; p += kWave) {
+      const uint8_t f = ft[r][p];
+      if (!(f & 0x80)) continue;
+      const int64_t off = (int64_t)s * n + i0 + p;
+      B.fl[off] = f & 0x7F;
+      if (!(f & FL_EXACT)) B.ri[off] = (uint8_t)cur;
+    }
   }
 }
 
@@ -1497,7 +1764,9 @@ __device__ void write_trivial(const QDesc &qd, int64_t n) {
 // by (distance, index), which contain a k-NN set also under ties.
 // Slots that keep no lists (implicit 2): builds act / xa / acc from the
 // flags (undecided sampled, undecided exact, accepted; discarded points
-// dropped), in index order, and switches the slot to list mode.
+// dropped), in index order, and switches the slot to list mode.  With the
+// sums kept point-major, the listed points' sums and round indices are
+// copied into the slot-major arrays that the finalisation reads.
 __device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry &G) {
   const int64_t n = G.n;
   const SlotArrays a = slot_arrays(B, n, s, sl->par);
@@ -1527,6 +1796,10 @@ __device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry 
       for (int w = 0; w < wave; ++w) pos += wc[w][c];
       int32_t *dst = c == 0 ? a.act : (c == 1 ? a.xa : a.acc);
       dst[pos] = (int32_t)i;
+      if (G.flagsets) {
+        a.S[i] = (int64_t)B.dpm[i * B.dpm_stride + s];
+        if (c == 0) a.ri[i] = (uint8_t)sl->cur;
+      }
     }
     __syncthreads();
     if (threadIdx.x < 3) {
@@ -1715,6 +1988,28 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
   Slot *sl = &slots[s];
   const int64_t n = G.n, m = G.m;
   if (sl->state == 1 && !admit_only) {
+    if (G.flagsets) {
+      // this round's counts, one record per point tile of k_decide_pm
+      const int64_t nt = (n + DQ_PT - 1) / DQ_PT;
+      const uint32_t *rec = reinterpret_cast<const uint32_t *>(B.part + (int64_t)s * B.part_stride);
+      int64_t c3[3] = {0, 0, 0};
+      for (int64_t t = threadIdx.x; t < nt; t += MT)
+        for (int k = 0; k < 3; ++k) c3[k] += rec[3 * t + k];
+      __shared__ int64_t red3[MT / kWave][3];
+      for (int k = 0; k < 3; ++k)
+        for (int o = kWave / 2; o > 0; o >>= 1) c3[k] += shfl_xor_i64(c3[k], o);
+      if (lane_id() == 0)
+        for (int k = 0; k < 3; ++k) red3[threadIdx.x / kWave][k] = c3[k];
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int64_t t3[3] = {0, 0, 0};
+        for (int w = 0; w < MT / kWave; ++w)
+          for (int k = 0; k < 3; ++k) t3[k] += red3[w][k];
+        sl->nn_act = (int32_t)t3[0];
+        sl->nn_xa = (int32_t)t3[1];
+        sl->nn_acc = sl->n_acc + (int32_t)t3[2];
+      }
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       sl->n_act = sl->nn_act;
@@ -1727,6 +2022,14 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
     __syncthreads();
     const int64_t nP = (int64_t)sl->n_act + sl->n_xa + sl->n_acc;
     if (ctl->stop_after > 0 && sl->rounds >= ctl->stop_after) {
+      if (G.flagsets) {  // the slot-major state of the inspected slot, from the point-major sums
+        const SlotArrays a = slot_arrays(B, n, s, sl->par);
+        for (int64_t i = threadIdx.x; i < n; i += MT) {
+          a.S[i] = (int64_t)B.dpm[i * B.dpm_stride + s];
+          if (a.fl[i] == 0) a.ri[i] = (uint8_t)sl->cur;
+        }
+        __syncthreads();
+      }
       if (threadIdx.x == 0) {
         sl->state = 2;  // frozen for inspection
         atomicAdd(&ctl->done, 1);
@@ -1793,7 +2096,8 @@ void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, dou
 
 // the exact round of query-lane batches (k_naive.hip: shares the scan's GEMM tile)
 void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, const int8_t *X8, const int32_t *xn,
-                        const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, hipStream_t st);
+                        const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, uint32_t *Dpm, int32_t nqp,
+                        hipStream_t st);
 
 int stage_rows_for(int64_t m, int64_t mp, int want) {
   // LDS: the transposed query tile (GRP x mp) plus the row tile (rows x m)
@@ -1819,11 +2123,50 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
   const int elem = G.dtype == KNN_U8 ? 1 : 4;
   const size_t qbytes = (size_t)G.m * elem;
   const bool qlds = qbytes <= 48 * 1024;
+  const unsigned ns = (unsigned)G.nslots;
+  if (G.flagsets && ql && qt && qd_buf && q8 && q8n && G.dtype == KNN_U8) {
+    // A query-lane batch that keeps its sums point-major: sampling (or the
+    // exact round) accumulates into D, then selection and decisions read D
+    // in tiles; no slot-major sums, no lists, no transposes.
+    uint8_t *A = reinterpret_cast<uint8_t *>(qd_buf + G.n * (int64_t)nqp);  // follows D in the arena
+    if (ql->exact) {
+      const int tk = prof_begin(PROF_EXACT, st);
+      launch_exact_ql_u8(slots, q8, q8n, G.x8, G.xn, B, G, ql->cur, ql->impl, qd_buf, nqp, st);
+      prof_end(tk, st, 0.0);
+    } else {
+      const unsigned bx = (unsigned)std::min<int64_t>((G.n + QL_NW - 1) / QL_NW, 2048);
+      const unsigned by = (unsigned)((nqp + QL_SLOTS - 1) / QL_SLOTS);
+      const int tk = prof_begin(PROF_SAMPLE, st);
+      if (G.metric == KNN_METRIC_L1)
+        hipLaunchKernelGGL(k_sample_ql_u8<KNN_METRIC_L1>, dim3(bx, by), dim3(QL_BT), 0, st, slots, X, qt, nqp, A,
+                           qd_buf, B, G, *ql);
+      else
+        hipLaunchKernelGGL(k_sample_ql_u8<KNN_METRIC_L2>, dim3(bx, by), dim3(QL_BT), 0, st, slots, X, qt, nqp, A,
+                           qd_buf, B, G, *ql);
+      prof_end(tk, st, 0.0);
+    }
+    int tk = prof_begin(PROF_SELECT, st);
+    const int64_t nsel = ((G.n + FS_PT - 1) / FS_PT) * ((nqp + FS_SL - 1) / FS_SL);
+    hipLaunchKernelGGL(k_select_pm, dim3((unsigned)xcd_grid(nsel)), dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur,
+                       (ql->cur == 0 && !ql->exact) ? 1 : 0);
+    hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, FS_PT);
+    prof_end(tk, st, 0.0);
+    tk = prof_begin(PROF_DECIDE, st);
+    const int64_t ndec = ((G.n + DQ_PT - 1) / DQ_PT) * ((nqp + DQ_SL - 1) / DQ_SL);
+    hipLaunchKernelGGL(k_decide_pm, dim3((unsigned)xcd_grid(ndec)), dim3(NT), 0, st, slots, qd_buf, A, nqp, B, G,
+                       ql->cur);
+    prof_end(tk, st, 0.0);
+    tk = prof_begin(PROF_FINISH, st);
+    if (G.dtype == KNN_U8)
+      hipLaunchKernelGGL(k_finish<KNN_U8>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, 0);
+    prof_end(tk, st, 0.0);
+    return;
+  }
   // exact round of a query-lane batch: one GEMM over (slots x points)
   const bool ql_exact = ql && ql->exact && q8 && q8n && G.dtype == KNN_U8;
   if (ql_exact) {
     const int tk = prof_begin(PROF_EXACT, st);
-    launch_exact_ql_u8(slots, q8, q8n, G.x8, G.xn, B, G, ql->cur, ql->impl, st);
+    launch_exact_ql_u8(slots, q8, q8n, G.x8, G.xn, B, G, ql->cur, ql->impl, qd_buf, nqp, st);
     prof_end(tk, st, 0.0);
     ql = nullptr;  // the rest of the step as usual
   }
@@ -1884,7 +2227,6 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     launch_sample_met<KNN_F32>(slots, X, B, G, qlds, qbytes, st);
   }
   prof_end(tok, st, 0.0);
-  const unsigned ns = (unsigned)G.nslots;
   if (any_cexact) {
     tok = prof_begin(PROF_CAND, st);
     hipLaunchKernelGGL(k_cand_partial, dim3((unsigned)((G.n + CAND_CH - 1) / CAND_CH), ns), dim3(NT), 0, st,

@@ -499,7 +499,7 @@ template <int MET>
 __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ slots, const int8_t *__restrict__ Q8,
                                                      const int32_t *__restrict__ qn, const int8_t *__restrict__ X8,
                                                      const int32_t *__restrict__ xn, Bufs B, Geometry G, int32_t cur,
-                                                     int32_t impl) {
+                                                     int32_t impl, uint32_t *__restrict__ Dpm, int32_t nqp) {
   __shared__ __align__(16) uint8_t smem[2 * STAGE];
   const int64_t n = G.n, mp = G.mp;
   const int ns = G.nslots;
@@ -529,10 +529,18 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
         if (i >= n) continue;
         const int64_t off = s * n + i;
         if (!impl && B.fl[off] != 0) continue;  // not an undecided sampled pair
-        B.S[off] = MET == KNN_METRIC_L1 ? (int64_t)(uint32_t)acc[a][b][v]
-                                        : qs + (int64_t)xn[i] - 2 * (int64_t)acc[a][b][v];
+        const int64_t v64 = MET == KNN_METRIC_L1 ? (int64_t)(uint32_t)acc[a][b][v]
+                                                 : qs + (int64_t)xn[i] - 2 * (int64_t)acc[a][b][v];
+        if (G.flagsets) {
+          // point-major sums (below 2^32 for m <= 65536); the round of the
+          // pair's last samples is recorded with its exact flag
+          Dpm[i * nqp + s] = (uint32_t)v64;
+          B.ri[off] = impl ? (uint8_t)0 : (uint8_t)(cur - 1);
+        } else {
+          B.S[off] = v64;
+          if (impl) B.ri[off] = 0;
+        }
         B.fl[off] = FL_EXACT;
-        if (impl) B.ri[off] = 0;
         ++my_pairs;
       }
     }
@@ -551,13 +559,16 @@ void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_
 }
 
 void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, const int8_t *X8, const int32_t *xn,
-                        const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, hipStream_t st) {
+                        const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, uint32_t *Dpm, int32_t nqp,
+                        hipStream_t st) {
   const int64_t nwork = ((G.n + NBP - 1) / NBP) * ((G.nslots + NBQ - 1) / NBQ);
   const dim3 grid((unsigned)xcd_grid(nwork));
   if (G.metric == KNN_METRIC_L1)
-    hipLaunchKernelGGL(k_exact_ql_u8<KNN_METRIC_L1>, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl);
+    hipLaunchKernelGGL(k_exact_ql_u8<KNN_METRIC_L1>, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl,
+                       Dpm, nqp);
   else
-    hipLaunchKernelGGL(k_exact_ql_u8<KNN_METRIC_L2>, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl);
+    hipLaunchKernelGGL(k_exact_ql_u8<KNN_METRIC_L2>, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl,
+                       Dpm, nqp);
 }
 
 // Merge per query: the k smallest keys over all ranges, sorted; index and

@@ -168,6 +168,8 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.q8n = q8x ? (int32_t *)at(o_q8n) : nullptr;
   E.nqp = nqp;
   E.B.cand = nullptr;
+  E.B.dpm = query_lane ? E.qsum : nullptr;
+  E.B.dpm_stride = nqp;
   E.G.n = n;
   E.G.m = db->m;
   E.G.dtype = db->dtype;

@@ -100,7 +100,8 @@ void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint
 void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_t *Q8, int32_t *qn, int32_t metric,
                      hipStream_t st);
 void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, const int8_t *X8, const int32_t *xn,
-                        const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, hipStream_t st);
+                        const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, uint32_t *Dpm, int32_t nqp,
+                        hipStream_t st);
 void launch_admit(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
                   const Bufs &B, const Geometry &G, hipStream_t st, bool direct = false);
 int64_t part_words(int64_t n, int32_t kmax, int32_t cmax);

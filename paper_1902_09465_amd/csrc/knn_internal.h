@@ -98,6 +98,9 @@ struct Bufs {
   uint64_t *part;       // [nslots][part_stride] per-chunk selection candidates
   int64_t part_stride;
   int32_t *cand;        // [nslots][kMaxKH] candidate-exact picks
+  uint32_t *dpm;        // query-lane batches: D, point-major [n][dpm_stride] (running sums when
+                        // Geometry::flagsets); nullptr otherwise
+  int64_t dpm_stride;
 };
 
 struct Geometry {
