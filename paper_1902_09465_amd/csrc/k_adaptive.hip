@@ -1099,15 +1099,11 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
   emit_smallest<SEL_E>(kl, k + 1, out + k, ss, cnt, cand, wtau);
 }
 
-// Fold + selection for query-lane rounds without candidate-exact: one block
-// takes a tile of FS_SL slots x FS_PT points of the point-major round totals
-// (transposed through LDS), adds them to the slot-major running sums, and
-// then - since the kept set P is exactly the points without a discard flag -
-// computes every kept point's bounds and emits the tile's k smallest UCB and
-// k+1 smallest LCB per slot, as k_select_partial does per chunk of P.
-// One wave handles one slot row at a time, eight points per lane.  Needs
-// k + 1 <= 64 (the wave selection below).
-constexpr int FS_SL = 4, FS_PT = 512;  // 4 slots: one slot row per wave, ~10 KB LDS (highest occupancy of those measured)
+// Tiles of the selection over point-major sums (k_select_pm): FS_SL slots x
+// FS_PT points, one wave per slot row, sixteen points per lane; the kept set
+// P is exactly the points without a discard flag.  Needs k + 1 <= 64 (the
+// wave selection below).
+constexpr int FS_SL = 4, FS_PT = 1024;  // one slot row per wave; ~18 KB LDS
 constexpr int FS_E = FS_PT / kWave;
 
 // The K (<= 64) smallest of the wave's E keys per lane (PAD = none), written
@@ -1162,69 +1158,6 @@ __device__ void wave_smallest(const uint64_t (&key)[E], int K, uint64_t *out, ui
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(NT) void k_fold_select_ql(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
-                                                       int32_t nqp, Bufs B, Geometry G, int32_t cur) {
-  __shared__ uint32_t t[FS_SL][FS_PT + 1];
-  __shared__ uint64_t cbuf[NT / kWave][kWave];
-  const int64_t n = G.n, m = G.m;
-  const int ns = G.nslots;
-  // work item (point tile, slot group), slot group fastest: the groups that
-  // share a point tile read the same lines of D (a 128-byte line holds 32
-  // slots), so they run back to back on one XCD
-  const int64_t ngroups = (nqp + FS_SL - 1) / FS_SL;
-  const int64_t w = xcd_work_item(ngroups * ((n + FS_PT - 1) / FS_PT));
-  if (w >= ngroups * ((n + FS_PT - 1) / FS_PT)) return;
-  const int64_t i0 = (w / ngroups) * FS_PT;
-  const int s0 = (int)(w % ngroups) * FS_SL;
-  const int64_t tile = w / ngroups;  // index of the partial lists of this tile
-  for (int idx = threadIdx.x; idx < FS_PT * FS_SL; idx += NT) {
-    const int p = idx / FS_SL, c = idx % FS_SL;
-    const int64_t i = i0 + p;
-    t[c][p] = (i < n && s0 + c < nqp) ? D[i * nqp + s0 + c] : QL_NONE;
-  }
-  __syncthreads();
-  const int lane = lane_id(), wave = threadIdx.x / kWave;
-  for (int r = wave; r < FS_SL; r += NT / kWave) {
-    const int sl = s0 + r;
-    if (sl >= ns) break;
-    const Slot *slp = &slots[sl];
-    if (slp->state != 1 || slp->cur != cur) continue;  // wave-uniform
-    const int k = slp->k;
-    uint64_t ku[FS_E], kl[FS_E];
-#pragma unroll
-    for (int e = 0; e < FS_E; ++e) {
-      const int p = e * kWave + lane;
-      const int64_t i = i0 + p;
-      ku[e] = kl[e] = ~0ull;
-      if (i >= n) continue;
-      const int64_t off = (int64_t)sl * n + i;
-      const uint32_t v = t[r][p];
-      uint8_t f, ri;
-      int64_t S;
-      if (v != QL_NONE) {
-        S = cur == 0 ? (int64_t)v : B.S[off] + (int64_t)v;
-        B.S[off] = S;
-        B.ri[off] = (uint8_t)cur;
-        if (cur == 0) B.fl[off] = 0;
-        f = cur == 0 ? 0 : B.fl[off];
-        ri = (uint8_t)cur;
-      } else {
-        f = B.fl[off];
-        if (f & FL_DISC) continue;
-        S = B.S[off];
-        ri = B.ri[off];
-      }
-      if (f & FL_DISC) continue;
-      double d, al;
-      point_bounds(slp, m, S, f, ri, d, al);
-      ku[e] = dkey(d + al);
-      kl[e] = dkey(d - al);
-    }
-    uint64_t *out = B.part + (int64_t)sl * B.part_stride + tile * (2 * k + 1);
-    wave_smallest<FS_E>(ku, k, out, cbuf[wave]);
-    wave_smallest<FS_E>(kl, k + 1, out + k, cbuf[wave]);
-  }
-}
 
 // Batches that keep their sums point-major (G.flagsets): D[i][s] is the
 // running sum S of pair (s, i) (the exact distance once the pair is exact),
@@ -1266,13 +1199,14 @@ __device__ __forceinline__ void pair_bounds(const Slot *sl, const RoundConsts &r
 
 // Selection for such batches: one block per tile of FS_SL slots x FS_PT
 // points (D transposed through LDS), the tile's k smallest UCB and k+1
-// smallest LCB per slot over the kept points, as k_fold_select_ql emits
-// them.  In a sampled round 0 every pair is undecided: its flag and round
+// smallest LCB per slot over the kept points (the partial lists that
+// k_select_merge reads, one per FS_PT points).  In a sampled round 0 every pair is undecided: its flag and round
 // index are initialised here.
 __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
                                                   int32_t nqp, Bufs B, Geometry G, int32_t cur, int32_t init) {
   __shared__ uint32_t t[FS_SL][FS_PT + 1];
   __shared__ uint64_t cbuf[NT / kWave][kWave];
+  __shared__ uint64_t sbuf[NT / kWave][kWave];
   const int64_t n = G.n, m = G.m;
   const int ns = G.nslots;
   const int64_t ngroups = (nqp + FS_SL - 1) / FS_SL;
@@ -1282,10 +1216,20 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
   const int64_t tile = w / ngroups;
   const int64_t i0 = tile * FS_PT;
   const int s0 = (int)(w % ngroups) * FS_SL;
-  for (int idx = threadIdx.x; idx < FS_PT * FS_SL; idx += NT) {
-    const int p = idx / FS_SL, c = idx % FS_SL;
-    const int64_t i = i0 + p;
-    t[c][p] = (i < n && s0 + c < nqp) ? D[i * nqp + s0 + c] : 0u;
+  {  // the tile's sums, every load of a thread in flight at once (clamped rows, zeroed after)
+    constexpr int PER = FS_PT * FS_SL / NT;
+    uint32_t v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = threadIdx.x + u * NT;
+      const int64_t i = min(i0 + idx / FS_SL, n - 1);
+      v[u] = D[i * nqp + s0 + idx % FS_SL];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = threadIdx.x + u * NT;
+      t[idx % FS_SL][idx / FS_SL] = (i0 + idx / FS_SL < n) ? v[u] : 0u;
+    }
   }
   __syncthreads();
   const int lane = lane_id(), wave = threadIdx.x / kWave;
@@ -1303,6 +1247,15 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
       const int p = e * kWave + lane;
       fv[e] = init ? (uint8_t)0 : (i0 + p < n ? flr[p] : (uint8_t)FL_DISC);
     }
+    // When every kept pair of the tile has the same width alpha(T[cur])
+    // (none exact, none accepted in an earlier round), UCB and LCB are both
+    // monotone in d^: the k smallest UCB and the k+1 smallest LCB are
+    // d^ + alpha and d^ - alpha of the k+1 smallest d^, so one selection
+    // serves both lists, with the same values as two separate ones.
+    bool mixed = false;
+#pragma unroll
+    for (int e = 0; e < FS_E; ++e) mixed |= (fv[e] & (FL_EXACT | FL_ACC)) != 0 && !(fv[e] & FL_DISC);
+    const bool uniform = __ballot(mixed) == 0;
     uint64_t ku[FS_E], kl[FS_E];
 #pragma unroll
     for (int e = 0; e < FS_E; ++e) {
@@ -1311,6 +1264,10 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
       ku[e] = kl[e] = ~0ull;
       const uint8_t f = fv[e];
       if (i >= n || (f & FL_DISC)) continue;
+      if (uniform) {
+        ku[e] = dkey((double)t[r][p] / rc.TW);
+        continue;
+      }
       const bool late = (f & FL_ACC) && !(f & FL_EXACT);  // accepted before this round
       double d, al;
       pair_bounds(slp, rc, (int64_t)t[r][p], f, late ? B.ri[(int64_t)sl * n + i] : (uint8_t)0, !late, d, al);
@@ -1328,8 +1285,22 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
       }
     }
     uint64_t *out = B.part + (int64_t)sl * B.part_stride + tile * (2 * k + 1);
-    wave_smallest<FS_E>(ku, k, out, cbuf[wave]);
-    wave_smallest<FS_E>(kl, k + 1, out + k, cbuf[wave]);
+    if (uniform) {
+      wave_smallest<FS_E>(ku, k + 1, sbuf[wave], cbuf[wave]);  // the k+1 smallest d^ (PAD past the real ones)
+      constexpr uint64_t PAD = ~0ull;
+      if (lane < k + 1) {
+        const uint64_t kd = sbuf[wave][lane];
+        const double d = dkey_inv(kd);
+        if (lane < k) out[lane] = kd == PAD ? PAD : dkey(d + rc.a);
+        out[k + lane] = kd == PAD ? PAD : dkey(d - rc.a);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();  // sbuf is reused by the next row
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      wave_smallest<FS_E>(ku, k, out, cbuf[wave]);
+      wave_smallest<FS_E>(kl, k + 1, out + k, cbuf[wave]);
+    }
   }
 }
 
@@ -1478,7 +1449,7 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
 
 constexpr int MT = 1024;  // merge / finish block size
 
-// fs_chunk > 0: the partials came from k_fold_select_ql, one per fs_chunk
+// fs_chunk > 0: the partials came from k_select_pm, one per fs_chunk
 // points of [0, n); otherwise from k_select_partial, one per SEL_CH of P.
 __global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, Bufs B, Geometry G, int32_t fs_chunk) {
   const int s = blockIdx.x;
@@ -1553,27 +1524,6 @@ __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B,
         cat[e] = exact ? 1 : 0;
       }
     }
-  }
-  if (G.flagsets) {
-    // no lists: only the per-slot counts, added without waiting for the
-    // atomics' results
-    int tot[3] = {0, 0, 0};
-#pragma unroll
-    for (int e = 0; e < DEC_E; ++e)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) tot[c] += __popcll(__ballot(cat[e] == c));
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) wcnt[0][wave][c] = tot[c];
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-      const int c = threadIdx.x;
-      int t = 0;
-      for (int w = 0; w < NW; ++w) t += wcnt[0][w][c];
-      if (t) atomicAdd(c == 0 ? &sl->nn_act : (c == 1 ? &sl->nn_xa : &sl->nn_acc), t);
-    }
-    return;
   }
 #pragma unroll
   for (int e = 0; e < DEC_E; ++e) {
@@ -2171,8 +2121,6 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     ql = nullptr;  // the rest of the step as usual
   }
   const bool use_ql = ql && !ql->exact && qt && qd_buf && G.dtype == KNN_U8;
-  // fold and selection in one pass (candidate-exact must run between them)
-  const bool fused_sel = use_ql && !any_cexact && G.kmax + 1 <= kWave;
   int tok = (use_ql || ql_exact) ? -1 : prof_begin(sample_kind == 1 ? PROF_EXACT : PROF_SAMPLE, st);
   if (ql_exact) {
     // sampling done above
@@ -2194,15 +2142,8 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
       hipLaunchKernelGGL(k_sample_ql_u8<KNN_METRIC_L2>, dim3(bx, by), dim3(QL_BT), 0, st, slots, X, qt, nqp, A, qd_buf,
                          B, G, *ql);
     prof_end(tok, st, 0.0);
-    if (fused_sel) {
-      tok = prof_begin(PROF_SELECT, st);
-      const int64_t nwork = ((G.n + FS_PT - 1) / FS_PT) * ((nqp + FS_SL - 1) / FS_SL);
-      hipLaunchKernelGGL(k_fold_select_ql, dim3((unsigned)xcd_grid(nwork)), dim3(NT), 0, st, slots, qd_buf, nqp, B, G,
-                         ql->cur);
-    } else {
-      tok = prof_begin(PROF_QL_AUX, st);
-      hipLaunchKernelGGL(k_fold_ql, tiles, dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur);
-    }
+    tok = prof_begin(PROF_QL_AUX, st);
+    hipLaunchKernelGGL(k_fold_ql, tiles, dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur);
   } else if (G.dtype == KNN_U8 && G.grouped) {
     size_t gbytes = std::max<size_t>((size_t)GRP * G.mp + 8 * GRP, qbytes);
     if (G.stage > 0) {
@@ -2237,14 +2178,10 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
       hipLaunchKernelGGL(k_cand_merge<KNN_F32>, dim3(ns), dim3(MT), 0, st, slots, X, B, G);
     prof_end(tok, st, 0.0);
   }
-  if (fused_sel) {
-    hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, FS_PT);
-  } else {
-    tok = prof_begin(PROF_SELECT, st);
-    hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((G.n + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st,
-                       slots, B, G);
-    hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, 0);
-  }
+  tok = prof_begin(PROF_SELECT, st);
+  hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((G.n + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st, slots,
+                     B, G);
+  hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, 0);
   prof_end(tok, st, 0.0);
   tok = prof_begin(PROF_DECIDE, st);
   hipLaunchKernelGGL(k_decide, dim3((unsigned)((G.n + DEC_CH - 1) / DEC_CH), ns), dim3(NT), 0, st, slots,
@@ -2272,7 +2209,8 @@ int64_t part_words(int64_t n, int32_t kmax, int32_t cmax) {
   int64_t nsel = (n + SEL_CH - 1) / SEL_CH;
   if (kmax + 1 <= kWave) nsel = std::max<int64_t>(nsel, (n + FS_PT - 1) / FS_PT);  // fused query-lane selection
   const int64_t ncand = (n + CAND_CH - 1) / CAND_CH;
-  const int64_t a = nsel * (2 * (int64_t)kmax + 1);
+  int64_t a = nsel * (2 * (int64_t)kmax + 1);
+  a = std::max<int64_t>(a, (3 * ((n + DQ_PT - 1) / DQ_PT) + 1) / 2);  // k_decide_pm's count records (u32 triples)
   const int64_t c = cmax > 0 ? ncand * (int64_t)min(cmax, CAND_CH) * 2 : 0;  // keys + packed ids
   return (a > c ? a : c) + 8;
 }
