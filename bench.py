@@ -485,8 +485,8 @@ def main():
     ok = contained(idx, cnt, X_t, Q_t, nidx, ndist, K, args.metric)
     n_ok = int(ok.sum().item())
     prof = {}
-    for kind, name in ((0, "sample"), (7, "sample_exact_round"), (8, "sample_transposes"), (1, "cand"),
-                       (2, "select"), (3, "decide"), (4, "finish")):
+    for kind, name in ((0, "sample"), (7, "sample_exact_round"), (8, "sample_transposes"), (9, "sample_sparse"),
+                       (1, "cand"), (2, "select"), (3, "decide"), (4, "finish")):
         ms, n_l, u = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         P._lib.check(lib.knn_prof_read(kind, ctypes.byref(ms), ctypes.byref(n_l), ctypes.byref(u)))
         prof[name] = dict(ms=ms.value, launches=n_l.value)

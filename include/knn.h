@@ -238,8 +238,9 @@ int knn_prof_enable(int on);
  * launches that run the exact round of a batch whose queries all share one
  * schedule (such launches are counted here instead of under 0), 8 the
  * point-major / slot-major transposes around query-lane sampling (flags in,
- * round totals out; under 0 is then the sampling kernel alone).  Waits for
- * the recorded events. */
+ * round totals out; under 0 is then the sampling kernel alone), 9 the
+ * per-query sampling (or exact sums) of the queries of a point-major batch
+ * whose undecided sets have become small.  Waits for the recorded events. */
 int knn_prof_read(int32_t kind, double *total_ms, int64_t *launches, double *units);
 
 /* Work counters since the last enable: [0] algorithmic bytes of the

@@ -352,6 +352,7 @@ __global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const u
   const int s = blockIdx.x;
   const Slot *sl = &slots[s];
   if (sl->state != 1) return;
+  if (G.flagsets && sl->implicit != 0) return;  // a dense slot of a point-major batch
   extern __shared__ __align__(16) uint8_t smem[];
   sample_slot_chunk<DT, MET, QLDS>(sl, s, (int64_t)blockIdx.y, X, B, G, smem);
 }
@@ -847,7 +848,8 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
   uint32_t run = 0;
   for (int g = 0; g < GRP; ++g) {
     const int s = s0 + g;
-    if (s < ns && slots[s].state == 1 && slots[s].cur == R.cur) run |= 1u << g;
+    if (s < ns && slots[s].state == 1 && slots[s].cur == R.cur && (!G.flagsets || slots[s].implicit != 0))
+      run |= 1u << g;
   }
   if (__ballot(run != 0) == 0) return;  // no running slot in this wave's range
   const uint32_t blk0 = R.t0 >> 2, blk1 = R.t1 >> 2;
@@ -1069,6 +1071,7 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
   const int s = blockIdx.y;
   const Slot *sl = &slots[s];
   if (sl->state != 1) return;
+  if (G.flagsets && sl->implicit != 0) return;  // a dense slot of a point-major batch
   const int64_t n = G.n, m = G.m;
   const int64_t nP = size_P(sl, n);
   const int64_t base = (int64_t)blockIdx.x * SEL_CH;
@@ -1216,6 +1219,14 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
   const int64_t tile = w / ngroups;
   const int64_t i0 = tile * FS_PT;
   const int s0 = (int)(w % ngroups) * FS_SL;
+  {  // nothing to do unless a slot of the tile runs this round in dense form
+    bool any = false;
+    for (int c = 0; c < FS_SL; ++c) {
+      const int sl = s0 + c;
+      any |= sl < ns && slots[sl].state == 1 && slots[sl].cur == cur && slots[sl].implicit != 0;
+    }
+    if (!any) return;
+  }
   {  // the tile's sums, every load of a thread in flight at once (clamped rows, zeroed after)
     constexpr int PER = FS_PT * FS_SL / NT;
     uint32_t v[PER];
@@ -1237,7 +1248,7 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
     const int sl = s0 + r;
     if (sl >= ns) break;
     const Slot *slp = &slots[sl];
-    if (slp->state != 1 || slp->cur != cur) continue;  // wave-uniform
+    if (slp->state != 1 || slp->cur != cur || slp->implicit == 0) continue;  // wave-uniform; sparse slots elsewhere
     const int k = slp->k;
     const RoundConsts rc = round_consts(slp, m, cur);
     const uint8_t *flr = B.fl + (int64_t)sl * n + i0;
@@ -1332,11 +1343,17 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
   const int pts = (int)min((int64_t)DQ_PT, n - i0);
   // which slots of the tile run this round (one read per slot, in parallel)
   __shared__ uint8_t srun[DQ_SL];
+  __shared__ int sany;
+  if (threadIdx.x == 0) sany = 0;
+  __syncthreads();
   if (threadIdx.x < DQ_SL) {
     const int sl = s0 + threadIdx.x;
-    srun[threadIdx.x] = (sl < ns && slots[sl].state == 1 && slots[sl].cur == cur) ? 1 : 0;
+    srun[threadIdx.x] =
+        (sl < ns && slots[sl].state == 1 && slots[sl].cur == cur && slots[sl].implicit != 0) ? 1 : 0;
+    if (srun[threadIdx.x]) sany = 1;
   }
   __syncthreads();
+  if (!sany) return;  // every slot of the tile is idle or sparse
   // stage the flags of the running slots (others: "not sampled"), four
   // bytes per lane when the rows allow 4-byte loads
   if ((n & 3) == 0 && pts == DQ_PT) {
@@ -1456,7 +1473,10 @@ __global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, B
   Slot *sl = &slots[s];
   if (sl->state != 1) return;
   const int64_t nP = size_P(sl, G.n);
-  const int64_t nch = fs_chunk > 0 ? (G.n + fs_chunk - 1) / fs_chunk : (nP + SEL_CH - 1) / SEL_CH;
+  // partial lists: per fs_chunk points of [0, n) (dense slots of point-major
+  // batches), else per SEL_CH elements of P
+  const bool dense = fs_chunk > 0 && (!G.flagsets || sl->implicit != 0);
+  const int64_t nch = dense ? (G.n + fs_chunk - 1) / fs_chunk : (nP + SEL_CH - 1) / SEL_CH;
   const int k = sl->k;
   const int64_t w = 2 * k + 1;
   const uint64_t *part = B.part + (int64_t)s * B.part_stride;
@@ -1488,6 +1508,7 @@ __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B,
   const int s = blockIdx.y;
   Slot *sl = &slots[s];
   if (sl->state != 1) return;
+  if (G.flagsets && sl->implicit != 0) return;  // a dense slot of a point-major batch
   const int64_t n = G.n, m = G.m;
   const int64_t nA = size_A(sl, n);
   const int64_t base = (int64_t)blockIdx.x * DEC_CH;
@@ -1716,8 +1737,9 @@ __device__ void write_trivial(const QDesc &qd, int64_t n) {
 // flags (undecided sampled, undecided exact, accepted; discarded points
 // dropped), in index order, and switches the slot to list mode.  With the
 // sums kept point-major, the listed points' sums and round indices are
-// copied into the slot-major arrays that the finalisation reads.
-__device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry &G) {
+// copied into the slot-major arrays that the list kernels read (with `all`,
+// the sums of the discarded points too, so the slot-major state is whole).
+__device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry &G, bool all = false) {
   const int64_t n = G.n;
   const SlotArrays a = slot_arrays(B, n, s, sl->par);
   constexpr int NW = MT / kWave;
@@ -1746,11 +1768,9 @@ __device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry 
       for (int w = 0; w < wave; ++w) pos += wc[w][c];
       int32_t *dst = c == 0 ? a.act : (c == 1 ? a.xa : a.acc);
       dst[pos] = (int32_t)i;
-      if (G.flagsets) {
-        a.S[i] = (int64_t)B.dpm[i * B.dpm_stride + s];
-        if (c == 0) a.ri[i] = (uint8_t)sl->cur;
-      }
+      if (c == 0 && G.flagsets) a.ri[i] = (uint8_t)sl->cur;
     }
+    if (G.flagsets && i < n && (c >= 0 || all)) a.S[i] = (int64_t)B.dpm[i * B.dpm_stride + s];
     __syncthreads();
     if (threadIdx.x < 3) {
       int t = 0;
@@ -1938,7 +1958,8 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
   Slot *sl = &slots[s];
   const int64_t n = G.n, m = G.m;
   if (sl->state == 1 && !admit_only) {
-    if (G.flagsets) {
+    const bool dense = G.flagsets && sl->implicit != 0;  // (uniform over the block)
+    if (dense) {
       // this round's counts, one record per point tile of k_decide_pm
       const int64_t nt = (n + DQ_PT - 1) / DQ_PT;
       const uint32_t *rec = reinterpret_cast<const uint32_t *>(B.part + (int64_t)s * B.part_stride);
@@ -1966,13 +1987,13 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
       sl->n_xa = sl->nn_xa;
       sl->n_acc = sl->nn_acc;
       sl->rounds += 1;
-      sl->implicit = G.flagsets ? 2 : 0;
+      sl->implicit = dense ? 2 : 0;
       sl->par ^= 1;
     }
     __syncthreads();
     const int64_t nP = (int64_t)sl->n_act + sl->n_xa + sl->n_acc;
     if (ctl->stop_after > 0 && sl->rounds >= ctl->stop_after) {
-      if (G.flagsets) {  // the slot-major state of the inspected slot, from the point-major sums
+      if (dense) {  // the slot-major state of the inspected slot, from the point-major sums
         const SlotArrays a = slot_arrays(B, n, s, sl->par);
         for (int64_t i = threadIdx.x; i < n; i += MT) {
           a.S[i] = (int64_t)B.dpm[i * B.dpm_stride + s];
@@ -1995,6 +2016,11 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
       }
       __syncthreads();
     } else {
+      // a dense slot of a point-major batch whose undecided set has become
+      // small continues in list form (per-slot kernels cost per undecided
+      // point, the point-major ones per point of the DB)
+      if (sl->implicit == 2 && G.sparse_div > 0 && ((int64_t)sl->n_act + sl->n_xa) * G.sparse_div <= n)
+        lists_from_flags(sl, s, B, G, true);
       if (threadIdx.x == 0) {
         const int cur = sl->cur + 1;
         sl->cur = cur;
@@ -2095,16 +2121,24 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
                            qd_buf, B, G, *ql);
       prof_end(tk, st, 0.0);
     }
-    int tk = prof_begin(PROF_SELECT, st);
+    // slots that turned sparse: per-slot sampling over their lists (or their
+    // exact sums in the exact round); the kernel skips the dense slots
+    int tk = prof_begin(PROF_SPARSE, st);
+    launch_sample_met<KNN_U8>(slots, X, B, G, qlds, qbytes, st);
+    prof_end(tk, st, 0.0);
+    tk = prof_begin(PROF_SELECT, st);
     const int64_t nsel = ((G.n + FS_PT - 1) / FS_PT) * ((nqp + FS_SL - 1) / FS_SL);
     hipLaunchKernelGGL(k_select_pm, dim3((unsigned)xcd_grid(nsel)), dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur,
                        (ql->cur == 0 && !ql->exact) ? 1 : 0);
+    hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((G.n + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st, slots,
+                       B, G);
     hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, FS_PT);
     prof_end(tk, st, 0.0);
     tk = prof_begin(PROF_DECIDE, st);
     const int64_t ndec = ((G.n + DQ_PT - 1) / DQ_PT) * ((nqp + DQ_SL - 1) / DQ_SL);
     hipLaunchKernelGGL(k_decide_pm, dim3((unsigned)xcd_grid(ndec)), dim3(NT), 0, st, slots, qd_buf, A, nqp, B, G,
                        ql->cur);
+    hipLaunchKernelGGL(k_decide, dim3((unsigned)((G.n + DEC_CH - 1) / DEC_CH), ns), dim3(NT), 0, st, slots, B, G);
     prof_end(tk, st, 0.0);
     tk = prof_begin(PROF_FINISH, st);
     if (G.dtype == KNN_U8)

@@ -522,6 +522,7 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
     for (int v = 0; v < 4; ++v) {
       const int64_t s = q0 + 32 * wq + 16 * a + 4 * (lane >> 4) + v;
       if (s >= ns || slots[s].state != 1 || slots[s].cur != cur) continue;
+      if (G.flagsets && slots[s].implicit == 0) continue;  // a sparse slot: its own exact pass
       const int64_t qs = MET == KNN_METRIC_L1 ? 0 : qn[s];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {

@@ -100,6 +100,7 @@ Knobs knobs_for(const knn_db_s *db) {
   k.stage_min = env_int("KNN_STAGE_MIN", k.stage_min);
   k.stage_rows = env_int("KNN_STAGE_ROWS", k.stage_rows);
   k.graph = env_int("KNN_GRAPH", k.graph);
+  k.sparse_div = env_int("KNN_SPARSE_DIV", k.sparse_div);
   return k;
 }
 
@@ -191,6 +192,7 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.G.mp = db->mp;
   E.G.kmax = kmax;
   E.G.metric = db->metric;
+  E.G.sparse_div = K.sparse_div;
   // grouped sampling needs the shared query tile (16 rows of mp bytes) in LDS
   // (its exact rounds use the shifted int8 copy for squared l2, and fall back to
   // per-slot sums for l1)

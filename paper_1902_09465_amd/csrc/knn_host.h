@@ -22,6 +22,8 @@ struct Knobs {
   int32_t stage_min = 1 << 30;  // LDS-staged rows from this round size (off)
   int32_t stage_rows = 8;
   int32_t graph = 1;        // capture and replay repeated batches
+  int32_t sparse_div = 16;  // point-major batches: slots with <= n / sparse_div undecided points switch
+                            // to per-slot lists (0: never)
 };
 }  // namespace knn
 

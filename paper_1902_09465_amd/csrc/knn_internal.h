@@ -121,9 +121,11 @@ struct Geometry {
   int32_t stage;        // grouped sampled rounds: point rows per LDS tile (0: gather from HBM)
   int32_t kmax;         // largest k of the slots' queries
   int32_t metric;       // KNN_METRIC_L2 (samples (x_ij - x_j)^2) or KNN_METRIC_L1 (|x_ij - x_j|)
-  int32_t flagsets;     // 1: slots keep no point lists (implicit 2 after round 0): every
-                        // kernel of the batch reads the sets from the flags
-  int32_t pad2;
+  int32_t flagsets;     // 1: point-major batch: dense slots (implicit 1/2) keep their sums
+                        // point-major and their sets in the flags; sparse slots (implicit 0)
+                        // use the per-slot list kernels
+  int32_t sparse_div;   // a dense slot turns sparse once its undecided count is <= n / sparse_div
+                        // (0: never)
 };
 
 // Order-preserving map of a non-NaN double to uint64 (and back).

@@ -18,7 +18,8 @@ enum ProfKind {
   PROF_NAIVE_REST = 6, // naive query prep + merge (+ f32 rescoring)
   PROF_EXACT = 7,      // k_sample launches of a lock-step batch's exact round
   PROF_QL_AUX = 8,     // query-lane sampling: flag transpose + fold of the round totals
-  PROF_KINDS = 9
+  PROF_SPARSE = 9,     // point-major batches: per-slot sampling / exact sums of their sparse slots
+  PROF_KINDS = 10
 };
 
 bool prof_enabled();

@@ -53,7 +53,7 @@ def test_tiny_config_parity(P, orc, seed):
         assert set(planted.tolist()) <= set(ref.tolist())
 
 
-@pytest.mark.parametrize("dtype", ["u8", "u8_staged", "u8_qlane", "u8_qlane_pure", "f32",
+@pytest.mark.parametrize("dtype", ["u8", "u8_staged", "u8_qlane", "u8_qlane_pure", "u8_qlane_pure_sparse", "f32",
                                    "u8_norepl", "u8_qlane_norepl", "u8_ungrouped_norepl", "f32_norepl"])
 def test_per_round_state_parity(P, orc, dtype, monkeypatch):
     """After every decide step the per-point (S, flags, round) equal the oracle's."""
@@ -63,6 +63,8 @@ def test_per_round_state_parity(P, orc, dtype, monkeypatch):
         monkeypatch.setenv("KNN_STAGE_ROWS", "16")
     if dtype.startswith("u8_qlane"):  # query-lane sampling even for a single slot
         monkeypatch.setenv("KNN_QL_MIN", "1")
+    if dtype.endswith("_sparse"):  # per-slot lists from round 1 on
+        monkeypatch.setenv("KNN_SPARSE_DIV", "1")
     if dtype.startswith("u8_ungrouped"):  # the per-query sampling kernel
         monkeypatch.setenv("KNN_GROUP", "0")
     if dtype.startswith("u8"):
@@ -72,7 +74,7 @@ def test_per_round_state_parity(P, orc, dtype, monkeypatch):
     db = P.KnnDB(dev(X))
     # candidate-exact on, except in the pure variant (fused fold + selection)
     kw = dict(h=4, delta=0.05, seed=int(g.integers(1 << 40)), b0=8, growth=1.5,
-              c_exact=0 if dtype.endswith("pure") else 3, sampling=1 if dtype.endswith("norepl") else 0)
+              c_exact=0 if "pure" in dtype else 3, sampling=1 if dtype.endswith("norepl") else 0)
     T = orc.schedule(8, 1.5, 1.0, X.shape[1])
     for r in range(1, len(T) + 2):
         S, fl, ri = db.adaptive_state(dev(Q), 6, P.default_params(**kw), r)
@@ -130,6 +132,8 @@ def test_more_queries_than_slots(P, orc):
 
 KNOBS = ([{"KNN_LPP": v} for v in ("1", "2", "4", "8", "16", "32", "64")] +
          [{"KNN_QL_MIN": "1"}, {"KNN_QL_MIN": "1", "KNN_GROUP": "0"}] +
+         # query-lane batches whose slots switch to per-slot lists after round 0, or never
+         [{"KNN_QL_MIN": "1", "KNN_SPARSE_DIV": "1"}, {"KNN_QL_MIN": "1", "KNN_SPARSE_DIV": "0"}] +
          [{"KNN_CH_SAMPLE": v} for v in ("64", "256", "4096")] + [{"KNN_GROUP": "0"}] +
          # every sampled round from point rows staged in LDS, at each tile height
          [{"KNN_STAGE_MIN": "4", "KNN_STAGE_ROWS": v} for v in ("8", "16", "32", "64")] +

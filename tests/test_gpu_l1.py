@@ -139,14 +139,16 @@ def test_l1_tiny_parity(P, orc, seed):
             assert set(planted.tolist()) <= set(ref.tolist())
 
 
-@pytest.mark.parametrize("path", ["u8", "u8_ungrouped", "u8_qlane", "u8_qlane_pure", "u8_norepl",
-                                  "u8_qlane_norepl", "f32", "f32_norepl"])
+@pytest.mark.parametrize("path", ["u8", "u8_ungrouped", "u8_qlane", "u8_qlane_pure", "u8_qlane_pure_sparse",
+                                  "u8_norepl", "u8_qlane_norepl", "f32", "f32_norepl"])
 def test_l1_per_round_state_parity(P, orc, path, monkeypatch):
     """After every decide step the per-point (S, flags, round) equal the oracle's."""
     if path.startswith("u8_qlane"):
         monkeypatch.setenv("KNN_QL_MIN", "1")
     if path.startswith("u8_ungrouped"):
         monkeypatch.setenv("KNN_GROUP", "0")
+    if path.endswith("_sparse"):  # per-slot lists from round 1 on
+        monkeypatch.setenv("KNN_SPARSE_DIV", "1")
     g = rng(78)
     if path.startswith("u8"):
         X, Q = gmm_u8(78, n=5003, m=202, n_centres=6, sigma=25.0, nq=1)
@@ -154,7 +156,7 @@ def test_l1_per_round_state_parity(P, orc, path, monkeypatch):
         X, Q = gmm_f32(78, n=5003, m=101, n_centres=6, sigma=0.3, nq=1)
     db = l1db(P, X)
     kw = dict(h=4, delta=0.05, seed=int(g.integers(1 << 40)), b0=8, growth=1.5,
-              c_exact=0 if path.endswith("pure") else 3, sampling=1 if path.endswith("norepl") else 0)
+              c_exact=0 if "pure" in path else 3, sampling=1 if path.endswith("norepl") else 0)
     T = orc.schedule(8, 1.5, 1.0, X.shape[1])
     for r in range(1, len(T) + 2):
         S, fl, ri = db.adaptive_state(dev(Q), 6, P.default_params(**kw), r)
@@ -165,7 +167,8 @@ def test_l1_per_round_state_parity(P, orc, path, monkeypatch):
         assert np.array_equal(ri, rio), f"round {r}: round index differs"
 
 
-KNOBS = [{}, {"KNN_GROUP": "0"}, {"KNN_QL_MIN": "1"}, {"KNN_QL": "0"}, {"KNN_LPP": "4"},
+KNOBS = [{}, {"KNN_GROUP": "0"}, {"KNN_QL_MIN": "1"}, {"KNN_QL_MIN": "1", "KNN_SPARSE_DIV": "1"}, {"KNN_QL": "0"},
+         {"KNN_LPP": "4"},
          {"KNN_CH_SAMPLE": "100"}, {"KNN_STAGE_MIN": "4", "KNN_STAGE_ROWS": "16"}]
 
 
@@ -179,6 +182,7 @@ def test_l1_batched_paths_parity(P, orc, knob, sampling, monkeypatch):
     X, Q = gmm_u8(14, n=3001, m=200, n_centres=5, sigma=20.0, nq=20)
     db = l1db(P, X)
     check_batch(P, orc, db, X, Q, 6, h=6, delta=0.05, seed=3, c_exact=4, sampling=sampling)
+    check_batch(P, orc, db, X, Q, 6, h=6, delta=0.05, seed=4, c_exact=0, sampling=sampling)
 
 
 def test_l1_query_lane_batch_large(P, orc):
