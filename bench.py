@@ -524,12 +524,15 @@ def main():
                  "launches": samp["launches"], "ops_per_launch": s_ops,
                  # bytes per launch if every query read its own samples (no sharing)
                  "alg_bytes_per_launch_unshared": alg_bytes / max(1, samp["launches"] + exr["launches"])}
-    # with the draws shared by all queries of the batch: the round totals D
-    # [n][1024] u32 written, the point-major flags A [n][1024] read in every
-    # round but the first, and one byte per distinct draw
+    # with the draws shared by all queries of the batch: the running sums D
+    # [n][1024] u32 written in every round and read in every round but the
+    # first, the point-major flags A [n][1024] read in every round but the
+    # first, and one byte per distinct draw
     r_per_step = samp["launches"] / max(1, args.steps)
-    rl_sample["alg_bytes_per_launch"] = (N * NQ * 4 + N * NQ * (r_per_step - 1) / max(1.0, r_per_step)
-                                         + draws / max(1, samp["launches"]))
+    later = (r_per_step - 1) / max(1.0, r_per_step)  # fraction of the launches after round 0
+    rl_sample["alg_bytes_per_launch"] = (N * NQ * 4 + N * NQ * (4 + 1) * later + draws / max(1, samp["launches"]))
+    if rl_sample["traffic"]:
+        rl_sample["achieved_hbm_gbs"] = rl_sample["traffic"] / s_avg / 1e9 if s_avg > 0 else 0.0
     rl_sample["frac"] = rl_sample["achieved"] / DOT4_PEAK_TOPS
     if not l1:
         rl_sample["traffic"] = stored_traffic()

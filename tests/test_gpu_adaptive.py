@@ -368,3 +368,47 @@ def test_without_replacement_batched(P, orc):
         ref, rst = orc.adaptive(X, Q[q], 10, oparams(orc, **kw))
         assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
         assert int(base[2][q]["coord_evals"]) == rst["coord_evals"]
+
+
+def test_batched_int_config_sampled(P, orc):
+    """The batched-integer workload at full size (n = 100,000 x m = 3072 uint8
+    32-centre mixture, 1,024 queries, k = h = 10, delta = 0.01) in the launch
+    configuration the benchmark times (one query-lane batch with point-major
+    sums, graph replay on the second call): every set contains the true 10-NN
+    of the exact scan, the replay equals the eager call, and sampled queries
+    equal the oracle exactly (indices and statistics)."""
+    X, Q = gmm_u8(2000, n=100_000, m=3072, n_centres=32, sigma=30.0, nq=1024)
+    db = P.KnnDB(dev(X))
+    Qd = dev(Q)
+    p = P.default_params(h=10, delta=0.01, seed=12345)
+    idx, cnt, st = db.adaptive(Qd, 10, p)
+    idx2, cnt2, _ = db.adaptive(Qd, 10, p, with_stats=False)
+    assert torch.equal(idx, idx2) and torch.equal(cnt, cnt2)
+    nidx, ndist = db.naive(Qd, 10)
+    idx_c, cnt_c, nidx, ndist = idx.cpu().numpy(), cnt.cpu().numpy(), nidx.cpu().numpy(), ndist.cpu().numpy()
+    for qi in range(1024):
+        got = idx_c[qi, :cnt_c[qi]]
+        dk = ndist[qi, 9]
+        assert set(nidx[qi][ndist[qi] < dk].tolist()) <= set(got.tolist()), qi
+    for qi in (0, 517):
+        ref, rst = orc.adaptive(X, Q[qi], 10, oparams(orc, h=10, delta=0.01, seed=12345))
+        assert idx_c[qi, :cnt_c[qi]].tolist() == ref.tolist(), qi
+        assert (int(st[qi]["coord_evals"]), int(st[qi]["rounds"]), int(st[qi]["exact_points"])) == \
+            (rst["coord_evals"], rst["rounds"], rst["exact_points"]), qi
+
+
+def test_float_config_sampled(P, orc):
+    """The float workload at full DB size (n = 1,000,000 x m = 128 fp32,
+    1,000-cluster mixture, k = h = 10, delta = 0.05), 256 of its queries in
+    one call: sampled queries equal the oracle (fixed-point sums, FP64
+    decisions) and contain the FP64 10-NN."""
+    X, Q = gmm_f32(3000, n=1_000_000, m=128, n_centres=1000, sigma=0.1, nq=256)
+    db = P.KnnDB(dev(X))
+    p = P.default_params(h=10, delta=0.05, seed=77)
+    idx, cnt, st = db.adaptive(dev(Q), 10, p)
+    idx_c, cnt_c = idx.cpu().numpy(), cnt.cpu().numpy()
+    for qi in (0, 255):
+        ref, rst = orc.adaptive(X, Q[qi], 10, oparams(orc, h=10, delta=0.05, seed=77))
+        assert idx_c[qi, :cnt_c[qi]].tolist() == ref.tolist(), qi
+        assert int(st[qi]["coord_evals"]) == rst["coord_evals"], qi
+        assert contains_knn(ref, brute_dists(X, Q[qi]), 10, rtol=1e-9)
