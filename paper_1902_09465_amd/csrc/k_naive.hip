@@ -206,11 +206,12 @@ __device__ __forceinline__ uint64_t merge_sorted64(uint64_t list, uint64_t cand)
 // the l1 distance sum_j |x_j - q_j| by v_sad_u8 (MET = l1, zero-padded u8
 // rows).  Either way lane l of wave w = 2 wq + wp ends with the value of
 // query 32 wq + 16 a + 4 (l / 16) + v and point 64 wp + 16 b + l % 16 in
-// acc[a][b][v] (the MFMA output layout).  The K loop is double-buffered: the
-// next 128-byte slice is loaded into registers while the current one is
-// consumed from LDS (one barrier per slice).  Rows beyond nq / pend read as
-// zeros.  smem: 2 x STAGE bytes.
-template <int MET>
+// acc[a][b][v] (the MFMA output layout).  The K loop runs over 128-byte
+// slices through two LDS buffers (one barrier per slice); the global loads
+// of the next PF slices are in flight in registers while the current slice
+// is consumed, so each load has PF slices of compute to arrive.  Rows beyond
+// nq / pend read as zeros.  smem: 2 x STAGE bytes.
+template <int MET, int PF = 1>
 __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int64_t nq, const int8_t *__restrict__ X8,
                                              int64_t q0, int64_t p0, int64_t pr1, int64_t mp, uint8_t *smem,
                                              v4i (&acc)[2][4]) {
@@ -296,19 +297,29 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
           acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
   };
+  static_assert(BK == 128, "load and store map eight 16-byte pieces per row");
   const int nsl = nks + (tail ? 1 : 0);
-  v4i ra[2], rb[4];
-  load(0, nks ? BK : tail, ra, rb);
-  store(0, ra, rb);
+  auto width = [&](int s) { return s < nks ? BK : tail; };
+  // PF register stages: stage u holds slices u, u + PF, ...; a stage is
+  // refilled once its slice is in LDS, PF slices before it is stored again
+  constexpr int NS = PF;
+  v4i ra[NS][2], rb[NS][4];
+#pragma unroll
+  for (int u = 0; u < NS; ++u)
+    if (u < nsl) load((int64_t)u * BK, width(u), ra[u], rb[u]);
+  store(0, ra[0], rb[0]);
   __syncthreads();
-  for (int sl = 0; sl < nsl; ++sl) {
-    const int buf = sl & 1;
-    const bool more = sl + 1 < nsl;
-    const int wnext = (sl + 1 < nks) ? BK : tail;
-    if (more) load((int64_t)(sl + 1) * BK, wnext, ra, rb);
-    compute(buf, sl < nks ? BK : tail);
-    if (more) store(buf ^ 1, ra, rb);
-    __syncthreads();
+  for (int base = 0; base < nsl; base += NS) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int sl = base + u;
+      if (sl >= nsl) break;
+      // stage u was stored to LDS in the previous iteration: refill it
+      if (sl + NS < nsl) load((int64_t)(sl + NS) * BK, width(sl + NS), ra[u], rb[u]);
+      compute(sl & 1, width(sl));
+      if (sl + 1 < nsl) store((sl + 1) & 1, ra[(u + 1) % NS], rb[(u + 1) % NS]);
+      __syncthreads();
+    }
   }
 }
 
@@ -512,24 +523,44 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
   const int64_t p0 = (w / nqt) * NBP;
   const int64_t q0 = (w % nqt) * NBQ;
   const int64_t pend = std::min(n, p0 + NBP);
+  // which of the tile's slots take this pass (read once, before the K loop)
+  __shared__ uint8_t take[NBQ];
+  if (threadIdx.x < NBQ) {
+    const int64_t s = q0 + threadIdx.x;
+    bool t = s < ns && slots[s].state == 1 && slots[s].cur == cur;
+    if (t && G.flagsets && slots[s].implicit == 0) t = false;  // a sparse slot: its own exact pass
+    take[threadIdx.x] = t ? 1 : 0;
+  }
   v4i acc[2][4];
-  gemm_u8_tile<MET>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);
+  gemm_u8_tile<MET, 3>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);  // (its barriers publish take[])
   const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
   uint64_t my_pairs = 0;
+  // the pairs' flags first, all loads in flight together (flag 0: an
+  // undecided sampled pair, the only ones made exact; every pair in round 0)
+  uint8_t fv[2][4][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+      const int64_t s = q0 + ql;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
+        fv[a][v][b] = (take[ql] && i < n) ? (impl ? (uint8_t)0 : B.fl[s * n + i]) : (uint8_t)1;
+      }
+    }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t s = q0 + 32 * wq + 16 * a + 4 * (lane >> 4) + v;
-      if (s >= ns || slots[s].state != 1 || slots[s].cur != cur) continue;
-      if (G.flagsets && slots[s].implicit == 0) continue;  // a sparse slot: its own exact pass
-      const int64_t qs = MET == KNN_METRIC_L1 ? 0 : qn[s];
+      const int64_t qs = (MET == KNN_METRIC_L1 || s >= ns) ? 0 : qn[s];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
+        if (fv[a][v][b] != 0) continue;
         const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
-        if (i >= n) continue;
         const int64_t off = s * n + i;
-        if (!impl && B.fl[off] != 0) continue;  // not an undecided sampled pair
         const int64_t v64 = MET == KNN_METRIC_L1 ? (int64_t)(uint32_t)acc[a][b][v]
                                                  : qs + (int64_t)xn[i] - 2 * (int64_t)acc[a][b][v];
         if (G.flagsets) {
