@@ -349,13 +349,12 @@ __global__ __launch_bounds__(256) void k_naive_u8_k64(const int8_t *__restrict__
   const int64_t pr0 = (int64_t)blockIdx.x * prange;
   const int64_t pr1 = std::min(n, pr0 + prange);
   const int wq = wave >> 1, wp = wave & 1;
-  uint64_t L[QPW];   // lane j: j-th smallest of query wave*QPW + t
-  uint64_t tau[QPW]; // k-th smallest (PAD while fewer than k)
+  uint64_t L[QPW];   // lane j: j-th smallest of query wave*QPW + t (its k-th, read from lane k - 1,
+                     // is the filter threshold; PAD while fewer than k)
   int cnt[QPW];      // keys in the query's buffer
 #pragma unroll
   for (int t = 0; t < QPW; ++t) {
     L[t] = PAD;
-    tau[t] = PAD;
     cnt[t] = 0;
   }
   for (int64_t p0 = pr0; p0 < pr1; p0 += NBP) {
@@ -383,7 +382,8 @@ __global__ __launch_bounds__(256) void k_naive_u8_k64(const int8_t *__restrict__
       const uint32_t d0 = Ds[ql * DSTR + lane], d1 = Ds[ql * DSTR + lane + 64];
       const uint64_t c0 = d0 == 0xFFFFFFFFu ? PAD : (((uint64_t)d0 << 32) | (uint64_t)(p0 + lane));
       const uint64_t c1 = d1 == 0xFFFFFFFFu ? PAD : (((uint64_t)d1 << 32) | (uint64_t)(p0 + lane + 64));
-      const bool a0 = c0 < tau[t], a1 = c1 < tau[t];
+      const uint64_t tau = wave_bcast_u64(L[t], k - 1);
+      const bool a0 = c0 < tau, a1 = c1 < tau;
       const uint64_t m0 = __ballot(a0), m1 = __ballot(a1);
       if ((m0 | m1) == 0) continue;  // wave-uniform
       const int n0 = __popcll(m0), n1 = __popcll(m1);
@@ -393,7 +393,6 @@ __global__ __launch_bounds__(256) void k_naive_u8_k64(const int8_t *__restrict__
         if (cnt[t] > 0) L[t] = merge_sorted64(L[t], lane < cnt[t] ? Cb[ql][lane] : PAD);
         L[t] = merge_sorted64(L[t], a0 ? c0 : PAD);
         L[t] = merge_sorted64(L[t], a1 ? c1 : PAD);
-        tau[t] = wave_bcast_u64(L[t], k - 1);
         cnt[t] = 0;
         continue;
       }
