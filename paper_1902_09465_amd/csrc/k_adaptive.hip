@@ -102,8 +102,9 @@ __device__ __forceinline__ void point_bounds(const Slot *sl, int64_t m, int64_t 
   }
 }
 
-// p-th element of the kept set P = [act | xa | acc] (identity while implicit;
-// with implicit 2 the caller skips points flagged discarded).
+// p-th element of the kept set P = [act | xa | acc] (identity in round 0).
+// Dense slots of point-major batches (implicit 2) are never enumerated this
+// way: their kernels read the sets from the flags.
 __device__ __forceinline__ int32_t elem_P(const Slot *sl, const SlotArrays &a, int64_t p) {
   if (sl->implicit) return (int32_t)p;
   if (p < sl->n_act) return a.act[p];
@@ -112,8 +113,7 @@ __device__ __forceinline__ int32_t elem_P(const Slot *sl, const SlotArrays &a, i
   return a.acc[p - sl->n_xa];
 }
 
-// p-th element of the undecided set A = [act | xa] (with implicit 2 the
-// caller skips points flagged accepted or discarded).
+// p-th element of the undecided set A = [act | xa] (identity in round 0).
 __device__ __forceinline__ int32_t elem_A(const Slot *sl, const SlotArrays &a, int64_t p) {
   if (sl->implicit) return (int32_t)p;
   if (p < sl->n_act) return a.act[p];
@@ -260,7 +260,6 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
     const int wave = threadIdx.x / kWave, lane = lane_id();
     for (int64_t p = base + wave; p < end; p += BT / kWave) {
       const int32_t i = implicit ? (int32_t)p : a.act[p];
-      if (implicit == 2 && a.fl[i] != 0) continue;  // not an undecided sampled point
       const uint8_t *row = X + (int64_t)i * m * elem;
       int64_t acc = 0;
       if constexpr (DT == KNN_U8) {
@@ -320,7 +319,6 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
   const int ph = perm_half_bits(mm);
   for (int64_t p = base + threadIdx.x / lpp; p < end; p += BT / lpp) {
     const int32_t i = implicit ? (int32_t)p : a.act[p];
-    if (implicit == 2 && a.fl[i] != 0) continue;  // (uniform over the point's lanes)
     const uint8_t *row = X + (int64_t)i * m * elem;
     const PermKey pk = norepl ? perm_key((uint32_t)i, k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
     int64_t acc = 0;
@@ -1085,7 +1083,7 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
 #pragma unroll
   for (int e = 0; e < SEL_E; ++e) {
     const int64_t p = base + (int64_t)e * NT + threadIdx.x;
-    if (p < nP && !(sl->implicit == 2 && (a.fl[elem_P(sl, a, p)] & FL_DISC))) {
+    if (p < nP) {
       const int32_t i = elem_P(sl, a, p);
       double d, al;
       point_bounds(sl, m, a.S[i], a.fl[i], a.ri[i], d, al);
@@ -1531,7 +1529,6 @@ __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B,
       const int32_t i = elem_A(sl, a, p);
       id[e] = i;
       const uint8_t f = a.fl[i];
-      if (sl->implicit == 2 && (f & (FL_DISC | FL_ACC))) continue;  // decided earlier
       double d, al;
       point_bounds(sl, m, a.S[i], f, a.ri[i], d, al);
       const double ucb = d + al, lcb = d - al;
