@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "knn_prof.h"
+
 namespace knn {
 
 constexpr int kWave = 64;
@@ -164,6 +166,39 @@ __device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v) {
     }
   }
   return v;
+}
+
+// The same network on one 32-bit key per lane (one exchange per step).
+__device__ __forceinline__ uint32_t wave_sort_u32(uint32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t o = (uint32_t)__shfl_xor((int)v, j);
+      const bool keep_min = (((l & j) == 0) == ((l & k) == 0));
+      v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+    }
+  }
+  return v;
+}
+
+// This block's copy of the measurement counters (kProfCopies copies,
+// kProfStride words apart).
+__device__ __forceinline__ uint64_t *prof_copy(uint64_t *c) {
+  return c + ((blockIdx.x + blockIdx.y * gridDim.x) % (unsigned)kProfCopies) * (unsigned)kProfStride;
+}
+
+// Adds each lane's v to *ctr with one atomic per wave (every lane of the
+// wave must be active): a per-lane atomic on one address serialises at L2.
+__device__ __forceinline__ void wave_count_add(uint64_t *ctr, uint64_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
+    v += ((uint64_t)hi << 32) | lo;
+  }
+  if (lane_id() == 0 && v != 0) atomicAdd(ctr, v);
 }
 
 // Lane l receives lane (63 - l)'s value.

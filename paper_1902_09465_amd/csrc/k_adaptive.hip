@@ -12,6 +12,9 @@
 //   k_select_merge    U, L1, L2 for the slot (eq. d_ind in round form)
 //   k_decide          discard / accept / keep, compacting the undecided list
 //   k_finish          stop rule, output, next round, admission of new queries
+// Query-lane batches that keep their running sums point-major use
+// k_sample_ql_u8 (or the exact round as one tiled pass), k_select_pm,
+// k_select_merge_pm and k_decide_pm instead, with the sets held as flags.
 // All decisions use the same IEEE double expressions as the CPU oracle
 // (compiled without FMA contraction); sums are integers, so the result does
 // not depend on launch shape, chunking or atomic order.
@@ -246,13 +249,13 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
     // running sum (read + write), the list entry and the round index
     const uint64_t pts = (uint64_t)(end - base);
     if (cur >= sl->R) {
-      atomicAdd(&G.prof[0], pts * (uint64_t)(m * elem + 14));
-      atomicAdd(&G.prof[2], pts * (uint64_t)m);
+      atomicAdd(&prof_copy(G.prof)[0], pts * (uint64_t)(m * elem + 14));
+      atomicAdd(&prof_copy(G.prof)[2], pts * (uint64_t)m);
     } else {
       const uint64_t B_r = (uint64_t)(sl->T[cur] - (cur ? sl->T[cur - 1] : 0));
-      atomicAdd(&G.prof[0], pts * (B_r * elem + 21));
-      atomicAdd(&G.prof[1], pts * B_r);
-      atomicAdd(&G.prof[3], pts * B_r);  // every sample is its own draw here
+      atomicAdd(&prof_copy(G.prof)[0], pts * (B_r * elem + 21));
+      atomicAdd(&prof_copy(G.prof)[1], pts * B_r);
+      atomicAdd(&prof_copy(G.prof)[3], pts * B_r);  // every sample is its own draw here
     }
   }
   if (cur >= sl->R) {
@@ -660,13 +663,11 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
       }
     }
-    if (G.prof) {
+    if (G.prof) {  // whole waves reach this point
       const uint64_t B_r = (uint64_t)(s_t1 - s_t0);
-      if (my_pairs) {
-        atomicAdd(&G.prof[0], my_pairs * (B_r + 21));
-        atomicAdd(&G.prof[1], my_pairs * B_r);
-      }
-      if (my_pts) atomicAdd(&G.prof[3], my_pts * B_r);
+      wave_count_add(&prof_copy(G.prof)[0], my_pairs * (B_r + 21));
+      wave_count_add(&prof_copy(G.prof)[1], my_pairs * B_r);
+      wave_count_add(&prof_copy(G.prof)[3], my_pts * B_r);
     }
     return;
   }
@@ -734,9 +735,9 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
       my_pairs += 1;
     }
   }
-  if (G.prof && my_pairs) {
-    atomicAdd(&G.prof[0], my_pairs * (uint64_t)(m + 14));
-    atomicAdd(&G.prof[2], my_pairs * (uint64_t)m);
+  if (G.prof) {  // whole waves reach this point
+    wave_count_add(&prof_copy(G.prof)[0], my_pairs * (uint64_t)(m + 14));
+    wave_count_add(&prof_copy(G.prof)[2], my_pairs * (uint64_t)m);
   }
 }
 
@@ -981,13 +982,11 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
     my_pairs += (uint64_t)__popc(act);
     if (lane == 0) my_pts += 1;
   }
-  if (G.prof) {
+  if (G.prof) {  // whole waves reach this point (a wave with nothing to do left together)
     const uint64_t B_r = (uint64_t)(R.t1 - R.t0);
-    if (my_pairs) {
-      atomicAdd(&G.prof[0], my_pairs * (B_r + 21));
-      atomicAdd(&G.prof[1], my_pairs * B_r);
-    }
-    if (my_pts) atomicAdd(&G.prof[3], my_pts * B_r);
+    wave_count_add(&prof_copy(G.prof)[0], my_pairs * (B_r + 21));
+    wave_count_add(&prof_copy(G.prof)[1], my_pairs * B_r);
+    wave_count_add(&prof_copy(G.prof)[3], my_pts * B_r);
   }
 }
 
@@ -1159,6 +1158,106 @@ __device__ void wave_smallest(const uint64_t (&key)[E], int K, uint64_t *out, ui
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The K (<= 64) smallest of N keys get(p), p in [0, N) (PAD = ~0 is no
+// key), ascending across the lanes (PAD past the real keys); the method of
+// wave_smallest with the keys read twice instead of held in registers.
+template <typename Get>
+__device__ uint64_t wave_smallest_gen(int64_t N, Get get, int K, uint64_t *cbuf) {
+  constexpr uint64_t PAD = ~0ull;
+  const int lane = lane_id();
+  uint64_t mn = PAD;
+  for (int64_t p = lane; p < N; p += kWave) {
+    const uint64_t v = get(p);
+    mn = v < mn ? v : mn;
+  }
+  const uint64_t tau = wave_bcast_u64(wave_sort_u64(mn), K - 1);
+  int cnt = 0;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  for (int64_t p0 = 0; p0 < N; p0 += kWave) {  // wave-uniform trip count
+    const int64_t p = p0 + lane;
+    const uint64_t v = p < N ? get(p) : PAD;
+    const bool c = v <= tau && v != PAD;
+    const uint64_t mk = __ballot(c);
+    const int pos = cnt + __popcll(mk & lt);
+    if (c && pos < kWave) cbuf[pos] = v;
+    cnt += __popcll(mk);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint64_t best = PAD;
+  if (cnt <= kWave) {
+    best = wave_sort_u64(lane < cnt ? cbuf[lane] : PAD);
+  } else {
+    for (int64_t p0 = 0; p0 < N; p0 += kWave) {
+      const int64_t p = p0 + lane;
+      const uint64_t c = wave_sort_u64(p < N ? get(p) : PAD);
+      const uint64_t r = wave_bcast_rev_u64(c);  // descending
+      uint64_t v = best < r ? best : r;          // bitonic: the 64 smallest of both
+#pragma unroll
+      for (int j = kWave / 2; j > 0; j >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, j);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
+      }
+      best = v;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();  // cbuf is reused by the next call
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return best;
+}
+
+// The same selection on 32-bit keys (PAD = ~0u, above every real key): the
+// K smallest come back ascending across the lanes, lane l holding the l-th
+// (PAD past the real keys).
+template <int E>
+__device__ uint32_t wave_smallest_u32(const uint32_t (&key)[E], int K, uint32_t *cbuf) {
+  constexpr uint32_t PAD = ~0u;
+  const int lane = lane_id();
+  uint32_t mn = key[0];
+#pragma unroll
+  for (int e = 1; e < E; ++e) mn = key[e] < mn ? key[e] : mn;
+  const uint32_t tau = (uint32_t)__shfl((int)wave_sort_u32(mn), K - 1);
+  int cnt = 0;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const bool c = key[e] <= tau && key[e] != PAD;
+    const uint64_t mk = __ballot(c);
+    const int pos = cnt + __popcll(mk & lt);
+    if (c && pos < kWave) cbuf[pos] = key[e];
+    cnt += __popcll(mk);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint32_t best;
+  if (cnt <= kWave) {
+    best = wave_sort_u32(lane < cnt ? cbuf[lane] : PAD);
+  } else {
+    best = wave_sort_u32(key[0]);
+#pragma unroll
+    for (int e = 1; e < E; ++e) {
+      const uint32_t c = wave_sort_u32(key[e]);
+      const uint32_t r = (uint32_t)__shfl((int)c, kWave - 1 - lane);  // descending
+      uint32_t v = best < r ? best : r;                                // bitonic: the 64 smallest of both
+#pragma unroll
+      for (int j = kWave / 2; j > 0; j >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, j);
+        v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
+      }
+      best = v;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();  // cbuf is reused by the next call
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return best;
+}
+
 
 // Batches that keep their sums point-major (G.flagsets): D[i][s] is the
 // running sum S of pair (s, i) (the exact distance once the pair is exact),
@@ -1201,13 +1300,13 @@ __device__ __forceinline__ void pair_bounds(const Slot *sl, const RoundConsts &r
 // Selection for such batches: one block per tile of FS_SL slots x FS_PT
 // points (D transposed through LDS), the tile's k smallest UCB and k+1
 // smallest LCB per slot over the kept points (the partial lists that
-// k_select_merge reads, one per FS_PT points).  In a sampled round 0 every pair is undecided: its flag and round
+// k_select_merge_pm reads, one per FS_PT points).  In a sampled round 0 every pair is undecided: its flag and round
 // index are initialised here.
 __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
                                                   int32_t nqp, Bufs B, Geometry G, int32_t cur, int32_t init) {
-  __shared__ uint32_t t[FS_SL][FS_PT + 1];
+  constexpr int TS = FS_PT + 4;  // row stride in words: rows stay 16-byte aligned
+  __shared__ __align__(16) uint32_t t[FS_SL][TS];
   __shared__ uint64_t cbuf[NT / kWave][kWave];
-  __shared__ uint64_t sbuf[NT / kWave][kWave];
   const int64_t n = G.n, m = G.m;
   const int ns = G.nslots;
   const int64_t ngroups = (nqp + FS_SL - 1) / FS_SL;
@@ -1225,23 +1324,32 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
     }
     if (!any) return;
   }
-  {  // the tile's sums, every load of a thread in flight at once (clamped rows, zeroed after)
-    constexpr int PER = FS_PT * FS_SL / NT;
-    uint32_t v[PER];
+  {  // the tile's sums: one 16-byte load per point (the FS_SL slots; nqp is a
+     // multiple of 16), all in flight at once (clamped rows, zeroed after)
+    static_assert(FS_SL == 4, "one 16-byte load per point");
+    constexpr int PER = FS_PT / NT;
+    uint4 v[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int idx = threadIdx.x + u * NT;
-      const int64_t i = min(i0 + idx / FS_SL, n - 1);
-      v[u] = D[i * nqp + s0 + idx % FS_SL];
+      const int64_t i = min(i0 + threadIdx.x + u * NT, n - 1);
+      v[u] = *reinterpret_cast<const uint4 *>(D + i * nqp + s0);
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int idx = threadIdx.x + u * NT;
-      t[idx % FS_SL][idx / FS_SL] = (i0 + idx / FS_SL < n) ? v[u] : 0u;
+      const int pt = threadIdx.x + u * NT;
+      const bool in = i0 + pt < n;
+      t[0][pt] = in ? v[u].x : 0u;
+      t[1][pt] = in ? v[u].y : 0u;
+      t[2][pt] = in ? v[u].z : 0u;
+      t[3][pt] = in ? v[u].w : 0u;
     }
   }
   __syncthreads();
   const int lane = lane_id(), wave = threadIdx.x / kWave;
+  // whole tile with 4-byte aligned flag rows: each lane takes four runs of
+  // four consecutive points (flags as one word, sums as one 16-byte read)
+  const bool fast = i0 + FS_PT <= n && (n & 3) == 0;
+  constexpr uint32_t PAD32 = ~0u;  // above every sum (S < m * 65025 < 2^32 - 1)
   for (int r = wave; r < FS_SL; r += NT / kWave) {
     const int sl = s0 + r;
     if (sl >= ns) break;
@@ -1249,64 +1357,97 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
     if (slp->state != 1 || slp->cur != cur || slp->implicit == 0) continue;  // wave-uniform; sparse slots elsewhere
     const int k = slp->k;
     const RoundConsts rc = round_consts(slp, m, cur);
-    const uint8_t *flr = B.fl + (int64_t)sl * n + i0;
-    uint8_t fv[FS_E];
+    uint8_t *flr = B.fl + (int64_t)sl * n + i0;
+    // The keys of the kept pairs (their sums; PAD when discarded or past
+    // n) and which classes of kept pairs the tile holds: exact, sampled up
+    // to T[cur], or accepted in an earlier round.
+    uint32_t kt[FS_E];
+    bool has_x = false, has_c = false, has_l = false;
+    if (fast) {
+      static_assert(FS_E == 16 && FS_PT == 4 * 4 * kWave, "four runs of four points per lane");
 #pragma unroll
-    for (int e = 0; e < FS_E; ++e) {  // every flag load in flight at once
-      const int p = e * kWave + lane;
-      fv[e] = init ? (uint8_t)0 : (i0 + p < n ? flr[p] : (uint8_t)FL_DISC);
-    }
-    // When every kept pair of the tile has the same width alpha(T[cur])
-    // (none exact, none accepted in an earlier round), UCB and LCB are both
-    // monotone in d^: the k smallest UCB and the k+1 smallest LCB are
-    // d^ + alpha and d^ - alpha of the k+1 smallest d^, so one selection
-    // serves both lists, with the same values as two separate ones.
-    bool mixed = false;
-#pragma unroll
-    for (int e = 0; e < FS_E; ++e) mixed |= (fv[e] & (FL_EXACT | FL_ACC)) != 0 && !(fv[e] & FL_DISC);
-    const bool uniform = __ballot(mixed) == 0;
-    uint64_t ku[FS_E], kl[FS_E];
-#pragma unroll
-    for (int e = 0; e < FS_E; ++e) {
-      const int p = e * kWave + lane;
-      const int64_t i = i0 + p;
-      ku[e] = kl[e] = ~0ull;
-      const uint8_t f = fv[e];
-      if (i >= n || (f & FL_DISC)) continue;
-      if (uniform) {
-        ku[e] = dkey((double)t[r][p] / rc.TW);
-        continue;
+      for (int u = 0; u < 4; ++u) {
+        const int p0 = 4 * kWave * u + 4 * lane;
+        const uint32_t fw = init ? 0u : *reinterpret_cast<const uint32_t *>(flr + p0);
+        const uint4 tv = *reinterpret_cast<const uint4 *>(&t[r][p0]);
+        constexpr uint32_t ONE = 0x01010101u;
+        const uint32_t kept = ~(fw >> 2) & ONE, ex = fw & ONE, ac = (fw >> 1) & ONE;
+        has_x |= (kept & ex) != 0;
+        has_l |= (kept & ac & ~ex) != 0;
+        has_c |= (kept & ~ac & ~ex) != 0;
+        kt[4 * u + 0] = (fw & 0x00000004u) ? PAD32 : tv.x;
+        kt[4 * u + 1] = (fw & 0x00000400u) ? PAD32 : tv.y;
+        kt[4 * u + 2] = (fw & 0x00040000u) ? PAD32 : tv.z;
+        kt[4 * u + 3] = (fw & 0x04000000u) ? PAD32 : tv.w;
       }
-      const bool late = (f & FL_ACC) && !(f & FL_EXACT);  // accepted before this round
-      double d, al;
-      pair_bounds(slp, rc, (int64_t)t[r][p], f, late ? B.ri[(int64_t)sl * n + i] : (uint8_t)0, !late, d, al);
-      ku[e] = dkey(d + al);
-      kl[e] = dkey(d - al);
-    }
-    if (init) {  // round 0: every pair of the slot is undecided, sampled at round 0
+      if (init) {  // round 0: every pair of the slot is undecided, sampled at round 0
+        uint8_t *rir = B.ri + (int64_t)sl * n + i0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int p0 = 4 * kWave * u + 4 * lane;
+          *reinterpret_cast<uint32_t *>(flr + p0) = 0u;
+          *reinterpret_cast<uint32_t *>(rir + p0) = 0u;
+        }
+      }
+    } else {
 #pragma unroll
       for (int e = 0; e < FS_E; ++e) {
-        const int64_t i = i0 + e * kWave + lane;
-        if (i < n) {
-          B.fl[(int64_t)sl * n + i] = 0;
-          B.ri[(int64_t)sl * n + i] = 0;
+        const int p = e * kWave + lane;
+        const bool in = i0 + p < n;
+        const uint8_t f = init ? (uint8_t)(in ? 0 : FL_DISC) : (in ? flr[p] : (uint8_t)FL_DISC);
+        const bool kept = !(f & FL_DISC);
+        has_x |= kept && (f & FL_EXACT);
+        has_l |= kept && (f & FL_ACC) && !(f & FL_EXACT);
+        has_c |= kept && !(f & (FL_ACC | FL_EXACT));
+        kt[e] = kept ? t[r][p] : PAD32;
+      }
+      if (init) {
+#pragma unroll
+        for (int e = 0; e < FS_E; ++e) {
+          const int p = e * kWave + lane;
+          if (i0 + p < n) {
+            flr[p] = 0;
+            B.ri[(int64_t)sl * n + i0 + p] = 0;
+          }
         }
       }
     }
+    // When every kept pair of the tile has the same divisor and width --
+    // all sampled up to T[cur] (T W, alpha(T[cur])), or all exact (m W, 0)
+    // -- UCB and LCB are both monotone in d^, and d^ is monotone in the
+    // integer sum S: the k smallest UCB and the k+1 smallest LCB are
+    // d^ + width and d^ - width of the k+1 smallest sums, so one selection
+    // on the 32-bit sums serves both lists, with the same values as two
+    // separate ones.  Pairs accepted in an earlier round keep their own
+    // round's bounds and take the general path.
+    const bool any_x = __ballot(has_x) != 0;
+    const bool uniform = __ballot(has_l) == 0 && (!any_x || __ballot(has_c) == 0);
     uint64_t *out = B.part + (int64_t)sl * B.part_stride + tile * (2 * k + 1);
     if (uniform) {
-      wave_smallest<FS_E>(ku, k + 1, sbuf[wave], cbuf[wave]);  // the k+1 smallest d^ (PAD past the real ones)
+      const uint32_t b = wave_smallest_u32<FS_E>(kt, k + 1, reinterpret_cast<uint32_t *>(cbuf[wave]));
       constexpr uint64_t PAD = ~0ull;
       if (lane < k + 1) {
-        const uint64_t kd = sbuf[wave][lane];
-        const double d = dkey_inv(kd);
-        if (lane < k) out[lane] = kd == PAD ? PAD : dkey(d + rc.a);
-        out[k + lane] = kd == PAD ? PAD : dkey(d - rc.a);
+        double d, al;  // the bounds of a pair with sum b, as pair_bounds gives them
+        pair_bounds(slp, rc, (int64_t)b, any_x ? (uint8_t)FL_EXACT : (uint8_t)0, (uint8_t)0, true, d, al);
+        if (lane < k) out[lane] = b == PAD32 ? PAD : dkey(d + al);
+        out[k + lane] = b == PAD32 ? PAD : dkey(d - al);
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();  // sbuf is reused by the next row
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
+    } else {  // (the flag writes of round 0 above are this wave's own: visible to its reads)
+      uint64_t ku[FS_E], kl[FS_E];
+#pragma unroll
+      for (int e = 0; e < FS_E; ++e) {
+        const int p = e * kWave + lane;
+        const int64_t i = i0 + p;
+        ku[e] = kl[e] = ~0ull;
+        if (i >= n) continue;
+        const uint8_t f = flr[p];
+        if (f & FL_DISC) continue;
+        const bool late = (f & FL_ACC) && !(f & FL_EXACT);  // accepted before this round
+        double d, al;
+        pair_bounds(slp, rc, (int64_t)t[r][p], f, late ? B.ri[(int64_t)sl * n + i] : (uint8_t)0, !late, d, al);
+        ku[e] = dkey(d + al);
+        kl[e] = dkey(d - al);
+      }
       wave_smallest<FS_E>(ku, k, out, cbuf[wave]);
       wave_smallest<FS_E>(kl, k + 1, out + k, cbuf[wave]);
     }
@@ -1385,14 +1526,12 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
   const bool run = srun[c] != 0;
   int c_act = 0, c_xa = 0, c_acc = 0;
   if (sl < nqp) {
-    double U = 0, L1 = 0, L2 = 0;
-    const Slot *slp = &slots[run ? sl : 0];
-    RoundConsts rc{1.0, 0.0, 1.0};
+    // the decisions as thresholds on the sums (k_select_merge_pm derives them
+    // from U, L1, L2 with the FP64 bounds), so no pair needs a division
+    int64_t th[4] = {0, 0, 0, 0};
     if (run) {
-      U = slp->U;
-      L1 = slp->L1;
-      L2 = slp->L2;
-      rc = round_consts(slp, m, cur);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) th[q] = slots[sl].sthr[q];
     }
     // DQ_B points per batch: their sums are loaded together, so the loads'
     // latency is paid once per batch
@@ -1410,13 +1549,11 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
         if (p >= pts) break;
         uint8_t f = ft[c][p];
         if (run && !(f & (FL_ACC | FL_DISC))) {
-          double d, al;
-          pair_bounds(slp, rc, (int64_t)sv[b], f, (uint8_t)cur, true, d, al);
-          const double ucb = d + al, lcb = d - al;
           const bool exact = (f & FL_EXACT) != 0;
-          if (lcb > U) {
+          const int64_t S = sv[b];
+          if (S > (exact ? th[2] : th[0])) {
             f |= FL_DISC | 0x80;
-          } else if (exact ? (ucb <= L1) : (ucb <= L2)) {
+          } else if (S <= (exact ? th[3] : th[1])) {
             f |= FL_ACC | 0x80;
             ++c_acc;
           } else if (exact) {
@@ -1464,17 +1601,45 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
 
 constexpr int MT = 1024;  // merge / finish block size
 
-// fs_chunk > 0: the partials came from k_select_pm, one per fs_chunk
-// points of [0, n); otherwise from k_select_partial, one per SEL_CH of P.
-__global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, Bufs B, Geometry G, int32_t fs_chunk) {
+// The decisions of an undecided pair at the current round as integer
+// thresholds on its sum S.  d = S / (T W) (or S / (m W) once exact) is a
+// correctly rounded quotient of an exactly represented integer, hence
+// non-decreasing in S, and so are UCB and LCB: "not discarded" (LCB <= U)
+// and "accepted" (UCB <= L2, or d <= L1 for an exact pair) hold exactly for
+// the sums up to some threshold.  The threshold is found by bisection over
+// [-1, 2^32) with the same FP64 expressions as every other decision (kind
+// 0/1: keep/accept of a sampled pair, 2/3: of an exact pair); -1 means no
+// sum qualifies.
+__device__ int64_t sum_threshold(const Slot *sl, const RoundConsts &rc, int kind, double U, double L1, double L2) {
+  const bool exact = kind >= 2, accept = (kind & 1) != 0;
+  auto holds = [&](int64_t S) -> bool {
+    double d, al;
+    pair_bounds(sl, rc, S, exact ? (uint8_t)FL_EXACT : (uint8_t)0, (uint8_t)0, true, d, al);
+    const double ucb = d + al, lcb = d - al;
+    if (!accept) return !(lcb > U);
+    return exact ? (ucb <= L1) : (ucb <= L2);
+  };
+  int64_t lo = -1, hi = (int64_t)1 << 32;  // holds below lo + 1, fails from hi on
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (holds(mid))
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// U, L1, L2 from the partial lists of k_select_partial (one per SEL_CH
+// elements of P).  skip_dense: the dense slots of a point-major batch are
+// k_select_merge_pm's.
+__global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, Bufs B, Geometry G, int32_t skip_dense) {
   const int s = blockIdx.x;
   Slot *sl = &slots[s];
   if (sl->state != 1) return;
+  if (skip_dense && sl->implicit != 0) return;
   const int64_t nP = size_P(sl, G.n);
-  // partial lists: per fs_chunk points of [0, n) (dense slots of point-major
-  // batches), else per SEL_CH elements of P
-  const bool dense = fs_chunk > 0 && (!G.flagsets || sl->implicit != 0);
-  const int64_t nch = dense ? (G.n + fs_chunk - 1) / fs_chunk : (nP + SEL_CH - 1) / SEL_CH;
+  const int64_t nch = (nP + SEL_CH - 1) / SEL_CH;
   const int k = sl->k;
   const int64_t w = 2 * k + 1;
   const uint64_t *part = B.part + (int64_t)s * B.part_stride;
@@ -1489,6 +1654,44 @@ __global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, B
     sl->U = dkey_inv(U);
     sl->L1 = dkey_inv(L1);
     sl->L2 = dkey_inv(L2);
+  }
+}
+
+// The same for the dense slots of a point-major batch, one wave per slot
+// over the partial lists of k_select_pm (one per FS_PT points of [0, n));
+// also the decisions as thresholds on the sums, for k_decide_pm.
+__global__ __launch_bounds__(NT) void k_select_merge_pm(Slot *__restrict__ slots, Bufs B, Geometry G) {
+  __shared__ uint64_t cbuf[NT / kWave][kWave];
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int s = blockIdx.x * (NT / kWave) + wave;
+  if (s >= G.nslots) return;  // wave-uniform from here on
+  Slot *sl = &slots[s];
+  if (sl->state != 1 || sl->implicit == 0) return;
+  const int64_t nch = (G.n + FS_PT - 1) / FS_PT;
+  const int k = sl->k;
+  const int64_t w = 2 * k + 1;
+  const uint64_t *part = B.part + (int64_t)s * B.part_stride;
+  // (32-bit index arithmetic: the lists hold fewer than 2^32 keys)
+  const uint32_t ku = (uint32_t)k, kl = (uint32_t)k + 1u, wu = (uint32_t)w;
+  auto gu = [&](int64_t p) -> uint64_t {
+    const uint32_t q = (uint32_t)p / ku;
+    return part[q * wu + ((uint32_t)p - q * ku)];
+  };
+  auto gl = [&](int64_t p) -> uint64_t {
+    const uint32_t q = (uint32_t)p / kl;
+    return part[q * wu + ku + ((uint32_t)p - q * kl)];
+  };
+  const uint64_t U = wave_bcast_u64(wave_smallest_gen(nch * k, gu, k, cbuf[wave]), k - 1);
+  const uint64_t lcb = wave_smallest_gen(nch * (k + 1), gl, k + 1, cbuf[wave]);
+  const uint64_t L1 = wave_bcast_u64(lcb, k - 1), L2 = wave_bcast_u64(lcb, k);
+  if (lane == 0) {
+    sl->U = dkey_inv(U);
+    sl->L1 = dkey_inv(L1);
+    sl->L2 = dkey_inv(L2);
+  }
+  if (lane < 4) {
+    const RoundConsts rc = round_consts(sl, G.m, sl->cur);
+    sl->sthr[lane] = sum_threshold(sl, rc, lane, dkey_inv(U), dkey_inv(L1), dkey_inv(L2));
   }
 }
 
@@ -2129,7 +2332,8 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
                        (ql->cur == 0 && !ql->exact) ? 1 : 0);
     hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((G.n + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st, slots,
                        B, G);
-    hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, FS_PT);
+    hipLaunchKernelGGL(k_select_merge_pm, dim3((ns + NT / kWave - 1) / (NT / kWave)), dim3(NT), 0, st, slots, B, G);
+    hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, 1);
     prof_end(tk, st, 0.0);
     tk = prof_begin(PROF_DECIDE, st);
     const int64_t ndec = ((G.n + DQ_PT - 1) / DQ_PT) * ((nqp + DQ_SL - 1) / DQ_SL);

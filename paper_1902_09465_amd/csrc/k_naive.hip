@@ -575,9 +575,9 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
         ++my_pairs;
       }
     }
-  if (G.prof && my_pairs) {
-    atomicAdd(&G.prof[0], my_pairs * (uint64_t)(G.m + 14));
-    atomicAdd(&G.prof[2], my_pairs * (uint64_t)G.m);
+  if (G.prof) {  // whole waves reach this point
+    wave_count_add(&prof_copy(G.prof)[0], my_pairs * (uint64_t)(G.m + 14));
+    wave_count_add(&prof_copy(G.prof)[2], my_pairs * (uint64_t)G.m);
   }
 }
 

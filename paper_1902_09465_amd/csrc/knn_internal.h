@@ -60,6 +60,9 @@ struct Slot {
   double W;
   const void *q;
   double U, L1, L2;     // thresholds of the current snapshot
+  int64_t sthr[4];      // point-major batches: the same decisions as integer sums S of the
+                        // round (S > sthr[0] discard, else S <= sthr[1] accept for a sampled
+                        // pair; sthr[2], sthr[3] for an exact pair), set with U, L1, L2
   int64_t coord_evals, exact_points;
   int32_t rounds, pad1;
   int32_t T[kMaxRounds];

@@ -45,7 +45,11 @@ int prof_begin(int kind, hipStream_t st) {
   if (!s.on) return -1;
   std::lock_guard<std::mutex> lk(s.mu);
   ProfRec r{kind, nullptr, nullptr, 0.0, false};
-  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+  // Timing-only events: without the system-scope fence a record does not
+  // write back and invalidate the caches, which would slow the next kernel.
+  // Kernels on one stream stay ordered by the stream itself.
+  const unsigned fl = hipEventDisableSystemFence;
+  if (hipEventCreateWithFlags(&r.a, fl) != hipSuccess || hipEventCreateWithFlags(&r.b, fl) != hipSuccess) return -1;
   (void)hipEventRecord(r.a, st);
   s.recs.push_back(r);
   return (int)s.recs.size() - 1;
@@ -79,8 +83,9 @@ int knn_prof_enable(int on) {
   ProfState &s = P();
   std::lock_guard<std::mutex> lk(s.mu);
   clear_locked(s);
-  if (on && !s.dcnt) HIP_TRY(hipMalloc(&s.dcnt, sizeof(uint64_t) * 8));
-  if (s.dcnt) HIP_TRY(hipMemset(s.dcnt, 0, sizeof(uint64_t) * 8));
+  const size_t words = (size_t)kProfCopies * kProfStride;
+  if (on && !s.dcnt) HIP_TRY(hipMalloc(&s.dcnt, sizeof(uint64_t) * words));
+  if (s.dcnt) HIP_TRY(hipMemset(s.dcnt, 0, sizeof(uint64_t) * words));
   s.host_cnt[0] = s.host_cnt[1] = s.host_cnt[2] = s.host_cnt[3] = 0;
   s.on = on != 0;
   return KNN_OK;
@@ -112,7 +117,10 @@ int knn_prof_counters(uint64_t *host_out8) {
   for (int i = 0; i < 8; ++i) host_out8[i] = 0;
   if (!s.dcnt) return KNN_OK;
   HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(host_out8, s.dcnt, sizeof(uint64_t) * 4, hipMemcpyDeviceToHost));
+  std::vector<uint64_t> all((size_t)kProfCopies * kProfStride);
+  HIP_TRY(hipMemcpy(all.data(), s.dcnt, sizeof(uint64_t) * all.size(), hipMemcpyDeviceToHost));
+  for (int c = 0; c < kProfCopies; ++c)
+    for (int i = 0; i < 4; ++i) host_out8[i] += all[(size_t)c * kProfStride + i];
   std::lock_guard<std::mutex> lk(s.mu);
   for (int i = 0; i < 4; ++i) host_out8[4 + i] = s.host_cnt[i];
   return KNN_OK;

@@ -22,6 +22,11 @@ enum ProfKind {
   PROF_KINDS = 10
 };
 
+// Device counters: kProfCopies copies of the four counters, one cache line
+// apart.  A block adds to the copy its index selects (device-scope atomics
+// on one address serialise); the host sums the copies.
+constexpr int kProfCopies = 64, kProfStride = 16;
+
 bool prof_enabled();
 uint64_t *prof_device_counters();  // NULL unless enabled
 int prof_begin(int kind, hipStream_t st);               // returns a token (or -1)
