@@ -1469,7 +1469,6 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
   // rows padded to an odd number of 4-byte words: the 64 lanes of a wave
   // read 64 different rows at one column without bank conflicts
   __shared__ __align__(16) uint8_t ft[DQ_SL][DQ_PT + 4];
-  __shared__ int cnt[NT / DQ_SL][DQ_SL][3];
   const int64_t n = G.n, m = G.m;
   const int ns = G.nslots;
   const int64_t ngroups = (nqp + DQ_SL - 1) / DQ_SL;
@@ -1521,62 +1520,102 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
     }
   }
   __syncthreads();
-  const int c = threadIdx.x % DQ_SL;  // this thread's slot within the tile
-  const int sl = s0 + c;
-  const bool run = srun[c] != 0;
-  int c_act = 0, c_xa = 0, c_acc = 0;
-  if (sl < nqp) {
+  // Each thread takes four consecutive slots of the tile (one 16-byte load
+  // of their sums and one 4-byte store of their "not sampled" bytes per
+  // point; nqp is a multiple of 16) and every DQ_P-th point.
+  constexpr int DQ_G = DQ_SL / 4, DQ_P = NT / DQ_G;
+  static_assert(DQ_SL % 4 == 0 && NT % DQ_G == 0, "four slots per thread");
+  __shared__ int cnt[NT / kWave][DQ_SL][3];
+  const int c4 = 4 * (threadIdx.x % DQ_G);  // first of this thread's slots within the tile
+  bool run[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) run[j] = srun[c4 + j] != 0;
+  int c_act[4] = {0, 0, 0, 0}, c_xa[4] = {0, 0, 0, 0}, c_acc[4] = {0, 0, 0, 0};
+  if (s0 + c4 < nqp) {
     // the decisions as thresholds on the sums (k_select_merge_pm derives them
     // from U, L1, L2 with the FP64 bounds), so no pair needs a division
-    int64_t th[4] = {0, 0, 0, 0};
-    if (run) {
+    // (named fields, picked by arithmetic below: a select between two
+    // array elements would become an indexed load from scratch memory)
+    struct Thr {
+      int64_t disc, acc, xdisc, xacc;
+    } th[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) th[q] = slots[sl].sthr[q];
+    for (int j = 0; j < 4; ++j) {
+      const Slot &sj = slots[run[j] ? s0 + c4 + j : 0];
+      th[j].disc = run[j] ? sj.sthr[0] : 0;
+      th[j].acc = run[j] ? sj.sthr[1] : 0;
+      th[j].xdisc = run[j] ? sj.sthr[2] : 0;
+      th[j].xacc = run[j] ? sj.sthr[3] : 0;
     }
     // DQ_B points per batch: their sums are loaded together, so the loads'
     // latency is paid once per batch
-    constexpr int DQ_B = 8, STEP = NT / DQ_SL;
-    for (int pb = threadIdx.x / DQ_SL; pb < pts; pb += STEP * DQ_B) {
-      uint32_t sv[DQ_B];
+    constexpr int DQ_B = 4;
+    for (int pb = threadIdx.x / DQ_G; pb < pts; pb += DQ_P * DQ_B) {
+      uint4 sv[DQ_B];
 #pragma unroll
       for (int b = 0; b < DQ_B; ++b) {  // unconditional loads (clamped to the tile): all in flight at once
-        const int p = min(pb + b * STEP, pts - 1);
-        sv[b] = D[(i0 + p) * nqp + sl];
+        const int p = min(pb + b * DQ_P, pts - 1);
+        sv[b] = *reinterpret_cast<const uint4 *>(D + (i0 + p) * nqp + s0 + c4);
       }
 #pragma unroll
       for (int b = 0; b < DQ_B; ++b) {
-        const int p = pb + b * STEP;
+        const int p = pb + b * DQ_P;
         if (p >= pts) break;
-        uint8_t f = ft[c][p];
-        if (run && !(f & (FL_ACC | FL_DISC))) {
-          const bool exact = (f & FL_EXACT) != 0;
-          const int64_t S = sv[b];
-          if (S > (exact ? th[2] : th[0])) {
-            f |= FL_DISC | 0x80;
-          } else if (S <= (exact ? th[3] : th[1])) {
-            f |= FL_ACC | 0x80;
-            ++c_acc;
-          } else if (exact) {
-            ++c_xa;
-          } else {
-            ++c_act;
+        const uint32_t S4[4] = {sv[b].x, sv[b].y, sv[b].z, sv[b].w};
+        uint32_t aw = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          uint8_t f = ft[c4 + j][p];
+          if (run[j] && !(f & (FL_ACC | FL_DISC))) {
+            const int64_t xm = -(int64_t)(f & FL_EXACT);  // all ones for an exact pair
+            const int64_t tdisc = th[j].disc ^ ((th[j].disc ^ th[j].xdisc) & xm);
+            const int64_t tacc = th[j].acc ^ ((th[j].acc ^ th[j].xacc) & xm);
+            const bool exact = xm != 0;
+            const int64_t S = S4[j];
+            if (S > tdisc) {
+              f |= FL_DISC | 0x80;
+            } else if (S <= tacc) {
+              f |= FL_ACC | 0x80;
+              ++c_acc[j];
+            } else if (exact) {
+              ++c_xa[j];
+            } else {
+              ++c_act[j];
+            }
+            ft[c4 + j][p] = f;
           }
-          ft[c][p] = f;
+          aw |= ((run[j] && (f & 0x7F) == 0) ? 0u : 1u) << (8 * j);
         }
-        A[(i0 + p) * nqp + sl] = (run && (f & 0x7F) == 0) ? (uint8_t)0 : (uint8_t)1;
+        *reinterpret_cast<uint32_t *>(A + (i0 + p) * nqp + s0 + c4) = aw;
       }
     }
   }
-  cnt[threadIdx.x / DQ_SL][c][0] = c_act;
-  cnt[threadIdx.x / DQ_SL][c][1] = c_xa;
-  cnt[threadIdx.x / DQ_SL][c][2] = c_acc;
+  // per wave, the lanes with the same slots (DQ_G apart) add their counts
+  static_assert(kWave == 4 * DQ_G, "four lanes of a wave share a slot group");
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int o = DQ_G; o < kWave; o <<= 1) {
+      c_act[j] += __shfl_xor(c_act[j], o);
+      c_xa[j] += __shfl_xor(c_xa[j], o);
+      c_acc[j] += __shfl_xor(c_acc[j], o);
+    }
+  }
+  if (lane_id() < DQ_G) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cnt[threadIdx.x / kWave][c4 + j][0] = c_act[j];
+      cnt[threadIdx.x / kWave][c4 + j][1] = c_xa[j];
+      cnt[threadIdx.x / kWave][c4 + j][2] = c_acc[j];
+    }
+  }
   __syncthreads();
   if (threadIdx.x < DQ_SL && srun[threadIdx.x]) {
     const int cs = threadIdx.x;
     const int s = s0 + cs;
     {
       int tot[3] = {0, 0, 0};
-      for (int q = 0; q < NT / DQ_SL; ++q)
+      for (int q = 0; q < NT / kWave; ++q)
         for (int k = 0; k < 3; ++k) tot[k] += cnt[q][cs][k];
       uint32_t *rec = reinterpret_cast<uint32_t *>(B.part + (int64_t)s * B.part_stride) + 3 * tile;
       rec[0] = (uint32_t)tot[0];
