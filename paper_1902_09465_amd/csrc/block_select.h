@@ -150,6 +150,31 @@ __device__ uint32_t block_kth_u32_gen(int64_t N, GetVal getval, Keep keep, int r
   return prefix;
 }
 
+// Lane l receives lane (l ^ j)'s value, for a j that is a constant after
+// unrolling.  Every lane of the wave must be active.  Exchanges within a
+// quad or a 16-lane row run as DPP moves (no trip through the LDS unit),
+// xor 4 and 16 as swizzles (no address operand), xor 32 as a permute.
+__device__ __forceinline__ uint32_t lane_xor_u32(uint32_t v, int j) {
+  switch (j) {
+    case 1:
+      return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+    case 2:
+      return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+    case 4:
+      return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (4 << 10) | 0x1F);  // swap groups of 4
+    case 8:
+      return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, true);  // row_ror:8 (16-lane rows)
+    case 16:
+      return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (16 << 10) | 0x1F);  // swap groups of 16
+    default:
+      return (uint32_t)__shfl_xor((int)v, j);
+  }
+}
+__device__ __forceinline__ uint64_t lane_xor_u64(uint64_t v, int j) {
+  const uint32_t lo = lane_xor_u32((uint32_t)v, j), hi = lane_xor_u32((uint32_t)(v >> 32), j);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Bitonic sort of one 64-bit key per lane across the wave (ascending with
 // the lane index), by exchanges between lanes: 21 compare-exchange steps.
 __device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v) {
@@ -158,9 +183,7 @@ __device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v) {
   for (int k = 2; k <= kWave; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, j);
-      const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j);
-      const uint64_t o = ((uint64_t)hi << 32) | lo;
+      const uint64_t o = lane_xor_u64(v, j);
       const bool keep_min = (((l & j) == 0) == ((l & k) == 0));
       v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
     }
@@ -175,7 +198,7 @@ __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t v) {
   for (int k = 2; k <= kWave; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t o = (uint32_t)__shfl_xor((int)v, j);
+      const uint32_t o = lane_xor_u32(v, j);
       const bool keep_min = (((l & j) == 0) == ((l & k) == 0));
       v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
     }

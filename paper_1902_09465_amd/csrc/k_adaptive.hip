@@ -1144,9 +1144,7 @@ __device__ void wave_smallest(const uint64_t (&key)[E], int K, uint64_t *out, ui
       uint64_t v = best < r ? best : r;          // bitonic: the 64 smallest of both
 #pragma unroll
       for (int j = kWave / 2; j > 0; j >>= 1) {
-        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, j);
-        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j);
-        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        const uint64_t o = lane_xor_u64(v, j);
         v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
       }
       best = v;
@@ -1196,9 +1194,7 @@ __device__ uint64_t wave_smallest_gen(int64_t N, Get get, int K, uint64_t *cbuf)
       uint64_t v = best < r ? best : r;          // bitonic: the 64 smallest of both
 #pragma unroll
       for (int j = kWave / 2; j > 0; j >>= 1) {
-        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, j);
-        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j);
-        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        const uint64_t o = lane_xor_u64(v, j);
         v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
       }
       best = v;
@@ -1220,7 +1216,7 @@ __device__ uint32_t wave_smallest_u32(const uint32_t (&key)[E], int K, uint32_t 
   uint32_t mn = key[0];
 #pragma unroll
   for (int e = 1; e < E; ++e) mn = key[e] < mn ? key[e] : mn;
-  const uint32_t tau = (uint32_t)__shfl((int)wave_sort_u32(mn), K - 1);
+  const uint32_t tau = (uint32_t)__builtin_amdgcn_readlane((int)wave_sort_u32(mn), K - 1);
   int cnt = 0;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
 #pragma unroll
@@ -1246,7 +1242,7 @@ __device__ uint32_t wave_smallest_u32(const uint32_t (&key)[E], int K, uint32_t 
       uint32_t v = best < r ? best : r;                                // bitonic: the 64 smallest of both
 #pragma unroll
       for (int j = kWave / 2; j > 0; j >>= 1) {
-        const uint32_t o = (uint32_t)__shfl_xor((int)v, j);
+        const uint32_t o = lane_xor_u32(v, j);
         v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
       }
       best = v;

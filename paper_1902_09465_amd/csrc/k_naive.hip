@@ -180,12 +180,6 @@ constexpr int BROW = BK + 16;           // LDS row stride of a stage
 constexpr int STAGE = (NBQ + NBP) * BROW;
 constexpr int CB = 32;                  // candidate buffer per query (<= 64)
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int j) {
-  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, j);
-  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j);
-  return ((uint64_t)hi << 32) | lo;
-}
-
 // list: sorted ascending over the lanes; cand: one key per lane (PAD = none).
 // Returns the 64 smallest of both, sorted ascending over the lanes.
 __device__ __forceinline__ uint64_t merge_sorted64(uint64_t list, uint64_t cand) {
@@ -195,7 +189,7 @@ __device__ __forceinline__ uint64_t merge_sorted64(uint64_t list, uint64_t cand)
   uint64_t v = list < c ? list : c;
 #pragma unroll
   for (int j = kWave / 2; j > 0; j >>= 1) {
-    const uint64_t o = shfl_xor_u64(v, j);
+    const uint64_t o = lane_xor_u64(v, j);
     v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
   }
   return v;
