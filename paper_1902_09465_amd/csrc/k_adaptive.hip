@@ -1293,6 +1293,42 @@ __device__ __forceinline__ void pair_bounds(const Slot *sl, const RoundConsts &r
   }
 }
 
+// Per slot, at the end of its partial-list area, the tiles of this round
+// whose kept pairs mix divisors or widths: a count, then the tile indices
+// (k_select_pm appends, k_select_pm_mixed selects them, k_select_merge_pm
+// clears the count; the first round, which never mixes, starts it at 0).
+__host__ __device__ inline int64_t fs_mixed_words(int64_t n) { return ((n + FS_PT - 1) / FS_PT + 2) / 2; }
+__device__ __forceinline__ uint32_t *fs_mixed(const Bufs &B, int sl, int64_t n) {
+  return reinterpret_cast<uint32_t *>(B.part + (int64_t)(sl + 1) * B.part_stride - fs_mixed_words(n));
+}
+
+constexpr int FS_TS = FS_PT + 4;  // LDS row stride in words: rows stay 16-byte aligned
+
+// The sums of a tile of FS_SL slots x FS_PT points, transposed into LDS rows:
+// one 16-byte load per point (the FS_SL slots; nqp is a multiple of 16), all
+// in flight at once (clamped rows, zeroed after).
+template <int BT>
+__device__ __forceinline__ void fs_stage_sums(uint32_t (*t)[FS_TS], const uint32_t *__restrict__ D, int32_t nqp,
+                                              int64_t i0, int s0, int64_t n) {
+  static_assert(FS_SL == 4, "one 16-byte load per point");
+  constexpr int PER = FS_PT / BT;
+  uint4 v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t i = min(i0 + threadIdx.x + u * BT, n - 1);
+    v[u] = *reinterpret_cast<const uint4 *>(D + i * nqp + s0);
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int pt = threadIdx.x + u * BT;
+    const bool in = i0 + pt < n;
+    t[0][pt] = in ? v[u].x : 0u;
+    t[1][pt] = in ? v[u].y : 0u;
+    t[2][pt] = in ? v[u].z : 0u;
+    t[3][pt] = in ? v[u].w : 0u;
+  }
+}
+
 // Selection for such batches: one block per tile of FS_SL slots x FS_PT
 // points (D transposed through LDS), the tile's k smallest UCB and k+1
 // smallest LCB per slot over the kept points (the partial lists that
@@ -1300,8 +1336,7 @@ __device__ __forceinline__ void pair_bounds(const Slot *sl, const RoundConsts &r
 // index are initialised here.
 __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
                                                   int32_t nqp, Bufs B, Geometry G, int32_t cur, int32_t init) {
-  constexpr int TS = FS_PT + 4;  // row stride in words: rows stay 16-byte aligned
-  __shared__ __align__(16) uint32_t t[FS_SL][TS];
+  __shared__ __align__(16) uint32_t t[FS_SL][FS_TS];
   __shared__ uint64_t cbuf[NT / kWave][kWave];
   const int64_t n = G.n, m = G.m;
   const int ns = G.nslots;
@@ -1320,26 +1355,7 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
     }
     if (!any) return;
   }
-  {  // the tile's sums: one 16-byte load per point (the FS_SL slots; nqp is a
-     // multiple of 16), all in flight at once (clamped rows, zeroed after)
-    static_assert(FS_SL == 4, "one 16-byte load per point");
-    constexpr int PER = FS_PT / NT;
-    uint4 v[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int64_t i = min(i0 + threadIdx.x + u * NT, n - 1);
-      v[u] = *reinterpret_cast<const uint4 *>(D + i * nqp + s0);
-    }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int pt = threadIdx.x + u * NT;
-      const bool in = i0 + pt < n;
-      t[0][pt] = in ? v[u].x : 0u;
-      t[1][pt] = in ? v[u].y : 0u;
-      t[2][pt] = in ? v[u].z : 0u;
-      t[3][pt] = in ? v[u].w : 0u;
-    }
-  }
+  fs_stage_sums<NT>(t, D, nqp, i0, s0, n);
   __syncthreads();
   const int lane = lane_id(), wave = threadIdx.x / kWave;
   // whole tile with 4-byte aligned flag rows: each lane takes four runs of
@@ -1428,24 +1444,67 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
         if (lane < k) out[lane] = b == PAD32 ? PAD : dkey(d + al);
         out[k + lane] = b == PAD32 ? PAD : dkey(d - al);
       }
-    } else {  // (the flag writes of round 0 above are this wave's own: visible to its reads)
-      uint64_t ku[FS_E], kl[FS_E];
+    }
+    if (lane == 0) {
+      uint32_t *ml = fs_mixed(B, sl, n);
+      if (init && tile == 0) ml[0] = 0;  // (round 0 never mixes: no appends race with this)
+      if (!uniform) ml[1 + atomicAdd(&ml[0], 1u)] = (uint32_t)tile;  // k_select_pm_mixed selects it
+    }
+  }
+}
+
+// The tiles that k_select_pm listed as mixed (pairs exact, sampled at the
+// round and accepted in earlier rounds side by side): each kept pair's
+// bounds from its own flag and round, then the k smallest UCB and the k+1
+// smallest LCB.  One single-wave block per slot; a slot without such tiles
+// leaves at once.
+__global__ __launch_bounds__(kWave) void k_select_pm_mixed(const Slot *__restrict__ slots,
+                                                           const uint32_t *__restrict__ D, int32_t nqp, Bufs B,
+                                                           Geometry G, int32_t cur, int32_t init) {
+  __shared__ __align__(16) uint32_t t[FS_SL][FS_TS];
+  __shared__ uint64_t cbuf[kWave];
+  const int64_t n = G.n, m = G.m;
+  const int sl = blockIdx.x;
+  if (init || sl >= G.nslots) return;
+  const Slot *slp = &slots[sl];
+  if (slp->state != 1 || slp->cur != cur || slp->implicit == 0) return;
+  const uint32_t *ml = fs_mixed(B, sl, n);
+  const uint32_t nmix = ml[0];
+  const int lane = lane_id();
+  const int k = slp->k;
+  const RoundConsts rc = round_consts(slp, m, cur);
+  const int r = sl % FS_SL;
+  for (uint32_t e0 = 0; e0 < nmix; ++e0) {
+    const int64_t tile = ml[1 + e0];
+    const int64_t i0 = tile * FS_PT;
+    __builtin_amdgcn_s_barrier();  // (one wave) the previous tile's reads of t are done
+    fs_stage_sums<kWave>(t, D, nqp, i0, sl - r, n);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint8_t *flr = B.fl + (int64_t)sl * n + i0;
+    uint64_t *out = B.part + (int64_t)sl * B.part_stride + tile * (2 * k + 1);
+    // upper bounds, then lower bounds: one key array live at a time
+#pragma nounroll
+    for (int lower = 0; lower < 2; ++lower) {
+      uint64_t key[FS_E];
 #pragma unroll
       for (int e = 0; e < FS_E; ++e) {
         const int p = e * kWave + lane;
         const int64_t i = i0 + p;
-        ku[e] = kl[e] = ~0ull;
+        key[e] = ~0ull;
         if (i >= n) continue;
         const uint8_t f = flr[p];
         if (f & FL_DISC) continue;
         const bool late = (f & FL_ACC) && !(f & FL_EXACT);  // accepted before this round
         double d, al;
         pair_bounds(slp, rc, (int64_t)t[r][p], f, late ? B.ri[(int64_t)sl * n + i] : (uint8_t)0, !late, d, al);
-        ku[e] = dkey(d + al);
-        kl[e] = dkey(d - al);
+        key[e] = lower ? dkey(d - al) : dkey(d + al);
       }
-      wave_smallest<FS_E>(ku, k, out, cbuf[wave]);
-      wave_smallest<FS_E>(kl, k + 1, out + k, cbuf[wave]);
+      if (lower)
+        wave_smallest<FS_E>(key, k + 1, out + k, cbuf);
+      else
+        wave_smallest<FS_E>(key, k, out, cbuf);
     }
   }
 }
@@ -1728,6 +1787,7 @@ __global__ __launch_bounds__(NT) void k_select_merge_pm(Slot *__restrict__ slots
     const RoundConsts rc = round_consts(sl, G.m, sl->cur);
     sl->sthr[lane] = sum_threshold(sl, rc, lane, dkey_inv(U), dkey_inv(L1), dkey_inv(L2));
   }
+  if (lane == 0) fs_mixed(B, s, G.n)[0] = 0;  // the next round's list of mixed tiles starts empty
 }
 
 // ---------------------------------------------------------------- decide
@@ -2365,6 +2425,8 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     const int64_t nsel = ((G.n + FS_PT - 1) / FS_PT) * ((nqp + FS_SL - 1) / FS_SL);
     hipLaunchKernelGGL(k_select_pm, dim3((unsigned)xcd_grid(nsel)), dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur,
                        (ql->cur == 0 && !ql->exact) ? 1 : 0);
+    hipLaunchKernelGGL(k_select_pm_mixed, dim3(ns), dim3(kWave), 0, st, slots, qd_buf, nqp, B, G, ql->cur,
+                       (ql->cur == 0 && !ql->exact) ? 1 : 0);
     hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((G.n + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st, slots,
                        B, G);
     hipLaunchKernelGGL(k_select_merge_pm, dim3((ns + NT / kWave - 1) / (NT / kWave)), dim3(NT), 0, st, slots, B, G);
@@ -2482,7 +2544,7 @@ int64_t part_words(int64_t n, int32_t kmax, int32_t cmax) {
   int64_t a = nsel * (2 * (int64_t)kmax + 1);
   a = std::max<int64_t>(a, (3 * ((n + DQ_PT - 1) / DQ_PT) + 1) / 2);  // k_decide_pm's count records (u32 triples)
   const int64_t c = cmax > 0 ? ncand * (int64_t)min(cmax, CAND_CH) * 2 : 0;  // keys + packed ids
-  return (a > c ? a : c) + 8;
+  return (a > c ? a : c) + fs_mixed_words(n) + 8;  // the mixed-tile list of k_select_pm at the end
 }
 
 }  // namespace knn
