@@ -91,9 +91,12 @@ class KnnDB:
             params = default_params()
         plist = [params] if isinstance(params, Params) else list(params)
         parr = (Params * len(plist))(*plist)
-        kh = [int(ks[q]) + (lambda p: p.h if p.h >= 0 else int(ks[q]))(plist[0 if len(plist) == 1 else q])
-              for q in range(nq)]
-        stride = int(max(1, min(max(kh), self.n)))
+        if len(plist) == 1:  # k + h per query (h < 0: h = k)
+            h = plist[0].h
+            kh_max = int(ks.max()) * 2 if h < 0 else int(ks.max()) + int(h)
+        else:
+            kh_max = max(int(ks[q]) + (plist[q].h if plist[q].h >= 0 else int(ks[q])) for q in range(nq))
+        stride = int(max(1, min(kh_max, self.n)))
         dev = Q.device
         idx = torch.empty((nq, stride), dtype=torch.int64, device=dev)
         cnt = torch.empty((nq,), dtype=torch.int32, device=dev)

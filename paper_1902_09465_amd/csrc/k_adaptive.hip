@@ -2037,35 +2037,65 @@ __device__ void write_trivial(const QDesc &qd, int64_t n) {
 __device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry &G, bool all = false) {
   const int64_t n = G.n;
   const SlotArrays a = slot_arrays(B, n, s, sl->par);
-  constexpr int NW = MT / kWave;
+  constexpr int NW = MT / kWave, V = 16;  // V consecutive points per thread and pass
   __shared__ int wc[NW][3];
   __shared__ int run[3];
   const int wave = threadIdx.x / kWave, lane = lane_id();
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  const bool vec = (n % V) == 0;  // the slot's flag row is 16-byte aligned
   if (threadIdx.x < 3) run[threadIdx.x] = 0;
   __syncthreads();
-  for (int64_t b = 0; b < n; b += MT) {
-    const int64_t i = b + threadIdx.x;
-    int c = -1;
-    if (i < n) {
-      const uint8_t f = a.fl[i];
-      c = (f & FL_DISC) ? -1 : (f & FL_ACC) ? 2 : (f & FL_EXACT) ? 1 : 0;
+  for (int64_t b = 0; b < n; b += (int64_t)MT * V) {
+    const int64_t i0 = b + (int64_t)threadIdx.x * V;
+    uint8_t f[V];
+    if (vec && i0 + V <= n) {
+      const uint4 w = *reinterpret_cast<const uint4 *>(a.fl + i0);
+      const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int v = 0; v < V; ++v) f[v] = (uint8_t)(ww[v >> 2] >> (8 * (v & 3)));
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) f[v] = i0 + v < n ? a.fl[i0 + v] : (uint8_t)FL_DISC;
     }
-    uint64_t mk[3];
+    // class of each point: -1 discarded, 0 undecided sampled, 1 undecided exact, 2 accepted
+    int c3[3] = {0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const uint8_t g = f[v];
+      if (g & FL_DISC) continue;
+      ++c3[(g & FL_ACC) ? 2 : (g & FL_EXACT) ? 1 : 0];
+    }
+    // exclusive positions in point order: wave scan, then the waves before
+    int inc[3] = {c3[0], c3[1], c3[2]};
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int t = __shfl_up(inc[k], d);
+        if (lane >= d) inc[k] += t;
+      }
+    }
+    if (lane == kWave - 1)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) wc[wave][k] = inc[k];
+    __syncthreads();
+    int pos[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      mk[k] = __ballot(c == k);
-      if (lane == 0) wc[wave][k] = __popcll(mk[k]);
+      pos[k] = run[k] + inc[k] - c3[k];
+      for (int w = 0; w < wave; ++w) pos[k] += wc[w][k];
     }
-    __syncthreads();
-    if (c >= 0) {
-      int pos = run[c] + __popcll(mk[c] & lt);
-      for (int w = 0; w < wave; ++w) pos += wc[w][c];
-      int32_t *dst = c == 0 ? a.act : (c == 1 ? a.xa : a.acc);
-      dst[pos] = (int32_t)i;
-      if (c == 0 && G.flagsets) a.ri[i] = (uint8_t)sl->cur;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int64_t i = i0 + v;
+      const uint8_t g = f[v];
+      const int c = (g & FL_DISC) ? -1 : (g & FL_ACC) ? 2 : (g & FL_EXACT) ? 1 : 0;
+      if (c >= 0) {
+        int32_t *dst = c == 0 ? a.act : (c == 1 ? a.xa : a.acc);
+        dst[pos[c]++] = (int32_t)i;
+        if (c == 0 && G.flagsets) a.ri[i] = (uint8_t)sl->cur;
+      }
+      if (G.flagsets && i < n && (c >= 0 || all)) a.S[i] = (int64_t)B.dpm[i * B.dpm_stride + s];
     }
-    if (G.flagsets && i < n && (c >= 0 || all)) a.S[i] = (int64_t)B.dpm[i * B.dpm_stride + s];
     __syncthreads();
     if (threadIdx.x < 3) {
       int t = 0;

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -104,6 +105,40 @@ Knobs knobs_for(const knn_db_s *db) {
   return k;
 }
 
+// A stream-ordered pool per device that keeps its memory mapped between
+// calls: the default pool hands an engine's arena back at every
+// synchronisation, and mapping it again costs about half a millisecond per
+// batch.  nullptr when the pool cannot be made (the default pool is used).
+static hipMemPool_t engine_pool() {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = pools.find(dev);
+  if (it != pools.end()) return it->second;
+  hipMemPoolProps props;
+  std::memset(&props, 0, sizeof(props));
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  hipMemPool_t pool = nullptr;
+  if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+    (void)hipGetLastError();
+    pool = nullptr;
+  } else {
+    uint64_t keep = UINT64_MAX;
+    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipMemPoolDestroy(pool);
+      pool = nullptr;
+    }
+  }
+  pools[dev] = pool;
+  return pool;
+}
+
 size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax) {
   const int64_t pw = part_words(n, kmax, cmax);
   return (size_t)n * (8 + 1 + 1 + 4 * 2 + 4 * 2 + 4) + (size_t)pw * 8 + sizeof(Slot) + 12 * 256;
@@ -142,9 +177,13 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   const size_t o_q8 = take(q8x ? (size_t)nqp * (size_t)db->mp : 0);
   const size_t o_q8n = take(q8x ? (size_t)nqp * 4 : 0);
   void *base = nullptr;
-  if (async_alloc)
-    HIP_TRY(hipMallocAsync(&base, off, st));
-  else
+  if (async_alloc) {
+    hipMemPool_t pool = engine_pool();
+    if (pool)
+      HIP_TRY(hipMallocFromPoolAsync(&base, off, pool, st));
+    else
+      HIP_TRY(hipMallocAsync(&base, off, st));
+  } else
     HIP_TRY(hipMalloc(&base, off));
   auto at = [&](size_t o) { return (uint8_t *)base + o; };
   E.db = db;
