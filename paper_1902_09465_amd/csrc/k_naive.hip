@@ -175,9 +175,10 @@ __device__ __forceinline__ uint32_t tile_dist(const int32_t *qn, const int32_t *
   return (uint32_t)((int64_t)qn[q] + (int64_t)xn[p] - 2 * (int64_t)acc);
 }
 
-constexpr int BK = 128;                 // bytes of K per pipeline stage
-constexpr int BROW = BK + 16;           // LDS row stride of a stage
-constexpr int STAGE = (NBQ + NBP) * BROW;
+// A pipeline slice is BK bytes of K (a multiple of the 64-byte MFMA step);
+// its LDS rows are padded by 16 bytes (conflict-free fragment reads).
+constexpr int stage_bytes(int BK) { return (NBQ + NBP) * (BK + 16); }
+constexpr int BK_NAIVE = 128, BK_EXACT = 64;  // the scan's and the exact round's slices
 constexpr int CB = 32;                  // candidate buffer per query (<= 64)
 
 // list: sorted ascending over the lanes; cand: one key per lane (PAD = none).
@@ -200,49 +201,54 @@ __device__ __forceinline__ uint64_t merge_sorted64(uint64_t list, uint64_t cand)
 // the l1 distance sum_j |x_j - q_j| by v_sad_u8 (MET = l1, zero-padded u8
 // rows).  Either way lane l of wave w = 2 wq + wp ends with the value of
 // query 32 wq + 16 a + 4 (l / 16) + v and point 64 wp + 16 b + l % 16 in
-// acc[a][b][v] (the MFMA output layout).  The K loop runs over 128-byte
+// acc[a][b][v] (the MFMA output layout).  The K loop runs over BK-byte
 // slices through two LDS buffers (one barrier per slice); the global loads
 // of the next PF slices are in flight in registers while the current slice
 // is consumed, so each load has PF slices of compute to arrive.  Rows beyond
-// nq / pend read as zeros.  smem: 2 x STAGE bytes.
-template <int MET, int PF = 1>
+// nq / pend read as zeros.  smem: 2 x stage_bytes(BK) bytes.
+template <int MET, int PF, int BK>
 __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int64_t nq, const int8_t *__restrict__ X8,
                                              int64_t q0, int64_t p0, int64_t pr1, int64_t mp, uint8_t *smem,
                                              v4i (&acc)[2][4]) {
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int wq = wave >> 1, wp = wave & 1;
-  const int nks = (int)(mp / BK), tail = (int)(mp % BK);  // tail: 0 or 64
+  constexpr int BROW = BK + 16, STAGE = stage_bytes(BK);
+  const int nks = (int)(mp / BK), tail = (int)(mp % BK);  // mp is a multiple of 64: tail 0 or 64
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
   // slice s covers K bytes [s BK, s BK + width): A 64 x width, B 128 x width
-  auto load = [&](int64_t k0, int width, v4i (&ra)[2], v4i (&rb)[4]) {
+  // a slice is CPR 16-byte pieces per row: the 256 threads take NA pieces
+  // of the query tile and NB of the point tile each
+  constexpr int CPR = BK / 16, NA = NBQ * CPR / 256, NB = NBP * CPR / 256;
+  static_assert(NA * 256 == NBQ * CPR && NB * 256 == NBP * CPR, "whole pieces per thread");
+  auto load = [&](int64_t k0, int width, v4i (&ra)[NA], v4i (&rb)[NB]) {
     const int per_row = width / 16;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int e = tid + 256 * h, r = e / 8, c = (e % 8) * 16;
+    for (int h = 0; h < NA; ++h) {
+      const int e = tid + 256 * h, r = e / CPR, c = (e % CPR) * 16;
       ra[h] = v4i{0, 0, 0, 0};
       if (c / 16 < per_row && q0 + r < nq) ra[h] = *reinterpret_cast<const v4i *>(Q8 + (q0 + r) * mp + k0 + c);
     }
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int e = tid + 256 * h, r = e / 8, c = (e % 8) * 16;
+    for (int h = 0; h < NB; ++h) {
+      const int e = tid + 256 * h, r = e / CPR, c = (e % CPR) * 16;
       rb[h] = v4i{0, 0, 0, 0};
       if (c / 16 < per_row && p0 + r < pr1) rb[h] = *reinterpret_cast<const v4i *>(X8 + (p0 + r) * mp + k0 + c);
     }
   };
-  auto store = [&](int buf, const v4i (&ra)[2], const v4i (&rb)[4]) {
+  auto store = [&](int buf, const v4i (&ra)[NA], const v4i (&rb)[NB]) {
     int8_t *As = reinterpret_cast<int8_t *>(smem) + buf * STAGE;
     int8_t *Bs = As + NBQ * BROW;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int e = tid + 256 * h, r = e / 8, c = (e % 8) * 16;
+    for (int h = 0; h < NA; ++h) {
+      const int e = tid + 256 * h, r = e / CPR, c = (e % CPR) * 16;
       *reinterpret_cast<v4i *>(As + r * BROW + c) = ra[h];
     }
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int e = tid + 256 * h, r = e / 8, c = (e % 8) * 16;
+    for (int h = 0; h < NB; ++h) {
+      const int e = tid + 256 * h, r = e / CPR, c = (e % CPR) * 16;
       *reinterpret_cast<v4i *>(Bs + r * BROW + c) = rb[h];
     }
   };
@@ -291,13 +297,13 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
           acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
   };
-  static_assert(BK == 128, "load and store map eight 16-byte pieces per row");
+  static_assert(BK % 64 == 0, "whole MFMA K steps per slice");
   const int nsl = nks + (tail ? 1 : 0);
   auto width = [&](int s) { return s < nks ? BK : tail; };
   // PF register stages: stage u holds slices u, u + PF, ...; a stage is
   // refilled once its slice is in LDS, PF slices before it is stored again
   constexpr int NS = PF;
-  v4i ra[NS][2], rb[NS][4];
+  v4i ra[NS][NA], rb[NS][NB];
 #pragma unroll
   for (int u = 0; u < NS; ++u)
     if (u < nsl) load((int64_t)u * BK, width(u), ra[u], rb[u]);
@@ -318,7 +324,7 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
 }
 
 // The scan for k <= 64:
-//  * the K loop is double-buffered: the next 128-byte slice of the query
+//  * the K loop is double-buffered: the next BK-byte slice of the query
 //    and point tiles is loaded into registers while the current one is
 //    consumed from LDS (one barrier per slice);
 //  * the per-query k smallest live in registers, one sorted list per query
@@ -335,7 +341,8 @@ __global__ __launch_bounds__(256) void k_naive_u8_k64(const int8_t *__restrict__
                                                       uint64_t *__restrict__ part, int64_t nranges) {
   constexpr uint64_t PAD = ~0ull;
   constexpr int QPW = NBQ / 4;  // queries owned by one wave in the epilogue
-  __shared__ __align__(16) uint8_t smem[2 * STAGE > NBQ * DSTR * 4 ? 2 * STAGE : NBQ * DSTR * 4];
+  __shared__ __align__(16) uint8_t smem[2 * stage_bytes(BK_NAIVE) > NBQ * DSTR * 4 ? 2 * stage_bytes(BK_NAIVE)
+                                                                                     : NBQ * DSTR * 4];
   __shared__ uint64_t Cb[NBQ][CB];
   uint32_t *Ds = reinterpret_cast<uint32_t *>(smem);
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -353,7 +360,7 @@ __global__ __launch_bounds__(256) void k_naive_u8_k64(const int8_t *__restrict__
   }
   for (int64_t p0 = pr0; p0 < pr1; p0 += NBP) {
     v4i acc[2][4];
-    gemm_u8_tile<MET>(Q8, nq, X8, q0, p0, pr1, mp, smem, acc);
+    gemm_u8_tile<MET, 1, BK_NAIVE>(Q8, nq, X8, q0, p0, pr1, mp, smem, acc);
     // distances of the tile into LDS (the stage buffers are free now)
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -413,7 +420,8 @@ __global__ __launch_bounds__(256) void k_naive_u8(const int8_t *__restrict__ Q8,
                                                   int64_t nq, int64_t n, int64_t mp, int k, int64_t prange,
                                                   uint64_t *__restrict__ part, int64_t nranges) {
   // the pipeline stages and the distance tile are never live at the same time
-  __shared__ __align__(16) uint8_t smem[2 * STAGE > NBQ * DSTR * 4 ? 2 * STAGE : NBQ * DSTR * 4];
+  __shared__ __align__(16) uint8_t smem[2 * stage_bytes(BK_NAIVE) > NBQ * DSTR * 4 ? 2 * stage_bytes(BK_NAIVE)
+                                                                                     : NBQ * DSTR * 4];
   uint32_t *Ds = reinterpret_cast<uint32_t *>(smem);
   __shared__ uint64_t L[NBQ * KC];
   __shared__ uint64_t Tau[NBQ];
@@ -428,7 +436,7 @@ __global__ __launch_bounds__(256) void k_naive_u8(const int8_t *__restrict__ Q8,
   __syncthreads();
   for (int64_t p0 = pr0; p0 < pr1; p0 += NBP) {
     v4i acc[2][4];
-    gemm_u8_tile<MET>(Q8, nq, X8, q0, p0, pr1, mp, smem, acc);
+    gemm_u8_tile<MET, 1, BK_NAIVE>(Q8, nq, X8, q0, p0, pr1, mp, smem, acc);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -499,12 +507,15 @@ __global__ __launch_bounds__(256) void k_build_q8(const Slot *__restrict__ slots
 // sampled pair (flag 0; every pair when the round is round 0), flag exact.
 // Exact in integers (int8 MFMA, int32 accumulation, m <= 65536).  For the l1
 // distance the same tiles sum |x_j - q_j| with v_sad_u8 on zero-padded rows.
-template <int MET>
+template <int MET, int PF>
 __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ slots, const int8_t *__restrict__ Q8,
                                                      const int32_t *__restrict__ qn, const int8_t *__restrict__ X8,
                                                      const int32_t *__restrict__ xn, Bufs B, Geometry G, int32_t cur,
                                                      int32_t impl, uint32_t *__restrict__ Dpm, int32_t nqp) {
-  __shared__ __align__(16) uint8_t smem[2 * STAGE];
+  // the K loop's stages, then the tile's point-major sums for the stores
+  constexpr int TROW = NBQ + 4;  // words per point row of the staged sums (16-byte aligned rows)
+  constexpr int SMEM = 2 * stage_bytes(BK_EXACT) > NBP * TROW * 4 ? 2 * stage_bytes(BK_EXACT) : NBP * TROW * 4;
+  __shared__ __align__(16) uint8_t smem[SMEM];
   const int64_t n = G.n, mp = G.mp;
   const int ns = G.nslots;
   // work item (point tile, query tile), query tile fastest: the query tiles
@@ -525,7 +536,7 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
     take[threadIdx.x] = t ? 1 : 0;
   }
   v4i acc[2][4];
-  gemm_u8_tile<MET, 3>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);  // (its barriers publish take[])
+  gemm_u8_tile<MET, PF, BK_EXACT>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);  // (its barriers publish take[])
   const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
   uint64_t my_pairs = 0;
   // the pairs' flags first, all loads in flight together (flag 0: an
@@ -543,23 +554,32 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
         fv[a][v][b] = (take[ql] && i < n) ? (impl ? (uint8_t)0 : B.fl[s * n + i]) : (uint8_t)1;
       }
     }
+  // point-major batches: the sums go through LDS as [point][query] rows, so
+  // that each point's 64 queries are stored as 16-byte pieces (a pair that
+  // keeps its sum is marked ~0, above every sum: m * 65025 < 2^32 - 1)
+  uint32_t *T = reinterpret_cast<uint32_t *>(smem);  // (the K loop ended with a barrier)
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t s = q0 + 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+      const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+      const int64_t s = q0 + ql;
       const int64_t qs = (MET == KNN_METRIC_L1 || s >= ns) ? 0 : qn[s];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        if (fv[a][v][b] != 0) continue;
-        const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
+        const int pl = 64 * wp + 16 * b + (lane & 15);
+        if (fv[a][v][b] != 0) {
+          if (G.flagsets) T[pl * TROW + ql] = ~0u;
+          continue;
+        }
+        const int64_t i = p0 + pl;
         const int64_t off = s * n + i;
         const int64_t v64 = MET == KNN_METRIC_L1 ? (int64_t)(uint32_t)acc[a][b][v]
                                                  : qs + (int64_t)xn[i] - 2 * (int64_t)acc[a][b][v];
         if (G.flagsets) {
           // point-major sums (below 2^32 for m <= 65536); the round of the
           // pair's last samples is recorded with its exact flag
-          Dpm[i * nqp + s] = (uint32_t)v64;
+          T[pl * TROW + ql] = (uint32_t)v64;
           B.ri[off] = impl ? (uint8_t)0 : (uint8_t)(cur - 1);
         } else {
           B.S[off] = v64;
@@ -569,6 +589,27 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
         ++my_pairs;
       }
     }
+  if (G.flagsets) {
+    __syncthreads();
+    // 16-byte pieces: NBP rows x NBQ / 4 pieces (nqp is a multiple of 16, so
+    // a piece's four queries are all below nqp or all at or past it)
+    constexpr int PIECES = NBP * NBQ / 4;
+    for (int e = threadIdx.x; e < PIECES; e += 256) {
+      const int pl = e / (NBQ / 4), qc = 4 * (e % (NBQ / 4));
+      const int64_t i = p0 + pl, s = q0 + qc;
+      if (i >= n || s >= nqp) continue;
+      const uint4 val = *reinterpret_cast<const uint4 *>(&T[pl * TROW + qc]);
+      uint32_t *dst = Dpm + i * nqp + s;
+      if (val.x != ~0u && val.y != ~0u && val.z != ~0u && val.w != ~0u) {
+        *reinterpret_cast<uint4 *>(dst) = val;
+      } else {
+        if (val.x != ~0u) dst[0] = val.x;
+        if (val.y != ~0u) dst[1] = val.y;
+        if (val.z != ~0u) dst[2] = val.z;
+        if (val.w != ~0u) dst[3] = val.w;
+      }
+    }
+  }
   if (G.prof) {  // whole waves reach this point
     wave_count_add(&prof_copy(G.prof)[0], my_pairs * (uint64_t)(G.m + 14));
     wave_count_add(&prof_copy(G.prof)[2], my_pairs * (uint64_t)G.m);
@@ -588,12 +629,25 @@ void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, 
                         hipStream_t st) {
   const int64_t nwork = ((G.n + NBP - 1) / NBP) * ((G.nslots + NBQ - 1) / NBQ);
   const dim3 grid((unsigned)xcd_grid(nwork));
-  if (G.metric == KNN_METRIC_L1)
-    hipLaunchKernelGGL(k_exact_ql_u8<KNN_METRIC_L1>, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl,
-                       Dpm, nqp);
-  else
-    hipLaunchKernelGGL(k_exact_ql_u8<KNN_METRIC_L2>, grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl,
-                       Dpm, nqp);
+  // slices of global loads in flight per thread (KNN_EXACT_PF: 3 (default), 4 or 6)
+  const int pf = [] {  // (read per launch, like the other knobs)
+    const char *e = std::getenv("KNN_EXACT_PF");
+    const int v = e ? std::atoi(e) : 3;
+    return (v == 4 || v == 6) ? v : 3;
+  }();
+#define KNN_EXACT_LAUNCH(MET_, PF_)                                                                           \
+  hipLaunchKernelGGL((k_exact_ql_u8<MET_, PF_>), grid, dim3(256), 0, st, slots, Q8, qn, X8, xn, B, G, cur, impl, \
+                     Dpm, nqp)
+  if (G.metric == KNN_METRIC_L1) {
+    if (pf == 3) KNN_EXACT_LAUNCH(KNN_METRIC_L1, 3);
+    else if (pf == 4) KNN_EXACT_LAUNCH(KNN_METRIC_L1, 4);
+    else KNN_EXACT_LAUNCH(KNN_METRIC_L1, 6);
+  } else {
+    if (pf == 3) KNN_EXACT_LAUNCH(KNN_METRIC_L2, 3);
+    else if (pf == 4) KNN_EXACT_LAUNCH(KNN_METRIC_L2, 4);
+    else KNN_EXACT_LAUNCH(KNN_METRIC_L2, 6);
+  }
+#undef KNN_EXACT_LAUNCH
 }
 
 // Merge per query: the k smallest keys over all ranges, sorted; index and

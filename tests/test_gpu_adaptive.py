@@ -163,6 +163,8 @@ KNOBS = ([{"KNN_LPP": v} for v in ("1", "2", "4", "8", "16", "32", "64")] +
          [{"KNN_QL_MIN": "1"}, {"KNN_QL_MIN": "1", "KNN_GROUP": "0"}] +
          # query-lane batches whose slots switch to per-slot lists after round 0, or never
          [{"KNN_QL_MIN": "1", "KNN_SPARSE_DIV": "1"}, {"KNN_QL_MIN": "1", "KNN_SPARSE_DIV": "0"}] +
+         # prefetch depth of the exact round's tiles
+         [{"KNN_QL_MIN": "1", "KNN_EXACT_PF": v} for v in ("4", "6")] +
          [{"KNN_CH_SAMPLE": v} for v in ("64", "256", "4096")] + [{"KNN_GROUP": "0"}] +
          # every sampled round from point rows staged in LDS, at each tile height
          [{"KNN_STAGE_MIN": "4", "KNN_STAGE_ROWS": v} for v in ("8", "16", "32", "64")] +
