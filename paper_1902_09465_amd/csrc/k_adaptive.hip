@@ -936,18 +936,23 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
           }
         }
       };
-      // two register stages: the loads of block d + 1 are in flight while d
-      // is summed (issued unconditionally, the last block once more, so that
-      // the wait before each sum covers only the older stage)
-      uint4 qa[4], qb[4];
+      // three register stages: the loads of blocks d + 1 and d + 2 are in
+      // flight while d is summed (issued unconditionally, the last block
+      // again at the end, so that the wait before each sum covers only the
+      // oldest stage)
+      uint4 qa[4], qb[4], qc[4];
       fetch(0, qa);
+      fetch(min(1, nb - 1), qb);
       int d = 0;
       for (;;) {
-        fetch(min(d + 1, nb - 1), qb);
+        fetch(min(d + 2, nb - 1), qc);
         consume(d, qa);
         if (++d >= nb) break;
-        fetch(min(d + 1, nb - 1), qa);
+        fetch(min(d + 2, nb - 1), qa);
         consume(d, qb);
+        if (++d >= nb) break;
+        fetch(min(d + 2, nb - 1), qb);
+        consume(d, qc);
         if (++d >= nb) break;
       }
     }
