@@ -498,12 +498,35 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
     if (e != hipSuccess && rc == KNN_OK)
       rc = fail(e == hipErrorOutOfMemory ? KNN_ENOMEM : KNN_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
   };
-  chk(hipMemcpyAsync(E.ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice, st), "copy ctl");
-  chk(hipMemcpyAsync(E.qd, P.qd.data(), sizeof(QDesc) * nq, hipMemcpyHostToDevice, st), "copy queries");
-  chk(hipMemcpyAsync(E.sched, P.sched.data(), sizeof(Sched) * P.sched.size(), hipMemcpyHostToDevice, st),
-      "copy schedules");
+  {  // the control block, query descriptors and schedules through the DB's pinned staging buffer
+    std::lock_guard<std::mutex> lk(db->stage_mu);
+    const size_t b_ctl = align_up(sizeof(Ctl), 256), b_qd = align_up(sizeof(QDesc) * nq, 256);
+    const size_t b_sc = sizeof(Sched) * P.sched.size(), need = b_ctl + b_qd + b_sc;
+    if (db->stage_done)
+      chk(hipEventSynchronize(db->stage_done), "staging wait");  // the previous batch's copies are done
+    else
+      chk(hipEventCreateWithFlags(&db->stage_done, hipEventDisableTiming), "staging event");
+    if (rc == KNN_OK && need > db->stage_cap) {
+      if (db->stage) (void)hipHostFree(db->stage);
+      db->stage = nullptr;
+      db->stage_cap = 0;
+      chk(hipHostMalloc(&db->stage, need), "staging buffer");
+      if (rc == KNN_OK) db->stage_cap = need;
+    }
+    if (rc == KNN_OK) {
+      uint8_t *h = static_cast<uint8_t *>(db->stage);
+      std::memcpy(h, &ctl, sizeof(Ctl));
+      std::memcpy(h + b_ctl, P.qd.data(), sizeof(QDesc) * nq);
+      std::memcpy(h + b_ctl + b_qd, P.sched.data(), b_sc);
+      chk(hipMemcpyAsync(E.ctl, h, sizeof(Ctl), hipMemcpyHostToDevice, st), "copy ctl");
+      chk(hipMemcpyAsync(E.qd, h + b_ctl, sizeof(QDesc) * nq, hipMemcpyHostToDevice, st), "copy queries");
+      chk(hipMemcpyAsync(E.sched, h + b_ctl + b_qd, b_sc, hipMemcpyHostToDevice, st), "copy schedules");
+      chk(hipEventRecord(db->stage_done, st), "staging record");
+    }
+  }
+  const bool lockstep = nq <= ns || stop_after > 0;
   if (rc == KNN_OK) {
-    if (nq <= ns || stop_after > 0) {
+    if (lockstep) {
       launch_lockstep(E, P, nq, K, st);
       chk(hipGetLastError(), "launch");
     } else {
@@ -532,8 +555,11 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
     *keep = E;
     return KNN_OK;  // caller frees
   }
-  const int rc2 = engine_destroy(E);
-  chk(hipStreamSynchronize(st), "hipStreamSynchronize");
+  const int rc2 = engine_destroy(E);  // (a stream-ordered free)
+  // a batch with every query in flight at once is stream-ordered: its host
+  // data went through the staging buffer, so the call returns without
+  // waiting; the polled form has synchronised already
+  if (!lockstep || rc != KNN_OK) chk(hipStreamSynchronize(st), "hipStreamSynchronize");
   return rc != KNN_OK ? rc : rc2;
 }
 
@@ -605,6 +631,8 @@ int knn_db_destroy(knn_db db) {
   if (db->users.load() > 0) return fail(KNN_EBUSY, "DB is held by a session");
   (void)hipDeviceSynchronize();
   if (db->plan) plan_free(db->plan);
+  if (db->stage) (void)hipHostFree(db->stage);
+  if (db->stage_done) (void)hipEventDestroy(db->stage_done);
   naive_free_db(db);
   if (db->owned) (void)hipFree(db->owned);
   delete db;

@@ -46,6 +46,12 @@ struct knn_db_s {
   std::mutex mu;
   knn::Plan *plan = nullptr;   // cached engine + captured graph of the last batch shape
   knn::Knobs tune;             // autotuned knobs (tune.valid)
+  // pinned staging of an eager batch's control block, query descriptors and
+  // schedules: reused once the previous batch's copies out of it are done
+  void *stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t stage_done = nullptr;
+  std::mutex stage_mu;
 };
 
 namespace knn {
