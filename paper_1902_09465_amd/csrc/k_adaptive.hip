@@ -19,6 +19,7 @@
 // (compiled without FMA contraction); sums are integers, so the result does
 // not depend on launch shape, chunking or atomic order.
 #include <algorithm>
+#include <cstdlib>
 
 #include "block_select.h"
 #include "knn_internal.h"
@@ -2419,6 +2420,14 @@ void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint
   hipLaunchKernelGGL(k_build_qt, dim3(blocks), dim3(NT), 0, st, slots, ns, m, nqp, qt);
 }
 
+// Point blocks of a query-lane sampling launch (each walks a contiguous
+// range of points).  KNN_QL_BLOCKS overrides the default.
+static unsigned ql_blocks_x(int64_t n) {
+  const char *e = std::getenv("KNN_QL_BLOCKS");
+  const int64_t want = e ? std::max<int64_t>(1, std::atoll(e)) : 2048;
+  return (unsigned)std::min<int64_t>((n + QL_NW - 1) / QL_NW, want);
+}
+
 void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
                  const Bufs &B, const Geometry &G0, bool any_cexact, hipStream_t st, int sample_kind,
                  int stage_rows, const QlRound *ql, const uint8_t *qt, int32_t nqp, uint32_t *qd_buf,
@@ -2440,7 +2449,7 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
       launch_exact_ql_u8(slots, q8, q8n, G.x8, G.xn, B, G, ql->cur, ql->impl, qd_buf, nqp, st);
       prof_end(tk, st, 0.0);
     } else {
-      const unsigned bx = (unsigned)std::min<int64_t>((G.n + QL_NW - 1) / QL_NW, 2048);
+      const unsigned bx = ql_blocks_x(G.n);
       const unsigned by = (unsigned)((nqp + QL_SLOTS - 1) / QL_SLOTS);
       const int tk = prof_begin(PROF_SAMPLE, st);
       if (G.metric == KNN_METRIC_L1)
@@ -2492,7 +2501,7 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
   if (ql_exact) {
     // sampling done above
   } else if (use_ql) {
-    const unsigned bx = (unsigned)std::min<int64_t>((G.n + QL_NW - 1) / QL_NW, 2048);
+    const unsigned bx = ql_blocks_x(G.n);
     const unsigned by = (unsigned)((nqp + QL_SLOTS - 1) / QL_SLOTS);
     uint8_t *A = reinterpret_cast<uint8_t *>(qd_buf + G.n * (int64_t)nqp);  // follows D in the arena
     const dim3 tiles((unsigned)((G.n + FT - 1) / FT), (unsigned)((nqp + FT - 1) / FT));
