@@ -313,6 +313,29 @@ def test_graph_replays_equal_eager(P, orc):
     assert torch.equal(got[0], eager[0][0])
 
 
+def test_batches_queued_without_sync(P, orc, monkeypatch):
+    """A batch whose queries all fit is stream-ordered: batches of different
+    queries and sizes queued back to back, with no synchronisation between
+    them, equal the same batches run one at a time (the host staging buffer
+    is reused and regrown, the engine arenas come from the pool)."""
+    monkeypatch.setenv("KNN_GRAPH", "0")  # the eager engine
+    X, Q = gmm_u8(73, n=6007, m=300, n_centres=6, sigma=25.0, nq=200)
+    db = P.KnnDB(dev(X))
+    p = P.default_params(h=6, delta=0.05, seed=9)
+    batches = [dev(Q[:96]), dev(Q[96:200]), dev(Q[:40]), dev(Q[50:146])]
+    ref = []
+    for b in batches:
+        i, c, _ = db.adaptive(b, 6, p, with_stats=False)
+        torch.cuda.synchronize()
+        ref.append((i.clone(), c.clone()))
+    got = [db.adaptive(b, 6, p, with_stats=False) for b in batches]
+    torch.cuda.synchronize()
+    for (gi, gc, _), (ri, rc) in zip(got, ref):
+        assert torch.equal(gi, ri) and torch.equal(gc, rc)
+    o = orc.adaptive(X, Q[100], 6, oparams(orc, h=6, delta=0.05, seed=9))[0]
+    assert got[1][0][4, :got[1][1][4]].cpu().tolist() == o.tolist()
+
+
 def test_autotune_keeps_results(P, orc):
     """The autotuner times every knob candidate, checks that all of them give
     the same output, keeps the fastest, and later calls still equal the oracle."""
