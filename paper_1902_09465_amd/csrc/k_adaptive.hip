@@ -1115,10 +1115,13 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
 }
 
 // Tiles of the selection over point-major sums (k_select_pm): FS_SL slots x
-// FS_PT points, one wave per slot row, sixteen points per lane; the kept set
-// P is exactly the points without a discard flag.  Needs k + 1 <= 64 (the
-// wave selection below).
-constexpr int FS_SL = 4, FS_PT = 1024;  // one slot row per wave; ~18 KB LDS
+// FS_PT points, one wave per slot row at a time, sixteen points per lane;
+// the kept set P is exactly the points without a discard flag.  Needs
+// k + 1 <= 64 (the wave selection below).  A tile reads FS_SL * 4 bytes of
+// each point's 128-byte line of D; wider tiles cut the L2-to-L1 traffic but
+// hold FS_SL x 4 KB of LDS per block, and measured slower (selection per
+// step: 4 slots 1.70 ms, 8 slots 1.85 ms, 16 slots 2.46 ms).
+constexpr int FS_SL = 4, FS_PT = 1024;
 constexpr int FS_E = FS_PT / kWave;
 
 // The K (<= 64) smallest of the wave's E keys per lane (PAD = none), written
@@ -1320,27 +1323,33 @@ __device__ __forceinline__ uint32_t *fs_mixed(const Bufs &B, int sl, int64_t n) 
 constexpr int FS_TS = FS_PT + 4;  // LDS row stride in words: rows stay 16-byte aligned
 
 // The sums of a tile of FS_SL slots x FS_PT points, transposed into LDS rows:
-// one 16-byte load per point (the FS_SL slots; nqp is a multiple of 16), all
-// in flight at once (clamped rows, zeroed after).
-template <int BT>
+// FS_SL / 4 16-byte loads per point (nqp is a multiple of 16), four points'
+// worth in flight at once per thread (clamped rows, zeroed after).
 __device__ __forceinline__ void fs_stage_sums(uint32_t (*t)[FS_TS], const uint32_t *__restrict__ D, int32_t nqp,
                                               int64_t i0, int s0, int64_t n) {
-  static_assert(FS_SL == 4, "one 16-byte load per point");
-  constexpr int PER = FS_PT / BT;
-  uint4 v[PER];
+  static_assert(FS_SL % 4 == 0 && FS_SL <= 16, "16-byte pieces of one line per point");
+  constexpr int PER = FS_PT / NT, Q = FS_SL / 4, U = 4;
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int64_t i = min(i0 + threadIdx.x + u * BT, n - 1);
-    v[u] = *reinterpret_cast<const uint4 *>(D + i * nqp + s0);
-  }
+  for (int u0 = 0; u0 < PER; u0 += U) {
+    uint4 v[U][Q];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int pt = threadIdx.x + u * BT;
-    const bool in = i0 + pt < n;
-    t[0][pt] = in ? v[u].x : 0u;
-    t[1][pt] = in ? v[u].y : 0u;
-    t[2][pt] = in ? v[u].z : 0u;
-    t[3][pt] = in ? v[u].w : 0u;
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = min(i0 + threadIdx.x + (u0 + u) * NT, n - 1);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) v[u][q] = *reinterpret_cast<const uint4 *>(D + i * nqp + s0 + 4 * q);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int pt = threadIdx.x + (u0 + u) * NT;
+      const bool in = i0 + pt < n;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        t[4 * q + 0][pt] = in ? v[u][q].x : 0u;
+        t[4 * q + 1][pt] = in ? v[u][q].y : 0u;
+        t[4 * q + 2][pt] = in ? v[u][q].z : 0u;
+        t[4 * q + 3][pt] = in ? v[u][q].w : 0u;
+      }
+    }
   }
 }
 
@@ -1370,7 +1379,7 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
     }
     if (!any) return;
   }
-  fs_stage_sums<NT>(t, D, nqp, i0, s0, n);
+  fs_stage_sums(t, D, nqp, i0, s0, n);
   __syncthreads();
   const int lane = lane_id(), wave = threadIdx.x / kWave;
   // whole tile with 4-byte aligned flag rows: each lane takes four runs of
@@ -1476,7 +1485,7 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
 __global__ __launch_bounds__(kWave) void k_select_pm_mixed(const Slot *__restrict__ slots,
                                                            const uint32_t *__restrict__ D, int32_t nqp, Bufs B,
                                                            Geometry G, int32_t cur, int32_t init) {
-  __shared__ __align__(16) uint32_t t[FS_SL][FS_TS];
+  __shared__ uint32_t tc[FS_PT];
   __shared__ uint64_t cbuf[kWave];
   const int64_t n = G.n, m = G.m;
   const int sl = blockIdx.x;
@@ -1488,12 +1497,15 @@ __global__ __launch_bounds__(kWave) void k_select_pm_mixed(const Slot *__restric
   const int lane = lane_id();
   const int k = slp->k;
   const RoundConsts rc = round_consts(slp, m, cur);
-  const int r = sl % FS_SL;
   for (uint32_t e0 = 0; e0 < nmix; ++e0) {
     const int64_t tile = ml[1 + e0];
     const int64_t i0 = tile * FS_PT;
-    __builtin_amdgcn_s_barrier();  // (one wave) the previous tile's reads of t are done
-    fs_stage_sums<kWave>(t, D, nqp, i0, sl - r, n);
+    __builtin_amdgcn_s_barrier();  // (one wave) the previous tile's reads of tc are done
+#pragma unroll
+    for (int e = 0; e < FS_E; ++e) {  // this slot's column of the tile (a rare path: 4-byte loads)
+      const int p = e * kWave + lane;
+      tc[p] = i0 + p < n ? D[(i0 + p) * nqp + sl] : 0u;
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -1513,7 +1525,7 @@ __global__ __launch_bounds__(kWave) void k_select_pm_mixed(const Slot *__restric
         if (f & FL_DISC) continue;
         const bool late = (f & FL_ACC) && !(f & FL_EXACT);  // accepted before this round
         double d, al;
-        pair_bounds(slp, rc, (int64_t)t[r][p], f, late ? B.ri[(int64_t)sl * n + i] : (uint8_t)0, !late, d, al);
+        pair_bounds(slp, rc, (int64_t)tc[p], f, late ? B.ri[(int64_t)sl * n + i] : (uint8_t)0, !late, d, al);
         key[e] = lower ? dkey(d - al) : dkey(d + al);
       }
       if (lower)
