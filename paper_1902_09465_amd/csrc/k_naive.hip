@@ -175,10 +175,18 @@ __device__ __forceinline__ uint32_t tile_dist(const int32_t *qn, const int32_t *
   return (uint32_t)((int64_t)qn[q] + (int64_t)xn[p] - 2 * (int64_t)acc);
 }
 
-// A pipeline slice is BK bytes of K (a multiple of the 64-byte MFMA step);
-// its LDS rows are padded by 16 bytes (conflict-free fragment reads).
-constexpr int stage_bytes(int BK) { return (NBQ + NBP) * (BK + 16); }
+// A pipeline slice is BK bytes of K (a multiple of the 64-byte MFMA step)
+// of a tile of nbq query rows and NBP point rows; its LDS rows are padded by
+// 16 bytes (conflict-free fragment reads).
+constexpr int stage_bytes(int BK, int nbq = NBQ) { return (nbq + NBP) * (BK + 16); }
 constexpr int BK_NAIVE = 128, BK_EXACT = 64;  // the scan's and the exact round's slices
+// the exact round's query fragments per wave (block tile: 32 WA queries).
+// Two for both distances: a 64 x 64 wave tile (four) doubles the fragment
+// reuse but measured slower for squared l2 (1.07 vs 0.89 ms per round at
+// 1024 x 100,000 x 3072: more registers, fewer waves), and the l1 tile
+// would hold the query bytes of every fragment in registers.
+template <int MET>
+constexpr int exact_wa() { return 2; }
 constexpr int CB = 32;                  // candidate buffer per query (<= 64)
 
 // list: sorted ascending over the lanes; cand: one key per lane (PAD = none).
@@ -206,23 +214,24 @@ __device__ __forceinline__ uint64_t merge_sorted64(uint64_t list, uint64_t cand)
 // of the next PF slices are in flight in registers while the current slice
 // is consumed, so each load has PF slices of compute to arrive.  Rows beyond
 // nq / pend read as zeros.  smem: 2 x stage_bytes(BK) bytes.
-template <int MET, int PF, int BK>
+template <int MET, int PF, int BK, int WA = 2>
 __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int64_t nq, const int8_t *__restrict__ X8,
                                              int64_t q0, int64_t p0, int64_t pr1, int64_t mp, uint8_t *smem,
-                                             v4i (&acc)[2][4]) {
+                                             v4i (&acc)[WA][4]) {
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int wq = wave >> 1, wp = wave & 1;
-  constexpr int BROW = BK + 16, STAGE = stage_bytes(BK);
+  constexpr int TQ = 32 * WA;  // query rows of the block tile (16 WA per wave)
+  constexpr int BROW = BK + 16, STAGE = stage_bytes(BK, TQ);
   const int nks = (int)(mp / BK), tail = (int)(mp % BK);  // mp is a multiple of 64: tail 0 or 64
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < WA; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
-  // slice s covers K bytes [s BK, s BK + width): A 64 x width, B 128 x width
+  // slice s covers K bytes [s BK, s BK + width): A TQ x width, B 128 x width
   // a slice is CPR 16-byte pieces per row: the 256 threads take NA pieces
   // of the query tile and NB of the point tile each
-  constexpr int CPR = BK / 16, NA = NBQ * CPR / 256, NB = NBP * CPR / 256;
-  static_assert(NA * 256 == NBQ * CPR && NB * 256 == NBP * CPR, "whole pieces per thread");
+  constexpr int CPR = BK / 16, NA = TQ * CPR / 256, NB = NBP * CPR / 256;
+  static_assert(NA * 256 == TQ * CPR && NB * 256 == NBP * CPR, "whole pieces per thread");
   auto load = [&](int64_t k0, int width, v4i (&ra)[NA], v4i (&rb)[NB]) {
     const int per_row = width / 16;
 #pragma unroll
@@ -240,7 +249,7 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
   };
   auto store = [&](int buf, const v4i (&ra)[NA], const v4i (&rb)[NB]) {
     int8_t *As = reinterpret_cast<int8_t *>(smem) + buf * STAGE;
-    int8_t *Bs = As + NBQ * BROW;
+    int8_t *Bs = As + TQ * BROW;
 #pragma unroll
     for (int h = 0; h < NA; ++h) {
       const int e = tid + 256 * h, r = e / CPR, c = (e % CPR) * 16;
@@ -254,22 +263,22 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
   };
   auto compute = [&](int buf, int width) {
     const int8_t *As = reinterpret_cast<const int8_t *>(smem) + buf * STAGE;
-    const int8_t *Bs = As + NBQ * BROW;
+    const int8_t *Bs = As + TQ * BROW;
     if constexpr (MET == KNN_METRIC_L1) {
       // 16 bytes of K at a time: the lane's 8 query rows and 4 point rows,
       // then 8 x 4 x 4 sums of absolute differences
       for (int kk = 0; kk < width; kk += 16) {
-        v4i qv[2][4], pv[4];
+        v4i qv[WA][4], pv[4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < WA; ++a)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            qv[a][v] = *reinterpret_cast<const v4i *>(As + (32 * wq + 16 * a + 4 * (lane >> 4) + v) * BROW + kk);
+            qv[a][v] = *reinterpret_cast<const v4i *>(As + (16 * WA * wq + 16 * a + 4 * (lane >> 4) + v) * BROW + kk);
 #pragma unroll
         for (int b = 0; b < 4; ++b)
           pv[b] = *reinterpret_cast<const v4i *>(Bs + (64 * wp + 16 * b + (lane & 15)) * BROW + kk);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < WA; ++a)
 #pragma unroll
           for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -283,15 +292,15 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
       return;
     }
     for (int kk = 0; kk < width; kk += 64) {
-      v4i af[2], bf[4];
+      v4i af[WA], bf[4];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-        af[a] = *reinterpret_cast<const v4i *>(As + (32 * wq + 16 * a + (lane & 15)) * BROW + kk + 16 * (lane >> 4));
+      for (int a = 0; a < WA; ++a)
+        af[a] = *reinterpret_cast<const v4i *>(As + (16 * WA * wq + 16 * a + (lane & 15)) * BROW + kk + 16 * (lane >> 4));
 #pragma unroll
       for (int b = 0; b < 4; ++b)
         bf[b] = *reinterpret_cast<const v4i *>(Bs + (64 * wp + 16 * b + (lane & 15)) * BROW + kk + 16 * (lane >> 4));
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < WA; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
@@ -512,63 +521,65 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
                                                      const int32_t *__restrict__ qn, const int8_t *__restrict__ X8,
                                                      const int32_t *__restrict__ xn, Bufs B, Geometry G, int32_t cur,
                                                      int32_t impl, uint32_t *__restrict__ Dpm, int32_t nqp) {
+  // block tile XQ queries x NBP points: each wave 16 XWA queries x 64 points
+  constexpr int XWA = exact_wa<MET>(), XQ = 32 * XWA;
   // the K loop's stages, then the tile's point-major sums for the stores
-  constexpr int TROW = NBQ + 4;  // words per point row of the staged sums (16-byte aligned rows)
-  constexpr int SMEM = 2 * stage_bytes(BK_EXACT) > NBP * TROW * 4 ? 2 * stage_bytes(BK_EXACT) : NBP * TROW * 4;
+  constexpr int TROW = XQ + 4;  // words per point row of the staged sums (16-byte aligned rows)
+  constexpr int SMEM = 2 * stage_bytes(BK_EXACT, XQ) > NBP * TROW * 4 ? 2 * stage_bytes(BK_EXACT, XQ)
+                                                                       : NBP * TROW * 4;
   __shared__ __align__(16) uint8_t smem[SMEM];
   const int64_t n = G.n, mp = G.mp;
   const int ns = G.nslots;
   // work item (point tile, query tile), query tile fastest: the query tiles
   // of one point tile read the same point rows, so they run back to back on
   // one XCD and the rows come from its L2
-  const int64_t nqt = (ns + NBQ - 1) / NBQ, nwork = nqt * ((n + NBP - 1) / NBP);
+  const int64_t nqt = (ns + XQ - 1) / XQ, nwork = nqt * ((n + NBP - 1) / NBP);
   const int64_t w = xcd_work_item(nwork);
   if (w >= nwork) return;
   const int64_t p0 = (w / nqt) * NBP;
-  const int64_t q0 = (w % nqt) * NBQ;
+  const int64_t q0 = (w % nqt) * XQ;
   const int64_t pend = std::min(n, p0 + NBP);
   // which of the tile's slots take this pass (read once, before the K loop)
-  __shared__ uint8_t take[NBQ];
-  if (threadIdx.x < NBQ) {
+  __shared__ uint8_t take[XQ];
+  if (threadIdx.x < XQ) {
     const int64_t s = q0 + threadIdx.x;
     bool t = s < ns && slots[s].state == 1 && slots[s].cur == cur;
     if (t && G.flagsets && slots[s].implicit == 0) t = false;  // a sparse slot: its own exact pass
     take[threadIdx.x] = t ? 1 : 0;
   }
-  v4i acc[2][4];
-  gemm_u8_tile<MET, PF, BK_EXACT>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);  // (its barriers publish take[])
+  v4i acc[XWA][4];
+  gemm_u8_tile<MET, PF, BK_EXACT, XWA>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);  // (its barriers publish take[])
   const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
   uint64_t my_pairs = 0;
-  // the pairs' flags first, all loads in flight together (flag 0: an
-  // undecided sampled pair, the only ones made exact; every pair in round 0)
-  uint8_t fv[2][4][4];
+  // point-major batches: the sums go through LDS as [point][query] rows, so
+  // that each point's queries are stored as 16-byte pieces (a pair that
+  // keeps its sum is marked ~0, above every sum: m * 65025 < 2^32 - 1)
+  uint32_t *T = reinterpret_cast<uint32_t *>(smem);  // (the K loop ended with a barrier)
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < XWA; ++a) {
+    // this fragment row's flags first, all loads in flight together (flag
+    // 0: an undecided sampled pair, the only ones made exact; every pair in
+    // round 0)
+    uint8_t fv[4][4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+      const int ql = 16 * XWA * wq + 16 * a + 4 * (lane >> 4) + v;
       const int64_t s = q0 + ql;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
-        fv[a][v][b] = (take[ql] && i < n) ? (impl ? (uint8_t)0 : B.fl[s * n + i]) : (uint8_t)1;
+        fv[v][b] = (take[ql] && i < n) ? (impl ? (uint8_t)0 : B.fl[s * n + i]) : (uint8_t)1;
       }
     }
-  // point-major batches: the sums go through LDS as [point][query] rows, so
-  // that each point's 64 queries are stored as 16-byte pieces (a pair that
-  // keeps its sum is marked ~0, above every sum: m * 65025 < 2^32 - 1)
-  uint32_t *T = reinterpret_cast<uint32_t *>(smem);  // (the K loop ended with a barrier)
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+      const int ql = 16 * XWA * wq + 16 * a + 4 * (lane >> 4) + v;
       const int64_t s = q0 + ql;
       const int64_t qs = (MET == KNN_METRIC_L1 || s >= ns) ? 0 : qn[s];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int pl = 64 * wp + 16 * b + (lane & 15);
-        if (fv[a][v][b] != 0) {
+        if (fv[v][b] != 0) {
           if (G.flagsets) T[pl * TROW + ql] = ~0u;
           continue;
         }
@@ -589,13 +600,14 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
         ++my_pairs;
       }
     }
+  }
   if (G.flagsets) {
     __syncthreads();
-    // 16-byte pieces: NBP rows x NBQ / 4 pieces (nqp is a multiple of 16, so
+    // 16-byte pieces: NBP rows x XQ / 4 pieces (nqp is a multiple of 16, so
     // a piece's four queries are all below nqp or all at or past it)
-    constexpr int PIECES = NBP * NBQ / 4;
+    constexpr int PIECES = NBP * XQ / 4;
     for (int e = threadIdx.x; e < PIECES; e += 256) {
-      const int pl = e / (NBQ / 4), qc = 4 * (e % (NBQ / 4));
+      const int pl = e / (XQ / 4), qc = 4 * (e % (XQ / 4));
       const int64_t i = p0 + pl, s = q0 + qc;
       if (i >= n || s >= nqp) continue;
       const uint4 val = *reinterpret_cast<const uint4 *>(&T[pl * TROW + qc]);
@@ -627,7 +639,8 @@ void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_
 void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, const int8_t *X8, const int32_t *xn,
                         const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, uint32_t *Dpm, int32_t nqp,
                         hipStream_t st) {
-  const int64_t nwork = ((G.n + NBP - 1) / NBP) * ((G.nslots + NBQ - 1) / NBQ);
+  const int xq = 32 * (G.metric == KNN_METRIC_L1 ? exact_wa<KNN_METRIC_L1>() : exact_wa<KNN_METRIC_L2>());
+  const int64_t nwork = ((G.n + NBP - 1) / NBP) * ((G.nslots + xq - 1) / xq);
   const dim3 grid((unsigned)xcd_grid(nwork));
   // slices of global loads in flight per thread (KNN_EXACT_PF: 3 (default), 4 or 6)
   const int pf = [] {  // (read per launch, like the other knobs)
