@@ -429,7 +429,7 @@ def main():
                     help="one copy of known size and one adaptive batch, for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures a single MI355X "
+        print("bench.py measures a single MI355X; multi-GPU runs are not supported "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
