@@ -14,6 +14,10 @@
  *    Arguments are checked before any work is enqueued; on error nothing is
  *    enqueued and knn_last_error() describes the failure (thread-local).
  *    No C++ exception crosses the ABI.
+ *  - Working memory of a batch comes from a stream-ordered pool per device
+ *    that the library keeps for the life of the process (memory freed by a
+ *    batch is reused by the next instead of being unmapped), plus one
+ *    pinned host staging buffer per DB, freed by knn_db_destroy.
  */
 #ifndef KNN_H
 #define KNN_H
