@@ -84,22 +84,24 @@ def test_per_round_state_parity(P, orc, dtype, monkeypatch):
         assert np.array_equal(ri, rio), f"round {r}: round index differs"
 
 
-def test_point_major_mixed_widths(P, orc, monkeypatch):
+@pytest.mark.parametrize("m", [2048, 512])
+def test_point_major_mixed_widths(P, orc, monkeypatch, m):
     """Point-major batch (query lanes, no candidate-exact, dense flags) where a
     pair is accepted rounds before the rest are decided: the selection tiles
-    that hold it mix widths.  Every round's state equals the oracle's, and so
-    does the result."""
+    that hold it mix widths (at m = 2048 in sampled rounds, at m = 512 also
+    in the exact round, beside exact pairs).  Every round's state equals the
+    oracle's, and so does the result."""
     monkeypatch.setenv("KNN_QL_MIN", "1")
     monkeypatch.setenv("KNN_SPARSE_DIV", "0")
     g = rng(31)
-    n, m = 3000, 2048
+    n = 3000
     d = np.concatenate([[0.002, 0.1], g.uniform(0.15, 0.2, 300), g.uniform(0.3, 0.5, n - 302)])
     d = d[g.permutation(n)]
     X, Q, _ = pm_half(31, n, m, d)
     db = P.KnnDB(dev(X))
     kw = dict(h=2, delta=0.05, seed=5, alpha_kind=2, c_alpha=0.01, c_exact=0)
     T = orc.schedule(64, 2.0, 1.0, m)
-    mixed_rounds = 0
+    mixed_rounds, mixed_exact = 0, False
     for r in range(1, len(T) + 2):
         S, fl, ri = db.adaptive_state(dev(Q), 2, P.default_params(**kw), r)
         _, _, (So, flo, rio) = orc.adaptive(X, Q[0], 2, oparams(orc, **kw), stop_after=r, dump=True)
@@ -108,8 +110,12 @@ def test_point_major_mixed_widths(P, orc, monkeypatch):
         assert np.array_equal(ri, rio), f"round {r}: round index differs"
         late = (flo & 2) != 0
         late &= (flo & 1) == 0
-        mixed_rounds += int(late.any() and (flo == 0).any())
+        exact = (flo & 1) != 0
+        mixed_rounds += int(late.any() and ((flo == 0).any() or exact.any()))
+        mixed_exact |= bool(late.any() and exact.any())
     assert mixed_rounds >= 1, "the instance never mixed widths"
+    if m == 512:
+        assert mixed_exact, "the exact round never saw a pair accepted earlier"
     check_query(P, orc, db, X, Q[0], 2, **kw)
 
 
