@@ -408,6 +408,67 @@ def uneven_bench(args):
     return 0
 
 
+def float_bench(args):
+    """The float workload (n = 1,000,000 x m = 128 fp32 points from a
+    1,000-centre Gaussian mixture, centres N(0,1), sigma = 0.1; k = h = 10,
+    delta = 0.05; one seed) on the first --float-queries of its 10,000
+    queries: adaptive (per-slot fp32 kernels, fixed-point sums) against the
+    naive split-BF16 MFMA scan with FP64 rescoring, whose sets and distances
+    are the exact reference for the containment check."""
+    import torch
+    from knn_inputs import gmm_f32
+
+    P = load_lib()
+    nq = int(args.float_queries)
+    log(f"generating the float workload ({nq} of its 10000 queries)")
+    X, Q = gmm_f32(3000, n=1_000_000, m=128, n_centres=1000, sigma=0.1, nq=10_000)
+    Q = np.ascontiguousarray(Q[:nq])
+    Xd = torch.from_numpy(X).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+    db = P.KnnDB(Xd)
+    K = 10
+    p = P.default_params(h=10, delta=0.05, seed=3001)
+    nidx, ndist = db.naive(Qd, K)
+    db.adaptive(Qd, K, p, with_stats=False)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        idx, cnt, _ = db.adaptive(Qd, K, p, with_stats=False)
+    torch.cuda.synchronize()
+    ad_s = (time.perf_counter() - t0) / args.steps
+    _, _, st = db.adaptive(Qd, K, p)
+    evals = st["coord_evals"].astype(np.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        db.naive(Qd, K, with_dist=False)
+    torch.cuda.synchronize()
+    nv_s = (time.perf_counter() - t0) / args.steps
+    # containment: every returned set holds the exact k nearest (FP64 distances of the naive scan,
+    # summed in coordinate order; the sums here run in another order, hence the relative 1e-9)
+    rtol = 1e-9
+    valid = idx >= 0
+    safe = torch.where(valid, idx, torch.zeros_like(idx))
+    pts = Xd[safe.reshape(-1)].reshape(nq, idx.shape[1], -1).double()
+    d = ((pts - Qd[:, None, :].double()) ** 2).sum(-1)
+    d = torch.where(valid, d, torch.full_like(d, float("inf")))
+    dk = ndist[:, K - 1]
+    strict = ndist < dk[:, None] * (1 - rtol)
+    member = (nidx[:, :, None] == idx[:, None, :]).any(-1)
+    ok = ((~strict | member).all(1) & ((d <= dk[:, None] * (1 + rtol)).sum(1) >= K)).sum().item()
+    out = {"metric": "float workload: queries/s adaptive vs naive BF16 MFMA + FP64 rescoring",
+           "value": nq / ad_s, "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"float: n=1000000 x m=128 fp32, 1000-centre Gaussian mixture sigma=0.1, "
+                                  f"{nq} of 10000 queries, k=10 h=10 delta=0.05"},
+           "contained": f"{ok}/{nq}",
+           "adaptive_ms_per_batch": ad_s * 1e3, "naive_ms_per_batch": nv_s * 1e3,
+           "naive_queries_per_s": nq / nv_s, "adaptive_vs_naive": nv_s / ad_s,
+           "evals_fraction_of_naive": float(evals.mean() / (X.shape[0] * X.shape[1]))}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -423,6 +484,8 @@ def main():
     ap.add_argument("--paper-sweep", action="store_true", help="Section 5 C_alpha sweep instead of the batch line")
     ap.add_argument("--trials", type=int, default=20)
     ap.add_argument("--uneven", action="store_true", help="uneven workload instead of the batch line")
+    ap.add_argument("--float", action="store_true", help="float workload instead of the batch line")
+    ap.add_argument("--float-queries", type=int, default=1024)
     ap.add_argument("--metric", choices=("l2", "l1"), default="l2",
                     help="distance of the batch line (l1: the same workload on an l1 DB)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -441,6 +504,8 @@ def main():
         return paper_sweep(args)
     if args.uneven:
         return uneven_bench(args)
+    if args.float:
+        return float_bench(args)
     if args.profile_pass:
         return profile_pass()
     import torch
