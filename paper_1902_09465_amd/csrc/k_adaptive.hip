@@ -346,6 +346,107 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
   __syncthreads();  // smem (the staged query) may be reused by the caller
 }
 
+
+// The exact round of a lock-step fp32 batch as one tiled pass over (slots x
+// points): per block 64 slots x 128 points, 32-coordinate slices of the
+// query and point rows staged transposed in LDS, each thread 8 slots x 4
+// points.  Every pair that the per-slot exact pass would make exact (flag 0,
+// or every point in round 0) gets the same integer sum of the same
+// fixed-point samples fixed_of(fl32(x - q)^2, F) (or |x - q| for l1), so the
+// result is the same; the rows are read once per 64 slots instead of once
+// per slot.
+constexpr int XF_Q = 64, XF_P = 128, XF_K = 32;
+template <int MET>
+__global__ __launch_bounds__(NT) void k_exact_f32_tile(const Slot *__restrict__ slots, const float *__restrict__ X,
+                                                       Bufs B, Geometry G) {
+  __shared__ __align__(16) float qs[XF_K][XF_Q + 4];  // (rows of 68 and 132 floats: 16-byte aligned)
+  __shared__ __align__(16) float xs[XF_K][XF_P + 4];
+  __shared__ const float *qrow[XF_Q];
+  __shared__ int qF[XF_Q];
+  __shared__ uint8_t take[XF_Q], impl[XF_Q];
+  const int64_t n = G.n, m = G.m;
+  const int ns = G.nslots;
+  const int64_t nqt = (ns + XF_Q - 1) / XF_Q, nwork = nqt * ((n + XF_P - 1) / XF_P);
+  const int64_t w = xcd_work_item(nwork);
+  if (w >= nwork) return;
+  const int64_t p0 = (w / nqt) * XF_P;  // query tiles of one point tile back to back (rows from L2)
+  const int q0 = (int)(w % nqt) * XF_Q;
+  if (threadIdx.x < XF_Q) {
+    const int s = q0 + threadIdx.x;
+    const bool t = s < ns && slots[s].state == 1 && slots[s].cur >= slots[s].R;
+    take[threadIdx.x] = t ? 1 : 0;
+    impl[threadIdx.x] = (t && slots[s].implicit) ? 1 : 0;
+    qrow[threadIdx.x] = t ? reinterpret_cast<const float *>(slots[s].q) : nullptr;
+    qF[threadIdx.x] = t ? slots[s].F : 0;
+  }
+  __syncthreads();
+  const int qg = threadIdx.x % 8, pg = threadIdx.x / 8;  // slots 8 qg .. 8 qg + 7, points 4 pg .. 4 pg + 3
+  int64_t acc[8][4];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0;
+  int F[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) F[a] = qF[8 * qg + a];
+  for (int64_t k0 = 0; k0 < m; k0 += XF_K) {
+    // stage the slice transposed: [coordinate][slot] and [coordinate][point]
+    for (int e = threadIdx.x; e < XF_Q * XF_K; e += NT) {
+      const int ql = e / XF_K, kk = e % XF_K;
+      const float *qr = qrow[ql];
+      qs[kk][ql] = (qr && k0 + kk < m) ? qr[k0 + kk] : 0.0f;
+    }
+    for (int e = threadIdx.x; e < XF_P * XF_K; e += NT) {
+      const int pl = e / XF_K, kk = e % XF_K;
+      const int64_t i = p0 + pl;
+      xs[kk][pl] = (i < n && k0 + kk < m) ? X[i * m + k0 + kk] : 0.0f;
+    }
+    __syncthreads();
+    const int kend = (int)min((int64_t)XF_K, m - k0);
+    for (int kk = 0; kk < kend; ++kk) {
+      const float4 qa = *reinterpret_cast<const float4 *>(&qs[kk][8 * qg]);
+      const float4 qb = *reinterpret_cast<const float4 *>(&qs[kk][8 * qg + 4]);
+      const float4 xv = *reinterpret_cast<const float4 *>(&xs[kk][4 * pg]);
+      const float qv[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+      const float xx[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const float d = xx[b] - qv[a];
+          acc[a][b] += MET == KNN_METRIC_L1 ? fixed_of(fabsf(d), F[a]) : fixed_of(d * d, F[a]);
+        }
+    }
+    __syncthreads();
+  }
+  uint64_t my_pairs = 0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ql = 8 * qg + a;
+    if (!take[ql]) continue;
+    const int s = q0 + ql;
+    const SlotArrays sa = slot_arrays(B, n, s, slots[s].par);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t i = p0 + 4 * pg + b;
+      if (i >= n) continue;
+      if (!impl[ql] && sa.fl[i] != 0) continue;  // only undecided sampled pairs
+      sa.S[i] = acc[a][b];
+      if (impl[ql]) {
+        sa.fl[i] = FL_EXACT;
+        sa.ri[i] = 0;
+      } else {
+        sa.fl[i] = FL_EXACT;
+      }
+      ++my_pairs;
+    }
+  }
+  if (G.prof) {  // whole waves reach this point
+    wave_count_add(&prof_copy(G.prof)[0], my_pairs * (uint64_t)(m * 4 + 14));
+    wave_count_add(&prof_copy(G.prof)[2], my_pairs * (uint64_t)m);
+  }
+}
+
 template <int DT, int MET, bool QLDS>
 __global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const uint8_t *__restrict__ X,
                                                Bufs B, Geometry G) {
@@ -2561,6 +2662,17 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
       hipLaunchKernelGGL(k_sample_grp_u8<KNN_METRIC_L2>, grid, dim3(GBT), gbytes, st, slots, X, G.x8, G.xn, G.mp, B, G);
   } else if (G.dtype == KNN_U8) {
     launch_sample_met<KNN_U8>(slots, X, B, G, qlds, qbytes, st);
+  } else if (sample_kind == 1) {
+    // the exact round of a lock-step fp32 batch (every running slot is in
+    // it): one tiled pass over (slots x points)
+    const int64_t nwork = ((G.nslots + XF_Q - 1) / XF_Q) * ((G.n + XF_P - 1) / XF_P);
+    const float *Xf = reinterpret_cast<const float *>(X);
+    if (G.metric == KNN_METRIC_L1)
+      hipLaunchKernelGGL(k_exact_f32_tile<KNN_METRIC_L1>, dim3((unsigned)xcd_grid(nwork)), dim3(NT), 0, st, slots, Xf,
+                         B, G);
+    else
+      hipLaunchKernelGGL(k_exact_f32_tile<KNN_METRIC_L2>, dim3((unsigned)xcd_grid(nwork)), dim3(NT), 0, st, slots, Xf,
+                         B, G);
   } else {
     launch_sample_met<KNN_F32>(slots, X, B, G, qlds, qbytes, st);
   }
