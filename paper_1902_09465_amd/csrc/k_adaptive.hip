@@ -1638,8 +1638,8 @@ __global__ __launch_bounds__(kWave) void k_select_pm_mixed(const Slot *__restric
 }
 
 // Decide for such batches, per tile of DQ_SL slots x DQ_PT points: the
-// slot-major flags are staged in LDS, each thread keeps one slot's
-// thresholds in registers and decides its pairs from D read point-major,
+// slot-major flags are staged in LDS, each thread keeps four slots'
+// thresholds in registers and decides their pairs from D read point-major,
 // writes the next round's point-major "not sampled" bytes A, and the
 // changed flags (and the round index of pairs decided while sampled) go
 // back slot-major.  Per slot the tile's counts of undecided sampled,
