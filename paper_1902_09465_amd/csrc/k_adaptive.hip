@@ -457,7 +457,13 @@ __global__ __launch_bounds__(NT) void k_sample(Slot *__restrict__ slots, const u
   if (sl->state != 1) return;
   if (G.flagsets && sl->implicit != 0) return;  // a dense slot of a point-major batch
   extern __shared__ __align__(16) uint8_t smem[];
-  sample_slot_chunk<DT, MET, QLDS>(sl, s, (int64_t)blockIdx.y, X, B, G, smem);
+  // chunks blockIdx.y, blockIdx.y + gridDim.y, ... of the slot's list (a
+  // grid narrower than the list is sized for the lists expected)
+  const int64_t nlist = sl->implicit ? G.n : sl->n_act;
+  for (int64_t c = blockIdx.y; c * G.ch_sample < nlist; c += gridDim.y) {
+    sample_slot_chunk<DT, MET, QLDS>(sl, s, c, X, B, G, smem);
+    __syncthreads();  // the next chunk restages the block's LDS
+  }
 }
 
 // ---------------------------------------------------------------- grouped sample (u8)
@@ -1180,15 +1186,10 @@ constexpr int SEL_CH = NT * SEL_E;
 // Per chunk of P: the k smallest upper bounds and the k+1 smallest lower
 // bounds (values).  U, L1, L2 of the whole set are order statistics of the
 // union of these lists.
-__global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots, Bufs B, Geometry G) {
-  const int s = blockIdx.y;
-  const Slot *sl = &slots[s];
-  if (sl->state != 1) return;
-  if (G.flagsets && sl->implicit != 0) return;  // a dense slot of a point-major batch
+__device__ void select_partial_chunk(const Slot *sl, int s, int64_t chunk, int64_t nP, const Bufs &B,
+                                     const Geometry &G) {
   const int64_t n = G.n, m = G.m;
-  const int64_t nP = size_P(sl, n);
-  const int64_t base = (int64_t)blockIdx.x * SEL_CH;
-  if (base >= nP) return;
+  const int64_t base = chunk * SEL_CH;
   const SlotArrays a = slot_arrays(B, n, s, sl->par);
   __shared__ SelScratch ss;
   __shared__ int cnt;
@@ -1210,9 +1211,23 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
     }
   }
   const int k = sl->k;
-  uint64_t *out = B.part + (int64_t)s * B.part_stride + (int64_t)blockIdx.x * (2 * k + 1);
+  uint64_t *out = B.part + (int64_t)s * B.part_stride + chunk * (2 * k + 1);
   emit_smallest<SEL_E>(ku, k, out, ss, cnt, cand, wtau);
   emit_smallest<SEL_E>(kl, k + 1, out + k, ss, cnt, cand, wtau);
+}
+
+// One partial list per SEL_CH elements of P: chunks blockIdx.x,
+// blockIdx.x + gridDim.x, ... of the slot's P.
+__global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots, Bufs B, Geometry G) {
+  const int s = blockIdx.y;
+  const Slot *sl = &slots[s];
+  if (sl->state != 1) return;
+  if (G.flagsets && sl->implicit != 0) return;  // a dense slot of a point-major batch
+  const int64_t nP = size_P(sl, G.n);
+  for (int64_t c = blockIdx.x; c * SEL_CH < nP; c += gridDim.x) {
+    select_partial_chunk(sl, s, c, nP, B, G);
+    __syncthreads();  // the next chunk reuses the block's LDS
+  }
 }
 
 // Tiles of the selection over point-major sums (k_select_pm): FS_SL slots x
@@ -1928,15 +1943,9 @@ constexpr int DEC_CH = NT * DEC_E;
 // d <= L1); otherwise keep undecided.  Survivors are compacted into the
 // next lists with one atomic per list and block (ballots give each lane its
 // place); order within a list is irrelevant to the result.
-__global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B, Geometry G) {
-  const int s = blockIdx.y;
-  Slot *sl = &slots[s];
-  if (sl->state != 1) return;
-  if (G.flagsets && sl->implicit != 0) return;  // a dense slot of a point-major batch
+__device__ void decide_chunk(Slot *sl, int s, int64_t chunk, int64_t nA, const Bufs &B, const Geometry &G) {
   const int64_t n = G.n, m = G.m;
-  const int64_t nA = size_A(sl, n);
-  const int64_t base = (int64_t)blockIdx.x * DEC_CH;
-  if (base >= nA) return;
+  const int64_t base = chunk * DEC_CH;
   const SlotArrays a = slot_arrays(B, n, s, sl->par);
   const double U = sl->U, L1 = sl->L1, L2 = sl->L2;
   constexpr int NW = NT / kWave;
@@ -2002,6 +2011,19 @@ __global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B,
         dst[pos] = id[e];
       }
     }
+  }
+}
+
+// Chunks blockIdx.x, blockIdx.x + gridDim.x, ... of the slot's undecided list.
+__global__ __launch_bounds__(NT) void k_decide(Slot *__restrict__ slots, Bufs B, Geometry G) {
+  const int s = blockIdx.y;
+  Slot *sl = &slots[s];
+  if (sl->state != 1) return;
+  if (G.flagsets && sl->implicit != 0) return;  // a dense slot of a point-major batch
+  const int64_t nA = size_A(sl, G.n);
+  for (int64_t c = blockIdx.x; c * DEC_CH < nA; c += gridDim.x) {
+    decide_chunk(sl, s, c, nA, B, G);
+    __syncthreads();  // the next chunk reuses the block's LDS
   }
 }
 
@@ -2499,10 +2521,12 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
 // Host-side launchers (called from the runtime).
 namespace knn {
 
+// max_list: the longest list expected (the grid covers it in one pass; the
+// kernel's chunk loop covers longer ones)
 template <int DT, int MET>
 static void launch_sample_dt(Slot *slots, const uint8_t *X, const Bufs &B, const Geometry &G, bool qlds,
-                             size_t qbytes, hipStream_t st) {
-  dim3 grid((unsigned)G.nslots, (unsigned)((G.n + G.ch_sample - 1) / G.ch_sample));
+                             size_t qbytes, hipStream_t st, int64_t max_list) {
+  dim3 grid((unsigned)G.nslots, (unsigned)std::max<int64_t>(1, (max_list + G.ch_sample - 1) / G.ch_sample));
   if (qlds)
     hipLaunchKernelGGL((k_sample<DT, MET, true>), grid, dim3(NT), qbytes, st, slots, X, B, G);
   else
@@ -2511,11 +2535,12 @@ static void launch_sample_dt(Slot *slots, const uint8_t *X, const Bufs &B, const
 
 template <int DT>
 static void launch_sample_met(Slot *slots, const uint8_t *X, const Bufs &B, const Geometry &G, bool qlds,
-                              size_t qbytes, hipStream_t st) {
+                              size_t qbytes, hipStream_t st, int64_t max_list = -1) {
+  if (max_list < 0) max_list = G.n;
   if (G.metric == KNN_METRIC_L1)
-    launch_sample_dt<DT, KNN_METRIC_L1>(slots, X, B, G, qlds, qbytes, st);
+    launch_sample_dt<DT, KNN_METRIC_L1>(slots, X, B, G, qlds, qbytes, st, max_list);
   else
-    launch_sample_dt<DT, KNN_METRIC_L2>(slots, X, B, G, qlds, qbytes, st);
+    launch_sample_dt<DT, KNN_METRIC_L2>(slots, X, B, G, qlds, qbytes, st, max_list);
 }
 
 void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, double hi, int32_t metric,
@@ -2548,6 +2573,15 @@ static unsigned ql_blocks_x(int64_t n) {
   const char *e = std::getenv("KNN_QL_BLOCKS");
   const int64_t want = e ? std::max<int64_t>(1, std::atoll(e)) : 2048;
   return (unsigned)std::min<int64_t>((n + QL_NW - 1) / QL_NW, want);
+}
+
+// Points of a slot's list that the per-slot grids of a point-major batch
+// cover in one pass: a slot there turns sparse with at most n / sparse_div
+// undecided points (plus its accepted ones); longer lists take more passes
+// of the kernels' chunk loops.  KNN_SPARSE_LIST overrides it.
+static int64_t sparse_list_len(const Geometry &G) {
+  if (const char *e = std::getenv("KNN_SPARSE_LIST")) return std::max<int64_t>(1, std::atoll(e));
+  return G.sparse_div > 0 ? std::min<int64_t>(G.n, G.n / G.sparse_div + kWave) : 1;
 }
 
 void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
@@ -2584,8 +2618,9 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     }
     // slots that turned sparse: per-slot sampling over their lists (or their
     // exact sums in the exact round); the kernel skips the dense slots
+    const int64_t sparse_list = sparse_list_len(G);
     int tk = prof_begin(PROF_SPARSE, st);
-    launch_sample_met<KNN_U8>(slots, X, B, G, qlds, qbytes, st);
+    launch_sample_met<KNN_U8>(slots, X, B, G, qlds, qbytes, st, sparse_list);
     prof_end(tk, st, 0.0);
     tk = prof_begin(PROF_SELECT, st);
     const int64_t nsel = ((G.n + FS_PT - 1) / FS_PT) * ((nqp + FS_SL - 1) / FS_SL);
@@ -2593,8 +2628,8 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
                        (ql->cur == 0 && !ql->exact) ? 1 : 0);
     hipLaunchKernelGGL(k_select_pm_mixed, dim3(ns), dim3(kWave), 0, st, slots, qd_buf, nqp, B, G, ql->cur,
                        (ql->cur == 0 && !ql->exact) ? 1 : 0);
-    hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((G.n + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st, slots,
-                       B, G);
+    hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((sparse_list + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st,
+                       slots, B, G);
     hipLaunchKernelGGL(k_select_merge_pm, dim3((ns + NT / kWave - 1) / (NT / kWave)), dim3(NT), 0, st, slots, B, G);
     hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, 1);
     prof_end(tk, st, 0.0);
@@ -2602,7 +2637,8 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     const int64_t ndec = ((G.n + DQ_PT - 1) / DQ_PT) * ((nqp + DQ_SL - 1) / DQ_SL);
     hipLaunchKernelGGL(k_decide_pm, dim3((unsigned)xcd_grid(ndec)), dim3(NT), 0, st, slots, qd_buf, A, nqp, B, G,
                        ql->cur);
-    hipLaunchKernelGGL(k_decide, dim3((unsigned)((G.n + DEC_CH - 1) / DEC_CH), ns), dim3(NT), 0, st, slots, B, G);
+    hipLaunchKernelGGL(k_decide, dim3((unsigned)((sparse_list + DEC_CH - 1) / DEC_CH), ns), dim3(NT), 0, st, slots,
+                       B, G);
     prof_end(tk, st, 0.0);
     tk = prof_begin(PROF_FINISH, st);
     if (G.dtype == KNN_U8)

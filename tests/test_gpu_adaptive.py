@@ -63,8 +63,9 @@ def test_per_round_state_parity(P, orc, dtype, monkeypatch):
         monkeypatch.setenv("KNN_STAGE_ROWS", "16")
     if dtype.startswith("u8_qlane"):  # query-lane sampling even for a single slot
         monkeypatch.setenv("KNN_QL_MIN", "1")
-    if dtype.endswith("_sparse"):  # per-slot lists from round 1 on
+    if dtype.endswith("_sparse"):  # per-slot lists from round 1 on, one chunk-looping block per slot
         monkeypatch.setenv("KNN_SPARSE_DIV", "1")
+        monkeypatch.setenv("KNN_SPARSE_LIST", "1")
     if dtype.startswith("u8_ungrouped"):  # the per-query sampling kernel
         monkeypatch.setenv("KNN_GROUP", "0")
     if dtype.startswith("u8"):
@@ -169,6 +170,8 @@ KNOBS = ([{"KNN_LPP": v} for v in ("1", "2", "4", "8", "16", "32", "64")] +
          [{"KNN_QL_MIN": "1"}, {"KNN_QL_MIN": "1", "KNN_GROUP": "0"}] +
          # query-lane batches whose slots switch to per-slot lists after round 0, or never
          [{"KNN_QL_MIN": "1", "KNN_SPARSE_DIV": "1"}, {"KNN_QL_MIN": "1", "KNN_SPARSE_DIV": "0"}] +
+         # ... whose per-slot kernels then run one block per slot, looping over the list's chunks
+         [{"KNN_QL_MIN": "1", "KNN_SPARSE_DIV": "1", "KNN_SPARSE_LIST": "1"}] +
          # prefetch depth of the exact round's tiles
          [{"KNN_QL_MIN": "1", "KNN_EXACT_PF": v} for v in ("4", "6")] +
          [{"KNN_CH_SAMPLE": v} for v in ("64", "256", "4096")] + [{"KNN_GROUP": "0"}] +
