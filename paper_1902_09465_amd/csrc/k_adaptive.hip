@@ -2180,17 +2180,20 @@ __device__ void write_trivial(const QDesc &qd, int64_t n) {
 // by (distance, index), which contain a k-NN set also under ties.
 // Slots that keep no lists (implicit 2): builds act / xa / acc from the
 // flags (undecided sampled, undecided exact, accepted; discarded points
-// dropped), in index order, and switches the slot to list mode.  With the
-// sums kept point-major, the listed points' sums and round indices are
-// copied into the slot-major arrays that the list kernels read (with `all`,
-// the sums of the discarded points too, so the slot-major state is whole).
+// dropped) and switches the slot to list mode.  Each wave places its points
+// in index order within a range that one LDS atomic per class reserves, so
+// the lists are in no particular order overall (no consumer depends on it:
+// the decide step compacts its lists the same way), and a wave with no kept
+// point does no scan.  With the sums kept point-major, the listed points'
+// sums and round indices are copied into the slot-major arrays that the
+// list kernels read (with `all`, the sums of the discarded points too, so
+// the slot-major state is whole).
 __device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry &G, bool all = false) {
   const int64_t n = G.n;
   const SlotArrays a = slot_arrays(B, n, s, sl->par);
-  constexpr int NW = MT / kWave, V = 16;  // V consecutive points per thread and pass
-  __shared__ int wc[NW][3];
+  constexpr int V = 16;  // V consecutive points per thread and pass
   __shared__ int run[3];
-  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int lane = lane_id();
   const bool vec = (n % V) == 0;  // the slot's flag row is 16-byte aligned
   if (threadIdx.x < 3) run[threadIdx.x] = 0;
   __syncthreads();
@@ -2214,25 +2217,24 @@ __device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry 
       if (g & FL_DISC) continue;
       ++c3[(g & FL_ACC) ? 2 : (g & FL_EXACT) ? 1 : 0];
     }
-    // exclusive positions in point order: wave scan, then the waves before
-    int inc[3] = {c3[0], c3[1], c3[2]};
+    int pos[3] = {0, 0, 0};
+    if (__ballot(c3[0] + c3[1] + c3[2] > 0) != 0) {  // (wave-uniform)
+      // inclusive scan over the wave's lanes, then the wave's range
+      int inc[3] = {c3[0], c3[1], c3[2]};
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
+      for (int d = 1; d < kWave; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int t = __shfl_up(inc[k], d);
+          if (lane >= d) inc[k] += t;
+        }
+      }
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const int t = __shfl_up(inc[k], d);
-        if (lane >= d) inc[k] += t;
+        int base = 0;
+        if (lane == kWave - 1 && inc[k] > 0) base = atomicAdd(&run[k], inc[k]);
+        pos[k] = __shfl(base, kWave - 1) + inc[k] - c3[k];
       }
-    }
-    if (lane == kWave - 1)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) wc[wave][k] = inc[k];
-    __syncthreads();
-    int pos[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      pos[k] = run[k] + inc[k] - c3[k];
-      for (int w = 0; w < wave; ++w) pos[k] += wc[w][k];
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -2246,14 +2248,8 @@ __device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry 
       }
       if (G.flagsets && i < n && (c >= 0 || all)) a.S[i] = (int64_t)B.dpm[i * B.dpm_stride + s];
     }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-      int t = 0;
-      for (int w = 0; w < NW; ++w) t += wc[w][threadIdx.x];
-      run[threadIdx.x] += t;
-    }
-    __syncthreads();
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     sl->n_act = run[0];
     sl->n_xa = run[1];
