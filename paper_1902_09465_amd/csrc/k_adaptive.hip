@@ -1894,14 +1894,17 @@ __global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, B
   }
 }
 
-// The same for the dense slots of a point-major batch, one wave per slot
-// over the partial lists of k_select_pm (one per FS_PT points of [0, n));
-// also the decisions as thresholds on the sums, for k_decide_pm.
-__global__ __launch_bounds__(NT) void k_select_merge_pm(Slot *__restrict__ slots, Bufs B, Geometry G) {
-  __shared__ uint64_t cbuf[NT / kWave][kWave];
+// The same for the dense slots of a point-major batch over the partial
+// lists of k_select_pm (one per FS_PT points of [0, n)): one block of two
+// waves per slot, the first selecting U and the second L1 and L2 at the same
+// time; then the decisions as thresholds on the sums, for k_decide_pm.
+constexpr int SMP_T = 2 * kWave;
+__global__ __launch_bounds__(SMP_T) void k_select_merge_pm(Slot *__restrict__ slots, Bufs B, Geometry G) {
+  __shared__ uint64_t cbuf[2][kWave];
+  __shared__ uint64_t ul[3];  // U, L1, L2 as keys
   const int wave = threadIdx.x / kWave, lane = lane_id();
-  const int s = blockIdx.x * (NT / kWave) + wave;
-  if (s >= G.nslots) return;  // wave-uniform from here on
+  const int s = blockIdx.x;
+  if (s >= G.nslots) return;  // block-uniform from here on
   Slot *sl = &slots[s];
   if (sl->state != 1 || sl->implicit == 0) return;
   const int64_t nch = (G.n + FS_PT - 1) / FS_PT;
@@ -1910,25 +1913,36 @@ __global__ __launch_bounds__(NT) void k_select_merge_pm(Slot *__restrict__ slots
   const uint64_t *part = B.part + (int64_t)s * B.part_stride;
   // (32-bit index arithmetic: the lists hold fewer than 2^32 keys)
   const uint32_t ku = (uint32_t)k, kl = (uint32_t)k + 1u, wu = (uint32_t)w;
-  auto gu = [&](int64_t p) -> uint64_t {
-    const uint32_t q = (uint32_t)p / ku;
-    return part[q * wu + ((uint32_t)p - q * ku)];
-  };
-  auto gl = [&](int64_t p) -> uint64_t {
-    const uint32_t q = (uint32_t)p / kl;
-    return part[q * wu + ku + ((uint32_t)p - q * kl)];
-  };
-  const uint64_t U = wave_bcast_u64(wave_smallest_gen(nch * k, gu, k, cbuf[wave]), k - 1);
-  const uint64_t lcb = wave_smallest_gen(nch * (k + 1), gl, k + 1, cbuf[wave]);
-  const uint64_t L1 = wave_bcast_u64(lcb, k - 1), L2 = wave_bcast_u64(lcb, k);
+  if (wave == 0) {
+    auto gu = [&](int64_t p) -> uint64_t {
+      const uint32_t q = (uint32_t)p / ku;
+      return part[q * wu + ((uint32_t)p - q * ku)];
+    };
+    const uint64_t U = wave_bcast_u64(wave_smallest_gen(nch * k, gu, k, cbuf[0]), k - 1);
+    if (lane == 0) ul[0] = U;
+  } else {
+    auto gl = [&](int64_t p) -> uint64_t {
+      const uint32_t q = (uint32_t)p / kl;
+      return part[q * wu + ku + ((uint32_t)p - q * kl)];
+    };
+    const uint64_t lcb = wave_smallest_gen(nch * (k + 1), gl, k + 1, cbuf[1]);
+    const uint64_t L1 = wave_bcast_u64(lcb, k - 1), L2 = wave_bcast_u64(lcb, k);
+    if (lane == 0) {
+      ul[1] = L1;
+      ul[2] = L2;
+    }
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  const double U = dkey_inv(ul[0]), L1 = dkey_inv(ul[1]), L2 = dkey_inv(ul[2]);
   if (lane == 0) {
-    sl->U = dkey_inv(U);
-    sl->L1 = dkey_inv(L1);
-    sl->L2 = dkey_inv(L2);
+    sl->U = U;
+    sl->L1 = L1;
+    sl->L2 = L2;
   }
   if (lane < 4) {
     const RoundConsts rc = round_consts(sl, G.m, sl->cur);
-    sl->sthr[lane] = sum_threshold(sl, rc, lane, dkey_inv(U), dkey_inv(L1), dkey_inv(L2));
+    sl->sthr[lane] = sum_threshold(sl, rc, lane, U, L1, L2);
   }
   if (lane == 0) fs_mixed(B, s, G.n)[0] = 0;  // the next round's list of mixed tiles starts empty
 }
@@ -2626,7 +2640,7 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
                        (ql->cur == 0 && !ql->exact) ? 1 : 0);
     hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((sparse_list + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st,
                        slots, B, G);
-    hipLaunchKernelGGL(k_select_merge_pm, dim3((ns + NT / kWave - 1) / (NT / kWave)), dim3(NT), 0, st, slots, B, G);
+    hipLaunchKernelGGL(k_select_merge_pm, dim3(ns), dim3(SMP_T), 0, st, slots, B, G);
     hipLaunchKernelGGL(k_select_merge, dim3(ns), dim3(MT), 0, st, slots, B, G, 1);
     prof_end(tk, st, 0.0);
     tk = prof_begin(PROF_DECIDE, st);
