@@ -32,6 +32,12 @@ constexpr int NT = 256;
 
 // ---------------------------------------------------------------- helpers
 
+__device__ __forceinline__ int64_t shfl_i64(int64_t v, int src) {
+  const int lo = __shfl((int)(uint32_t)v, src);
+  const int hi = __shfl((int)(uint32_t)((uint64_t)v >> 32), src);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __device__ __forceinline__ int64_t shfl_xor_i64(int64_t v, int mask) {
   const int lo = __shfl_xor((int)(uint32_t)v, mask);
   const int hi = __shfl_xor((int)(uint32_t)((uint64_t)v >> 32), mask);
@@ -1843,11 +1849,17 @@ constexpr int MT = 1024;  // merge / finish block size
 // correctly rounded quotient of an exactly represented integer, hence
 // non-decreasing in S, and so are UCB and LCB: "not discarded" (LCB <= U)
 // and "accepted" (UCB <= L2, or d <= L1 for an exact pair) hold exactly for
-// the sums up to some threshold.  The threshold is found by bisection over
-// [-1, 2^32) with the same FP64 expressions as every other decision (kind
-// 0/1: keep/accept of a sampled pair, 2/3: of an exact pair); -1 means no
-// sum qualifies.
-__device__ int64_t sum_threshold(const Slot *sl, const RoundConsts &rc, int kind, double U, double L1, double L2) {
+// the sums up to some threshold.  The threshold is searched over [-1, 2^32)
+// with the same FP64 expressions as every other decision (kind 0/1:
+// keep/accept of a sampled pair, 2/3: of an exact pair); -1 means no sum
+// qualifies.  Sixteen lanes of a wave search one threshold together: each
+// step tests sixteen sums spread over the open interval and keeps the part
+// between the last one that holds and the first one that fails (the
+// decisions are monotone in the sum, so those that hold come first), about
+// eight steps instead of thirty-three halvings.  Lanes 16 j .. 16 j + 15
+// return threshold j (a whole wave calls it).
+__device__ int64_t sum_threshold_wave(const Slot *sl, const RoundConsts &rc, double U, double L1, double L2) {
+  const int lane = lane_id(), kind = lane >> 4, sub = lane & 15;
   const bool exact = kind >= 2, accept = (kind & 1) != 0;
   auto holds = [&](int64_t S) -> bool {
     double d, al;
@@ -1856,13 +1868,18 @@ __device__ int64_t sum_threshold(const Slot *sl, const RoundConsts &rc, int kind
     if (!accept) return !(lcb > U);
     return exact ? (ucb <= L1) : (ucb <= L2);
   };
-  int64_t lo = -1, hi = (int64_t)1 << 32;  // holds below lo + 1, fails from hi on
+  int64_t lo = -1, hi = (int64_t)1 << 32;  // holds at lo (or lo = -1), fails at hi (or hi = 2^32)
+  // (lo and hi are the same in the sixteen lanes of a group: the loop is
+  // group-uniform, and the ballot and shuffles read lanes of the own group)
   while (hi - lo > 1) {
-    const int64_t mid = lo + (hi - lo) / 2;
-    if (holds(mid))
-      lo = mid;
-    else
-      hi = mid;
+    const int64_t probe = lo + ((hi - lo) * (sub + 1)) / 17;  // in (lo, hi), ascending in sub
+    const bool h = holds(probe);
+    const uint32_t mask = (uint32_t)(__ballot(h) >> (16 * kind)) & 0xFFFFu;
+    const int c = __popc(mask);  // the probes that hold: sub < c
+    const int64_t plo = shfl_i64(probe, 16 * kind + (c > 0 ? c - 1 : 0));
+    const int64_t phi = shfl_i64(probe, 16 * kind + (c < 16 ? c : 15));
+    if (c > 0) lo = plo;
+    if (c < 16) hi = phi;
   }
   return lo;
 }
@@ -1940,10 +1957,9 @@ __global__ __launch_bounds__(SMP_T) void k_select_merge_pm(Slot *__restrict__ sl
     sl->L1 = L1;
     sl->L2 = L2;
   }
-  if (lane < 4) {
-    const RoundConsts rc = round_consts(sl, G.m, sl->cur);
-    sl->sthr[lane] = sum_threshold(sl, rc, lane, U, L1, L2);
-  }
+  const RoundConsts rc = round_consts(sl, G.m, sl->cur);
+  const int64_t thr = sum_threshold_wave(sl, rc, U, L1, L2);
+  if ((lane & 15) == 0) sl->sthr[lane >> 4] = thr;
   if (lane == 0) fs_mixed(B, s, G.n)[0] = 0;  // the next round's list of mixed tiles starts empty
 }
 
