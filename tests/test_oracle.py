@@ -94,6 +94,28 @@ def test_alpha_footnote_falls_back_to_lemma(orc):
     assert math.isnan(orc.alpha(0, 5, 10, 1.5))
 
 
+def _alpha_golden():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "alpha.txt")):
+        if line.strip() and not line.startswith("#"):
+            kind, n, delta, c_alpha, u, a = line.split()
+            rows.append((int(kind), int(n), float(delta), float(c_alpha), int(u), float(a)))
+    return rows
+
+
+def test_alpha_golden_values(orc):
+    """Hand-derived widths (Section 4 footnote, Lemma 3 second form, its use
+    as the footnote's fallback when delta/n >= 0.05, and the Section 5 C_alpha
+    form), with the arithmetic written out in tests/golden/alpha.txt.  A change
+    to any term of any form moves at least one of these values by far more
+    than 1e-9."""
+    rows = _alpha_golden()
+    assert {r[0] for r in rows} == {0, 1, 2} and len(rows) >= 11
+    for kind, n, delta, c_alpha, u, want in rows:
+        got = orc.alpha(kind, u, n, delta, c_alpha)
+        assert abs(got - want) <= 1e-9 * max(1.0, want), (kind, n, delta, c_alpha, u, got, want)
+
+
 @pytest.mark.parametrize("kind,delta,shrink,expect_ok", [
     (0, 0.04, 1.0, True), (1, 0.2, 1.0, True), (0, 0.04, 0.2, False)])
 def test_alpha_anytime_coverage(orc, kind, delta, shrink, expect_ok):
