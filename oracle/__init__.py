@@ -62,6 +62,14 @@ def lib():
         L.orc_index.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
         L.orc_perm_index.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
         L.orc_perm_index.restype = ctypes.c_int64
+        L.orc_draw_shared.argtypes = [ctypes.c_uint64, ctypes.c_int64]
+        L.orc_draw_shared.restype = ctypes.c_uint32
+        L.orc_shared_index.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
+        L.orc_shared_index.restype = ctypes.c_int64
+        L.orc_shared_perm_index.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
+        L.orc_shared_perm_index.restype = ctypes.c_int64
+        L.orc_coord.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+        L.orc_coord.restype = ctypes.c_int64
         L.orc_index.restype = ctypes.c_int64
         L.orc_alpha.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                 ctypes.c_double, ctypes.c_double]
@@ -116,6 +124,22 @@ def philox(ctr, key):
 
 def perm_index(seed: int, i: int, t: int, m: int) -> int:
     return int(lib().orc_perm_index(seed, i, t, m))
+
+
+def draw_shared(seed: int, t: int) -> int:
+    return int(lib().orc_draw_shared(seed, t))
+
+
+def shared_index(seed: int, t: int, m: int) -> int:
+    return int(lib().orc_shared_index(seed, t, m))
+
+
+def shared_perm_index(seed: int, t: int, m: int) -> int:
+    return int(lib().orc_shared_perm_index(seed, t, m))
+
+
+def coord(sampling: int, seed: int, i: int, t: int, m: int) -> int:
+    return int(lib().orc_coord(sampling, seed, i, t, m))
 
 
 def draw(seed: int, i: int, t: int) -> int:

@@ -117,8 +117,10 @@ static uint32_t lowbias32(uint32_t x) {
   return x;
 }
 
-int64_t orc_perm_index(uint64_t seed, int64_t i, int64_t t, int64_t m) {
-  uint32_t ctr[4] = {0u, 0u, (uint32_t)i, 1u};
+/* Position t < m of the permutation whose four Feistel round keys are the
+ * Philox outputs for counter (0, 0, c2, c3). */
+static int64_t perm_at(uint64_t seed, uint32_t c2, uint32_t c3, int64_t t, int64_t m) {
+  uint32_t ctr[4] = {0u, 0u, c2, c3};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t rk[4];
   orc_philox4x32_10(ctr, key, rk);
@@ -138,6 +140,52 @@ int64_t orc_perm_index(uint64_t seed, int64_t i, int64_t t, int64_t m) {
     x = ((uint64_t)L << h) | R;
   } while ((int64_t)x >= m);
   return (int64_t)x;
+}
+
+/* Per-point permutation: round keys from counter (0, 0, i, 1). */
+int64_t orc_perm_index(uint64_t seed, int64_t i, int64_t t, int64_t m) {
+  return perm_at(seed, (uint32_t)i, 1u, t, m);
+}
+
+/* ------------------------------------------------------------------ */
+/* One coordinate sequence for all points.  Section 4 writes the        */
+/* estimator of every point with the same indices j_1, j_2, ...; point i */
+/* uses the first T_i of them.  Lemma 3 needs, per point, i.i.d. samples */
+/* that are bounded and unbiased; it says nothing about how the samples  */
+/* of different points relate (its event is a union over points), so a   */
+/* sequence shared by all points keeps the guarantee.                    */
+/*   with replacement:    j_t = floor(r m / 2^32), r = output (t mod 4)  */
+/*                        of Philox4x32-10(seed, counter (t/4, 0, 0, 2));*/
+/*   without replacement: j_t = pi(t), pi the Feistel permutation above  */
+/*                        with round keys from counter (0, 0, 0, 3).     */
+/* ------------------------------------------------------------------ */
+uint32_t orc_draw_shared(uint64_t seed, int64_t t) {
+  uint32_t ctr[4] = {(uint32_t)(t / 4), 0u, 0u, 2u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  orc_philox4x32_10(ctr, key, out);
+  return out[t % 4];
+}
+
+int64_t orc_shared_index(uint64_t seed, int64_t t, int64_t m) {
+  uint64_t r = orc_draw_shared(seed, t);
+  return (int64_t)((r * (uint64_t)m) >> 32);
+}
+
+int64_t orc_shared_perm_index(uint64_t seed, int64_t t, int64_t m) {
+  return perm_at(seed, 0u, 3u, t, m);
+}
+
+/* Coordinate of sample t of point i under sampling mode 0 (per point, with
+ * replacement), 1 (per point, without), 2 (shared, with), 3 (shared,
+ * without). */
+int64_t orc_coord(int32_t sampling, uint64_t seed, int64_t i, int64_t t, int64_t m) {
+  switch (sampling) {
+    case 1: return orc_perm_index(seed, i, t, m);
+    case 2: return orc_shared_index(seed, t, m);
+    case 3: return orc_shared_perm_index(seed, t, m);
+    default: return orc_index(seed, i, t, m);
+  }
 }
 
 /* ------------------------------------------------------------------ */
@@ -193,7 +241,8 @@ typedef struct {
   int32_t metric; /* ORC_L2 or ORC_L1 */
   double W;
   double scale; /* 2^F */
-  int32_t norepl; /* sampling without replacement */
+  int32_t sampling; /* 0..3, see orc_coord */
+  int32_t norepl;   /* sampling without replacement (modes 1 and 3) */
 } inst_t;
 
 static int ceil_log2(double x) {
@@ -250,7 +299,7 @@ static int64_t exact_sum(const inst_t *I, int64_t i) {
 static int64_t sampled_sum(const inst_t *I, uint64_t seed, int64_t i, int64_t t0, int64_t t1) {
   int64_t s = 0;
   for (int64_t t = t0; t < t1; ++t)
-    s += sample_value(I, i, I->norepl ? orc_perm_index(seed, i, t, I->m) : orc_index(seed, i, t, I->m));
+    s += sample_value(I, i, orc_coord(I->sampling, seed, i, t, I->m));
   return s;
 }
 
@@ -336,8 +385,9 @@ int32_t orc_adaptive(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t
     return 0;
   }
   I.scale = ldexp(1.0, F);
-  if (p->sampling < 0 || p->sampling > 1) return -1;
-  I.norepl = p->sampling;
+  if (p->sampling < 0 || p->sampling > 3) return -1;
+  I.sampling = p->sampling;
+  I.norepl = p->sampling & 1;
 
   double alpha_r[MAX_ROUNDS];
   for (int32_t r = 0; r < R; ++r) {
@@ -595,8 +645,9 @@ int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t met
     return 0;
   }
   I.scale = ldexp(1.0, F);
-  if (p->sampling < 0 || p->sampling > 1) return -1;
-  I.norepl = p->sampling;
+  if (p->sampling < 0 || p->sampling > 3) return -1;
+  I.sampling = p->sampling;
+  I.norepl = p->sampling & 1;
   double thr_d = ceil(theta * (double)m);
   const int64_t thr = thr_d >= (double)m ? m : (thr_d < 1.0 ? 1 : (int64_t)thr_d);
   alg1_state_t A;
@@ -613,8 +664,7 @@ int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t met
   #define ALG1_SAMPLE(i) do {                                                   \
     int64_t i_ = (i);                                                           \
     A.T[i_] += 1;                                                               \
-    A.S[i_] += sample_value(&I, i_, I.norepl ? orc_perm_index(p->seed, i_, A.T[i_] - 1, m)  \
-                                             : orc_index(p->seed, i_, A.T[i_] - 1, m));      \
+    A.S[i_] += sample_value(&I, i_, orc_coord(I.sampling, p->seed, i_, A.T[i_] - 1, m));      \
     evals += 1;                                                                 \
     if (A.T[i_] >= thr) {                                                       \
       A.S[i_] = exact_sum(&I, i_);                                              \

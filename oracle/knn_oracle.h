@@ -37,7 +37,10 @@ typedef struct {
   float    growth;      /* T grows by max(4, ceil4(T*(g-1))) per round; 0 -> 2 */
   float    theta_exact; /* go exact once the next target reaches ceil(theta*m); 0 -> 1 */
   int32_t  c_exact;     /* candidate-exact count (0 = pure round form) */
-  int32_t  sampling;    /* 0 with replacement, 1 without (orc_perm_index) */
+  int32_t  sampling;    /* coordinates of point i: 0 drawn with replacement (orc_index),
+                            1 without (orc_perm_index); one sequence shared by all points:
+                            2 with replacement (orc_shared_index), 3 without
+                            (orc_shared_perm_index) */
 } orc_params;
 
 typedef struct {
@@ -72,6 +75,16 @@ double orc_alpha(int32_t kind, int64_t u, int64_t n, double delta, double c_alph
  * [0, m) (cycle walking, Black & Rogaway 2002).  lowbias32(x): x ^= x >> 16;
  * x *= 0x7feb352d; x ^= x >> 15; x *= 0x846ca68b; x ^= x >> 16. */
 int64_t orc_perm_index(uint64_t seed, int64_t i, int64_t t, int64_t m);
+
+/* One coordinate sequence for all points (Section 4 writes every point's
+ * estimator over the same j_1, j_2, ...): the 32-bit draw of sample t
+ * (Philox counter (t/4, 0, 0, 2)), its coordinate, the coordinate without
+ * replacement (round keys from counter (0, 0, 0, 3)), and the coordinate of
+ * sample t of point i under any sampling mode 0..3. */
+uint32_t orc_draw_shared(uint64_t seed, int64_t t);
+int64_t orc_shared_index(uint64_t seed, int64_t t, int64_t m);
+int64_t orc_shared_perm_index(uint64_t seed, int64_t t, int64_t m);
+int64_t orc_coord(int32_t sampling, uint64_t seed, int64_t i, int64_t t, int64_t m);
 
 /* Round schedule: fills T[0..R-1] with the cumulative sample targets of the
  * sampled rounds; round R is the exact round.  Returns R, or -1 if the

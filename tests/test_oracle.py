@@ -539,3 +539,131 @@ def test_without_replacement_contains(orc, seed):
     idx, st, T = orc.alg1(X, q, 5, orc.make_params(h=5, delta=0.05, seed=seed, sampling=1))
     assert contains_knn(idx, brute_dists(X, q), 5)
     assert st["coord_evals"] == int(T.sum())  # exact at T = m costs nothing more
+
+
+# ----------------------------------------------------------------------------
+# One coordinate sequence shared by all points (Section 4 writes every
+# point's estimator over the same indices j_1, j_2, ...; Lemma 3 needs
+# i.i.d. samples per point only)
+
+
+def test_shared_draw_matches_rocrand_engine(orc):
+    """The shared draw of sample t is output t mod 4 of Philox4x32-10 with
+    counter (t/4, 0, 0, 2): rocRAND's engine(seed, subsequence = 2^33,
+    offset = t).next(), compiled from rocRAND's header as an independent
+    implementation."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand"):
+        pytest.skip("rocRAND headers / hipcc not available")
+    g = rng(12)
+    pairs = [(0, 0), (1, 3), (2**64 - 1, 1000001)]
+    for _ in range(200):
+        pairs.append((int(g.integers(0, 2**63)), int(g.integers(0, 2**20))))
+    with tempfile.TemporaryDirectory() as td:
+        exe = os.path.join(td, "probe")
+        subprocess.check_call([hipcc, "-O1", "-I/opt/rocm/include",
+                               os.path.join(GOLDEN, "rocrand_philox_probe.cpp"), "-o", exe],
+                              stderr=subprocess.DEVNULL)
+        inp = "".join(f"{s} {2**33} {t}\n" for s, t in pairs)
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    ref = [int(x) for x in out.split()]
+    assert [orc.draw_shared(s, t) for s, t in pairs] == ref
+    # the coordinate is floor(r m / 2^32) of that draw, the same for every point
+    for (s, t), r in list(zip(pairs, ref))[:40]:
+        for m in (1, 97, 3072):
+            j = (r * m) >> 32
+            assert orc.shared_index(s, t, m) == j
+            assert orc.coord(2, s, 0, t, m) == j and orc.coord(2, s, 12345, t, m) == j
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 100, 3072, 4097])
+def test_shared_perm_is_bijection_common_to_points(orc, m):
+    for seed in (0, 77, 2**40 + 3):
+        vals = [orc.shared_perm_index(seed, t, m) for t in range(m)]
+        assert sorted(vals) == list(range(m)), (m, seed)
+        assert [orc.coord(3, seed, 9, t, m) for t in range(min(m, 50))] == vals[:50]
+
+
+def test_shared_round0_sums_over_common_coordinates(orc):
+    """After round 0 every point's running sum is the numpy sum of its squared
+    (or absolute) differences over the same B0 shared coordinates; two equal
+    points therefore keep equal sums in every round, which per-point draws do
+    not give."""
+    X, Q = uniform_u8(31, n=400, m=512)
+    X[17] = X[311]
+    for sampling, coords in ((2, [orc.shared_index(8, t, 512) for t in range(64)]),
+                             (3, [orc.shared_perm_index(8, t, 512) for t in range(64)])):
+        for metric in (0, 1):
+            p = orc.make_params(h=5, delta=0.01, seed=8, sampling=sampling)
+            _, _, (S, fl, ri) = orc.adaptive(X, Q[0], 5, p, stop_after=1, dump=True, metric=metric)
+            diff = X[:, coords].astype(np.int64) - Q[0, coords].astype(np.int64)[None, :]
+            want = (np.abs(diff) if metric else diff * diff).sum(axis=1)
+            assert np.array_equal(S, want), (sampling, metric)
+        for r in (2, 3, 4):
+            _, _, (S, fl, ri) = orc.adaptive(X, Q[0], 5, p, stop_after=r, dump=True)
+            assert S[17] == S[311] and ri[17] == ri[311]
+    _, _, (S0, _, _) = orc.adaptive(X, Q[0], 5, orc.make_params(h=5, seed=8), stop_after=1, dump=True)
+    assert S0[17] != S0[311]
+
+
+def test_shared_unbiased_estimator(orc):
+    """E d^ = d over seeds with the shared sequence (Section 4 estimator)."""
+    X, Q = uniform_u8(5, n=50, m=256)
+    d = brute_dists(X, Q[0]) / (256 * 65025.0)
+    est = []
+    for s in range(300):
+        _, _, (S, _, _) = orc.adaptive(X, Q[0], 3, orc.make_params(seed=s, sampling=2),
+                                       stop_after=1, dump=True)
+        est.append(S / (64 * 65025.0))
+    est = np.array(est)
+    z = (est.mean(axis=0) - d) / (est.std(axis=0, ddof=1) / math.sqrt(len(est)))
+    assert np.max(np.abs(z)) < 4.5, np.max(np.abs(z))
+
+
+@pytest.mark.parametrize("sampling", [2, 3])
+def test_shared_worked_example_unchanged(orc, sampling):
+    """The RNG-free antipodal example decides the same way whatever the
+    coordinates: discards at T = 256 in the pure form, 256,000 evaluations;
+    74,240 with candidate-exact."""
+    X, Q, where = antipodal()
+    idx, st = orc.adaptive(X, Q[0], 5, orc.make_params(h=5, delta=0.01, seed=3, sampling=sampling))
+    assert sorted(idx.tolist()) == where.tolist()
+    assert st == dict(coord_evals=256_000, rounds=3, count=5, exact_points=0)
+    idx, st = orc.adaptive(X, Q[0], 5, orc.make_params(h=5, delta=0.01, seed=3, sampling=sampling, c_exact=10))
+    assert sorted(idx.tolist()) == where.tolist()
+    # without replacement an exact distance costs only the m - T coordinates not yet seen
+    want = 64_000 + 10 * (1024 - (64 if sampling == 3 else 0))
+    assert st == dict(coord_evals=want, rounds=1, count=5, exact_points=10)
+
+
+@pytest.mark.parametrize("sampling", [2, 3])
+def test_shared_miss_rate_within_delta(orc, sampling):
+    """Theorem 1 with the shared sequence: misses <= delta over 1,000 seeds on
+    instances decided before the exact round."""
+    delta, N = 0.01, 1000
+    misses, evals = _miss_count(
+        orc, range(N), lambda s: orc.make_params(h=5, delta=delta, seed=20_000 + s, c_exact=10,
+                                                 sampling=sampling))
+    assert misses <= sps.binom.ppf(0.999, N, delta), misses
+    assert np.median(evals) < 600 * 1024
+
+
+def test_shared_miss_rate_negative_control(orc):
+    misses, _ = _miss_count(
+        orc, range(200), lambda s: orc.make_params(h=5, delta=0.01, seed=s, alpha_kind=2,
+                                                   c_alpha=1e-4, sampling=2))
+    assert misses >= 20, misses
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_shared_contains_knn(orc, seed):
+    from knn_inputs import gap_family
+    X, q = gap_family(900 + seed, n=500, m=256, k=5, near=5, mid=20)
+    d = brute_dists(X, q)
+    for sampling in (2, 3):
+        for ce in (0, 10):
+            idx, st = orc.adaptive(X, q, 5, orc.make_params(h=5, delta=0.05, seed=seed, sampling=sampling,
+                                                            c_exact=ce))
+            assert contains_knn(idx, d, 5), (sampling, ce)
+        idx, st, T = orc.alg1(X, q, 5, orc.make_params(h=5, delta=0.05, seed=seed, sampling=sampling))
+        assert contains_knn(idx, d, 5)
