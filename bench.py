@@ -31,23 +31,24 @@ METRIC = "k-NN queries/s adaptive vs naive MFMA (true k-NN contained), p50/p99 l
 N, M, NQ, K, H, DELTA = 100_000, 3072, 1024, 10, 10, 0.01
 HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0
-# Sampled rounds are bound by the vector ALU.  Its int8 dot-product peak:
-# 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s, each a
-# v_dot4 of four multiply-adds (8 ops): 314.6 TOP/s.  Algorithmic ops per
-# (query, sample) pair: the two multiply-adds x.q and q.q of
-# (x - q)^2 = x^2 - 2 x.q + q^2 (x^2 is shared by all queries of a point).
-# Per distinct coordinate draw (shared by every query with the same seed):
-# Philox4x32-10 share 20 32-bit ops (10 rounds x (2 mul_lo + 2 mul_hi + 4 xor)
-# / 4 draws), index 1, gather 1 = 22 lane-instructions, i.e. 22 x 8 op slots.
+# Sampled rounds are bound by the vector ALU.  Its peak in 8-op slots:
+# 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s, each at
+# most a v_dot4 of four multiply-adds (8 ops): 314.6 TOP/s.  Algorithmic work
+# of a sampled round: 3 integer ops (difference, square, add) per (query,
+# sample) pair, and one random index per distinct coordinate draw (shared by
+# every query with the same seed), counted as the lane-instructions it takes:
+# Philox4x32-10's share 20 (10 rounds x (2 mul_lo + 2 mul_hi + 4 xor) / 4
+# draws), the multiply-shift 1 and the gather 1 = 22.
 VALU_LANE_INSTR_PEAK = 39.3e12
 DOT4_PEAK_TOPS = 314.6
-OPS_PER_PAIR = 4
-OPS_PER_DRAW = 22 * 8
-# l1 distance: one v_sad_u8 (four absolute differences and four additions,
-# 8 op slots, the same 314.6 TOP/s peak) per query and four coordinates, so
-# 2 ops per (query, coordinate) pair -- in the sampled rounds, the exact
-# round and the naive scan alike.
-OPS_PER_PAIR_L1 = 2
+OPS_PER_PAIR = 3
+OPS_PER_DRAW = 22
+# l1 distance: 3 ops per (query, sample) pair in the sampled rounds as well
+# (difference, absolute value, add); the exact round and the naive scan run
+# one v_sad_u8 (four absolute differences and four additions, 8 op slots)
+# per query and four coordinates: 2 ops per (query, coordinate) pair.
+OPS_PER_PAIR_L1 = 3
+OPS_PER_ELEM_L1 = 2
 METRIC_L1 = "l1 distance: k-NN queries/s adaptive vs naive v_sad_u8 scan (true k-NN contained)"
 
 
@@ -586,7 +587,7 @@ def main():
     s_avg = samp["ms"] / max(1, samp["launches"]) / 1e3
     e_avg = exr["ms"] / max(1, exr["launches"]) / 1e3
     s_ops = (draws * OPS_PER_DRAW + pairs * (OPS_PER_PAIR_L1 if l1 else OPS_PER_PAIR)) / max(1, samp["launches"])
-    e_ops = 2.0 * exact_elems / max(1, exr["launches"])
+    e_ops = (OPS_PER_ELEM_L1 if l1 else 2.0) * exact_elems / max(1, exr["launches"])
     rl_sample = {"bound": "alu", "achieved": s_ops / s_avg / 1e12 if s_avg > 0 else 0.0,
                  "peak": DOT4_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
                  "kernel": "k_sample_ql_u8 (sampled rounds, query-lane)", "avg_launch_ms": s_avg * 1e3,
@@ -600,11 +601,12 @@ def main():
     r_per_step = samp["launches"] / max(1, args.steps)
     later = (r_per_step - 1) / max(1.0, r_per_step)  # fraction of the launches after round 0
     rl_sample["alg_bytes_per_launch"] = (N * NQ * 4 + N * NQ * (4 + 1) * later + draws / max(1, samp["launches"]))
-    if rl_sample["traffic"]:
-        rl_sample["achieved_hbm_gbs"] = rl_sample["traffic"] / s_avg / 1e9 if s_avg > 0 else 0.0
     rl_sample["frac"] = rl_sample["achieved"] / DOT4_PEAK_TOPS
     if not l1:
         rl_sample["traffic"] = stored_traffic()
+    if rl_sample["traffic"] and s_avg > 0:
+        rl_sample["achieved_hbm_gbs"] = rl_sample["traffic"] / s_avg / 1e9
+        rl_sample["hbm_frac"] = rl_sample["achieved_hbm_gbs"] / HBM_PEAK_GBS
     # exact round: one tiled pass over (queries x points), a GEMM on the
     # matrix cores for squared l2, v_sad_u8 sums on the vector ALU for l1
     e_peak = DOT4_PEAK_TOPS if l1 else INT8_PEAK_TOPS
@@ -615,6 +617,25 @@ def main():
                 "avg_launch_ms": e_avg * 1e3, "launches": exr["launches"], "ops_per_launch": e_ops}
     rl_exact["frac"] = rl_exact["achieved"] / e_peak
     roofline = rl_exact if dom == "sample_exact_round" else rl_sample
+
+    # ---------------- the same workload with a seed per query (what independent
+    # callers and the serving session send): the draws are not shared, so the
+    # batch runs on the per-query sampling kernels
+    seeds_q = [P.default_params(h=H, delta=DELTA, seed=12345 + q) for q in range(NQ)]
+    log("per-query seeds: warmup")
+    db.adaptive(Q_t, K, seeds_q, with_stats=False)
+    torch.cuda.synchronize()
+    pq_steps = max(1, min(args.steps, 2))
+    t0 = time.perf_counter()
+    for s in range(pq_steps):
+        idx_p, cnt_p, _ = db.adaptive(Q_t, K, seeds_q, with_stats=False)
+    torch.cuda.synchronize()
+    pq_ms = (time.perf_counter() - t0) * 1e3 / pq_steps
+    pq_ok = int(contained(idx_p, cnt_p, X_t, Q_t, nidx, ndist, K, args.metric).sum().item())
+    log(f"per-query seeds: {pq_ms:.1f} ms per batch, {pq_ok}/{NQ} contained")
+    per_query_seeds = {"ms_per_step": pq_ms, "queries_per_s": pq_ok / (pq_ms / 1e3), "steps": pq_steps,
+                       "contained": f"{pq_ok}/{NQ}",
+                       "note": "same queries, seed 12345 + q for query q: no draws shared between queries"}
 
     # ---------------- naive MFMA scan, same batch
     for w in range(args.warmup):
@@ -655,7 +676,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": ("batched_int_l1" if l1 else "batched_int") +
                                ": n=100000 points x m=3072 uint8, 32-centre Gaussian mixture "
-                               "sigma=30, 1024 queries, k=10 h=10 delta=0.01, footnote width, B0=64, g=2" +
+                               "sigma=30, 1024 queries sharing one seed, k=10 h=10 delta=0.01, footnote width, "
+                               "B0=64, g=2, coordinates drawn per point with replacement" +
                                (", l1 distance" if l1 else ""),
                    "global_batch": NQ, "seq_len": M, "parallelism": "single GPU"},
         "contained": f"{n_ok}/{NQ}",
@@ -667,6 +689,7 @@ def main():
         "naive": naive_info,
         "adaptive_vs_naive": (value / (NQ / naive_s)) if naive_s > 0 else None,
         "kernels_ms_per_step": {k_: v["ms"] / args.steps for k_, v in prof.items()},
+        "per_query_seeds": per_query_seeds,
         "graph_replay": {"ms_per_step": graph_ms, "same_result": same_graph,
                          "note": "timed region above runs eagerly with per-kernel HIP events; this is the "
                                  "cached engine replaying its captured launch graph, events off"},

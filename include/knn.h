@@ -154,14 +154,22 @@ int knn_adaptive(knn_db db, const void *dev_queries, int64_t nq, const int32_t *
                  const knn_params *p, int64_t np, int64_t *dev_out_idx, int64_t out_stride,
                  int32_t *dev_out_count, knn_stats *dev_out_stats, void *stream);
 
-/* Debug/parity hook: runs query 0 of the same call as knn_adaptive for
- * `stop_after` decide steps and copies the per-point state to host arrays
- * of length n: S (int64 running sums), fl (bit 0 exact, bit 1 accepted,
- * bit 2 discarded) and ri (round index of the point's last sampled target).
- * Synchronous. */
-int knn_adaptive_state(knn_db db, const void *dev_query, int32_t k, const knn_params *p,
-                       int32_t stop_after, int64_t *host_S, uint8_t *host_fl,
-                       uint8_t *host_ri, void *stream);
+/* Debug/parity hook: runs the same call as knn_adaptive (same arguments:
+ * nq queries, host_k[nq], p[np]) with every query in flight at once, stops
+ * each query after `stop_after` decide steps, and copies the per-point state
+ * of query `query` to host arrays of length n: S (int64 running sums), fl
+ * (bit 0 exact, bit 1 accepted, bit 2 discarded) and ri (round index of the
+ * point's last sampled target).  A query that finished in fewer decide steps
+ * leaves its final state.  The batch takes the launch path knn_adaptive
+ * would take for it (shared-seed batches: the query-lane kernels and their
+ * point-major sums), so the state of any slot of such a batch can be
+ * compared with a reference run of that query alone.  Synchronous.
+ * Errors: EINVAL (as knn_adaptive, stop_after < 1, query outside [0, nq),
+ * a trivial query), ENOMEM (the nq queries do not fit in device memory at
+ * once), EDEVICE. */
+int knn_adaptive_state(knn_db db, const void *dev_queries, int64_t nq, const int32_t *host_k,
+                       const knn_params *p, int64_t np, int64_t query, int32_t stop_after,
+                       int64_t *host_S, uint8_t *host_fl, uint8_t *host_ri, void *stream);
 
 /* Autotuner for the performance knobs of the adaptive path (none of them
  * changes a result): runs knn_adaptive on these queries (same k for all,

@@ -16,7 +16,7 @@ import numpy as np
 
 __all__ = [
     "rng", "tiny", "gmm_u8", "gmm_f32", "uniform_u8", "uneven", "antipodal",
-    "subspace", "pm_half", "coherent", "gap_family", "serving_dbs", "CONFIGS",
+    "subspace", "pm_half", "coherent", "gap_family", "planted_corners", "serving_dbs", "CONFIGS",
 ]
 
 
@@ -153,6 +153,36 @@ def pm_half(seed: int, n: int, m: int, dists=None):
         idx = g.choice(m, size=int(flips[i]), replace=False)
         X[i, idx] = 255 - X[i, idx]
     return X, q[None, :], flips
+
+
+def planted_corners(seed: int, n: int, m: int, nq: int, near, gaps, mid: int = 3,
+                    mid_gap: float = 0.12):
+    """Many queries over one database of corners of {0,255}^m, each query with
+    its own near points at its own distance.
+
+    Bulk points and queries are random corners, so every bulk point differs
+    from every query in about half of the coordinates.  Query j owns near[j]
+    points that differ from it in round((gaps[j] + 0.01 t) m) coordinates
+    (t = 0, 1, ...) and `mid` points at gaps[j] + mid_gap + 0.05 t, placed at
+    random indices.  Returns (X, Q)."""
+    g = rng(seed)
+    X = g.integers(0, 2, size=(n, m), dtype=np.uint8) * np.uint8(255)
+    Q = g.integers(0, 2, size=(nq, m), dtype=np.uint8) * np.uint8(255)
+    total = int(np.sum(near)) + mid * nq
+    if total > n:
+        raise ValueError("database too small for the planted points")
+    slots = g.permutation(n)[:total]
+    pos = 0
+    for j in range(nq):
+        fr = [gaps[j] + 0.01 * t for t in range(int(near[j]))]
+        fr += [gaps[j] + mid_gap + 0.05 * t for t in range(mid)]
+        for f in fr:
+            x = Q[j].copy()
+            idx = g.choice(m, size=int(np.rint(min(f, 1.0) * m)), replace=False)
+            x[idx] = 255 - x[idx]
+            X[slots[pos]] = x
+            pos += 1
+    return X, Q
 
 
 def coherent(seed: int, n: int, m: int):

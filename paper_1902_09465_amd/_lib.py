@@ -59,7 +59,8 @@ EXPORTS = [
     ("knn_db_metric", ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
     ("knn_schedule", ctypes.c_int, [ctypes.POINTER(Params), _I64, _I64, _P, _P, ctypes.POINTER(_I32)]),
     ("knn_adaptive", ctypes.c_int, [_P, _P, _I64, _P, ctypes.POINTER(Params), _I64, _P, _I64, _P, _P, _P]),
-    ("knn_adaptive_state", ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(Params), _I32, _P, _P, _P, _P]),
+    ("knn_adaptive_state", ctypes.c_int, [_P, _P, _I64, _P, ctypes.POINTER(Params), _I64, _I64, _I32, _P, _P, _P,
+                                          _P]),
     ("knn_naive", ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P]),
     ("knn_autotune", ctypes.c_int, [_P, _P, _I64, _I32, ctypes.POINTER(Params), _I32, _I32, ctypes.c_char_p,
                                     ctypes.c_size_t, _P]),

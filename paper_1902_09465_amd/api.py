@@ -126,16 +126,22 @@ class KnnDB:
             out[name] = float(ms)
         return out
 
-    def adaptive_state(self, q: torch.Tensor, k: int, params: Params, stop_after: int, stream=None):
-        """Per-point state (S, fl, ri) of query q after `stop_after` decide steps."""
-        q = self._queries(q)
+    def adaptive_state(self, Q: torch.Tensor, k, params: Params | Sequence[Params], stop_after: int,
+                       query: int = 0, stream=None):
+        """Per-point state (S, fl, ri) of query `query` of the batch Q (run as
+        knn_adaptive would run it) after `stop_after` decide steps."""
+        Q = self._queries(Q)
+        nq = Q.shape[0]
+        ks = np.full(nq, k, dtype=np.int32) if np.isscalar(k) else np.ascontiguousarray(k, dtype=np.int32)
+        plist = [params] if isinstance(params, Params) else list(params)
+        parr = (Params * len(plist))(*plist)
         S = np.zeros(self.n, dtype=np.int64)
         fl = np.zeros(self.n, dtype=np.uint8)
         ri = np.zeros(self.n, dtype=np.uint8)
-        check(lib().knn_adaptive_state(self.handle, ctypes.c_void_p(q.data_ptr()), k, ctypes.byref(params),
-                                       stop_after, S.ctypes.data_as(ctypes.c_void_p),
-                                       fl.ctypes.data_as(ctypes.c_void_p), ri.ctypes.data_as(ctypes.c_void_p),
-                                       _stream_handle(stream)))
+        check(lib().knn_adaptive_state(self.handle, ctypes.c_void_p(Q.data_ptr()), nq,
+                                       ks.ctypes.data_as(ctypes.c_void_p), parr, len(plist), query, stop_after,
+                                       S.ctypes.data_as(ctypes.c_void_p), fl.ctypes.data_as(ctypes.c_void_p),
+                                       ri.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream)))
         return S, fl, ri
 
     def naive(self, Q: torch.Tensor, k: int, stream=None, with_dist: bool = True):

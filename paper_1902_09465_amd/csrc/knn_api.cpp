@@ -453,9 +453,9 @@ static int run_graph(knn_db_s *db, const Prepared &P, int64_t nq, int64_t ns, bo
   return KNN_OK;
 }
 
-// Runs the slot engine over the prepared queries.  stop_after > 0 freezes
-// slot 0 after that many decide steps (debug state dump) and leaves the
-// engine allocated in *keep.
+// Runs the slot engine over the prepared queries.  stop_after > 0 (debug
+// state dump) runs every query in a slot of its own, freezes each after
+// that many decide steps and leaves the engine allocated in *keep.
 static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int32_t stop_after, Engine *keep) {
   const int64_t n = db->n, m = db->m;
   const Knobs K = knobs_for(db);
@@ -468,8 +468,8 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
   int64_t ns = (int64_t)(budget / per_slot);
   ns = std::min<int64_t>(ns, nq);
   ns = std::min<int64_t>(ns, env_int("KNN_MAX_SLOTS", 65535));
-  if (stop_after > 0) ns = 1;
   if (ns < 1) return fail(KNN_ENOMEM, "not enough device memory for one query slot");
+  if (stop_after > 0 && ns < nq) return fail(KNN_ENOMEM, "the queries of a state dump do not fit at once");
   // queries that share seed and schedule draw identical coordinates: let
   // the sampling kernel serve them in groups
   bool same = true;
@@ -807,28 +807,38 @@ int knn_autotune(knn_db db, const void *dev_queries, int64_t nq, int32_t k, cons
   return rc;
 }
 
-int knn_adaptive_state(knn_db db, const void *dev_query, int32_t k, const knn_params *p, int32_t stop_after,
-                       int64_t *host_S, uint8_t *host_fl, uint8_t *host_ri, void *stream) {
-  if (!db || !dev_query || !p || !host_S || !host_fl || !host_ri) return fail(KNN_EINVAL, "NULL argument");
+int knn_adaptive_state(knn_db db, const void *dev_queries, int64_t nq, const int32_t *host_k, const knn_params *p,
+                       int64_t np, int64_t query, int32_t stop_after, int64_t *host_S, uint8_t *host_fl,
+                       uint8_t *host_ri, void *stream) {
+  if (!db || !dev_queries || !host_k || !p || !host_S || !host_fl || !host_ri) return fail(KNN_EINVAL, "NULL argument");
+  if (nq < 1 || nq >= (int64_t)1 << 31) return fail(KNN_EINVAL, "bad nq");
+  if (np != 1 && np != nq) return fail(KNN_EINVAL, "np must be 1 or nq");
+  if (query < 0 || query >= nq) return fail(KNN_EINVAL, "query outside [0, nq)");
   if (stop_after < 1) return fail(KNN_EINVAL, "stop_after must be >= 1");
   hipStream_t st = (hipStream_t)stream;
-  const int64_t kh = k + (p->h < 0 ? k : p->h);
+  int64_t stride = 1;
+  for (int64_t q = 0; q < nq; ++q) {
+    const knn_params &pp = p[np == 1 ? 0 : q];
+    stride = std::max<int64_t>(stride, (int64_t)host_k[q] + (pp.h < 0 ? host_k[q] : pp.h));
+  }
+  stride = std::min<int64_t>(stride, std::max<int64_t>(db->n, 1));
   int64_t *d_idx = nullptr;
   int32_t *d_cnt = nullptr;
-  HIP_TRY(hipMalloc(&d_idx, sizeof(int64_t) * std::max<int64_t>(kh, 1)));
-  HIP_TRY(hipMalloc(&d_cnt, sizeof(int32_t)));
+  HIP_TRY(hipMalloc(&d_idx, sizeof(int64_t) * stride * nq));
+  HIP_TRY(hipMalloc(&d_cnt, sizeof(int32_t) * nq));
   Prepared P;
-  int rc = prepare(db, dev_query, 1, &k, p, 1, d_idx, std::max<int64_t>(kh, 1), d_cnt, nullptr, P);
-  if (rc == KNN_OK && P.qd[0].trivial) rc = fail(KNN_EINVAL, "trivial query (k + h >= n) has no state");
+  int rc = prepare(db, dev_queries, nq, host_k, p, np, d_idx, stride, d_cnt, nullptr, P);
+  if (rc == KNN_OK && P.qd[query].trivial) rc = fail(KNN_EINVAL, "trivial query (k + h >= n) has no state");
   Engine E;
   if (rc == KNN_OK) {
     std::lock_guard<std::mutex> lk(db->mu);
-    rc = run_engine(db, P, 1, st, stop_after, &E);
+    rc = run_engine(db, P, nq, st, stop_after, &E);
     if (rc == KNN_OK) {
-      const int64_t n = db->n;
-      hipError_t e = hipMemcpyAsync(host_S, E.B.S, n * 8, hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipMemcpyAsync(host_fl, E.B.fl, n, hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipMemcpyAsync(host_ri, E.B.ri, n, hipMemcpyDeviceToHost, st);
+      // the first admission hands query q to slot q
+      const int64_t n = db->n, off = query * n;
+      hipError_t e = hipMemcpyAsync(host_S, E.B.S + off, n * 8, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(host_fl, E.B.fl + off, n, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(host_ri, E.B.ri + off, n, hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
       const int rc2 = engine_destroy(E);
       if (e == hipSuccess) e = hipStreamSynchronize(st);

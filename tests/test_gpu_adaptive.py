@@ -8,7 +8,9 @@ import numpy as np
 import pytest
 import torch
 
-from knn_inputs import antipodal, coherent, gmm_f32, gmm_u8, pm_half, rng, tiny, uniform_u8
+from concurrent.futures import ThreadPoolExecutor
+
+from knn_inputs import antipodal, coherent, gmm_f32, gmm_u8, planted_corners, pm_half, rng, tiny, uniform_u8
 from tests.helpers import brute_dists, contains_knn
 
 pytestmark = pytest.mark.gpu
@@ -28,6 +30,14 @@ def dev(a):
 
 def oparams(orc, **kw):
     return orc.make_params(**kw)
+
+
+def oracle_many(orc, X, Q, ks, kw, queries):
+    """The oracle on several queries at once (one thread per query; the
+    oracle is plain C called through ctypes, which releases the GIL)."""
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(lambda q: orc.adaptive(X, Q[q], int(ks[q]), oparams(orc, **kw)), queries))
 
 
 def check_query(P, orc, db, X, q, k, **kw):
@@ -118,6 +128,58 @@ def test_point_major_mixed_widths(P, orc, monkeypatch, m):
     if m == 512:
         assert mixed_exact, "the exact round never saw a pair accepted earlier"
     check_query(P, orc, db, X, Q[0], 2, **kw)
+
+
+def _decisive_batch():
+    """80 queries over one database of corners (n = 6000, m = 1024), each with
+    its own near points at its own distance, k cycling over 1, 5, 10, 20."""
+    nq = 80
+    ks = np.array([(1, 5, 10, 20)[j % 4] for j in range(nq)], dtype=np.int32)
+    gaps = rng(5).uniform(0.02, 0.4, size=nq)
+    X, Q = planted_corners(91, 6000, 1024, nq, ks, gaps)
+    return X, Q, ks
+
+
+DECISIVE_KW = dict(h=-1, delta=0.01, seed=2024, alpha_kind=2, c_alpha=0.1, c_exact=0)
+
+
+@pytest.mark.parametrize("sparse_div", ["16", "0"])
+def test_point_major_batch_decides_in_sampled_rounds(P, orc, monkeypatch, sparse_div):
+    """The launch shape the benchmark times -- one seed shared by many queries,
+    k + 1 <= 64, no candidate-exact: query-lane sampling, point-major sums,
+    four-slot selection tiles and 64-slot decide tiles (80 queries: two decide
+    tiles) -- on data where sampled rounds discard and accept points and the
+    queries decide differently.  Every query's set and statistics equal the
+    oracle's; the per-round state of slots 0, 1, 64 and 79 equals the
+    oracle's after every decide step.  With the default switch (slots whose
+    undecided set falls to n/16 continue on per-slot lists) and with slots
+    kept dense to the end."""
+    monkeypatch.setenv("KNN_SPARSE_DIV", sparse_div)
+    X, Q, ks = _decisive_batch()
+    n = X.shape[0]
+    db = P.KnnDB(dev(X))
+    p = P.default_params(**DECISIVE_KW)
+    idx, cnt, st = db.adaptive(dev(Q), ks, p)
+    idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
+    refs = oracle_many(orc, X, Q, ks, DECISIVE_KW, range(len(ks)))
+    for q, (ref, rst) in enumerate(refs):
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert (int(st[q]["coord_evals"]), int(st[q]["rounds"]), int(st[q]["count"]),
+                int(st[q]["exact_points"])) == (rst["coord_evals"], rst["rounds"], rst["count"],
+                                                rst["exact_points"]), q
+    # decisions are taken before the exact round for most queries, after a
+    # different number of rounds
+    assert sum(r[1]["exact_points"] < n for r in refs) >= 60
+    assert len({r[1]["rounds"] for r in refs}) >= 3
+    Qd = dev(Q)
+    for slot in (0, 1, 64, 79):
+        for r in range(1, refs[slot][1]["rounds"] + 1):
+            S, fl, ri = db.adaptive_state(Qd, ks, p, r, query=slot)
+            _, _, (So, flo, rio) = orc.adaptive(X, Q[slot], int(ks[slot]), oparams(orc, **DECISIVE_KW),
+                                                stop_after=r, dump=True)
+            assert np.array_equal(fl, flo), f"slot {slot} round {r}: flags differ"
+            assert np.array_equal(S, So), f"slot {slot} round {r}: sums differ"
+            assert np.array_equal(ri, rio), f"slot {slot} round {r}: round index differs"
 
 
 @pytest.mark.parametrize("variant", ["pure", "cexact", "b0_4", "lemma", "calpha", "theta"])
@@ -453,8 +515,9 @@ def test_batched_int_config_sampled(P, orc):
         got = idx_c[qi, :cnt_c[qi]]
         dk = ndist[qi, 9]
         assert set(nidx[qi][ndist[qi] < dk].tolist()) <= set(got.tolist()), qi
-    for qi in (0, 517):
-        ref, rst = orc.adaptive(X, Q[qi], 10, oparams(orc, h=10, delta=0.01, seed=12345))
+    sample = list(range(0, 1024, 16))  # 64 queries spread over the batch's slots
+    refs = oracle_many(orc, X, Q, np.full(1024, 10), dict(h=10, delta=0.01, seed=12345), sample)
+    for qi, (ref, rst) in zip(sample, refs):
         assert idx_c[qi, :cnt_c[qi]].tolist() == ref.tolist(), qi
         assert (int(st[qi]["coord_evals"]), int(st[qi]["rounds"]), int(st[qi]["exact_points"])) == \
             (rst["coord_evals"], rst["rounds"], rst["exact_points"]), qi
