@@ -207,6 +207,23 @@ int knn_autotune(knn_db db, const void *dev_queries, int64_t nq, int32_t k, cons
 int knn_naive(knn_db db, const void *dev_queries, int64_t nq, int32_t k,
               int64_t *dev_out_idx, double *dev_out_dist, void *stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, serving loops and harnesses that forbid allocation: knn_naive on
+ * a u8 DB (same arguments, same results) that calls no allocator.  Its
+ * working memory (the shifted query rows, nq * (mp + 4) + 512 bytes with mp
+ * = m rounded up to 64, and 8 * k bytes per query and point range for the
+ * candidate lists) lives in a fixed array of KNN_NOALLOC_SCRATCH_MB MiB that
+ * the library holds on each device it runs on until the process ends; the
+ * point ranges are widened until the lists fit.  Every call on a device
+ * shares that device's array: calls that overlap on one GPU (on different
+ * streams, or from several threads) race -- serialise them.  Nothing in the
+ * array needs clearing between calls.  Stream-ordered.  Errors: as
+ * knn_naive, plus EINVAL for an f32 DB and for a batch whose query rows
+ * alone do not fit (the message gives the bytes needed). */
+#define KNN_NOALLOC_SCRATCH_MB 64
+int knn_naive_noalloc(knn_db db, const void *dev_queries, int64_t nq, int32_t k,
+                      int64_t *dev_out_idx, double *dev_out_dist, void *stream);
+
 /* ----------------------------------------------------------- session --- */
 
 /* Serving session: resident DBs, a background loop that admits submitted

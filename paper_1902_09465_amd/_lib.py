@@ -62,6 +62,7 @@ EXPORTS = [
     ("knn_adaptive_state", ctypes.c_int, [_P, _P, _I64, _P, ctypes.POINTER(Params), _I64, _I64, _I32, _P, _P, _P,
                                           _P]),
     ("knn_naive", ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P]),
+    ("knn_naive_noalloc", ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P]),
     ("knn_autotune", ctypes.c_int, [_P, _P, _I64, _I32, ctypes.POINTER(Params), _I32, _I32, ctypes.c_char_p,
                                     ctypes.c_size_t, _P]),
     ("knn_session_create", ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(_P)]),

@@ -157,6 +157,23 @@ class KnnDB:
         return idx, dist
 
 
+    def naive_noalloc(self, Q: torch.Tensor, k: int, idx: torch.Tensor, dist: torch.Tensor | None = None,
+                      stream=None):
+        """knn_naive_noalloc into caller-provided outputs (u8 DBs): idx [nq, k]
+        int64 and dist [nq, k] float64 (or None).  The library allocates nothing."""
+        Q = self._queries(Q)
+        nq = Q.shape[0]
+        if idx.shape != (nq, k) or idx.dtype != torch.int64 or not idx.is_contiguous():
+            raise ValueError("idx must be a contiguous int64 [nq, k] tensor")
+        if dist is not None and (dist.shape != (nq, k) or dist.dtype != torch.float64 or not dist.is_contiguous()):
+            raise ValueError("dist must be a contiguous float64 [nq, k] tensor")
+        check(lib().knn_naive_noalloc(self.handle, ctypes.c_void_p(Q.data_ptr()), nq, k,
+                                      ctypes.c_void_p(idx.data_ptr()),
+                                      ctypes.c_void_p(dist.data_ptr()) if dist is not None else None,
+                                      _stream_handle(stream)))
+        return idx, dist
+
+
 class Session:
     """Serving session (continuous batching with memory admission)."""
 

@@ -16,6 +16,8 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "block_select.h"
@@ -715,14 +717,35 @@ static void launch_naive_u8(const int8_t *Q8, const int32_t *qn, const int8_t *X
                        part, nranges);
 }
 
+// Working memory of one u8 scan: the shifted (or zero-padded) query rows,
+// their squared norms and the per-range candidate lists.
+struct NaiveU8Ws {
+  int64_t prange = 0, nranges = 0;
+  size_t bytes_q = 0, bytes_qn = 0, bytes_part = 0;
+  size_t total() const { return bytes_q + bytes_qn + bytes_part; }
+};
+
+static NaiveU8Ws naive_u8_ws(const knn_db_s *db, int64_t nq, int32_t k, int64_t prange) {
+  NaiveU8Ws w;
+  w.prange = prange;
+  w.nranges = (db->n + prange - 1) / prange;
+  w.bytes_q = (size_t)nq * db->mp + 256;
+  w.bytes_qn = sizeof(int32_t) * nq + 256;
+  w.bytes_part = sizeof(uint64_t) * nq * w.nranges * k;
+  return w;
+}
+
+// ws: the caller's working memory of ws_cap bytes, or nullptr (allocated
+// here, stream-ordered).  With fixed memory the point ranges grow until the
+// candidate lists fit (the k smallest keys do not depend on the ranges).
 static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
-                    hipStream_t st) {
+                    hipStream_t st, void *ws_fixed = nullptr, size_t ws_cap = 0) {
   const bool l1 = db->metric == KNN_METRIC_L1;
   // squared l2 distances below 2^32 (and exact int32 MFMA sums); l1 sums below 2^32
   if (!l1 && db->m > 65536) return fail(KNN_EINVAL, "naive u8 scan supports m <= 65536");
   if (l1 && db->m > 16777216) return fail(KNN_EINVAL, "naive u8 l1 scan supports m <= 2^24");
   if (k > 128) return fail(KNN_EINVAL, "naive u8 scan supports k <= 128");
-  const int64_t n = db->n, mp = db->mp;
+  const int64_t n = db->n;
   const int64_t qt = (nq + NBQ - 1) / NBQ;
   // about KNN_NAIVE_BLOCKS blocks in all (default 512: two per CU, one
   // wave of blocks); longer point ranges amortise each block's first tiles,
@@ -731,14 +754,24 @@ static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int6
   const int64_t nblk = std::max<int64_t>(1, nb_env ? std::atoll(nb_env) : 512);
   int64_t prange = (n * qt + nblk - 1) / nblk;
   prange = std::max<int64_t>(NBP, (prange + NBP - 1) / NBP * NBP);
-  const int64_t nranges = (n + prange - 1) / prange;
-  const size_t bytes_q = (size_t)nq * mp + 256, bytes_qn = sizeof(int32_t) * nq + 256,
-               bytes_part = sizeof(uint64_t) * nq * nranges * k;
-  void *ws = nullptr;
-  HIP_TRY(hipMallocAsync(&ws, bytes_q + bytes_qn + bytes_part, st));
+  NaiveU8Ws w = naive_u8_ws(db, nq, k, prange);
+  void *ws = ws_fixed;
+  if (ws_fixed) {
+    while (w.total() > ws_cap && w.nranges > 1) {
+      prange = (prange * 2 + NBP - 1) / NBP * NBP;
+      w = naive_u8_ws(db, nq, k, std::min<int64_t>(prange, (n + NBP - 1) / NBP * NBP));
+    }
+    if (w.total() > ws_cap)
+      return fail(KNN_EINVAL, "naive scan needs " + std::to_string(w.total()) + " bytes of working memory, more than "
+                                  "the fixed " + std::to_string(ws_cap));
+  } else {
+    HIP_TRY(hipMallocAsync(&ws, w.total(), st));
+  }
+  prange = w.prange;
+  const int64_t nranges = w.nranges, mp = db->mp;
   int8_t *Q8 = (int8_t *)ws;
-  int32_t *qn = (int32_t *)((uint8_t *)ws + bytes_q);
-  uint64_t *part = (uint64_t *)((uint8_t *)ws + bytes_q + bytes_qn);
+  int32_t *qn = (int32_t *)((uint8_t *)ws + w.bytes_q);
+  uint64_t *part = (uint64_t *)((uint8_t *)ws + w.bytes_q + w.bytes_qn);
   int tok = prof_begin(PROF_NAIVE_REST, st);
   if (l1)  // zero-padded u8 query rows
     hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)nq), dim3(256), 0, st, dq, nq, db->m, mp, 1, (uint8_t *)Q8);
@@ -758,8 +791,44 @@ static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int6
   hipLaunchKernelGGL(k_naive_merge, dim3((unsigned)nq), dim3(1024), 0, st, part, nranges, k, out_idx, out_dist);
   prof_end(tok, st, 0.0);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipFreeAsync(ws, st));
+  if (!ws_fixed) HIP_TRY(hipFreeAsync(ws, st));
   return KNN_OK;
+}
+
+// ------------------------------------------------- allocation-free scan
+
+// Fixed working memory of knn_naive_noalloc: one array per device for the
+// life of the process.  Host code never passes `scratch` itself to a kernel
+// (in host code the name is a host-side stand-in); it passes the device
+// address that hipGetSymbolAddress returns, looked up once per device.
+constexpr size_t kNoallocScratch = (size_t)KNN_NOALLOC_SCRATCH_MB << 20;
+static __device__ __align__(256) uint8_t scratch[kNoallocScratch];
+
+static int scratch_address(void **out) {
+  static std::mutex mu;
+  static std::map<int, void *> addr;  // device -> address of its copy of the array
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(KNN_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    it = addr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return KNN_OK;
+}
+
+int naive_run_noalloc(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
+                      hipStream_t st) {
+  if (db->dtype != KNN_U8) return fail(KNN_EINVAL, "knn_naive_noalloc supports u8 DBs only");
+  void *ws = nullptr;
+  const int rc = scratch_address(&ws);
+  if (rc != KNN_OK) return rc;
+  return naive_u8(db, (const uint8_t *)dq, nq, k, out_idx, out_dist, st, ws, kNoallocScratch);
 }
 
 int naive_run(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,

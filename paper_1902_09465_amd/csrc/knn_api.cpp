@@ -861,4 +861,14 @@ int knn_naive(knn_db db, const void *dev_queries, int64_t nq, int32_t k, int64_t
   return naive_run(db, dev_queries, nq, k, dev_out_idx, dev_out_dist, (hipStream_t)stream);
 }
 
+int knn_naive_noalloc(knn_db db, const void *dev_queries, int64_t nq, int32_t k, int64_t *dev_out_idx,
+                      double *dev_out_dist, void *stream) {
+  if (!db || !dev_out_idx) return fail(KNN_EINVAL, "NULL argument");
+  if (nq < 0 || nq >= (int64_t)1 << 31) return fail(KNN_EINVAL, "bad nq");
+  if (k < 1 || k > KNN_MAX_KH || k > db->n) return fail(KNN_EINVAL, "k must lie in [1, min(n, KNN_MAX_KH)]");
+  if (nq == 0) return KNN_OK;
+  if (!dev_queries) return fail(KNN_EINVAL, "NULL queries");
+  return naive_run_noalloc(db, dev_queries, nq, k, dev_out_idx, dev_out_dist, (hipStream_t)stream);
+}
+
 }  // extern "C"

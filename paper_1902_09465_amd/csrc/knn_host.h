@@ -119,6 +119,9 @@ int naive_prepare_db(knn_db_s *db, hipStream_t st);
 int naive_run(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
               hipStream_t st);
 void naive_free_db(knn_db_s *db);
+// knn_naive_noalloc: u8 scan in the fixed per-device working memory
+int naive_run_noalloc(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
+                      hipStream_t st);
 // rows of elem-byte values copied with zero padding from m to mp elements (the l1 scans' operands)
 void launch_pad_rows(const uint8_t *X, int64_t rows, int64_t m, int64_t mp, int elem, uint8_t *out, hipStream_t st);
 // k_naive_f32.hip
