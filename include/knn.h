@@ -69,14 +69,24 @@ typedef struct {
   float theta_exact;   /* a point goes exact once the next target reaches ceil(theta m) (0 -> 1) */
   int32_t c_exact;     /* >= 0; the c_exact undecided points with the smallest estimate are
                           made exact after every sampling step (0 = pure round form) */
-  int32_t sampling;    /* 0: coordinates drawn with replacement (Section 4);
+  int32_t sampling;    /* coordinates of the samples (Section 4):
+                          0: drawn with replacement, sample t of point i from output t mod 4
+                          of Philox4x32-10(key seed, counter (t/4, 0, i, 0)), coordinate
+                          floor(r m / 2^32);
                           1: without replacement (Section 4 footnote): sample t < m of point i
                           is pi(t) for a per-(seed, point) permutation pi of [0, m) -- a
                           four-round Feistel network on 2h bits (2^2h >= m, h >= 1) with
                           round keys Philox4x32-10(seed, counter (0, 0, i, 1)) and round
                           function F(k, v) = lowbias32(v xor k) mod 2^h, cycle-walked into
                           [0, m) (Black & Rogaway); d^ at T = m is then the exact distance,
-                          and an exact distance costs the m - T coordinates not yet seen */
+                          and an exact distance costs the m - T coordinates not yet seen;
+                          2, 3: as 0 and 1, but one coordinate sequence j_1, j_2, ... serves
+                          every point (counter words (0, 2) for the draws, (0, 3) for the
+                          round keys).  Each point's samples are still i.i.d. (2) or a
+                          uniform permutation (3), which is all Lemma 3 uses, so the
+                          guarantee of Theorem 1 is unchanged.  Queries that share seed and
+                          schedule then share every sampled coordinate, and their sampled
+                          rounds run as int8 matrix products over the gathered coordinates */
 } knn_params;
 
 /* Per-query statistics (24 bytes). */

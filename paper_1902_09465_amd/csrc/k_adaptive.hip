@@ -325,16 +325,18 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
     while (lpp < kWave && (uint32_t)(2 * lpp) <= nb) lpp <<= 1;
   }
   const int sub = threadIdx.x % lpp;
-  const bool norepl = sl->norepl != 0;
+  const bool norepl = sl->norepl != 0, shared = sl->shared != 0;
   const int ph = perm_half_bits(mm);
+  const uint32_t c3 = draw_c3(shared, false);
   for (int64_t p = base + threadIdx.x / lpp; p < end; p += BT / lpp) {
     const int32_t i = implicit ? (int32_t)p : a.act[p];
     const uint8_t *row = X + (int64_t)i * m * elem;
-    const PermKey pk = norepl ? perm_key((uint32_t)i, k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
+    const uint32_t c2 = draw_c2((uint32_t)i, shared);
+    const PermKey pk = norepl ? perm_key(c2, draw_c3(shared, true), k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
     int64_t acc = 0;
     for (uint32_t b = blk0 + sub; b < blk1; b += lpp) {
       uint32_t js[4];
-      draw_block(b, (uint32_t)i, k0, k1, mm, norepl, ph, pk, js);
+      draw_block(b, c2, c3, k0, k1, mm, norepl, ph, pk, js);
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc += sample_val<DT, MET>(row, q, js[e], F);
     }
@@ -550,15 +552,16 @@ __device__ __forceinline__ void reduce_store(uint32_t (&v)[GRP], int lane, uint3
 template <int MET>
 __device__ __forceinline__ void point_sums(const uint8_t *row, const uint8_t *qT, uint32_t i, uint32_t b_first,
                                            uint32_t step, uint32_t blk1, uint32_t k0, uint32_t k1, uint32_t mm,
-                                           bool norepl, uint32_t (&acc)[GRP]) {
+                                           bool norepl, bool shared, uint32_t (&acc)[GRP]) {
   uint32_t qq[GRP], xq[GRP], xx = 0;
 #pragma unroll
   for (int g = 0; g < GRP; ++g) qq[g] = xq[g] = 0;
   const int ph = perm_half_bits(mm);
-  const PermKey pk = norepl ? perm_key(i, k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
+  const uint32_t c2 = draw_c2(i, shared), c3 = draw_c3(shared, false);
+  const PermKey pk = norepl ? perm_key(c2, draw_c3(shared, true), k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
   auto fetch = [&](uint32_t blk, uint32_t (&xv)[4], uint4 (&qv)[4]) {
     uint32_t js[4];
-    draw_block(blk, i, k0, k1, mm, norepl, ph, pk, js);
+    draw_block(blk, c2, c3, k0, k1, mm, norepl, ph, pk, js);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       xv[e] = row[js[e]];
@@ -646,7 +649,7 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                       const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
                                                       int64_t mp, Bufs B, Geometry G) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ int s_mode, s_cur, s_impl, s_norepl;
+  __shared__ int s_mode, s_cur, s_impl, s_norepl, s_shared;
   __shared__ uint32_t s_run;
   __shared__ uint64_t s_seed;
   __shared__ uint32_t s_t0, s_t1;
@@ -655,7 +658,7 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int64_t n = G.n, m = G.m;
   if (threadIdx.x == 0) {
     uint32_t run = 0;
-    int mode = 1, cur = 0, impl = 0, norepl = 0;
+    int mode = 1, cur = 0, impl = 0, norepl = 0, shared = 0;
     uint64_t seed = 0;
     uint32_t t0 = 0, t1 = 0;
     for (int g = 0; g < GRP; ++g) {
@@ -671,17 +674,20 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
         seed = sl->seed;
         impl = sl->implicit == 1;
         norepl = sl->norepl;
+        shared = sl->shared;
         t0 = a0;
         t1 = a1;
         mode = exact ? 2 : 1;
       } else if (c != cur || (exact ? 2 : 1) != mode || (sl->implicit == 1) != (impl != 0) ||
-                 (!exact && (sl->seed != seed || sl->norepl != norepl || a0 != t0 || a1 != t1))) {
+                 (!exact && (sl->seed != seed || sl->norepl != norepl || sl->shared != shared || a0 != t0 ||
+                             a1 != t1))) {
         mode = 0;
       }
       run |= 1u << g;
     }
     s_run = run;
     s_norepl = norepl;
+    s_shared = shared;
     s_mode = run ? mode : -1;
     s_cur = cur;
     s_impl = impl;
@@ -745,7 +751,7 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
           if (act) {  // uniform within the lanes of this point
             uint32_t acc[GRP];
             point_sums<MET>(xt + (size_t)pt * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, s_norepl,
-                       acc);
+                       s_shared, acc);
             reduce_store_lpp(lpp, acc, lane, act, g0, n, i, cur, B);
             if (sub == 0) {
               my_pts += 1;
@@ -769,7 +775,7 @@ __global__ __launch_bounds__(GBT) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (act == 0) continue;  // uniform within the lanes of this point
         uint32_t acc[GRP];
         point_sums<MET>(X + (int64_t)i * m, smem, (uint32_t)i, blk0 + sub, (uint32_t)lpp, blk1, k0, k1, mm, s_norepl,
-                   acc);
+                   s_shared, acc);
         reduce_store_lpp(lpp, acc, lane, act, g0, n, i, cur, B);
         if (sub == 0) {
           my_pts += 1;
@@ -948,6 +954,102 @@ __global__ __launch_bounds__(NT) void k_build_qt(const Slot *__restrict__ slots,
   }
 }
 
+// ------------------------------------------- one sequence for all points
+
+// Boundary b of the gathered copies: T'_0 = 0, T'_b = T[b - 1] for b <= R,
+// T'_{R+1} = m (sampling without replacement: the exact round's remaining
+// coordinates).
+__device__ __forceinline__ int64_t seq_boundary(const Sched *sc, int b, int64_t m) {
+  return b == 0 ? 0 : (b <= sc->R ? (int64_t)sc->T[b - 1] : m);
+}
+
+// Coordinate of sample t of the sequence every point shares (counter words
+// (0, 2), or the permutation keyed by (0, 3)), for t < tlen; ~0u for t in
+// [tlen, kp).
+__global__ __launch_bounds__(NT) void k_seq_coords(uint64_t seed, int32_t norepl, int64_t m, int32_t tlen,
+                                                   int64_t kp, uint32_t *__restrict__ js) {
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), mm = (uint32_t)m;
+  const int ph = perm_half_bits(mm);
+  const PermKey pk = norepl ? perm_key(0u, draw_c3(true, true), k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
+  for (int64_t b = (int64_t)blockIdx.x * NT + threadIdx.x; 4 * b < kp; b += (int64_t)gridDim.x * NT) {
+    uint32_t j4[4] = {~0u, ~0u, ~0u, ~0u};
+    if (4 * b < tlen) draw_block((uint32_t)b, 0u, draw_c3(true, false), k0, k1, mm, norepl != 0, ph, pk, j4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) js[4 * b + e] = 4 * b + e < tlen ? j4[e] : ~0u;
+  }
+}
+
+// Rows at the sequence's coordinates, out[r][t] = row_r[js[t]] (as x - 128
+// for squared l2, raw bytes for l1; zero where js[t] is none): the points
+// (rows = n), or the running slots' queries (QUERIES, rows = nqp; idle
+// slots give zero rows).  One wave per row, sixteen bytes per lane and step.
+template <int MET, bool QUERIES>
+__global__ __launch_bounds__(NT) void k_seq_gather(const uint8_t *__restrict__ X, const Slot *__restrict__ slots,
+                                                   int32_t ns, int64_t rows, int64_t m,
+                                                   const uint32_t *__restrict__ js, int64_t kp,
+                                                   int8_t *__restrict__ out) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * (NT / kWave);
+  for (int64_t r = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
+    const uint8_t *row = nullptr;
+    if constexpr (QUERIES) {
+      if (r < ns && slots[r].state == 1) row = reinterpret_cast<const uint8_t *>(slots[r].q);
+    } else {
+      row = X + r * m;
+    }
+    for (int64_t t0 = 16 * (int64_t)lane; t0 < kp; t0 += 16 * kWave) {
+      const uint4 *jp = reinterpret_cast<const uint4 *>(js + t0);
+      uint32_t w[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const uint4 j = jp[d];
+        const uint32_t jj[4] = {j.x, j.y, j.z, j.w};
+        uint32_t word = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          uint32_t v = 0;
+          if (row && jj[e] != ~0u) v = MET == KNN_METRIC_L2 ? (uint32_t)(row[jj[e]] ^ 0x80u) : (uint32_t)row[jj[e]];
+          word |= v << (8 * e);
+        }
+        w[d] = word;
+      }
+      *reinterpret_cast<uint4 *>(out + r * kp + t0) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+}
+
+// Squared norms of gathered rows (x - 128 bytes) over the samples before
+// each boundary: out[b * ostride + r] = sum_{t < T'_b} S[r][t]^2 for b < nb.
+// One wave per row.
+__global__ __launch_bounds__(NT) void k_seq_norms(const int8_t *__restrict__ S, int64_t rows, int64_t kp,
+                                                  const Sched *__restrict__ sc, int32_t nb, int64_t m,
+                                                  int32_t *__restrict__ out, int64_t ostride) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * (NT / kWave);
+  for (int64_t r = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
+    const uint32_t *row = reinterpret_cast<const uint32_t *>(S + r * kp);
+    int32_t run = 0;
+    if (lane == 0) out[r] = 0;
+    for (int b = 1; b < nb; ++b) {
+      // words of samples [T'_{b-1}, T'_b): T'_{b-1} is a multiple of 4, and
+      // bytes past the last sample are zero
+      const int64_t w0 = seq_boundary(sc, b - 1, m) / 4, w1 = (seq_boundary(sc, b, m) + 3) / 4;
+      int32_t part = 0;
+      for (int64_t w = w0 + lane; w < w1; w += kWave) {
+        const uint32_t v = row[w];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int32_t x = (int32_t)(int8_t)(v >> (8 * e));
+          part += x * x;
+        }
+      }
+      for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o);
+      run += part;
+      if (lane == 0) out[(int64_t)b * ostride + r] = run;
+    }
+  }
+}
+
 template <int MET>
 __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__ slots, const uint8_t *__restrict__ X,
                                                         const uint8_t *__restrict__ QT, int32_t nqp,
@@ -968,8 +1070,9 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
   const uint32_t blk0 = R.t0 >> 2, blk1 = R.t1 >> 2;
   const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
   const uint32_t mm = (uint32_t)m;
-  const bool norepl = R.norepl != 0;
+  const bool norepl = R.norepl != 0, shared = R.shared != 0;
   const int ph = perm_half_bits(mm);
+  const uint32_t c3 = draw_c3(shared, false);
   // QT through a buffer descriptor: the row offset j * nqp is a wave-uniform
   // scalar and the lane's column a fixed vector offset, so a load costs no
   // address arithmetic (and reads past the matrix return zeros)
@@ -1012,7 +1115,8 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
       continue;
     }
     const uint8_t *row = X + i * m;
-    const PermKey pk = norepl ? perm_key((uint32_t)i, k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
+    const uint32_t c2 = draw_c2((uint32_t)i, shared);
+    const PermKey pk = norepl ? perm_key(c2, draw_c3(shared, true), k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
     uint32_t qq[GRP], xq[GRP], xx = 0;
 #pragma unroll
     for (int g = 0; g < GRP; ++g) qq[g] = xq[g] = 0;
@@ -1020,7 +1124,7 @@ __global__ __launch_bounds__(QL_BT) void k_sample_ql_u8(const Slot *__restrict__
       // lane l draws block bb + l
       uint32_t jv[4] = {0u, 0u, 0u, 0u}, xv = 0;
       if (bb + lane < blk1) {
-        draw_block(bb + lane, (uint32_t)i, k0, k1, mm, norepl, ph, pk, jv);
+        draw_block(bb + lane, c2, c3, k0, k1, mm, norepl, ph, pk, jv);
         xv = (uint32_t)row[jv[0]] | ((uint32_t)row[jv[1]] << 8) | ((uint32_t)row[jv[2]] << 16) |
              ((uint32_t)row[jv[3]] << 24);
       }
@@ -2440,6 +2544,7 @@ __device__ void admit(Slot *sl, const QDesc *qd, const Sched *sched, Ctl *ctl, i
     sl->c_exact = d.c_exact;
     sl->F = d.F;
     sl->norepl = d.norepl;
+    sl->shared = d.shared;
     sl->seed = d.seed;
     sl->W = d.W;
     sl->q = d.q;
@@ -2579,6 +2684,11 @@ void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, 
                         const Bufs &B, const Geometry &G, int32_t cur, int32_t impl, uint32_t *Dpm, int32_t nqp,
                         hipStream_t st);
 
+// rounds of a batch that shares one coordinate sequence (k_naive.hip: the same tiles)
+void launch_round_seq_u8(const Slot *slots, const SeqBufs &q, int32_t lo, int32_t hi, int64_t t0, int64_t t1,
+                         const uint8_t *A, uint32_t *D, int32_t nqp, const Bufs &B, const Geometry &G, int32_t cur,
+                         int32_t impl, int32_t exact, hipStream_t st);
+
 int stage_rows_for(int64_t m, int64_t mp, int want) {
   // LDS: the transposed query tile (GRP x mp) plus the row tile (rows x m)
   constexpr int64_t kLds = 160 * 1024 - 4096;  // static shared memory of the kernel stays below 4 KB
@@ -2591,6 +2701,27 @@ void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint
   const int64_t total = m * (int64_t)nqp;
   const unsigned blocks = (unsigned)std::min<int64_t>((total + NT - 1) / NT, 4096);
   hipLaunchKernelGGL(k_build_qt, dim3(blocks), dim3(NT), 0, st, slots, ns, m, nqp, qt);
+}
+
+void launch_seq_prepare(const Slot *slots, const Sched *sc, int32_t ns, int32_t nqp, const uint8_t *X, int64_t n,
+                        int64_t m, uint64_t seed, int32_t norepl, int32_t metric, const SeqBufs &q, hipStream_t st) {
+  const unsigned cb = (unsigned)std::min<int64_t>((q.kp / 4 + NT - 1) / NT, 1024);
+  hipLaunchKernelGGL(k_seq_coords, dim3(cb), dim3(NT), 0, st, seed, norepl, m, q.tlen, q.kp, q.js);
+  const unsigned gx = (unsigned)std::min<int64_t>((n + 3) / 4, 8192), gq = (unsigned)((nqp + 3) / 4);
+  if (metric == KNN_METRIC_L1) {
+    hipLaunchKernelGGL((k_seq_gather<KNN_METRIC_L1, false>), dim3(gx), dim3(NT), 0, st, X, slots, ns, n, m, q.js,
+                       q.kp, q.xs);
+    hipLaunchKernelGGL((k_seq_gather<KNN_METRIC_L1, true>), dim3(gq), dim3(NT), 0, st, X, slots, ns, (int64_t)nqp, m,
+                       q.js, q.kp, q.qs);
+  } else {
+    hipLaunchKernelGGL((k_seq_gather<KNN_METRIC_L2, false>), dim3(gx), dim3(NT), 0, st, X, slots, ns, n, m, q.js,
+                       q.kp, q.xs);
+    hipLaunchKernelGGL((k_seq_gather<KNN_METRIC_L2, true>), dim3(gq), dim3(NT), 0, st, X, slots, ns, (int64_t)nqp, m,
+                       q.js, q.kp, q.qs);
+    hipLaunchKernelGGL(k_seq_norms, dim3(gx), dim3(NT), 0, st, q.xs, n, q.kp, sc, q.nb, m, q.xn, n);
+    hipLaunchKernelGGL(k_seq_norms, dim3(gq), dim3(NT), 0, st, q.qs, (int64_t)nqp, q.kp, sc, q.nb, m, q.qn,
+                       (int64_t)nqp);
+  }
 }
 
 // Point blocks of a query-lane sampling launch (each walks a contiguous
@@ -2613,7 +2744,7 @@ static int64_t sparse_list_len(const Geometry &G) {
 void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
                  const Bufs &B, const Geometry &G0, bool any_cexact, hipStream_t st, int sample_kind,
                  int stage_rows, const QlRound *ql, const uint8_t *qt, int32_t nqp, uint32_t *qd_buf,
-                 const int8_t *q8, const int32_t *q8n) {
+                 const int8_t *q8, const int32_t *q8n, const SeqBufs *seq) {
   Geometry G = G0;
   G.prof = prof_device_counters();
   G.stage = (G.dtype == KNN_U8 && G.grouped) ? stage_rows : 0;
@@ -2626,7 +2757,14 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     // exact round) accumulates into D, then selection and decisions read D
     // in tiles; no slot-major sums, no lists, no transposes.
     uint8_t *A = reinterpret_cast<uint8_t *>(qd_buf + G.n * (int64_t)nqp);  // follows D in the arena
-    if (ql->exact) {
+    if (seq && seq->xs && (!ql->exact || ql->norepl)) {
+      // one coordinate sequence for all points: the round's columns of the
+      // gathered copies, as one product over (queries x points)
+      const int tk = prof_begin(ql->exact ? PROF_EXACT : PROF_SAMPLE, st);
+      launch_round_seq_u8(slots, *seq, ql->cur, ql->cur + 1, ql->t0, ql->t1, A, qd_buf, nqp, B, G, ql->cur, ql->impl,
+                          ql->exact, st);
+      prof_end(tk, st, 0.0);
+    } else if (ql->exact) {
       const int tk = prof_begin(PROF_EXACT, st);
       launch_exact_ql_u8(slots, q8, q8n, G.x8, G.xn, B, G, ql->cur, ql->impl, qd_buf, nqp, st);
       prof_end(tk, st, 0.0);

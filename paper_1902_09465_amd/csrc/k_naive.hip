@@ -216,15 +216,29 @@ __device__ __forceinline__ uint64_t merge_sorted64(uint64_t list, uint64_t cand)
 // of the next PF slices are in flight in registers while the current slice
 // is consumed, so each load has PF slices of compute to arrive.  Rows beyond
 // nq / pend read as zeros.  smem: 2 x stage_bytes(BK) bytes.
-template <int MET, int PF, int BK, int WA = 2>
+//
+// The K range is [kb, ke) of rows of mp bytes (kb and ke multiples of 64;
+// the whole row by default).  With MASK, only the 4-byte words whose columns
+// lie in [mlo, mhi) (multiples of 4) count: the others of the query rows
+// are read as zeros (and, for l1, of the point rows too).
+template <int MET, int PF, int BK, int WA = 2, bool MASK = false>
 __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int64_t nq, const int8_t *__restrict__ X8,
                                              int64_t q0, int64_t p0, int64_t pr1, int64_t mp, uint8_t *smem,
-                                             v4i (&acc)[WA][4]) {
+                                             v4i (&acc)[WA][4], int64_t kb = 0, int64_t ke = -1, int64_t mlo = 0,
+                                             int64_t mhi = 0) {
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int wq = wave >> 1, wp = wave & 1;
   constexpr int TQ = 32 * WA;  // query rows of the block tile (16 WA per wave)
   constexpr int BROW = BK + 16, STAGE = stage_bytes(BK, TQ);
-  const int nks = (int)(mp / BK), tail = (int)(mp % BK);  // mp is a multiple of 64: tail 0 or 64
+  if (ke < 0) ke = mp;
+  const int nks = (int)((ke - kb) / BK), tail = (int)((ke - kb) % BK);  // multiples of 64: tail 0 or 64 (BK 128)
+  auto mask = [&](int64_t col, v4i &v) {
+    if constexpr (MASK) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (col + 4 * d < mlo || col + 4 * d >= mhi) v[d] = 0;
+    }
+  };
 #pragma unroll
   for (int a = 0; a < WA; ++a)
 #pragma unroll
@@ -241,12 +255,14 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
       const int e = tid + 256 * h, r = e / CPR, c = (e % CPR) * 16;
       ra[h] = v4i{0, 0, 0, 0};
       if (c / 16 < per_row && q0 + r < nq) ra[h] = *reinterpret_cast<const v4i *>(Q8 + (q0 + r) * mp + k0 + c);
+      mask(k0 + c, ra[h]);
     }
 #pragma unroll
     for (int h = 0; h < NB; ++h) {
       const int e = tid + 256 * h, r = e / CPR, c = (e % CPR) * 16;
       rb[h] = v4i{0, 0, 0, 0};
       if (c / 16 < per_row && p0 + r < pr1) rb[h] = *reinterpret_cast<const v4i *>(X8 + (p0 + r) * mp + k0 + c);
+      if constexpr (MET == KNN_METRIC_L1) mask(k0 + c, rb[h]);
     }
   };
   auto store = [&](int buf, const v4i (&ra)[NA], const v4i (&rb)[NB]) {
@@ -317,7 +333,7 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
   v4i ra[NS][NA], rb[NS][NB];
 #pragma unroll
   for (int u = 0; u < NS; ++u)
-    if (u < nsl) load((int64_t)u * BK, width(u), ra[u], rb[u]);
+    if (u < nsl) load(kb + (int64_t)u * BK, width(u), ra[u], rb[u]);
   store(0, ra[0], rb[0]);
   __syncthreads();
   for (int base = 0; base < nsl; base += NS) {
@@ -326,7 +342,7 @@ __device__ __forceinline__ void gemm_u8_tile(const int8_t *__restrict__ Q8, int6
       const int sl = base + u;
       if (sl >= nsl) break;
       // stage u was stored to LDS in the previous iteration: refill it
-      if (sl + NS < nsl) load((int64_t)(sl + NS) * BK, width(sl + NS), ra[u], rb[u]);
+      if (sl + NS < nsl) load(kb + (int64_t)(sl + NS) * BK, width(sl + NS), ra[u], rb[u]);
       compute(sl & 1, width(sl));
       if (sl + 1 < nsl) store((sl + 1) & 1, ra[(u + 1) % NS], rb[(u + 1) % NS]);
       __syncthreads();
@@ -628,6 +644,133 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
     wave_count_add(&prof_copy(G.prof)[0], my_pairs * (uint64_t)(G.m + 14));
     wave_count_add(&prof_copy(G.prof)[2], my_pairs * (uint64_t)G.m);
   }
+}
+
+// One round of a point-major batch whose queries share one coordinate
+// sequence (sampling 2 or 3): the round's samples t0 <= t < t1 are columns
+// [t0, t1) of the gathered copies QS [nqp][kp] and XS [n][kp], so the sums
+// of all (query, point) pairs are one product over that column range, on
+// the same tiles as the exact round.  For squared l2 a pair's round sum is
+// |x'|^2 + |q'|^2 - 2 x'.q' over the range (x' = x - 128; the range norms are
+// differences of the prefix norms at boundaries lo and hi); for l1 the
+// v_sad_u8 sum over the range.  The sum is added to the pair's running sum
+// in D where the pair is sampled this round (its "not sampled" byte in A is
+// zero; round 0: every pair of a running slot, D starts from zero).  The
+// exact round of sampling without replacement (exact = 1) adds the
+// coordinates not seen yet, [T_{R-1}, m): the running sum becomes the exact
+// distance, and the pair is marked exact as in k_exact_ql_u8.
+template <int MET, int PF>
+__global__ __launch_bounds__(256) void k_round_seq_u8(const Slot *__restrict__ slots, const int8_t *__restrict__ QS,
+                                                      const int8_t *__restrict__ XS, int64_t kp,
+                                                      const int32_t *__restrict__ qn, const int32_t *__restrict__ xn,
+                                                      int32_t lo, int32_t hi, int64_t t0, int64_t t1,
+                                                      const uint8_t *__restrict__ A, uint32_t *__restrict__ D,
+                                                      int32_t nqp, Bufs B, Geometry G, int32_t cur, int32_t impl,
+                                                      int32_t exact) {
+  constexpr int XWA = exact_wa<MET>(), XQ = 32 * XWA;
+  constexpr int TROW = XQ + 4;
+  constexpr int SMEM = 2 * stage_bytes(BK_EXACT, XQ) > NBP * TROW * 4 ? 2 * stage_bytes(BK_EXACT, XQ)
+                                                                       : NBP * TROW * 4;
+  __shared__ __align__(16) uint8_t smem[SMEM];
+  const int64_t n = G.n;
+  const int ns = G.nslots;
+  const int64_t nqt = (ns + XQ - 1) / XQ, nwork = nqt * ((n + NBP - 1) / NBP);
+  const int64_t w = xcd_work_item(nwork);
+  if (w >= nwork) return;
+  const int64_t p0 = (w / nqt) * NBP;
+  const int64_t q0 = (w % nqt) * XQ;
+  const int64_t pend = std::min(n, p0 + NBP);
+  __shared__ uint8_t take[XQ];
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  if (threadIdx.x < XQ) {
+    const int64_t s = q0 + threadIdx.x;
+    const bool t = s < ns && slots[s].state == 1 && slots[s].cur == cur && slots[s].implicit != 0;
+    take[threadIdx.x] = t ? 1 : 0;
+    if (t) any = 1;
+  }
+  __syncthreads();
+  if (!any) return;  // (block-uniform) no dense slot of this query tile runs this round
+  // the K slices covering [t0, t1); words outside it count as zero
+  const int64_t kb = t0 / 64 * 64, ke = std::min<int64_t>(kp, (t1 + 63) / 64 * 64);
+  v4i acc[XWA][4];
+  gemm_u8_tile<MET, PF, BK_EXACT, XWA, true>(QS, (int64_t)nqp, XS, q0, p0, pend, kp, smem, acc, kb, ke, t0, t1);
+  const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
+  // the round sums through LDS as [point][query] rows (the K loop ended with a barrier)
+  uint32_t *T = reinterpret_cast<uint32_t *>(smem);
+#pragma unroll
+  for (int a = 0; a < XWA; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ql = 16 * XWA * wq + 16 * a + 4 * (lane >> 4) + v;
+      const int64_t s = q0 + ql;
+      int64_t qr = 0;
+      if (MET == KNN_METRIC_L2 && s < nqp) qr = (int64_t)qn[(int64_t)hi * nqp + s] - qn[(int64_t)lo * nqp + s];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int pl = 64 * wp + 16 * b + (lane & 15);
+        const int64_t i = p0 + pl;
+        uint32_t val = 0;
+        if (i < n) {
+          if constexpr (MET == KNN_METRIC_L1) {
+            val = (uint32_t)acc[a][b][v];
+          } else {
+            const int64_t xr = (int64_t)xn[(int64_t)hi * n + i] - xn[(int64_t)lo * n + i];
+            val = (uint32_t)(xr + qr - 2 * (int64_t)acc[a][b][v]);
+          }
+        }
+        T[pl * TROW + ql] = val;
+      }
+    }
+  __syncthreads();
+  // 16-byte pieces of D: four queries of one point (nqp is a multiple of 16)
+  uint64_t my_pairs = 0;
+  constexpr int PIECES = NBP * XQ / 4;
+  for (int e = threadIdx.x; e < PIECES; e += 256) {
+    const int pl = e / (XQ / 4), qc = 4 * (e % (XQ / 4));
+    const int64_t i = p0 + pl, s = q0 + qc;
+    if (i >= n || s >= nqp) continue;
+    const uint32_t tk = take[qc] | (take[qc + 1] << 8) | (take[qc + 2] << 16) | (take[qc + 3] << 24);
+    if (tk == 0) continue;
+    const uint32_t a4 = impl ? 0u : *reinterpret_cast<const uint32_t *>(A + i * nqp + s);
+    uint32_t *dst = D + i * nqp + s;
+    const uint4 val = *reinterpret_cast<const uint4 *>(&T[pl * TROW + qc]);
+    const uint4 old = impl ? make_uint4(0u, 0u, 0u, 0u) : *reinterpret_cast<const uint4 *>(dst);
+    const uint32_t vv[4] = {val.x, val.y, val.z, val.w}, oo[4] = {old.x, old.y, old.z, old.w};
+    uint32_t nw[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool sampled = ((tk >> (8 * u)) & 1u) != 0 && ((a4 >> (8 * u)) & 255u) == 0;
+      nw[u] = sampled ? oo[u] + vv[u] : oo[u];
+      if (sampled) {
+        ++my_pairs;
+        if (exact) {
+          const int64_t off = (s + u) * n + i;
+          B.fl[off] = FL_EXACT;
+          B.ri[off] = impl ? (uint8_t)0 : (uint8_t)(cur - 1);
+        }
+      }
+    }
+    *reinterpret_cast<uint4 *>(dst) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
+  }
+  if (G.prof) {  // whole waves reach this point
+    wave_count_add(&prof_copy(G.prof)[exact ? 2 : 1], my_pairs * (uint64_t)(t1 - t0));
+  }
+}
+
+void launch_round_seq_u8(const Slot *slots, const SeqBufs &q, int32_t lo, int32_t hi, int64_t t0, int64_t t1,
+                         const uint8_t *A, uint32_t *D, int32_t nqp, const Bufs &B, const Geometry &G, int32_t cur,
+                         int32_t impl, int32_t exact, hipStream_t st) {
+  const int xq = 32 * (G.metric == KNN_METRIC_L1 ? exact_wa<KNN_METRIC_L1>() : exact_wa<KNN_METRIC_L2>());
+  const int64_t nwork = ((G.n + NBP - 1) / NBP) * ((G.nslots + xq - 1) / xq);
+  const dim3 grid((unsigned)xcd_grid(nwork));
+  if (G.metric == KNN_METRIC_L1)
+    hipLaunchKernelGGL((k_round_seq_u8<KNN_METRIC_L1, 3>), grid, dim3(256), 0, st, slots, q.qs, q.xs, q.kp, q.qn, q.xn,
+                       lo, hi, t0, t1, A, D, nqp, B, G, cur, impl, exact);
+  else
+    hipLaunchKernelGGL((k_round_seq_u8<KNN_METRIC_L2, 3>), grid, dim3(256), 0, st, slots, q.qs, q.xs, q.kp, q.qn, q.xn,
+                       lo, hi, t0, t1, A, D, nqp, B, G, cur, impl, exact);
 }
 
 void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_t *Q8, int32_t *qn, int32_t metric,

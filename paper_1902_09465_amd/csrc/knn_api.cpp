@@ -145,7 +145,7 @@ size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax) {
 }
 
 int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cmax, int64_t qcap, int64_t nsched,
-                  hipStream_t st, bool async_alloc, bool grouped, bool query_lane) {
+                  hipStream_t st, bool async_alloc, bool grouped, bool query_lane, int32_t seq_tlen, int32_t seq_nb) {
   const Knobs K = knobs_for(db);
   const int64_t n = db->n;
   const int64_t pw = part_words(n, kmax, cmax);
@@ -176,6 +176,15 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
                    db->m <= 65536;
   const size_t o_q8 = take(q8x ? (size_t)nqp * (size_t)db->mp : 0);
   const size_t o_q8n = take(q8x ? (size_t)nqp * 4 : 0);
+  // a shared coordinate sequence: its coordinates, the points and queries at
+  // them, and their prefix norms at the round boundaries
+  const bool seq = q8x && seq_tlen > 0;
+  const int64_t kp = seq ? ((int64_t)seq_tlen + 63) / 64 * 64 : 0;
+  const size_t o_js = take(seq ? (size_t)kp * 4 : 0);
+  const size_t o_xs = take(seq ? (size_t)n * kp : 0);
+  const size_t o_qs = take(seq ? (size_t)nqp * kp : 0);
+  const size_t o_xsn = take(seq ? (size_t)seq_nb * n * 4 : 0);
+  const size_t o_qsn = take(seq ? (size_t)seq_nb * nqp * 4 : 0);
   void *base = nullptr;
   if (async_alloc) {
     hipMemPool_t pool = engine_pool();
@@ -207,6 +216,17 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.q8 = q8x ? (int8_t *)at(o_q8) : nullptr;
   E.q8n = q8x ? (int32_t *)at(o_q8n) : nullptr;
   E.nqp = nqp;
+  E.seq = SeqBufs{};
+  if (seq) {
+    E.seq.js = (uint32_t *)at(o_js);
+    E.seq.xs = (int8_t *)at(o_xs);
+    E.seq.qs = (int8_t *)at(o_qs);
+    E.seq.xn = (int32_t *)at(o_xsn);
+    E.seq.qn = (int32_t *)at(o_qsn);
+    E.seq.kp = kp;
+    E.seq.tlen = seq_tlen;
+    E.seq.nb = seq_nb;
+  }
   E.B.cand = nullptr;
   E.B.dpm = query_lane ? E.qsum : nullptr;
   E.B.dpm_stride = nqp;
@@ -257,7 +277,7 @@ int engine_destroy(Engine &E) {
 
 void engine_step(Engine &E, bool any_cexact, int sample_kind, int stage_rows, const QlRound *ql) {
   launch_step(E.slots, E.qd, E.sched, E.ctl, E.db->X, E.B, E.G, any_cexact, E.st, sample_kind, stage_rows, ql, E.qt,
-              E.nqp, E.qsum, E.q8, E.q8n);
+              E.nqp, E.qsum, E.q8, E.q8n, E.seq.xs ? &E.seq : nullptr);
 }
 
 int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &pp, QDesc &d, Sched &sc) {
@@ -276,8 +296,9 @@ int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &pp, QDesc &d, Sc
   d.W = db->dtype == KNN_U8 ? (db->metric == KNN_METRIC_L1 ? 255.0 : 65025.0) : 0.0;
   d.F = 0;
   d.trivial = kh >= db->n ? 1 : 0;
-  if (pp.sampling < 0 || pp.sampling > 1) return fail(KNN_EINVAL, "sampling must be 0 or 1");
-  d.norepl = pp.sampling;
+  if (pp.sampling < 0 || pp.sampling > 3) return fail(KNN_EINVAL, "sampling must be 0, 1, 2 or 3");
+  d.norepl = pp.sampling & 1;
+  d.shared = pp.sampling >> 1;
   return KNN_OK;
 }
 
@@ -324,6 +345,25 @@ static int prepare(knn_db_s *db, const void *dq, int64_t nq, const int32_t *host
   return KNN_OK;
 }
 
+// A query-lane batch that keeps its sums point-major (see launch_lockstep)
+// and whose queries share one coordinate sequence runs its rounds on copies
+// of the points and queries gathered at the sequence's coordinates: the
+// samples they hold (the last sampled target; with the permutation, all m,
+// so the exact round adds the rest) and the norm boundaries.
+static void seq_geometry(const knn_db_s *db, const Prepared &P, bool query_lane, int32_t &tlen, int32_t &nb) {
+  tlen = nb = 0;
+  if (!query_lane || P.qd.empty() || !P.qd[0].shared || P.sched.size() != 1 || P.any_cexact || P.kmax + 1 > 64)
+    return;
+  const int32_t R = P.sched[0].R;
+  if (P.qd[0].norepl) {
+    tlen = (int32_t)db->m;
+    nb = R + 2;
+  } else if (R > 0) {
+    tlen = P.sched[0].T[R - 1];
+    nb = R + 1;
+  }
+}
+
 // The launches of a batch whose queries all start together: (float
 // query prep,) first admission, (query-lane transposed queries,) then one
 // step per round.  With one shared schedule, step t runs round t for all
@@ -340,6 +380,12 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   // candidate-exact, k + 1 <= 64) and whose exact round is one tiled pass
   // read the sets from the flags alone: no per-slot point lists are built
   E.G.flagsets = (E.qt && E.q8 && lockstep && !P.any_cexact && P.kmax + 1 <= 64) ? 1 : 0;
+  // one coordinate sequence for every point: the points and queries gathered
+  // at its coordinates once, then every round is a range of their columns
+  const bool seq = E.seq.xs && E.G.flagsets;
+  if (seq)
+    launch_seq_prepare(E.slots, E.sched, (int32_t)E.ns, E.nqp, db->X, n, m, P.qd[0].seed, P.qd[0].norepl,
+                       db->metric, E.seq, st);
   // long rounds of grouped sampling read whole point rows into LDS
   const int stage_rows = E.G.grouped ? stage_rows_for(m, db->mp, K.stage_rows) : 0;
   for (int t = 0; t < P.rmax + 1; ++t) {
@@ -353,9 +399,14 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
     if (ql) {
       qr.seed = P.qd[0].seed;
       qr.norepl = P.qd[0].norepl;
+      qr.shared = P.qd[0].shared;
       qr.exact = t >= P.sched[0].R;
       qr.t0 = (t && !qr.exact) ? (uint32_t)P.sched[0].T[t - 1] : 0u;
       qr.t1 = qr.exact ? 0u : (uint32_t)P.sched[0].T[t];
+      if (seq && qr.exact && qr.norepl) {  // the coordinates not sampled yet
+        qr.t0 = t ? (uint32_t)P.sched[0].T[t - 1] : 0u;
+        qr.t1 = (uint32_t)m;
+      }
       qr.cur = t;
       qr.impl = t == 0;
     }
@@ -407,6 +458,10 @@ static int run_graph(knn_db_s *db, const Prepared &P, int64_t nq, int64_t ns, bo
   put(hdr, sizeof(hdr));
   put(&K, sizeof(K));
   put(P.sched.data(), sizeof(Sched) * P.sched.size());
+  if (query_lane) {  // the shared seed and draw kind are arguments of the captured sampling launches
+    const uint64_t sd[2] = {P.qd[0].seed, (uint64_t)P.qd[0].norepl | ((uint64_t)P.qd[0].shared << 1)};
+    put(sd, sizeof(sd));
+  }
   Plan *pl = db->plan;
   if (!pl || pl->key != key) {
     if (pl) {
@@ -415,7 +470,10 @@ static int run_graph(knn_db_s *db, const Prepared &P, int64_t nq, int64_t ns, bo
     }
     std::unique_ptr<Plan> np(new Plan());
     np->key = key;
-    int rc = engine_create(np->E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, false, same, query_lane);
+    int32_t seq_tlen = 0, seq_nb = 0;
+    seq_geometry(db, P, query_lane, seq_tlen, seq_nb);
+    int rc = engine_create(np->E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, false, same, query_lane,
+                           seq_tlen, seq_nb);
     if (rc != KNN_OK) return rc;
     Ctl ctl;
     std::memset(&ctl, 0, sizeof(ctl));
@@ -474,7 +532,8 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
   // the sampling kernel serve them in groups
   bool same = true;
   for (int64_t q = 1; q < nq && same; ++q)
-    same = P.qd[q].seed == P.qd[0].seed && P.qd[q].sched == P.qd[0].sched && P.qd[q].norepl == P.qd[0].norepl;
+    same = P.qd[q].seed == P.qd[0].seed && P.qd[q].sched == P.qd[0].sched && P.qd[q].norepl == P.qd[0].norepl &&
+           P.qd[q].shared == P.qd[0].shared;
   // Query-lane sampling: with every query in flight at once (nq <= ns) and
   // one seed and schedule, all slots run the same round at each step, so a
   // wave can serve one point for many slots at a time.
@@ -486,7 +545,10 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
       K.stage_min >= (1 << 30))
     return run_graph(db, P, nq, ns, same, query_lane, K, st);
   Engine E;
-  int rc = engine_create(E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, true, same, query_lane);
+  int32_t seq_tlen = 0, seq_nb = 0;
+  seq_geometry(db, P, query_lane, seq_tlen, seq_nb);
+  int rc = engine_create(E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, true, same, query_lane, seq_tlen,
+                         seq_nb);
   if (rc != KNN_OK) return rc;
   Ctl ctl;
   std::memset(&ctl, 0, sizeof(ctl));

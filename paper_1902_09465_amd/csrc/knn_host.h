@@ -84,10 +84,14 @@ struct Engine {
                              // queries' bytes, zero-padded)
   int32_t *q8n = nullptr;    // ... and their squared norms [nqp] (squared l2)
   int32_t nqp = 0;
+  SeqBufs seq;               // one coordinate sequence for all points: its gathered copies (seq.xs null: none)
 };
 size_t engine_slot_bytes(int64_t n, int32_t kmax, int32_t cmax);
+// seq_tlen > 0: also the gathered copies of a shared coordinate sequence
+// holding seq_tlen samples, with seq_nb norm boundaries
 int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cmax, int64_t qcap, int64_t nsched,
-                  hipStream_t st, bool async_alloc, bool grouped, bool query_lane = false);
+                  hipStream_t st, bool async_alloc, bool grouped, bool query_lane = false, int32_t seq_tlen = 0,
+                  int32_t seq_nb = 0);
 int engine_destroy(Engine &E);
 void engine_step(Engine &E, bool any_cexact, int sample_kind = 0, int stage_rows = 0, const QlRound *ql = nullptr);
 // rows per LDS tile for grouped sampled rounds of an m-dimensional DB (0: none fits)
@@ -103,7 +107,13 @@ void launch_prep_f32(QDesc *qd, int32_t nq, int64_t n, int64_t m, double lo, dou
 void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, const uint8_t *X,
                  const Bufs &B, const Geometry &G, bool any_cexact, hipStream_t st, int sample_kind = 0,
                  int stage_rows = 0, const QlRound *ql = nullptr, const uint8_t *qt = nullptr, int32_t nqp = 0,
-                 uint32_t *qd_buf = nullptr, const int8_t *q8 = nullptr, const int32_t *q8n = nullptr);
+                 uint32_t *qd_buf = nullptr, const int8_t *q8 = nullptr, const int32_t *q8n = nullptr,
+                 const SeqBufs *seq = nullptr);
+void launch_seq_prepare(const Slot *slots, const Sched *sc, int32_t ns, int32_t nqp, const uint8_t *X, int64_t n,
+                        int64_t m, uint64_t seed, int32_t norepl, int32_t metric, const SeqBufs &q, hipStream_t st);
+void launch_round_seq_u8(const Slot *slots, const SeqBufs &q, int32_t lo, int32_t hi, int64_t t0, int64_t t1,
+                         const uint8_t *A, uint32_t *D, int32_t nqp, const Bufs &B, const Geometry &G, int32_t cur,
+                         int32_t impl, int32_t exact, hipStream_t st);
 void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint8_t *qt, hipStream_t st);
 void launch_build_q8(const Slot *slots, int32_t ns, int64_t m, int64_t mp, int8_t *Q8, int32_t *qn, int32_t metric,
                      hipStream_t st);

@@ -37,6 +37,8 @@ struct QDesc {
   int32_t F;            // f32 fixed-point shift (0 for u8)
   int32_t trivial;      // 1: k+h >= n or zero range -> return the first min(n,k+h) indices
   int32_t norepl;       // 1: coordinates drawn without replacement
+  int32_t shared;       // 1: one coordinate sequence for all points (counter words (0, 2) / (0, 3))
+  int32_t pad0;
   int64_t *out_idx;     // row of out_stride int64
   int32_t *out_count;
   knn_stats *out_stats;
@@ -56,6 +58,7 @@ struct Slot {
   int32_t nn_act, nn_xa, nn_acc; // sizes being built by k_decide
   int32_t k, kh, R, c_exact;
   int32_t F, norepl;
+  int32_t shared, pad2;  // shared: one coordinate sequence for all points
   uint64_t seed;
   double W;
   const void *q;
@@ -78,6 +81,24 @@ struct QlRound {
   int32_t impl;         // 1: round 0, every point undecided
   int32_t exact;        // 1: the exact round (t0, t1, seed unused)
   int32_t norepl;       // 1: coordinates drawn without replacement
+  int32_t shared;       // 1: one coordinate sequence for all points
+  int32_t pad;
+};
+
+// A point-major batch whose queries share one coordinate sequence
+// (sampling 2 or 3, one seed): the sequence and the points and queries
+// gathered at its coordinates, so that a round's samples are a range of
+// columns of these copies.
+struct SeqBufs {
+  uint32_t *js = nullptr;  // [kp] coordinate of sample t (~0u past the samples held)
+  int8_t *xs = nullptr;    // [n][kp] points at the sequence's coordinates (x - 128; l1: raw bytes)
+  int8_t *qs = nullptr;    // [nqp][kp] the queries, likewise (rows of idle slots zero)
+  int32_t *xn = nullptr;   // [nb][n] squared norms of the xs rows over the samples t < T'_b (l2)
+  int32_t *qn = nullptr;   // [nb][nqp] the same for the qs rows
+  int64_t kp = 0;          // row length, a multiple of 64
+  int32_t tlen = 0;        // samples held: the last sampled target, or m without replacement
+  int32_t nb = 0;          // boundaries T'_0 = 0, T'_b = T[b-1] (b <= R), and T'_{R+1} = m
+                           // without replacement
 };
 
 // Engine control block (device).

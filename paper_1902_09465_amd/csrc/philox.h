@@ -6,7 +6,10 @@
 // The draw for sample t of point i under seed s is output (t mod 4) of
 // Philox4x32-10 with key (s lo, s hi) and counter (t/4, 0, i, 0) -- the same
 // stream as rocRAND's philox engine with subsequence i and offset t.  A
-// 32-bit draw r maps to the coordinate floor(r m / 2^32).
+// 32-bit draw r maps to the coordinate floor(r m / 2^32).  When one
+// coordinate sequence serves every point (the estimator of Section 4 is
+// written over indices j_1, j_2, ... that need not depend on the point), the
+// counter is (t/4, 0, 0, 2) instead.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -54,8 +57,14 @@ struct PermKey {
   uint32_t k[4];
 };
 
-__device__ __forceinline__ PermKey perm_key(uint32_t i, uint32_t s0, uint32_t s1) {
-  const P4 r = philox10(0u, 0u, i, 1u, s0, s1);
+// Counter words (c2, c3) of point i's draws: (i, 0) per point, with the
+// permutation's round keys at (i, 1); one sequence shared by all points
+// uses (0, 2) and (0, 3).
+__device__ __forceinline__ uint32_t draw_c2(uint32_t i, bool shared) { return shared ? 0u : i; }
+__device__ __forceinline__ uint32_t draw_c3(bool shared, bool perm) { return (shared ? 2u : 0u) | (perm ? 1u : 0u); }
+
+__device__ __forceinline__ PermKey perm_key(uint32_t c2, uint32_t c3, uint32_t s0, uint32_t s1) {
+  const P4 r = philox10(0u, 0u, c2, c3, s0, s1);
   return PermKey{{r.x, r.y, r.z, r.w}};
 }
 
@@ -90,14 +99,15 @@ __device__ __forceinline__ uint32_t perm_coord(uint32_t t, uint32_t m, int h, co
   return x;
 }
 
-// The four coordinates of draw block b (samples 4b .. 4b + 3) of point i.
-__device__ __forceinline__ void draw_block(uint32_t b, uint32_t i, uint32_t s0, uint32_t s1, uint32_t m, bool norepl,
-                                           int h, const PermKey &pk, uint32_t (&js)[4]) {
+// The four coordinates of draw block b (samples 4b .. 4b + 3) of the
+// sequence with counter words (c2, c3) (draw_c2 / draw_c3).
+__device__ __forceinline__ void draw_block(uint32_t b, uint32_t c2, uint32_t c3, uint32_t s0, uint32_t s1, uint32_t m,
+                                           bool norepl, int h, const PermKey &pk, uint32_t (&js)[4]) {
   if (norepl) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) js[e] = perm_coord(4u * b + (uint32_t)e, m, h, pk);
   } else {
-    const P4 r = philox10(b, 0u, i, 0u, s0, s1);
+    const P4 r = philox10(b, 0u, c2, c3, s0, s1);
     js[0] = coord_of(r.x, m);
     js[1] = coord_of(r.y, m);
     js[2] = coord_of(r.z, m);

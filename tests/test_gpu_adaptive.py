@@ -63,8 +63,17 @@ def test_tiny_config_parity(P, orc, seed):
         assert set(planted.tolist()) <= set(ref.tolist())
 
 
+def sampling_of(name: str) -> int:
+    """Sampling mode of a parametrisation name: _norepl without replacement,
+    _shared one coordinate sequence for all points (modes 0..3)."""
+    return (1 if "norepl" in name else 0) + (2 if "shared" in name else 0)
+
+
 @pytest.mark.parametrize("dtype", ["u8", "u8_staged", "u8_qlane", "u8_qlane_pure", "u8_qlane_pure_sparse", "f32",
-                                   "u8_norepl", "u8_qlane_norepl", "u8_ungrouped_norepl", "f32_norepl"])
+                                   "u8_norepl", "u8_qlane_norepl", "u8_ungrouped_norepl", "f32_norepl",
+                                   "u8_shared", "u8_shared_norepl", "u8_ungrouped_shared", "u8_qlane_shared_norepl",
+                                   "u8_qlane_pure_shared", "u8_qlane_pure_shared_norepl",
+                                   "u8_qlane_pure_sparse_shared_norepl", "f32_shared", "f32_shared_norepl"])
 def test_per_round_state_parity(P, orc, dtype, monkeypatch):
     """After every decide step the per-point (S, flags, round) equal the oracle's."""
     g = rng(77)
@@ -73,7 +82,7 @@ def test_per_round_state_parity(P, orc, dtype, monkeypatch):
         monkeypatch.setenv("KNN_STAGE_ROWS", "16")
     if dtype.startswith("u8_qlane"):  # query-lane sampling even for a single slot
         monkeypatch.setenv("KNN_QL_MIN", "1")
-    if dtype.endswith("_sparse"):  # per-slot lists from round 1 on, one chunk-looping block per slot
+    if "_sparse" in dtype:  # per-slot lists from round 1 on, one chunk-looping block per slot
         monkeypatch.setenv("KNN_SPARSE_DIV", "1")
         monkeypatch.setenv("KNN_SPARSE_LIST", "1")
     if dtype.startswith("u8_ungrouped"):  # the per-query sampling kernel
@@ -85,7 +94,7 @@ def test_per_round_state_parity(P, orc, dtype, monkeypatch):
     db = P.KnnDB(dev(X))
     # candidate-exact on, except in the pure variant (fused fold + selection)
     kw = dict(h=4, delta=0.05, seed=int(g.integers(1 << 40)), b0=8, growth=1.5,
-              c_exact=0 if "pure" in dtype else 3, sampling=1 if dtype.endswith("norepl") else 0)
+              c_exact=0 if "pure" in dtype else 3, sampling=sampling_of(dtype))
     T = orc.schedule(8, 1.5, 1.0, X.shape[1])
     for r in range(1, len(T) + 2):
         S, fl, ri = db.adaptive_state(dev(Q), 6, P.default_params(**kw), r)
@@ -143,8 +152,8 @@ def _decisive_batch():
 DECISIVE_KW = dict(h=-1, delta=0.01, seed=2024, alpha_kind=2, c_alpha=0.1, c_exact=0)
 
 
-@pytest.mark.parametrize("sparse_div", ["16", "0"])
-def test_point_major_batch_decides_in_sampled_rounds(P, orc, monkeypatch, sparse_div):
+@pytest.mark.parametrize("sparse_div,sampling", [("16", 0), ("0", 0), ("16", 2), ("0", 2), ("16", 3), ("0", 3)])
+def test_point_major_batch_decides_in_sampled_rounds(P, orc, monkeypatch, sparse_div, sampling):
     """The launch shape the benchmark times -- one seed shared by many queries,
     k + 1 <= 64, no candidate-exact: query-lane sampling, point-major sums,
     four-slot selection tiles and 64-slot decide tiles (80 queries: two decide
@@ -153,15 +162,18 @@ def test_point_major_batch_decides_in_sampled_rounds(P, orc, monkeypatch, sparse
     oracle's; the per-round state of slots 0, 1, 64 and 79 equals the
     oracle's after every decide step.  With the default switch (slots whose
     undecided set falls to n/16 continue on per-slot lists) and with slots
-    kept dense to the end."""
+    kept dense to the end.  With one coordinate sequence for all points
+    (sampling 2 and 3) the rounds run as int8 products over the gathered
+    coordinates (without replacement the exact round adds the rest)."""
     monkeypatch.setenv("KNN_SPARSE_DIV", sparse_div)
     X, Q, ks = _decisive_batch()
     n = X.shape[0]
     db = P.KnnDB(dev(X))
-    p = P.default_params(**DECISIVE_KW)
+    kw = dict(DECISIVE_KW, sampling=sampling)
+    p = P.default_params(**kw)
     idx, cnt, st = db.adaptive(dev(Q), ks, p)
     idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
-    refs = oracle_many(orc, X, Q, ks, DECISIVE_KW, range(len(ks)))
+    refs = oracle_many(orc, X, Q, ks, kw, range(len(ks)))
     for q, (ref, rst) in enumerate(refs):
         assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
         assert (int(st[q]["coord_evals"]), int(st[q]["rounds"]), int(st[q]["count"]),
@@ -175,7 +187,7 @@ def test_point_major_batch_decides_in_sampled_rounds(P, orc, monkeypatch, sparse
     for slot in (0, 1, 64, 79):
         for r in range(1, refs[slot][1]["rounds"] + 1):
             S, fl, ri = db.adaptive_state(Qd, ks, p, r, query=slot)
-            _, _, (So, flo, rio) = orc.adaptive(X, Q[slot], int(ks[slot]), oparams(orc, **DECISIVE_KW),
+            _, _, (So, flo, rio) = orc.adaptive(X, Q[slot], int(ks[slot]), oparams(orc, **kw),
                                                 stop_after=r, dump=True)
             assert np.array_equal(fl, flo), f"slot {slot} round {r}: flags differ"
             assert np.array_equal(S, So), f"slot {slot} round {r}: sums differ"
@@ -376,6 +388,18 @@ def test_graph_replays_equal_eager(P, orc):
             torch.cuda.synchronize()
             assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
             _ = db.naive(b, 3)  # eager work between replays
+    # the same shape with another seed (and with a shared coordinate sequence)
+    # replays nothing captured for the first seed
+    for p2 in (P.default_params(h=6, delta=0.05, seed=6), P.default_params(h=6, delta=0.05, seed=6, sampling=3)):
+        got = db.adaptive(batches[0], 6, p2)
+        os.environ["KNN_GRAPH"] = "0"
+        try:
+            ref = db.adaptive(batches[0], 6, p2)
+        finally:
+            del os.environ["KNN_GRAPH"]
+        assert torch.equal(got[0], ref[0]) and np.array_equal(got[2], ref[2])
+        o = orc.adaptive(X, Q[7], 6, oparams(orc, h=6, delta=0.05, seed=6, sampling=p2.sampling))[0]
+        assert got[0][7, :got[1][7]].cpu().tolist() == o.tolist()
     # a batch of another shape rebuilds the plan, then the first shape again
     other = db.adaptive(dev(Q[:50]), 6, p)
     ref50 = orc.adaptive(X, Q[3], 6, oparams(orc, h=6, delta=0.05, seed=5))[0]
@@ -472,13 +496,15 @@ def test_uneven_config_sampled(P, orc):
         assert int(st[qi]["coord_evals"]) == rst["coord_evals"], qi
 
 
-def test_without_replacement_batched(P, orc):
-    """Sampling without replacement, 64 queries with one seed (query-lane
-    sampling and the exact-round GEMM), against the oracle and the per-query
-    path; knob invariance."""
+@pytest.mark.parametrize("sampling", [1, 2, 3])
+def test_sampling_modes_batched(P, orc, sampling):
+    """Sampling without replacement (1), or one coordinate sequence for all
+    points (2: with replacement, 3: without; the rounds as products over the
+    gathered coordinates), 64 queries with one seed, against the oracle, the
+    grouped and the per-query paths; knob invariance."""
     X, Q = gmm_u8(81, n=9001, m=500, n_centres=8, sigma=30.0, nq=64)
     db = P.KnnDB(dev(X))
-    kw = dict(h=10, delta=0.01, seed=77, sampling=1)
+    kw = dict(h=10, delta=0.01, seed=77, sampling=sampling)
     base = db.adaptive(dev(Q), 10, P.default_params(**kw))
     for env in ({"KNN_QL": "0"}, {"KNN_QL": "0", "KNN_GROUP": "0"}, {"KNN_QL_MIN": "1", "KNN_CH_SAMPLE": "64"}):
         os.environ.update(env)

@@ -140,14 +140,15 @@ def test_l1_tiny_parity(P, orc, seed):
 
 
 @pytest.mark.parametrize("path", ["u8", "u8_ungrouped", "u8_qlane", "u8_qlane_pure", "u8_qlane_pure_sparse",
-                                  "u8_norepl", "u8_qlane_norepl", "f32", "f32_norepl"])
+                                  "u8_norepl", "u8_qlane_norepl", "f32", "f32_norepl", "u8_shared",
+                                  "u8_qlane_pure_shared", "u8_qlane_pure_shared_norepl", "f32_shared_norepl"])
 def test_l1_per_round_state_parity(P, orc, path, monkeypatch):
     """After every decide step the per-point (S, flags, round) equal the oracle's."""
     if path.startswith("u8_qlane"):
         monkeypatch.setenv("KNN_QL_MIN", "1")
     if path.startswith("u8_ungrouped"):
         monkeypatch.setenv("KNN_GROUP", "0")
-    if path.endswith("_sparse"):  # per-slot lists from round 1 on
+    if "_sparse" in path:  # per-slot lists from round 1 on
         monkeypatch.setenv("KNN_SPARSE_DIV", "1")
     g = rng(78)
     if path.startswith("u8"):
@@ -156,7 +157,8 @@ def test_l1_per_round_state_parity(P, orc, path, monkeypatch):
         X, Q = gmm_f32(78, n=5003, m=101, n_centres=6, sigma=0.3, nq=1)
     db = l1db(P, X)
     kw = dict(h=4, delta=0.05, seed=int(g.integers(1 << 40)), b0=8, growth=1.5,
-              c_exact=0 if "pure" in path else 3, sampling=1 if path.endswith("norepl") else 0)
+              c_exact=0 if "pure" in path else 3,
+              sampling=(1 if "norepl" in path else 0) + (2 if "shared" in path else 0))
     T = orc.schedule(8, 1.5, 1.0, X.shape[1])
     for r in range(1, len(T) + 2):
         S, fl, ri = db.adaptive_state(dev(Q), 6, P.default_params(**kw), r)
@@ -173,7 +175,7 @@ KNOBS = [{}, {"KNN_GROUP": "0"}, {"KNN_QL_MIN": "1"}, {"KNN_QL_MIN": "1", "KNN_S
 
 
 @pytest.mark.parametrize("knob", KNOBS, ids=lambda k: ",".join(f"{a}={b}" for a, b in k.items()) or "default")
-@pytest.mark.parametrize("sampling", [0, 1])
+@pytest.mark.parametrize("sampling", [0, 1, 2, 3])
 def test_l1_batched_paths_parity(P, orc, knob, sampling, monkeypatch):
     """A batch sharing seed and schedule (16-slot groups, or query lanes with
     KNN_QL_MIN=1), each query equal to the oracle run alone."""
