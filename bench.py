@@ -88,10 +88,11 @@ def stored_traffic():
         return None
 
 
-def profile_pass():
-    """The workload of the counter passes: a plain device copy of COPY_BYTES
-    (calibrates FETCH_SIZE / WRITE_SIZE), then one adaptive batch of the
-    batched-integer workload, launched eagerly (no graph)."""
+def profile_pass(args):
+    """The workload of the counter and kernel-trace passes: a plain device copy
+    of COPY_BYTES (calibrates FETCH_SIZE / WRITE_SIZE), then `--steps`
+    adaptive batches of the batched-integer workload in sampling mode
+    `--sampling`, launched eagerly (no graph)."""
     os.environ["KNN_GRAPH"] = "0"
     import torch
     from knn_inputs import gmm_u8
@@ -105,9 +106,11 @@ def profile_pass():
     X, Q = gmm_u8(2000, n=N, m=M, n_centres=32, sigma=30.0, nq=NQ)
     db = P.KnnDB(torch.from_numpy(X).cuda())
     Qd = torch.from_numpy(Q).cuda()
-    idx, cnt, _ = db.adaptive(Qd, K, P.default_params(h=H, delta=DELTA, seed=12345), with_stats=False)
-    torch.cuda.synchronize()
-    log(f"profile pass done: {int((cnt > 0).sum())} queries answered")
+    for s in range(args.steps):
+        idx, cnt, _ = db.adaptive(Qd, K, P.default_params(h=H, delta=DELTA, seed=12345, sampling=args.sampling),
+                                  with_stats=False)
+        torch.cuda.synchronize()
+        log(f"profile pass batch {s + 1}/{args.steps} done: {int((cnt > 0).sum())} queries answered")
     return 0
 
 
@@ -142,20 +145,21 @@ def contained(idx, cnt, X_t, Q_t, nidx, ndist, k, metric="l2"):
 
 
 def _oracle_worker(args):
-    X, q, k, h, delta, seed, metric = args
+    X, q, k, h, delta, seed, metric, sampling = args
     import oracle
     t0 = time.perf_counter()
-    idx, st = oracle.adaptive(X, q, k, oracle.make_params(h=h, delta=delta, seed=seed), metric=metric)
+    idx, st = oracle.adaptive(X, q, k, oracle.make_params(h=h, delta=delta, seed=seed, sampling=sampling),
+                              metric=metric)
     return time.perf_counter() - t0, st["coord_evals"]
 
 
-def cpu_baseline(X, Q, seconds_hint, metric=0):
+def cpu_baseline(X, Q, seconds_hint, metric=0, sampling=0):
     """The oracle, untuned, on this host's cores: one query per process."""
     import oracle
     oracle.build()
     cores = max(1, min(os.cpu_count() or 1, 16))
     nqs = cores
-    jobs = [(X, Q[i], K, H, DELTA, 12345, metric) for i in range(nqs)]
+    jobs = [(X, Q[i], K, H, DELTA, 12345, metric, sampling) for i in range(nqs)]
     t0 = time.perf_counter()
     ctx = mp.get_context("fork")
     with ctx.Pool(cores) as pool:
@@ -470,6 +474,144 @@ def float_bench(args):
     return 0
 
 
+SAMPLING_NAMES = {0: "coordinates drawn per point with replacement",
+                  1: "coordinates drawn per point without replacement",
+                  2: "one coordinate sequence shared by all points, with replacement",
+                  3: "one coordinate sequence shared by all points, without replacement"}
+
+
+def run_adaptive(P, lib, db, X_t, Q_t, params, nidx, ndist, args, warmup, steps, label, graph=True):
+    """Warm-up, then `steps` timed adaptive batches with per-kernel events;
+    containment, statistics, the rooflines of the step's kernels and (graph)
+    the same batch replayed as a captured graph."""
+    import ctypes
+    import torch
+    l1 = args.metric == "l1"
+    for w in range(warmup):
+        log(f"{label} warmup {w + 1}/{warmup}")
+        db.adaptive(Q_t, K, params, with_stats=False)
+    torch.cuda.synchronize()
+    P._lib.check(lib.knn_prof_enable(1))
+    # the calls are stream-ordered: the host queues step s + 1 while step s
+    # runs; each step's span is read from events between the steps (the
+    # library and torch both use the null stream here)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    marks[0].record()
+    for s in range(steps):
+        idx, cnt, _ = db.adaptive(Q_t, K, params, with_stats=False)
+        marks[s + 1].record()
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t_all
+    step_ms = [marks[s].elapsed_time(marks[s + 1]) for s in range(steps)]
+    for s in range(steps):
+        log(f"{label} step {s + 1}/{steps}: {step_ms[s]:.1f} ms")
+    # containment and statistics (outside the timed region)
+    ok = contained(idx, cnt, X_t, Q_t, nidx, ndist, K, args.metric)
+    n_ok = int(ok.sum().item())
+    prof = {}
+    for kind, name in ((0, "sample"), (7, "sample_exact_round"), (8, "sample_aux"), (9, "sample_sparse"),
+                       (1, "cand"), (2, "select"), (3, "decide"), (4, "finish")):
+        ms, n_l, u = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        P._lib.check(lib.knn_prof_read(kind, ctypes.byref(ms), ctypes.byref(n_l), ctypes.byref(u)))
+        prof[name] = dict(ms=ms.value, launches=n_l.value)
+    cnts = np.zeros(8, dtype=np.uint64)
+    P._lib.check(lib.knn_prof_counters(cnts.ctypes.data_as(ctypes.c_void_p)))
+    P._lib.check(lib.knn_prof_enable(0))
+    _, _, stats = db.adaptive(Q_t, K, params, with_stats=True)
+    torch.cuda.synchronize()
+    evals = stats["coord_evals"].astype(np.float64)
+    ms_per_step = total_s * 1e3 / steps
+    out = {"value": n_ok / (ms_per_step / 1e3), "ms_per_step": ms_per_step, "step_ms": step_ms, "n_ok": n_ok,
+           "contained": f"{n_ok}/{NQ}", "evals": evals, "idx": idx, "cnt": cnt, "prof": prof,
+           "fraction_of_naive_evals": float(evals.mean() / (N * M)),
+           "kernels_ms_per_step": {k_: v["ms"] / steps for k_, v in prof.items()}}
+    if graph:
+        # the same batch replayed through the cached engine's captured graph
+        # (timing events off: the graph path is taken only then)
+        db.adaptive(Q_t, K, params, with_stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            idx_g, cnt_g, _ = db.adaptive(Q_t, K, params, with_stats=False)
+        torch.cuda.synchronize()
+        out["graph_ms"] = (time.perf_counter() - t0) * 1e3 / steps
+        out["same_graph"] = bool(torch.equal(idx_g, idx) and torch.equal(cnt_g, cnt))
+
+    # rooflines (averages over the timed steps)
+    shared = params.sampling >= 2
+    alg_bytes, pairs, exact_elems, draws_pp = (float(c) for c in cnts[:4])
+    draws = draws_pp + float(cnts[5])
+    out["work"] = (alg_bytes, pairs, exact_elems, draws)
+    samp, exr = prof["sample"], prof["sample_exact_round"]
+    s_avg = samp["ms"] / max(1, samp["launches"]) / 1e3
+    e_avg = exr["ms"] / max(1, exr["launches"]) / 1e3
+    if shared and not l1:
+        # sampled rounds as int8 products over the gathered coordinates: 2 ops
+        # per (query, sample) pair on the matrix cores
+        s_ops = 2.0 * pairs / max(1, samp["launches"])
+        rl_sample = {"bound": "mfma", "achieved": s_ops / s_avg / 1e12 if s_avg > 0 else 0.0,
+                     "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
+                     "kernel": "k_round_seq_u8<l2> (sampled rounds, int8 MFMA over the gathered coordinates)",
+                     "avg_launch_ms": s_avg * 1e3, "launches": samp["launches"], "ops_per_launch": s_ops}
+        rl_sample["frac"] = rl_sample["achieved"] / INT8_PEAK_TOPS
+    else:
+        s_ops = (draws * OPS_PER_DRAW + pairs * (OPS_PER_PAIR_L1 if l1 else OPS_PER_PAIR)) / max(1, samp["launches"])
+        rl_sample = {"bound": "alu", "achieved": s_ops / s_avg / 1e12 if s_avg > 0 else 0.0,
+                     "peak": DOT4_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
+                     "kernel": ("k_round_seq_u8<l1> (sampled rounds, v_sad_u8 tiles over the gathered coordinates)"
+                                if shared else "k_sample_ql_u8 (sampled rounds, query-lane)"),
+                     "avg_launch_ms": s_avg * 1e3,
+                     "launches": samp["launches"], "ops_per_launch": s_ops}
+        rl_sample["frac"] = rl_sample["achieved"] / DOT4_PEAK_TOPS
+        if not shared:
+            # with the draws shared by all queries of the batch: the running
+            # sums D [n][1024] u32 written in every round and read in every
+            # round but the first, the point-major flags A [n][1024] read in
+            # every round but the first, and one byte per distinct draw
+            r_per_step = samp["launches"] / max(1, steps)
+            later = (r_per_step - 1) / max(1.0, r_per_step)
+            rl_sample["alg_bytes_per_launch"] = (N * NQ * 4 + N * NQ * (4 + 1) * later +
+                                                 draws / max(1, samp["launches"]))
+            if not l1 and params.sampling == 0:
+                rl_sample["traffic"] = stored_traffic()
+            if rl_sample["traffic"] and s_avg > 0:
+                rl_sample["achieved_hbm_gbs"] = rl_sample["traffic"] / s_avg / 1e9
+                rl_sample["hbm_frac"] = rl_sample["achieved_hbm_gbs"] / HBM_PEAK_GBS
+    # exact round: one tiled pass over (queries x points), a GEMM on the
+    # matrix cores for squared l2, v_sad_u8 sums on the vector ALU for l1
+    e_ops = (OPS_PER_ELEM_L1 if l1 else 2.0) * exact_elems / max(1, exr["launches"])
+    e_peak = DOT4_PEAK_TOPS if l1 else INT8_PEAK_TOPS
+    rl_exact = {"bound": "alu" if l1 else "mfma", "achieved": e_ops / e_avg / 1e12 if e_avg > 0 else 0.0,
+                "peak": e_peak, "unit": "TOP/s", "traffic": None,
+                "kernel": (("k_round_seq_u8" if params.sampling == 3 else "k_exact_ql_u8") +
+                           ("<l1> (exact round, v_sad_u8 tiles)" if l1 else "<l2> (exact round, int8 MFMA GEMM)")),
+                "avg_launch_ms": e_avg * 1e3, "launches": exr["launches"], "ops_per_launch": e_ops}
+    rl_exact["frac"] = rl_exact["achieved"] / e_peak
+    # selection and decisions stream the point-major sums D [n][1024] u32
+    # and the flags [1024][n] (5 bytes per (query, point)); decisions also
+    # write the next round's "not sampled" bytes A (1 byte)
+    def hbm_rl(name, kernel, per_pair):
+        pr = prof[name]
+        avg = pr["ms"] / max(1, pr["launches"]) / 1e3
+        b = per_pair * N * NQ
+        ach = b / avg / 1e9 if avg > 0 else 0.0
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": None, "kernel": kernel, "avg_launch_ms": avg * 1e3, "launches": pr["launches"],
+                "alg_bytes_per_launch": b}
+    rl_select = hbm_rl("select", "k_select_pm + merges (k-th bound selection)", 5)
+    rl_decide = hbm_rl("decide", "k_decide_pm + k_decide (decisions)", 6)
+    dom = max(prof, key=lambda k_: prof[k_]["ms"])
+    out["dominant_kernel"] = dom
+    out["roofline"] = {"sample_exact_round": rl_exact, "select": rl_select, "decide": rl_decide}.get(dom, rl_sample)
+    out["roofline_sampled_rounds"] = rl_sample
+    out["roofline_exact_round"] = rl_exact
+    out["roofline_select"] = rl_select
+    out["roofline_decide"] = rl_decide
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -487,6 +629,8 @@ def main():
     ap.add_argument("--uneven", action="store_true", help="uneven workload instead of the batch line")
     ap.add_argument("--float", action="store_true", help="float workload instead of the batch line")
     ap.add_argument("--float-queries", type=int, default=1024)
+    ap.add_argument("--sampling", type=int, choices=(0, 1, 2, 3), default=0,
+                    help="sampling mode of the headline batch (knn_params.sampling)")
     ap.add_argument("--metric", choices=("l2", "l1"), default="l2",
                     help="distance of the batch line (l1: the same workload on an l1 DB)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -508,7 +652,7 @@ def main():
     if args.float:
         return float_bench(args)
     if args.profile_pass:
-        return profile_pass()
+        return profile_pass(args)
     import torch
     from knn_inputs import gmm_u8
 
@@ -522,7 +666,7 @@ def main():
     Q_t = torch.from_numpy(Q).cuda()
     l1 = args.metric == "l1"
     db = P.KnnDB(X_t, metric=args.metric)
-    params = P.default_params(h=H, delta=DELTA, seed=12345)
+    params = P.default_params(h=H, delta=DELTA, seed=12345, sampling=args.sampling)
     torch.cuda.synchronize()
 
     log("exact reference (naive scan: int8 MFMA, or v_sad_u8 for l1)")
@@ -530,98 +674,31 @@ def main():
     torch.cuda.synchronize()
 
     # ---------------- adaptive: warmup, then exactly `steps` timed steps
-    for w in range(args.warmup):
-        log(f"adaptive warmup {w + 1}/{args.warmup}")
-        db.adaptive(Q_t, K, params, with_stats=False)
-    torch.cuda.synchronize()
-    P._lib.check(lib.knn_prof_enable(1))
-    ok_counts = []
-    # the calls are stream-ordered: the host queues step s + 1 while step s
-    # runs; each step's span is read from events between the steps (the
-    # library and torch both use the null stream here)
-    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
-    marks[0].record()
-    for s in range(args.steps):
-        idx, cnt, _ = db.adaptive(Q_t, K, params, with_stats=False)
-        marks[s + 1].record()
-    torch.cuda.synchronize()
-    total_s = time.perf_counter() - t_all
-    step_ms = [marks[s].elapsed_time(marks[s + 1]) for s in range(args.steps)]
-    for s in range(args.steps):
-        log(f"adaptive step {s + 1}/{args.steps}: {step_ms[s]:.1f} ms")
-    # containment and statistics (outside the timed region)
-    ok = contained(idx, cnt, X_t, Q_t, nidx, ndist, K, args.metric)
-    n_ok = int(ok.sum().item())
-    prof = {}
-    for kind, name in ((0, "sample"), (7, "sample_exact_round"), (8, "sample_transposes"), (9, "sample_sparse"),
-                       (1, "cand"), (2, "select"), (3, "decide"), (4, "finish")):
-        ms, n_l, u = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
-        P._lib.check(lib.knn_prof_read(kind, ctypes.byref(ms), ctypes.byref(n_l), ctypes.byref(u)))
-        prof[name] = dict(ms=ms.value, launches=n_l.value)
-    cnts = np.zeros(8, dtype=np.uint64)
-    P._lib.check(lib.knn_prof_counters(cnts.ctypes.data_as(ctypes.c_void_p)))
-    P._lib.check(lib.knn_prof_enable(0))
-    _, _, stats = db.adaptive(Q_t, K, params, with_stats=True)
-    torch.cuda.synchronize()
-    evals = stats["coord_evals"].astype(np.float64)
+    head = run_adaptive(P, lib, db, X_t, Q_t, params, nidx, ndist, args, args.warmup, args.steps, "adaptive")
+    value, ms_per_step, step_ms, prof = head["value"], head["ms_per_step"], head["step_ms"], head["prof"]
+    n_ok, evals, idx, cnt = head["n_ok"], head["evals"], head["idx"], head["cnt"]
+    dom, roofline, rl_exact = head["dominant_kernel"], head["roofline"], head["roofline_exact_round"]
+    graph_ms, same_graph = head["graph_ms"], head["same_graph"]
+    alg_bytes, pairs, exact_elems, draws = head["work"]
 
-    ms_per_step = total_s * 1e3 / args.steps
-    value = n_ok / (ms_per_step / 1e3)
-    # the same batch replayed through the cached engine's captured graph
-    # (timing events off: the graph path is taken only then)
-    db.adaptive(Q_t, K, params, with_stats=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        idx_g, cnt_g, _ = db.adaptive(Q_t, K, params, with_stats=False)
-    torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    same_graph = bool(torch.equal(idx_g, idx) and torch.equal(cnt_g, cnt))
-
-    # dominant kernel class of the step and its roofline (averages over the timed steps)
-    dom = max(prof, key=lambda k_: prof[k_]["ms"])
-    alg_bytes, pairs, exact_elems, draws = (float(c) for c in cnts[:4])
-    samp, exr = prof["sample"], prof["sample_exact_round"]
-    s_avg = samp["ms"] / max(1, samp["launches"]) / 1e3
-    e_avg = exr["ms"] / max(1, exr["launches"]) / 1e3
-    s_ops = (draws * OPS_PER_DRAW + pairs * (OPS_PER_PAIR_L1 if l1 else OPS_PER_PAIR)) / max(1, samp["launches"])
-    e_ops = (OPS_PER_ELEM_L1 if l1 else 2.0) * exact_elems / max(1, exr["launches"])
-    rl_sample = {"bound": "alu", "achieved": s_ops / s_avg / 1e12 if s_avg > 0 else 0.0,
-                 "peak": DOT4_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
-                 "kernel": "k_sample_ql_u8 (sampled rounds, query-lane)", "avg_launch_ms": s_avg * 1e3,
-                 "launches": samp["launches"], "ops_per_launch": s_ops,
-                 # bytes per launch if every query read its own samples (no sharing)
-                 "alg_bytes_per_launch_unshared": alg_bytes / max(1, samp["launches"] + exr["launches"])}
-    # with the draws shared by all queries of the batch: the running sums D
-    # [n][1024] u32 written in every round and read in every round but the
-    # first, the point-major flags A [n][1024] read in every round but the
-    # first, and one byte per distinct draw
-    r_per_step = samp["launches"] / max(1, args.steps)
-    later = (r_per_step - 1) / max(1.0, r_per_step)  # fraction of the launches after round 0
-    rl_sample["alg_bytes_per_launch"] = (N * NQ * 4 + N * NQ * (4 + 1) * later + draws / max(1, samp["launches"]))
-    rl_sample["frac"] = rl_sample["achieved"] / DOT4_PEAK_TOPS
-    if not l1:
-        rl_sample["traffic"] = stored_traffic()
-    if rl_sample["traffic"] and s_avg > 0:
-        rl_sample["achieved_hbm_gbs"] = rl_sample["traffic"] / s_avg / 1e9
-        rl_sample["hbm_frac"] = rl_sample["achieved_hbm_gbs"] / HBM_PEAK_GBS
-    # exact round: one tiled pass over (queries x points), a GEMM on the
-    # matrix cores for squared l2, v_sad_u8 sums on the vector ALU for l1
-    e_peak = DOT4_PEAK_TOPS if l1 else INT8_PEAK_TOPS
-    rl_exact = {"bound": "alu" if l1 else "mfma", "achieved": e_ops / e_avg / 1e12 if e_avg > 0 else 0.0,
-                "peak": e_peak, "unit": "TOP/s", "traffic": None,
-                "kernel": ("k_exact_ql_u8<l1> (exact round, v_sad_u8 tiles)" if l1 else
-                           "k_exact_ql_u8<l2> (exact round, int8 MFMA GEMM)"),
-                "avg_launch_ms": e_avg * 1e3, "launches": exr["launches"], "ops_per_launch": e_ops}
-    rl_exact["frac"] = rl_exact["achieved"] / e_peak
-    roofline = rl_exact if dom == "sample_exact_round" else rl_sample
+    # ---------------- the other sampling modes on the same batch (one seed):
+    # 0 and 1 draw per point (query-lane sampler), 2 and 3 share one coordinate
+    # sequence between all points (rounds as int8 products over the gathered
+    # coordinates)
+    other_modes = {}
+    for mode in (0, 1, 2, 3):
+        if mode == args.sampling:
+            continue
+        pm = P.default_params(h=H, delta=DELTA, seed=12345, sampling=mode)
+        r = run_adaptive(P, lib, db, X_t, Q_t, pm, nidx, ndist, args, 1, args.steps, f"sampling {mode}",
+                         graph=False)
+        other_modes[str(mode)] = {k_: r[k_] for k_ in ("value", "ms_per_step", "contained", "fraction_of_naive_evals",
+                                                      "kernels_ms_per_step", "dominant_kernel", "roofline")}
 
     # ---------------- the same workload with a seed per query (what independent
     # callers and the serving session send): the draws are not shared, so the
     # batch runs on the per-query sampling kernels
-    seeds_q = [P.default_params(h=H, delta=DELTA, seed=12345 + q) for q in range(NQ)]
+    seeds_q = [P.default_params(h=H, delta=DELTA, seed=12345 + q, sampling=args.sampling) for q in range(NQ)]
     log("per-query seeds: warmup")
     db.adaptive(Q_t, K, seeds_q, with_stats=False)
     torch.cuda.synchronize()
@@ -677,7 +754,7 @@ def main():
         "config": {"workload": ("batched_int_l1" if l1 else "batched_int") +
                                ": n=100000 points x m=3072 uint8, 32-centre Gaussian mixture "
                                "sigma=30, 1024 queries sharing one seed, k=10 h=10 delta=0.01, footnote width, "
-                               "B0=64, g=2, coordinates drawn per point with replacement" +
+                               "B0=64, g=2, " + SAMPLING_NAMES[args.sampling] +
                                (", l1 distance" if l1 else ""),
                    "global_batch": NQ, "seq_len": M, "parallelism": "single GPU"},
         "contained": f"{n_ok}/{NQ}",
@@ -690,18 +767,22 @@ def main():
         "adaptive_vs_naive": (value / (NQ / naive_s)) if naive_s > 0 else None,
         "kernels_ms_per_step": {k_: v["ms"] / args.steps for k_, v in prof.items()},
         "per_query_seeds": per_query_seeds,
+        "other_sampling_modes": other_modes,
         "graph_replay": {"ms_per_step": graph_ms, "same_result": same_graph,
                          "note": "timed region above runs eagerly with per-kernel HIP events; this is the "
                                  "cached engine replaying its captured launch graph, events off"},
         "dominant_kernel": dom,
         "roofline": roofline,
+        "roofline_sampled_rounds": head["roofline_sampled_rounds"],
         "roofline_exact_round": rl_exact,
+        "roofline_select": head["roofline_select"],
+        "roofline_decide": head["roofline_decide"],
         "work": {"draws": draws, "query_samples": pairs, "exact_elements": exact_elems,
                  "alg_bytes": alg_bytes},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on host cores)")
-        out["cpu_baseline"] = cpu_baseline(X, Q, args.cpu_seconds, 1 if l1 else 0)
+        out["cpu_baseline"] = cpu_baseline(X, Q, args.cpu_seconds, 1 if l1 else 0, args.sampling)
     print(json.dumps(out), flush=True)
     db.close()
     return 0

@@ -277,7 +277,8 @@ int knn_prof_enable(int on);
  * launches that run the exact round of a batch whose queries all share one
  * schedule (such launches are counted here instead of under 0), 8 the
  * point-major / slot-major transposes around query-lane sampling (flags in,
- * round totals out; under 0 is then the sampling kernel alone), 9 the
+ * round totals out; under 0 is then the sampling kernel alone), or the
+ * gather of the points and queries at a shared coordinate sequence, 9 the
  * per-query sampling (or exact sums) of the queries of a point-major batch
  * whose undecided sets have become small.  Waits for the recorded events. */
 int knn_prof_read(int32_t kind, double *total_ms, int64_t *launches, double *units);
@@ -286,7 +287,8 @@ int knn_prof_read(int32_t kind, double *total_ms, int64_t *launches, double *uni
  * adaptive sampling kernel, [1] (query, sample) pairs drawn, [2] exact-distance
  * (query, coordinate) pairs, [3] distinct coordinate draws (queries sharing a
  * seed share them), [4] float naive queries that fell back to an exact rescan,
- * [5..7] reserved.  host_out8: host, 8 entries.  Synchronises the device. */
+ * [5] distinct draws of shared coordinate sequences (one sequence serves a
+ * whole batch), [6..7] reserved.  host_out8: host, 8 entries.  Synchronises the device. */
 int knn_prof_counters(uint64_t *host_out8);
 
 #ifdef __cplusplus

@@ -982,39 +982,91 @@ __global__ __launch_bounds__(NT) void k_seq_coords(uint64_t seed, int32_t norepl
 // Rows at the sequence's coordinates, out[r][t] = row_r[js[t]] (as x - 128
 // for squared l2, raw bytes for l1; zero where js[t] is none): the points
 // (rows = n), or the running slots' queries (QUERIES, rows = nqp; idle
-// slots give zero rows).  One wave per row, sixteen bytes per lane and step.
-template <int MET, bool QUERIES>
+// slots give zero rows).  One wave per row: the row is read into the wave's
+// part of LDS with 4-byte loads (LDS: rows of mr = m rounded up to 16
+// bytes, when m is a multiple of 4 and four such rows fit), then each lane
+// gathers sixteen bytes per step from it; otherwise the bytes come from the
+// row in global memory.  The block's waves take rows together, so the
+// barriers around each row are uniform.
+template <int MET, bool QUERIES, bool STAGE>
 __global__ __launch_bounds__(NT) void k_seq_gather(const uint8_t *__restrict__ X, const Slot *__restrict__ slots,
                                                    int32_t ns, int64_t rows, int64_t m,
                                                    const uint32_t *__restrict__ js, int64_t kp,
                                                    int8_t *__restrict__ out) {
-  const int lane = lane_id();
-  const int64_t nw = (int64_t)gridDim.x * (NT / kWave);
-  for (int64_t r = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
+  extern __shared__ __align__(16) uint8_t srow[];
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  const int64_t mr = (m + 15) / 16 * 16;
+  uint8_t *my = srow + (STAGE ? wave * mr : 0);
+  // the coordinates as 16-bit values after the rows (m <= 65536; 0xFFFF: none)
+  uint16_t *jl = reinterpret_cast<uint16_t *>(srow + (STAGE ? 4 * mr : 0));
+  if constexpr (STAGE) {
+    for (int64_t t = threadIdx.x; t < kp; t += NT) jl[t] = js[t] == ~0u ? (uint16_t)0xFFFFu : (uint16_t)js[t];
+    __syncthreads();
+  }
+  for (int64_t base = (int64_t)blockIdx.x * (NT / kWave); base < rows; base += (int64_t)gridDim.x * (NT / kWave)) {
+    const int64_t r = base + wave;
     const uint8_t *row = nullptr;
-    if constexpr (QUERIES) {
-      if (r < ns && slots[r].state == 1) row = reinterpret_cast<const uint8_t *>(slots[r].q);
-    } else {
-      row = X + r * m;
-    }
-    for (int64_t t0 = 16 * (int64_t)lane; t0 < kp; t0 += 16 * kWave) {
-      const uint4 *jp = reinterpret_cast<const uint4 *>(js + t0);
-      uint32_t w[4];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const uint4 j = jp[d];
-        const uint32_t jj[4] = {j.x, j.y, j.z, j.w};
-        uint32_t word = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          uint32_t v = 0;
-          if (row && jj[e] != ~0u) v = MET == KNN_METRIC_L2 ? (uint32_t)(row[jj[e]] ^ 0x80u) : (uint32_t)row[jj[e]];
-          word |= v << (8 * e);
-        }
-        w[d] = word;
+    if (r < rows) {
+      if constexpr (QUERIES) {
+        if (r < ns && slots[r].state == 1) row = reinterpret_cast<const uint8_t *>(slots[r].q);
+      } else {
+        row = X + r * m;
       }
-      *reinterpret_cast<uint4 *>(out + r * kp + t0) = make_uint4(w[0], w[1], w[2], w[3]);
     }
+    if constexpr (STAGE) {
+      if (row && ((uintptr_t)row & 3u) == 0) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(row);
+        for (int64_t w = lane; w < m / 4; w += kWave) reinterpret_cast<uint32_t *>(my)[w] = src[w];
+      } else if (row) {  // (a query row need not be 4-byte aligned)
+        for (int64_t j = lane; j < m; j += kWave) my[j] = row[j];
+      }
+      __syncthreads();
+    }
+    const uint8_t *from = STAGE ? my : row;
+    if (r < rows) {
+      for (int64_t t0 = 16 * (int64_t)lane; t0 < kp; t0 += 16 * kWave) {
+        uint32_t jj[16];
+        if constexpr (STAGE) {
+          const uint4 *jp = reinterpret_cast<const uint4 *>(jl + t0);
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            const uint4 j = jp[d];
+            const uint32_t hw[4] = {j.x, j.y, j.z, j.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const uint32_t a = hw[e] & 0xFFFFu, b = hw[e] >> 16;
+              jj[8 * d + 2 * e] = a == 0xFFFFu ? ~0u : a;
+              jj[8 * d + 2 * e + 1] = b == 0xFFFFu ? ~0u : b;
+            }
+          }
+        } else {
+          const uint4 *jp = reinterpret_cast<const uint4 *>(js + t0);
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            const uint4 j = jp[d];
+            jj[4 * d] = j.x;
+            jj[4 * d + 1] = j.y;
+            jj[4 * d + 2] = j.z;
+            jj[4 * d + 3] = j.w;
+          }
+        }
+        uint32_t w[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          uint32_t word = 0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint32_t j = jj[4 * d + e];
+            uint32_t v = 0;
+            if (row && j != ~0u) v = MET == KNN_METRIC_L2 ? (uint32_t)(from[j] ^ 0x80u) : (uint32_t)from[j];
+            word |= v << (8 * e);
+          }
+          w[d] = word;
+        }
+        *reinterpret_cast<uint4 *>(out + r * kp + t0) = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+    if constexpr (STAGE) __syncthreads();  // the row buffer is refilled next
   }
 }
 
@@ -2707,21 +2759,32 @@ void launch_seq_prepare(const Slot *slots, const Sched *sc, int32_t ns, int32_t 
                         int64_t m, uint64_t seed, int32_t norepl, int32_t metric, const SeqBufs &q, hipStream_t st) {
   const unsigned cb = (unsigned)std::min<int64_t>((q.kp / 4 + NT - 1) / NT, 1024);
   hipLaunchKernelGGL(k_seq_coords, dim3(cb), dim3(NT), 0, st, seed, norepl, m, q.tlen, q.kp, q.js);
-  const unsigned gx = (unsigned)std::min<int64_t>((n + 3) / 4, 8192), gq = (unsigned)((nqp + 3) / 4);
+  const unsigned gx = (unsigned)std::min<int64_t>((n + 3) / 4, 2048), gq = (unsigned)((nqp + 3) / 4);
+  // rows staged in LDS (with the coordinates as 16-bit values) when m is a
+  // multiple of 4 and both fit in 64 KB
+  const int64_t mr = (m + 15) / 16 * 16;
+  const bool stage = m % 4 == 0 && m < 65536 && 4 * mr + 2 * q.kp <= 65536;
+  const size_t lds = stage ? (size_t)(4 * mr + 2 * q.kp) : 0;
+#define KNN_SEQ_GATHER(MET_, Q_, ROWS_, OUT_, GRID_)                                                              \
+  do {                                                                                                           \
+    if (stage)                                                                                                   \
+      hipLaunchKernelGGL((k_seq_gather<MET_, Q_, true>), dim3(GRID_), dim3(NT), lds, st, X, slots, ns, ROWS_, m, \
+                         q.js, q.kp, OUT_);                                                                      \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_seq_gather<MET_, Q_, false>), dim3(GRID_), dim3(NT), 0, st, X, slots, ns, ROWS_, m,  \
+                         q.js, q.kp, OUT_);                                                                      \
+  } while (0)
   if (metric == KNN_METRIC_L1) {
-    hipLaunchKernelGGL((k_seq_gather<KNN_METRIC_L1, false>), dim3(gx), dim3(NT), 0, st, X, slots, ns, n, m, q.js,
-                       q.kp, q.xs);
-    hipLaunchKernelGGL((k_seq_gather<KNN_METRIC_L1, true>), dim3(gq), dim3(NT), 0, st, X, slots, ns, (int64_t)nqp, m,
-                       q.js, q.kp, q.qs);
+    KNN_SEQ_GATHER(KNN_METRIC_L1, false, n, q.xs, gx);
+    KNN_SEQ_GATHER(KNN_METRIC_L1, true, (int64_t)nqp, q.qs, gq);
   } else {
-    hipLaunchKernelGGL((k_seq_gather<KNN_METRIC_L2, false>), dim3(gx), dim3(NT), 0, st, X, slots, ns, n, m, q.js,
-                       q.kp, q.xs);
-    hipLaunchKernelGGL((k_seq_gather<KNN_METRIC_L2, true>), dim3(gq), dim3(NT), 0, st, X, slots, ns, (int64_t)nqp, m,
-                       q.js, q.kp, q.qs);
+    KNN_SEQ_GATHER(KNN_METRIC_L2, false, n, q.xs, gx);
+    KNN_SEQ_GATHER(KNN_METRIC_L2, true, (int64_t)nqp, q.qs, gq);
     hipLaunchKernelGGL(k_seq_norms, dim3(gx), dim3(NT), 0, st, q.xs, n, q.kp, sc, q.nb, m, q.xn, n);
     hipLaunchKernelGGL(k_seq_norms, dim3(gq), dim3(NT), 0, st, q.qs, (int64_t)nqp, q.kp, sc, q.nb, m, q.qn,
                        (int64_t)nqp);
   }
+#undef KNN_SEQ_GATHER
 }
 
 // Point blocks of a query-lane sampling launch (each walks a contiguous

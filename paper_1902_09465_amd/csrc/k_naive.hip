@@ -699,6 +699,38 @@ __global__ __launch_bounds__(256) void k_round_seq_u8(const Slot *__restrict__ s
   const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
   // the round sums through LDS as [point][query] rows (the K loop ended with a barrier)
   uint32_t *T = reinterpret_cast<uint32_t *>(smem);
+  uint64_t my_pairs = 0;
+  if (exact) {
+    // pairs made exact: the undecided sampled ones (flag 0), marked here in
+    // the fragment layout (sixteen consecutive points of one query per lane
+    // group), all flag loads of a fragment row in flight together
+#pragma unroll
+    for (int a = 0; a < XWA; ++a) {
+      uint8_t fv[4][4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ql = 16 * XWA * wq + 16 * a + 4 * (lane >> 4) + v;
+        const int64_t s = q0 + ql;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
+          fv[v][b] = (take[ql] && i < n) ? (impl ? (uint8_t)0 : B.fl[s * n + i]) : (uint8_t)1;
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t s = q0 + 16 * XWA * wq + 16 * a + 4 * (lane >> 4) + v;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if (fv[v][b] != 0) continue;
+          const int64_t off = s * n + p0 + 64 * wp + 16 * b + (lane & 15);
+          B.fl[off] = FL_EXACT;
+          B.ri[off] = impl ? (uint8_t)0 : (uint8_t)(cur - 1);
+          ++my_pairs;
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int a = 0; a < XWA; ++a)
 #pragma unroll
@@ -725,7 +757,8 @@ __global__ __launch_bounds__(256) void k_round_seq_u8(const Slot *__restrict__ s
     }
   __syncthreads();
   // 16-byte pieces of D: four queries of one point (nqp is a multiple of 16)
-  uint64_t my_pairs = 0;
+  // (loading them before the K loop measured slower: the registers cost
+  // half the waves)
   constexpr int PIECES = NBP * XQ / 4;
   for (int e = threadIdx.x; e < PIECES; e += 256) {
     const int pl = e / (XQ / 4), qc = 4 * (e % (XQ / 4));
@@ -743,14 +776,7 @@ __global__ __launch_bounds__(256) void k_round_seq_u8(const Slot *__restrict__ s
     for (int u = 0; u < 4; ++u) {
       const bool sampled = ((tk >> (8 * u)) & 1u) != 0 && ((a4 >> (8 * u)) & 255u) == 0;
       nw[u] = sampled ? oo[u] + vv[u] : oo[u];
-      if (sampled) {
-        ++my_pairs;
-        if (exact) {
-          const int64_t off = (s + u) * n + i;
-          B.fl[off] = FL_EXACT;
-          B.ri[off] = impl ? (uint8_t)0 : (uint8_t)(cur - 1);
-        }
-      }
+      if (sampled && !exact) ++my_pairs;
     }
     *reinterpret_cast<uint4 *>(dst) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
   }

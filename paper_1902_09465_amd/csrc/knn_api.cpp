@@ -383,9 +383,13 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   // one coordinate sequence for every point: the points and queries gathered
   // at its coordinates once, then every round is a range of their columns
   const bool seq = E.seq.xs && E.G.flagsets;
-  if (seq)
+  if (seq) {
+    const int tk = prof_begin(PROF_QL_AUX, st);
     launch_seq_prepare(E.slots, E.sched, (int32_t)E.ns, E.nqp, db->X, n, m, P.qd[0].seed, P.qd[0].norepl,
                        db->metric, E.seq, st);
+    prof_end(tk, st, 0.0);
+    prof_add_host(1, (uint64_t)E.seq.tlen);  // its distinct draws: one sequence for the whole batch
+  }
   // long rounds of grouped sampling read whole point rows into LDS
   const int stage_rows = E.G.grouped ? stage_rows_for(m, db->mp, K.stage_rows) : 0;
   for (int t = 0; t < P.rmax + 1; ++t) {

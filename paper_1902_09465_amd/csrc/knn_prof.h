@@ -17,7 +17,8 @@ enum ProfKind {
   PROF_NAIVE_GEMM = 5, // naive MFMA scan with fused top-k
   PROF_NAIVE_REST = 6, // naive query prep + merge (+ f32 rescoring)
   PROF_EXACT = 7,      // k_sample launches of a lock-step batch's exact round
-  PROF_QL_AUX = 8,     // query-lane sampling: flag transpose + fold of the round totals
+  PROF_QL_AUX = 8,     // query-lane sampling: flag transpose + fold of the round totals; or the
+                       // gather of a shared coordinate sequence
   PROF_SPARSE = 9,     // point-major batches: per-slot sampling / exact sums of their sparse slots
   PROF_KINDS = 10
 };
