@@ -16,7 +16,7 @@ import numpy as np
 
 __all__ = [
     "rng", "tiny", "gmm_u8", "gmm_f32", "uniform_u8", "uneven", "antipodal",
-    "subspace", "pm_half", "coherent", "gap_family", "planted_corners", "serving_dbs", "CONFIGS",
+    "subspace", "pm_half", "coherent", "gap_family", "planted_corners", "easy_corners", "serving_dbs", "CONFIGS",
 ]
 
 
@@ -109,6 +109,27 @@ def uneven(seed: int = 4000, n: int = 250_000, m: int = 1024, nq: int = 4096,
             pos += 1
     Q[n_easy:] = 127 + g.integers(0, 2, size=(nq - n_easy, m), dtype=np.uint8)
     return X, Q, kq
+
+
+def easy_corners(seed: int, n: int, m: int, nq: int, k: int = 10, noise: int = 8, chunk: int = 8192):
+    """The easy half of the uneven workload on its own: bulk points are random
+    corners of {0,255}^m; each of the nq queries is a random corner that owns
+    k planted points (the corner moved inwards by integer noise in
+    [0, noise]) at random indices.  Returns (X, Q)."""
+    g = rng(seed)
+    if nq * k > n:
+        raise ValueError("database too small for the planted points")
+    X = np.empty((n, m), dtype=np.uint8)
+    for s0 in range(0, n, chunk):
+        e = min(n, s0 + chunk)
+        X[s0:e] = g.integers(0, 2, size=(e - s0, m), dtype=np.uint8) * np.uint8(255)
+    Q = g.integers(0, 2, size=(nq, m), dtype=np.uint8) * np.uint8(255)
+    slots = g.permutation(n)[:nq * k]
+    for qi in range(nq):
+        d = g.integers(0, noise + 1, size=(k, m)).astype(np.int16)
+        c = Q[qi].astype(np.int16)[None, :]
+        X[slots[qi * k:(qi + 1) * k]] = np.where(c == 255, 255 - d, d).astype(np.uint8)
+    return X, Q
 
 
 def antipodal(seed: int = 7, n: int = 1000, m: int = 1024, copies: int = 5):

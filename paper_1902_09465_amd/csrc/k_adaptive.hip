@@ -982,92 +982,138 @@ __global__ __launch_bounds__(NT) void k_seq_coords(uint64_t seed, int32_t norepl
 // Rows at the sequence's coordinates, out[r][t] = row_r[js[t]] (as x - 128
 // for squared l2, raw bytes for l1; zero where js[t] is none): the points
 // (rows = n), or the running slots' queries (QUERIES, rows = nqp; idle
-// slots give zero rows).  One wave per row: the row is read into the wave's
-// part of LDS with 4-byte loads (LDS: rows of mr = m rounded up to 16
-// bytes, when m is a multiple of 4 and four such rows fit), then each lane
-// gathers sixteen bytes per step from it; otherwise the bytes come from the
-// row in global memory.  The block's waves take rows together, so the
-// barriers around each row are uniform.
+// slots give zero rows).  One row per block at a time: with STAGE the row
+// is read into LDS by the whole block (16-, 4- or 1-byte loads as its
+// alignment allows) and the coordinates are kept in LDS as 16-bit values
+// (m < 65536; 0xFFFF: none); each thread then gathers sixteen bytes per
+// step.  Without STAGE the bytes come from the row in global memory.
 template <int MET, bool QUERIES, bool STAGE>
 __global__ __launch_bounds__(NT) void k_seq_gather(const uint8_t *__restrict__ X, const Slot *__restrict__ slots,
                                                    int32_t ns, int64_t rows, int64_t m,
                                                    const uint32_t *__restrict__ js, int64_t kp,
                                                    int8_t *__restrict__ out) {
   extern __shared__ __align__(16) uint8_t srow[];
-  const int lane = lane_id(), wave = threadIdx.x / kWave;
   const int64_t mr = (m + 15) / 16 * 16;
-  uint8_t *my = srow + (STAGE ? wave * mr : 0);
-  // the coordinates as 16-bit values after the rows (m <= 65536; 0xFFFF: none)
-  uint16_t *jl = reinterpret_cast<uint16_t *>(srow + (STAGE ? 4 * mr : 0));
+  uint16_t *jl = reinterpret_cast<uint16_t *>(srow + (STAGE ? mr : 0));
   if constexpr (STAGE) {
     for (int64_t t = threadIdx.x; t < kp; t += NT) jl[t] = js[t] == ~0u ? (uint16_t)0xFFFFu : (uint16_t)js[t];
     __syncthreads();
   }
-  for (int64_t base = (int64_t)blockIdx.x * (NT / kWave); base < rows; base += (int64_t)gridDim.x * (NT / kWave)) {
-    const int64_t r = base + wave;
-    const uint8_t *row = nullptr;
-    if (r < rows) {
-      if constexpr (QUERIES) {
-        if (r < ns && slots[r].state == 1) row = reinterpret_cast<const uint8_t *>(slots[r].q);
-      } else {
-        row = X + r * m;
-      }
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const uint8_t *row = nullptr;  // (block-uniform)
+    if constexpr (QUERIES) {
+      if (r < ns && slots[r].state == 1) row = reinterpret_cast<const uint8_t *>(slots[r].q);
+    } else {
+      row = X + r * m;
     }
     if constexpr (STAGE) {
-      if (row && ((uintptr_t)row & 3u) == 0) {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(row);
-        for (int64_t w = lane; w < m / 4; w += kWave) reinterpret_cast<uint32_t *>(my)[w] = src[w];
-      } else if (row) {  // (a query row need not be 4-byte aligned)
-        for (int64_t j = lane; j < m; j += kWave) my[j] = row[j];
+      if (row) {
+        const uintptr_t al = (uintptr_t)row;
+        if ((m & 15) == 0 && (al & 15) == 0) {
+          for (int64_t w = threadIdx.x; w < m / 16; w += NT)
+            reinterpret_cast<uint4 *>(srow)[w] = reinterpret_cast<const uint4 *>(row)[w];
+        } else if ((m & 3) == 0 && (al & 3) == 0) {
+          for (int64_t w = threadIdx.x; w < m / 4; w += NT)
+            reinterpret_cast<uint32_t *>(srow)[w] = reinterpret_cast<const uint32_t *>(row)[w];
+        } else {
+          for (int64_t j = threadIdx.x; j < m; j += NT) srow[j] = row[j];
+        }
       }
       __syncthreads();
     }
-    const uint8_t *from = STAGE ? my : row;
-    if (r < rows) {
-      for (int64_t t0 = 16 * (int64_t)lane; t0 < kp; t0 += 16 * kWave) {
-        uint32_t jj[16];
-        if constexpr (STAGE) {
-          const uint4 *jp = reinterpret_cast<const uint4 *>(jl + t0);
+    const uint8_t *from = STAGE ? srow : row;
+    for (int64_t t0 = 16 * (int64_t)threadIdx.x; t0 < kp; t0 += 16 * NT) {
+      uint32_t jj[16];
+      if constexpr (STAGE) {
+        const uint4 *jp = reinterpret_cast<const uint4 *>(jl + t0);
 #pragma unroll
-          for (int d = 0; d < 2; ++d) {
-            const uint4 j = jp[d];
-            const uint32_t hw[4] = {j.x, j.y, j.z, j.w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const uint32_t a = hw[e] & 0xFFFFu, b = hw[e] >> 16;
-              jj[8 * d + 2 * e] = a == 0xFFFFu ? ~0u : a;
-              jj[8 * d + 2 * e + 1] = b == 0xFFFFu ? ~0u : b;
-            }
-          }
-        } else {
-          const uint4 *jp = reinterpret_cast<const uint4 *>(js + t0);
-#pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            const uint4 j = jp[d];
-            jj[4 * d] = j.x;
-            jj[4 * d + 1] = j.y;
-            jj[4 * d + 2] = j.z;
-            jj[4 * d + 3] = j.w;
-          }
-        }
-        uint32_t w[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          uint32_t word = 0;
+        for (int d = 0; d < 2; ++d) {
+          const uint4 j = jp[d];
+          const uint32_t hw[4] = {j.x, j.y, j.z, j.w};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const uint32_t j = jj[4 * d + e];
-            uint32_t v = 0;
-            if (row && j != ~0u) v = MET == KNN_METRIC_L2 ? (uint32_t)(from[j] ^ 0x80u) : (uint32_t)from[j];
-            word |= v << (8 * e);
+            const uint32_t lo = hw[e] & 0xFFFFu, hi = hw[e] >> 16;
+            jj[8 * d + 2 * e] = lo == 0xFFFFu ? ~0u : lo;
+            jj[8 * d + 2 * e + 1] = hi == 0xFFFFu ? ~0u : hi;
           }
-          w[d] = word;
         }
-        *reinterpret_cast<uint4 *>(out + r * kp + t0) = make_uint4(w[0], w[1], w[2], w[3]);
+      } else {
+        const uint4 *jp = reinterpret_cast<const uint4 *>(js + t0);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const uint4 j = jp[d];
+          jj[4 * d] = j.x;
+          jj[4 * d + 1] = j.y;
+          jj[4 * d + 2] = j.z;
+          jj[4 * d + 3] = j.w;
+        }
       }
+      uint32_t w[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t j = jj[4 * d + e];
+          uint32_t v = 0;
+          if (row && j != ~0u) v = MET == KNN_METRIC_L2 ? (uint32_t)(from[j] ^ 0x80u) : (uint32_t)from[j];
+          word |= v << (8 * e);
+        }
+        w[d] = word;
+      }
+      *reinterpret_cast<uint4 *>(out + r * kp + t0) = make_uint4(w[0], w[1], w[2], w[3]);
     }
     if constexpr (STAGE) __syncthreads();  // the row buffer is refilled next
   }
+}
+
+// Sampled rounds of the sparse slots of a point-major batch whose queries
+// share one coordinate sequence: the samples [t0, t1) of pair (s, i) are
+// columns t0..t1-1 of the gathered rows XS[i] and QS[s], so the round sum is
+// a contiguous sum over those bytes (no draws).  Lanes per point: enough
+// for one 4-byte word per lane and step, up to a whole wave.  The sums go
+// to the slot-major running sums, like k_sample's.
+template <int MET>
+__global__ __launch_bounds__(NT) void k_sample_seq_sparse(const Slot *__restrict__ slots, SeqBufs q, Bufs B,
+                                                          Geometry G) {
+  const int s = blockIdx.x;
+  const Slot *sl = &slots[s];
+  if (sl->state != 1 || sl->implicit != 0) return;  // dense slots run the tiled round
+  const int cur = sl->cur;
+  if (cur >= sl->R) return;  // the exact round takes the per-slot exact pass
+  const int64_t n = G.n;
+  const SlotArrays a = slot_arrays(B, n, s, sl->par);
+  const int64_t nlist = sl->n_act;
+  const int64_t w0 = (cur ? (int64_t)sl->T[cur - 1] : 0) / 4, w1 = (int64_t)sl->T[cur] / 4;
+  const int64_t words = w1 - w0;
+  const int lpp = words <= 16 ? 16 : (words <= 32 ? 32 : kWave);
+  const int sub = threadIdx.x % lpp;
+  const uint32_t *qrow = reinterpret_cast<const uint32_t *>(q.qs + (int64_t)s * q.kp);
+  uint64_t my_pts = 0;
+  for (int64_t c = blockIdx.y; c * G.ch_sample < nlist; c += gridDim.y) {
+    const int64_t base = c * G.ch_sample, end = min(nlist, base + (int64_t)G.ch_sample);
+    for (int64_t p = base + threadIdx.x / lpp; p < end; p += NT / lpp) {
+      const int32_t i = a.act[p];
+      const uint32_t *xrow = reinterpret_cast<const uint32_t *>(q.xs + (int64_t)i * q.kp);
+      uint32_t acc = 0;  // below 2^32: at most m < 65536 samples of at most 255^2
+      for (int64_t w = w0 + sub; w < w1; w += lpp) {
+        if constexpr (MET == KNN_METRIC_L1) {
+          acc = __builtin_amdgcn_sad_u8(xrow[w], qrow[w], acc);
+        } else {
+          const uint32_t xu = xrow[w] ^ 0x80808080u, qu = qrow[w] ^ 0x80808080u;  // back to unsigned bytes
+          acc += __builtin_amdgcn_udot4(xu, xu, 0u, false) + __builtin_amdgcn_udot4(qu, qu, 0u, false) -
+                 2u * __builtin_amdgcn_udot4(xu, qu, 0u, false);
+        }
+      }
+      for (int o = lpp / 2; o > 0; o >>= 1) acc += (uint32_t)__shfl_xor((int)acc, o);
+      if (sub == 0) {
+        a.S[i] += (int64_t)acc;
+        a.ri[i] = (uint8_t)cur;
+        ++my_pts;
+      }
+    }
+  }
+  if (G.prof && my_pts) atomicAdd(&prof_copy(G.prof)[1], my_pts * (uint64_t)(4 * words));
 }
 
 // Squared norms of gathered rows (x - 128 bytes) over the samples before
@@ -2374,6 +2420,9 @@ __device__ void write_trivial(const QDesc &qd, int64_t n) {
 // sums and round indices are copied into the slot-major arrays that the
 // list kernels read (with `all`, the sums of the discarded points too, so
 // the slot-major state is whole).
+// all: for a slot that turns sparse (every undecided point listed, the
+// sums copied by k_pm_to_slot afterwards); otherwise the kept points' sums
+// are copied here (a finishing slot).
 __device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry &G, bool all = false) {
   const int64_t n = G.n;
   const SlotArrays a = slot_arrays(B, n, s, sl->par);
@@ -2432,7 +2481,7 @@ __device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry 
         dst[pos[c]++] = (int32_t)i;
         if (c == 0 && G.flagsets) a.ri[i] = (uint8_t)sl->cur;
       }
-      if (G.flagsets && i < n && (c >= 0 || all)) a.S[i] = (int64_t)B.dpm[i * B.dpm_stride + s];
+      if (G.flagsets && i < n && c >= 0 && !all) a.S[i] = (int64_t)B.dpm[i * B.dpm_stride + s];
     }
   }
   __syncthreads();
@@ -2441,8 +2490,47 @@ __device__ void lists_from_flags(Slot *sl, int s, const Bufs &B, const Geometry 
     sl->n_xa = run[1];
     sl->n_acc = run[2];
     sl->implicit = 0;
+    if (all && G.flagsets) sl->pm_copy = 1;
   }
   __syncthreads();
+}
+
+// The step's slots that turned sparse (pm_copy) take their running sums
+// slot-major: S[s][i] = D[i][s] for every point, 64 x 64 tiles transposed
+// through LDS so that the point-major reads and slot-major writes are both
+// coalesced.  Tiles whose 64 slots have nothing to copy leave at once.
+__global__ __launch_bounds__(NT) void k_pm_to_slot(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
+                                                   int32_t nqp, Bufs B, Geometry G) {
+  __shared__ uint32_t t[FT][FT + 1];
+  __shared__ uint8_t cp[FT];
+  __shared__ int any;
+  const int64_t n = G.n;
+  const int ns = G.nslots;
+  const int s0 = (int)blockIdx.y * FT;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  if (threadIdx.x < FT) {
+    const int sl = s0 + threadIdx.x;
+    cp[threadIdx.x] = (sl < ns && slots[sl].pm_copy) ? 1 : 0;
+    if (cp[threadIdx.x]) any = 1;
+  }
+  __syncthreads();
+  if (!any) return;
+  const int c = threadIdx.x % FT, r0 = threadIdx.x / FT;
+  for (int64_t i0 = (int64_t)blockIdx.x * FT; i0 < n; i0 += (int64_t)gridDim.x * FT) {
+    for (int r = r0; r < FT; r += NT / FT) {
+      const int64_t i = i0 + r;
+      const int sl = s0 + c;
+      t[r][c] = (i < n && sl < nqp) ? D[i * nqp + sl] : 0u;
+    }
+    __syncthreads();
+    for (int r = r0; r < FT; r += NT / FT) {
+      const int sl = s0 + r;
+      const int64_t i = i0 + c;
+      if (sl < ns && i < n && cp[r]) B.S[(int64_t)sl * n + i] = (int64_t)t[c][r];
+    }
+    __syncthreads();
+  }
 }
 
 template <int DT>
@@ -2601,6 +2689,7 @@ __device__ void admit(Slot *sl, const QDesc *qd, const Sched *sched, Ctl *ctl, i
     sl->W = d.W;
     sl->q = d.q;
     sl->rounds = 0;
+    sl->pm_copy = 0;
     sl->coord_evals = sc.R == 0 ? n * m : n * (int64_t)sc.T[0];
     sl->exact_points = sc.R == 0 ? n : 0;
     sl->state = 1;
@@ -2617,6 +2706,7 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
   const int64_t n = G.n, m = G.m;
   if (sl->state == 1 && !admit_only) {
     const bool dense = G.flagsets && sl->implicit != 0;  // (uniform over the block)
+    if (threadIdx.x == 0) sl->pm_copy = 0;  // (copied after the previous step's k_finish)
     if (dense) {
       // this round's counts, one record per point tile of k_decide_pm
       const int64_t nt = (n + DQ_PT - 1) / DQ_PT;
@@ -2755,24 +2845,30 @@ void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint
   hipLaunchKernelGGL(k_build_qt, dim3(blocks), dim3(NT), 0, st, slots, ns, m, nqp, qt);
 }
 
+constexpr size_t kSeqGatherLds = 160 * 1024 - 4096;  // dynamic LDS a gather block may take
+
 void launch_seq_prepare(const Slot *slots, const Sched *sc, int32_t ns, int32_t nqp, const uint8_t *X, int64_t n,
                         int64_t m, uint64_t seed, int32_t norepl, int32_t metric, const SeqBufs &q, hipStream_t st) {
   const unsigned cb = (unsigned)std::min<int64_t>((q.kp / 4 + NT - 1) / NT, 1024);
   hipLaunchKernelGGL(k_seq_coords, dim3(cb), dim3(NT), 0, st, seed, norepl, m, q.tlen, q.kp, q.js);
-  const unsigned gx = (unsigned)std::min<int64_t>((n + 3) / 4, 2048), gq = (unsigned)((nqp + 3) / 4);
-  // rows staged in LDS (with the coordinates as 16-bit values) when m is a
-  // multiple of 4 and both fit in 64 KB
+  const unsigned gx = (unsigned)std::min<int64_t>(n, 8192), gq = (unsigned)nqp;
+  // rows staged in LDS, with the coordinates as 16-bit values (m < 65536),
+  // when both fit in the LDS a block may take
   const int64_t mr = (m + 15) / 16 * 16;
-  const bool stage = m % 4 == 0 && m < 65536 && 4 * mr + 2 * q.kp <= 65536;
-  const size_t lds = stage ? (size_t)(4 * mr + 2 * q.kp) : 0;
+  const size_t lds = (size_t)(mr + 2 * q.kp);
+  const bool stage = m < 65536 && lds <= kSeqGatherLds;
 #define KNN_SEQ_GATHER(MET_, Q_, ROWS_, OUT_, GRID_)                                                              \
   do {                                                                                                           \
-    if (stage)                                                                                                   \
+    if (stage) {                                                                                                 \
+      if (lds > 65536)                                                                                           \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_seq_gather<MET_, Q_, true>),                 \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSeqGatherLds);              \
       hipLaunchKernelGGL((k_seq_gather<MET_, Q_, true>), dim3(GRID_), dim3(NT), lds, st, X, slots, ns, ROWS_, m, \
                          q.js, q.kp, OUT_);                                                                      \
-    else                                                                                                         \
+    } else {                                                                                                     \
       hipLaunchKernelGGL((k_seq_gather<MET_, Q_, false>), dim3(GRID_), dim3(NT), 0, st, X, slots, ns, ROWS_, m,  \
                          q.js, q.kp, OUT_);                                                                      \
+    }                                                                                                            \
   } while (0)
   if (metric == KNN_METRIC_L1) {
     KNN_SEQ_GATHER(KNN_METRIC_L1, false, n, q.xs, gx);
@@ -2847,7 +2943,16 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     // exact sums in the exact round); the kernel skips the dense slots
     const int64_t sparse_list = sparse_list_len(G);
     int tk = prof_begin(PROF_SPARSE, st);
-    launch_sample_met<KNN_U8>(slots, X, B, G, qlds, qbytes, st, sparse_list);
+    if (seq && seq->xs && !ql->exact) {
+      // shared sequence: the sparse slots' samples are columns of the gathered rows
+      const dim3 grid(ns, (unsigned)std::max<int64_t>(1, (sparse_list + G.ch_sample - 1) / G.ch_sample));
+      if (G.metric == KNN_METRIC_L1)
+        hipLaunchKernelGGL(k_sample_seq_sparse<KNN_METRIC_L1>, grid, dim3(NT), 0, st, slots, *seq, B, G);
+      else
+        hipLaunchKernelGGL(k_sample_seq_sparse<KNN_METRIC_L2>, grid, dim3(NT), 0, st, slots, *seq, B, G);
+    } else {
+      launch_sample_met<KNN_U8>(slots, X, B, G, qlds, qbytes, st, sparse_list);
+    }
     prof_end(tk, st, 0.0);
     tk = prof_begin(PROF_SELECT, st);
     const int64_t nsel = ((G.n + FS_PT - 1) / FS_PT) * ((nqp + FS_SL - 1) / FS_SL);
@@ -2870,6 +2975,9 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     tk = prof_begin(PROF_FINISH, st);
     if (G.dtype == KNN_U8)
       hipLaunchKernelGGL(k_finish<KNN_U8>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, 0);
+    // slots that turned sparse in this step: their sums, slot-major
+    const dim3 ct((unsigned)std::min<int64_t>((G.n + FT - 1) / FT, 128), (unsigned)((nqp + FT - 1) / FT));
+    hipLaunchKernelGGL(k_pm_to_slot, ct, dim3(NT), 0, st, slots, qd_buf, nqp, B, G);
     prof_end(tk, st, 0.0);
     return;
   }

@@ -559,12 +559,18 @@ __global__ __launch_bounds__(256) void k_exact_ql_u8(const Slot *__restrict__ sl
   const int64_t pend = std::min(n, p0 + NBP);
   // which of the tile's slots take this pass (read once, before the K loop)
   __shared__ uint8_t take[XQ];
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
   if (threadIdx.x < XQ) {
     const int64_t s = q0 + threadIdx.x;
     bool t = s < ns && slots[s].state == 1 && slots[s].cur == cur;
     if (t && G.flagsets && slots[s].implicit == 0) t = false;  // a sparse slot: its own exact pass
     take[threadIdx.x] = t ? 1 : 0;
+    if (t) any = 1;
   }
+  __syncthreads();
+  if (!any) return;  // (block-uniform) no slot of this query tile takes the pass
   v4i acc[XWA][4];
   gemm_u8_tile<MET, PF, BK_EXACT, XWA>(Q8, (int64_t)ns, X8, q0, p0, pend, mp, smem, acc);  // (its barriers publish take[])
   const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;

@@ -67,7 +67,9 @@ struct Slot {
                         // round (S > sthr[0] discard, else S <= sthr[1] accept for a sampled
                         // pair; sthr[2], sthr[3] for an exact pair), set with U, L1, L2
   int64_t coord_evals, exact_points;
-  int32_t rounds, pad1;
+  int32_t rounds;
+  int32_t pm_copy;      // point-major batches: 1 in the step where the slot turned sparse (its sums
+                        // are then copied slot-major by k_pm_to_slot after k_finish)
   int32_t T[kMaxRounds];
   double alpha[kMaxRounds];
 };
