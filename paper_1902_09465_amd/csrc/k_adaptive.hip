@@ -1073,6 +1073,8 @@ __global__ __launch_bounds__(NT) void k_seq_gather(const uint8_t *__restrict__ X
 // a contiguous sum over those bytes (no draws).  Lanes per point: enough
 // for one 4-byte word per lane and step, up to a whole wave.  The sums go
 // to the slot-major running sums, like k_sample's.
+constexpr int SEQ_SP = 64;  // list entries per block of k_sample_seq_sparse
+
 template <int MET>
 __global__ __launch_bounds__(NT) void k_sample_seq_sparse(const Slot *__restrict__ slots, SeqBufs q, Bufs B,
                                                           Geometry G) {
@@ -1090,8 +1092,8 @@ __global__ __launch_bounds__(NT) void k_sample_seq_sparse(const Slot *__restrict
   const int sub = threadIdx.x % lpp;
   const uint32_t *qrow = reinterpret_cast<const uint32_t *>(q.qs + (int64_t)s * q.kp);
   uint64_t my_pts = 0;
-  for (int64_t c = blockIdx.y; c * G.ch_sample < nlist; c += gridDim.y) {
-    const int64_t base = c * G.ch_sample, end = min(nlist, base + (int64_t)G.ch_sample);
+  for (int64_t c = blockIdx.y; c * SEQ_SP < nlist; c += gridDim.y) {
+    const int64_t base = c * SEQ_SP, end = min(nlist, base + (int64_t)SEQ_SP);
     for (int64_t p = base + threadIdx.x / lpp; p < end; p += NT / lpp) {
       const int32_t i = a.act[p];
       const uint32_t *xrow = reinterpret_cast<const uint32_t *>(q.xs + (int64_t)i * q.kp);
@@ -1118,10 +1120,13 @@ __global__ __launch_bounds__(NT) void k_sample_seq_sparse(const Slot *__restrict
 
 // Squared norms of gathered rows (x - 128 bytes) over the samples before
 // each boundary: out[b * ostride + r] = sum_{t < T'_b} S[r][t]^2 for b < nb.
-// One wave per row.
+// The boundary T'_{R+1} = m (sampling without replacement) is the full-row
+// norm, copied from `full` (the points' or queries' norms of the naive
+// scan) instead of summed.  One wave per row.
 __global__ __launch_bounds__(NT) void k_seq_norms(const int8_t *__restrict__ S, int64_t rows, int64_t kp,
                                                   const Sched *__restrict__ sc, int32_t nb, int64_t m,
-                                                  int32_t *__restrict__ out, int64_t ostride) {
+                                                  const int32_t *__restrict__ full, int32_t *__restrict__ out,
+                                                  int64_t ostride) {
   const int lane = lane_id();
   const int64_t nw = (int64_t)gridDim.x * (NT / kWave);
   for (int64_t r = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
@@ -1129,6 +1134,10 @@ __global__ __launch_bounds__(NT) void k_seq_norms(const int8_t *__restrict__ S, 
     int32_t run = 0;
     if (lane == 0) out[r] = 0;
     for (int b = 1; b < nb; ++b) {
+      if (b == sc->R + 1) {  // all m coordinates
+        if (lane == 0) out[(int64_t)b * ostride + r] = full[r];
+        continue;
+      }
       // words of samples [T'_{b-1}, T'_b): T'_{b-1} is a multiple of 4, and
       // bytes past the last sample are zero
       const int64_t w0 = seq_boundary(sc, b - 1, m) / 4, w1 = (seq_boundary(sc, b, m) + 3) / 4;
@@ -2848,7 +2857,8 @@ void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint
 constexpr size_t kSeqGatherLds = 160 * 1024 - 4096;  // dynamic LDS a gather block may take
 
 void launch_seq_prepare(const Slot *slots, const Sched *sc, int32_t ns, int32_t nqp, const uint8_t *X, int64_t n,
-                        int64_t m, uint64_t seed, int32_t norepl, int32_t metric, const SeqBufs &q, hipStream_t st) {
+                        int64_t m, uint64_t seed, int32_t norepl, int32_t metric, const SeqBufs &q,
+                        const int32_t *xnorm, const int32_t *qnorm, hipStream_t st) {
   const unsigned cb = (unsigned)std::min<int64_t>((q.kp / 4 + NT - 1) / NT, 1024);
   hipLaunchKernelGGL(k_seq_coords, dim3(cb), dim3(NT), 0, st, seed, norepl, m, q.tlen, q.kp, q.js);
   const unsigned gx = (unsigned)std::min<int64_t>(n, 8192), gq = (unsigned)nqp;
@@ -2876,8 +2886,8 @@ void launch_seq_prepare(const Slot *slots, const Sched *sc, int32_t ns, int32_t 
   } else {
     KNN_SEQ_GATHER(KNN_METRIC_L2, false, n, q.xs, gx);
     KNN_SEQ_GATHER(KNN_METRIC_L2, true, (int64_t)nqp, q.qs, gq);
-    hipLaunchKernelGGL(k_seq_norms, dim3(gx), dim3(NT), 0, st, q.xs, n, q.kp, sc, q.nb, m, q.xn, n);
-    hipLaunchKernelGGL(k_seq_norms, dim3(gq), dim3(NT), 0, st, q.qs, (int64_t)nqp, q.kp, sc, q.nb, m, q.qn,
+    hipLaunchKernelGGL(k_seq_norms, dim3(gx), dim3(NT), 0, st, q.xs, n, q.kp, sc, q.nb, m, xnorm, q.xn, n);
+    hipLaunchKernelGGL(k_seq_norms, dim3(gq), dim3(NT), 0, st, q.qs, (int64_t)nqp, q.kp, sc, q.nb, m, qnorm, q.qn,
                        (int64_t)nqp);
   }
 #undef KNN_SEQ_GATHER
@@ -2945,7 +2955,7 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     int tk = prof_begin(PROF_SPARSE, st);
     if (seq && seq->xs && !ql->exact) {
       // shared sequence: the sparse slots' samples are columns of the gathered rows
-      const dim3 grid(ns, (unsigned)std::max<int64_t>(1, (sparse_list + G.ch_sample - 1) / G.ch_sample));
+      const dim3 grid(ns, (unsigned)std::max<int64_t>(1, std::min<int64_t>((sparse_list + SEQ_SP - 1) / SEQ_SP, 256)));
       if (G.metric == KNN_METRIC_L1)
         hipLaunchKernelGGL(k_sample_seq_sparse<KNN_METRIC_L1>, grid, dim3(NT), 0, st, slots, *seq, B, G);
       else

@@ -386,7 +386,7 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   if (seq) {
     const int tk = prof_begin(PROF_QL_AUX, st);
     launch_seq_prepare(E.slots, E.sched, (int32_t)E.ns, E.nqp, db->X, n, m, P.qd[0].seed, P.qd[0].norepl,
-                       db->metric, E.seq, st);
+                       db->metric, E.seq, db->norm_i, E.q8n, st);
     prof_end(tk, st, 0.0);
     prof_add_host(1, (uint64_t)E.seq.tlen);  // its distinct draws: one sequence for the whole batch
   }
