@@ -236,13 +236,20 @@ int knn_naive_noalloc(knn_db db, const void *dev_queries, int64_t nq, int32_t k,
 
 /* ----------------------------------------------------------- session --- */
 
-/* Serving session: resident DBs, a background loop that admits submitted
- * queries while their state fits hbm_budget_bytes, and runs admitted
- * queries of different k and delta together (continuous batching: queries
- * join at round boundaries of queries already running). */
+/* Serving session: resident DBs, a background loop per DB that admits
+ * submitted queries while their state fits hbm_budget_bytes, and runs
+ * admitted queries of different k and delta together (continuous batching:
+ * queries join at round boundaries of queries already running).  The budget
+ * is shared by all DBs: an admitted query holds its DB's per-query state
+ * (about 34 bytes per point of the DB, plus its result row) until its result
+ * has been copied out.  Each DB's slot arena is sized so that the DB alone
+ * can use the whole budget (at most 1024 queries in flight per DB).
+ * Errors: EINVAL (budget below 1 MiB, NULL). */
 int knn_session_create(size_t hbm_budget_bytes, knn_session *out);
 
-/* Makes `db` resident in the session; *db_id identifies it in submit. */
+/* Makes `db` resident in the session; *db_id identifies it in submit.
+ * Errors: EINVAL, ENOMEM (the budget does not hold one query of this DB, or
+ * the slot arena cannot be allocated), EDEVICE. */
 int knn_session_add_db(knn_session s, knn_db db, int32_t *db_id);
 
 /* Enqueues one query (host_query: host, [m] of the DB's dtype; copied

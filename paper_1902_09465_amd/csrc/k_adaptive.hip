@@ -2793,7 +2793,99 @@ __global__ __launch_bounds__(MT) void k_finish(Slot *__restrict__ slots, const Q
       return;
     }
   }
-  if (sl->state == 0) admit(sl, qd, sched, ctl, n, m, admit_only == 2);
+  if (sl->state == 0 && !G.packed_admit) admit(sl, qd, sched, ctl, n, m, admit_only == 2);
+}
+
+// Packed admission (one block): the queries submitted but not yet admitted
+// go to the lowest idle slots, in slot order, so that running slots stay
+// packed at the bottom of the engine; then Ctl::run_hi = 1 + the highest
+// running slot, which bounds the slots the next step's kernels cover.
+__global__ __launch_bounds__(MT) void k_admit_packed(Slot *__restrict__ slots, const QDesc *__restrict__ qd,
+                                                     const Sched *__restrict__ sched, Ctl *ctl, int64_t n,
+                                                     int64_t m, int32_t ns) {
+  __shared__ int base, wsum[MT / kWave], hi;
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  if (threadIdx.x == 0) {
+    base = 0;
+    hi = 0;
+  }
+  __syncthreads();
+  const int nq = ctl->nq, first = ctl->next_query;
+  for (int s0 = 0; s0 < ns; s0 += MT) {
+    const int s = s0 + (int)threadIdx.x;
+    const bool idle = s < ns && slots[s].state == 0;
+    // rank of this idle slot among the idle slots below it
+    const uint64_t bal = __ballot(idle);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    if (lane == 0) wsum[wave] = __popcll(bal);
+    __syncthreads();
+    int before = base;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    const int rank = before + __popcll(bal & lt);
+    const int qseq = first + rank;
+    if (idle && qseq < nq) {
+      Slot *sl = &slots[s];
+      const int qi = ctl->qcap > 0 ? qseq % ctl->qcap : qseq;
+      const QDesc &d = qd[qi];
+      if (d.trivial) {
+        const int64_t cnt = d.kh < n ? d.kh : n;
+        for (int64_t j = 0; j < d.out_stride; ++j) d.out_idx[j] = j < cnt ? j : -1;
+        *d.out_count = (int32_t)cnt;
+        if (d.out_stats) {
+          d.out_stats->coord_evals = 0;
+          d.out_stats->rounds = 0;
+          d.out_stats->count = (int32_t)cnt;
+          d.out_stats->exact_points = 0;
+        }
+        __threadfence();
+        atomicAdd(&ctl->done, 1);
+      } else {
+        const Sched &sc = sched[d.sched];
+        for (int r = 0; r < kMaxRounds; ++r) {
+          sl->T[r] = sc.T[r];
+          sl->alpha[r] = sc.alpha[r];
+        }
+        sl->qi = qi;
+        sl->cur = 0;
+        sl->par = 0;
+        sl->implicit = 1;
+        sl->n_act = (int32_t)n;
+        sl->n_xa = 0;
+        sl->n_acc = 0;
+        sl->nn_act = 0;
+        sl->nn_xa = 0;
+        sl->nn_acc = 0;
+        sl->k = d.k;
+        sl->kh = d.kh;
+        sl->R = sc.R;
+        sl->c_exact = d.c_exact;
+        sl->F = d.F;
+        sl->norepl = d.norepl;
+        sl->shared = d.shared;
+        sl->seed = d.seed;
+        sl->W = d.W;
+        sl->q = d.q;
+        sl->rounds = 0;
+        sl->pm_copy = 0;
+        sl->coord_evals = sc.R == 0 ? n * m : n * (int64_t)sc.T[0];
+        sl->exact_points = sc.R == 0 ? n : 0;
+        sl->state = 1;
+      }
+    }
+    if (s < ns && slots[s].state == 1) atomicMax(&hi, s + 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < MT / kWave; ++w) tot += wsum[w];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int took = min(base, max(0, nq - first));
+    ctl->next_query = first + took;
+    ctl->run_hi = hi;
+  }
 }
 
 // ---------------------------------------------------------------- launch table
@@ -3082,6 +3174,8 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     hipLaunchKernelGGL(k_finish<KNN_U8>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, 0);
   else
     hipLaunchKernelGGL(k_finish<KNN_F32>, dim3(ns), dim3(MT), 0, st, slots, qd, sched, ctl, X, B, G, 0);
+  if (G.packed_admit)
+    hipLaunchKernelGGL(k_admit_packed, dim3(1), dim3(MT), 0, st, slots, qd, sched, ctl, G.n, G.m, G.nslots_all);
   prof_end(tok, st, 0.0);
 }
 

@@ -234,6 +234,8 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.G.m = db->m;
   E.G.dtype = db->dtype;
   E.G.nslots = (int32_t)ns;
+  E.G.nslots_all = (int32_t)ns;
+  E.G.packed_admit = 0;
   // points per sampling block: about 1024 blocks per step over all slots
   // (single queries on small DBs still spread over the GPU), at most the
   // knob's value, at least 16

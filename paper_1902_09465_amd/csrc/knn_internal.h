@@ -110,7 +110,8 @@ struct Ctl {
   int32_t nq;           // queries submitted so far (the host may raise it between steps)
   int32_t stop_after;   // > 0: debug stop after that many decide steps (no output)
   int32_t qcap;         // QDesc/Sched tables are rings of qcap entries (query qi at qi % qcap)
-  int32_t pad[3];
+  int32_t run_hi;       // packed admission: 1 + the highest slot running after the last admission
+  int32_t pad[2];
 };
 
 // Device buffers of one engine instance (per-slot arrays are [nslots][n]).
@@ -150,6 +151,10 @@ struct Geometry {
   int32_t flagsets;     // 1: point-major batch: dense slots (implicit 1/2) keep their sums
                         // point-major and their sets in the flags; sparse slots (implicit 0)
                         // use the per-slot list kernels
+  int32_t nslots_all;   // slots of the engine; nslots may be lower for a step (packed admission:
+                        // every running slot lies below nslots)
+  int32_t packed_admit; // 1: queries are admitted into the lowest idle slots by k_admit_packed
+                        // (one block, after k_finish), which also reports Ctl::run_hi
   int32_t sparse_div;   // a dense slot turns sparse once its undecided count is <= n / sparse_div
                         // (0: never)
 };

@@ -1,18 +1,23 @@
 // knn_session.cpp -- serving session: resident DBs, memory-admitted query
 // slots, and continuous batching.
 //
-// Each DB added to a session gets a slot engine (device state for a fixed
-// number of in-flight queries, sized from the session's HBM budget) on its
-// own HIP stream, device rings for query vectors, descriptors and results,
-// and its own worker thread, so that DBs progress independently.  A worker
-// loops:
-//   1. moves submitted requests into free ring entries (uploads the queries,
-//      descriptors and schedules of the whole batch, then raises the
-//      engine's query count);
+// Each DB added to a session gets a slot engine (device state for up to
+// kSessionMaxSlots in-flight queries, and at most as many as the session's
+// budget holds for that DB) on its own HIP stream, device rings for query
+// vectors, descriptors and results, and its own worker thread, so that DBs
+// progress independently.  Requests of all DBs are admitted against one
+// shared budget: a request takes its DB's per-query state bytes (running
+// sums, flags, lists and selection space for the DB's n points, plus its
+// ring entry) from the budget when it enters a ring entry and returns them
+// when its result has been copied out.  A worker loops:
+//   1. moves submitted requests into free ring entries while the budget has
+//      room for them (uploads the queries, descriptors and schedules of the
+//      whole batch, then raises the engine's query count);
 //   2. launches one round ("step") on the engine -- queries admitted on the
 //      device join at this round boundary while the others continue where
 //      they are;
-//   3. synchronises its stream and collects finished queries.
+//   3. copies the result counts, then the results of every query that
+//      finished in the step, with one synchronisation for each.
 // Requests therefore overlap on the device and are admitted as slots and
 // memory free up; each result depends only on (query, DB, k, params).
 #include <hip/hip_runtime.h>
@@ -65,6 +70,8 @@ struct DbEngine {
   int64_t inflight = 0;
   std::deque<Request *> pending;
   std::vector<int32_t> hcnt;
+  size_t req_bytes = 0;        // state bytes one request of this DB takes from the budget
+  int32_t run_hi = 0;          // 1 + the highest running slot after the last step's admission
   int32_t nq_host = 0;         // source of the query-count upload
   std::condition_variable cv;  // new requests for this DB
   std::thread worker;
@@ -73,7 +80,8 @@ struct DbEngine {
 }  // namespace knn
 
 struct knn_session_s {
-  size_t budget = 0, reserved = 0;
+  size_t budget = 0;
+  size_t in_use = 0;   // state bytes of the requests in ring entries (all DBs)
   std::mutex mu;
   std::vector<std::unique_ptr<knn::DbEngine>> dbs;
   std::unordered_map<uint64_t, knn::Request *> reqs;
@@ -122,6 +130,8 @@ static int upload(DbEngine &D, std::vector<Request *> &batch, std::string &err) 
   return KNN_OK;
 }
 
+// Marks every request of the DB's ring done with an error and frees its
+// ring entry and budget (under the session lock); the worker then idles.
 static void fail_all(knn_session_s *S, DbEngine &D, const std::string &msg) {
   std::lock_guard<std::mutex> lk(S->mu);
   S->fail_msg = msg;
@@ -131,23 +141,39 @@ static void fail_all(knn_session_s *S, DbEngine &D, const std::string &msg) {
       D.ring[s]->done = true;
       D.ring[s]->err = KNN_EDEVICE;
       D.ring[s] = nullptr;
+      S->in_use -= D.req_bytes;
     }
   D.inflight = 0;
+  for (Request *r : D.pending) {  // never admitted: failed too, so that their polls end
+    r->done = true;
+    r->err = KNN_EDEVICE;
+  }
+  D.pending.clear();
 }
 
 static void db_loop(knn_session_s *S, DbEngine *Dp) {
   DbEngine &D = *Dp;
   std::string err;
+  std::vector<int64_t> fin;  // ring entries whose query finished in this step
+  std::vector<std::vector<int64_t>> fidx;
+  std::vector<knn_stats> fst;
   while (!S->stop.load()) {
-    // 1. admission: move pending requests into free ring entries
+    if (S->failed.load()) {  // a device error: nothing more runs on this session
+      std::unique_lock<std::mutex> lk(S->mu);
+      D.cv.wait_for(lk, std::chrono::milliseconds(5));
+      continue;
+    }
+    // 1. admission: move pending requests into free ring entries while the
+    //    shared budget holds their state
     std::vector<Request *> batch;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       int32_t next = D.submitted;
       while (!D.pending.empty() && D.ring[next % D.qcap] == nullptr &&
-             D.inflight + (int64_t)batch.size() < D.qcap) {
+             D.inflight + (int64_t)batch.size() < D.qcap && S->in_use + D.req_bytes <= S->budget) {
         batch.push_back(D.pending.front());
         D.pending.pop_front();
+        S->in_use += D.req_bytes;
         ++next;
       }
       if (batch.empty() && D.inflight == 0) {
@@ -155,42 +181,59 @@ static void db_loop(knn_session_s *S, DbEngine *Dp) {
         continue;
       }
     }
-    if (!batch.empty() && upload(D, batch, err) != KNN_OK) {
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->fail_msg = err;
-      S->failed = 1;
-      for (Request *r : batch) {
-        r->done = true;
-        r->err = KNN_EDEVICE;
+    if (!batch.empty()) {
+      const int64_t before = D.submitted;
+      if (upload(D, batch, err) != KNN_OK) {
+        // the requests that reached the ring are failed there; the rest here
+        const int64_t placed = D.submitted - before;
+        fail_all(S, D, err);
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (size_t j = (size_t)placed; j < batch.size(); ++j) {
+          batch[j]->done = true;
+          batch[j]->err = KNN_EDEVICE;
+          S->in_use -= D.req_bytes;
+        }
+        continue;
       }
-      continue;
     }
-    // 2. one round
+    // 2. one round over the slots that can be running (admission keeps them
+    //    packed below run_hi; new queries are admitted at the end of the step)
+    D.E.G.nslots = std::max<int32_t>(1, std::min<int32_t>((int32_t)D.E.ns, D.run_hi));
     engine_step(D.E, true);
-    // 3. collect finished queries
+    // 3. collect finished queries: the counts (and the new run_hi), then the
+    //    rows and statistics of the finished ones, one synchronisation each
     hipError_t e = hipMemcpyAsync(D.hcnt.data(), D.dcnt, sizeof(int32_t) * D.qcap, hipMemcpyDeviceToHost, D.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&D.run_hi, &D.E.ctl->run_hi, sizeof(int32_t), hipMemcpyDeviceToHost, D.st);
     if (e == hipSuccess) e = hipStreamSynchronize(D.st);
+    fin.clear();
+    for (int64_t s = 0; s < D.qcap && e == hipSuccess; ++s)
+      if (D.ring[s] && D.hcnt[s] >= 0) fin.push_back(s);
+    if (fidx.size() < fin.size()) fidx.resize(fin.size());
+    fst.assign(fin.size(), knn_stats{});
+    for (size_t f = 0; f < fin.size() && e == hipSuccess; ++f) {
+      const int64_t s = fin[f];
+      const int64_t kh = std::max<int64_t>(std::min<int64_t>(D.ring[s]->d.kh, kSessionMaxKH), 1);
+      fidx[f].assign(kh, -1);
+      e = hipMemcpyAsync(fidx[f].data(), D.didx + s * kSessionMaxKH, sizeof(int64_t) * kh, hipMemcpyDeviceToHost,
+                         D.st);
+      if (e == hipSuccess) e = hipMemcpyAsync(&fst[f], D.dstats + s, sizeof(knn_stats), hipMemcpyDeviceToHost, D.st);
+    }
+    if (e == hipSuccess && !fin.empty()) e = hipStreamSynchronize(D.st);
     if (e != hipSuccess) {
       fail_all(S, D, std::string("session step: ") + hipGetErrorString(e));
       continue;
     }
-    for (int64_t s = 0; s < D.qcap; ++s) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t f = 0; f < fin.size(); ++f) {
+      const int64_t s = fin[f];
       Request *r = D.ring[s];
-      if (!r || D.hcnt[s] < 0) continue;
       r->count = D.hcnt[s];
-      std::vector<int64_t> idx(std::max<int64_t>(r->d.kh, 1), -1);
-      knn_stats st{};
-      e = hipMemcpyAsync(idx.data(), D.didx + s * kSessionMaxKH, sizeof(int64_t) * std::min<int64_t>(r->d.kh, kSessionMaxKH),
-                         hipMemcpyDeviceToHost, D.st);
-      if (e == hipSuccess) e = hipMemcpyAsync(&st, D.dstats + s, sizeof(knn_stats), hipMemcpyDeviceToHost, D.st);
-      if (e == hipSuccess) e = hipStreamSynchronize(D.st);
-      std::lock_guard<std::mutex> lk(S->mu);
-      r->idx.swap(idx);
-      r->st = st;
-      if (e != hipSuccess) r->err = KNN_EDEVICE;
+      r->idx.swap(fidx[f]);
+      r->st = fst[f];
       r->done = true;
       D.ring[s] = nullptr;
       D.inflight--;
+      S->in_use -= D.req_bytes;
     }
   }
 }
@@ -218,11 +261,14 @@ int knn_session_add_db(knn_session S, knn_db db, int32_t *db_id) {
   const size_t per_ring = (size_t)m * elem + kSessionMaxKH * 8 + 4 + sizeof(knn_stats) + sizeof(QDesc) + sizeof(Sched);
   std::unique_ptr<DbEngine> D(new DbEngine());
   D->db = db;
-  // Memory admission: each DB reserves half of the budget still free for its
-  // query slots (at least one slot); requests beyond its slots wait on the host.
-  const size_t avail = S->budget > S->reserved ? S->budget - S->reserved : 0;
-  int64_t ns = (int64_t)((avail / 2) / (per_slot + 2 * per_ring));
-  ns = std::max<int64_t>(1, std::min<int64_t>(ns, kSessionMaxSlots));
+  // Slots: as many as the whole budget holds for this DB (a DB may use all
+  // of it while the others are idle), at most kSessionMaxSlots; requests
+  // beyond the free slots or the free budget wait on the host.
+  const size_t req_bytes = per_slot + 2 * per_ring;
+  int64_t ns = (int64_t)(S->budget / req_bytes);
+  if (ns < 1) return fail(KNN_ENOMEM, "the session budget does not hold one query of this DB");
+  ns = std::min<int64_t>(ns, kSessionMaxSlots);
+  D->req_bytes = req_bytes;
   D->qcap = 2 * ns;
   HIP_TRY(hipStreamCreateWithFlags(&D->st, hipStreamNonBlocking));
   int rc = engine_create(D->E, db, ns, (int32_t)kSessionMaxKH, (int32_t)kSessionMaxKH, D->qcap, D->qcap, D->st, false,
@@ -231,6 +277,7 @@ int knn_session_add_db(knn_session S, knn_db db, int32_t *db_id) {
     (void)hipStreamDestroy(D->st);
     return rc;
   }
+  D->E.G.packed_admit = 1;  // queries go to the lowest idle slots; steps cover the slots below run_hi
   hipError_t e = hipMalloc(&D->dq, (size_t)D->qcap * m * elem);
   if (e == hipSuccess) e = hipMalloc(&D->didx, sizeof(int64_t) * D->qcap * kSessionMaxKH);
   if (e == hipSuccess) e = hipMalloc(&D->dcnt, sizeof(int32_t) * D->qcap);
@@ -253,7 +300,6 @@ int knn_session_add_db(knn_session S, knn_db db, int32_t *db_id) {
   D->hcnt.assign(D->qcap, -1);
   db->users++;
   std::lock_guard<std::mutex> lk(S->mu);
-  S->reserved += (size_t)ns * per_slot + (size_t)D->qcap * per_ring;
   *db_id = (int32_t)S->dbs.size();
   DbEngine *Dp = D.get();
   S->dbs.push_back(std::move(D));

@@ -2,7 +2,9 @@
 result is the same alone and in a mix, and equals the oracle."""
 from __future__ import annotations
 
+import os
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -76,7 +78,7 @@ def test_session_alone_vs_mix_and_oracle(P, orc):
 def test_session_tiny_budget_queues_requests(P, orc):
     X, Q = gmm_u8(41, n=3000, m=128, n_centres=4, sigma=30.0, nq=25)
     db = P.KnnDB(dev(X))
-    sess = P.Session(2 << 20)  # room for a single query slot
+    sess = P.Session(2 << 20)  # room for a few queries of this DB: most requests wait on the host
     d = sess.add_db(db)
     p = P.default_params(h=5, seed=7)
     tickets = [sess.submit(d, Q[i], 5, p) for i in range(25)]
@@ -105,4 +107,46 @@ def test_session_errors(P):
         from paper_1902_09465_amd._lib import check
         check(lib().knn_db_destroy(db.handle))
     assert e.value.code == -4
+    sess.close()
+
+
+def test_session_serving_dbs_full_size(P, orc):
+    """The three serving databases at their full sizes (50,000 x 784 u8;
+    500,000 x 256 f32; 2,000,000 x 96 f32) resident in one session with a
+    shared budget: 300 requests of random DB, k in 1..50, delta in {0.01,
+    0.05} and seeds, all in flight together; sampled requests equal the same
+    request run alone and the oracle."""
+    from knn_inputs import serving_dbs
+    data = serving_dbs(5000, scale=1.0)
+    dbs = [P.KnnDB(dev(X)) for X, _ in data]
+    sess = P.Session(48 << 30)
+    ids = [sess.add_db(db) for db in dbs]
+    g = rng(5200)
+    reqs = []
+    for _ in range(300):
+        d = int(g.integers(0, 3))
+        q = data[d][1][int(g.integers(0, data[d][1].shape[0]))]
+        k = int(g.integers(1, 51))
+        p = P.default_params(h=k, delta=0.01 if g.integers(0, 2) == 0 else 0.05, seed=int(g.integers(1 << 40)))
+        reqs.append((d, q, k, p))
+    tickets = [sess.submit(ids[d], q, k, p) for d, q, k, p in reqs]
+    mixed = [wait(sess, t, 2 * k, timeout=120.0) for (d, q, k, p), t in zip(reqs, tickets)]
+    sample = []
+    for d in range(3):  # two requests of each DB
+        sample += [i for i, r in enumerate(reqs) if r[0] == d][:2]
+    for i in sample:
+        d, q, k, p = reqs[i]
+        alone = wait(sess, sess.submit(ids[d], q, k, p), 2 * k, timeout=120.0)
+        assert alone[0].tolist() == mixed[i][0].tolist(), i
+        assert alone[1] == mixed[i][1], i
+
+    def ref(i):
+        d, q, k, p = reqs[i]
+        return orc.adaptive(data[d][0], q, k, orc.make_params(h=p.h, delta=p.delta, seed=p.seed))
+
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        refs = list(ex.map(ref, sample))
+    for i, (ridx, rst) in zip(sample, refs):
+        assert mixed[i][0].tolist() == ridx.tolist(), i
+        assert mixed[i][1]["coord_evals"] == rst["coord_evals"], i
     sess.close()
