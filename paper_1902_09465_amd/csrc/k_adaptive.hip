@@ -1557,6 +1557,151 @@ __device__ uint64_t wave_smallest_gen(int64_t N, Get get, int K, uint64_t *cbuf)
   return best;
 }
 
+// ---- selections of up to 128 keys: a 128-key list is two registers per
+// lane, sorted ascending with lane l holding ranks l (lo) and 64 + l (hi).
+__device__ __forceinline__ uint32_t lx(uint32_t v, int j) { return lane_xor_u32(v, j); }
+__device__ __forceinline__ uint64_t lx(uint64_t v, int j) { return lane_xor_u64(v, j); }
+__device__ __forceinline__ uint32_t wsort(uint32_t v) { return wave_sort_u32(v); }
+__device__ __forceinline__ uint64_t wsort(uint64_t v) { return wave_sort_u64(v); }
+__device__ __forceinline__ uint32_t wrev(uint32_t v) { return (uint32_t)__shfl((int)v, kWave - 1 - lane_id()); }
+__device__ __forceinline__ uint64_t wrev(uint64_t v) { return wave_bcast_rev_u64(v); }
+__device__ __forceinline__ uint32_t wbcast(uint32_t v, int src) { return (uint32_t)__builtin_amdgcn_readlane((int)v, src); }
+__device__ __forceinline__ uint64_t wbcast(uint64_t v, int src) { return wave_bcast_u64(v, src); }
+
+// A sequence bitonic across the lanes, sorted ascending.
+template <typename T>
+__device__ __forceinline__ T bitonic_clean(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int j = kWave / 2; j > 0; j >>= 1) {
+    const T o = lx(v, j);
+    v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
+  }
+  return v;
+}
+
+// Two sorted 64-key columns a, b -> the sorted 128-key list (lo, hi).
+template <typename T>
+__device__ __forceinline__ void merge64x2(T a, T b, T &lo, T &hi) {
+  const T rb = wrev(b);  // a ascending, rb descending: min / max are the two bitonic halves
+  lo = bitonic_clean(a < rb ? a : rb);
+  hi = bitonic_clean(a < rb ? rb : a);
+}
+
+// The 128 smallest of a sorted 128-key list (lo, hi) and a sorted 64-key
+// column c, sorted (c is taken as padded to 128 with keys above all).
+template <typename T>
+__device__ __forceinline__ void merge128_col(T &lo, T &hi, T c) {
+  const T rc = wrev(c);
+  const T h2 = hi < rc ? hi : rc;  // (lo, h2): the 128 smallest, bitonic
+  const T a = lo < h2 ? lo : h2, b = lo < h2 ? h2 : lo;
+  lo = bitonic_clean(a);
+  hi = bitonic_clean(b);
+}
+
+// The 128-key list's rank r (wave-uniform r < 128).
+template <typename T>
+__device__ __forceinline__ T rank128(T lo, T hi, int r) {
+  return r < kWave ? wbcast(lo, r) : wbcast(hi, r - kWave);
+}
+
+// The K (64 < K <= 128) smallest of the wave's E keys per lane, as a sorted
+// 128-key list (PAD past the real keys).  The two smallest keys of each lane
+// are 128 real keys (or PAD), so their K-th smallest bounds the K-th
+// smallest key from above; the keys at or below that bound are sorted at
+// once when at most 128, else every key column is merged into the list.
+template <int E, typename T>
+__device__ void wave_smallest128(const T (&key)[E], int K, T *cbuf, T &lo, T &hi) {
+  const T PAD = (T)~(T)0;
+  const int lane = lane_id();
+  T m1 = PAD, m2 = PAD;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const T v = key[e];
+    if (v < m1) {
+      m2 = m1;
+      m1 = v;
+    } else if (v < m2) {
+      m2 = v;
+    }
+  }
+  T a, b;
+  merge64x2(wsort(m1), wsort(m2), a, b);
+  const T tau = rank128(a, b, K - 1);
+  int cnt = 0;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const bool c = key[e] <= tau && key[e] != PAD;
+    const uint64_t mk = __ballot(c);
+    const int pos = cnt + __popcll(mk & lt);
+    if (c && pos < 2 * kWave) cbuf[pos] = key[e];
+    cnt += __popcll(mk);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (cnt <= 2 * kWave) {
+    merge64x2(wsort(lane < cnt ? cbuf[lane] : PAD), wsort(lane + kWave < cnt ? cbuf[lane + kWave] : PAD), lo, hi);
+  } else {
+    lo = wsort(key[0]);
+    hi = PAD;
+#pragma unroll
+    for (int e = 1; e < E; ++e) merge128_col(lo, hi, wsort(key[e]));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();  // cbuf is reused by the next call
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same for N keys get(p), p in [0, N), read twice instead of held in
+// registers (64 < K <= 128).
+template <typename Get>
+__device__ void wave_smallest128_gen(int64_t N, Get get, int K, uint64_t *cbuf, uint64_t &lo, uint64_t &hi) {
+  constexpr uint64_t PAD = ~0ull;
+  const int lane = lane_id();
+  uint64_t m1 = PAD, m2 = PAD;
+  for (int64_t p = lane; p < N; p += kWave) {
+    const uint64_t v = get(p);
+    if (v < m1) {
+      m2 = m1;
+      m1 = v;
+    } else if (v < m2) {
+      m2 = v;
+    }
+  }
+  uint64_t a, b;
+  merge64x2(wsort(m1), wsort(m2), a, b);
+  const uint64_t tau = rank128(a, b, K - 1);
+  int cnt = 0;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  for (int64_t p0 = 0; p0 < N; p0 += kWave) {  // wave-uniform trip count
+    const int64_t p = p0 + lane;
+    const uint64_t v = p < N ? get(p) : PAD;
+    const bool c = v <= tau && v != PAD;
+    const uint64_t mk = __ballot(c);
+    const int pos = cnt + __popcll(mk & lt);
+    if (c && pos < 2 * kWave) cbuf[pos] = v;
+    cnt += __popcll(mk);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (cnt <= 2 * kWave) {
+    merge64x2(wsort(lane < cnt ? cbuf[lane] : PAD), wsort(lane + kWave < cnt ? cbuf[lane + kWave] : PAD), lo, hi);
+  } else {
+    lo = PAD;
+    hi = PAD;
+    for (int64_t p0 = 0; p0 < N; p0 += kWave) {
+      const int64_t p = p0 + lane;
+      merge128_col(lo, hi, wsort(p < N ? get(p) : PAD));
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();  // cbuf is reused by the next call
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The same selection on 32-bit keys (PAD = ~0u, above every real key): the
 // K smallest come back ascending across the lanes, lane l holding the l-th
 // (PAD past the real keys).
@@ -1691,6 +1836,9 @@ __device__ __forceinline__ void fs_stage_sums(uint32_t (*t)[FS_TS], const uint32
 // smallest LCB per slot over the kept points (the partial lists that
 // k_select_merge_pm reads, one per FS_PT points).  In a sampled round 0 every pair is undecided: its flag and round
 // index are initialised here.
+// WIDE: some slot's k + 1 exceeds 64 (lists of up to 128 keys; the K <= 64
+// instance stays within 64 VGPRs).
+template <bool WIDE>
 __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
                                                   int32_t nqp, Bufs B, Geometry G, int32_t cur, int32_t init) {
   __shared__ __align__(16) uint32_t t[FS_SL][FS_TS];
@@ -1793,13 +1941,24 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
     const bool uniform = __ballot(has_l) == 0 && (!any_x || __ballot(has_c) == 0);
     uint64_t *out = B.part + (int64_t)sl * B.part_stride + tile * (2 * k + 1);
     if (uniform) {
-      const uint32_t b = wave_smallest_u32<FS_E>(kt, k + 1, reinterpret_cast<uint32_t *>(cbuf[wave]));
       constexpr uint64_t PAD = ~0ull;
-      if (lane < k + 1) {
-        double d, al;  // the bounds of a pair with sum b, as pair_bounds gives them
-        pair_bounds(slp, rc, (int64_t)b, any_x ? (uint8_t)FL_EXACT : (uint8_t)0, (uint8_t)0, true, d, al);
-        if (lane < k) out[lane] = b == PAD32 ? PAD : dkey(d + al);
-        out[k + lane] = b == PAD32 ? PAD : dkey(d - al);
+      uint32_t bv[2];
+      if (!WIDE || k + 1 <= kWave) {
+        bv[0] = wave_smallest_u32<FS_E>(kt, k + 1, reinterpret_cast<uint32_t *>(cbuf[wave]));
+        bv[1] = PAD32;
+      } else {  // (k + 1 <= 128) ranks lane and 64 + lane
+        wave_smallest128<FS_E, uint32_t>(kt, k + 1, reinterpret_cast<uint32_t *>(cbuf[wave]), bv[0], bv[1]);
+      }
+#pragma unroll
+      for (int h = 0; h < (WIDE ? 2 : 1); ++h) {
+        const int r = lane + kWave * h;
+        if (r < k + 1) {
+          const uint32_t b = bv[h];
+          double d, al;  // the bounds of a pair with sum b, as pair_bounds gives them
+          pair_bounds(slp, rc, (int64_t)b, any_x ? (uint8_t)FL_EXACT : (uint8_t)0, (uint8_t)0, true, d, al);
+          if (r < k) out[r] = b == PAD32 ? PAD : dkey(d + al);
+          out[k + r] = b == PAD32 ? PAD : dkey(d - al);
+        }
       }
     }
     if (lane == 0) {
@@ -1819,7 +1978,7 @@ __global__ __launch_bounds__(kWave) void k_select_pm_mixed(const Slot *__restric
                                                            const uint32_t *__restrict__ D, int32_t nqp, Bufs B,
                                                            Geometry G, int32_t cur, int32_t init) {
   __shared__ uint32_t tc[FS_PT];
-  __shared__ uint64_t cbuf[kWave];
+  __shared__ uint64_t cbuf[2 * kWave];
   const int64_t n = G.n, m = G.m;
   const int sl = blockIdx.x;
   if (init || sl >= G.nslots) return;
@@ -1861,10 +2020,16 @@ __global__ __launch_bounds__(kWave) void k_select_pm_mixed(const Slot *__restric
         pair_bounds(slp, rc, (int64_t)tc[p], f, late ? B.ri[(int64_t)sl * n + i] : (uint8_t)0, !late, d, al);
         key[e] = lower ? dkey(d - al) : dkey(d + al);
       }
-      if (lower)
-        wave_smallest<FS_E>(key, k + 1, out + k, cbuf);
-      else
-        wave_smallest<FS_E>(key, k, out, cbuf);
+      const int K = lower ? k + 1 : k;
+      uint64_t *o = lower ? out + k : out;
+      if (K <= kWave) {
+        wave_smallest<FS_E>(key, K, o, cbuf);
+      } else {  // (K <= 128)
+        uint64_t lo, hi;
+        wave_smallest128<FS_E, uint64_t>(key, K, cbuf, lo, hi);
+        o[lane] = lo;
+        if (lane + kWave < K) o[lane + kWave] = hi;
+      }
     }
   }
 }
@@ -2128,7 +2293,7 @@ __global__ __launch_bounds__(MT) void k_select_merge(Slot *__restrict__ slots, B
 // time; then the decisions as thresholds on the sums, for k_decide_pm.
 constexpr int SMP_T = 2 * kWave;
 __global__ __launch_bounds__(SMP_T) void k_select_merge_pm(Slot *__restrict__ slots, Bufs B, Geometry G) {
-  __shared__ uint64_t cbuf[2][kWave];
+  __shared__ uint64_t cbuf[2][2 * kWave];
   __shared__ uint64_t ul[3];  // U, L1, L2 as keys
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int s = blockIdx.x;
@@ -2146,15 +2311,31 @@ __global__ __launch_bounds__(SMP_T) void k_select_merge_pm(Slot *__restrict__ sl
       const uint32_t q = (uint32_t)p / ku;
       return part[q * wu + ((uint32_t)p - q * ku)];
     };
-    const uint64_t U = wave_bcast_u64(wave_smallest_gen(nch * k, gu, k, cbuf[0]), k - 1);
+    uint64_t U;
+    if (k <= kWave) {
+      U = wave_bcast_u64(wave_smallest_gen(nch * k, gu, k, cbuf[0]), k - 1);
+    } else {
+      uint64_t lo, hi;
+      wave_smallest128_gen(nch * k, gu, k, cbuf[0], lo, hi);
+      U = rank128(lo, hi, k - 1);
+    }
     if (lane == 0) ul[0] = U;
   } else {
     auto gl = [&](int64_t p) -> uint64_t {
       const uint32_t q = (uint32_t)p / kl;
       return part[q * wu + ku + ((uint32_t)p - q * kl)];
     };
-    const uint64_t lcb = wave_smallest_gen(nch * (k + 1), gl, k + 1, cbuf[1]);
-    const uint64_t L1 = wave_bcast_u64(lcb, k - 1), L2 = wave_bcast_u64(lcb, k);
+    uint64_t L1, L2;
+    if (k + 1 <= kWave) {
+      const uint64_t lcb = wave_smallest_gen(nch * (k + 1), gl, k + 1, cbuf[1]);
+      L1 = wave_bcast_u64(lcb, k - 1);
+      L2 = wave_bcast_u64(lcb, k);
+    } else {
+      uint64_t lo, hi;
+      wave_smallest128_gen(nch * (k + 1), gl, k + 1, cbuf[1], lo, hi);
+      L1 = rank128(lo, hi, k - 1);
+      L2 = rank128(lo, hi, k);
+    }
     if (lane == 0) {
       ul[1] = L1;
       ul[2] = L2;
@@ -3058,8 +3239,12 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     prof_end(tk, st, 0.0);
     tk = prof_begin(PROF_SELECT, st);
     const int64_t nsel = ((G.n + FS_PT - 1) / FS_PT) * ((nqp + FS_SL - 1) / FS_SL);
-    hipLaunchKernelGGL(k_select_pm, dim3((unsigned)xcd_grid(nsel)), dim3(NT), 0, st, slots, qd_buf, nqp, B, G, ql->cur,
-                       (ql->cur == 0 && !ql->exact) ? 1 : 0);
+    if (G.kmax + 1 > kWave)
+      hipLaunchKernelGGL(k_select_pm<true>, dim3((unsigned)xcd_grid(nsel)), dim3(NT), 0, st, slots, qd_buf, nqp, B, G,
+                         ql->cur, (ql->cur == 0 && !ql->exact) ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_select_pm<false>, dim3((unsigned)xcd_grid(nsel)), dim3(NT), 0, st, slots, qd_buf, nqp, B, G,
+                         ql->cur, (ql->cur == 0 && !ql->exact) ? 1 : 0);
     hipLaunchKernelGGL(k_select_pm_mixed, dim3(ns), dim3(kWave), 0, st, slots, qd_buf, nqp, B, G, ql->cur,
                        (ql->cur == 0 && !ql->exact) ? 1 : 0);
     hipLaunchKernelGGL(k_select_partial, dim3((unsigned)((sparse_list + SEL_CH - 1) / SEL_CH), ns), dim3(NT), 0, st,
@@ -3191,7 +3376,7 @@ void launch_admit(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, co
 
 int64_t part_words(int64_t n, int32_t kmax, int32_t cmax) {
   int64_t nsel = (n + SEL_CH - 1) / SEL_CH;
-  if (kmax + 1 <= kWave) nsel = std::max<int64_t>(nsel, (n + FS_PT - 1) / FS_PT);  // fused query-lane selection
+  if (kmax + 1 <= kPmMaxK1) nsel = std::max<int64_t>(nsel, (n + FS_PT - 1) / FS_PT);  // point-major selection
   const int64_t ncand = (n + CAND_CH - 1) / CAND_CH;
   int64_t a = nsel * (2 * (int64_t)kmax + 1);
   a = std::max<int64_t>(a, (3 * ((n + DQ_PT - 1) / DQ_PT) + 1) / 2);  // k_decide_pm's count records (u32 triples)

@@ -354,7 +354,7 @@ static int prepare(knn_db_s *db, const void *dq, int64_t nq, const int32_t *host
 // so the exact round adds the rest) and the norm boundaries.
 static void seq_geometry(const knn_db_s *db, const Prepared &P, bool query_lane, int32_t &tlen, int32_t &nb) {
   tlen = nb = 0;
-  if (!query_lane || P.qd.empty() || !P.qd[0].shared || P.sched.size() != 1 || P.any_cexact || P.kmax + 1 > 64)
+  if (!query_lane || P.qd.empty() || !P.qd[0].shared || P.sched.size() != 1 || P.any_cexact || P.kmax + 1 > kPmMaxK1)
     return;
   const int32_t R = P.sched[0].R;
   if (P.qd[0].norepl) {
@@ -379,9 +379,9 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   if (E.q8) launch_build_q8(E.slots, (int32_t)E.ns, m, db->mp, E.q8, E.q8n, db->metric, st);
   const bool lockstep = P.sched.size() == 1;
   // Query-lane batches whose every round runs the fused fold + selection (no
-  // candidate-exact, k + 1 <= 64) and whose exact round is one tiled pass
+  // candidate-exact, k + 1 <= 128) and whose exact round is one tiled pass
   // read the sets from the flags alone: no per-slot point lists are built
-  E.G.flagsets = (E.qt && E.q8 && lockstep && !P.any_cexact && P.kmax + 1 <= 64) ? 1 : 0;
+  E.G.flagsets = (E.qt && E.q8 && lockstep && !P.any_cexact && P.kmax + 1 <= kPmMaxK1) ? 1 : 0;
   // one coordinate sequence for every point: the points and queries gathered
   // at its coordinates once, then every round is a range of their columns
   const bool seq = E.seq.xs && E.G.flagsets;

@@ -9,6 +9,7 @@
 namespace knn {
 
 constexpr int kMaxRounds = KNN_MAX_ROUNDS;
+constexpr int kPmMaxK1 = 128;  // point-major batches: k + 1 <= kPmMaxK1 (selection lists of two wave registers)
 constexpr int kMaxKH = KNN_MAX_KH;
 
 // Point flags (per query, per point).  The dump format of

@@ -194,6 +194,41 @@ def test_point_major_batch_decides_in_sampled_rounds(P, orc, monkeypatch, sparse
             assert np.array_equal(ri, rio), f"slot {slot} round {r}: round index differs"
 
 
+@pytest.mark.parametrize("sampling", [0, 3])
+def test_point_major_batch_wide_k(P, orc, monkeypatch, sampling):
+    """Point-major batches with k + 1 up to 128: selection lists of two
+    registers per lane.  80 queries with k cycling over 1, 63, 64, 100, 127
+    (ranks k - 1 and k on either side of the 64-lane boundary) on data where
+    sampled rounds decide; every query's set and statistics equal the
+    oracle's, and so does the per-round state of slots 2 (k = 64), 3
+    (k = 100) and 4 (k = 127)."""
+    monkeypatch.setenv("KNN_SPARSE_DIV", "0")  # every round on the point-major kernels
+    nq = 80
+    ks = np.array([(1, 63, 64, 100, 127)[j % 5] for j in range(nq)], dtype=np.int32)
+    gaps = rng(6).uniform(0.02, 0.3, size=nq)
+    X, Q = planted_corners(92, 12000, 1024, nq, ks, gaps)
+    db = P.KnnDB(dev(X))
+    kw = dict(DECISIVE_KW, sampling=sampling)
+    p = P.default_params(**kw)
+    idx, cnt, st = db.adaptive(dev(Q), ks, p)
+    idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
+    refs = oracle_many(orc, X, Q, ks, kw, range(nq))
+    for q, (ref, rst) in enumerate(refs):
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert (int(st[q]["coord_evals"]), int(st[q]["rounds"]), int(st[q]["exact_points"])) == \
+            (rst["coord_evals"], rst["rounds"], rst["exact_points"]), q
+    assert sum(r[1]["exact_points"] < X.shape[0] for r in refs) >= 40
+    Qd = dev(Q)
+    for slot in (2, 3, 4):
+        for r in range(1, refs[slot][1]["rounds"] + 1):
+            S, fl, ri = db.adaptive_state(Qd, ks, p, r, query=slot)
+            _, _, (So, flo, rio) = orc.adaptive(X, Q[slot], int(ks[slot]), oparams(orc, **kw), stop_after=r,
+                                                dump=True)
+            assert np.array_equal(fl, flo), f"slot {slot} round {r}: flags differ"
+            assert np.array_equal(S, So), f"slot {slot} round {r}: sums differ"
+            assert np.array_equal(ri, rio), f"slot {slot} round {r}: round index differs"
+
+
 @pytest.mark.parametrize("variant", ["pure", "cexact", "b0_4", "lemma", "calpha", "theta"])
 def test_variants_parity(P, orc, variant):
     X, Q = gmm_u8(5, n=3000, m=300, n_centres=4, sigma=20.0, nq=3)
