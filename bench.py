@@ -66,6 +66,8 @@ def log(msg):
 # source is unchanged.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sample_ql_u8_batched_int_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_09465_amd", "csrc", "k_adaptive.hip")
+ROUND_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_round_seq_u8_batched_int_traffic.txt")
+ROUND_KERNEL_SRC = os.path.join(ROOT, "paper_1902_09465_amd", "csrc", "k_naive.hip")
 COPY_BYTES = 1 << 30
 
 
@@ -75,16 +77,16 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic():
-    """Bytes per launch of k_sample_ql_u8 from the committed counter summary,
-    or None when the summary is missing or was taken on other source."""
+def stored_traffic(path, src):
+    """Bytes per launch of a kernel from its committed counter summary, or
+    None when the summary is missing or was taken on other source."""
     try:
         kv = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(path):
             if ":" in line and not line.startswith(" "):
                 a, b = line.split(":", 1)
                 kv[a.strip()] = b.strip()
-        if kv.get("source_sha256_16") != source_hash(KERNEL_SRC):
+        if kv.get("source_sha256_16") != source_hash(src):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -373,12 +375,17 @@ def uneven_bench(args):
     n_easy = Q.shape[0] // 2
     parts = {"all": np.arange(Q.shape[0]), "easy": np.arange(n_easy), "hard": np.arange(n_easy, Q.shape[0])}
     res = {}
-    for variant, (name, sel) in [(v, pn) for v in ("pure", "candidate_exact") for pn in parts.items()]:
+    variants = ("pure", "pure_shared", "candidate_exact")
+    for variant, (name, sel) in [(v, pn) for v in variants for pn in parts.items()]:
         qs = Qd[torch.from_numpy(sel).cuda()].contiguous()
         kk = ks[sel]
-        # pure round form, or with the 2k smallest estimates made exact each round
+        # pure round form (coordinates drawn per point, or one sequence shared
+        # by all points without replacement), or with the 2k smallest
+        # estimates made exact each round
         if variant == "pure":
             p = P.default_params(h=-1, delta=0.01, seed=4001)
+        elif variant == "pure_shared":
+            p = P.default_params(h=-1, delta=0.01, seed=4001, sampling=3)
         else:
             p = [P.default_params(h=-1, delta=0.01, seed=4001, c_exact=int(2 * kv)) for kv in kk]
         name = f"{variant}_{name}"
@@ -407,10 +414,11 @@ def uneven_bench(args):
         log(f"{name}: adaptive {len(sel) / ad_s:.0f} q/s, naive {len(sel) / nv_s:.0f} q/s, "
             f"evaluations {res[name]['evals_fraction_of_naive']:.3f} of naive")
     out = {"metric": "uneven workload: queries/s adaptive vs naive MFMA (whole batch, easy half, hard half)",
-           "value": res["pure_all"]["adaptive_queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+           "value": res["pure_shared_all"]["adaptive_queries_per_s"], "unit": "queries/s", "n_gpus": 1,
            "higher_is_better": True, "dtype": "u8", "data": "synthetic",
            "config": {"workload": "uneven: n=250000 x m=1024 uint8 binary corners, 4096 queries (2048 easy with k "
-                                  "planted points, 2048 hard), k in (1, 10, 100), h = k, delta = 0.01"},
+                                  "planted points, 2048 hard), k in (1, 10, 100), h = k, delta = 0.01, one seed; "
+                                  "value: the pure round form with one coordinate sequence shared by all points"},
            "parts": res}
     print(json.dumps(out), flush=True)
     return 0
@@ -609,15 +617,31 @@ def run_adaptive(P, lib, db, X_t, Q_t, params, nidx, ndist, args, warmup, steps,
     samp, exr = prof["sample"], prof["sample_exact_round"]
     s_avg = samp["ms"] / max(1, samp["launches"]) / 1e3
     e_avg = exr["ms"] / max(1, exr["launches"]) / 1e3
-    if shared and not l1:
-        # sampled rounds as int8 products over the gathered coordinates: 2 ops
-        # per (query, sample) pair on the matrix cores
-        s_ops = 2.0 * pairs / max(1, samp["launches"])
-        rl_sample = {"bound": "mfma", "achieved": s_ops / s_avg / 1e12 if s_avg > 0 else 0.0,
-                     "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
-                     "kernel": "k_round_seq_u8<l2> (sampled rounds, int8 MFMA over the gathered coordinates)",
-                     "avg_launch_ms": s_avg * 1e3, "launches": samp["launches"], "ops_per_launch": s_ops}
-        rl_sample["frac"] = rl_sample["achieved"] / INT8_PEAK_TOPS
+    if shared:
+        # sampled rounds as products over the gathered coordinates (int8 MFMA
+        # for squared l2, v_sad_u8 for l1).  Per launch the running sums D
+        # [n][1024] u32 are written (round 0) or read and written with the
+        # "not sampled" bytes A (later rounds): 4 or 9 bytes per (query,
+        # point), against a product of 2 B_r ops per pair -- at these round
+        # sizes the state traffic, not the matrix cores, bounds the kernel.
+        r_per_step = samp["launches"] / max(1, steps)
+        b_pair = (4.0 + 9.0 * (r_per_step - 1)) / max(1.0, r_per_step)
+        cols = pairs / max(1.0, float(N * NQ))  # columns the timed launches sampled (all steps)
+        s_bytes = b_pair * N * NQ + (N + NQ) * cols / max(1, samp["launches"])
+        s_ops = (2.0 if not l1 else OPS_PER_ELEM_L1) * pairs / max(1, samp["launches"])
+        rl_sample = {"bound": "hbm", "achieved": s_bytes / s_avg / 1e9 if s_avg > 0 else 0.0,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+                     "kernel": ("k_round_seq_u8<l1> (sampled rounds, v_sad_u8 tiles over the gathered coordinates)"
+                                if l1 else
+                                "k_round_seq_u8<l2> (sampled rounds, int8 MFMA over the gathered coordinates)"),
+                     "avg_launch_ms": s_avg * 1e3, "launches": samp["launches"], "alg_bytes_per_launch": s_bytes,
+                     "ops_per_launch": s_ops,
+                     "ops_rate_tops": s_ops / s_avg / 1e12 if s_avg > 0 else 0.0}
+        rl_sample["frac"] = rl_sample["achieved"] / HBM_PEAK_GBS
+        if not l1 and params.sampling == 3:
+            rl_sample["traffic"] = stored_traffic(ROUND_TRAFFIC_FILE, ROUND_KERNEL_SRC)
+        if rl_sample["traffic"] and s_avg > 0:
+            rl_sample["traffic_gbs"] = rl_sample["traffic"] / s_avg / 1e9
     else:
         s_ops = (draws * OPS_PER_DRAW + pairs * (OPS_PER_PAIR_L1 if l1 else OPS_PER_PAIR)) / max(1, samp["launches"])
         rl_sample = {"bound": "alu", "achieved": s_ops / s_avg / 1e12 if s_avg > 0 else 0.0,
@@ -637,7 +661,7 @@ def run_adaptive(P, lib, db, X_t, Q_t, params, nidx, ndist, args, warmup, steps,
             rl_sample["alg_bytes_per_launch"] = (N * NQ * 4 + N * NQ * (4 + 1) * later +
                                                  draws / max(1, samp["launches"]))
             if not l1 and params.sampling == 0:
-                rl_sample["traffic"] = stored_traffic()
+                rl_sample["traffic"] = stored_traffic(TRAFFIC_FILE, KERNEL_SRC)
             if rl_sample["traffic"] and s_avg > 0:
                 rl_sample["achieved_hbm_gbs"] = rl_sample["traffic"] / s_avg / 1e9
                 rl_sample["hbm_frac"] = rl_sample["achieved_hbm_gbs"] / HBM_PEAK_GBS

@@ -375,8 +375,6 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   const int64_t n = db->n, m = db->m;
   if (db->dtype == KNN_F32) launch_prep_f32(E.qd, (int32_t)nq, n, m, db->lo, db->hi, db->metric, st);
   launch_admit(E.slots, E.qd, E.sched, E.ctl, db->X, E.B, E.G, st, true);
-  if (E.qt) launch_build_qt(E.slots, (int32_t)E.ns, m, E.nqp, E.qt, st);
-  if (E.q8) launch_build_q8(E.slots, (int32_t)E.ns, m, db->mp, E.q8, E.q8n, db->metric, st);
   const bool lockstep = P.sched.size() == 1;
   // Query-lane batches whose every round runs the fused fold + selection (no
   // candidate-exact, k + 1 <= 128) and whose exact round is one tiled pass
@@ -384,7 +382,10 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   E.G.flagsets = (E.qt && E.q8 && lockstep && !P.any_cexact && P.kmax + 1 <= kPmMaxK1) ? 1 : 0;
   // one coordinate sequence for every point: the points and queries gathered
   // at its coordinates once, then every round is a range of their columns
+  // (the transposed queries of the query-lane sampler are then not read)
   const bool seq = E.seq.xs && E.G.flagsets;
+  if (E.qt && !seq) launch_build_qt(E.slots, (int32_t)E.ns, m, E.nqp, E.qt, st);
+  if (E.q8) launch_build_q8(E.slots, (int32_t)E.ns, m, db->mp, E.q8, E.q8n, db->metric, st);
   if (seq) {
     const int tk = prof_begin(PROF_QL_AUX, st);
     launch_seq_prepare(E.slots, E.sched, (int32_t)E.ns, E.nqp, db->X, n, m, P.qd[0].seed, P.qd[0].norepl,

@@ -500,6 +500,22 @@ def test_subspace_calpha_parity(P, orc, c_alpha):
         assert int(st[q]["coord_evals"]) == rst["coord_evals"]
 
 
+@pytest.mark.parametrize("pdim", [10, 1000])
+def test_subspace_paper_shape_parity(P, orc, pdim):
+    """Section 5 at the paper's shape: n = 1000 points of m = 12288
+    coordinates (x = cQy with subspace dimension p), k = h = 10,
+    delta = 0.001, the C_alpha width at 0.01; three trials each with its own
+    data and seed (one query per call, as in the experiment).  Sets and
+    statistics equal the oracle's."""
+    from knn_inputs import subspace
+    for trial in range(3):
+        X, Q = subspace(10_000 + 97 * pdim + trial, n=1000, m=12288, p=pdim, nq=1)
+        db = P.KnnDB(dev(X))
+        kw = dict(h=10, delta=0.001, seed=trial + 1, alpha_kind=2, c_alpha=0.01)
+        check_query(P, orc, db, X, Q[0], 10, **kw)
+        db.close()
+
+
 def test_uneven_config_sampled(P, orc):
     """The uneven workload at full size (n = 250,000 x m = 1024, 4,096 queries,
     half easy / half hard, k cycling over 1, 10, 100, one seed): every query's
