@@ -487,9 +487,11 @@ def float_bench(args):
     """The float workload (n = 1,000,000 x m = 128 fp32 points from a
     1,000-centre Gaussian mixture, centres N(0,1), sigma = 0.1; k = h = 10,
     delta = 0.05; one seed) on the first --float-queries of its 10,000
-    queries: adaptive (per-slot fp32 kernels, fixed-point sums) against the
-    naive split-BF16 MFMA scan with FP64 rescoring, whose sets and distances
-    are the exact reference for the containment check."""
+    queries: adaptive in the --sampling mode (fixed-point sums; with a shared
+    coordinate sequence every round is a tile pass over the point and query
+    copies gathered at it, otherwise per-slot draws) against the naive
+    split-BF16 MFMA scan with FP64 rescoring, whose sets and distances are the
+    exact reference for the containment check."""
     import torch
     from knn_inputs import gmm_f32
 
@@ -502,8 +504,16 @@ def float_bench(args):
     Qd = torch.from_numpy(Q).cuda()
     db = P.KnnDB(Xd)
     K = 10
-    p = P.default_params(h=10, delta=0.05, seed=3001)
+    p = P.default_params(h=10, delta=0.05, seed=3001, sampling=args.sampling)
+    import ctypes
+    lib = P.lib()
+    P._lib.check(lib.knn_prof_enable(1))
     nidx, ndist = db.naive(Qd, K)
+    torch.cuda.synchronize()
+    cnts = np.zeros(8, dtype=np.uint64)
+    P._lib.check(lib.knn_prof_counters(cnts.ctypes.data_as(ctypes.c_void_p)))
+    P._lib.check(lib.knn_prof_enable(0))
+    rescans = int(cnts[4])
     db.adaptive(Qd, K, p, with_stats=False)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -535,10 +545,12 @@ def float_bench(args):
            "value": nq / ad_s, "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"float: n=1000000 x m=128 fp32, 1000-centre Gaussian mixture sigma=0.1, "
-                                  f"{nq} of 10000 queries, k=10 h=10 delta=0.05"},
+                                  f"{nq} of 10000 queries, k=10 h=10 delta=0.05",
+                      "sampling": SAMPLING_NAMES[args.sampling]},
            "contained": f"{ok}/{nq}",
            "adaptive_ms_per_batch": ad_s * 1e3, "naive_ms_per_batch": nv_s * 1e3,
            "naive_queries_per_s": nq / nv_s, "adaptive_vs_naive": nv_s / ad_s,
+           "naive_exact_rescans": rescans,
            "evals_fraction_of_naive": float(evals.mean() / (X.shape[0] * X.shape[1]))}
     print(json.dumps(out), flush=True)
     return 0

@@ -311,4 +311,19 @@ __device__ __forceinline__ void topk_insert(uint64_t *list, int k, uint64_t &tau
   }
 }
 
+// list: sorted ascending over the lanes; cand: one key per lane (PAD = none).
+// Returns the 64 smallest of both, sorted ascending over the lanes.
+__device__ __forceinline__ uint64_t merge_sorted64(uint64_t list, uint64_t cand) {
+  const int lane = lane_id();
+  uint64_t c = wave_sort_u64(cand);
+  c = wave_bcast_rev_u64(c);  // descending
+  uint64_t v = list < c ? list : c;
+#pragma unroll
+  for (int j = kWave / 2; j > 0; j >>= 1) {
+    const uint64_t o = lane_xor_u64(v, j);
+    v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
+  }
+  return v;
+}
+
 }  // namespace knn

@@ -364,30 +364,46 @@ __device__ void sample_slot_chunk(const Slot *sl, int s, int64_t chunk, const ui
 // result is the same; the rows are read once per 64 slots instead of once
 // per slot.
 constexpr int XF_Q = 64, XF_P = 128, XF_K = 32;
+// Columns [c0, c1) of rows of `stride` floats: the points X (or their copy
+// gathered at a shared coordinate sequence) and the queries (the slots' own
+// rows, or QS [slot][stride] of the gathered queries).  mode 0: the exact
+// round -- the pairs' sums become these columns' sums and the pairs exact;
+// mode 1: a sampled round -- added to the sums of the undecided sampled
+// pairs (round 0: every pair, sums set), round index cur; mode 2: the exact
+// round of sampling without replacement -- the columns not yet sampled are
+// added and the pairs become exact.  Only slots at round `cur` take part.
 template <int MET>
 __global__ __launch_bounds__(NT) void k_exact_f32_tile(const Slot *__restrict__ slots, const float *__restrict__ X,
+                                                       int64_t stride, int64_t c0, int64_t c1,
+                                                       const float *__restrict__ QS, int32_t mode, int32_t cur,
                                                        Bufs B, Geometry G) {
   __shared__ __align__(16) float qs[XF_K][XF_Q + 4];  // (rows of 68 and 132 floats: 16-byte aligned)
   __shared__ __align__(16) float xs[XF_K][XF_P + 4];
   __shared__ const float *qrow[XF_Q];
   __shared__ int qF[XF_Q];
   __shared__ uint8_t take[XF_Q], impl[XF_Q];
-  const int64_t n = G.n, m = G.m;
+  __shared__ int any;
+  const int64_t n = G.n;
   const int ns = G.nslots;
   const int64_t nqt = (ns + XF_Q - 1) / XF_Q, nwork = nqt * ((n + XF_P - 1) / XF_P);
   const int64_t w = xcd_work_item(nwork);
   if (w >= nwork) return;
   const int64_t p0 = (w / nqt) * XF_P;  // query tiles of one point tile back to back (rows from L2)
   const int q0 = (int)(w % nqt) * XF_Q;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
   if (threadIdx.x < XF_Q) {
     const int s = q0 + threadIdx.x;
-    const bool t = s < ns && slots[s].state == 1 && slots[s].cur >= slots[s].R;
+    // (cur < 0: every slot at its exact round)
+    const bool t = s < ns && slots[s].state == 1 && (cur < 0 ? slots[s].cur >= slots[s].R : slots[s].cur == cur);
     take[threadIdx.x] = t ? 1 : 0;
     impl[threadIdx.x] = (t && slots[s].implicit) ? 1 : 0;
-    qrow[threadIdx.x] = t ? reinterpret_cast<const float *>(slots[s].q) : nullptr;
+    qrow[threadIdx.x] = !t ? nullptr : (QS ? QS + (int64_t)s * stride : reinterpret_cast<const float *>(slots[s].q));
     qF[threadIdx.x] = t ? slots[s].F : 0;
+    if (t) any = 1;
   }
   __syncthreads();
+  if (!any) return;  // (block-uniform) no slot of this query tile is at this round
   const int qg = threadIdx.x % 8, pg = threadIdx.x / 8;  // slots 8 qg .. 8 qg + 7, points 4 pg .. 4 pg + 3
   int64_t acc[8][4];
 #pragma unroll
@@ -397,20 +413,20 @@ __global__ __launch_bounds__(NT) void k_exact_f32_tile(const Slot *__restrict__ 
   int F[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) F[a] = qF[8 * qg + a];
-  for (int64_t k0 = 0; k0 < m; k0 += XF_K) {
+  for (int64_t k0 = c0; k0 < c1; k0 += XF_K) {
     // stage the slice transposed: [coordinate][slot] and [coordinate][point]
     for (int e = threadIdx.x; e < XF_Q * XF_K; e += NT) {
       const int ql = e / XF_K, kk = e % XF_K;
       const float *qr = qrow[ql];
-      qs[kk][ql] = (qr && k0 + kk < m) ? qr[k0 + kk] : 0.0f;
+      qs[kk][ql] = (qr && k0 + kk < c1) ? qr[k0 + kk] : 0.0f;
     }
     for (int e = threadIdx.x; e < XF_P * XF_K; e += NT) {
       const int pl = e / XF_K, kk = e % XF_K;
       const int64_t i = p0 + pl;
-      xs[kk][pl] = (i < n && k0 + kk < m) ? X[i * m + k0 + kk] : 0.0f;
+      xs[kk][pl] = (i < n && k0 + kk < c1) ? X[i * stride + k0 + kk] : 0.0f;
     }
     __syncthreads();
-    const int kend = (int)min((int64_t)XF_K, m - k0);
+    const int kend = (int)min((int64_t)XF_K, c1 - k0);
     for (int kk = 0; kk < kend; ++kk) {
       const float4 qa = *reinterpret_cast<const float4 *>(&qs[kk][8 * qg]);
       const float4 qb = *reinterpret_cast<const float4 *>(&qs[kk][8 * qg + 4]);
@@ -439,19 +455,25 @@ __global__ __launch_bounds__(NT) void k_exact_f32_tile(const Slot *__restrict__ 
       const int64_t i = p0 + 4 * pg + b;
       if (i >= n) continue;
       if (!impl[ql] && sa.fl[i] != 0) continue;  // only undecided sampled pairs
-      sa.S[i] = acc[a][b];
-      if (impl[ql]) {
-        sa.fl[i] = FL_EXACT;
-        sa.ri[i] = 0;
+      if (mode == 1) {  // a sampled round
+        if (impl[ql]) {
+          sa.S[i] = acc[a][b];
+          sa.fl[i] = 0;
+        } else {
+          sa.S[i] += acc[a][b];
+        }
+        sa.ri[i] = (uint8_t)cur;
       } else {
+        sa.S[i] = (mode == 2 && !impl[ql]) ? sa.S[i] + acc[a][b] : acc[a][b];
         sa.fl[i] = FL_EXACT;
+        if (impl[ql]) sa.ri[i] = 0;
       }
       ++my_pairs;
     }
   }
   if (G.prof) {  // whole waves reach this point
-    wave_count_add(&prof_copy(G.prof)[0], my_pairs * (uint64_t)(m * 4 + 14));
-    wave_count_add(&prof_copy(G.prof)[2], my_pairs * (uint64_t)m);
+    const uint64_t cols = (uint64_t)(c1 - c0);
+    wave_count_add(&prof_copy(G.prof)[mode == 1 ? 1 : 2], my_pairs * cols);
   }
 }
 
@@ -1116,6 +1138,36 @@ __global__ __launch_bounds__(NT) void k_sample_seq_sparse(const Slot *__restrict
     }
   }
   if (G.prof && my_pts) atomicAdd(&prof_copy(G.prof)[1], my_pts * (uint64_t)(4 * words));
+}
+
+// Float rows at the sequence's coordinates, out[r][t] = row_r[js[t]] (zero
+// where js[t] is none): the points (rows = n) or the running slots' queries
+// (QUERIES, rows = ns).  One row per block at a time, staged in LDS when
+// STAGE (m floats).
+template <bool QUERIES, bool STAGE>
+__global__ __launch_bounds__(NT) void k_seq_gather_f32(const float *__restrict__ X, const Slot *__restrict__ slots,
+                                                       int64_t rows, int64_t m, const uint32_t *__restrict__ js,
+                                                       int64_t kp, float *__restrict__ out) {
+  extern __shared__ __align__(16) float frow[];
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const float *row = nullptr;  // (block-uniform)
+    if constexpr (QUERIES) {
+      if (slots[r].state == 1) row = reinterpret_cast<const float *>(slots[r].q);
+    } else {
+      row = X + r * m;
+    }
+    if constexpr (STAGE) {
+      if (row)
+        for (int64_t j = threadIdx.x; j < m; j += NT) frow[j] = row[j];
+      __syncthreads();
+    }
+    const float *from = STAGE ? frow : row;
+    for (int64_t t = threadIdx.x; t < kp; t += NT) {
+      const uint32_t j = js[t];
+      out[r * kp + t] = (row && j != ~0u) ? from[j] : 0.0f;
+    }
+    if constexpr (STAGE) __syncthreads();
+  }
 }
 
 // Squared norms of gathered rows (x - 128 bytes) over the samples before
@@ -3129,6 +3181,25 @@ void launch_build_qt(const Slot *slots, int32_t ns, int64_t m, int32_t nqp, uint
 
 constexpr size_t kSeqGatherLds = 160 * 1024 - 4096;  // dynamic LDS a gather block may take
 
+void launch_seq_prepare_f32(const Slot *slots, int32_t ns, const float *X, int64_t n, int64_t m, uint64_t seed,
+                            int32_t norepl, const SeqBufs &q, hipStream_t st) {
+  const unsigned cb = (unsigned)std::min<int64_t>((q.kp / 4 + NT - 1) / NT, 1024);
+  hipLaunchKernelGGL(k_seq_coords, dim3(cb), dim3(NT), 0, st, seed, norepl, m, q.tlen, q.kp, q.js);
+  const size_t lds = (size_t)m * 4;
+  const unsigned gx = (unsigned)std::min<int64_t>(n, 8192), gq = (unsigned)std::max<int32_t>(1, ns);
+  if (lds <= 65536) {
+    hipLaunchKernelGGL((k_seq_gather_f32<false, true>), dim3(gx), dim3(NT), lds, st, X, slots, n, m, q.js, q.kp,
+                       q.xf);
+    hipLaunchKernelGGL((k_seq_gather_f32<true, true>), dim3(gq), dim3(NT), lds, st, X, slots, (int64_t)ns, m, q.js,
+                       q.kp, q.qf);
+  } else {
+    hipLaunchKernelGGL((k_seq_gather_f32<false, false>), dim3(gx), dim3(NT), 0, st, X, slots, n, m, q.js, q.kp,
+                       q.xf);
+    hipLaunchKernelGGL((k_seq_gather_f32<true, false>), dim3(gq), dim3(NT), 0, st, X, slots, (int64_t)ns, m, q.js,
+                       q.kp, q.qf);
+  }
+}
+
 void launch_seq_prepare(const Slot *slots, const Sched *sc, int32_t ns, int32_t nqp, const uint8_t *X, int64_t n,
                         int64_t m, uint64_t seed, int32_t norepl, int32_t metric, const SeqBufs &q,
                         const int32_t *xnorm, const int32_t *qnorm, hipStream_t st) {
@@ -3320,17 +3391,25 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
       hipLaunchKernelGGL(k_sample_grp_u8<KNN_METRIC_L2>, grid, dim3(GBT), gbytes, st, slots, X, G.x8, G.xn, G.mp, B, G);
   } else if (G.dtype == KNN_U8) {
     launch_sample_met<KNN_U8>(slots, X, B, G, qlds, qbytes, st);
-  } else if (sample_kind == 1) {
-    // the exact round of a lock-step fp32 batch (every running slot is in
-    // it): one tiled pass over (slots x points)
+  } else if (sample_kind == 1 || (seq && seq->xf && ql && (!ql->exact || ql->norepl))) {
+    // a lock-step fp32 batch (every running slot is at this round): its exact
+    // round as one tiled pass over (slots x points); with a shared coordinate
+    // sequence also its sampled rounds (columns of the gathered copies), and
+    // without replacement the exact round adds the columns not yet sampled
     const int64_t nwork = ((G.nslots + XF_Q - 1) / XF_Q) * ((G.n + XF_P - 1) / XF_P);
-    const float *Xf = reinterpret_cast<const float *>(X);
+    const bool on_seq = seq && seq->xf && ql && (!ql->exact || ql->norepl);
+    const float *Xf = on_seq ? seq->xf : reinterpret_cast<const float *>(X);
+    const int64_t stride = on_seq ? seq->kp : G.m;
+    const int64_t c0 = on_seq ? (int64_t)ql->t0 : 0, c1 = on_seq ? (int64_t)ql->t1 : G.m;
+    const int32_t mode = !on_seq ? 0 : (ql->exact ? 2 : 1);
+    const int32_t cur = ql ? ql->cur : -1;
+    const float *QS = on_seq ? seq->qf : nullptr;
     if (G.metric == KNN_METRIC_L1)
       hipLaunchKernelGGL(k_exact_f32_tile<KNN_METRIC_L1>, dim3((unsigned)xcd_grid(nwork)), dim3(NT), 0, st, slots, Xf,
-                         B, G);
+                         stride, c0, c1, QS, mode, cur, B, G);
     else
       hipLaunchKernelGGL(k_exact_f32_tile<KNN_METRIC_L2>, dim3((unsigned)xcd_grid(nwork)), dim3(NT), 0, st, slots, Xf,
-                         B, G);
+                         stride, c0, c1, QS, mode, cur, B, G);
   } else {
     launch_sample_met<KNN_F32>(slots, X, B, G, qlds, qbytes, st);
   }

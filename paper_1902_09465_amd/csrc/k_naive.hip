@@ -191,21 +191,6 @@ template <int MET>
 constexpr int exact_wa() { return 2; }
 constexpr int CB = 32;                  // candidate buffer per query (<= 64)
 
-// list: sorted ascending over the lanes; cand: one key per lane (PAD = none).
-// Returns the 64 smallest of both, sorted ascending over the lanes.
-__device__ __forceinline__ uint64_t merge_sorted64(uint64_t list, uint64_t cand) {
-  const int lane = lane_id();
-  uint64_t c = wave_sort_u64(cand);
-  c = wave_bcast_rev_u64(c);  // descending
-  uint64_t v = list < c ? list : c;
-#pragma unroll
-  for (int j = kWave / 2; j > 0; j >>= 1) {
-    const uint64_t o = lane_xor_u64(v, j);
-    v = ((lane & j) == 0) ? (o < v ? o : v) : (o > v ? o : v);
-  }
-  return v;
-}
-
 // One block's 64 x 128 tile (queries q0.., points p0..) over the whole K
 // range: x'.q' on the matrix cores (MET = squared l2, shifted int8 rows), or
 // the l1 distance sum_j |x_j - q_j| by v_sad_u8 (MET = l1, zero-padded u8

@@ -8,13 +8,17 @@
 // 2. Error bound per pair: |d~ - d| <= E = c1 |q| |x| + c2 (|q|^2 + |x|^2),
 //    c1 covering the split (3.01 2^-16 per product) and fp32 accumulation of
 //    3m terms (3m 2^-24), doubled for safety; c2 the fp32 epilogue roundings.
-// 3. Each block keeps, per query, the k smallest upper bounds u = d~ + E and
-//    the KL smallest lower bounds l = d~ - E over its range of points.  The
-//    k-th smallest upper bound tau over all ranges bounds d_(k) from above;
-//    every true k-NN point has l <= d <= tau.  A range whose lower-bound list
-//    is full with its largest entry still <= tau may have dropped a candidate:
-//    that query is rescanned exactly.
-// 4. Candidates (l <= tau) are rescored in FP64, summing (x_j - q_j)^2 in
+// 3. Each block keeps, per query and over its range of points, the k
+//    smallest upper bounds u = d~ + E (in a wave's registers, lane j the
+//    j-th smallest, fed through a small LDS buffer), and appends to the
+//    range's candidate list every point whose lower bound l = d~ - E is at
+//    or below the running k-th smallest upper bound tau_r of the points
+//    seen so far.  The k-th smallest upper bound tau over all ranges bounds
+//    d_(k) from above, and tau <= the final tau_r <= every running tau_r
+//    of every range, so every true k-NN point (l <= d <= d_(k) <= tau) is in
+//    a candidate list.  A list that overflows its capacity sends its query
+//    to an exact rescan.
+// 4. Candidates with l <= tau are rescored in FP64, summing (x_j - q_j)^2 in
 //    coordinate order like the CPU reference, and the k smallest by
 //    (distance, index) are returned.
 // The l1 distance has no product form: its tile sums |x_j - q_j| in fp32 on
@@ -81,8 +85,9 @@ __global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ A,
 }
 
 constexpr int FBQ = 64, FBP = 128, FROWB = 80, FDSTR = FBP + 4;
-constexpr int KCU = 64;  // upper-bound list capacity (k <= 64)
-constexpr int KCL = 64;  // lower-bound list capacity per range
+constexpr int KCU = 64;   // upper-bound list capacity (k <= 64): one wave register per query
+constexpr int FCB = 16;   // buffered upper-bound candidates per query before a merge
+constexpr int FCL = 384;  // candidate list capacity per (query, range)
 
 template <int MET>
 __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ Qh, const uint16_t *__restrict__ Ql,
@@ -90,28 +95,81 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
                                                    const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xl,
                                                    const float *__restrict__ xn, const float *__restrict__ xr,
                                                    int64_t nq, int64_t n, int64_t mp, int k, int64_t prange,
-                                                   float c1, float c2, uint64_t *__restrict__ part, int64_t nranges) {
+                                                   float c1, float c2, uint64_t *__restrict__ part,
+                                                   uint64_t *__restrict__ cand, int32_t *__restrict__ ncand,
+                                                   int64_t nranges) {
+  constexpr uint64_t PAD = ~0ull;
+  constexpr int QPW = FBQ / 4;  // queries owned by one wave in the epilogue
   __shared__ __align__(16) uint8_t tiles[FBQ * FDSTR * 4];
   static_assert(2 * (FBQ + FBP) * FROWB <= FBQ * FDSTR * 4, "tile union too small");
   uint8_t *Ah = tiles, *Al = tiles + FBQ * FROWB;
   uint8_t *Bh = tiles + 2 * FBQ * FROWB, *Bl = Bh + FBP * FROWB;
   float *Ds = reinterpret_cast<float *>(tiles);
-  __shared__ uint64_t LU[FBQ * KCU];
-  __shared__ uint64_t LL[FBQ * KCL];
-  __shared__ uint64_t TU[FBQ], TL[FBQ];
+  __shared__ uint64_t Cb[FBQ][FCB];
+  // per query of the block: its sorted upper-bound list (entry j the j-th
+  // smallest, PAD while fewer than k), the count of its LDS buffer and of
+  // its candidate list in this range, and its norms
+  __shared__ uint64_t Lq[FBQ][kWave];
+  __shared__ uint64_t tauq[FBQ];  // entry k - 1 of the query's list
+  __shared__ int cbq[FBQ], ncq[FBQ];
+  __shared__ float qnq[FBQ], qrq[FBQ];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int64_t q0 = (int64_t)blockIdx.y * FBQ;
   const int64_t pr0 = (int64_t)blockIdx.x * prange;
   const int64_t pr1 = std::min(n, pr0 + prange);
-  for (int j = tid; j < FBQ * KCU; j += 256) LU[j] = ~0ull - (uint64_t)(j % KCU);
-  for (int j = tid; j < FBQ * KCL; j += 256) LL[j] = ~0ull - (uint64_t)(j % KCL);
-  for (int j = tid; j < FBQ; j += 256) {
-    TU[j] = ~0ull;
-    TL[j] = ~0ull;
-  }
   const int wq = wave >> 1, wp = wave & 1;
+  for (int j = tid; j < FBQ * kWave; j += 256) Lq[j / kWave][j % kWave] = PAD;
+  if (tid < FBQ) {
+    const int64_t q = q0 + tid;
+    tauq[tid] = PAD;
+    cbq[tid] = 0;
+    ncq[tid] = 0;
+    qnq[tid] = (MET == KNN_METRIC_L1 || q >= nq) ? 0.0f : qn[q];
+    qrq[tid] = (MET == KNN_METRIC_L1 || q >= nq) ? 0.0f : qr[q];
+  }
   __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  // squared l2: the next 64-byte K slice of the tile's query and point rows
+  // (hi and lo), loaded into registers one slice ahead
+  v4i_f pah = v4i_f{0, 0, 0, 0}, pal = v4i_f{0, 0, 0, 0}, pbh[2], pbl[2];
+  auto fetch = [&](int64_t pt, int64_t k0) {
+    {
+      const int r = tid >> 2, c = (tid & 3) * 16;
+      pah = v4i_f{0, 0, 0, 0};
+      pal = v4i_f{0, 0, 0, 0};
+      if (q0 + r < nq) {
+        pah = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Qh + (q0 + r) * mp + k0) + c);
+        pal = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Ql + (q0 + r) * mp + k0) + c);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = (tid >> 2) + 64 * h, c = (tid & 3) * 16;
+      pbh[h] = v4i_f{0, 0, 0, 0};
+      pbl[h] = v4i_f{0, 0, 0, 0};
+      if (pt + r < pr1) {
+        pbh[h] = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Xh + (pt + r) * mp + k0) + c);
+        pbl[h] = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Xl + (pt + r) * mp + k0) + c);
+      }
+    }
+  };
+  if constexpr (MET != KNN_METRIC_L1) {
+    if (pr0 < pr1) fetch(pr0, 0);
+  }
   for (int64_t p0 = pr0; p0 < pr1; p0 += FBP) {
+    // this lane's two points' norms, loaded before the K loop so that their
+    // latency is hidden (every query of the wave uses them)
+    float xnv[2] = {0.0f, 0.0f}, xrv[2] = {0.0f, 0.0f};
+    if constexpr (MET != KNN_METRIC_L1) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t p = p0 + lane + 64 * h;
+        if (p < pr1) {
+          xnv[h] = xn[p];
+          xrv[h] = xr[p];
+        }
+      }
+    }
     v4f_f acc[2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -162,28 +220,25 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
       }
     } else
     for (int64_t k0 = 0; k0 < mp; k0 += 32) {  // 32 bf16 = 64 bytes per row per step
+      // the prefetched slice into LDS, then the next one's loads (this
+      // tile's next slice, or the next tile's first) in flight while this
+      // one is consumed -- and, for a tile's last slice, during the epilogue
       {
         const int r = tid >> 2, c = (tid & 3) * 16;
-        v4i_f vh = v4i_f{0, 0, 0, 0}, vl = v4i_f{0, 0, 0, 0};
-        if (q0 + r < nq) {
-          vh = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Qh + (q0 + r) * mp + k0) + c);
-          vl = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Ql + (q0 + r) * mp + k0) + c);
-        }
-        *reinterpret_cast<v4i_f *>(Ah + r * FROWB + c) = vh;
-        *reinterpret_cast<v4i_f *>(Al + r * FROWB + c) = vl;
+        *reinterpret_cast<v4i_f *>(Ah + r * FROWB + c) = pah;
+        *reinterpret_cast<v4i_f *>(Al + r * FROWB + c) = pal;
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int r = (tid >> 2) + 64 * h, c = (tid & 3) * 16;
-        v4i_f vh = v4i_f{0, 0, 0, 0}, vl = v4i_f{0, 0, 0, 0};
-        if (p0 + r < pr1) {
-          vh = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Xh + (p0 + r) * mp + k0) + c);
-          vl = *reinterpret_cast<const v4i_f *>(reinterpret_cast<const uint8_t *>(Xl + (p0 + r) * mp + k0) + c);
-        }
-        *reinterpret_cast<v4i_f *>(Bh + r * FROWB + c) = vh;
-        *reinterpret_cast<v4i_f *>(Bl + r * FROWB + c) = vl;
+        *reinterpret_cast<v4i_f *>(Bh + r * FROWB + c) = pbh[h];
+        *reinterpret_cast<v4i_f *>(Bl + r * FROWB + c) = pbl[h];
       }
       __syncthreads();
+      if (k0 + 32 < mp)
+        fetch(p0, k0 + 32);
+      else if (p0 + FBP < pr1)
+        fetch(p0 + FBP, 0);
       v8bf_f ah[2], al[2], bh[4], bl[4];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
@@ -216,48 +271,106 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
         for (int v = 0; v < 4; ++v) {
           const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
           const int pl = 64 * wp + 16 * b + (lane & 15);
-          float d = 0.0f;
-          if (p0 + pl < pr1 && q0 + ql < nq)
-            d = MET == KNN_METRIC_L1 ? acc[a][b][v] : (qn[q0 + ql] + xn[p0 + pl]) - 2.0f * acc[a][b][v];
-          Ds[ql * FDSTR + pl] = d;
+          // the l1 sum, or the dot product q.x (the epilogue adds the norms)
+          Ds[ql * FDSTR + pl] = acc[a][b][v];
         }
     __syncthreads();
-#pragma unroll 1
-    for (int t = 0; t < FBQ / 4; ++t) {
-      const int ql = wave * (FBQ / 4) + t;
-      if (q0 + ql >= nq) break;
-      const float qnv = MET == KNN_METRIC_L1 ? 0.0f : qn[q0 + ql], qrv = MET == KNN_METRIC_L1 ? 0.0f : qr[q0 + ql];
+    // per query of this wave: upper bounds below the running k-th one go to
+    // the LDS buffer (merged into the list when it would overflow); points
+    // whose lower bound is at or below it join the range's candidates
+#pragma unroll 2
+    for (int t = 0; t < QPW; ++t) {
+      const int ql = wave * QPW + t;
+      const int64_t q = q0 + ql;
+      if (q >= nq) break;  // (wave-uniform)
+      const float qnv = qnq[ql], qrv = qrq[ql];
       uint64_t cu[2], cl[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int pl = lane + 64 * h;
         const int64_t p = p0 + pl;
+        cu[h] = PAD;
+        cl[h] = PAD;
         if (p < pr1) {
-          const float d = Ds[ql * FDSTR + pl];
-          const float E = MET == KNN_METRIC_L1 ? c1 * d : c1 * qrv * xr[p] + c2 * (qnv + xn[p]);
+          const float dot = Ds[ql * FDSTR + pl];
+          const float d = MET == KNN_METRIC_L1 ? dot : (qnv + xnv[h]) - 2.0f * dot;
+          const float E = MET == KNN_METRIC_L1 ? c1 * d : c1 * qrv * xrv[h] + c2 * (qnv + xnv[h]);
           cu[h] = ((uint64_t)fkey(d + E) << 32) | (uint64_t)p;
           cl[h] = ((uint64_t)fkey(d - E) << 32) | (uint64_t)p;
-        } else {
-          cu[h] = ~0ull;
-          cl[h] = ~0ull;
         }
       }
-      uint64_t tu = TU[ql], tl = TL[ql];
-      topk_insert<KCU>(LU + ql * KCU, k, tu, cu[0], cu[1]);
-      topk_insert<KCL>(LL + ql * KCL, KCL, tl, cl[0], cl[1]);
-      if (lane == 0) {
-        TU[ql] = tu;
-        TL[ql] = tl;
+      uint64_t tau = tauq[ql];
+      if (tau == PAD) {
+        // until the list holds k upper bounds, this tile's go straight into
+        // it, so that the bound below is finite from the first tile on
+        const int cb = cbq[ql];
+        uint64_t L = Lq[ql][lane];
+        if (cb > 0) L = merge_sorted64(L, lane < cb ? Cb[ql][lane] : PAD);
+        L = merge_sorted64(L, cu[0]);
+        L = merge_sorted64(L, cu[1]);
+        cu[0] = PAD;
+        cu[1] = PAD;
+        Lq[ql][lane] = L;
+        tau = wave_bcast_u64(L, k - 1);
+        if (lane == 0) {
+          cbq[ql] = 0;
+          tauq[ql] = tau;
+        }
+      }
+      // tau: the k-th smallest upper bound of the points seen so far (the
+      // buffered ones left out: a larger value, so a superset of the candidates)
+      const uint32_t tau_key = (uint32_t)(tau >> 32);
+      const bool g0 = cl[0] != PAD && (uint32_t)(cl[0] >> 32) <= tau_key;
+      const bool g1 = cl[1] != PAD && (uint32_t)(cl[1] >> 32) <= tau_key;
+      const uint64_t m0 = __ballot(g0), m1 = __ballot(g1);
+      if (m0 | m1) {  // (wave-uniform) candidates: lower bound <= tau
+        const int nc = ncq[ql];
+        uint64_t *dst = cand + (q * nranges + blockIdx.x) * (int64_t)FCL;
+        const int n0 = __popcll(m0);
+        const int pa = nc + __popcll(m0 & lt), pb = nc + n0 + __popcll(m1 & lt);
+        if (g0 && pa < FCL) dst[pa] = cl[0];
+        if (g1 && pb < FCL) dst[pb] = cl[1];
+        if (lane == 0) ncq[ql] = nc + n0 + __popcll(m1);
+      }
+      const bool a0 = cu[0] < tau, a1 = cu[1] < tau;
+      const uint64_t u0 = __ballot(a0), u1 = __ballot(a1);
+      if (u0 | u1) {  // (wave-uniform) upper bounds below tau
+        const int n0 = __popcll(u0), n1 = __popcll(u1);
+        const int cb = cbq[ql];
+        if (cb + n0 + n1 > FCB) {
+          // does not fit: the buffer (written in earlier tiles, before the
+          // last barrier) and this tile's candidates merge into the list
+          uint64_t L = Lq[ql][lane];
+          if (cb > 0) L = merge_sorted64(L, lane < cb ? Cb[ql][lane] : PAD);
+          L = merge_sorted64(L, a0 ? cu[0] : PAD);
+          L = merge_sorted64(L, a1 ? cu[1] : PAD);
+          Lq[ql][lane] = L;
+          const uint64_t nt = wave_bcast_u64(L, k - 1);
+          if (lane == 0) {
+            cbq[ql] = 0;
+            tauq[ql] = nt;
+          }
+        } else {
+          if (a0) Cb[ql][cb + __popcll(u0 & lt)] = cu[0];
+          if (a1) Cb[ql][cb + n0 + __popcll(u1 & lt)] = cu[1];
+          if (lane == 0) cbq[ql] = cb + n0 + n1;
+        }
       }
     }
     __syncthreads();
   }
-  for (int t = 0; t < FBQ / 4; ++t) {
-    const int ql = wave * (FBQ / 4) + t;
-    if (q0 + ql >= nq) break;
-    uint64_t *dst = part + ((q0 + ql) * nranges + blockIdx.x) * (int64_t)(k + KCL);
-    for (int j = lane; j < k; j += 64) dst[j] = LU[ql * KCU + j];
-    for (int j = lane; j < KCL; j += 64) dst[k + j] = LL[ql * KCL + j];
+  // final merge; per query the range's k smallest upper bounds and the
+  // length of its candidate list
+#pragma unroll 1
+  for (int t = 0; t < QPW; ++t) {
+    const int ql = wave * QPW + t;
+    const int64_t q = q0 + ql;
+    if (q >= nq) break;
+    uint64_t L = Lq[ql][lane];
+    const int cb = cbq[ql];
+    if (cb > 0) L = merge_sorted64(L, lane < cb ? Cb[ql][lane] : PAD);
+    if (lane < k) part[(q * nranges + blockIdx.x) * (int64_t)k + lane] = L;
+    if (lane == 0) ncand[q * nranges + blockIdx.x] = ncq[ql];
   }
 }
 
@@ -280,20 +393,20 @@ __device__ __forceinline__ double exact_f64(const float *__restrict__ X, const f
 
 constexpr int FCAP = 2048;  // candidate capacity per query in the merge
 
-__global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__restrict__ part, int64_t nranges, int k,
+__global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__restrict__ part,
+                                                          const uint64_t *__restrict__ candl,
+                                                          const int32_t *__restrict__ ncand, int64_t nranges, int k,
                                                           const float *__restrict__ X, const float *__restrict__ Q,
                                                           int64_t m, int met, int64_t *__restrict__ out_idx,
                                                           double *__restrict__ out_dist, int32_t *__restrict__ flag) {
   const int64_t q = blockIdx.x;
-  const int64_t w = k + KCL;
-  const uint64_t *pq = part + q * nranges * w;
+  const uint64_t *pq = part + q * nranges * k;
   __shared__ SelScratch ss;
   __shared__ uint64_t key[FCAP];
   __shared__ int32_t id[FCAP];
   __shared__ int cnt, bad;
   int less;
-  const uint64_t tk =
-      block_kth_gen<1024>(nranges * k, [&](int64_t t) { return pq[(t / k) * w + (t % k)]; }, k, ss, &less);
+  const uint64_t tk = block_kth_gen<1024>(nranges * k, [&](int64_t t) { return pq[t]; }, k, ss, &less);
   const float tau = fkey_inv((uint32_t)(tk >> 32));
   const uint32_t tau_key = fkey(tau + fabsf(tau) * 1e-6f + 1e-30f);  // tiny margin over fp32 rounding
   if (threadIdx.x == 0) {
@@ -301,25 +414,20 @@ __global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__rest
     bad = 0;
   }
   __syncthreads();
-  // completeness: a full lower-bound list whose largest entry is <= tau may have dropped candidates
-  for (int64_t r = threadIdx.x; r < nranges; r += 1024) {
-    const uint64_t *L = pq + r * w + k;
-    uint64_t mx = 0;
-    bool full = true;
-    for (int j = 0; j < KCL; ++j) {
-      if (L[j] >= 0xFFFFFFFF00000000ull) full = false;  // a sentinel: the range had fewer points
-      mx = L[j] > mx ? L[j] : mx;
-    }
-    if (full && (uint32_t)(mx >> 32) <= tau_key) atomicOr(&bad, 1);
-  }
+  // a range whose candidate list overflowed may have dropped a candidate
+  for (int64_t r = threadIdx.x; r < nranges; r += 1024)
+    if (ncand[q * nranges + r] > FCL) atomicOr(&bad, 1);
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < nranges * KCL; t += 1024) {
-    const uint64_t e = pq[(t / KCL) * w + k + (t % KCL)];
-    if (e >= 0xFFFFFFFF00000000ull) continue;
-    if ((uint32_t)(e >> 32) <= tau_key) {
-      const int pos = atomicAdd(&cnt, 1);
-      if (pos < FCAP) id[pos] = (int32_t)(e & 0xFFFFFFFFu);
-      else atomicOr(&bad, 1);
+  if (!bad) {
+    for (int64_t t = threadIdx.x; t < nranges * FCL; t += 1024) {
+      const int64_t r = t / FCL, j = t % FCL;
+      if (j >= ncand[q * nranges + r]) continue;
+      const uint64_t e = candl[(q * nranges + r) * FCL + j];
+      if ((uint32_t)(e >> 32) <= tau_key) {
+        const int pos = atomicAdd(&cnt, 1);
+        if (pos < FCAP) id[pos] = (int32_t)(e & 0xFFFFFFFFu);
+        else atomicOr(&bad, 1);
+      }
     }
   }
   __syncthreads();
@@ -417,13 +525,17 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
   const float c1 = l1 ? (float)(2.0 * ((double)m + 2.0) * u24) : (float)(2.0 * 2.0 * (3.01 * u16 + 3.1 * (double)m * u24));
   const float c2 = (float)(8.0 * u24);
   const size_t b_qs = (size_t)nq * mp * 2 * 2, b_qn = sizeof(float) * nq * 2 + 512,
-               b_part = sizeof(uint64_t) * nq * nranges * (k + KCL), b_flag = sizeof(int32_t) * nq + 256;
+               b_part = sizeof(uint64_t) * nq * nranges * k + 256,
+               b_cand = sizeof(uint64_t) * nq * nranges * FCL, b_nc = sizeof(int32_t) * nq * nranges + 256,
+               b_flag = sizeof(int32_t) * nq + 256;
   void *ws = nullptr;
-  HIP_TRY(hipMallocAsync(&ws, b_qs + b_qn + b_part + b_flag, st));
+  HIP_TRY(hipMallocAsync(&ws, b_qs + b_qn + b_part + b_cand + b_nc + b_flag, st));
   uint16_t *Qh = (uint16_t *)ws, *Ql = Qh + (size_t)nq * mp;
   float *qn = (float *)((uint8_t *)ws + b_qs), *qr = qn + nq;
   uint64_t *part = (uint64_t *)((uint8_t *)ws + b_qs + b_qn);
-  int32_t *flag = (int32_t *)((uint8_t *)ws + b_qs + b_qn + b_part);
+  uint64_t *candl = (uint64_t *)((uint8_t *)ws + b_qs + b_qn + b_part);
+  int32_t *ncand = (int32_t *)((uint8_t *)ws + b_qs + b_qn + b_part + b_cand);
+  int32_t *flag = (int32_t *)((uint8_t *)ws + b_qs + b_qn + b_part + b_cand + b_nc);
   int tok = prof_begin(PROF_NAIVE_REST, st);
   if (l1)  // zero-padded f32 query rows (nq x mp x 4 bytes, the size of the split pair)
     launch_pad_rows(reinterpret_cast<const uint8_t *>(dq), nq, m, mp, 4, reinterpret_cast<uint8_t *>(Qh), st);
@@ -434,15 +546,15 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
   if (l1)
     hipLaunchKernelGGL(k_naive_f32<KNN_METRIC_L1>, dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st, Qh,
                        nullptr, nullptr, nullptr, reinterpret_cast<const uint16_t *>(db->xpad), nullptr, nullptr,
-                       nullptr, nq, n, mp, k, prange, c1, c2, part, nranges);
+                       nullptr, nq, n, mp, k, prange, c1, c2, part, candl, ncand, nranges);
   else
     hipLaunchKernelGGL(k_naive_f32<KNN_METRIC_L2>, dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st, Qh, Ql,
                        qn, qr, db->xbf, db->xbf + cells, db->norm_f, db->rownorm, nq, n, mp, k, prange, c1, c2, part,
-                       nranges);
+                       candl, ncand, nranges);
   // work units: l2 three BF16 products of 2 operations; l1 a difference and an addition
   prof_end(tok, st, (l1 ? 2.0 : 3.0 * 2.0) * (double)nq * (double)n * (double)m);
   tok = prof_begin(PROF_NAIVE_REST, st);
-  hipLaunchKernelGGL(k_naive_f32_merge, dim3((unsigned)nq), dim3(1024), 0, st, part, nranges, k,
+  hipLaunchKernelGGL(k_naive_f32_merge, dim3((unsigned)nq), dim3(1024), 0, st, part, candl, ncand, nranges, k,
                      (const float *)db->X, dq, m, db->metric, out_idx, out_dist, flag);
   prof_end(tok, st, 0.0);
   HIP_TRY(hipGetLastError());

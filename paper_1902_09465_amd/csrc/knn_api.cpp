@@ -102,6 +102,7 @@ Knobs knobs_for(const knn_db_s *db) {
   k.stage_rows = env_int("KNN_STAGE_ROWS", k.stage_rows);
   k.graph = env_int("KNN_GRAPH", k.graph);
   k.sparse_div = env_int("KNN_SPARSE_DIV", k.sparse_div);
+  k.seq = env_int("KNN_SEQ", k.seq);
   return k;
 }
 
@@ -179,12 +180,15 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   // a shared coordinate sequence: its coordinates, the points and queries at
   // them, and their prefix norms at the round boundaries
   const bool seq = q8x && seq_tlen > 0;
-  const int64_t kp = seq ? ((int64_t)seq_tlen + 63) / 64 * 64 : 0;
-  const size_t o_js = take(seq ? (size_t)kp * 4 : 0);
+  const bool seqf = db->dtype == KNN_F32 && seq_tlen > 0;  // fp32: float copies, no norms
+  const int64_t kp = (seq || seqf) ? ((int64_t)seq_tlen + 63) / 64 * 64 : 0;
+  const size_t o_js = take((seq || seqf) ? (size_t)kp * 4 : 0);
   const size_t o_xs = take(seq ? (size_t)n * kp : 0);
   const size_t o_qs = take(seq ? (size_t)nqp * kp : 0);
   const size_t o_xsn = take(seq ? (size_t)seq_nb * n * 4 : 0);
   const size_t o_qsn = take(seq ? (size_t)seq_nb * nqp * 4 : 0);
+  const size_t o_xf = take(seqf ? (size_t)n * kp * 4 : 0);
+  const size_t o_qf = take(seqf ? (size_t)ns * kp * 4 : 0);
   void *base = nullptr;
   if (async_alloc) {
     hipMemPool_t pool = engine_pool();
@@ -217,6 +221,14 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   E.q8n = q8x ? (int32_t *)at(o_q8n) : nullptr;
   E.nqp = nqp;
   E.seq = SeqBufs{};
+  if (seqf) {
+    E.seq.js = (uint32_t *)at(o_js);
+    E.seq.xf = (float *)at(o_xf);
+    E.seq.qf = (float *)at(o_qf);
+    E.seq.kp = kp;
+    E.seq.tlen = seq_tlen;
+    E.seq.nb = seq_nb;
+  }
   if (seq) {
     E.seq.js = (uint32_t *)at(o_js);
     E.seq.xs = (int8_t *)at(o_xs);
@@ -279,7 +291,7 @@ int engine_destroy(Engine &E) {
 
 void engine_step(Engine &E, bool any_cexact, int sample_kind, int stage_rows, const QlRound *ql) {
   launch_step(E.slots, E.qd, E.sched, E.ctl, E.db->X, E.B, E.G, any_cexact, E.st, sample_kind, stage_rows, ql, E.qt,
-              E.nqp, E.qsum, E.q8, E.q8n, E.seq.xs ? &E.seq : nullptr);
+              E.nqp, E.qsum, E.q8, E.q8n, (E.seq.xs || E.seq.xf) ? &E.seq : nullptr);
 }
 
 int make_qdesc(const knn_db_s *db, int32_t k, const knn_params &pp, QDesc &d, Sched &sc) {
@@ -352,10 +364,17 @@ static int prepare(knn_db_s *db, const void *dq, int64_t nq, const int32_t *host
 // of the points and queries gathered at the sequence's coordinates: the
 // samples they hold (the last sampled target; with the permutation, all m,
 // so the exact round adds the rest) and the norm boundaries.
-static void seq_geometry(const knn_db_s *db, const Prepared &P, bool query_lane, int32_t &tlen, int32_t &nb) {
+static void seq_geometry(const knn_db_s *db, const Prepared &P, const Knobs &K, bool query_lane, bool same,
+                         int64_t nq, int64_t ns, int32_t &tlen, int32_t &nb) {
   tlen = nb = 0;
-  if (!query_lane || P.qd.empty() || !P.qd[0].shared || P.sched.size() != 1 || P.any_cexact || P.kmax + 1 > kPmMaxK1)
+  if (!K.seq || P.qd.empty() || !P.qd[0].shared || P.sched.size() != 1) return;
+  if (db->dtype == KNN_F32) {
+    // a lock-step fp32 batch whose queries share seed and draw kind: every
+    // round as tiles over the float copies
+    if (!same || nq > ns) return;
+  } else if (!query_lane || P.any_cexact || P.kmax + 1 > kPmMaxK1) {
     return;
+  }
   const int32_t R = P.sched[0].R;
   if (P.qd[0].norepl) {
     tlen = (int32_t)db->m;
@@ -386,6 +405,14 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   const bool seq = E.seq.xs && E.G.flagsets;
   if (E.qt && !seq) launch_build_qt(E.slots, (int32_t)E.ns, m, E.nqp, E.qt, st);
   if (E.q8) launch_build_q8(E.slots, (int32_t)E.ns, m, db->mp, E.q8, E.q8n, db->metric, st);
+  const bool seqf = E.seq.xf != nullptr && lockstep;
+  if (seqf) {
+    const int tk = prof_begin(PROF_QL_AUX, st);
+    launch_seq_prepare_f32(E.slots, (int32_t)E.ns, (const float *)db->X, n, m, P.qd[0].seed, P.qd[0].norepl, E.seq,
+                           st);
+    prof_end(tk, st, 0.0);
+    prof_add_host(1, (uint64_t)E.seq.tlen);
+  }
   if (seq) {
     const int tk = prof_begin(PROF_QL_AUX, st);
     launch_seq_prepare(E.slots, E.sched, (int32_t)E.ns, E.nqp, db->X, n, m, P.qd[0].seed, P.qd[0].norepl,
@@ -402,7 +429,9 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
       if (b_r >= K.stage_min) stage = stage_rows;
     }
     QlRound qr{};
-    const bool ql = E.qt && (t < P.sched[0].R || (t == P.sched[0].R && E.q8));
+    // the round's descriptor: query-lane batches, and lock-step fp32 batches
+    // (whose rounds run as tiles)
+    const bool ql = (E.qt && (t < P.sched[0].R || (t == P.sched[0].R && E.q8))) || seqf;
     if (ql) {
       qr.seed = P.qd[0].seed;
       qr.norepl = P.qd[0].norepl;
@@ -410,7 +439,7 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
       qr.exact = t >= P.sched[0].R;
       qr.t0 = (t && !qr.exact) ? (uint32_t)P.sched[0].T[t - 1] : 0u;
       qr.t1 = qr.exact ? 0u : (uint32_t)P.sched[0].T[t];
-      if (seq && qr.exact && qr.norepl) {  // the coordinates not sampled yet
+      if ((seq || seqf) && qr.exact && qr.norepl) {  // the coordinates not sampled yet
         qr.t0 = t ? (uint32_t)P.sched[0].T[t - 1] : 0u;
         qr.t1 = (uint32_t)m;
       }
@@ -465,7 +494,7 @@ static int run_graph(knn_db_s *db, const Prepared &P, int64_t nq, int64_t ns, bo
   put(hdr, sizeof(hdr));
   put(&K, sizeof(K));
   put(P.sched.data(), sizeof(Sched) * P.sched.size());
-  if (query_lane) {  // the shared seed and draw kind are arguments of the captured sampling launches
+  if (query_lane || (same && P.qd[0].shared)) {  // the shared seed and draw kind are arguments of captured launches
     const uint64_t sd[2] = {P.qd[0].seed, (uint64_t)P.qd[0].norepl | ((uint64_t)P.qd[0].shared << 1)};
     put(sd, sizeof(sd));
   }
@@ -478,7 +507,7 @@ static int run_graph(knn_db_s *db, const Prepared &P, int64_t nq, int64_t ns, bo
     std::unique_ptr<Plan> np(new Plan());
     np->key = key;
     int32_t seq_tlen = 0, seq_nb = 0;
-    seq_geometry(db, P, query_lane, seq_tlen, seq_nb);
+    seq_geometry(db, P, K, query_lane, same, nq, ns, seq_tlen, seq_nb);
     int rc = engine_create(np->E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, false, same, query_lane,
                            seq_tlen, seq_nb);
     if (rc != KNN_OK) return rc;
@@ -553,7 +582,7 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
     return run_graph(db, P, nq, ns, same, query_lane, K, st);
   Engine E;
   int32_t seq_tlen = 0, seq_nb = 0;
-  seq_geometry(db, P, query_lane, seq_tlen, seq_nb);
+  seq_geometry(db, P, K, query_lane, same, nq, ns, seq_tlen, seq_nb);
   int rc = engine_create(E, db, ns, P.kmax, P.cmax, nq, (int64_t)P.sched.size(), st, true, same, query_lane, seq_tlen,
                          seq_nb);
   if (rc != KNN_OK) return rc;

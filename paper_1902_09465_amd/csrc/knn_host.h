@@ -24,6 +24,7 @@ struct Knobs {
   int32_t graph = 1;        // capture and replay repeated batches
   int32_t sparse_div = 16;  // point-major batches: slots with <= n / sparse_div undecided points switch
                             // to per-slot lists (0: never)
+  int32_t seq = 1;          // shared coordinate sequences: rounds over gathered copies allowed
 };
 }  // namespace knn
 
@@ -112,6 +113,8 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
 void launch_seq_prepare(const Slot *slots, const Sched *sc, int32_t ns, int32_t nqp, const uint8_t *X, int64_t n,
                         int64_t m, uint64_t seed, int32_t norepl, int32_t metric, const SeqBufs &q,
                         const int32_t *xnorm, const int32_t *qnorm, hipStream_t st);
+void launch_seq_prepare_f32(const Slot *slots, int32_t ns, const float *X, int64_t n, int64_t m, uint64_t seed,
+                            int32_t norepl, const SeqBufs &q, hipStream_t st);
 void launch_round_seq_u8(const Slot *slots, const SeqBufs &q, int32_t lo, int32_t hi, int64_t t0, int64_t t1,
                          const uint8_t *A, uint32_t *D, int32_t nqp, const Bufs &B, const Geometry &G, int32_t cur,
                          int32_t impl, int32_t exact, hipStream_t st);

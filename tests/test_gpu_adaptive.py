@@ -2,6 +2,7 @@
 oracle -- returned sets, statistics and per-round state, bit-exact."""
 from __future__ import annotations
 
+import ctypes
 import os
 
 import numpy as np
@@ -570,6 +571,45 @@ def test_sampling_modes_batched(P, orc, sampling):
         ref, rst = orc.adaptive(X, Q[q], 10, oparams(orc, **kw))
         assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
         assert int(base[2][q]["coord_evals"]) == rst["coord_evals"]
+
+
+@pytest.mark.parametrize("sampling", [2, 3])
+@pytest.mark.parametrize("metric", ["l2", "l1"])
+def test_f32_shared_sequence_batched(P, orc, monkeypatch, sampling, metric):
+    """A float batch of 48 queries with one seed and one coordinate sequence
+    for all points: every round is a tile pass over the point and query
+    copies gathered at the sequence (without replacement the exact round adds
+    the columns not yet sampled).  Equal to the same batch with the copies
+    switched off (per-pair draws of the same sequence), and to the oracle on
+    sampled queries (indices and statistics)."""
+    X, Q = gmm_f32(83, n=6007, m=300, n_centres=8, sigma=0.3, nq=48)
+    db = P.KnnDB(dev(X), metric=metric)
+    kw = dict(h=8, delta=0.02, seed=91, sampling=sampling, b0=16, growth=2.0)
+    lib = P.lib()
+
+    def gathers():  # launches of the sequence gather (profiling kind 8) since the last enable
+        ms, nl, u = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        P._lib.check(lib.knn_prof_read(8, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(u)))
+        return nl.value
+
+    P._lib.check(lib.knn_prof_enable(1))
+    try:
+        base = db.adaptive(dev(Q), 8, P.default_params(**kw))
+        assert gathers() == 1, "the batch did not run on the gathered copies"
+        monkeypatch.setenv("KNN_SEQ", "0")
+        P._lib.check(lib.knn_prof_enable(1))
+        alt = db.adaptive(dev(Q), 8, P.default_params(**kw))
+        assert gathers() == 0
+    finally:
+        P._lib.check(lib.knn_prof_enable(0))
+    assert torch.equal(base[0], alt[0]) and torch.equal(base[1], alt[1]) and np.array_equal(base[2], alt[2])
+    idx, cnt = base[0].cpu().numpy(), base[1].cpu().numpy()
+    refs = oracle_many(orc, X, Q, [8] * 48, dict(kw), range(0, 48, 7)) if metric == "l2" else \
+        [orc.adaptive(X, Q[q], 8, oparams(orc, **kw), metric=1) for q in range(0, 48, 7)]
+    for q, (ref, rst) in zip(range(0, 48, 7), refs):
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert int(base[2][q]["coord_evals"]) == rst["coord_evals"], q
+        assert int(base[2][q]["rounds"]) == rst["rounds"], q
 
 
 def test_batched_int_config_sampled(P, orc):
