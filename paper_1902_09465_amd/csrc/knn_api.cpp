@@ -550,7 +550,8 @@ static int run_graph(knn_db_s *db, const Prepared &P, int64_t nq, int64_t ns, bo
 // Runs the slot engine over the prepared queries.  stop_after > 0 (debug
 // state dump) runs every query in a slot of its own, freezes each after
 // that many decide steps and leaves the engine allocated in *keep.
-static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int32_t stop_after, Engine *keep) {
+static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int32_t stop_after, Engine *keep,
+                      bool allow_graph = true) {
   const int64_t n = db->n, m = db->m;
   const Knobs K = knobs_for(db);
   const size_t per_slot = engine_slot_bytes(n, P.kmax, P.cmax);
@@ -570,6 +571,26 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
   for (int64_t q = 1; q < nq && same; ++q)
     same = P.qd[q].seed == P.qd[0].seed && P.qd[q].sched == P.qd[0].sched && P.qd[q].norepl == P.qd[0].norepl &&
            P.qd[q].shared == P.qd[0].shared;
+  // More queries than slots, all with one seed and schedule: consecutive
+  // lock-step batches of at most ns queries (equal sizes but the last, which
+  // runs uncaptured so that the cached graph keeps the common shape), each on
+  // the lock-step paths, instead of recycling slots round by round.
+  if (same && nq > ns && P.sched.size() == 1 && stop_after == 0 && !keep) {
+    const int64_t nch = (nq + ns - 1) / ns, c = (nq + nch - 1) / nch;
+    for (int64_t q0 = 0; q0 < nq; q0 += c) {
+      const int64_t len = std::min(c, nq - q0);
+      Prepared Pc;
+      Pc.qd.assign(P.qd.begin() + q0, P.qd.begin() + q0 + len);
+      Pc.sched = P.sched;
+      Pc.kmax = P.kmax;
+      Pc.cmax = P.cmax;
+      Pc.rmax = P.rmax;
+      Pc.any_cexact = P.any_cexact;
+      const int rc = run_engine(db, Pc, len, st, 0, nullptr, allow_graph && len == c);
+      if (rc != KNN_OK) return rc;
+    }
+    return KNN_OK;
+  }
   // Query-lane sampling: with every query in flight at once (nq <= ns) and
   // one seed and schedule, all slots run the same round at each step, so a
   // wave can serve one point for many slots at a time.
@@ -577,7 +598,7 @@ static int run_engine(knn_db_s *db, Prepared &P, int64_t nq, hipStream_t st, int
                           P.sched.size() == 1 && ns >= K.ql_min && K.ql != 0;
   // Repeated batches of one shape replay a captured launch sequence on a
   // cached engine (not with timing on, and not for LDS-staged rounds).
-  if (K.graph != 0 && stop_after == 0 && !keep && nq <= ns && P.sched.size() == 1 && !prof_enabled() &&
+  if (allow_graph && K.graph != 0 && stop_after == 0 && !keep && nq <= ns && P.sched.size() == 1 && !prof_enabled() &&
       K.stage_min >= (1 << 30))
     return run_graph(db, P, nq, ns, same, query_lane, K, st);
   Engine E;

@@ -612,6 +612,32 @@ def test_f32_shared_sequence_batched(P, orc, monkeypatch, sampling, metric):
         assert int(base[2][q]["rounds"]) == rst["rounds"], q
 
 
+@pytest.mark.parametrize("dtype,sampling", [("u8", 3), ("u8", 0), ("f32", 3)])
+def test_batch_larger_than_slots_in_chunks(P, orc, monkeypatch, dtype, sampling):
+    """A one-seed batch with more queries than slots runs as consecutive
+    lock-step batches (equal sizes, the last one smaller and uncaptured):
+    results and statistics equal those of the batch run at once, on both a
+    first and a repeated (replayed) call, and the oracle's on a few queries."""
+    if dtype == "u8":
+        X, Q = gmm_u8(85, n=4001, m=256, n_centres=6, sigma=30.0, nq=100)
+    else:
+        X, Q = gmm_f32(85, n=4001, m=96, n_centres=6, sigma=0.3, nq=100)
+    db = P.KnnDB(dev(X))
+    kw = dict(h=6, delta=0.05, seed=17, sampling=sampling)
+    base = db.adaptive(dev(Q), 6, P.default_params(**kw))
+    for cap in ("33", "40"):  # four chunks of 25; chunks of 34, 34 and 32
+        monkeypatch.setenv("KNN_MAX_SLOTS", cap)
+        for _ in range(2):
+            got = db.adaptive(dev(Q), 6, P.default_params(**kw))
+            assert torch.equal(base[0], got[0]) and torch.equal(base[1], got[1]), cap
+            assert np.array_equal(base[2], got[2]), cap
+    idx, cnt = base[0].cpu().numpy(), base[1].cpu().numpy()
+    for q in (0, 34, 99):
+        ref, rst = orc.adaptive(X, Q[q], 6, oparams(orc, **kw))
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert int(base[2][q]["coord_evals"]) == rst["coord_evals"], q
+
+
 def test_batched_int_config_sampled(P, orc):
     """The batched-integer workload at full size (n = 100,000 x m = 3072 uint8
     32-centre mixture, 1,024 queries, k = h = 10, delta = 0.01) in the launch
