@@ -151,23 +151,33 @@ __device__ uint32_t block_kth_u32_gen(int64_t N, GetVal getval, Keep keep, int r
 }
 
 // Lane l receives lane (l ^ j)'s value, for a j that is a constant after
-// unrolling.  Every lane of the wave must be active.  Exchanges within a
-// quad or a 16-lane row run as DPP moves (no trip through the LDS unit),
-// xor 4 and 16 as swizzles (no address operand), xor 32 as a permute.
+// unrolling.  Every lane of the wave must be active.  No exchange goes
+// through the LDS unit: within a quad and a 16-lane row they are DPP moves
+// (xor 4 as the half-row mirror, lane i to 7 - i, then the quad reversal,
+// i to i ^ 3: together i to i ^ 4), across rows the gfx950 lane swaps (the
+// swap of a register with itself leaves the partner rows in one of its two
+// results).
 __device__ __forceinline__ uint32_t lane_xor_u32(uint32_t v, int j) {
   switch (j) {
     case 1:
       return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
     case 2:
       return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
-    case 4:
-      return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (4 << 10) | 0x1F);  // swap groups of 4
+    case 4: {
+      const int t = __builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+      return (uint32_t)__builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, true);      // quad_perm [3,2,1,0]
+    }
     case 8:
       return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, true);  // row_ror:8 (16-lane rows)
-    case 16:
-      return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (16 << 10) | 0x1F);  // swap groups of 16
-    default:
-      return (uint32_t)__shfl_xor((int)v, j);
+    case 16: {
+      // rows (0,1) and (2,3) swapped: the first result holds row r ^ 1 in rows 1 and 3, the second in rows 0 and 2
+      const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+      return (__lane_id() & 16) ? r[0] : r[1];
+    }
+    default: {  // 32: halves swapped, likewise
+      const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+      return (__lane_id() & 32) ? r[0] : r[1];
+    }
   }
 }
 __device__ __forceinline__ uint64_t lane_xor_u64(uint64_t v, int j) {
@@ -224,17 +234,20 @@ __device__ __forceinline__ void wave_count_add(uint64_t *ctr, uint64_t v) {
   if (lane_id() == 0 && v != 0) atomicAdd(ctr, v);
 }
 
-// Lane l receives lane (63 - l)'s value.
+// Lane l receives lane (63 - l)'s value: the row mirror (l ^ 15 within a
+// 16-lane row, a DPP move), then rows swapped by xor 16 and xor 32.
+__device__ __forceinline__ uint32_t lane_rev_u32(uint32_t v) {
+  const uint32_t m = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true);  // row_mirror
+  return lane_xor_u32(lane_xor_u32(m, 16), 32);
+}
 __device__ __forceinline__ uint64_t wave_bcast_rev_u64(uint64_t v) {
-  const int src = kWave - 1 - lane_id();
-  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
-  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
-  return ((uint64_t)hi << 32) | lo;
+  return ((uint64_t)lane_rev_u32((uint32_t)(v >> 32)) << 32) | lane_rev_u32((uint32_t)v);
 }
 
+// Every lane receives lane src's value (src the same in every lane).
 __device__ __forceinline__ uint64_t wave_bcast_u64(uint64_t v, int src) {
-  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
-  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
   return ((uint64_t)hi << 32) | lo;
 }
 

@@ -1613,7 +1613,7 @@ __device__ __forceinline__ uint32_t lx(uint32_t v, int j) { return lane_xor_u32(
 __device__ __forceinline__ uint64_t lx(uint64_t v, int j) { return lane_xor_u64(v, j); }
 __device__ __forceinline__ uint32_t wsort(uint32_t v) { return wave_sort_u32(v); }
 __device__ __forceinline__ uint64_t wsort(uint64_t v) { return wave_sort_u64(v); }
-__device__ __forceinline__ uint32_t wrev(uint32_t v) { return (uint32_t)__shfl((int)v, kWave - 1 - lane_id()); }
+__device__ __forceinline__ uint32_t wrev(uint32_t v) { return lane_rev_u32(v); }
 __device__ __forceinline__ uint64_t wrev(uint64_t v) { return wave_bcast_rev_u64(v); }
 __device__ __forceinline__ uint32_t wbcast(uint32_t v, int src) { return (uint32_t)__builtin_amdgcn_readlane((int)v, src); }
 __device__ __forceinline__ uint64_t wbcast(uint64_t v, int src) { return wave_bcast_u64(v, src); }
@@ -1784,7 +1784,7 @@ __device__ uint32_t wave_smallest_u32(const uint32_t (&key)[E], int K, uint32_t 
 #pragma unroll
     for (int e = 1; e < E; ++e) {
       const uint32_t c = wave_sort_u32(key[e]);
-      const uint32_t r = (uint32_t)__shfl((int)c, kWave - 1 - lane);  // descending
+      const uint32_t r = lane_rev_u32(c);  // descending
       uint32_t v = best < r ? best : r;                                // bitonic: the 64 smallest of both
 #pragma unroll
       for (int j = kWave / 2; j > 0; j >>= 1) {
@@ -1902,40 +1902,41 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
   const int64_t tile = w / ngroups;
   const int64_t i0 = tile * FS_PT;
   const int s0 = (int)(w % ngroups) * FS_SL;
-  {  // nothing to do unless a slot of the tile runs this round in dense form
-    bool any = false;
-    for (int c = 0; c < FS_SL; ++c) {
-      const int sl = s0 + c;
-      any |= sl < ns && slots[sl].state == 1 && slots[sl].cur == cur && slots[sl].implicit != 0;
-    }
-    if (!any) return;
-  }
+  static_assert(FS_SL == NT / kWave, "one wave per slot of the tile");
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  // this wave's slot, when it runs this round in dense form (wave-uniform);
+  // nothing to do unless one of the tile's slots does
+  const int sl = s0 + wave;
+  const Slot *slp = &slots[sl < ns ? sl : 0];
+  const bool act = sl < ns && (slp->state == 1) & (slp->cur == cur) & (slp->implicit != 0);
+  if (__syncthreads_or(act ? 1 : 0) == 0) return;
+  // whole tile with 4-byte aligned flag rows: each lane takes four runs of
+  // four consecutive points (flags as one word, sums as one 16-byte read);
+  // the flag words are loaded together with the sums
+  const bool fast = i0 + FS_PT <= n && (n & 3) == 0;
+  static_assert(FS_E == 16 && FS_PT == 4 * 4 * kWave, "four runs of four points per lane");
+  uint8_t *flr = B.fl + (int64_t)(act ? sl : 0) * n + i0;
+  uint32_t fpre[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    fpre[u] = (fast && act && !init) ? *reinterpret_cast<const uint32_t *>(flr + 4 * kWave * u + 4 * lane) : 0u;
   fs_stage_sums(t, D, nqp, i0, s0, n);
   __syncthreads();
-  const int lane = lane_id(), wave = threadIdx.x / kWave;
-  // whole tile with 4-byte aligned flag rows: each lane takes four runs of
-  // four consecutive points (flags as one word, sums as one 16-byte read)
-  const bool fast = i0 + FS_PT <= n && (n & 3) == 0;
   constexpr uint32_t PAD32 = ~0u;  // above every sum (S < m * 65025 < 2^32 - 1)
-  for (int r = wave; r < FS_SL; r += NT / kWave) {
-    const int sl = s0 + r;
-    if (sl >= ns) break;
-    const Slot *slp = &slots[sl];
-    if (slp->state != 1 || slp->cur != cur || slp->implicit == 0) continue;  // wave-uniform; sparse slots elsewhere
+  if (act) {
+    const int r = wave;
     const int k = slp->k;
     const RoundConsts rc = round_consts(slp, m, cur);
-    uint8_t *flr = B.fl + (int64_t)sl * n + i0;
     // The keys of the kept pairs (their sums; PAD when discarded or past
     // n) and which classes of kept pairs the tile holds: exact, sampled up
     // to T[cur], or accepted in an earlier round.
     uint32_t kt[FS_E];
     bool has_x = false, has_c = false, has_l = false;
     if (fast) {
-      static_assert(FS_E == 16 && FS_PT == 4 * 4 * kWave, "four runs of four points per lane");
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int p0 = 4 * kWave * u + 4 * lane;
-        const uint32_t fw = init ? 0u : *reinterpret_cast<const uint32_t *>(flr + p0);
+        const uint32_t fw = fpre[u];
         const uint4 tv = *reinterpret_cast<const uint4 *>(&t[r][p0]);
         constexpr uint32_t ONE = 0x01010101u;
         const uint32_t kept = ~(fw >> 2) & ONE, ex = fw & ONE, ac = (fw >> 1) & ONE;
@@ -2180,13 +2181,20 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
     // DQ_B points per batch: their sums are loaded together, so the loads'
     // latency is paid once per batch
     constexpr int DQ_B = 4;
-    for (int pb = threadIdx.x / DQ_G; pb < pts; pb += DQ_P * DQ_B) {
-      uint4 sv[DQ_B];
+    uint4 sn[DQ_B];  // the next batch's sums, loaded while the current batch is decided
+    auto load_batch = [&](int pb, uint4 (&sv)[DQ_B]) {
 #pragma unroll
       for (int b = 0; b < DQ_B; ++b) {  // unconditional loads (clamped to the tile): all in flight at once
         const int p = min(pb + b * DQ_P, pts - 1);
         sv[b] = *reinterpret_cast<const uint4 *>(D + (i0 + p) * nqp + s0 + c4);
       }
+    };
+    load_batch(threadIdx.x / DQ_G, sn);
+    for (int pb = threadIdx.x / DQ_G; pb < pts; pb += DQ_P * DQ_B) {
+      uint4 sv[DQ_B];
+#pragma unroll
+      for (int b = 0; b < DQ_B; ++b) sv[b] = sn[b];
+      if (pb + DQ_P * DQ_B < pts) load_batch(pb + DQ_P * DQ_B, sn);
 #pragma unroll
       for (int b = 0; b < DQ_B; ++b) {
         const int p = pb + b * DQ_P;

@@ -659,10 +659,7 @@ __global__ __launch_bounds__(256) void k_round_seq_u8(const Slot *__restrict__ s
                                                       int32_t nqp, Bufs B, Geometry G, int32_t cur, int32_t impl,
                                                       int32_t exact) {
   constexpr int XWA = exact_wa<MET>(), XQ = 32 * XWA;
-  constexpr int TROW = XQ + 4;
-  constexpr int SMEM = 2 * stage_bytes(BK_EXACT, XQ) > NBP * TROW * 4 ? 2 * stage_bytes(BK_EXACT, XQ)
-                                                                       : NBP * TROW * 4;
-  __shared__ __align__(16) uint8_t smem[SMEM];
+  __shared__ __align__(16) uint8_t smem[2 * stage_bytes(BK_EXACT, XQ)];
   const int64_t n = G.n;
   const int ns = G.nslots;
   const int64_t nqt = (ns + XQ - 1) / XQ, nwork = nqt * ((n + NBP - 1) / NBP);
@@ -688,8 +685,6 @@ __global__ __launch_bounds__(256) void k_round_seq_u8(const Slot *__restrict__ s
   v4i acc[XWA][4];
   gemm_u8_tile<MET, PF, BK_EXACT, XWA, true>(QS, (int64_t)nqp, XS, q0, p0, pend, kp, smem, acc, kb, ke, t0, t1);
   const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
-  // the round sums through LDS as [point][query] rows (the K loop ended with a barrier)
-  uint32_t *T = reinterpret_cast<uint32_t *>(smem);
   uint64_t my_pairs = 0;
   if (exact) {
     // pairs made exact: the undecided sampled ones (flag 0), marked here in
@@ -722,54 +717,54 @@ __global__ __launch_bounds__(256) void k_round_seq_u8(const Slot *__restrict__ s
       }
     }
   }
+  // The round sums go to D straight from the fragment layout: for query
+  // group a and point group b a lane holds four consecutive queries of one
+  // point, one 16-byte piece of that point's row of D (nqp is a multiple
+  // of 16, so the four are all below nqp or all at or past it).  Per query
+  // group the pieces' "not sampled" words and old sums of all four point
+  // groups are loaded together, then added to and stored.  Sums are taken
+  // mod 2^32: every running sum is below 2^32 (m <= 65536).
+  uint32_t xr[4];  // the points' range norms |x'|^2 over [lo, hi)
 #pragma unroll
-  for (int a = 0; a < XWA; ++a)
+  for (int b = 0; b < 4; ++b) {
+    const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
+    xr[b] = (MET == KNN_METRIC_L2 && i < n) ? (uint32_t)(xn[(int64_t)hi * n + i] - xn[(int64_t)lo * n + i]) : 0u;
+  }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int ql = 16 * XWA * wq + 16 * a + 4 * (lane >> 4) + v;
-      const int64_t s = q0 + ql;
-      int64_t qr = 0;
-      if (MET == KNN_METRIC_L2 && s < nqp) qr = (int64_t)qn[(int64_t)hi * nqp + s] - qn[(int64_t)lo * nqp + s];
+  for (int a = 0; a < XWA; ++a) {
+    const int ql = 16 * XWA * wq + 16 * a + 4 * (lane >> 4);
+    const int64_t s = q0 + ql;
+    const uint32_t tk = take[ql] | (take[ql + 1] << 8) | (take[ql + 2] << 16) | (take[ql + 3] << 24);
+    uint32_t qr[4] = {0u, 0u, 0u, 0u};
+    if (MET == KNN_METRIC_L2 && s < nqp && tk != 0) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int pl = 64 * wp + 16 * b + (lane & 15);
-        const int64_t i = p0 + pl;
-        uint32_t val = 0;
-        if (i < n) {
-          if constexpr (MET == KNN_METRIC_L1) {
-            val = (uint32_t)acc[a][b][v];
-          } else {
-            const int64_t xr = (int64_t)xn[(int64_t)hi * n + i] - xn[(int64_t)lo * n + i];
-            val = (uint32_t)(xr + qr - 2 * (int64_t)acc[a][b][v]);
-          }
-        }
-        T[pl * TROW + ql] = val;
+      for (int v = 0; v < 4; ++v) qr[v] = (uint32_t)(qn[(int64_t)hi * nqp + s + v] - qn[(int64_t)lo * nqp + s + v]);
+    }
+    uint32_t a4[4];
+    uint4 old[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {  // all loads of the query group in flight together
+      const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
+      const bool ok = i < n && s < nqp && tk != 0 && !impl;
+      a4[b] = ok ? *reinterpret_cast<const uint32_t *>(A + i * nqp + s) : 0u;
+      old[b] = ok ? *reinterpret_cast<const uint4 *>(D + i * nqp + s) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
+      if (i >= n || s >= nqp || tk == 0) continue;
+      const uint32_t oo[4] = {old[b].x, old[b].y, old[b].z, old[b].w};
+      uint32_t nw[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t val = MET == KNN_METRIC_L1 ? (uint32_t)acc[a][b][v]
+                                                  : xr[b] + qr[v] - 2u * (uint32_t)acc[a][b][v];
+        const bool sampled = ((tk >> (8 * v)) & 1u) != 0 && ((a4[b] >> (8 * v)) & 255u) == 0;
+        nw[v] = sampled ? oo[v] + val : oo[v];
+        if (sampled && !exact) ++my_pairs;
       }
+      *reinterpret_cast<uint4 *>(D + i * nqp + s) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
     }
-  __syncthreads();
-  // 16-byte pieces of D: four queries of one point (nqp is a multiple of 16)
-  // (loading them before the K loop measured slower: the registers cost
-  // half the waves)
-  constexpr int PIECES = NBP * XQ / 4;
-  for (int e = threadIdx.x; e < PIECES; e += 256) {
-    const int pl = e / (XQ / 4), qc = 4 * (e % (XQ / 4));
-    const int64_t i = p0 + pl, s = q0 + qc;
-    if (i >= n || s >= nqp) continue;
-    const uint32_t tk = take[qc] | (take[qc + 1] << 8) | (take[qc + 2] << 16) | (take[qc + 3] << 24);
-    if (tk == 0) continue;
-    const uint32_t a4 = impl ? 0u : *reinterpret_cast<const uint32_t *>(A + i * nqp + s);
-    uint32_t *dst = D + i * nqp + s;
-    const uint4 val = *reinterpret_cast<const uint4 *>(&T[pl * TROW + qc]);
-    const uint4 old = impl ? make_uint4(0u, 0u, 0u, 0u) : *reinterpret_cast<const uint4 *>(dst);
-    const uint32_t vv[4] = {val.x, val.y, val.z, val.w}, oo[4] = {old.x, old.y, old.z, old.w};
-    uint32_t nw[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool sampled = ((tk >> (8 * u)) & 1u) != 0 && ((a4 >> (8 * u)) & 255u) == 0;
-      nw[u] = sampled ? oo[u] + vv[u] : oo[u];
-      if (sampled && !exact) ++my_pairs;
-    }
-    *reinterpret_cast<uint4 *>(dst) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
   }
   if (G.prof) {  // whole waves reach this point
     wave_count_add(&prof_copy(G.prof)[exact ? 2 : 1], my_pairs * (uint64_t)(t1 - t0));
