@@ -209,11 +209,16 @@ int knn_autotune(knn_db db, const void *dev_queries, int64_t nq, int32_t k, cons
  * the distances equal an FP64 scan.  l1 (no matrix-core form) -- u8: exact
  * integer sums of absolute differences (v_sad_u8); f32: fp32 sums with an
  * error bound, candidates rescored in FP64 in coordinate order.
+ * Above the fused top-k lists' capacity (u8 k > 128, f32 k > 64) every query
+ * is scanned exactly instead, one block per query with the k smallest found
+ * by radix selection over all n keys (integer distances for u8, FP64 in
+ * coordinate order for f32): the same results, at a DB read per query.
  *  dev_out_idx : device, [nq][k] int64 (ascending distance).
  *  dev_out_dist: device, [nq][k] double (unnormalised squared l2 or l1
  *                distance), or NULL.
- * Stream-ordered.  Errors: EINVAL (k < 1, k > min(n, KNN_MAX_KH), u8 k > 128,
- * f32 k > 64, NULL), ENOMEM, EDEVICE. */
+ * Stream-ordered (the f32 exact scans synchronise the stream before
+ * returning).  Errors: EINVAL (k < 1, k > min(n, KNN_MAX_KH), NULL), ENOMEM,
+ * EDEVICE. */
 int knn_naive(knn_db db, const void *dev_queries, int64_t nq, int32_t k,
               int64_t *dev_out_idx, double *dev_out_dist, void *stream);
 
@@ -228,8 +233,9 @@ int knn_naive(knn_db db, const void *dev_queries, int64_t nq, int32_t k,
  * shares that device's array: calls that overlap on one GPU (on different
  * streams, or from several threads) race -- serialise them.  Nothing in the
  * array needs clearing between calls.  Stream-ordered.  Errors: as
- * knn_naive, plus EINVAL for an f32 DB and for a batch whose query rows
- * alone do not fit (the message gives the bytes needed). */
+ * knn_naive, plus EINVAL for an f32 DB, for k > 128 (the exact per-query
+ * scan needs scratch of 8 n bytes per query) and for a batch whose query
+ * rows alone do not fit (the message gives the bytes needed). */
 #define KNN_NOALLOC_SCRATCH_MB 64
 int knn_naive_noalloc(knn_db db, const void *dev_queries, int64_t nq, int32_t k,
                       int64_t *dev_out_idx, double *dev_out_dist, void *stream);

@@ -977,6 +977,105 @@ static int scratch_address(void **out) {
   return KNN_OK;
 }
 
+// The exact scan for k above the fused top-k lists' capacity (k up to
+// KNN_MAX_KH): one block per query.  Each point's distance in integers (a
+// wave per point: coalesced row reads, four bytes a lane per step, the
+// query row from the caches), its key (distance << 32 | index) in scratch,
+// the k-th smallest key by radix selection, then the k keys at or below it
+// (distinct: the index is part of the key) sorted -- the (distance, index)
+// order of the fused scan.
+template <int MET>
+__global__ __launch_bounds__(1024) void k_naive_u8_full(const uint8_t *__restrict__ X, const uint8_t *__restrict__ Q,
+                                                        int64_t n, int64_t m, int k, int64_t q0,
+                                                        uint64_t *__restrict__ scratch, int64_t *__restrict__ out_idx,
+                                                        double *__restrict__ out_dist) {
+  const int64_t q = q0 + blockIdx.x;
+  uint64_t *keys = scratch + (int64_t)blockIdx.x * n;
+  const uint8_t *qv = Q + q * m;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const bool words = (m & 3) == 0;
+  for (int64_t i = wave; i < n; i += 1024 / kWave) {
+    const uint8_t *row = X + i * m;
+    uint32_t acc = 0;  // below 2^32: m <= 65536 (squared l2) or m <= 2^24 (l1)
+    if (words) {
+      const uint32_t *r4 = reinterpret_cast<const uint32_t *>(row), *q4 = reinterpret_cast<const uint32_t *>(qv);
+      for (int64_t w = lane; w < m / 4; w += kWave) {
+        const uint32_t xv = r4[w], qw = q4[w];
+        if constexpr (MET == KNN_METRIC_L1) {
+          acc += __builtin_amdgcn_sad_u8(xv, qw, 0u);
+        } else {
+          acc += __builtin_amdgcn_udot4(xv, xv, 0u, false) + __builtin_amdgcn_udot4(qw, qw, 0u, false) -
+                 2u * __builtin_amdgcn_udot4(xv, qw, 0u, false);
+        }
+      }
+    } else {
+      for (int64_t j = lane; j < m; j += kWave) {
+        const int d = (int)row[j] - (int)qv[j];
+        acc += MET == KNN_METRIC_L1 ? (uint32_t)(d < 0 ? -d : d) : (uint32_t)(d * d);
+      }
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) acc += (uint32_t)__shfl_xor((int)acc, o);
+    if (lane == 0) keys[i] = ((uint64_t)acc << 32) | (uint64_t)i;
+  }
+  __syncthreads();
+  __shared__ SelScratch ss;
+  __shared__ uint64_t key[kMaxKH];
+  __shared__ int32_t id[kMaxKH];
+  __shared__ int cnt;
+  int less;
+  const uint64_t v = block_kth_gen<1024>(n, [&](int64_t i) { return keys[i]; }, k, ss, &less);
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const uint64_t kk = keys[i];
+    if (kk <= v) {
+      const int pos = atomicAdd(&cnt, 1);
+      if (pos < kMaxKH) {
+        key[pos] = kk;
+        id[pos] = (int32_t)i;
+      }
+    }
+  }
+  __syncthreads();
+  int len = 1;
+  while (len < k) len <<= 1;
+  for (int t = k + (int)threadIdx.x; t < len; t += 1024) {
+    key[t] = ~0ull;
+    id[t] = 0x7FFFFFFF;
+  }
+  block_bitonic_sort<1024>(key, id, len);
+  for (int t = threadIdx.x; t < k; t += 1024) {
+    out_idx[q * k + t] = (int64_t)(key[t] & 0xFFFFFFFFu);
+    if (out_dist) out_dist[q * k + t] = (double)(key[t] >> 32);
+  }
+}
+
+static int naive_u8_full(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int64_t *out_idx,
+                         double *out_dist, hipStream_t st) {
+  const bool l1 = db->metric == KNN_METRIC_L1;
+  if (!l1 && db->m > 65536) return fail(KNN_EINVAL, "naive u8 scan supports m <= 65536");
+  if (l1 && db->m > 16777216) return fail(KNN_EINVAL, "naive u8 l1 scan supports m <= 2^24");
+  const int64_t n = db->n, m = db->m;
+  // queries per launch: their keys fit in 1 GiB of scratch
+  const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, (1ll << 30) / (n * 8)));
+  uint64_t *scratch = nullptr;
+  HIP_TRY(hipMallocAsync(&scratch, sizeof(uint64_t) * n * batch, st));
+  const int tok = prof_begin(PROF_NAIVE_GEMM, st);
+  for (int64_t q0 = 0; q0 < nq; q0 += batch) {
+    const unsigned cnt = (unsigned)std::min<int64_t>(batch, nq - q0);
+    if (l1)
+      hipLaunchKernelGGL(k_naive_u8_full<KNN_METRIC_L1>, dim3(cnt), dim3(1024), 0, st, db->X, dq, n, m, (int)k, q0,
+                         scratch, out_idx, out_dist);
+    else
+      hipLaunchKernelGGL(k_naive_u8_full<KNN_METRIC_L2>, dim3(cnt), dim3(1024), 0, st, db->X, dq, n, m, (int)k, q0,
+                         scratch, out_idx, out_dist);
+  }
+  prof_end(tok, st, (l1 ? 2.0 : 3.0) * (double)nq * (double)n * (double)m);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipFreeAsync(scratch, st));
+  return KNN_OK;
+}
+
 int naive_run_noalloc(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
                       hipStream_t st) {
   if (db->dtype != KNN_U8) return fail(KNN_EINVAL, "knn_naive_noalloc supports u8 DBs only");
@@ -988,7 +1087,9 @@ int naive_run_noalloc(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64
 
 int naive_run(knn_db_s *db, const void *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
               hipStream_t st) {
-  if (db->dtype == KNN_U8) return naive_u8(db, (const uint8_t *)dq, nq, k, out_idx, out_dist, st);
+  if (db->dtype == KNN_U8)
+    return k > 128 ? naive_u8_full(db, (const uint8_t *)dq, nq, k, out_idx, out_dist, st)
+                   : naive_u8(db, (const uint8_t *)dq, nq, k, out_idx, out_dist, st);
   return naive_f32(db, (const float *)dq, nq, k, out_idx, out_dist, st);
 }
 

@@ -510,9 +510,37 @@ int naive_prepare_db_f32(knn_db_s *db, hipStream_t st) {
   return KNN_OK;
 }
 
+// Exact FP64 scans of the listed queries (k_naive_f32_full), as many per
+// launch as 1 GiB of distance scratch holds.
+static int exact_f32_queries(knn_db_s *db, const float *dq, const std::vector<int32_t> &ids, int32_t k,
+                             int64_t *out_idx, double *out_dist, hipStream_t st) {
+  if (ids.empty()) return KNN_OK;
+  const int64_t n = db->n, m = db->m;
+  const int64_t batch = std::max<int64_t>(1, std::min<int64_t>((int64_t)ids.size(), (1ll << 30) / (n * 8)));
+  int32_t *dq_ids = nullptr;
+  double *scratch = nullptr;
+  HIP_TRY(hipMallocAsync(&dq_ids, sizeof(int32_t) * ids.size(), st));
+  HIP_TRY(hipMallocAsync(&scratch, sizeof(double) * n * batch, st));
+  HIP_TRY(hipMemcpyAsync(dq_ids, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, st));
+  for (int64_t b0 = 0; b0 < (int64_t)ids.size(); b0 += batch) {
+    const int64_t cnt = std::min<int64_t>(batch, (int64_t)ids.size() - b0);
+    hipLaunchKernelGGL(k_naive_f32_full, dim3((unsigned)cnt), dim3(1024), 0, st, (const float *)db->X, dq, n, m,
+                       db->metric, k, dq_ids + b0, scratch, out_idx, out_dist);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipFreeAsync(scratch, st));
+  HIP_TRY(hipFreeAsync(dq_ids, st));
+  HIP_TRY(hipStreamSynchronize(st));  // (the host list is freed on return)
+  return KNN_OK;
+}
+
 int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out_idx, double *out_dist,
               hipStream_t st) {
-  if (k > KCU) return fail(KNN_EINVAL, "naive f32 scan supports k <= 64");
+  if (k > KCU) {  // above the upper-bound lists' capacity: every query scanned exactly in FP64
+    std::vector<int32_t> all((size_t)nq);
+    for (int64_t q = 0; q < nq; ++q) all[(size_t)q] = (int32_t)q;
+    return exact_f32_queries(db, dq, all, k, out_idx, out_dist, st);
+  }
   const bool l1 = db->metric == KNN_METRIC_L1;
   const int64_t n = db->n, m = db->m, mp = db->mp;
   const size_t cells = (size_t)n * mp;
@@ -566,22 +594,9 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
   for (int64_t q = 0; q < nq; ++q)
     if (hflag[q]) redo.push_back((int32_t)q);
   prof_add_host(0, (uint64_t)redo.size());
-  if (!redo.empty()) {
-    const int64_t batch = std::max<int64_t>(1, std::min<int64_t>((int64_t)redo.size(), (1ll << 30) / (n * 8)));
-    int32_t *dq_ids = nullptr;
-    double *scratch = nullptr;
-    HIP_TRY(hipMallocAsync(&dq_ids, sizeof(int32_t) * redo.size(), st));
-    HIP_TRY(hipMallocAsync(&scratch, sizeof(double) * n * batch, st));
-    HIP_TRY(hipMemcpyAsync(dq_ids, redo.data(), sizeof(int32_t) * redo.size(), hipMemcpyHostToDevice, st));
-    for (int64_t b0 = 0; b0 < (int64_t)redo.size(); b0 += batch) {
-      const int64_t cnt = std::min<int64_t>(batch, (int64_t)redo.size() - b0);
-      hipLaunchKernelGGL(k_naive_f32_full, dim3((unsigned)cnt), dim3(1024), 0, st, (const float *)db->X, dq, n, m,
-                         db->metric, k, dq_ids + b0, scratch, out_idx, out_dist);
-    }
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipFreeAsync(scratch, st));
-    HIP_TRY(hipFreeAsync(dq_ids, st));
-    HIP_TRY(hipStreamSynchronize(st));
+  {
+    const int rc = exact_f32_queries(db, dq, redo, k, out_idx, out_dist, st);
+    if (rc != KNN_OK) return rc;
   }
   HIP_TRY(hipFreeAsync(ws, st));
   return KNN_OK;

@@ -104,3 +104,26 @@ def test_naive_f32_float_config_sampled(P, orc):
         ri, rd = orc.naive(X, Q[q], 10)
         assert idx[q].tolist() == ri.tolist(), q
         assert np.array_equal(dist[q], rd)
+
+
+@pytest.mark.parametrize("dtype,metric,k", [("u8", "l2", 129), ("u8", "l2", 700), ("u8", "l1", 300),
+                                            ("f32", "l2", 65), ("f32", "l1", 200)])
+def test_naive_large_k_exact_scan(P, orc, dtype, metric, k):
+    """k above the fused lists' capacity (u8 128, f32 64): every query is
+    scanned exactly; indices and distances equal the oracle's, ties by index
+    included (few distinct values for u8)."""
+    g = rng(k + (7 if dtype == "f32" else 0) + (1 if metric == "l1" else 0))
+    n, m, nq = 3001, 61, 7
+    if dtype == "u8":
+        X = g.integers(0, 6, size=(n, m), dtype=np.uint8)
+        Q = g.integers(0, 6, size=(nq, m), dtype=np.uint8)
+    else:
+        X = g.standard_normal((n, m)).astype(np.float32)
+        Q = (X[g.integers(0, n, size=nq)] + 0.1 * g.standard_normal((nq, m))).astype(np.float32)
+    db = P.KnnDB(dev(X), metric=metric)
+    idx, dist = db.naive(dev(Q), k)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    for q in range(nq):
+        ri, rd = orc.naive(X, Q[q], k, metric=1 if metric == "l1" else 0)
+        assert idx[q].tolist() == ri.tolist(), q
+        assert np.array_equal(dist[q], rd), q
