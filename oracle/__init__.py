@@ -87,6 +87,10 @@ def lib():
                                ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int64,
                                P, ctypes.POINTER(Stats), P]
         L.orc_alg1.restype = ctypes.c_int32
+        L.orc_alg1_heaps.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
+                                     ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int64,
+                                     P, ctypes.POINTER(Stats), P]
+        L.orc_alg1_heaps.restype = ctypes.c_int32
         L.orc_naive.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
                                 ctypes.c_int32, P, P]
         L.orc_naive.restype = ctypes.c_int32
@@ -201,9 +205,11 @@ def adaptive(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
 
 
 def alg1(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
-         max_iter: int = 1 << 40, metric: int = 0):
+         max_iter: int = 1 << 40, metric: int = 0, heaps: bool = False):
     """Algorithm 1, sequential as published.  Returns (idx[k+h], stats dict,
-    final sample counts T[n])."""
+    final sample counts T[n]).  heaps: the Section 4.1 bookkeeping (coupled
+    heaps, O(log n) per iteration) instead of the ordered array; the same
+    results."""
     X = np.ascontiguousarray(X)
     q = np.ascontiguousarray(q, dtype=X.dtype)
     n, m = X.shape
@@ -213,8 +219,9 @@ def alg1(X: np.ndarray, q: np.ndarray, k: int, params: Params | None = None,
     out = np.full(k + h, -1, dtype=np.int64)
     T = np.zeros(n, dtype=np.int64)
     st = Stats()
-    rc = lib().orc_alg1(_ptr(X), n, m, _dtype_code(X), metric, _ptr(q), k, ctypes.byref(params), max_iter,
-                        _ptr(out), ctypes.byref(st), _ptr(T))
+    fn = lib().orc_alg1_heaps if heaps else lib().orc_alg1
+    rc = fn(_ptr(X), n, m, _dtype_code(X), metric, _ptr(q), k, ctypes.byref(params), max_iter,
+            _ptr(out), ctypes.byref(st), _ptr(T))
     if rc == -2:
         raise RuntimeError("Algorithm 1 did not terminate within max_iter iterations")
     if rc != 0:

@@ -727,6 +727,270 @@ int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t met
   return rc;
 }
 
+/* ------------------------------------------------------------------ */
+/* Algorithm 1 with the bookkeeping of Section 4.1 (Figure fig:heaps):   */
+/* the points are split into S_close (first k by (d^, index)), S_middle  */
+/* (next h) and S_far (the rest), each with its coupled heaps -- close:  */
+/* max-heaps on d^ and on d^ + alpha; middle: min- and max-heap on d^    */
+/* and max-heap on alpha; far: min-heaps on d^ and on d^ - alpha.  q1,   */
+/* q2 and b2 are heap tops; an updated point leaves its set's heaps and  */
+/* comes back with its new bounds, then extreme elements are swapped     */
+/* between neighbouring sets until the (d^, index) order across the sets */
+/* holds again: O(log n) per iteration after an O(n) heapify (Floyd).    */
+/* Every choice breaks ties as orc_alg1 does, so both return the same.   */
+/* ------------------------------------------------------------------ */
+typedef int (*above_fn)(const alg1_state_t *A, int64_t a, int64_t b);
+
+typedef struct {
+  int64_t *h;   /* heap array of point indices */
+  int64_t *at;  /* at[i]: position of point i in h, -1 when absent */
+  int64_t len;
+  above_fn above; /* above(a, b): a belongs nearer the top than b */
+} iheap_t;
+
+static int ab_dmin(const alg1_state_t *A, int64_t a, int64_t b) { return before(A, a, b); }
+static int ab_dmax(const alg1_state_t *A, int64_t a, int64_t b) { return before(A, b, a); }
+static int ab_ucb(const alg1_state_t *A, int64_t a, int64_t b) {  /* largest d^ + alpha, then smaller index */
+  double va = A->dh[a] + A->al[a], vb = A->dh[b] + A->al[b];
+  return va > vb || (va == vb && a < b);
+}
+static int ab_lcb(const alg1_state_t *A, int64_t a, int64_t b) {  /* smallest d^ - alpha, then smaller index */
+  double va = A->dh[a] - A->al[a], vb = A->dh[b] - A->al[b];
+  return va < vb || (va == vb && a < b);
+}
+static int ab_alpha(const alg1_state_t *A, int64_t a, int64_t b) {  /* largest alpha, then earlier by (d^, index) */
+  return A->al[a] > A->al[b] || (A->al[a] == A->al[b] && before(A, a, b));
+}
+
+static void ih_set(iheap_t *H, int64_t p, int64_t i) { H->h[p] = i; H->at[i] = p; }
+static void ih_up(const alg1_state_t *A, iheap_t *H, int64_t p) {
+  int64_t i = H->h[p];
+  while (p > 0) {
+    int64_t par = (p - 1) / 2;
+    if (!H->above(A, i, H->h[par])) break;
+    ih_set(H, p, H->h[par]);
+    p = par;
+  }
+  ih_set(H, p, i);
+}
+static void ih_down(const alg1_state_t *A, iheap_t *H, int64_t p) {
+  int64_t i = H->h[p];
+  for (;;) {
+    int64_t c = 2 * p + 1;
+    if (c >= H->len) break;
+    if (c + 1 < H->len && H->above(A, H->h[c + 1], H->h[c])) ++c;
+    if (!H->above(A, H->h[c], i)) break;
+    ih_set(H, p, H->h[c]);
+    p = c;
+  }
+  ih_set(H, p, i);
+}
+static void ih_push(const alg1_state_t *A, iheap_t *H, int64_t i) {
+  H->h[H->len] = i;
+  H->at[i] = H->len;
+  H->len += 1;
+  ih_up(A, H, H->len - 1);
+}
+static void ih_remove(const alg1_state_t *A, iheap_t *H, int64_t i) {
+  int64_t p = H->at[i];
+  H->at[i] = -1;
+  H->len -= 1;
+  if (p == H->len) return;
+  const int64_t x = H->h[H->len];  /* the last element fills the hole, then moves up or down */
+  ih_set(H, p, x);
+  ih_up(A, H, p);
+  if (H->at[x] == p) ih_down(A, H, p);
+}
+static void ih_heapify(const alg1_state_t *A, iheap_t *H) {  /* Floyd's bottom-up construction */
+  for (int64_t p = 0; p < H->len; ++p) H->at[H->h[p]] = p;
+  for (int64_t p = H->len / 2 - 1; p >= 0; --p) ih_down(A, H, p);
+}
+
+enum { SET_CLOSE = 0, SET_MIDDLE = 1, SET_FAR = 2 };
+typedef struct {
+  iheap_t c_d, c_ucb, m_dmin, m_dmax, m_al, f_d, f_lcb;
+  uint8_t *set;
+} alg1_heaps_t;
+
+static void set_insert(const alg1_state_t *A, alg1_heaps_t *H, int s, int64_t i) {
+  H->set[i] = (uint8_t)s;
+  if (s == SET_CLOSE) { ih_push(A, &H->c_d, i); ih_push(A, &H->c_ucb, i); }
+  else if (s == SET_MIDDLE) { ih_push(A, &H->m_dmin, i); ih_push(A, &H->m_dmax, i); ih_push(A, &H->m_al, i); }
+  else { ih_push(A, &H->f_d, i); ih_push(A, &H->f_lcb, i); }
+}
+static void set_remove(const alg1_state_t *A, alg1_heaps_t *H, int64_t i) {
+  int s = H->set[i];
+  if (s == SET_CLOSE) { ih_remove(A, &H->c_d, i); ih_remove(A, &H->c_ucb, i); }
+  else if (s == SET_MIDDLE) { ih_remove(A, &H->m_dmin, i); ih_remove(A, &H->m_dmax, i); ih_remove(A, &H->m_al, i); }
+  else { ih_remove(A, &H->f_d, i); ih_remove(A, &H->f_lcb, i); }
+}
+/* moves i from its set to set s */
+static void set_move(const alg1_state_t *A, alg1_heaps_t *H, int64_t i, int s) {
+  set_remove(A, H, i);
+  set_insert(A, H, s, i);
+}
+/* swaps extreme elements of neighbouring sets until every close point
+ * precedes every middle point and every middle point every far point */
+static void restore_order(const alg1_state_t *A, alg1_heaps_t *H, int64_t h) {
+  for (;;) {
+    int changed = 0;
+    if (h > 0) {
+      int64_t a = H->c_d.h[0], b = H->m_dmin.h[0];
+      if (before(A, b, a)) { set_move(A, H, a, SET_MIDDLE); set_move(A, H, b, SET_CLOSE); changed = 1; }
+      a = H->m_dmax.h[0]; b = H->f_d.h[0];
+      if (before(A, b, a)) { set_move(A, H, a, SET_FAR); set_move(A, H, b, SET_MIDDLE); changed = 1; }
+    } else {
+      int64_t a = H->c_d.h[0], b = H->f_d.h[0];
+      if (before(A, b, a)) { set_move(A, H, a, SET_FAR); set_move(A, H, b, SET_CLOSE); changed = 1; }
+    }
+    if (!changed) return;
+  }
+}
+
+static int heap_alloc(iheap_t *H, int64_t n, above_fn f) {
+  H->h = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  H->at = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  H->len = 0;
+  H->above = f;
+  if (!H->h || !H->at) return -1;
+  for (int64_t i = 0; i < n; ++i) H->at[i] = -1;
+  return 0;
+}
+static void heap_free(iheap_t *H) { free(H->h); free(H->at); }
+
+int32_t orc_alg1_heaps(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
+                       const void *q, int32_t k, const orc_params *p, int64_t max_iter,
+                       int64_t *out_idx, orc_stats *st, int64_t *T_out) {
+  if (!X || !q || !p || !out_idx || !st || n < 1 || m < 1 || k < 1) return -1;
+  if (dtype != ORC_U8 && dtype != ORC_F32) return -1;
+  if (!(p->delta > 0.0 && p->delta < 1.0)) return -1;
+  if (p->alpha_kind < 0 || p->alpha_kind > 2) return -1;
+  if (p->alpha_kind == 2 && !(p->c_alpha > 0.0)) return -1;
+  const double theta = p->theta_exact == 0.0f ? 1.0 : (double)p->theta_exact;
+  if (!(theta > 0.0)) return -1;
+  const int64_t h = p->h < 0 ? (int64_t)k : p->h;
+  const int64_t kh = (int64_t)k + h;
+  memset(st, 0, sizeof(*st));
+  for (int64_t a = 0; a < kh; ++a) out_idx[a] = -1;
+  if (n <= kh) {
+    for (int64_t i = 0; i < n; ++i) {
+      out_idx[i] = i;
+      if (T_out) T_out[i] = 0;
+    }
+    st->count = (int32_t)n;
+    return 0;
+  }
+  inst_t I;
+  memset(&I, 0, sizeof(I));
+  I.n = n; I.m = m; I.dtype = dtype; I.metric = metric;
+  if (dtype == ORC_U8) { I.xu = (const uint8_t *)X; I.qu = (const uint8_t *)q; }
+  else { I.xf = (const float *)X; I.qf = (const float *)q; }
+  int32_t F;
+  int sc = orc_scaling(X, n, m, dtype, metric, q, &I.W, &F);
+  if (sc < 0) return -1;
+  if (sc == 1) {  /* zero range: every distance is 0 */
+    for (int64_t a = 0; a < kh; ++a) out_idx[a] = a;
+    st->count = (int32_t)kh;
+    return 0;
+  }
+  I.scale = ldexp(1.0, F);
+  if (p->sampling < 0 || p->sampling > 3) return -1;
+  I.sampling = p->sampling;
+  I.norepl = p->sampling & 1;
+  double thr_d = ceil(theta * (double)m);
+  const int64_t thr = thr_d >= (double)m ? m : (thr_d < 1.0 ? 1 : (int64_t)thr_d);
+  alg1_state_t A;
+  A.S = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+  A.T = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+  A.ex = (uint8_t *)calloc((size_t)n, 1);
+  A.dh = (double *)calloc((size_t)n, sizeof(double));
+  A.al = (double *)calloc((size_t)n, sizeof(double));
+  keyidx_t *tmp = (keyidx_t *)malloc(sizeof(keyidx_t) * (size_t)n);
+  alg1_heaps_t H;
+  H.set = (uint8_t *)calloc((size_t)n, 1);
+  int bad = !A.S || !A.T || !A.ex || !A.dh || !A.al || !tmp || !H.set;
+  bad |= heap_alloc(&H.c_d, n, ab_dmax) | heap_alloc(&H.c_ucb, n, ab_ucb);
+  bad |= heap_alloc(&H.m_dmin, n, ab_dmin) | heap_alloc(&H.m_dmax, n, ab_dmax) | heap_alloc(&H.m_al, n, ab_alpha);
+  bad |= heap_alloc(&H.f_d, n, ab_dmin) | heap_alloc(&H.f_lcb, n, ab_lcb);
+  int32_t rc = 0;
+  int64_t evals = 0, exact_pts = 0, it = 0;
+  if (bad) { rc = -1; goto done; }
+  /* one more sample of point i (or its exact distance at the threshold),
+   * the same update as orc_alg1 */
+  #define ALG1H_SAMPLE(i) do {                                                  \
+    int64_t i_ = (i);                                                           \
+    A.T[i_] += 1;                                                               \
+    A.S[i_] += sample_value(&I, i_, orc_coord(I.sampling, p->seed, i_, A.T[i_] - 1, m));      \
+    evals += 1;                                                                 \
+    if (A.T[i_] >= thr) {                                                       \
+      A.S[i_] = exact_sum(&I, i_);                                              \
+      A.ex[i_] = 1;                                                             \
+      evals += exact_cost(&I, A.T[i_]);                                         \
+      exact_pts += 1;                                                           \
+      A.dh[i_] = dhat_of(&I, A.S[i_], m);                                       \
+      A.al[i_] = 0.0;                                                           \
+    } else {                                                                    \
+      A.dh[i_] = dhat_of(&I, A.S[i_], A.T[i_]);                                 \
+      A.al[i_] = orc_alpha(p->alpha_kind, A.T[i_], n, p->delta, p->c_alpha);    \
+    }                                                                           \
+  } while (0)
+  for (int64_t i = 0; i < n; ++i) ALG1H_SAMPLE(i);
+  /* the initial split by (d^, index), each set's heaps built bottom-up */
+  for (int64_t i = 0; i < n; ++i) { tmp[i].key = A.dh[i]; tmp[i].idx = i; }
+  qsort(tmp, (size_t)n, sizeof(keyidx_t), cmp_keyidx);
+  for (int64_t a = 0; a < n; ++a) {
+    const int64_t i = tmp[a].idx;
+    if (a < k) {
+      H.set[i] = SET_CLOSE;
+      H.c_d.h[H.c_d.len++] = i; H.c_ucb.h[H.c_ucb.len++] = i;
+    } else if (a < kh) {
+      H.set[i] = SET_MIDDLE;
+      H.m_dmin.h[H.m_dmin.len++] = i; H.m_dmax.h[H.m_dmax.len++] = i; H.m_al.h[H.m_al.len++] = i;
+    } else {
+      H.set[i] = SET_FAR;
+      H.f_d.h[H.f_d.len++] = i; H.f_lcb.h[H.f_lcb.len++] = i;
+    }
+  }
+  ih_heapify(&A, &H.c_d); ih_heapify(&A, &H.c_ucb);
+  ih_heapify(&A, &H.m_dmin); ih_heapify(&A, &H.m_dmax); ih_heapify(&A, &H.m_al);
+  ih_heapify(&A, &H.f_d); ih_heapify(&A, &H.f_lcb);
+  for (;;) {
+    const int64_t q1 = H.c_ucb.h[0], q2 = H.f_lcb.h[0];                /* eq. d_ind */
+    if (A.dh[q1] + A.al[q1] <= A.dh[q2] - A.al[q2]) break;             /* eq. termination */
+    int64_t b2 = q2;                                                   /* eq. blowbupdef */
+    if (h > 0 && A.al[H.m_al.h[0]] > A.al[q2]) b2 = H.m_al.h[0];
+    if (++it > max_iter) { rc = -2; break; }
+    const int64_t pick[2] = {q1, b2};
+    for (int c = 0; c < 2; ++c) {
+      const int64_t i = pick[c];
+      if (A.ex[i]) continue;  /* its distance is exact already */
+      const int s = H.set[i];
+      set_remove(&A, &H, i);
+      ALG1H_SAMPLE(i);
+      set_insert(&A, &H, s, i);
+    }
+    restore_order(&A, &H, h);
+  }
+  #undef ALG1H_SAMPLE
+  {  /* the returned set: close and middle, by (d^, index) */
+    int64_t c = 0;
+    for (int64_t i = 0; i < n; ++i)
+      if (H.set[i] != SET_FAR) { tmp[c].key = A.dh[i]; tmp[c].idx = i; ++c; }
+    qsort(tmp, (size_t)c, sizeof(keyidx_t), cmp_keyidx);
+    for (int64_t a = 0; a < kh; ++a) out_idx[a] = tmp[a].idx;
+  }
+  st->coord_evals = evals;
+  st->rounds = it > INT32_MAX ? INT32_MAX : (int32_t)it;
+  st->count = (int32_t)kh;
+  st->exact_points = exact_pts;
+  if (T_out) for (int64_t i = 0; i < n; ++i) T_out[i] = A.ex[i] ? m : A.T[i];
+done:
+  free(A.S); free(A.T); free(A.ex); free(A.dh); free(A.al); free(tmp); free(H.set);
+  heap_free(&H.c_d); heap_free(&H.c_ucb); heap_free(&H.m_dmin); heap_free(&H.m_dmax); heap_free(&H.m_al);
+  heap_free(&H.f_d); heap_free(&H.f_lcb);
+  return rc;
+}
+
 int32_t orc_naive(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
                   const void *q, int32_t k, int64_t *out_idx, double *out_dist) {
   if (!X || !q || !out_idx || n < 1 || m < 1 || k < 1) return -1;

@@ -127,6 +127,18 @@ int32_t orc_alg1(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t met
                  const void *q, int32_t k, const orc_params *p, int64_t max_iter,
                  int64_t *out_idx, orc_stats *st, int64_t *T_out);
 
+/* Algorithm 1 with the bookkeeping of Section 4.1 (Figure fig:heaps): the
+ * first k, the next h and the remaining points by (d^, index) each keep
+ * coupled binary heaps (close: max on d^ and on d^ + alpha; middle: min and
+ * max on d^, max on alpha; far: min on d^ and on d^ - alpha), built bottom-up
+ * (Floyd); q1, q2 and b2 are heap tops, and after an iteration's updates
+ * extreme points are swapped between neighbouring sets until the order
+ * holds again -- O(log n) per iteration.  Same arguments, ties and results
+ * as orc_alg1. */
+int32_t orc_alg1_heaps(const void *X, int64_t n, int64_t m, int32_t dtype, int32_t metric,
+                       const void *q, int32_t k, const orc_params *p, int64_t max_iter,
+                       int64_t *out_idx, orc_stats *st, int64_t *T_out);
+
 /* Naive brute force of Section 3: all distances, k smallest by (d, index).
  * u8: exact int64 sums; f32: double sums in coordinate order.
  * out_dist receives the unnormalised distances (squared l2, or l1). */

@@ -481,6 +481,54 @@ def test_alg1_sample_bound(orc, seed):
     assert updates <= 2 * bound
 
 
+def _alg1_cases():
+    from knn_inputs import gap_family, gmm_f32
+    cases = []
+    for seed in range(3):
+        X, q = gap_family(500 + seed, n=500, m=256, k=5, near=5, mid=20)
+        cases.append((f"gap{seed}", X, q, 5, dict(h=5, delta=0.05, seed=seed), 0))
+    X, Q, _ = tiny(1001, n=600)
+    cases.append(("tiny_h0", X, Q[0], 5, dict(h=0, delta=0.01, seed=3), 0))
+    cases.append(("tiny_k1", X, Q[0], 1, dict(h=2, delta=0.01, seed=4, alpha_kind=1), 0))
+    Xa, qa, _ = antipodal(9, n=800, m=512, copies=5)
+    cases.append(("antipodal", Xa, qa[0], 5, dict(h=5, delta=0.01, seed=5), 0))
+    Xt, qt = uniform_u8(11, n=400, m=24)  # few distinct values: many equal estimates and widths
+    Xt = (Xt % 3).astype(np.uint8)
+    qt = (qt % 3).astype(np.uint8)
+    cases.append(("ties", Xt, qt[0], 4, dict(h=3, delta=0.1, seed=6), 0))
+    cases.append(("ties_l1_shared", Xt, qt[0], 4, dict(h=3, delta=0.1, seed=7, sampling=3), 1))
+    Xf, Qf = gmm_f32(12, n=500, m=64, n_centres=5, sigma=0.3, nq=1)
+    cases.append(("f32_calpha", Xf, Qf[0], 6, dict(h=6, delta=0.05, seed=8, alpha_kind=2, c_alpha=0.05), 0))
+    cases.append(("f32_norepl", Xf, Qf[0], 6, dict(h=4, delta=0.05, seed=9, sampling=1), 0))
+    return cases
+
+
+@pytest.mark.parametrize("case", _alg1_cases(), ids=lambda c: c[0])
+def test_alg1_heaps_equal_ordered_array(orc, case):
+    """Section 4.1: the heap bookkeeping (seven coupled heaps, O(log n) per
+    iteration) makes the same choices as the ordered array -- the same
+    returned set in order, iterations, evaluations, exact points and final
+    sample counts -- on gaps, planted, antipodal, tie-heavy, l1, shared and
+    without-replacement draws, h = 0, k = 1 and every width kind."""
+    _, X, q, k, kw, metric = case
+    a = orc.alg1(X, q, k, orc.make_params(**kw), metric=metric)
+    b = orc.alg1(X, q, k, orc.make_params(**kw), metric=metric, heaps=True)
+    assert a[0].tolist() == b[0].tolist()
+    assert a[1] == b[1]
+    assert np.array_equal(a[2], b[2])
+    assert a[1]["iterations"] > 0
+
+
+def test_alg1_heaps_large_n(orc):
+    """The heap form at a size where the ordered array's O(n) fix-ups would
+    dominate (n = 50,000): it returns a set containing the true k-NN."""
+    from knn_inputs import gap_family
+    X, q = gap_family(77, n=50_000, m=128, k=5, near=5, mid=20)
+    idx, st, T = orc.alg1(X, q, 5, orc.make_params(h=5, delta=0.05, seed=1), heaps=True)
+    assert contains_knn(idx, brute_dists(X, q), 5)
+    assert st["coord_evals"] == int(T.sum()) + 128 * st["exact_points"]
+
+
 def test_alg1_small_n_and_invalid(orc):
     X, _ = uniform_u8(5, n=8, m=16)
     idx, st, _ = orc.alg1(X, X[0], 3, orc.make_params(h=5))
