@@ -89,7 +89,31 @@ constexpr int KCU = 64;   // upper-bound list capacity (k <= 64): one wave regis
 constexpr int FCB = 16;   // buffered upper-bound candidates per query before a merge
 constexpr int FCL = 384;  // candidate list capacity per (query, range)
 
-template <int MET>
+constexpr int64_t FPROBE = 4;  // tiles of every range in the probe pass
+
+// Per query: the k-th smallest of the ranges' upper-bound lists (a key of
+// a real point's upper bound, so >= d_(k)) lowers the shared bound.
+__global__ __launch_bounds__(256) void k_naive_f32_tau0(const uint64_t *__restrict__ part, int64_t nranges, int k,
+                                                        uint32_t *__restrict__ gtau) {
+  const int64_t q = blockIdx.x;
+  const uint64_t *pq = part + q * nranges * k;
+  __shared__ SelScratch ss;
+  int less;
+  const uint64_t v = block_kth_gen<256>(nranges * k, [&](int64_t t) { return pq[t]; }, k, ss, &less);
+  if (threadIdx.x == 0 && v != ~0ull) atomicMin(&gtau[q], (uint32_t)(v >> 32));
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t len, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+// SCREEN = false: the lists pass (running k smallest upper bounds per
+// query and range, candidates below the running bound); true: the screen
+// pass, with every query's bound fixed beforehand in gtau -- candidates
+// are the pairs whose lower bound is at or below it, and nothing else is
+// kept.
+template <int MET, bool SCREEN>
 __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ Qh, const uint16_t *__restrict__ Ql,
                                                    const float *__restrict__ qn, const float *__restrict__ qr,
                                                    const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xl,
@@ -97,7 +121,7 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
                                                    int64_t nq, int64_t n, int64_t mp, int k, int64_t prange,
                                                    float c1, float c2, uint64_t *__restrict__ part,
                                                    uint64_t *__restrict__ cand, int32_t *__restrict__ ncand,
-                                                   int64_t nranges) {
+                                                   int64_t nranges, uint32_t *__restrict__ gtau, int64_t max_tiles) {
   constexpr uint64_t PAD = ~0ull;
   constexpr int QPW = FBQ / 4;  // queries owned by one wave in the epilogue
   __shared__ __align__(16) uint8_t tiles[FBQ * FDSTR * 4];
@@ -111,17 +135,29 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
   // its candidate list in this range, and its norms
   __shared__ uint64_t Lq[FBQ][kWave];
   __shared__ uint64_t tauq[FBQ];  // entry k - 1 of the query's list
+  __shared__ __align__(16) float tauf[FBQ];  // the same as a float (+inf while the list holds fewer than k)
   __shared__ int cbq[FBQ], ncq[FBQ];
-  __shared__ float qnq[FBQ], qrq[FBQ];
+  __shared__ __align__(16) float qnq[FBQ], qrq[FBQ];
+  __shared__ uint8_t qflag[FBQ];       // the query has a pair in this tile that passes the screen
+  // the smallest running tau any range of the query has published (a key;
+  // ~0 none yet), read once per tile: every range's tau bounds d_(k) from
+  // above, so the smallest one screens candidates as soundly as its own
+  __shared__ uint32_t gtk[FBQ];
+  __shared__ __align__(16) float gtf[FBQ];
+  __shared__ float txn[FBP], txr[FBP];  // the tile's point norms
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int64_t q0 = (int64_t)blockIdx.y * FBQ;
   const int64_t pr0 = (int64_t)blockIdx.x * prange;
-  const int64_t pr1 = std::min(n, pr0 + prange);
+  const int64_t pr1 = std::min(std::min(n, pr0 + prange), pr0 + max_tiles * FBP);  // (a probe pass: its first tiles)
   const int wq = wave >> 1, wp = wave & 1;
   for (int j = tid; j < FBQ * kWave; j += 256) Lq[j / kWave][j % kWave] = PAD;
   if (tid < FBQ) {
     const int64_t q = q0 + tid;
     tauq[tid] = PAD;
+    tauf[tid] = INFINITY;
+    gtk[tid] = ~0u;
+    gtf[tid] = INFINITY;
+    qflag[tid] = 0;
     cbq[tid] = 0;
     ncq[tid] = 0;
     qnq[tid] = (MET == KNN_METRIC_L1 || q >= nq) ? 0.0f : qn[q];
@@ -129,6 +165,16 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
   }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  // the fragment layout's queries of this lane: 32 wq + 16 a + 4 (lane >> 4) + v
+  float qnf[2][4], cqr[2][4];  // |q|^2 and c1 |q| (squared l2)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
+      qnf[a][v] = qnq[ql];
+      cqr[a][v] = c1 * qrq[ql];
+    }
   // squared l2: the next 64-byte K slice of the tile's query and point rows
   // (hi and lo), loaded into registers one slice ahead
   v4i_f pah = v4i_f{0, 0, 0, 0}, pal = v4i_f{0, 0, 0, 0}, pbh[2], pbl[2];
@@ -156,17 +202,27 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
   if constexpr (MET != KNN_METRIC_L1) {
     if (pr0 < pr1) fetch(pr0, 0);
   }
+  if (SCREEN && tid < FBQ && q0 + tid < nq) {  // (fixed for the whole pass)
+    const uint32_t g = gtau[q0 + tid];
+    gtk[tid] = g;
+    gtf[tid] = g == ~0u ? INFINITY : fkey_inv(g);
+  }
   for (int64_t p0 = pr0; p0 < pr1; p0 += FBP) {
-    // this lane's two points' norms, loaded before the K loop so that their
-    // latency is hidden (every query of the wave uses them)
-    float xnv[2] = {0.0f, 0.0f}, xrv[2] = {0.0f, 0.0f};
+    if (!SCREEN && tid < FBQ && q0 + tid < nq) {  // (read by this tile's screen, after the K loop's barriers)
+      const uint32_t g = __hip_atomic_load(&gtau[q0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      gtk[tid] = g;
+      gtf[tid] = g == ~0u ? INFINITY : fkey_inv(g);
+    }
+    // this lane's four points of the fragment layout (64 wp + 16 b + (lane &
+    // 15)): norms loaded before the K loop so that their latency is hidden
+    float xnf[4] = {0.0f, 0.0f, 0.0f, 0.0f}, xrf[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (MET != KNN_METRIC_L1) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int64_t p = p0 + lane + 64 * h;
+      for (int b = 0; b < 4; ++b) {
+        const int64_t p = p0 + 64 * wp + 16 * b + (lane & 15);
         if (p < pr1) {
-          xnv[h] = xn[p];
-          xrv[h] = xr[p];
+          xnf[b] = xn[p];
+          xrf[b] = xr[p];
         }
       }
     }
@@ -262,7 +318,63 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
         }
       __syncthreads();
     }
-    // approximate distances of the tile
+    // Screen in the fragment layout: a pair can matter to its query only
+    // if its lower bound l = d~ - E is at or below the query's running tau
+    // (the upper bound d~ + E >= l, so an insertion needs it too).  The
+    // expressions are the per-query pass's own, so this is a superset of
+    // its conditions; queries with no such pair in the tile are skipped
+    // there (they would change nothing).
+    bool anyq = false;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int ql0 = 32 * wq + 16 * a + 4 * (lane >> 4);
+      const v4f_f tl = *reinterpret_cast<const v4f_f *>(&tauf[ql0]);
+      const v4f_f tg = *reinterpret_cast<const v4f_f *>(&gtf[ql0]);
+      const v4f_f tq = v4f_f{fminf(tl[0], tg[0]), fminf(tl[1], tg[1]), fminf(tl[2], tg[2]), fminf(tl[3], tg[3])};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        bool f = false;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int64_t p = p0 + 64 * wp + 16 * b + (lane & 15);
+          const float dot = acc[a][b][v];
+          float lo;
+          if constexpr (MET == KNN_METRIC_L1) {
+            lo = dot - c1 * dot;
+          } else {
+            const float sn = qnf[a][v] + xnf[b];
+            const float d = sn - 2.0f * dot;
+            lo = d - (cqr[a][v] * xrf[b] + c2 * sn);
+          }
+          const bool pass = p < pr1 && q0 + ql0 + v < nq && lo <= tq[v];  // (padding queries of the last tile: none)
+          if constexpr (SCREEN) {
+            if (pass) {  // a candidate: appended to the query's list of this range
+              const int ql = ql0 + v;
+              const int pos = atomicAdd(&ncq[ql], 1);
+              if (pos < FCL) cand[((q0 + ql) * nranges + blockIdx.x) * (int64_t)FCL + pos] =
+                  ((uint64_t)fkey(lo) << 32) | (uint64_t)p;
+            }
+          }
+          f |= pass;
+        }
+        if constexpr (!SCREEN) {
+          const uint64_t mk = __ballot(f);
+          if ((lane & 15) == 0 && ((mk >> (lane & 48)) & 0xFFFFull) != 0) qflag[ql0 + v] = 1;
+          anyq |= mk != 0;
+        }
+      }
+    }
+    if constexpr (SCREEN) continue;  // (the next tile's first LDS writes follow the K loop's last barrier)
+    if ((lane >> 4) == 0) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int pl = 64 * wp + 16 * b + lane;
+        txn[pl] = xnf[b];
+        txr[pl] = xrf[b];
+      }
+    }
+    if (__syncthreads_or(anyq ? 1 : 0) == 0) continue;  // (block-uniform) nothing in this tile for any query
+    // the tile's sums (dot products, or l1 sums) as [query][point] rows
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -271,18 +383,19 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
         for (int v = 0; v < 4; ++v) {
           const int ql = 32 * wq + 16 * a + 4 * (lane >> 4) + v;
           const int pl = 64 * wp + 16 * b + (lane & 15);
-          // the l1 sum, or the dot product q.x (the epilogue adds the norms)
           Ds[ql * FDSTR + pl] = acc[a][b][v];
         }
     __syncthreads();
-    // per query of this wave: upper bounds below the running k-th one go to
-    // the LDS buffer (merged into the list when it would overflow); points
-    // whose lower bound is at or below it join the range's candidates
-#pragma unroll 2
+    // per flagged query of this wave: upper bounds below the running k-th
+    // one go to the LDS buffer (merged into the list when it would
+    // overflow); points whose lower bound is at or below it join the
+    // range's candidates
+#pragma unroll 1
     for (int t = 0; t < QPW; ++t) {
       const int ql = wave * QPW + t;
       const int64_t q = q0 + ql;
       if (q >= nq) break;  // (wave-uniform)
+      if (!qflag[ql]) continue;
       const float qnv = qnq[ql], qrv = qrq[ql];
       uint64_t cu[2], cl[2];
 #pragma unroll
@@ -293,8 +406,9 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
         cl[h] = PAD;
         if (p < pr1) {
           const float dot = Ds[ql * FDSTR + pl];
-          const float d = MET == KNN_METRIC_L1 ? dot : (qnv + xnv[h]) - 2.0f * dot;
-          const float E = MET == KNN_METRIC_L1 ? c1 * d : c1 * qrv * xrv[h] + c2 * (qnv + xnv[h]);
+          const float xnv = txn[pl], xrv = txr[pl];
+          const float d = MET == KNN_METRIC_L1 ? dot : (qnv + xnv) - 2.0f * dot;
+          const float E = MET == KNN_METRIC_L1 ? c1 * d : c1 * qrv * xrv + c2 * (qnv + xnv);
           cu[h] = ((uint64_t)fkey(d + E) << 32) | (uint64_t)p;
           cl[h] = ((uint64_t)fkey(d - E) << 32) | (uint64_t)p;
         }
@@ -315,11 +429,15 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
         if (lane == 0) {
           cbq[ql] = 0;
           tauq[ql] = tau;
+          tauf[ql] = tau == PAD ? INFINITY : fkey_inv((uint32_t)(tau >> 32));
+          if (tau != PAD) atomicMin(&gtau[q], (uint32_t)(tau >> 32));
         }
       }
       // tau: the k-th smallest upper bound of the points seen so far (the
-      // buffered ones left out: a larger value, so a superset of the candidates)
-      const uint32_t tau_key = (uint32_t)(tau >> 32);
+      // buffered ones left out: a larger value, so a superset of the
+      // candidates); candidates are screened by the smaller of it and the
+      // smallest published by any range of the query
+      const uint32_t tau_key = min((uint32_t)(tau >> 32), gtk[ql]);
       const bool g0 = cl[0] != PAD && (uint32_t)(cl[0] >> 32) <= tau_key;
       const bool g1 = cl[1] != PAD && (uint32_t)(cl[1] >> 32) <= tau_key;
       const uint64_t m0 = __ballot(g0), m1 = __ballot(g1);
@@ -349,6 +467,8 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
           if (lane == 0) {
             cbq[ql] = 0;
             tauq[ql] = nt;
+            tauf[ql] = nt == PAD ? INFINITY : fkey_inv((uint32_t)(nt >> 32));
+            if (nt != PAD) atomicMin(&gtau[q], (uint32_t)(nt >> 32));
           }
         } else {
           if (a0) Cb[ql][cb + __popcll(u0 & lt)] = cu[0];
@@ -356,9 +476,11 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
           if (lane == 0) cbq[ql] = cb + n0 + n1;
         }
       }
+      if (lane == 0) qflag[ql] = 0;
     }
     __syncthreads();
   }
+  __syncthreads();  // (the screen pass's appends counted)
   // final merge; per query the range's k smallest upper bounds and the
   // length of its candidate list
 #pragma unroll 1
@@ -366,6 +488,10 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
     const int ql = wave * QPW + t;
     const int64_t q = q0 + ql;
     if (q >= nq) break;
+    if (SCREEN) {
+      if (lane == 0) ncand[q * nranges + blockIdx.x] = ncq[ql];
+      continue;
+    }
     uint64_t L = Lq[ql][lane];
     const int cb = cbq[ql];
     if (cb > 0) L = merge_sorted64(L, lane < cb ? Cb[ql][lane] : PAD);
@@ -398,16 +524,14 @@ __global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__rest
                                                           const int32_t *__restrict__ ncand, int64_t nranges, int k,
                                                           const float *__restrict__ X, const float *__restrict__ Q,
                                                           int64_t m, int met, int64_t *__restrict__ out_idx,
-                                                          double *__restrict__ out_dist, int32_t *__restrict__ flag) {
+                                                          double *__restrict__ out_dist, int32_t *__restrict__ flag,
+                                                          const uint32_t *__restrict__ gtau) {
   const int64_t q = blockIdx.x;
-  const uint64_t *pq = part + q * nranges * k;
-  __shared__ SelScratch ss;
   __shared__ uint64_t key[FCAP];
   __shared__ int32_t id[FCAP];
   __shared__ int cnt, bad;
-  int less;
-  const uint64_t tk = block_kth_gen<1024>(nranges * k, [&](int64_t t) { return pq[t]; }, k, ss, &less);
-  const float tau = fkey_inv((uint32_t)(tk >> 32));
+  // the screen pass's bound (>= d_(k)); every candidate lies at or below it
+  const float tau = gtau[q] == ~0u ? INFINITY : fkey_inv(gtau[q]);
   const uint32_t tau_key = fkey(tau + fabsf(tau) * 1e-6f + 1e-30f);  // tiny margin over fp32 rounding
   if (threadIdx.x == 0) {
     cnt = 0;
@@ -555,15 +679,18 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
   const size_t b_qs = (size_t)nq * mp * 2 * 2, b_qn = sizeof(float) * nq * 2 + 512,
                b_part = sizeof(uint64_t) * nq * nranges * k + 256,
                b_cand = sizeof(uint64_t) * nq * nranges * FCL, b_nc = sizeof(int32_t) * nq * nranges + 256,
-               b_flag = sizeof(int32_t) * nq + 256;
+               b_flag = sizeof(int32_t) * nq + 256, b_gtau = sizeof(uint32_t) * nq + 256;
   void *ws = nullptr;
-  HIP_TRY(hipMallocAsync(&ws, b_qs + b_qn + b_part + b_cand + b_nc + b_flag, st));
+  HIP_TRY(hipMallocAsync(&ws, b_qs + b_qn + b_part + b_cand + b_nc + b_flag + b_gtau, st));
   uint16_t *Qh = (uint16_t *)ws, *Ql = Qh + (size_t)nq * mp;
   float *qn = (float *)((uint8_t *)ws + b_qs), *qr = qn + nq;
   uint64_t *part = (uint64_t *)((uint8_t *)ws + b_qs + b_qn);
   uint64_t *candl = (uint64_t *)((uint8_t *)ws + b_qs + b_qn + b_part);
   int32_t *ncand = (int32_t *)((uint8_t *)ws + b_qs + b_qn + b_part + b_cand);
   int32_t *flag = (int32_t *)((uint8_t *)ws + b_qs + b_qn + b_part + b_cand + b_nc);
+  uint32_t *gtau = (uint32_t *)((uint8_t *)ws + b_qs + b_qn + b_part + b_cand + b_nc + b_flag);
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((nq + 255) / 256, 1024)), dim3(256), 0, st, gtau, nq,
+                     ~0u);
   int tok = prof_begin(PROF_NAIVE_REST, st);
   if (l1)  // zero-padded f32 query rows (nq x mp x 4 bytes, the size of the split pair)
     launch_pad_rows(reinterpret_cast<const uint8_t *>(dq), nq, m, mp, 4, reinterpret_cast<uint8_t *>(Qh), st);
@@ -571,19 +698,39 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
     hipLaunchKernelGGL(k_split_rows, dim3((unsigned)nq), dim3(256), 0, st, dq, nq, m, mp, Qh, Ql, qn, qr);
   prof_end(tok, st, 0.0);
   tok = prof_begin(PROF_NAIVE_GEMM, st);
-  if (l1)
-    hipLaunchKernelGGL(k_naive_f32<KNN_METRIC_L1>, dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st, Qh,
-                       nullptr, nullptr, nullptr, reinterpret_cast<const uint16_t *>(db->xpad), nullptr, nullptr,
-                       nullptr, nq, n, mp, k, prange, c1, c2, part, candl, ncand, nranges);
-  else
-    hipLaunchKernelGGL(k_naive_f32<KNN_METRIC_L2>, dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st, Qh, Ql,
-                       qn, qr, db->xbf, db->xbf + cells, db->norm_f, db->rownorm, nq, n, mp, k, prange, c1, c2, part,
-                       candl, ncand, nranges);
+  auto scan = [&](int64_t tiles, bool screen) {
+    if (l1 && screen)
+      hipLaunchKernelGGL((k_naive_f32<KNN_METRIC_L1, true>), dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st,
+                         Qh, nullptr, nullptr, nullptr, reinterpret_cast<const uint16_t *>(db->xpad), nullptr, nullptr,
+                         nullptr, nq, n, mp, k, prange, c1, c2, part, candl, ncand, nranges, gtau, tiles);
+    else if (screen)
+      hipLaunchKernelGGL((k_naive_f32<KNN_METRIC_L2, true>), dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st,
+                         Qh, Ql, qn, qr, db->xbf, db->xbf + cells, db->norm_f, db->rownorm, nq, n, mp, k, prange, c1,
+                         c2, part, candl, ncand, nranges, gtau, tiles);
+    else if (l1)
+      hipLaunchKernelGGL((k_naive_f32<KNN_METRIC_L1, false>), dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st, Qh,
+                         nullptr, nullptr, nullptr, reinterpret_cast<const uint16_t *>(db->xpad), nullptr, nullptr,
+                         nullptr, nq, n, mp, k, prange, c1, c2, part, candl, ncand, nranges, gtau, tiles);
+    else
+      hipLaunchKernelGGL((k_naive_f32<KNN_METRIC_L2, false>), dim3((unsigned)nranges, (unsigned)qt), dim3(256), 0, st, Qh, Ql,
+                         qn, qr, db->xbf, db->xbf + cells, db->norm_f, db->rownorm, nq, n, mp, k, prange, c1, c2, part,
+                         candl, ncand, nranges, gtau, tiles);
+  };
+  // A probe over the first FPROBE tiles of every range (the lists pass)
+  // gives each query tau0, the k-th smallest upper bound of the union of
+  // the ranges' lists: the upper bound of a real point, so tau0 >= d_(k),
+  // and every true k-NN point has l <= d <= d_(k) <= tau0.  The full scan
+  // then only screens: the pairs with l <= tau0 are the candidates, at
+  // least k of them (the points that gave tau0).  Over a sample of s of
+  // the n points, about k n / s points lie below tau0.
+  scan(FPROBE, false);
+  hipLaunchKernelGGL(k_naive_f32_tau0, dim3((unsigned)nq), dim3(256), 0, st, part, nranges, k, gtau);
+  scan(INT64_MAX / 2 / FBP, true);
   // work units: l2 three BF16 products of 2 operations; l1 a difference and an addition
   prof_end(tok, st, (l1 ? 2.0 : 3.0 * 2.0) * (double)nq * (double)n * (double)m);
   tok = prof_begin(PROF_NAIVE_REST, st);
   hipLaunchKernelGGL(k_naive_f32_merge, dim3((unsigned)nq), dim3(1024), 0, st, part, candl, ncand, nranges, k,
-                     (const float *)db->X, dq, m, db->metric, out_idx, out_dist, flag);
+                     (const float *)db->X, dq, m, db->metric, out_idx, out_dist, flag, gtau);
   prof_end(tok, st, 0.0);
   HIP_TRY(hipGetLastError());
   // queries whose candidate list may be incomplete are rescanned exactly
