@@ -129,11 +129,11 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
   uint8_t *Ah = tiles, *Al = tiles + FBQ * FROWB;
   uint8_t *Bh = tiles + 2 * FBQ * FROWB, *Bl = Bh + FBP * FROWB;
   float *Ds = reinterpret_cast<float *>(tiles);
-  __shared__ uint64_t Cb[FBQ][FCB];
+  __shared__ uint64_t Cb[SCREEN ? 1 : FBQ][FCB];  // (the screen pass keeps no lists)
   // per query of the block: its sorted upper-bound list (entry j the j-th
   // smallest, PAD while fewer than k), the count of its LDS buffer and of
   // its candidate list in this range, and its norms
-  __shared__ uint64_t Lq[FBQ][kWave];
+  __shared__ uint64_t Lq[SCREEN ? 1 : FBQ][kWave];
   __shared__ uint64_t tauq[FBQ];  // entry k - 1 of the query's list
   __shared__ __align__(16) float tauf[FBQ];  // the same as a float (+inf while the list holds fewer than k)
   __shared__ int cbq[FBQ], ncq[FBQ];
@@ -150,7 +150,8 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
   const int64_t pr0 = (int64_t)blockIdx.x * prange;
   const int64_t pr1 = std::min(std::min(n, pr0 + prange), pr0 + max_tiles * FBP);  // (a probe pass: its first tiles)
   const int wq = wave >> 1, wp = wave & 1;
-  for (int j = tid; j < FBQ * kWave; j += 256) Lq[j / kWave][j % kWave] = PAD;
+  if (!SCREEN)
+    for (int j = tid; j < FBQ * kWave; j += 256) Lq[j / kWave][j % kWave] = PAD;
   if (tid < FBQ) {
     const int64_t q = q0 + tid;
     tauq[tid] = PAD;
