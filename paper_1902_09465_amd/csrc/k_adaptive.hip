@@ -3305,7 +3305,9 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     int tk = prof_begin(PROF_SPARSE, st);
     if (seq && seq->xs && !ql->exact) {
       // shared sequence: the sparse slots' samples are columns of the gathered rows
-      const dim3 grid(ns, (unsigned)std::max<int64_t>(1, std::min<int64_t>((sparse_list + SEQ_SP - 1) / SEQ_SP, 256)));
+      // (a few blocks per slot, looping over the list: with no sparse slot
+      // the launch is 16 blocks per slot that leave at once)
+      const dim3 grid(ns, (unsigned)std::max<int64_t>(1, std::min<int64_t>((sparse_list + SEQ_SP - 1) / SEQ_SP, 16)));
       if (G.metric == KNN_METRIC_L1)
         hipLaunchKernelGGL(k_sample_seq_sparse<KNN_METRIC_L1>, grid, dim3(NT), 0, st, slots, *seq, B, G);
       else

@@ -8,17 +8,17 @@
 // 2. Error bound per pair: |d~ - d| <= E = c1 |q| |x| + c2 (|q|^2 + |x|^2),
 //    c1 covering the split (3.01 2^-16 per product) and fp32 accumulation of
 //    3m terms (3m 2^-24), doubled for safety; c2 the fp32 epilogue roundings.
-// 3. Each block keeps, per query and over its range of points, the k
-//    smallest upper bounds u = d~ + E (in a wave's registers, lane j the
-//    j-th smallest, fed through a small LDS buffer), and appends to the
-//    range's candidate list every point whose lower bound l = d~ - E is at
-//    or below the running k-th smallest upper bound tau_r of the points
-//    seen so far.  The k-th smallest upper bound tau over all ranges bounds
-//    d_(k) from above, and tau <= the final tau_r <= every running tau_r
-//    of every range, so every true k-NN point (l <= d <= d_(k) <= tau) is in
-//    a candidate list.  A list that overflows its capacity sends its query
-//    to an exact rescan.
-// 4. Candidates with l <= tau are rescored in FP64, summing (x_j - q_j)^2 in
+// 3. A probe over the first tiles of every point range keeps, per query and
+//    range, the k smallest upper bounds u = d~ + E of the points it sees
+//    (in a wave register, lane j the j-th smallest, fed through a small LDS
+//    buffer).  tau0, the k-th smallest u over the union of those lists, is
+//    the upper bound of k real points, so tau0 >= d_(k); every true k-NN
+//    point has l = d~ - E <= d <= d_(k) <= tau0.
+// 4. The full scan screens each pair in the MFMA fragment layout and
+//    appends the pairs with l <= tau0 to the (query, range) candidate list;
+//    over a probe of s of the n points about k n / s points lie below tau0.
+//    A list that overflows its capacity sends its query to an exact rescan.
+// 5. The candidates are rescored in FP64, summing (x_j - q_j)^2 in
 //    coordinate order like the CPU reference, and the k smallest by
 //    (distance, index) are returned.
 // The l1 distance has no product form: its tile sums |x_j - q_j| in fp32 on
@@ -108,11 +108,11 @@ __global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t len, uint32_t v) {
     a[i] = v;
 }
 
-// SCREEN = false: the lists pass (running k smallest upper bounds per
-// query and range, candidates below the running bound); true: the screen
-// pass, with every query's bound fixed beforehand in gtau -- candidates
-// are the pairs whose lower bound is at or below it, and nothing else is
-// kept.
+// SCREEN = false: the probe (the k smallest upper bounds per query over
+// the first max_tiles tiles of each range, kept in a wave register per
+// query); true: the screen pass, with every query's bound fixed
+// beforehand in gtau -- the candidates are the pairs whose lower bound is
+// at or below it, and nothing else is kept.
 template <int MET, bool SCREEN>
 __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ Qh, const uint16_t *__restrict__ Ql,
                                                    const float *__restrict__ qn, const float *__restrict__ qr,
@@ -139,11 +139,7 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
   __shared__ int cbq[FBQ], ncq[FBQ];
   __shared__ __align__(16) float qnq[FBQ], qrq[FBQ];
   __shared__ uint8_t qflag[FBQ];       // the query has a pair in this tile that passes the screen
-  // the smallest running tau any range of the query has published (a key;
-  // ~0 none yet), read once per tile: every range's tau bounds d_(k) from
-  // above, so the smallest one screens candidates as soundly as its own
-  __shared__ uint32_t gtk[FBQ];
-  __shared__ __align__(16) float gtf[FBQ];
+  __shared__ __align__(16) float gtf[FBQ];  // the screen pass's fixed bound per query
   __shared__ float txn[FBP], txr[FBP];  // the tile's point norms
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int64_t q0 = (int64_t)blockIdx.y * FBQ;
@@ -156,7 +152,6 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
     const int64_t q = q0 + tid;
     tauq[tid] = PAD;
     tauf[tid] = INFINITY;
-    gtk[tid] = ~0u;
     gtf[tid] = INFINITY;
     qflag[tid] = 0;
     cbq[tid] = 0;
@@ -205,15 +200,9 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
   }
   if (SCREEN && tid < FBQ && q0 + tid < nq) {  // (fixed for the whole pass)
     const uint32_t g = gtau[q0 + tid];
-    gtk[tid] = g;
     gtf[tid] = g == ~0u ? INFINITY : fkey_inv(g);
   }
   for (int64_t p0 = pr0; p0 < pr1; p0 += FBP) {
-    if (!SCREEN && tid < FBQ && q0 + tid < nq) {  // (read by this tile's screen, after the K loop's barriers)
-      const uint32_t g = __hip_atomic_load(&gtau[q0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      gtk[tid] = g;
-      gtf[tid] = g == ~0u ? INFINITY : fkey_inv(g);
-    }
     // this lane's four points of the fragment layout (64 wp + 16 b + (lane &
     // 15)): norms loaded before the K loop so that their latency is hidden
     float xnf[4] = {0.0f, 0.0f, 0.0f, 0.0f}, xrf[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -319,19 +308,19 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
         }
       __syncthreads();
     }
-    // Screen in the fragment layout: a pair can matter to its query only
-    // if its lower bound l = d~ - E is at or below the query's running tau
-    // (the upper bound d~ + E >= l, so an insertion needs it too).  The
-    // expressions are the per-query pass's own, so this is a superset of
-    // its conditions; queries with no such pair in the tile are skipped
-    // there (they would change nothing).
+    // Screen in the fragment layout.  Screen pass: a pair is a candidate
+    // when its lower bound l = d~ - E is at or below the query's fixed
+    // bound, and is appended at once.  Probe: a pair can enter the query's
+    // list only when its upper bound d~ + E is at or below the running one;
+    // the expressions are the per-query pass's own, so the flag is a
+    // superset of its condition, and queries with no such pair in the tile
+    // are skipped there (they would change nothing).
     bool anyq = false;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int ql0 = 32 * wq + 16 * a + 4 * (lane >> 4);
-      const v4f_f tl = *reinterpret_cast<const v4f_f *>(&tauf[ql0]);
-      const v4f_f tg = *reinterpret_cast<const v4f_f *>(&gtf[ql0]);
-      const v4f_f tq = v4f_f{fminf(tl[0], tg[0]), fminf(tl[1], tg[1]), fminf(tl[2], tg[2]), fminf(tl[3], tg[3])};
+      // (screen pass: the fixed bound; probe: the query's running bound here)
+      const v4f_f tq = *reinterpret_cast<const v4f_f *>(SCREEN ? &gtf[ql0] : &tauf[ql0]);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         bool f = false;
@@ -339,15 +328,19 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
         for (int b = 0; b < 4; ++b) {
           const int64_t p = p0 + 64 * wp + 16 * b + (lane & 15);
           const float dot = acc[a][b][v];
-          float lo;
+          // the screen pass tests the lower bound (a candidate), the probe
+          // the upper bound (an insertion into the running list)
+          float bnd;
           if constexpr (MET == KNN_METRIC_L1) {
-            lo = dot - c1 * dot;
+            bnd = SCREEN ? dot - c1 * dot : dot + c1 * dot;
           } else {
             const float sn = qnf[a][v] + xnf[b];
             const float d = sn - 2.0f * dot;
-            lo = d - (cqr[a][v] * xrf[b] + c2 * sn);
+            const float E = cqr[a][v] * xrf[b] + c2 * sn;
+            bnd = SCREEN ? d - E : d + E;
           }
-          const bool pass = p < pr1 && q0 + ql0 + v < nq && lo <= tq[v];  // (padding queries of the last tile: none)
+          const float lo = bnd;
+          const bool pass = p < pr1 && q0 + ql0 + v < nq && bnd <= tq[v];  // (padding queries of the last tile: none)
           if constexpr (SCREEN) {
             if (pass) {  // a candidate: appended to the query's list of this range
               const int ql = ql0 + v;
@@ -389,8 +382,7 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
     __syncthreads();
     // per flagged query of this wave: upper bounds below the running k-th
     // one go to the LDS buffer (merged into the list when it would
-    // overflow); points whose lower bound is at or below it join the
-    // range's candidates
+    // overflow)
 #pragma unroll 1
     for (int t = 0; t < QPW; ++t) {
       const int ql = wave * QPW + t;
@@ -398,20 +390,18 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
       if (q >= nq) break;  // (wave-uniform)
       if (!qflag[ql]) continue;
       const float qnv = qnq[ql], qrv = qrq[ql];
-      uint64_t cu[2], cl[2];
+      uint64_t cu[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int pl = lane + 64 * h;
         const int64_t p = p0 + pl;
         cu[h] = PAD;
-        cl[h] = PAD;
         if (p < pr1) {
           const float dot = Ds[ql * FDSTR + pl];
           const float xnv = txn[pl], xrv = txr[pl];
           const float d = MET == KNN_METRIC_L1 ? dot : (qnv + xnv) - 2.0f * dot;
           const float E = MET == KNN_METRIC_L1 ? c1 * d : c1 * qrv * xrv + c2 * (qnv + xnv);
           cu[h] = ((uint64_t)fkey(d + E) << 32) | (uint64_t)p;
-          cl[h] = ((uint64_t)fkey(d - E) << 32) | (uint64_t)p;
         }
       }
       uint64_t tau = tauq[ql];
@@ -431,26 +421,10 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
           cbq[ql] = 0;
           tauq[ql] = tau;
           tauf[ql] = tau == PAD ? INFINITY : fkey_inv((uint32_t)(tau >> 32));
-          if (tau != PAD) atomicMin(&gtau[q], (uint32_t)(tau >> 32));
         }
       }
       // tau: the k-th smallest upper bound of the points seen so far (the
-      // buffered ones left out: a larger value, so a superset of the
-      // candidates); candidates are screened by the smaller of it and the
-      // smallest published by any range of the query
-      const uint32_t tau_key = min((uint32_t)(tau >> 32), gtk[ql]);
-      const bool g0 = cl[0] != PAD && (uint32_t)(cl[0] >> 32) <= tau_key;
-      const bool g1 = cl[1] != PAD && (uint32_t)(cl[1] >> 32) <= tau_key;
-      const uint64_t m0 = __ballot(g0), m1 = __ballot(g1);
-      if (m0 | m1) {  // (wave-uniform) candidates: lower bound <= tau
-        const int nc = ncq[ql];
-        uint64_t *dst = cand + (q * nranges + blockIdx.x) * (int64_t)FCL;
-        const int n0 = __popcll(m0);
-        const int pa = nc + __popcll(m0 & lt), pb = nc + n0 + __popcll(m1 & lt);
-        if (g0 && pa < FCL) dst[pa] = cl[0];
-        if (g1 && pb < FCL) dst[pb] = cl[1];
-        if (lane == 0) ncq[ql] = nc + n0 + __popcll(m1);
-      }
+      // buffered ones left out)
       const bool a0 = cu[0] < tau, a1 = cu[1] < tau;
       const uint64_t u0 = __ballot(a0), u1 = __ballot(a1);
       if (u0 | u1) {  // (wave-uniform) upper bounds below tau
@@ -469,7 +443,6 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
             cbq[ql] = 0;
             tauq[ql] = nt;
             tauf[ql] = nt == PAD ? INFINITY : fkey_inv((uint32_t)(nt >> 32));
-            if (nt != PAD) atomicMin(&gtau[q], (uint32_t)(nt >> 32));
           }
         } else {
           if (a0) Cb[ql][cb + __popcll(u0 & lt)] = cu[0];
@@ -519,9 +492,9 @@ __device__ __forceinline__ double exact_f64(const float *__restrict__ X, const f
 }
 
 constexpr int FCAP = 2048;  // candidate capacity per query in the merge
+constexpr int FMT = 1024;   // threads of a merge block (one candidate each while rescoring)
 
-__global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__restrict__ part,
-                                                          const uint64_t *__restrict__ candl,
+__global__ __launch_bounds__(FMT) void k_naive_f32_merge(const uint64_t *__restrict__ candl,
                                                           const int32_t *__restrict__ ncand, int64_t nranges, int k,
                                                           const float *__restrict__ X, const float *__restrict__ Q,
                                                           int64_t m, int met, int64_t *__restrict__ out_idx,
@@ -540,11 +513,11 @@ __global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__rest
   }
   __syncthreads();
   // a range whose candidate list overflowed may have dropped a candidate
-  for (int64_t r = threadIdx.x; r < nranges; r += 1024)
+  for (int64_t r = threadIdx.x; r < nranges; r += FMT)
     if (ncand[q * nranges + r] > FCL) atomicOr(&bad, 1);
   __syncthreads();
   if (!bad) {
-    for (int64_t t = threadIdx.x; t < nranges * FCL; t += 1024) {
+    for (int64_t t = threadIdx.x; t < nranges * FCL; t += FMT) {
       const int64_t r = t / FCL, j = t % FCL;
       if (j >= ncand[q * nranges + r]) continue;
       const uint64_t e = candl[(q * nranges + r) * FCL + j];
@@ -562,16 +535,16 @@ __global__ __launch_bounds__(1024) void k_naive_f32_merge(const uint64_t *__rest
   }
   const int c = cnt;
   const float *qv = Q + q * m;
-  for (int t = threadIdx.x; t < c; t += 1024) key[t] = dkey(exact_f64(X, qv, m, id[t], met));
+  for (int t = threadIdx.x; t < c; t += FMT) key[t] = dkey(exact_f64(X, qv, m, id[t], met));
   __syncthreads();
   int len = 1;
   while (len < c) len <<= 1;
-  for (int t = c + (int)threadIdx.x; t < len; t += 1024) {
+  for (int t = c + (int)threadIdx.x; t < len; t += FMT) {
     key[t] = ~0ull;
     id[t] = 0x7FFFFFFF;
   }
-  block_bitonic_sort<1024>(key, id, len);
-  for (int t = threadIdx.x; t < k; t += 1024) {
+  block_bitonic_sort<FMT>(key, id, len);
+  for (int t = threadIdx.x; t < k; t += FMT) {
     out_idx[q * k + t] = t < c ? (int64_t)id[t] : -1;
     if (out_dist) out_dist[q * k + t] = t < c ? dkey_inv(key[t]) : INFINITY;
   }
@@ -730,7 +703,7 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
   // work units: l2 three BF16 products of 2 operations; l1 a difference and an addition
   prof_end(tok, st, (l1 ? 2.0 : 3.0 * 2.0) * (double)nq * (double)n * (double)m);
   tok = prof_begin(PROF_NAIVE_REST, st);
-  hipLaunchKernelGGL(k_naive_f32_merge, dim3((unsigned)nq), dim3(1024), 0, st, part, candl, ncand, nranges, k,
+  hipLaunchKernelGGL(k_naive_f32_merge, dim3((unsigned)nq), dim3(FMT), 0, st, candl, ncand, nranges, k,
                      (const float *)db->X, dq, m, db->metric, out_idx, out_dist, flag, gtau);
   prof_end(tok, st, 0.0);
   HIP_TRY(hipGetLastError());
