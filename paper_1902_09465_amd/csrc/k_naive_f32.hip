@@ -89,7 +89,8 @@ constexpr int KCU = 64;   // upper-bound list capacity (k <= 64): one wave regis
 constexpr int FCB = 16;   // buffered upper-bound candidates per query before a merge
 constexpr int FCL = 384;  // candidate list capacity per (query, range)
 
-constexpr int64_t FPROBE = 4;  // tiles of every range in the probe pass
+constexpr int64_t FPROBE = 4;         // at least this many tiles of every range in the probe pass
+constexpr int64_t FPROBE_PTS = 32768;  // and at least this many points in all
 
 // Per query: the k-th smallest of the ranges' upper-bound lists (a key of
 // a real point's upper bound, so >= d_(k)) lowers the shared bound.
@@ -690,14 +691,19 @@ int naive_f32(knn_db_s *db, const float *dq, int64_t nq, int32_t k, int64_t *out
                          qn, qr, db->xbf, db->xbf + cells, db->norm_f, db->rownorm, nq, n, mp, k, prange, c1, c2, part,
                          candl, ncand, nranges, gtau, tiles);
   };
-  // A probe over the first FPROBE tiles of every range (the lists pass)
-  // gives each query tau0, the k-th smallest upper bound of the union of
-  // the ranges' lists: the upper bound of a real point, so tau0 >= d_(k),
-  // and every true k-NN point has l <= d <= d_(k) <= tau0.  The full scan
-  // then only screens: the pairs with l <= tau0 are the candidates, at
-  // least k of them (the points that gave tau0).  Over a sample of s of
-  // the n points, about k n / s points lie below tau0.
-  scan(FPROBE, false);
+  // A probe over the first tiles of every range (the lists pass) gives
+  // each query tau0, the k-th smallest upper bound of the union of the
+  // ranges' lists: the upper bound of a real point, so tau0 >= d_(k), and
+  // every true k-NN point has l <= d <= d_(k) <= tau0.  The full scan then
+  // only screens: the pairs with l <= tau0 are the candidates, at least k
+  // of them (the points that gave tau0).  Over a probe of s of the n
+  // points about k n / s points lie below tau0, so s is sized for about
+  // 1,024 candidates per query at most (the merge holds FCAP) and about
+  // FCL / 4 per (query, range).
+  const int64_t s_want = std::max<int64_t>(FPROBE_PTS, std::max<int64_t>((int64_t)k * n / 1024,
+                                                                           (int64_t)k * n / (FCL / 4 * nranges)));
+  const int64_t probe_tiles = std::max<int64_t>(FPROBE, (std::min(s_want, n) + nranges * FBP - 1) / (nranges * FBP));
+  scan(probe_tiles, false);
   hipLaunchKernelGGL(k_naive_f32_tau0, dim3((unsigned)nq), dim3(256), 0, st, part, nranges, k, gtau);
   scan(INT64_MAX / 2 / FBP, true);
   // work units: l2 three BF16 products of 2 operations; l1 a difference and an addition

@@ -94,11 +94,23 @@ def test_naive_f32_clustered_and_ties(P, orc):
 
 def test_naive_f32_float_config_sampled(P, orc):
     """The float workload (n = 1,000,000 x 128, 10,000 queries from a
-    1,000-cluster mixture); eight sampled queries against the oracle."""
+    1,000-cluster mixture); eight sampled queries against the oracle, and
+    no query needs the exact rescan (the probe is sized so that every
+    candidate list fits, also with few point ranges per query tile)."""
+    import ctypes
     from knn_inputs import gmm_f32
     X, Q = gmm_f32(3000, n=1_000_000, m=128, n_centres=1000, sigma=0.1, nq=10_000)
     db = P.KnnDB(dev(X))
-    idx, dist = db.naive(dev(Q), 10)
+    lib = P.lib()
+    P._lib.check(lib.knn_prof_enable(1))
+    try:
+        idx, dist = db.naive(dev(Q), 10)
+        torch.cuda.synchronize()
+        cnts = np.zeros(8, dtype=np.uint64)
+        P._lib.check(lib.knn_prof_counters(cnts.ctypes.data_as(ctypes.c_void_p)))
+    finally:
+        P._lib.check(lib.knn_prof_enable(0))
+    assert int(cnts[4]) == 0, f"{int(cnts[4])} queries rescanned"
     idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
     for q in (0, 1, 63, 64, 4999, 9998, 9999, 1234):
         ri, rd = orc.naive(X, Q[q], 10)
