@@ -204,6 +204,14 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
     gtf[tid] = g == ~0u ? INFINITY : fkey_inv(g);
   }
   for (int64_t p0 = pr0; p0 < pr1; p0 += FBP) {
+    if (!SCREEN && tid < FBQ && q0 + tid < nq) {
+      // probe: the smallest running bound any range of the query has
+      // published; the union's k-th smallest upper bound lies at or below
+      // it, so a pair whose upper bound exceeds it cannot change the result
+      // (read by this tile's screen, after the K loop's barriers)
+      const uint32_t g = __hip_atomic_load(&gtau[q0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      gtf[tid] = g == ~0u ? INFINITY : fkey_inv(g);
+    }
     // this lane's four points of the fragment layout (64 wp + 16 b + (lane &
     // 15)): norms loaded before the K loop so that their latency is hidden
     float xnf[4] = {0.0f, 0.0f, 0.0f, 0.0f}, xrf[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -320,8 +328,14 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int ql0 = 32 * wq + 16 * a + 4 * (lane >> 4);
-      // (screen pass: the fixed bound; probe: the query's running bound here)
-      const v4f_f tq = *reinterpret_cast<const v4f_f *>(SCREEN ? &gtf[ql0] : &tauf[ql0]);
+      // (screen pass: the fixed bound; probe: the smaller of the query's
+      // running bound here and the smallest any range has published)
+      const v4f_f tg = *reinterpret_cast<const v4f_f *>(&gtf[ql0]);
+      v4f_f tq = tg;
+      if constexpr (!SCREEN) {
+        const v4f_f tl = *reinterpret_cast<const v4f_f *>(&tauf[ql0]);
+        tq = v4f_f{fminf(tl[0], tg[0]), fminf(tl[1], tg[1]), fminf(tl[2], tg[2]), fminf(tl[3], tg[3])};
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         bool f = false;
@@ -422,6 +436,7 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
           cbq[ql] = 0;
           tauq[ql] = tau;
           tauf[ql] = tau == PAD ? INFINITY : fkey_inv((uint32_t)(tau >> 32));
+          if (tau != PAD) atomicMin(&gtau[q], (uint32_t)(tau >> 32));
         }
       }
       // tau: the k-th smallest upper bound of the points seen so far (the
@@ -444,6 +459,7 @@ __global__ __launch_bounds__(256) void k_naive_f32(const uint16_t *__restrict__ 
             cbq[ql] = 0;
             tauq[ql] = nt;
             tauf[ql] = nt == PAD ? INFINITY : fkey_inv((uint32_t)(nt >> 32));
+            if (nt != PAD) atomicMin(&gtau[q], (uint32_t)(nt >> 32));
           }
         } else {
           if (a0) Cb[ql][cb + __popcll(u0 & lt)] = cu[0];
@@ -494,6 +510,22 @@ __device__ __forceinline__ double exact_f64(const float *__restrict__ X, const f
 
 constexpr int FCAP = 2048;  // candidate capacity per query in the merge
 constexpr int FMT = 1024;   // threads of a merge block (one candidate each while rescoring)
+constexpr int FROWS = 12288;  // floats of LDS for candidate rows staged by the merge (48 KB)
+constexpr int FRANGES = 1024;  // point ranges whose lists the merge enumerates by prefix sums
+
+// The same sum over a row staged in LDS (stride >= m) and the query in LDS.
+__device__ __forceinline__ double exact_f64_lds(const float *row, const float *q, int64_t m, int met) {
+  double s = 0.0;
+  if (met == KNN_METRIC_L1) {
+    for (int64_t j = 0; j < m; ++j) s += fabs((double)row[j] - (double)q[j]);
+    return s;
+  }
+  for (int64_t j = 0; j < m; ++j) {
+    const double d = (double)row[j] - (double)q[j];
+    s += d * d;
+  }
+  return s;
+}
 
 __global__ __launch_bounds__(FMT) void k_naive_f32_merge(const uint64_t *__restrict__ candl,
                                                           const int32_t *__restrict__ ncand, int64_t nranges, int k,
@@ -513,20 +545,44 @@ __global__ __launch_bounds__(FMT) void k_naive_f32_merge(const uint64_t *__restr
     bad = 0;
   }
   __syncthreads();
-  // a range whose candidate list overflowed may have dropped a candidate
+  // a range whose candidate list overflowed may have dropped a candidate;
+  // the lists' lengths, then their entries enumerated through the prefix
+  // sums of the lengths (ranges at most FRANGES here, else range by range)
+  __shared__ int32_t pre[FRANGES + 1];
   for (int64_t r = threadIdx.x; r < nranges; r += FMT)
     if (ncand[q * nranges + r] > FCL) atomicOr(&bad, 1);
+  const bool small = nranges <= FRANGES;
+  if (small && threadIdx.x == 0) {
+    int acc = 0;
+    for (int64_t r = 0; r < nranges; ++r) {
+      pre[r] = acc;
+      acc += min(ncand[q * nranges + r], FCL);
+    }
+    pre[nranges] = acc;
+  }
   __syncthreads();
-  if (!bad) {
+  auto take = [&](uint64_t e) {
+    if ((uint32_t)(e >> 32) <= tau_key) {
+      const int pos = atomicAdd(&cnt, 1);
+      if (pos < FCAP) id[pos] = (int32_t)(e & 0xFFFFFFFFu);
+      else atomicOr(&bad, 1);
+    }
+  };
+  if (!bad && small) {
+    for (int t = threadIdx.x; t < pre[nranges]; t += FMT) {
+      int lo = 0, hi = (int)nranges;  // the range r with pre[r] <= t < pre[r + 1]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (pre[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      take(candl[(q * nranges + lo) * FCL + (t - pre[lo])]);
+    }
+  } else if (!bad) {
     for (int64_t t = threadIdx.x; t < nranges * FCL; t += FMT) {
       const int64_t r = t / FCL, j = t % FCL;
       if (j >= ncand[q * nranges + r]) continue;
-      const uint64_t e = candl[(q * nranges + r) * FCL + j];
-      if ((uint32_t)(e >> 32) <= tau_key) {
-        const int pos = atomicAdd(&cnt, 1);
-        if (pos < FCAP) id[pos] = (int32_t)(e & 0xFFFFFFFFu);
-        else atomicOr(&bad, 1);
-      }
+      take(candl[(q * nranges + r) * FCL + j]);
     }
   }
   __syncthreads();
@@ -536,7 +592,29 @@ __global__ __launch_bounds__(FMT) void k_naive_f32_merge(const uint64_t *__restr
   }
   const int c = cnt;
   const float *qv = Q + q * m;
-  for (int t = threadIdx.x; t < c; t += FMT) key[t] = dkey(exact_f64(X, qv, m, id[t], met));
+  // Rescoring, each candidate's sum in coordinate order by one thread.  For
+  // short rows the candidates' rows are staged in LDS a batch at a time by
+  // coalesced loads (rows padded to an odd stride: one bank per thread),
+  // the query too; long rows are read from global memory directly.
+  __shared__ float rows[FROWS];
+  const int64_t stride = m | 1;
+  const int nb = (int)std::min<int64_t>(FMT, (FROWS - stride) / stride);  // (one stride for the query)
+  if (nb >= 32) {
+    float *qs = rows + (int64_t)nb * stride;
+    for (int64_t j = threadIdx.x; j < m; j += FMT) qs[j] = qv[j];
+    for (int c0 = 0; c0 < c; c0 += nb) {
+      const int cb = std::min(nb, c - c0);
+      __syncthreads();  // (the previous batch's rows are consumed)
+      for (int64_t e = threadIdx.x; e < (int64_t)cb * m; e += FMT) {
+        const int64_t r = e / m, j = e - r * m;
+        rows[r * stride + j] = X[(int64_t)id[c0 + r] * m + j];
+      }
+      __syncthreads();
+      if (threadIdx.x < cb) key[c0 + threadIdx.x] = dkey(exact_f64_lds(rows + threadIdx.x * stride, qs, m, met));
+    }
+  } else {
+    for (int t = threadIdx.x; t < c; t += FMT) key[t] = dkey(exact_f64(X, qv, m, id[t], met));
+  }
   __syncthreads();
   int len = 1;
   while (len < c) len <<= 1;
