@@ -993,7 +993,15 @@ __global__ __launch_bounds__(NT) void k_seq_coords(uint64_t seed, int32_t norepl
   const PermKey pk = norepl ? perm_key(0u, draw_c3(true, true), k0, k1) : PermKey{{0u, 0u, 0u, 0u}};
   for (int64_t b = (int64_t)blockIdx.x * NT + threadIdx.x; 4 * b < kp; b += (int64_t)gridDim.x * NT) {
     uint32_t j4[4] = {~0u, ~0u, ~0u, ~0u};
-    if (4 * b < tlen) draw_block((uint32_t)b, 0u, draw_c3(true, false), k0, k1, mm, norepl != 0, ph, pk, j4);
+    if (4 * b + 4 <= tlen || (!norepl && 4 * b < tlen)) {
+      draw_block((uint32_t)b, 0u, draw_c3(true, false), k0, k1, mm, norepl != 0, ph, pk, j4);
+    } else if (4 * b < tlen) {
+      // the last, partial block of a permutation: only positions below
+      // tlen = m (the cycle walk from a position >= m need not return below m)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * b + e < tlen) j4[e] = perm_coord((uint32_t)(4 * b + e), mm, ph, pk);
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) js[4 * b + e] = 4 * b + e < tlen ? j4[e] : ~0u;
   }

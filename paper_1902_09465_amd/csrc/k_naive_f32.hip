@@ -89,7 +89,7 @@ constexpr int KCU = 64;   // upper-bound list capacity (k <= 64): one wave regis
 constexpr int FCB = 16;   // buffered upper-bound candidates per query before a merge
 constexpr int FCL = 384;  // candidate list capacity per (query, range)
 
-constexpr int64_t FPROBE = 4;         // at least this many tiles of every range in the probe pass
+constexpr int64_t FPROBE = 1;         // at least this many tiles of every range in the probe pass
 constexpr int64_t FPROBE_PTS = 32768;  // and at least this many points in all
 
 // Per query: the k-th smallest of the ranges' upper-bound lists (a key of

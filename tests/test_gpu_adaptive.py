@@ -612,7 +612,32 @@ def test_f32_shared_sequence_batched(P, orc, monkeypatch, sampling, metric):
         assert int(base[2][q]["rounds"]) == rst["rounds"], q
 
 
-@pytest.mark.parametrize("dtype,sampling", [("u8", 3), ("u8", 0), ("f32", 3)])
+@pytest.mark.parametrize("n,m,k,h,sampling,metric", [(257, 3, 20, 20, 3, "l2"), (130, 1, 5, 3, 2, "l2"),
+                                                  (300, 70, 1, 0, 3, "l1"), (1000, 129, 33, 10, 2, "l1")])
+def test_f32_shared_sequence_odd_shapes(P, orc, n, m, k, h, sampling, metric):
+    """The fp32 shared-sequence tiles on ragged shapes (point and column
+    counts off the tile sizes, m = 1, k = 1 with h = 0, k + h near n):
+    every query of a 21-query batch equals the oracle and the per-pair path."""
+    g = rng(n + 7 * m + k)
+    X = g.standard_normal((n, m)).astype(np.float32)
+    Q = (X[g.integers(0, n, size=21)] + 0.3 * g.standard_normal((21, m))).astype(np.float32)
+    db = P.KnnDB(dev(X), metric=metric)
+    kw = dict(h=h, delta=0.05, seed=29, sampling=sampling, b0=4, growth=2.0)
+    base = db.adaptive(dev(Q), k, P.default_params(**kw))
+    os.environ["KNN_SEQ"] = "0"
+    try:
+        alt = db.adaptive(dev(Q), k, P.default_params(**kw))
+    finally:
+        del os.environ["KNN_SEQ"]
+    assert torch.equal(base[0], alt[0]) and torch.equal(base[1], alt[1]) and np.array_equal(base[2], alt[2])
+    idx, cnt = base[0].cpu().numpy(), base[1].cpu().numpy()
+    for q in range(21):
+        ref, rst = orc.adaptive(X, Q[q], k, oparams(orc, **kw), metric=1 if metric == "l1" else 0)
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert int(base[2][q]["coord_evals"]) == rst["coord_evals"], q
+
+
+@pytest.mark.parametrize("dtype,sampling", [("u8", 3), ("u8", 0), ("f32", 3), ("f32", 1)])
 def test_batch_larger_than_slots_in_chunks(P, orc, monkeypatch, dtype, sampling):
     """A one-seed batch with more queries than slots runs as consecutive
     lock-step batches (equal sizes, the last one smaller and uncaptured):

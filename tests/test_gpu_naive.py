@@ -139,3 +139,27 @@ def test_naive_large_k_exact_scan(P, orc, dtype, metric, k):
         ri, rd = orc.naive(X, Q[q], k, metric=1 if metric == "l1" else 0)
         assert idx[q].tolist() == ri.tolist(), q
         assert np.array_equal(dist[q], rd), q
+
+
+def test_naive_f32_one_query_many_ranges(P, orc):
+    """One query over 200,000 points: the scan splits the points into about
+    a thousand ranges, the probe takes a tile of each; the set and the
+    distances equal the oracle's and no query is rescanned."""
+    import ctypes
+    g = rng(4242)
+    X = g.standard_normal((200_000, 64)).astype(np.float32)
+    Q = (X[[12345]] + 0.05 * g.standard_normal((1, 64))).astype(np.float32)
+    db = P.KnnDB(dev(X))
+    lib = P.lib()
+    P._lib.check(lib.knn_prof_enable(1))
+    try:
+        idx, dist = db.naive(dev(Q), 10)
+        torch.cuda.synchronize()
+        cnts = np.zeros(8, dtype=np.uint64)
+        P._lib.check(lib.knn_prof_counters(cnts.ctypes.data_as(ctypes.c_void_p)))
+    finally:
+        P._lib.check(lib.knn_prof_enable(0))
+    assert int(cnts[4]) == 0
+    ri, rd = orc.naive(X, Q[0], 10)
+    assert idx.cpu().numpy()[0].tolist() == ri.tolist()
+    assert np.array_equal(dist.cpu().numpy()[0], rd)
