@@ -859,7 +859,7 @@ def main():
                                "sigma=30, 1024 queries sharing one seed, k=10 h=10 delta=0.01, footnote width, "
                                "B0=64, g=2, " + SAMPLING_NAMES[args.sampling] +
                                (", l1 distance" if l1 else ""),
-                   "global_batch": NQ, "seq_len": M, "parallelism": "single GPU"},
+                   "queries": NQ, "n": N, "m": M, "parallelism": "single GPU"},
         "contained": f"{n_ok}/{NQ}",
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "note": "whole-batch span per step on the stream (all 1024 queries finish together; "
