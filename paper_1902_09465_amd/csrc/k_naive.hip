@@ -118,7 +118,11 @@ int naive_prepare_db(knn_db_s *db, hipStream_t st) {
   }
   if (db->dtype == KNN_U8) {
     HIP_TRY(hipMalloc(&db->xs8, (size_t)db->n * db->mp));
-    HIP_TRY(hipMalloc(&db->norm_i, sizeof(int32_t) * db->n));
+    // norms padded to whole 256-point tiles (the wide scan loads a tile's
+    // norms as one 1 KB piece)
+    const size_t nn = (size_t)(db->n + 255) / 256 * 256;
+    HIP_TRY(hipMalloc(&db->norm_i, sizeof(int32_t) * nn));
+    HIP_TRY(hipMemsetAsync(db->norm_i, 0, sizeof(int32_t) * nn, st));
     hipLaunchKernelGGL(k_prep_u8_rows, dim3((unsigned)db->n), dim3(256), 0, st, db->X, db->n, db->m, db->mp,
                        db->xs8, db->norm_i);
     HIP_TRY(hipGetLastError());
@@ -820,6 +824,390 @@ void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, 
 #undef KNN_EXACT_LAUNCH
 }
 
+// ---------------------------------------------------------------- wide u8 scan (squared l2, k <= 64)
+
+// Block tile 128 queries x 256 points, eight waves of 64 x 64 (wave w:
+// queries 64 (w >> 2) + [0, 64), points 64 (w & 3) + [0, 64); the MFMA
+// output layout as in gemm_u8_tile).  The K loop runs over 64-byte stages of
+// both row tiles held in a ring of NST LDS buffers.  Stages arrive by direct
+// global-to-LDS loads (global_load_lds_dwordx4: one wave instruction moves
+// 16 rows x 64 bytes, lane j writing bytes [16 j, 16 j + 16) of its 1 KB), so
+// nothing is staged in registers.  A row's four 16-byte pieces are stored permuted by
+// wswz(row), which makes the fragment reads (16 rows, one piece each)
+// conflict-free.  A stage's fragments are read into registers while the
+// previous stage's products run, so NST - 2 stages are in flight during the
+// products.  The stage stream runs on across the block's tiles: the next
+// tile's first stages load during a tile's epilogue.
+namespace wide {
+constexpr int TQ = 128, TP = 256, BK = 64;
+constexpr int STAGE = (TQ + TP) * BK;           // 24 KB
+constexpr int DMA = STAGE / 1024 / 8;           // wave instructions per wave and stage (3)
+constexpr int SUB = 8;                          // candidates per (query, point quarter) and tile (< 0x77)
+constexpr int WSTR = 68;                        // row stride (words) of a staged wave tile
+__device__ __forceinline__ int wswz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
+// s_waitcnt with only the vector-memory count bounded (expcnt and lgkmcnt at
+// their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x70 | 0xF00);
+}
+}  // namespace wide
+
+// One wave-wide global-to-LDS load: 16 bytes per lane from gptr to LDS bytes
+// [lds + 16 lane, lds + 16 lane + 16) (lds the same in every lane).  Inline
+// asm rather than the builtin: the compiler cannot tell the ring's buffers
+// apart and would wait for every load in flight before each LDS read; the
+// ring's own waits (wide_sync) order these writes before their reads.  No
+// register is written (the data goes to LDS), so nothing is left pending in
+// registers.
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+  return (uint32_t)(uintptr_t)((__attribute__((address_space(3))) const void *)p);
+}
+__device__ __forceinline__ void lds_load16(const void *gptr, uint32_t lds) {
+  const uint32_t a = __builtin_amdgcn_readfirstlane(lds);
+  uint32_t m0_saved;  // m0 is restored for the compiler's own uses
+  asm volatile(
+      "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
+      : "=&s"(m0_saved)
+      : "v"(gptr), "s"(a)
+      : "memory");
+}
+
+// The 16-byte piece of K this lane loads for every stage row it fills (row
+// 16 e + lane / 4 of the stage's 1 KB piece e): (lane % 4) ^ wswz(row), where
+// the row's low four bits are lane / 4.
+__device__ __forceinline__ int wide_piece(int lane) { return 16 * ((lane & 3) ^ wide::wswz(lane >> 2)); }
+
+// The wave's fragments of one stage (K step 64): query rows 64 wq + 16 a,
+// point rows 64 wp + 16 b of the stage.
+__device__ __forceinline__ void wide_frag(const uint8_t *slot, v4i (&af)[4], v4i (&bf)[4]) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 2, wp = wave & 3;
+  const int off = (lane & 15) * 64 + 16 * ((lane >> 4) ^ wide::wswz(lane & 15));
+#pragma unroll
+  for (int a = 0; a < 4; ++a) af[a] = *reinterpret_cast<const v4i *>(slot + (64 * wq + 16 * a) * 64 + off);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) bf[b] = *reinterpret_cast<const v4i *>(slot + (wide::TQ + 64 * wp + 16 * b) * 64 + off);
+}
+
+__device__ __forceinline__ void wide_mma(const v4i (&af)[4], const v4i (&bf)[4], v4i (&acc)[4][4]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
+}
+
+// Wait until this wave's loads of the stage before the last `ahead` issued
+// stages (ahead <= 3) have landed, then barrier: every wave's loads of it have
+// landed and every wave is done with the previous stage's buffer.
+__device__ __forceinline__ void wide_sync(int ahead) {
+  asm volatile("" ::: "memory");
+  if (ahead >= 3) wide::wait_vm<3 * wide::DMA>();
+  else if (ahead == 2) wide::wait_vm<2 * wide::DMA>();
+  else if (ahead == 1) wide::wait_vm<wide::DMA>();
+  else wide::wait_vm<0>();
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS reads are done
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Sorted 64-lane list (ascending keys, PAD at the end): insert key x.
+__device__ __forceinline__ uint64_t list_insert(uint64_t L, uint64_t x) {
+  const int lane = lane_id();
+  const int pos = __popcll(__ballot(L < x));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)L, 0x138, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(L >> 32), 0x138, 0xF, 0xF, false);
+  const uint64_t up = ((uint64_t)hi << 32) | lo;  // lane l: L of lane l - 1 (wave_shr:1)
+  return lane < pos ? L : (lane == pos ? x : up);
+}
+
+// The list with the candidates (one per lane, ~0 = none) absorbed: the 64
+// smallest keys of both, sorted.  Up to 12 candidates are inserted one at a
+// time (an insertion costs about a twelfth of a sort and merge); more are
+// sorted, and merged unless the list is empty.
+__device__ __forceinline__ uint64_t list_absorb(uint64_t L, uint64_t cand) {
+  uint64_t mask = __ballot(cand != ~0ull);
+  if (mask == 0) return L;
+  if (__popcll(mask) > 12) {
+    if (wave_bcast_u64(L, 0) == ~0ull) return wave_sort_u64(cand);
+    return merge_sorted64(L, cand);
+  }
+  while (mask) {
+    const int j = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    L = list_insert(L, wave_bcast_u64(cand, j));
+  }
+  return L;
+}
+
+// The scan for k <= 64 on the wide tile.  Per block: one 128-query tile and
+// one range of whole point tiles; the blocks of one range run on one XCD
+// (they read the same point rows).  Each query's running list (the 64
+// smallest keys (distance << 32 | index) so far, sorted over the lanes) lives
+// in the registers of its owner wave (queries 16 w .. 16 w + 15).  Epilogue of
+// a tile, once every list holds k keys: each wave compares its 64 x 64
+// distances in the fragment layout with the owners' k-th keys (tauq) and
+// appends the few below to a per (query, point quarter) buffer of SUB keys;
+// the owners absorb them and publish their new k-th keys.  The first tile of
+// a range (lists not yet full), and the queries whose buffer overflowed, take
+// the other way: each wave tile's distances are staged in LDS in turn and the
+// owners absorb them one point row at a time.
+template <int NST>
+__global__ __launch_bounds__(512) void k_naive_u8_wide(const int8_t *__restrict__ Q8, const int32_t *__restrict__ qn,
+                                                       const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
+                                                       int64_t nq, int64_t n, int64_t mp, int k, int64_t nranges,
+                                                       uint64_t *__restrict__ part) {
+  using namespace wide;
+  constexpr uint64_t PAD = ~0ull;
+  static_assert(NST >= 3 && NST <= 5, "stages in flight: 1..3");
+  __shared__ __align__(1024) uint8_t ring[NST * STAGE];
+  // the candidate buffers, or (staged way, after they are read) one wave
+  // tile's distances
+  constexpr int CBW = TQ * 4 * SUB * 2 > 64 * WSTR ? TQ * 4 * SUB * 2 : 64 * WSTR;
+  __shared__ __align__(16) uint32_t cbw[CBW];
+  uint64_t(*Cb)[4 * SUB] = reinterpret_cast<uint64_t(*)[4 * SUB]>(cbw);
+  uint32_t *Ds = cbw;
+  __shared__ uint64_t tauq[TQ];
+  __shared__ uint32_t qnl[TQ];   // |q'|^2 of the tile's queries
+  // |x'|^2 of the points of the tiles in flight (tile t_lo + i in buffer i % NST:
+  // at most NST tiles have a stage loaded and not yet multiplied)
+  __shared__ __align__(16) uint32_t xnl[NST][TP];
+  __shared__ uint32_t cntq[TQ];  // byte wp: candidates of point quarter wp this tile (SUB + 1: overflow)
+  __shared__ int flags[2];       // per tile parity: bit 0 some list not yet full, bit 1 overflow
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, wq = wave >> 2, wp = wave & 3, g = lane >> 4;
+  const int64_t nqt = (nq + TQ - 1) / TQ;
+  const int64_t j = blockIdx.x / kXcds;
+  const int64_t r = (j / nqt) * kXcds + blockIdx.x % kXcds;  // point range (all its query tiles on one XCD)
+  if (r >= nranges) return;
+  const int64_t q0 = (j % nqt) * TQ;
+  const int64_t ntile = (n + TP - 1) / TP;
+  const int64_t t_lo = r * ntile / nranges, t_hi = (r + 1) * ntile / nranges;
+  const int nsl = (int)(mp / BK);
+  const int nst = (int)((t_hi - t_lo) * nsl);  // the block's stages
+  // loads: per wave and stage one 1 KB piece of the query rows (piece
+  // `wave`) and two of the point rows (pieces wave + 8, wave + 16); rows past
+  // nq (n) repeat the last row, which the epilogue ignores
+  const int piece = wide_piece(lane), rl = 16 * wave + (lane >> 2);
+  const int8_t *asrc = Q8 + std::min<int64_t>(q0 + rl, nq - 1) * mp + piece;
+  const int8_t *bsrc0 = nullptr, *bsrc1 = nullptr;
+  int it = 0, isl = 0, iss = 0;  // next stage to load: tile t_lo + it, stage isl; stages loaded so far
+  auto point_rows = [&]() {
+    const int64_t tp = (t_lo + it) * TP;
+    bsrc0 = X8 + std::min<int64_t>(tp + rl, n - 1) * mp + piece;
+    bsrc1 = X8 + std::min<int64_t>(tp + 128 + rl, n - 1) * mp + piece;
+  };
+  const uint32_t ring_lds = lds_addr(ring), xnl_lds = lds_addr(&xnl[0][0]);
+  int islot = 0, ixn = 0;  // ring buffer of the next load; norm buffer of the next tile
+  auto issue = [&]() {
+    const uint32_t slot = ring_lds + islot * STAGE + 1024 * wave;
+    const int64_t k0 = (int64_t)isl * BK;
+    lds_load16(asrc + k0, slot);
+    lds_load16(bsrc0 + k0, slot + 8 * 1024);
+    lds_load16(bsrc1 + k0, slot + 16 * 1024);
+    // with a tile's first stage, wave 0 also loads the tile's point norms
+    // (the norm array is padded to whole tiles)
+    if (isl == 0) {
+      if (wave == 0) lds_load16(xn + (t_lo + it) * TP + 4 * lane, xnl_lds + ixn * TP * 4);
+      ixn = ixn + 1 == NST ? 0 : ixn + 1;
+    }
+    islot = islot + 1 == NST ? 0 : islot + 1;
+    ++iss;
+    if (++isl == nsl) {
+      isl = 0;
+      ++it;
+      if (t_lo + it < t_hi) point_rows();
+    }
+  };
+  if (tid < TQ) {  // (before the first ring loads: the compiler waits for this load with vmcnt(0))
+    tauq[tid] = q0 + tid < nq ? PAD : 0ull;  // nothing passes for a query past nq
+    qnl[tid] = q0 + tid < nq ? (uint32_t)qn[q0 + tid] : 0u;
+    cntq[tid] = 0;
+  }
+  point_rows();
+#pragma unroll
+  for (int s = 0; s < NST - 1; ++s)
+    if (s < nst) issue();
+  // the fragments of a stage are read one stage ahead of its products
+  v4i fa[4], fb[4];
+  wide_sync(iss - 1);
+  wide_frag(ring, fa, fb);
+  int rslot = 1;  // ring buffer of the stage after the current one
+  uint64_t L[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) L[t] = PAD;
+  if (tid == 0) {
+    flags[0] = 1;
+    flags[1] = 0;
+  }
+  int s = 0;
+  for (int64_t t = t_lo; t < t_hi; ++t) {
+    const int64_t tp0 = t * TP, pend = std::min(n, tp0 + TP);
+    v4i acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+    // stage s + 1 landed (and every wave is past stage s - 1, whose buffer
+    // takes the next load); its fragments load during this stage's products.
+    // After the block's last stage the read is of a stale buffer and unused.
+    // Two stages per iteration, the fragment registers in alternation.
+    v4i na[4], nb[4];
+    auto step = [&](v4i(&ca)[4], v4i(&cb)[4], v4i(&xa)[4], v4i(&xb)[4]) {
+      wide_sync(std::max(0, iss - 2 - s));
+      if (iss < nst) issue();
+      wide_frag(ring + rslot * STAGE, xa, xb);
+      rslot = rslot + 1 == NST ? 0 : rslot + 1;
+      wide_mma(ca, cb, acc);
+      ++s;
+    };
+    int sl = 0;
+    for (; sl + 1 < nsl; sl += 2) {
+      step(fa, fb, na, nb);
+      step(na, nb, fa, fb);
+    }
+    if (sl < nsl) {
+      step(fa, fb, na, nb);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        fa[e] = na[e];
+        fb[e] = nb[e];
+      }
+    }
+    uint32_t xv[4];  // |x'|^2 of the lane's points (fragment columns; loaded with the tile's first stage)
+    bool pok[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int pl = 64 * wp + 16 * b + (lane & 15);
+      pok[b] = tp0 + pl < pend;
+      xv[b] = xnl[(t - t_lo) % NST][pl];  // (buffer (t - t_lo) % NST: loaded with the tile's first stage)
+    }
+    uint32_t qv[4][4];  // |q'|^2 of the lane's queries (fragment rows)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qv[a][v] = qnl[64 * wq + 16 * a + 4 * g + v];
+    const int par = (int)((t - t_lo) & 1);
+    const int fl0 = flags[par];  // written before the stage barriers of this tile
+    uint32_t need = 0;           // owner: queries 16 wave + i that take the staged way this tile
+    if (!(fl0 & 1)) {
+      // screen in the fragment layout against the owners' k-th keys: a
+      // 32-bit test of the distance first (d <= the k-th key's distance, a
+      // superset), the exact key test only for a fragment row with a hit
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ql = 64 * wq + 16 * a + 4 * g + v;
+          const uint64_t tau = tauq[ql];
+          const uint32_t th = (uint32_t)(tau >> 32);
+          uint32_t d[4];
+          bool hit = false;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            d[b] = qv[a][v] + xv[b] - 2u * (uint32_t)acc[a][b][v];
+            hit = hit || (pok[b] && d[b] <= th);
+          }
+          if (__ballot(hit) == 0) continue;  // wave-uniform
+          int cnt = 0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const uint64_t key = ((uint64_t)d[b] << 32) | (uint64_t)(tp0 + 64 * wp + 16 * b + (lane & 15));
+            const bool pass = pok[b] && key < tau;
+            const uint64_t m = __ballot(pass);
+            const uint32_t gm = (uint32_t)(m >> (16 * g)) & 0xFFFFu;
+            const int pre = __popc(gm & ((1u << (lane & 15)) - 1u));
+            if (pass && cnt + pre < SUB) Cb[ql][SUB * wp + cnt + pre] = key;
+            cnt += __popc(gm);
+          }
+          if ((lane & 15) == 0 && cnt > 0)
+            reinterpret_cast<uint8_t *>(cntq)[4 * ql + wp] = (uint8_t)std::min(cnt, SUB + 1);
+        }
+      if (tid == 0) flags[par ^ 1] = 0;  // (read again two tiles on, after many barriers)
+      __syncthreads();
+      // owners absorb their buffers; an overflowed query takes the staged way.
+      // Lane i < 16 reads the counts of query 16 wave + i.
+      const uint32_t c4l = lane < 16 ? cntq[16 * wave + lane] : 0u;
+      const uint64_t has = __ballot(c4l != 0);
+      const uint64_t ovf = __ballot(((c4l + 0x77777777u) & 0x80808080u) != 0);  // some byte above SUB
+      if (c4l != 0) cntq[16 * wave + lane] = 0;
+      const int any = ovf != 0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (!((has >> i) & 1u)) continue;  // wave-uniform
+        if ((ovf >> i) & 1u) {
+          need |= 1u << i;
+          continue;
+        }
+        const int ql = 16 * wave + i;
+        const uint32_t c4 = (uint32_t)__builtin_amdgcn_readlane((int)c4l, i);
+        // lane j < 4 SUB: entry j % SUB of quarter j / SUB
+        const int sub = (lane / SUB) & 3, e = lane % SUB;
+        const uint64_t cand = (lane < 4 * SUB && e < (int)((c4 >> (8 * sub)) & 255u)) ? Cb[ql][lane] : PAD;
+        L[i] = list_absorb(L[i], cand);
+        const uint64_t tau = wave_bcast_u64(L[i], k - 1);
+        if (lane == 0) tauq[ql] = tau;
+      }
+      if (any && lane == 0) atomicOr(&flags[par], 2);
+      __syncthreads();
+    } else {
+      if (tid == 0) flags[par ^ 1] = 0;
+      need = 0xFFFFu;
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (q0 + 16 * wave + i >= nq) need &= ~(1u << i);
+    }
+    if ((fl0 & 1) || (flags[par] & 2)) {  // block-uniform
+      // the staged way: each wave tile's distances through LDS in turn
+      for (int w8 = 0; w8 < 8; ++w8) {
+        if (wave == w8) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int ql = 16 * a + 4 * g + v;
+                const uint32_t d = qv[a][v] + xv[b] - 2u * (uint32_t)acc[a][b][v];
+                Ds[ql * WSTR + 16 * b + (lane & 15)] = pok[b] ? d : 0xFFFFFFFFu;
+              }
+        }
+        __syncthreads();
+        if ((wave >> 2) == (w8 >> 2) && need != 0) {
+          const int64_t pb = tp0 + 64 * (w8 & 3) + lane;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            if (!((need >> i) & 1u)) continue;
+            const int ql = 16 * (wave & 3) + i;  // row of the staged tile
+            const uint32_t d = Ds[ql * WSTR + lane];
+            const uint64_t key = d == 0xFFFFFFFFu ? PAD : (((uint64_t)d << 32) | (uint64_t)pb);
+            const uint64_t tau = wave_bcast_u64(L[i], k - 1);
+            L[i] = list_absorb(L[i], key < tau ? key : PAD);
+          }
+        }
+        __syncthreads();
+      }
+      bool full = true;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const uint64_t tau = wave_bcast_u64(L[i], k - 1);
+        if ((need >> i) & 1u) {
+          if (lane == 0) tauq[16 * wave + i] = tau;
+          full = full && tau != PAD;
+        }
+      }
+      // a query past nq keeps tauq = PAD but never counts against `full`
+      if (!full && lane == 0) atomicOr(&flags[par ^ 1], 1);
+    }
+    // (the next tile's stage barriers order these LDS writes before its reads)
+  }
+  // the block's list per query -> part[q][range][k]
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int64_t q = q0 + 16 * wave + i;
+    if (q < nq && lane < k) part[(q * nranges + r) * (int64_t)k + lane] = L[i];
+  }
+}
+
 // Merge per query: the k smallest keys over all ranges, sorted; index and
 // distance out.
 __global__ __launch_bounds__(1024) void k_naive_merge(const uint64_t *__restrict__ part, int64_t nranges, int k,
@@ -901,11 +1289,61 @@ static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int6
   if (l1 && db->m > 16777216) return fail(KNN_EINVAL, "naive u8 l1 scan supports m <= 2^24");
   if (k > 128) return fail(KNN_EINVAL, "naive u8 scan supports k <= 128");
   const int64_t n = db->n;
+  const char *nb_env = std::getenv("KNN_NAIVE_BLOCKS");
+  const char *wide_env = std::getenv("KNN_NAIVE_WIDE");
+  if (!l1 && k <= 64 && !(wide_env && wide_env[0] == '0')) {
+    // the wide tile: about KNN_NAIVE_BLOCKS blocks (default 256, one per CU),
+    // point ranges of whole 256-point tiles
+    const int64_t nqt = (nq + wide::TQ - 1) / wide::TQ, ntile = (n + wide::TP - 1) / wide::TP;
+    const int64_t nblk = std::max<int64_t>(1, nb_env ? std::atoll(nb_env) : 256);
+    int64_t nranges = std::max<int64_t>(1, std::min<int64_t>(ntile, (nblk + nqt - 1) / nqt));
+    NaiveU8Ws w;
+    w.bytes_q = (size_t)nq * db->mp + 256;
+    w.bytes_qn = sizeof(int32_t) * nq + 256;
+    auto part_bytes = [&](int64_t nr) { return sizeof(uint64_t) * (size_t)nq * (size_t)nr * (size_t)k; };
+    w.bytes_part = part_bytes(nranges);
+    void *ws = ws_fixed;
+    if (ws_fixed) {
+      while (w.total() > ws_cap && nranges > 1) {
+        nranges = (nranges + 1) / 2;
+        w.bytes_part = part_bytes(nranges);
+      }
+      if (w.total() > ws_cap)
+        return fail(KNN_EINVAL, "naive scan needs " + std::to_string(w.total()) + " bytes of working memory, more "
+                                    "than the fixed " + std::to_string(ws_cap));
+    } else {
+      HIP_TRY(hipMallocAsync(&ws, w.total(), st));
+    }
+    int8_t *Q8 = (int8_t *)ws;
+    int32_t *qn = (int32_t *)((uint8_t *)ws + w.bytes_q);
+    uint64_t *part = (uint64_t *)((uint8_t *)ws + w.bytes_q + w.bytes_qn);
+    int tok = prof_begin(PROF_NAIVE_REST, st);
+    hipLaunchKernelGGL(k_prep_u8_queries, dim3((unsigned)nq), dim3(256), 0, st, dq, db->m, db->mp, Q8, qn);
+    prof_end(tok, st, 0.0);
+    tok = prof_begin(PROF_NAIVE_GEMM, st);
+    const int64_t nblocks = (nranges + kXcds - 1) / kXcds * kXcds * nqt;
+    // LDS ring stages (KNN_NAIVE_STAGES: 3, 4 or 5 (default); NST - 1 in flight)
+    const char *ns_env = std::getenv("KNN_NAIVE_STAGES");
+    const int nstages = ns_env ? std::atoi(ns_env) : 5;
+#define KNN_WIDE_LAUNCH(NST_)                                                                                  \
+  hipLaunchKernelGGL(k_naive_u8_wide<NST_>, dim3((unsigned)nblocks), dim3(512), 0, st, Q8, qn, db->xs8,       \
+                     db->norm_i, nq, n, db->mp, k, nranges, part)
+    if (nstages == 3) KNN_WIDE_LAUNCH(3);
+    else if (nstages == 4) KNN_WIDE_LAUNCH(4);
+    else KNN_WIDE_LAUNCH(5);
+#undef KNN_WIDE_LAUNCH
+    prof_end(tok, st, 2.0 * (double)nq * (double)n * (double)db->m);
+    tok = prof_begin(PROF_NAIVE_REST, st);
+    hipLaunchKernelGGL(k_naive_merge, dim3((unsigned)nq), dim3(1024), 0, st, part, nranges, k, out_idx, out_dist);
+    prof_end(tok, st, 0.0);
+    HIP_TRY(hipGetLastError());
+    if (!ws_fixed) HIP_TRY(hipFreeAsync(ws, st));
+    return KNN_OK;
+  }
   const int64_t qt = (nq + NBQ - 1) / NBQ;
   // about KNN_NAIVE_BLOCKS blocks in all (default 512: two per CU, one
   // wave of blocks); longer point ranges amortise each block's first tiles,
   // where every distance still enters the running lists
-  const char *nb_env = std::getenv("KNN_NAIVE_BLOCKS");
   const int64_t nblk = std::max<int64_t>(1, nb_env ? std::atoll(nb_env) : 512);
   int64_t prange = (n * qt + nblk - 1) / nblk;
   prange = std::max<int64_t>(NBP, (prange + NBP - 1) / NBP * NBP);

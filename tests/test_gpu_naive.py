@@ -61,6 +61,35 @@ def test_naive_u8_batched_config_sampled(P, orc):
         assert np.array_equal(dist[q], rd)
 
 
+@pytest.mark.parametrize("n,m,nq,k,blocks", [(5000, 256, 200, 10, 2), (5000, 128, 130, 64, 2), (9000, 64, 300, 1, 3),
+                                              (3000, 320, 129, 33, 1), (2600, 192, 1, 5, 1), (70, 64, 3, 10, 256),
+                                              (1000, 100, 5, 64, 1)])
+def test_naive_u8_wide_tile_ranges(P, orc, monkeypatch, n, m, nq, k, blocks):
+    """The scan's 128-query x 256-point tile (k <= 64) with few point ranges,
+    so that a block walks many tiles: a range's first tile fills the lists
+    through LDS, later tiles are screened in the fragment layout against
+    each list's k-th key, and a buffer that overflows sends its query the
+    staged way again.  Half the queries sit next to a point, so the top of
+    each list is crowded.  Every query equals the oracle, and the 64 x 128
+    tile (KNN_NAIVE_WIDE=0) gives the same indices and distances."""
+    g = rng(11 * n + m + k)
+    X = g.integers(0, 256, size=(n, m), dtype=np.uint8)
+    Q = g.integers(0, 256, size=(nq, m), dtype=np.uint8)
+    near = X[g.integers(0, n, nq // 2)].astype(np.int64) + g.integers(-3, 4, (nq // 2, m))
+    Q[: nq // 2] = np.clip(near, 0, 255).astype(np.uint8)
+    db = P.KnnDB(dev(X))
+    monkeypatch.setenv("KNN_NAIVE_BLOCKS", str(blocks))
+    idx, dist = db.naive(dev(Q), k)
+    monkeypatch.setenv("KNN_NAIVE_WIDE", "0")
+    idx0, dist0 = db.naive(dev(Q), k)
+    assert torch.equal(idx, idx0) and torch.equal(dist, dist0)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    for q in range(nq):
+        ri, rd = orc.naive(X, Q[q], k)
+        assert idx[q].tolist() == ri.tolist(), q
+        assert np.array_equal(dist[q], rd), q
+
+
 @pytest.mark.parametrize("n,m,nq,k", [(5003, 100, 70, 10), (3000, 128, 65, 64), (777, 3, 5, 1),
                                       (2049, 300, 17, 33)])
 def test_naive_f32_parity(P, orc, n, m, nq, k):
