@@ -97,7 +97,8 @@ def profile_pass(args):
     """The workload of the counter and kernel-trace passes: a plain device copy
     of COPY_BYTES (calibrates FETCH_SIZE / WRITE_SIZE), then `--steps`
     adaptive batches of the batched-integer workload in sampling mode
-    `--sampling`, launched eagerly (no graph)."""
+    `--sampling`, launched eagerly (no graph); with --naive, `--steps` naive
+    scans of the same batch instead."""
     os.environ["KNN_GRAPH"] = "0"
     import torch
     from knn_inputs import gmm_u8
@@ -111,6 +112,12 @@ def profile_pass(args):
     X, Q = gmm_u8(2000, n=N, m=M, n_centres=32, sigma=30.0, nq=NQ)
     db = P.KnnDB(torch.from_numpy(X).cuda())
     Qd = torch.from_numpy(Q).cuda()
+    if args.naive:
+        for s in range(args.steps):
+            db.naive(Qd, K, with_dist=False)
+            torch.cuda.synchronize()
+            log(f"profile pass naive scan {s + 1}/{args.steps} done")
+        return 0
     for s in range(args.steps):
         idx, cnt, _ = db.adaptive(Qd, K, P.default_params(h=H, delta=DELTA, seed=12345, sampling=args.sampling),
                                   with_stats=False)
@@ -734,6 +741,7 @@ def main():
                          "reported beside it)")
     ap.add_argument("--metric", choices=("l2", "l1"), default="l2",
                     help="distance of the batch line (l1: the same workload on an l1 DB)")
+    ap.add_argument("--naive", action="store_true", help="with --profile-pass: naive scans instead of adaptive batches")
     ap.add_argument("--profile-pass", action="store_true",
                     help="one copy of known size and one adaptive batch, for rocprofv3 --pmc")
     args = ap.parse_args()

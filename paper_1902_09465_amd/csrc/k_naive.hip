@@ -826,6 +826,8 @@ void launch_exact_ql_u8(const Slot *slots, const int8_t *Q8, const int32_t *qn, 
 
 // ---------------------------------------------------------------- wide u8 scan (squared l2, k <= 64)
 
+__global__ void k_fill_u64(uint64_t *p, uint64_t v) { p[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = v; }
+
 // Block tile 128 queries x 256 points, eight waves of 64 x 64 (wave w:
 // queries 64 (w >> 2) + [0, 64), points 64 (w & 3) + [0, 64); the MFMA
 // output layout as in gemm_u8_tile).  The K loop runs over 64-byte stages of
@@ -946,20 +948,29 @@ __device__ __forceinline__ uint64_t list_absorb(uint64_t L, uint64_t cand) {
 // smallest keys (distance << 32 | index) so far, sorted over the lanes) lives
 // in the registers of its owner wave (queries 16 w .. 16 w + 15).  Epilogue of
 // a tile, once every list holds k keys: each wave compares its 64 x 64
-// distances in the fragment layout with the owners' k-th keys (tauq) and
-// appends the few below to a per (query, point quarter) buffer of SUB keys;
-// the owners absorb them and publish their new k-th keys.  The first tile of
-// a range (lists not yet full), and the queries whose buffer overflowed, take
-// the other way: each wave tile's distances are staged in LDS in turn and the
+// distances in the fragment layout with the queries' bounds and appends the
+// few below to a per (query, point quarter) buffer of SUB keys; the owners
+// absorb them and publish their new k-th keys.  The first tile of a range
+// (lists not yet full), and the queries whose buffer overflowed, take the
+// other way: each wave tile's distances are staged in LDS in turn and the
 // owners absorb them one point row at a time.
+//
+// A query's bound is the smaller of its list's k-th key and gtau[q], the
+// smallest k-th key any range has published (atomicMin).  A key above some
+// range's k-th key has k smaller keys in that range, so it is not among the
+// query's k nearest and may be dropped; the true k nearest all pass (a key
+// equal to a published k-th key is that range's own point).  gtau is read
+// back once per tile, by the same LDS loads as the stages, so a range's list
+// may hold fewer than k keys at the end; the merge takes the k smallest of
+// all lists.
 template <int NST>
 __global__ __launch_bounds__(512) void k_naive_u8_wide(const int8_t *__restrict__ Q8, const int32_t *__restrict__ qn,
                                                        const int8_t *__restrict__ X8, const int32_t *__restrict__ xn,
                                                        int64_t nq, int64_t n, int64_t mp, int k, int64_t nranges,
-                                                       uint64_t *__restrict__ part) {
+                                                       uint64_t *__restrict__ part, uint64_t *__restrict__ gtau) {
   using namespace wide;
   constexpr uint64_t PAD = ~0ull;
-  static_assert(NST >= 3 && NST <= 5, "stages in flight: 1..3");
+  static_assert(NST >= 3 && NST <= 4, "stages in flight: 1..2");
   __shared__ __align__(1024) uint8_t ring[NST * STAGE];
   // the candidate buffers, or (staged way, after they are read) one wave
   // tile's distances
@@ -972,6 +983,7 @@ __global__ __launch_bounds__(512) void k_naive_u8_wide(const int8_t *__restrict_
   // |x'|^2 of the points of the tiles in flight (tile t_lo + i in buffer i % NST:
   // at most NST tiles have a stage loaded and not yet multiplied)
   __shared__ __align__(16) uint32_t xnl[NST][TP];
+  __shared__ __align__(16) uint64_t gtl[NST][TQ];  // gtau of the tile's queries, likewise per tile in flight
   __shared__ uint32_t cntq[TQ];  // byte wp: candidates of point quarter wp this tile (SUB + 1: overflow)
   __shared__ int flags[2];       // per tile parity: bit 0 some list not yet full, bit 1 overflow
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, wq = wave >> 2, wp = wave & 3, g = lane >> 4;
@@ -996,7 +1008,7 @@ __global__ __launch_bounds__(512) void k_naive_u8_wide(const int8_t *__restrict_
     bsrc0 = X8 + std::min<int64_t>(tp + rl, n - 1) * mp + piece;
     bsrc1 = X8 + std::min<int64_t>(tp + 128 + rl, n - 1) * mp + piece;
   };
-  const uint32_t ring_lds = lds_addr(ring), xnl_lds = lds_addr(&xnl[0][0]);
+  const uint32_t ring_lds = lds_addr(ring), xnl_lds = lds_addr(&xnl[0][0]), gtl_lds = lds_addr(&gtl[0][0]);
   int islot = 0, ixn = 0;  // ring buffer of the next load; norm buffer of the next tile
   auto issue = [&]() {
     const uint32_t slot = ring_lds + islot * STAGE + 1024 * wave;
@@ -1008,6 +1020,7 @@ __global__ __launch_bounds__(512) void k_naive_u8_wide(const int8_t *__restrict_
     // (the norm array is padded to whole tiles)
     if (isl == 0) {
       if (wave == 0) lds_load16(xn + (t_lo + it) * TP + 4 * lane, xnl_lds + ixn * TP * 4);
+      if (wave == 1) lds_load16(gtau + q0 + 2 * lane, gtl_lds + ixn * TQ * 8);  // (gtau padded to whole tiles)
       ixn = ixn + 1 == NST ? 0 : ixn + 1;
     }
     islot = islot + 1 == NST ? 0 : islot + 1;
@@ -1086,19 +1099,20 @@ __global__ __launch_bounds__(512) void k_naive_u8_wide(const int8_t *__restrict_
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int v = 0; v < 4; ++v) qv[a][v] = qnl[64 * wq + 16 * a + 4 * g + v];
+    const uint64_t *gt = gtl[(t - t_lo) % NST];
     const int par = (int)((t - t_lo) & 1);
     const int fl0 = flags[par];  // written before the stage barriers of this tile
     uint32_t need = 0;           // owner: queries 16 wave + i that take the staged way this tile
     if (!(fl0 & 1)) {
-      // screen in the fragment layout against the owners' k-th keys: a
-      // 32-bit test of the distance first (d <= the k-th key's distance, a
-      // superset), the exact key test only for a fragment row with a hit
+      // screen in the fragment layout against the queries' bounds: a 32-bit
+      // test of the distance first (d <= the bound's distance, a superset),
+      // the exact key test only for a fragment row with a hit
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int ql = 64 * wq + 16 * a + 4 * g + v;
-          const uint64_t tau = tauq[ql];
+          const uint64_t tau = std::min(tauq[ql], gt[ql]);
           const uint32_t th = (uint32_t)(tau >> 32);
           uint32_t d[4];
           bool hit = false;
@@ -1145,7 +1159,10 @@ __global__ __launch_bounds__(512) void k_naive_u8_wide(const int8_t *__restrict_
         const uint64_t cand = (lane < 4 * SUB && e < (int)((c4 >> (8 * sub)) & 255u)) ? Cb[ql][lane] : PAD;
         L[i] = list_absorb(L[i], cand);
         const uint64_t tau = wave_bcast_u64(L[i], k - 1);
-        if (lane == 0) tauq[ql] = tau;
+        if (lane == 0) {
+          tauq[ql] = tau;
+          if (tau < gt[ql]) atomicMin((unsigned long long *)&gtau[q0 + ql], (unsigned long long)tau);
+        }
       }
       if (any && lane == 0) atomicOr(&flags[par], 2);
       __syncthreads();
@@ -1180,7 +1197,7 @@ __global__ __launch_bounds__(512) void k_naive_u8_wide(const int8_t *__restrict_
             const int ql = 16 * (wave & 3) + i;  // row of the staged tile
             const uint32_t d = Ds[ql * WSTR + lane];
             const uint64_t key = d == 0xFFFFFFFFu ? PAD : (((uint64_t)d << 32) | (uint64_t)pb);
-            const uint64_t tau = wave_bcast_u64(L[i], k - 1);
+            const uint64_t tau = std::min(wave_bcast_u64(L[i], k - 1), gt[16 * wave + i]);
             L[i] = list_absorb(L[i], key < tau ? key : PAD);
           }
         }
@@ -1189,13 +1206,17 @@ __global__ __launch_bounds__(512) void k_naive_u8_wide(const int8_t *__restrict_
       bool full = true;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
+        const int ql = 16 * wave + i;
         const uint64_t tau = wave_bcast_u64(L[i], k - 1);
         if ((need >> i) & 1u) {
-          if (lane == 0) tauq[16 * wave + i] = tau;
-          full = full && tau != PAD;
+          if (lane == 0) {
+            tauq[ql] = tau;
+            if (tau < gt[ql]) atomicMin((unsigned long long *)&gtau[q0 + ql], (unsigned long long)tau);
+          }
+          full = full && std::min(tau, gt[ql]) != PAD;
         }
       }
-      // a query past nq keeps tauq = PAD but never counts against `full`
+      // a query past nq never counts against `full`
       if (!full && lane == 0) atomicOr(&flags[par ^ 1], 1);
     }
     // (the next tile's stage barriers order these LDS writes before its reads)
@@ -1299,7 +1320,10 @@ static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int6
     int64_t nranges = std::max<int64_t>(1, std::min<int64_t>(ntile, (nblk + nqt - 1) / nqt));
     NaiveU8Ws w;
     w.bytes_q = (size_t)nq * db->mp + 256;
-    w.bytes_qn = sizeof(int32_t) * nq + 256;
+    // the query norms, then (256-byte aligned) the published k-th keys, whole
+    // 128-query tiles
+    const size_t qn_bytes = (sizeof(int32_t) * nq + 255) / 256 * 256;
+    w.bytes_qn = qn_bytes + sizeof(uint64_t) * (size_t)nqt * wide::TQ;
     auto part_bytes = [&](int64_t nr) { return sizeof(uint64_t) * (size_t)nq * (size_t)nr * (size_t)k; };
     w.bytes_part = part_bytes(nranges);
     void *ws = ws_fixed;
@@ -1316,21 +1340,23 @@ static int naive_u8(knn_db_s *db, const uint8_t *dq, int64_t nq, int32_t k, int6
     }
     int8_t *Q8 = (int8_t *)ws;
     int32_t *qn = (int32_t *)((uint8_t *)ws + w.bytes_q);
+    uint64_t *gtau = (uint64_t *)((uint8_t *)ws + w.bytes_q + qn_bytes);
     uint64_t *part = (uint64_t *)((uint8_t *)ws + w.bytes_q + w.bytes_qn);
     int tok = prof_begin(PROF_NAIVE_REST, st);
     hipLaunchKernelGGL(k_prep_u8_queries, dim3((unsigned)nq), dim3(256), 0, st, dq, db->m, db->mp, Q8, qn);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)nqt), dim3(wide::TQ), 0, st, gtau, ~0ull);
     prof_end(tok, st, 0.0);
     tok = prof_begin(PROF_NAIVE_GEMM, st);
     const int64_t nblocks = (nranges + kXcds - 1) / kXcds * kXcds * nqt;
-    // LDS ring stages (KNN_NAIVE_STAGES: 3, 4 or 5 (default); NST - 1 in flight)
+    // LDS ring stages (KNN_NAIVE_STAGES: 3 or 4 (default); NST - 2 in flight
+    // during a stage's products)
     const char *ns_env = std::getenv("KNN_NAIVE_STAGES");
-    const int nstages = ns_env ? std::atoi(ns_env) : 5;
+    const int nstages = ns_env ? std::atoi(ns_env) : 4;
 #define KNN_WIDE_LAUNCH(NST_)                                                                                  \
   hipLaunchKernelGGL(k_naive_u8_wide<NST_>, dim3((unsigned)nblocks), dim3(512), 0, st, Q8, qn, db->xs8,       \
-                     db->norm_i, nq, n, db->mp, k, nranges, part)
+                     db->norm_i, nq, n, db->mp, k, nranges, part, gtau)
     if (nstages == 3) KNN_WIDE_LAUNCH(3);
-    else if (nstages == 4) KNN_WIDE_LAUNCH(4);
-    else KNN_WIDE_LAUNCH(5);
+    else KNN_WIDE_LAUNCH(4);
 #undef KNN_WIDE_LAUNCH
     prof_end(tok, st, 2.0 * (double)nq * (double)n * (double)db->m);
     tok = prof_begin(PROF_NAIVE_REST, st);
