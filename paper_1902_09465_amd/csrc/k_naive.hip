@@ -5,8 +5,11 @@
 //       ||x - q||^2 = ||x'||^2 + ||q'||^2 - 2 x'.q',
 //     x'.q' by v_mfma_i32_16x16x64_i8 (exact int32 for m <= 65536), so
 //     distances are exact integers.  The k smallest (distance, index) per
-//     query are kept in LDS while the tile loop streams the points
-//     (fused epilogue, the n-by-nq distance matrix is never stored).
+//     query and point range are kept in registers or LDS while the tile
+//     loop streams the points (fused epilogue, the n-by-nq distance matrix
+//     is never stored); a merge takes the k smallest over the ranges.  For
+//     k <= 64 the wide tile (128 queries x 256 points, stages loaded
+//     straight into LDS) runs; l1 and larger k the 64 x 128 tile.
 // f32: split-BF16 MFMA with an error bound and FP64 rescoring (k_naive_f32.hip).
 // l1 distance (sum_j |x_j - q_j|; no product form, so no matrix cores): the
 //     same tiles and top-k epilogue, with the tile's distances summed by
@@ -846,7 +849,9 @@ constexpr int STAGE = (TQ + TP) * BK;           // 24 KB
 constexpr int DMA = STAGE / 1024 / 8;           // wave instructions per wave and stage (3)
 constexpr int SUB = 8;                          // candidates per (query, point quarter) and tile (< 0x77)
 constexpr int WSTR = 68;                        // row stride (words) of a staged wave tile
-__device__ __forceinline__ int wswz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
+// (measured: no LDS bank conflicts on gfx950 with this permutation; the
+// fragment reads of a 64-byte-row layout without it conflict)
+__device__ __forceinline__ int wswz(int r) { return (r >> 1) & 3; }
 // s_waitcnt with only the vector-memory count bounded (expcnt and lgkmcnt at
 // their maxima)
 template <int N>
