@@ -676,22 +676,30 @@ __global__ __launch_bounds__(256) void k_round_seq_u8(const Slot *__restrict__ s
   const int64_t q0 = (w % nqt) * XQ;
   const int64_t pend = std::min(n, p0 + NBP);
   __shared__ uint8_t take[XQ];
-  __shared__ int any;
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
+  const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
+  // the range norms |x'|^2 and |q'|^2 over [lo, hi) of the tile's points and
+  // queries; they and the slots' flags load together, before the products
+  __shared__ uint32_t xrl[NBP], qrl[XQ];
+  bool tmine = false;
   if (threadIdx.x < XQ) {
     const int64_t s = q0 + threadIdx.x;
-    const bool t = s < ns && slots[s].state == 1 && slots[s].cur == cur && slots[s].implicit != 0;
-    take[threadIdx.x] = t ? 1 : 0;
-    if (t) any = 1;
+    tmine = s < ns && slots[s].state == 1 && slots[s].cur == cur && slots[s].implicit != 0;
+    take[threadIdx.x] = tmine ? 1 : 0;
   }
-  __syncthreads();
-  if (!any) return;  // (block-uniform) no dense slot of this query tile runs this round
+  if (threadIdx.x < NBP) {
+    const int64_t i = p0 + threadIdx.x;
+    xrl[threadIdx.x] =
+        (MET == KNN_METRIC_L2 && i < n) ? (uint32_t)(xn[(int64_t)hi * n + i] - xn[(int64_t)lo * n + i]) : 0u;
+  } else if (threadIdx.x < NBP + XQ) {
+    const int64_t s = q0 + threadIdx.x - NBP;
+    qrl[threadIdx.x - NBP] =
+        (MET == KNN_METRIC_L2 && s < nqp) ? (uint32_t)(qn[(int64_t)hi * nqp + s] - qn[(int64_t)lo * nqp + s]) : 0u;
+  }
+  if (!__syncthreads_or(tmine)) return;  // (block-uniform) no dense slot of this query tile runs this round
   // the K slices covering [t0, t1); words outside it count as zero
   const int64_t kb = t0 / 64 * 64, ke = std::min<int64_t>(kp, (t1 + 63) / 64 * 64);
   v4i acc[XWA][4];
   gemm_u8_tile<MET, PF, BK_EXACT, XWA, true>(QS, (int64_t)nqp, XS, q0, p0, pend, kp, smem, acc, kb, ke, t0, t1);
-  const int lane = lane_id(), wave = threadIdx.x >> 6, wq = wave >> 1, wp = wave & 1;
   uint64_t my_pairs = 0;
   if (exact) {
     // pairs made exact: the undecided sampled ones (flag 0), marked here in
@@ -731,21 +739,16 @@ __global__ __launch_bounds__(256) void k_round_seq_u8(const Slot *__restrict__ s
   // group the pieces' "not sampled" words and old sums of all four point
   // groups are loaded together, then added to and stored.  Sums are taken
   // mod 2^32: every running sum is below 2^32 (m <= 65536).
-  uint32_t xr[4];  // the points' range norms |x'|^2 over [lo, hi)
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int64_t i = p0 + 64 * wp + 16 * b + (lane & 15);
-    xr[b] = (MET == KNN_METRIC_L2 && i < n) ? (uint32_t)(xn[(int64_t)hi * n + i] - xn[(int64_t)lo * n + i]) : 0u;
-  }
 #pragma unroll
   for (int a = 0; a < XWA; ++a) {
     const int ql = 16 * XWA * wq + 16 * a + 4 * (lane >> 4);
     const int64_t s = q0 + ql;
     const uint32_t tk = take[ql] | (take[ql + 1] << 8) | (take[ql + 2] << 16) | (take[ql + 3] << 24);
-    uint32_t qr[4] = {0u, 0u, 0u, 0u};
-    if (MET == KNN_METRIC_L2 && s < nqp && tk != 0) {
+    uint32_t xr[4], qr[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) qr[v] = (uint32_t)(qn[(int64_t)hi * nqp + s + v] - qn[(int64_t)lo * nqp + s + v]);
+    for (int e = 0; e < 4; ++e) {
+      xr[e] = xrl[64 * wp + 16 * e + (lane & 15)];
+      qr[e] = qrl[ql + e];
     }
     uint32_t a4[4];
     uint4 old[4];
