@@ -849,6 +849,24 @@ def main():
         naive_info = {"queries_per_s": NQ / naive_s, "ms_per_batch": naive_s * 1e3,
                       "mfma_int8_tops": naive_tops, "mfma_frac": naive_tops / naive_peak}
 
+    # ---------------- a plain 1 GiB device-to-device copy: the rate this
+    # memory system sustains for streaming reads and writes, beside the peak
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda").fill_(7)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * COPY_BYTES * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    for rl_ in (roofline, head["roofline_sampled_rounds"], rl_exact, head["roofline_select"], head["roofline_decide"]):
+        if rl_.get("bound") == "hbm":
+            rl_["copy_gbs"] = copy_gbs  # bytes read + written per second by a 1 GiB device copy, same run
+            rl_["frac_of_copy"] = rl_["achieved"] / copy_gbs
+
     out = {
         "metric": METRIC_L1 if l1 else METRIC,
         "value": value,
