@@ -1014,17 +1014,23 @@ __global__ __launch_bounds__(NT) void k_seq_coords(uint64_t seed, int32_t norepl
 // is read into LDS by the whole block (16-, 4- or 1-byte loads as its
 // alignment allows) and the coordinates are kept in LDS as 16-bit values
 // (m < 65536; 0xFFFF: none); each thread then gathers sixteen bytes per
-// step.  Without STAGE the bytes come from the row in global memory.
-template <int MET, bool QUERIES, bool STAGE>
-__global__ __launch_bounds__(NT) void k_seq_gather(const uint8_t *__restrict__ X, const Slot *__restrict__ slots,
+// step.  Without STAGE the bytes come from the row in global memory.  BT
+// threads per block: 1024 for staged rows whose LDS leaves room for fewer
+// than four blocks per CU, so that enough loads are in flight, else 256.  Only the columns
+// [c0, c1) (multiples of 16) are written, and only their coordinates are
+// held in LDS; with `need` set and *need == 0 the launch does nothing.
+template <int MET, bool QUERIES, bool STAGE, int BT = NT>
+__global__ __launch_bounds__(BT) void k_seq_gather(const uint8_t *__restrict__ X, const Slot *__restrict__ slots,
                                                    int32_t ns, int64_t rows, int64_t m,
                                                    const uint32_t *__restrict__ js, int64_t kp,
-                                                   int8_t *__restrict__ out) {
+                                                   int8_t *__restrict__ out, int64_t c0, int64_t c1,
+                                                   const int32_t *__restrict__ need) {
+  if (need && *need == 0) return;
   extern __shared__ __align__(16) uint8_t srow[];
   const int64_t mr = (m + 15) / 16 * 16;
   uint16_t *jl = reinterpret_cast<uint16_t *>(srow + (STAGE ? mr : 0));
   if constexpr (STAGE) {
-    for (int64_t t = threadIdx.x; t < kp; t += NT) jl[t] = js[t] == ~0u ? (uint16_t)0xFFFFu : (uint16_t)js[t];
+    for (int64_t t = c0 + threadIdx.x; t < c1; t += BT) jl[t - c0] = js[t] == ~0u ? (uint16_t)0xFFFFu : (uint16_t)js[t];
     __syncthreads();
   }
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
@@ -1038,22 +1044,22 @@ __global__ __launch_bounds__(NT) void k_seq_gather(const uint8_t *__restrict__ X
       if (row) {
         const uintptr_t al = (uintptr_t)row;
         if ((m & 15) == 0 && (al & 15) == 0) {
-          for (int64_t w = threadIdx.x; w < m / 16; w += NT)
+          for (int64_t w = threadIdx.x; w < m / 16; w += BT)
             reinterpret_cast<uint4 *>(srow)[w] = reinterpret_cast<const uint4 *>(row)[w];
         } else if ((m & 3) == 0 && (al & 3) == 0) {
-          for (int64_t w = threadIdx.x; w < m / 4; w += NT)
+          for (int64_t w = threadIdx.x; w < m / 4; w += BT)
             reinterpret_cast<uint32_t *>(srow)[w] = reinterpret_cast<const uint32_t *>(row)[w];
         } else {
-          for (int64_t j = threadIdx.x; j < m; j += NT) srow[j] = row[j];
+          for (int64_t j = threadIdx.x; j < m; j += BT) srow[j] = row[j];
         }
       }
       __syncthreads();
     }
     const uint8_t *from = STAGE ? srow : row;
-    for (int64_t t0 = 16 * (int64_t)threadIdx.x; t0 < kp; t0 += 16 * NT) {
+    for (int64_t t0 = c0 + 16 * (int64_t)threadIdx.x; t0 < c1; t0 += 16 * BT) {
       uint32_t jj[16];
       if constexpr (STAGE) {
-        const uint4 *jp = reinterpret_cast<const uint4 *>(jl + t0);
+        const uint4 *jp = reinterpret_cast<const uint4 *>(jl + (t0 - c0));
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
           const uint4 j = jp[d];
@@ -1184,14 +1190,17 @@ __global__ __launch_bounds__(NT) void k_seq_gather_f32(const float *__restrict__
 __global__ __launch_bounds__(NT) void k_seq_norms(const int8_t *__restrict__ S, int64_t rows, int64_t kp,
                                                   const Sched *__restrict__ sc, int32_t nb, int64_t m,
                                                   const int32_t *__restrict__ full, int32_t *__restrict__ out,
-                                                  int64_t ostride) {
+                                                  int64_t ostride, int32_t b_lo, int32_t b_hi,
+                                                  const int32_t *__restrict__ need) {
+  // boundaries b_lo <= b < min(b_hi, nb), continuing from boundary b_lo - 1
+  if (need && *need == 0) return;
   const int lane = lane_id();
   const int64_t nw = (int64_t)gridDim.x * (NT / kWave);
   for (int64_t r = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
     const uint32_t *row = reinterpret_cast<const uint32_t *>(S + r * kp);
-    int32_t run = 0;
-    if (lane == 0) out[r] = 0;
-    for (int b = 1; b < nb; ++b) {
+    int32_t run = b_lo > 1 ? out[(int64_t)(b_lo - 1) * ostride + r] : 0;
+    if (lane == 0 && b_lo <= 1) out[r] = 0;
+    for (int b = std::max(1, b_lo); b < min(b_hi, nb); ++b) {
       if (b == sc->R + 1) {  // all m coordinates
         if (lane == 0) out[(int64_t)b * ostride + r] = full[r];
         continue;
@@ -3214,41 +3223,89 @@ void launch_seq_prepare_f32(const Slot *slots, int32_t ns, const float *X, int64
   }
 }
 
+// Whether any slot is running (dense: and holds its sets as flags; the exact
+// round's product over the gathered copies runs only for those).
+__global__ __launch_bounds__(1024) void k_seq_any_dense(const Slot *__restrict__ slots, int32_t ns,
+                                                        int32_t *__restrict__ flag, int32_t dense) {
+  bool any = false;
+  for (int s = threadIdx.x; s < ns; s += 1024)
+    any = any || (slots[s].state == 1 && (!dense || slots[s].implicit != 0));
+  const int r = __syncthreads_or(any ? 1 : 0);
+  if (threadIdx.x == 0) *flag = r ? 1 : 0;
+}
+
+// The gather of the point rows (or, QUERIES, the slots' query rows) over
+// columns [c0, c1), or nothing when need is set and reads 0 at run time.
+// Staged rows take m bytes of LDS and the coordinates of a launch two bytes
+// each: a column range whose coordinates do not fit beside the row is split
+// into launches of whole 64-column pieces (each stages the rows again).
+template <bool QUERIES>
+static void launch_seq_gather_cols(const Slot *slots, int32_t ns, const uint8_t *X, int64_t rows, int64_t m,
+                                   int32_t metric, const SeqBufs &q, int8_t *out, int64_t c0, int64_t c1,
+                                   const int32_t *need, hipStream_t st) {
+  const unsigned grid = (unsigned)(QUERIES ? rows : std::min<int64_t>(rows, 8192));
+  const int64_t mr = (m + 15) / 16 * 16;
+  const int64_t room = ((int64_t)kSeqGatherLds - mr) / 2 / 64 * 64;  // coordinates per staged launch
+  const bool stage = m < 65536 && room >= 64;
+  const int64_t step = stage ? room : (c1 - c0);
+  for (int64_t a = c0; a < c1; a += step) {
+    const int64_t b = std::min(c1, a + step);
+    const size_t lds = (size_t)(mr + 2 * (b - a));
+#define KNN_SEQ_GATHER_LAUNCH(MET_)                                                                                \
+  do {                                                                                                             \
+    if (stage && lds > 40 * 1024) {                                                                                \
+      if (lds > 65536)                                                                                             \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_seq_gather<MET_, QUERIES, true, 1024>),         \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSeqGatherLds);                \
+      hipLaunchKernelGGL((k_seq_gather<MET_, QUERIES, true, 1024>), dim3(grid), dim3(1024), lds, st, X, slots, ns, \
+                         rows, m, q.js, q.kp, out, a, b, need);                                                    \
+    } else if (stage) {                                                                                            \
+      hipLaunchKernelGGL((k_seq_gather<MET_, QUERIES, true>), dim3(grid), dim3(NT), lds, st, X, slots, ns, rows,  \
+                         m, q.js, q.kp, out, a, b, need);                                                          \
+    } else {                                                                                                       \
+      hipLaunchKernelGGL((k_seq_gather<MET_, QUERIES, false>), dim3(grid), dim3(NT), 0, st, X, slots, ns, rows, m, \
+                         q.js, q.kp, out, a, b, need);                                                             \
+    }                                                                                                              \
+  } while (0)
+    if (metric == KNN_METRIC_L1)
+      KNN_SEQ_GATHER_LAUNCH(KNN_METRIC_L1);
+    else
+      KNN_SEQ_GATHER_LAUNCH(KNN_METRIC_L2);
+#undef KNN_SEQ_GATHER_LAUNCH
+  }
+}
+
 void launch_seq_prepare(const Slot *slots, const Sched *sc, int32_t ns, int32_t nqp, const uint8_t *X, int64_t n,
                         int64_t m, uint64_t seed, int32_t norepl, int32_t metric, const SeqBufs &q,
-                        const int32_t *xnorm, const int32_t *qnorm, hipStream_t st) {
+                        const int32_t *xnorm, const int32_t *qnorm, int64_t ca, int32_t ba, hipStream_t st) {
   const unsigned cb = (unsigned)std::min<int64_t>((q.kp / 4 + NT - 1) / NT, 1024);
   hipLaunchKernelGGL(k_seq_coords, dim3(cb), dim3(NT), 0, st, seed, norepl, m, q.tlen, q.kp, q.js);
   const unsigned gx = (unsigned)std::min<int64_t>(n, 8192), gq = (unsigned)nqp;
-  // rows staged in LDS, with the coordinates as 16-bit values (m < 65536),
-  // when both fit in the LDS a block may take
-  const int64_t mr = (m + 15) / 16 * 16;
-  const size_t lds = (size_t)(mr + 2 * q.kp);
-  const bool stage = m < 65536 && lds <= kSeqGatherLds;
-#define KNN_SEQ_GATHER(MET_, Q_, ROWS_, OUT_, GRID_)                                                              \
-  do {                                                                                                           \
-    if (stage) {                                                                                                 \
-      if (lds > 65536)                                                                                           \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_seq_gather<MET_, Q_, true>),                 \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSeqGatherLds);              \
-      hipLaunchKernelGGL((k_seq_gather<MET_, Q_, true>), dim3(GRID_), dim3(NT), lds, st, X, slots, ns, ROWS_, m, \
-                         q.js, q.kp, OUT_);                                                                      \
-    } else {                                                                                                     \
-      hipLaunchKernelGGL((k_seq_gather<MET_, Q_, false>), dim3(GRID_), dim3(NT), 0, st, X, slots, ns, ROWS_, m,  \
-                         q.js, q.kp, OUT_);                                                                      \
-    }                                                                                                            \
-  } while (0)
-  if (metric == KNN_METRIC_L1) {
-    KNN_SEQ_GATHER(KNN_METRIC_L1, false, n, q.xs, gx);
-    KNN_SEQ_GATHER(KNN_METRIC_L1, true, (int64_t)nqp, q.qs, gq);
-  } else {
-    KNN_SEQ_GATHER(KNN_METRIC_L2, false, n, q.xs, gx);
-    KNN_SEQ_GATHER(KNN_METRIC_L2, true, (int64_t)nqp, q.qs, gq);
-    hipLaunchKernelGGL(k_seq_norms, dim3(gx), dim3(NT), 0, st, q.xs, n, q.kp, sc, q.nb, m, xnorm, q.xn, n);
+  // the queries' rows at every column (they are few), with all their norms;
+  // the points' rows at the first rounds' columns [0, ca), with the norms at
+  // the boundaries below ba (the later columns: launch_seq_gather_more)
+  launch_seq_gather_cols<false>(slots, ns, X, n, m, metric, q, q.xs, 0, ca, nullptr, st);
+  launch_seq_gather_cols<true>(slots, ns, X, (int64_t)nqp, m, metric, q, q.qs, 0, q.kp, nullptr, st);
+  if (metric == KNN_METRIC_L2) {
+    hipLaunchKernelGGL(k_seq_norms, dim3(gx), dim3(NT), 0, st, q.xs, n, q.kp, sc, q.nb, m, xnorm, q.xn, n, 0, ba,
+                       (const int32_t *)nullptr);
     hipLaunchKernelGGL(k_seq_norms, dim3(gq), dim3(NT), 0, st, q.qs, (int64_t)nqp, q.kp, sc, q.nb, m, qnorm, q.qn,
-                       (int64_t)nqp);
+                       (int64_t)nqp, 0, q.nb, (const int32_t *)nullptr);
   }
-#undef KNN_SEQ_GATHER
+}
+
+void launch_seq_gather_more(const Slot *slots, int32_t ns, const Sched *sc, const uint8_t *X, int64_t n, int64_t m,
+                            int32_t metric, const SeqBufs &q, int64_t c0, int64_t c1, int32_t b0, int32_t b1,
+                            int32_t dense, const int32_t *xnorm, hipStream_t st) {
+  if (c0 >= c1 && b0 >= b1) return;
+  int32_t *flag = q.flag + (dense ? 1 : 0);
+  hipLaunchKernelGGL(k_seq_any_dense, dim3(1), dim3(1024), 0, st, slots, ns, flag, dense);
+  if (c0 < c1) launch_seq_gather_cols<false>(slots, ns, X, n, m, metric, q, q.xs, c0, c1, flag, st);
+  if (metric == KNN_METRIC_L2 && b0 < b1) {
+    const unsigned gx = (unsigned)std::min<int64_t>(n, 8192);
+    hipLaunchKernelGGL(k_seq_norms, dim3(gx), dim3(NT), 0, st, q.xs, n, q.kp, sc, q.nb, m, xnorm, q.xn, n, b0, b1,
+                       (const int32_t *)flag);
+  }
 }
 
 // Point blocks of a query-lane sampling launch (each walks a contiguous

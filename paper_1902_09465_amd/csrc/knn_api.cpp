@@ -187,6 +187,7 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
   const size_t o_qs = take(seq ? (size_t)nqp * kp : 0);
   const size_t o_xsn = take(seq ? (size_t)seq_nb * n * 4 : 0);
   const size_t o_qsn = take(seq ? (size_t)seq_nb * nqp * 4 : 0);
+  const size_t o_sflag = take(seq ? 256 : 0);
   const size_t o_xf = take(seqf ? (size_t)n * kp * 4 : 0);
   const size_t o_qf = take(seqf ? (size_t)ns * kp * 4 : 0);
   void *base = nullptr;
@@ -235,6 +236,7 @@ int engine_create(Engine &E, knn_db_s *db, int64_t ns, int32_t kmax, int32_t cma
     E.seq.qs = (int8_t *)at(o_qs);
     E.seq.xn = (int32_t *)at(o_xsn);
     E.seq.qn = (int32_t *)at(o_qsn);
+    E.seq.flag = (int32_t *)at(o_sflag);
     E.seq.kp = kp;
     E.seq.tlen = seq_tlen;
     E.seq.nb = seq_nb;
@@ -413,10 +415,31 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
     prof_end(tk, st, 0.0);
     prof_add_host(1, (uint64_t)E.seq.tlen);
   }
+  // The points' rows are gathered in up to three parts: the columns of the
+  // first six rounds [0, seq_ca) up front; the later sampled rounds' columns
+  // [seq_ca, seq_c1) before round seq_ra + 1, if a slot is still running;
+  // the exact round's [seq_c1, kp) before it, if a slot is still dense.
+  // (A batch whose slots finish early never reads the later columns; each
+  // part reads the point rows once more.)  Their norms follow each part.
+  int64_t seq_ca = 0, seq_c1 = 0;
+  int32_t seq_ra = -1, seq_ba = 1;
+  const int seq_R = P.sched[0].R;
+  if (seq && seq_R > 0) {
+    seq_ra = std::min(seq_R - 1, 5);
+    seq_ca = std::min<int64_t>(E.seq.kp, ((int64_t)P.sched[0].T[seq_ra] + 63) / 64 * 64);
+    seq_c1 = std::min<int64_t>(E.seq.kp, ((int64_t)P.sched[0].T[seq_R - 1] + 63) / 64 * 64);
+    seq_ba = seq_ra + 2;  // boundaries b <= seq_ra + 1 lie below seq_ca
+    // deferring the exact round's columns costs one more read of the point
+    // rows when they are needed: only worth it when they are half of m or more
+    if (2 * (E.seq.kp - seq_c1) < m) {
+      if (seq_ca == seq_c1) seq_ca = E.seq.kp;
+      seq_c1 = E.seq.kp;
+    }
+  }
   if (seq) {
     const int tk = prof_begin(PROF_QL_AUX, st);
     launch_seq_prepare(E.slots, E.sched, (int32_t)E.ns, E.nqp, db->X, n, m, P.qd[0].seed, P.qd[0].norepl,
-                       db->metric, E.seq, db->norm_i, E.q8n, st);
+                       db->metric, E.seq, db->norm_i, E.q8n, seq_ca, seq_ba, st);
     prof_end(tk, st, 0.0);
     prof_add_host(1, (uint64_t)E.seq.tlen);  // its distinct draws: one sequence for the whole batch
   }
@@ -445,6 +468,18 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
       }
       qr.cur = t;
       qr.impl = t == 0;
+    }
+    if (seq && ql && !qr.exact && t == seq_ra + 1) {
+      const int tk = prof_begin(PROF_QL_AUX, st);
+      launch_seq_gather_more(E.slots, (int32_t)E.ns, E.sched, db->X, n, m, db->metric, E.seq, seq_ca, seq_c1, seq_ba,
+                             seq_R + 1, 0, db->norm_i, st);
+      prof_end(tk, st, 0.0);
+    }
+    if (seq && ql && qr.exact && qr.norepl) {
+      const int tk = prof_begin(PROF_QL_AUX, st);
+      launch_seq_gather_more(E.slots, (int32_t)E.ns, E.sched, db->X, n, m, db->metric, E.seq, seq_c1, E.seq.kp,
+                             std::max(seq_ba, seq_R + 1), seq_R + 2, 1, db->norm_i, st);
+      prof_end(tk, st, 0.0);
     }
     engine_step(E, P.any_cexact, (lockstep && t == P.rmax) ? 1 : 0, stage, ql ? &qr : nullptr);
   }

@@ -110,9 +110,18 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
                  int stage_rows = 0, const QlRound *ql = nullptr, const uint8_t *qt = nullptr, int32_t nqp = 0,
                  uint32_t *qd_buf = nullptr, const int8_t *q8 = nullptr, const int32_t *q8n = nullptr,
                  const SeqBufs *seq = nullptr);
+// The shared sequence's coordinates, the queries' rows at them with their
+// prefix norms at every round boundary, and the points' rows at columns
+// [0, ca) (a multiple of 64, or kp) with their norms at boundaries b < ba.
 void launch_seq_prepare(const Slot *slots, const Sched *sc, int32_t ns, int32_t nqp, const uint8_t *X, int64_t n,
                         int64_t m, uint64_t seed, int32_t norepl, int32_t metric, const SeqBufs &q,
-                        const int32_t *xnorm, const int32_t *qnorm, hipStream_t st);
+                        const int32_t *xnorm, const int32_t *qnorm, int64_t ca, int32_t ba, hipStream_t st);
+// The points' rows at columns [c0, c1) and their norms at boundaries
+// b0 <= b < b1, when (checked on the device) some slot is running, or with
+// `dense` some running slot is dense.
+void launch_seq_gather_more(const Slot *slots, int32_t ns, const Sched *sc, const uint8_t *X, int64_t n, int64_t m,
+                            int32_t metric, const SeqBufs &q, int64_t c0, int64_t c1, int32_t b0, int32_t b1,
+                            int32_t dense, const int32_t *xnorm, hipStream_t st);
 void launch_seq_prepare_f32(const Slot *slots, int32_t ns, const float *X, int64_t n, int64_t m, uint64_t seed,
                             int32_t norepl, const SeqBufs &q, hipStream_t st);
 void launch_round_seq_u8(const Slot *slots, const SeqBufs &q, int32_t lo, int32_t hi, int64_t t0, int64_t t1,

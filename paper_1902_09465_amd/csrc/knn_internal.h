@@ -100,6 +100,7 @@ struct SeqBufs {
   int32_t *qn = nullptr;   // [nb][nqp] the same for the qs rows
   float *xf = nullptr;     // fp32 DBs: [n][kp] points at the sequence's coordinates (no xs, qs, norms)
   float *qf = nullptr;     // fp32 DBs: [nslots][kp] the slots' queries, likewise
+  int32_t *flag = nullptr;  // device word: whether the exact round's columns are needed (set per batch)
   int64_t kp = 0;          // row length, a multiple of 64
   int32_t tlen = 0;        // samples held: the last sampled target, or m without replacement
   int32_t nb = 0;          // boundaries T'_0 = 0, T'_b = T[b-1] (b <= R), and T'_{R+1} = m
