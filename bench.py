@@ -435,9 +435,11 @@ def easy_bench(args):
     """Easy-gap batches, where adaptive is meant to win: the easy half of the
     uneven workload on its own (n = 100,000 corners of {0,255}^m, 1,024
     queries each owning k = 10 planted points at a small gap, the rest far;
-    h = k, delta = 0.01, the footnote width, one seed) at m = 1024, 4096 and
-    16384.  Adaptive in sampling modes 0 and 3 against the naive int8-MFMA
-    scan of the same queries; containment against that scan."""
+    h = k, delta = 0.01, the footnote width, one seed) at m = 1024, 4096,
+    16384, 32768 and 65535 (the largest m of the shared-sequence kernels).  Adaptive
+    in sampling modes 0 and 3 (first round B0 = 64), and in mode 3 with the
+    larger first rounds of --easy-b0, against the naive int8-MFMA scan of the
+    same queries; containment against that scan."""
     import torch
     from knn_inputs import easy_corners
 
@@ -460,8 +462,11 @@ def easy_bench(args):
         torch.cuda.synchronize()
         nv_s = (time.perf_counter() - t0) / args.steps
         row = {"m": m, "naive_ms": nv_s * 1e3, "naive_queries_per_s": nq / nv_s}
-        for mode in (0, 3):
-            p = P.default_params(h=k, delta=0.01, seed=6001, sampling=mode)
+        # sampling 0 and 3 with the default first round (B0 = 64); sampling 3
+        # again with each larger first round of --easy-b0
+        runs = [(0, 64), (3, 64)] + [(3, b) for b in args.easy_b0 if b != 64]
+        for mode, b0 in runs:
+            p = P.default_params(h=k, delta=0.01, seed=6001, sampling=mode, b0=b0)
             for _ in range(args.warmup):
                 db.adaptive(Q_t, k, p, with_stats=False)
             torch.cuda.synchronize()
@@ -473,9 +478,10 @@ def easy_bench(args):
             ok = int(contained(idx, cnt, X_t, Q_t, nidx, ndist, k).sum().item())
             _, _, st = db.adaptive(Q_t, k, p)
             frac = float(st["coord_evals"].astype(np.float64).mean() / (n * m))
-            row[f"sampling{mode}"] = {"ms": ad_s * 1e3, "queries_per_s": ok / ad_s, "contained": f"{ok}/{nq}",
-                                      "evals_fraction_of_naive": frac, "adaptive_vs_naive": nv_s / ad_s}
-            log(f"m = {m} sampling {mode}: adaptive {ad_s * 1e3:.2f} ms ({ok}/{nq} contained, "
+            key = f"sampling{mode}" + ("" if b0 == 64 else f"_b0_{b0}")
+            row[key] = {"ms": ad_s * 1e3, "queries_per_s": ok / ad_s, "contained": f"{ok}/{nq}", "b0": b0,
+                        "evals_fraction_of_naive": frac, "adaptive_vs_naive": nv_s / ad_s}
+            log(f"m = {m} sampling {mode} B0 = {b0}: adaptive {ad_s * 1e3:.2f} ms ({ok}/{nq} contained, "
                 f"{frac:.3f} of the naive evaluations), naive {nv_s * 1e3:.2f} ms")
         rows.append(row)
         db.close()
@@ -484,7 +490,8 @@ def easy_bench(args):
     out = {"metric": "easy-gap batches: queries/s adaptive vs naive MFMA (true k-NN contained)",
            "unit": "queries/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u8", "data": "synthetic",
            "config": {"workload": f"easy corners: n = {n} corners of (0,255)^m, {nq} queries with k = {k} planted "
-                                  "points each (inward noise 0..8), h = k, delta = 0.01, footnote width, one seed"},
+                                  "points each (inward noise 0..8), h = k, delta = 0.01, footnote width, one seed, "
+                                  "first round B0 = 64 (and the --easy-b0 values in sampling 3), growth 2"},
            "rows": rows}
     print(json.dumps(out), flush=True)
     return 0
@@ -734,7 +741,9 @@ def main():
     ap.add_argument("--uneven", action="store_true", help="uneven workload instead of the batch line")
     ap.add_argument("--float", action="store_true", help="float workload instead of the batch line")
     ap.add_argument("--easy", action="store_true", help="easy-gap batches at several m instead of the batch line")
-    ap.add_argument("--easy-m", type=int, nargs="+", default=[1024, 4096, 16384])
+    ap.add_argument("--easy-m", type=int, nargs="+", default=[1024, 4096, 16384, 32768, 65535])
+    ap.add_argument("--easy-b0", type=int, nargs="+", default=[1024],
+                    help="first-round sample counts tried in sampling 3 besides the default 64")
     ap.add_argument("--float-queries", type=int, default=1024)
     ap.add_argument("--sampling", type=int, choices=(0, 1, 2, 3), default=3,
                     help="sampling mode of the headline batch (knn_params.sampling; the other modes are "

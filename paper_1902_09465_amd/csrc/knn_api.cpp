@@ -416,7 +416,8 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
     prof_add_host(1, (uint64_t)E.seq.tlen);
   }
   // The points' rows are gathered in up to three parts: the columns of the
-  // first six rounds [0, seq_ca) up front; the later sampled rounds' columns
+  // first rounds [0, seq_ca) up front (rounds with T <= max(2048, 2 T_0));
+  // the later sampled rounds' columns
   // [seq_ca, seq_c1) before round seq_ra + 1, if a slot is still running;
   // the exact round's [seq_c1, kp) before it, if a slot is still dense.
   // (A batch whose slots finish early never reads the later columns; each
@@ -425,7 +426,9 @@ static void launch_lockstep(Engine &E, const Prepared &P, int64_t nq, const Knob
   int32_t seq_ra = -1, seq_ba = 1;
   const int seq_R = P.sched[0].R;
   if (seq && seq_R > 0) {
-    seq_ra = std::min(seq_R - 1, 5);
+    const int64_t tcap = std::max<int64_t>(2048, 2 * (int64_t)P.sched[0].T[0]);
+    seq_ra = 0;
+    while (seq_ra + 1 < seq_R && (int64_t)P.sched[0].T[seq_ra + 1] <= tcap) ++seq_ra;
     seq_ca = std::min<int64_t>(E.seq.kp, ((int64_t)P.sched[0].T[seq_ra] + 63) / 64 * 64);
     seq_c1 = std::min<int64_t>(E.seq.kp, ((int64_t)P.sched[0].T[seq_R - 1] + 63) / 64 * 64);
     seq_ba = seq_ra + 2;  // boundaries b <= seq_ra + 1 lie below seq_ca
