@@ -663,6 +663,41 @@ def test_batch_larger_than_slots_in_chunks(P, orc, monkeypatch, dtype, sampling)
         assert int(base[2][q]["coord_evals"]) == rst["coord_evals"], q
 
 
+@pytest.mark.parametrize("data", ["hard", "easy"])
+def test_shared_sequence_gather_in_parts(P, orc, data):
+    """Sampling 3 at m = 8192 (T = 64 ... 4096, then the exact round): the
+    points' rows at the sequence's coordinates are gathered in three parts,
+    the first rounds' columns (T <= 2048) up front, T = 4096's before its
+    round if a slot still runs, the exact round's before it if a slot is
+    still dense.  On uniform rows every point of every query reaches the
+    exact round, so every part is gathered and read; on easy corners every
+    query settles by T = 1024 and the later parts are skipped on the device.
+    Every query's set and statistics equal the oracle's."""
+    from knn_inputs import easy_corners
+    n, m, nq, k = 1500, 8192, 70, 5
+    if data == "hard":
+        g = rng(4242)
+        X = g.integers(0, 256, (n, m), dtype=np.uint8)
+        Q = g.integers(0, 256, (nq, m), dtype=np.uint8)
+    else:
+        X, Q = easy_corners(4243, n, m, nq, k)
+    db = P.KnnDB(dev(X))
+    kw = dict(h=k, delta=0.01, seed=21, sampling=3)
+    idx, cnt, st = db.adaptive(dev(Q), k, P.default_params(**kw))
+    idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
+    refs = oracle_many(orc, X, Q, [k] * nq, kw, range(nq))
+    for q, (ref, rst) in enumerate(refs):
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert (int(st[q]["coord_evals"]), int(st[q]["rounds"]), int(st[q]["count"]), int(st[q]["exact_points"])) == \
+            (rst["coord_evals"], rst["rounds"], rst["count"], rst["exact_points"]), q
+    exact = [rst["exact_points"] for _, rst in refs]
+    if data == "hard":
+        assert all(e == n for e in exact)  # the exact round's columns were gathered and used
+    else:
+        assert all(e == 0 for e in exact) and max(rst["rounds"] for _, rst in refs) <= 6
+    db.close()
+
+
 def test_batched_int_config_sampled(P, orc):
     """The batched-integer workload at full size (n = 100,000 x m = 3072 uint8
     32-centre mixture, 1,024 queries, k = h = 10, delta = 0.01) in the launch
