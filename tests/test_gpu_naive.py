@@ -63,7 +63,8 @@ def test_naive_u8_batched_config_sampled(P, orc):
 
 @pytest.mark.parametrize("n,m,nq,k,blocks", [(5000, 256, 200, 10, 2), (5000, 128, 130, 64, 2), (9000, 64, 300, 1, 3),
                                               (3000, 320, 129, 33, 1), (2600, 192, 1, 5, 1), (70, 64, 3, 10, 256),
-                                              (1000, 100, 5, 64, 1)])
+                                              (1000, 100, 5, 64, 1), (1000, 65536, 5, 7, 256),
+                                              (3000, 64, 1100, 10, 256)])
 def test_naive_u8_wide_tile_ranges(P, orc, monkeypatch, n, m, nq, k, blocks):
     """The scan's 128-query x 256-point tile (k <= 64) with few point ranges,
     so that a block walks many tiles: a range's first tile fills the lists
