@@ -1011,8 +1011,9 @@ __global__ __launch_bounds__(NT) void k_seq_coords(uint64_t seed, int32_t norepl
 // for squared l2, raw bytes for l1; zero where js[t] is none): the points
 // (rows = n), or the running slots' queries (QUERIES, rows = nqp; idle
 // slots give zero rows).  One row per block at a time: with STAGE the row
-// is read into LDS by the whole block (16-, 4- or 1-byte loads as its
-// alignment allows) and the coordinates are kept in LDS as 16-bit values
+// is read into LDS by the whole block (a point row as the aligned 16-byte
+// words that cover it, at any m; a query row with 16-, 4- or 1-byte loads
+// as its alignment allows) and the coordinates are kept in LDS as 16-bit values
 // (m < 65536; 0xFFFF: none); each thread then gathers sixteen bytes per
 // step.  Without STAGE the bytes come from the row in global memory.  BT
 // threads per block: 1024 for staged rows whose LDS leaves room for fewer
@@ -1028,7 +1029,7 @@ __global__ __launch_bounds__(BT) void k_seq_gather(const uint8_t *__restrict__ X
   if (need && *need == 0) return;
   extern __shared__ __align__(16) uint8_t srow[];
   const int64_t mr = (m + 15) / 16 * 16;
-  uint16_t *jl = reinterpret_cast<uint16_t *>(srow + (STAGE ? mr : 0));
+  uint16_t *jl = reinterpret_cast<uint16_t *>(srow + (STAGE ? mr + 16 : 0));
   if constexpr (STAGE) {
     for (int64_t t = c0 + threadIdx.x; t < c1; t += BT) jl[t - c0] = js[t] == ~0u ? (uint16_t)0xFFFFu : (uint16_t)js[t];
     __syncthreads();
@@ -1040,8 +1041,26 @@ __global__ __launch_bounds__(BT) void k_seq_gather(const uint8_t *__restrict__ X
     } else {
       row = X + r * m;
     }
+    int64_t shift = 0;  // the row's offset in its staged copy (block-uniform)
     if constexpr (STAGE) {
-      if (row) {
+      if (!QUERIES) {
+        // the aligned 16-byte words that cover the row, read whole where they
+        // lie inside the matrix (at either end of an unaligned row they hold
+        // bytes of the next or previous row, which nothing reads); bytes of
+        // a word that reaches past the matrix are read one by one
+        shift = (int64_t)((uintptr_t)row & 15);
+        const uint8_t *base = row - shift, *end = X + rows * m;
+        const int64_t nw = (shift + m + 15) / 16;
+        for (int64_t w = threadIdx.x; w < nw; w += BT) {
+          const uint8_t *p = base + 16 * w;
+          if (p >= X && p + 16 <= end) {
+            reinterpret_cast<uint4 *>(srow)[w] = *reinterpret_cast<const uint4 *>(p);
+          } else {
+            for (int e = 0; e < 16; ++e)
+              if (p + e >= row && p + e < row + m) srow[16 * w + e] = p[e];
+          }
+        }
+      } else if (row) {
         const uintptr_t al = (uintptr_t)row;
         if ((m & 15) == 0 && (al & 15) == 0) {
           for (int64_t w = threadIdx.x; w < m / 16; w += BT)
@@ -1055,7 +1074,7 @@ __global__ __launch_bounds__(BT) void k_seq_gather(const uint8_t *__restrict__ X
       }
       __syncthreads();
     }
-    const uint8_t *from = STAGE ? srow : row;
+    const uint8_t *from = STAGE ? srow + shift : row;
     for (int64_t t0 = c0 + 16 * (int64_t)threadIdx.x; t0 < c1; t0 += 16 * BT) {
       uint32_t jj[16];
       if constexpr (STAGE) {
@@ -3236,7 +3255,7 @@ __global__ __launch_bounds__(1024) void k_seq_any_dense(const Slot *__restrict__
 
 // The gather of the point rows (or, QUERIES, the slots' query rows) over
 // columns [c0, c1), or nothing when need is set and reads 0 at run time.
-// Staged rows take m bytes of LDS and the coordinates of a launch two bytes
+// Staged rows take m + 16 bytes of LDS and the coordinates of a launch two bytes
 // each: a column range whose coordinates do not fit beside the row is split
 // into launches of whole 64-column pieces (each stages the rows again).
 template <bool QUERIES>
@@ -3245,12 +3264,12 @@ static void launch_seq_gather_cols(const Slot *slots, int32_t ns, const uint8_t 
                                    const int32_t *need, hipStream_t st) {
   const unsigned grid = (unsigned)(QUERIES ? rows : std::min<int64_t>(rows, 8192));
   const int64_t mr = (m + 15) / 16 * 16;
-  const int64_t room = ((int64_t)kSeqGatherLds - mr) / 2 / 64 * 64;  // coordinates per staged launch
+  const int64_t room = ((int64_t)kSeqGatherLds - mr - 16) / 2 / 64 * 64;  // coordinates per staged launch
   const bool stage = m < 65536 && room >= 64;
   const int64_t step = stage ? room : (c1 - c0);
   for (int64_t a = c0; a < c1; a += step) {
     const int64_t b = std::min(c1, a + step);
-    const size_t lds = (size_t)(mr + 2 * (b - a));
+    const size_t lds = (size_t)(mr + 16 + 2 * (b - a));
 #define KNN_SEQ_GATHER_LAUNCH(MET_)                                                                                \
   do {                                                                                                             \
     if (stage && lds > 40 * 1024) {                                                                                \

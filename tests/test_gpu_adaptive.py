@@ -698,6 +698,42 @@ def test_shared_sequence_gather_in_parts(P, orc, data):
     db.close()
 
 
+@pytest.mark.parametrize("m,sampling,data", [(1001, 3, "gmm"), (1001, 2, "gmm"), (8191, 3, "hard")])
+def test_shared_sequence_unaligned_rows(P, orc, m, sampling, data):
+    """A borrowed point matrix that starts 3 bytes past a 16-byte boundary,
+    with odd m: the point rows start at every offset modulo 16, the first
+    row's leading word and the last row's trailing word reach outside the
+    matrix (the bytes around it are 0xEE, so a byte read from there would
+    change the sums).  The staged gather copies each row as the aligned words
+    that cover it.  At m = 8191 on uniform rows every query reaches the exact
+    round, so all three parts of the gather run.  Every query's set and
+    statistics equal the oracle's."""
+    n, nq, k = (3001, 40, 5) if m == 1001 else (1500, 40, 5)
+    if data == "hard":
+        g = rng(4244)
+        X = g.integers(0, 256, (n, m), dtype=np.uint8)
+        Q = g.integers(0, 256, (nq, m), dtype=np.uint8)
+    else:
+        X, Q = gmm_u8(4245, n=n, m=m, n_centres=6, sigma=25.0, nq=nq)
+    off = 3
+    buf = torch.full((X.size + off + 29,), 0xEE, dtype=torch.uint8, device="cuda")
+    buf[off:off + X.size] = dev(X.reshape(-1))
+    Xd = buf[off:off + X.size].view(n, m)
+    assert Xd.data_ptr() % 16 == off
+    db = P.KnnDB(Xd)
+    kw = dict(h=k, delta=0.01, seed=23, sampling=sampling)
+    idx, cnt, st = db.adaptive(dev(Q), k, P.default_params(**kw))
+    idx, cnt = idx.cpu().numpy(), cnt.cpu().numpy()
+    refs = oracle_many(orc, X, Q, [k] * nq, kw, range(nq))
+    for q, (ref, rst) in enumerate(refs):
+        assert idx[q, :cnt[q]].tolist() == ref.tolist(), q
+        assert (int(st[q]["coord_evals"]), int(st[q]["rounds"]), int(st[q]["count"]), int(st[q]["exact_points"])) == \
+            (rst["coord_evals"], rst["rounds"], rst["count"], rst["exact_points"]), q
+    if data == "hard":
+        assert all(rst["exact_points"] == n for _, rst in refs)
+    db.close()
+
+
 def test_batched_int_config_sampled(P, orc):
     """The batched-integer workload at full size (n = 100,000 x m = 3072 uint8
     32-centre mixture, 1,024 queries, k = h = 10, delta = 0.01) in the launch
