@@ -1534,13 +1534,18 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
 }
 
 // Tiles of the selection over point-major sums (k_select_pm): FS_SL slots x
-// FS_PT points, one wave per slot row at a time, sixteen points per lane;
+// FS_PT points, one wave per slot (FS_NT threads), sixteen points per lane;
 // the kept set P is exactly the points without a discard flag.  Needs
 // k + 1 <= 64 (the wave selection below).  A tile reads FS_SL * 4 bytes of
-// each point's 128-byte line of D; wider tiles cut the L2-to-L1 traffic but
-// hold FS_SL x 4 KB of LDS per block, and measured slower (selection per
-// step: 4 slots 1.70 ms, 8 slots 1.85 ms, 16 slots 2.46 ms).
-constexpr int FS_SL = 4, FS_PT = 1024;
+// each point's line of D: the staging is bound by the number of lines a
+// block touches (4 slots: 173 us per launch for the staging alone on the
+// batched-integer workload, 8 slots: 126 us, 16 slots: 117 us), the
+// selections by the vector ALU (111 us without the loads), and the two
+// overlap only across blocks resident on a CU together.  Per launch with
+// both: 4 slots 197 us, 8 slots 174 us, 16 slots 204 us (two 1024-thread
+// blocks per CU, which leaves the loads of one block little to overlap).
+constexpr int FS_SL = 8, FS_PT = 1024;
+constexpr int FS_NT = FS_SL * kWave;
 constexpr int FS_E = FS_PT / kWave;
 
 // The K (<= 64) smallest of the wave's E keys per lane (PAD = none), written
@@ -1887,24 +1892,24 @@ __device__ __forceinline__ uint32_t *fs_mixed(const Bufs &B, int sl, int64_t n) 
 constexpr int FS_TS = FS_PT + 4;  // LDS row stride in words: rows stay 16-byte aligned
 
 // The sums of a tile of FS_SL slots x FS_PT points, transposed into LDS rows:
-// FS_SL / 4 16-byte loads per point (nqp is a multiple of 16), four points'
-// worth in flight at once per thread (clamped rows, zeroed after).
+// FS_SL / 4 16-byte loads per point (nqp is a multiple of 16), up to four
+// points' worth in flight at once per thread (clamped rows, zeroed after).
 __device__ __forceinline__ void fs_stage_sums(uint32_t (*t)[FS_TS], const uint32_t *__restrict__ D, int32_t nqp,
                                               int64_t i0, int s0, int64_t n) {
   static_assert(FS_SL % 4 == 0 && FS_SL <= 16, "16-byte pieces of one line per point");
-  constexpr int PER = FS_PT / NT, Q = FS_SL / 4, U = 4;
+  constexpr int PER = FS_PT / FS_NT, Q = FS_SL / 4, U = PER < 4 ? PER : 4;
 #pragma unroll
   for (int u0 = 0; u0 < PER; u0 += U) {
     uint4 v[U][Q];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t i = min(i0 + threadIdx.x + (u0 + u) * NT, n - 1);
+      const int64_t i = min(i0 + threadIdx.x + (u0 + u) * FS_NT, n - 1);
 #pragma unroll
       for (int q = 0; q < Q; ++q) v[u][q] = *reinterpret_cast<const uint4 *>(D + i * nqp + s0 + 4 * q);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int pt = threadIdx.x + (u0 + u) * NT;
+      const int pt = threadIdx.x + (u0 + u) * FS_NT;
       const bool in = i0 + pt < n;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
@@ -1925,10 +1930,10 @@ __device__ __forceinline__ void fs_stage_sums(uint32_t (*t)[FS_TS], const uint32
 // WIDE: some slot's k + 1 exceeds 64 (lists of up to 128 keys; the K <= 64
 // instance stays within 64 VGPRs).
 template <bool WIDE>
-__global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
+__global__ __launch_bounds__(FS_NT) void k_select_pm(const Slot *__restrict__ slots, const uint32_t *__restrict__ D,
                                                   int32_t nqp, Bufs B, Geometry G, int32_t cur, int32_t init) {
   __shared__ __align__(16) uint32_t t[FS_SL][FS_TS];
-  __shared__ uint64_t cbuf[NT / kWave][kWave];
+  __shared__ uint64_t cbuf[FS_NT / kWave][kWave];
   const int64_t n = G.n, m = G.m;
   const int ns = G.nslots;
   const int64_t ngroups = (nqp + FS_SL - 1) / FS_SL;
@@ -1938,7 +1943,7 @@ __global__ __launch_bounds__(NT) void k_select_pm(const Slot *__restrict__ slots
   const int64_t tile = w / ngroups;
   const int64_t i0 = tile * FS_PT;
   const int s0 = (int)(w % ngroups) * FS_SL;
-  static_assert(FS_SL == NT / kWave, "one wave per slot of the tile");
+  static_assert(FS_SL == FS_NT / kWave, "one wave per slot of the tile");
   const int lane = lane_id(), wave = threadIdx.x / kWave;
   // this wave's slot, when it runs this round in dense form (wave-uniform);
   // nothing to do unless one of the tile's slots does
@@ -3403,10 +3408,10 @@ void launch_step(Slot *slots, const QDesc *qd, const Sched *sched, Ctl *ctl, con
     tk = prof_begin(PROF_SELECT, st);
     const int64_t nsel = ((G.n + FS_PT - 1) / FS_PT) * ((nqp + FS_SL - 1) / FS_SL);
     if (G.kmax + 1 > kWave)
-      hipLaunchKernelGGL(k_select_pm<true>, dim3((unsigned)xcd_grid(nsel)), dim3(NT), 0, st, slots, qd_buf, nqp, B, G,
+      hipLaunchKernelGGL(k_select_pm<true>, dim3((unsigned)xcd_grid(nsel)), dim3(FS_NT), 0, st, slots, qd_buf, nqp, B, G,
                          ql->cur, (ql->cur == 0 && !ql->exact) ? 1 : 0);
     else
-      hipLaunchKernelGGL(k_select_pm<false>, dim3((unsigned)xcd_grid(nsel)), dim3(NT), 0, st, slots, qd_buf, nqp, B, G,
+      hipLaunchKernelGGL(k_select_pm<false>, dim3((unsigned)xcd_grid(nsel)), dim3(FS_NT), 0, st, slots, qd_buf, nqp, B, G,
                          ql->cur, (ql->cur == 0 && !ql->exact) ? 1 : 0);
     hipLaunchKernelGGL(k_select_pm_mixed, dim3(ns), dim3(kWave), 0, st, slots, qd_buf, nqp, B, G, ql->cur,
                        (ql->cur == 0 && !ql->exact) ? 1 : 0);
