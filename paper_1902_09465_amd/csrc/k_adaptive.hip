@@ -2127,21 +2127,25 @@ __global__ __launch_bounds__(kWave) void k_select_pm_mixed(const Slot *__restric
 }
 
 // Decide for such batches, per tile of DQ_SL slots x DQ_PT points: the
-// slot-major flags are staged in LDS, each thread keeps four slots'
-// thresholds in registers and decides their pairs from D read point-major,
-// writes the next round's point-major "not sampled" bytes A, and the
-// changed flags (and the round index of pairs decided while sampled) go
-// back slot-major.  Per slot the tile's counts of undecided sampled,
-// undecided exact and newly accepted pairs go to the slot's partial-list
-// area (consumed by k_finish), so no atomics are needed.
+// slot-major flags are staged in LDS as one word per (group of four slots,
+// point), each thread keeps its group's thresholds in registers and decides
+// the group's four pairs of a point at once from D read point-major, writes
+// the next round's point-major "not sampled" bytes A, and the changed flags
+// (and the round index of pairs decided while sampled) go back slot-major.
+// Per slot the tile's counts of undecided sampled, undecided exact and newly
+// accepted pairs go to the slot's partial-list area (consumed by k_finish),
+// so no atomics are needed.
 constexpr int DQ_SL = 64, DQ_PT = 512;
+constexpr int DQ_G = DQ_SL / 4;   // groups of four slots
+constexpr int DQ_TS = DQ_PT + 4;  // LDS row stride in words
 __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, const uint32_t *__restrict__ D,
                                                   uint8_t *__restrict__ A, int32_t nqp, Bufs B, Geometry G,
                                                   int32_t cur) {
-  // rows padded to an odd number of 4-byte words: the 64 lanes of a wave
-  // read 64 different rows at one column without bank conflicts
-  __shared__ __align__(16) uint8_t ft[DQ_SL][DQ_PT + 4];
-  const int64_t n = G.n, m = G.m;
+  // ft[g][p]: byte j holds the flag of slot s0 + 4 g + j at point i0 + p.
+  // The row stride (DQ_PT + 4 words) puts the 16 groups x 4 points that a
+  // wave reads at once in different banks.
+  __shared__ __align__(16) uint32_t ft[DQ_G][DQ_TS];
+  const int64_t n = G.n;
   const int ns = G.nslots;
   const int64_t ngroups = (nqp + DQ_SL - 1) / DQ_SL;
   const int64_t nwork = ngroups * ((n + DQ_PT - 1) / DQ_PT);
@@ -2164,60 +2168,81 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
   }
   __syncthreads();
   if (!sany) return;  // every slot of the tile is idle or sparse
-  // stage the flags of the running slots (others: "not sampled"), four
-  // bytes per lane when the rows allow 4-byte loads
+  static_assert(FL_EXACT == 1 && FL_ACC == 2 && FL_DISC == 4, "flag bits 0, 1, 2; bit 7 marks a change");
+  // stage the flags of the running slots (others: discarded, "not sampled")
   if ((n & 3) == 0 && pts == DQ_PT) {
-    // whole tile, 4-byte words: each wave loads its rows' words together
-    constexpr int RW = DQ_SL / (NT / kWave), WPR = DQ_PT / 4 / kWave;  // rows per wave, words per lane and row
-    uint32_t wv[RW][WPR];
+    // whole tile, 4-byte words: each thread reads the same word (four
+    // points) of its group's four rows -- the lanes of a wave take
+    // consecutive words of one row -- and writes the four points' words,
+    // the 4 x 4 bytes transposed
+    constexpr int QW = DQ_PT / 4, ITEMS = DQ_G * QW / NT;
+    static_assert(DQ_G * QW % NT == 0 && QW % kWave == 0, "whole items per thread, one group per wave load");
+    uint32_t wv[ITEMS][4];
 #pragma unroll
-    for (int j = 0; j < RW; ++j) {
-      const int r = threadIdx.x / kWave + j * (NT / kWave);
-      const uint32_t *src = reinterpret_cast<const uint32_t *>(B.fl + (int64_t)(srun[r] ? s0 + r : 0) * n + i0);
-      static_assert(FL_DISC == 4, "four FL_DISC bytes");
+    for (int it = 0; it < ITEMS; ++it) {
+      const int idx = threadIdx.x + it * NT, g = idx / QW, c = idx % QW;
 #pragma unroll
-      for (int q = 0; q < WPR; ++q) wv[j][q] = srun[r] ? src[lane_id() + q * kWave] : 0x04040404u;
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * g + j;
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(B.fl + (int64_t)(srun[r] ? s0 + r : 0) * n + i0);
+        wv[it][j] = srun[r] ? src[c] : 0x04040404u;
+      }
     }
 #pragma unroll
-    for (int j = 0; j < RW; ++j) {
-      const int r = threadIdx.x / kWave + j * (NT / kWave);
+    for (int it = 0; it < ITEMS; ++it) {
+      const int idx = threadIdx.x + it * NT, g = idx / QW, c = idx % QW;
+      uint32_t o[4];
 #pragma unroll
-      for (int q = 0; q < WPR; ++q) *reinterpret_cast<uint32_t *>(&ft[r][4 * (lane_id() + q * kWave)]) = wv[j][q];
+      for (int e = 0; e < 4; ++e)
+        o[e] = ((wv[it][0] >> (8 * e)) & 0xFFu) | (((wv[it][1] >> (8 * e)) & 0xFFu) << 8) |
+               (((wv[it][2] >> (8 * e)) & 0xFFu) << 16) | (((wv[it][3] >> (8 * e)) & 0xFFu) << 24);
+      *reinterpret_cast<uint4 *>(&ft[g][4 * c]) = make_uint4(o[0], o[1], o[2], o[3]);
     }
   } else {
     for (int r = threadIdx.x / kWave; r < DQ_SL; r += NT / kWave) {
       const bool run = srun[r] != 0;
       const uint8_t *src = B.fl + (int64_t)(run ? s0 + r : 0) * n + i0;
-      for (int p = lane_id(); p < DQ_PT; p += kWave) ft[r][p] = (run && p < pts) ? src[p] : (uint8_t)FL_DISC;
+      uint8_t *dst = reinterpret_cast<uint8_t *>(&ft[r >> 2][0]) + (r & 3);
+      for (int p = lane_id(); p < DQ_PT; p += kWave) dst[4 * p] = (run && p < pts) ? src[p] : (uint8_t)FL_DISC;
     }
   }
   __syncthreads();
-  // Each thread takes four consecutive slots of the tile (one 16-byte load
-  // of their sums and one 4-byte store of their "not sampled" bytes per
-  // point; nqp is a multiple of 16) and every DQ_P-th point.
-  constexpr int DQ_G = DQ_SL / 4, DQ_P = NT / DQ_G;
-  static_assert(DQ_SL % 4 == 0 && NT % DQ_G == 0, "four slots per thread");
+  // Each thread takes one group of four consecutive slots (one 16-byte
+  // load of their sums, one flag word and one 4-byte store of their "not
+  // sampled" bytes per point; nqp is a multiple of 16) and every DQ_P-th
+  // point.  Per-slot counts are kept as bytes of one word (at most
+  // DQ_PT / DQ_P = 32 per thread, 128 after the sum over a wave's four
+  // threads of a group).
+  constexpr int DQ_P = NT / DQ_G;
+  static_assert(NT % DQ_G == 0 && DQ_PT / DQ_P * (kWave / DQ_G) < 256, "byte counters");
   __shared__ int cnt[NT / kWave][DQ_SL][3];
-  const int c4 = 4 * (threadIdx.x % DQ_G);  // first of this thread's slots within the tile
-  bool run[4];
+  const int g = threadIdx.x % DQ_G, c4 = 4 * g;  // this thread's group; its first slot within the tile
+  uint32_t runm = 0;  // bit 0 of byte j: slot c4 + j runs
 #pragma unroll
-  for (int j = 0; j < 4; ++j) run[j] = srun[c4 + j] != 0;
-  int c_act[4] = {0, 0, 0, 0}, c_xa[4] = {0, 0, 0, 0}, c_acc[4] = {0, 0, 0, 0};
+  for (int j = 0; j < 4; ++j) runm |= (srun[c4 + j] ? 1u : 0u) << (8 * j);
+  uint32_t c_act = 0, c_xa = 0, c_acc = 0;  // byte j: slot c4 + j
   if (s0 + c4 < nqp) {
     // the decisions as thresholds on the sums (k_select_merge_pm derives them
-    // from U, L1, L2 with the FP64 bounds), so no pair needs a division
-    // (named fields, picked by arithmetic below: a select between two
-    // array elements would become an indexed load from scratch memory)
+    // from U, L1, L2 with the FP64 bounds), so no pair needs a division.  A
+    // threshold t in [-1, 2^32) becomes the 32-bit bound min(max(t + 1, 0),
+    // 2^32 - 1): with every sum below 2^32 - 1, S > t holds exactly when
+    // S >= bound, and S <= t exactly when S < bound.
+    auto bound = [](int64_t t) -> uint32_t {
+      return t + 1 <= 0 ? 0u : (t + 1 >= 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)(t + 1));
+    };
+    // (named fields, picked by arithmetic below: a select between two array
+    // elements would become an indexed load from scratch memory)
     struct Thr {
-      int64_t disc, acc, xdisc, xacc;
+      uint32_t disc, acc, xdisc, xacc;  // discard: S >= disc; accept: S < acc (sampled / exact pairs)
     } th[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const Slot &sj = slots[run[j] ? s0 + c4 + j : 0];
-      th[j].disc = run[j] ? sj.sthr[0] : 0;
-      th[j].acc = run[j] ? sj.sthr[1] : 0;
-      th[j].xdisc = run[j] ? sj.sthr[2] : 0;
-      th[j].xacc = run[j] ? sj.sthr[3] : 0;
+      const bool rj = (runm >> (8 * j)) & 1u;
+      const Slot &sj = slots[rj ? s0 + c4 + j : 0];
+      th[j].disc = rj ? bound(sj.sthr[0]) : 0u;
+      th[j].acc = rj ? bound(sj.sthr[1]) : 0u;
+      th[j].xdisc = rj ? bound(sj.sthr[2]) : 0u;
+      th[j].xacc = rj ? bound(sj.sthr[3]) : 0u;
     }
     // DQ_B points per batch: their sums are loaded together, so the loads'
     // latency is paid once per batch
@@ -2230,6 +2255,7 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
         sv[b] = *reinterpret_cast<const uint4 *>(D + (i0 + p) * nqp + s0 + c4);
       }
     };
+    constexpr uint32_t B0 = 0x01010101u;
     load_batch(threadIdx.x / DQ_G, sn);
     for (int pb = threadIdx.x / DQ_G; pb < pts; pb += DQ_P * DQ_B) {
       uint4 sv[DQ_B];
@@ -2240,52 +2266,52 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
       for (int b = 0; b < DQ_B; ++b) {
         const int p = pb + b * DQ_P;
         if (p >= pts) break;
-        const uint32_t S4[4] = {sv[b].x, sv[b].y, sv[b].z, sv[b].w};
-        uint32_t aw = 0;
+        uint32_t f = ft[g][p];
+        // bit 0 of byte j: the pair is undecided (running, neither accepted nor discarded)
+        const uint32_t und = runm & ~((f >> 1) | (f >> 2)) & B0;
+        if (und) {
+          const uint32_t S4[4] = {sv[b].x, sv[b].y, sv[b].z, sv[b].w};
+          uint32_t dm = 0, am = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          uint8_t f = ft[c4 + j][p];
-          if (run[j] && !(f & (FL_ACC | FL_DISC))) {
-            const int64_t xm = -(int64_t)(f & FL_EXACT);  // all ones for an exact pair
-            const int64_t tdisc = th[j].disc ^ ((th[j].disc ^ th[j].xdisc) & xm);
-            const int64_t tacc = th[j].acc ^ ((th[j].acc ^ th[j].xacc) & xm);
-            const bool exact = xm != 0;
-            const int64_t S = S4[j];
-            if (S > tdisc) {
-              f |= FL_DISC | 0x80;
-            } else if (S <= tacc) {
-              f |= FL_ACC | 0x80;
-              ++c_acc[j];
-            } else if (exact) {
-              ++c_xa[j];
-            } else {
-              ++c_act[j];
-            }
-            ft[c4 + j][p] = f;
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t xm = 0u - ((f >> (8 * j)) & 1u);  // all ones for an exact pair
+            const uint32_t td = th[j].disc ^ ((th[j].disc ^ th[j].xdisc) & xm);
+            const uint32_t ta = th[j].acc ^ ((th[j].acc ^ th[j].xacc) & xm);
+            const bool dj = S4[j] >= td;
+            dm |= (dj ? 1u : 0u) << (8 * j);
+            am |= ((!dj && S4[j] < ta) ? 1u : 0u) << (8 * j);
           }
-          aw |= ((run[j] && (f & 0x7F) == 0) ? 0u : 1u) << (8 * j);
+          dm &= und;
+          am &= und;
+          const uint32_t rest = und & ~dm & ~am, ex = f & B0;
+          c_acc += am;
+          c_xa += rest & ex;
+          c_act += rest & ~ex;
+          if (dm | am) {
+            f |= (dm << 2) | (am << 1) | ((dm | am) << 7);
+            ft[g][p] = f;
+          }
         }
-        *reinterpret_cast<uint32_t *>(A + (i0 + p) * nqp + s0 + c4) = aw;
+        // "not sampled" next round: not running, or any flag set (bits 0..6)
+        const uint32_t nz = (((f & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) >> 7) & B0;
+        *reinterpret_cast<uint32_t *>(A + (i0 + p) * nqp + s0 + c4) = nz | (~runm & B0);
       }
     }
   }
-  // per wave, the lanes with the same slots (DQ_G apart) add their counts
+  // per wave, the lanes with the same group (DQ_G apart) add their counts
   static_assert(kWave == 4 * DQ_G, "four lanes of a wave share a slot group");
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-#pragma unroll
-    for (int o = DQ_G; o < kWave; o <<= 1) {
-      c_act[j] += __shfl_xor(c_act[j], o);
-      c_xa[j] += __shfl_xor(c_xa[j], o);
-      c_acc[j] += __shfl_xor(c_acc[j], o);
-    }
+  for (int o = DQ_G; o < kWave; o <<= 1) {
+    c_act += (uint32_t)__shfl_xor((int)c_act, o);
+    c_xa += (uint32_t)__shfl_xor((int)c_xa, o);
+    c_acc += (uint32_t)__shfl_xor((int)c_acc, o);
   }
   if (lane_id() < DQ_G) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      cnt[threadIdx.x / kWave][c4 + j][0] = c_act[j];
-      cnt[threadIdx.x / kWave][c4 + j][1] = c_xa[j];
-      cnt[threadIdx.x / kWave][c4 + j][2] = c_acc[j];
+      cnt[threadIdx.x / kWave][c4 + j][0] = (int)((c_act >> (8 * j)) & 0xFFu);
+      cnt[threadIdx.x / kWave][c4 + j][1] = (int)((c_xa >> (8 * j)) & 0xFFu);
+      cnt[threadIdx.x / kWave][c4 + j][2] = (int)((c_acc >> (8 * j)) & 0xFFu);
     }
   }
   __syncthreads();
@@ -2307,8 +2333,9 @@ __global__ __launch_bounds__(NT) void k_decide_pm(Slot *__restrict__ slots, cons
   for (int r = threadIdx.x / kWave; r < DQ_SL; r += NT / kWave) {
     const int s = s0 + r;
     if (s >= ns) break;
+    const uint8_t *row = reinterpret_cast<const uint8_t *>(&ft[r >> 2][0]) + (r & 3);
     for (int p = lane_id(); p < pts; p += kWave) {
-      const uint8_t f = ft[r][p];
+      const uint8_t f = row[4 * p];
       if (!(f & 0x80)) continue;
       const int64_t off = (int64_t)s * n + i0 + p;
       B.fl[off] = f & 0x7F;
