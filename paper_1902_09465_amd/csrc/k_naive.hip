@@ -701,8 +701,47 @@ __global__ __launch_bounds__(256) void k_round_seq_u8(const Slot *__restrict__ s
   v4i acc[XWA][4];
   gemm_u8_tile<MET, PF, BK_EXACT, XWA, true>(QS, (int64_t)nqp, XS, q0, p0, pend, kp, smem, acc, kb, ke, t0, t1);
   uint64_t my_pairs = 0;
-  if (exact) {
-    // pairs made exact: the undecided sampled ones (flag 0), marked here in
+  if (exact && (n & 15) == 0 && p0 + NBP <= n) {
+    // pairs made exact: the undecided sampled ones (flag 0).  A whole tile
+    // with 16-byte aligned flag rows: each thread takes 32 consecutive
+    // points of one query (four threads per row of the tile), reads their
+    // flags and round bytes as 16-byte words, and rewrites the words that
+    // hold a zero flag (flag FL_EXACT, round cur - 1; with implicit sets
+    // every pair is undecided and nothing is read)
+    static_assert(XQ * NBP == 256 * 32, "32 points of one query per thread");
+    static_assert(FL_EXACT == 1, "a zero byte becomes FL_EXACT by or-ing in its bit 0");
+    const int r = threadIdx.x >> 2;
+    if (take[r]) {
+      const int64_t off = (q0 + r) * n + p0 + 32 * (threadIdx.x & 3);
+      const uint32_t rep = 0x01010101u * (impl ? 0u : (uint32_t)(uint8_t)(cur - 1));
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint4 fw = impl ? make_uint4(0u, 0u, 0u, 0u) : *reinterpret_cast<const uint4 *>(B.fl + off + 16 * h);
+        const uint32_t fv[4] = {fw.x, fw.y, fw.z, fw.w};
+        uint32_t zm[4], any = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {  // bit 7 of each zero byte
+          zm[e] = ~((((fv[e] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | fv[e])) & 0x80808080u;
+          any |= zm[e];
+          my_pairs += (uint64_t)__popc(zm[e]);
+        }
+        if (any) {
+          const uint4 rw = impl ? make_uint4(0u, 0u, 0u, 0u) : *reinterpret_cast<const uint4 *>(B.ri + off + 16 * h);
+          const uint32_t rv[4] = {rw.x, rw.y, rw.z, rw.w};
+          uint32_t nf[4], nr[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint32_t mk = (zm[e] >> 7) * 0xFFu;  // 0xFF in each zero byte
+            nf[e] = fv[e] | (zm[e] >> 7);            // FL_EXACT
+            nr[e] = (rv[e] & ~mk) | (rep & mk);
+          }
+          *reinterpret_cast<uint4 *>(B.fl + off + 16 * h) = make_uint4(nf[0], nf[1], nf[2], nf[3]);
+          *reinterpret_cast<uint4 *>(B.ri + off + 16 * h) = make_uint4(nr[0], nr[1], nr[2], nr[3]);
+        }
+      }
+    }
+  } else if (exact) {
+    // (the last, partial tile, or flag rows not 16-byte aligned) marked in
     // the fragment layout (sixteen consecutive points of one query per lane
     // group), all flag loads of a fragment row in flight together
 #pragma unroll

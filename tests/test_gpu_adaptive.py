@@ -700,14 +700,15 @@ def test_shared_sequence_gather_in_parts(P, orc, data):
 
 @pytest.mark.parametrize("m,sampling,data", [(1001, 3, "gmm"), (1001, 2, "gmm"), (8191, 3, "hard")])
 def test_shared_sequence_unaligned_rows(P, orc, m, sampling, data):
-    """A borrowed point matrix that starts 3 bytes past a 16-byte boundary,
-    with odd m: the point rows start at every offset modulo 16, the first
-    row's leading word and the last row's trailing word reach outside the
-    matrix (the bytes around it are 0xEE, so a byte read from there would
-    change the sums).  The staged gather copies each row as the aligned words
-    that cover it.  At m = 8191 on uniform rows every query reaches the exact
-    round, so all three parts of the gather run.  Every query's set and
-    statistics equal the oracle's."""
+    """A borrowed point matrix that starts 3 bytes past a 16-byte boundary
+    (the DB takes an aligned copy of it; the bytes around it are 0xEE, so a
+    copy that took any of them would change the sums), with odd m: the point
+    rows start at every offset modulo 16 and the last row's trailing word
+    reaches past the matrix.  The staged gather copies each row as the
+    aligned words that cover it, the bytes past the matrix one by one.  At
+    m = 8191 on uniform rows every query reaches the exact round, so all
+    three parts of the gather run.  Every query's set and statistics equal
+    the oracle's."""
     n, nq, k = (3001, 40, 5) if m == 1001 else (1500, 40, 5)
     if data == "hard":
         g = rng(4244)
