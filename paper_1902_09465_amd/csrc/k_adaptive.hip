@@ -1205,7 +1205,10 @@ __global__ __launch_bounds__(NT) void k_seq_gather_f32(const float *__restrict__
 // each boundary: out[b * ostride + r] = sum_{t < T'_b} S[r][t]^2 for b < nb.
 // The boundary T'_{R+1} = m (sampling without replacement) is the full-row
 // norm, copied from `full` (the points' or queries' norms of the naive
-// scan) instead of summed.  One wave per row.
+// scan) instead of summed.  One wave per row.  When the summed boundaries'
+// words fit NRW words per lane (up to 4 KB of a row), a lane loads all of
+// its words at once and each boundary's sum is taken from their squares
+// in registers; longer ranges take one boundary at a time.
 __global__ __launch_bounds__(NT) void k_seq_norms(const int8_t *__restrict__ S, int64_t rows, int64_t kp,
                                                   const Sched *__restrict__ sc, int32_t nb, int64_t m,
                                                   const int32_t *__restrict__ full, int32_t *__restrict__ out,
@@ -1213,19 +1216,55 @@ __global__ __launch_bounds__(NT) void k_seq_norms(const int8_t *__restrict__ S, 
                                                   const int32_t *__restrict__ need) {
   // boundaries b_lo <= b < min(b_hi, nb), continuing from boundary b_lo - 1
   if (need && *need == 0) return;
+  constexpr int NRW = 16;
   const int lane = lane_id();
   const int64_t nw = (int64_t)gridDim.x * (NT / kWave);
+  // boundaries [bs, bx) are summed; R + 1 (the last), when below be, is copied
+  const int bs = std::max(1, (int)b_lo), be = min((int)b_hi, (int)nb), bx = min(be, sc->R + 1);
+  // words [wa, wz) of the summed boundaries: T'_{b-1} is a multiple of 4, and
+  // bytes past the last sample are zero
+  const int64_t wa = bs < bx ? seq_boundary(sc, bs - 1, m) / 4 : 0;
+  const int64_t wz = bs < bx ? (seq_boundary(sc, bx - 1, m) + 3) / 4 : 0;
+  const bool held = wz - wa <= (int64_t)kWave * NRW;
+  if (bs >= bx) {  // nothing to sum: boundary 0 and the full-row boundary at most, one thread per row
+    for (int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x; r < rows; r += (int64_t)gridDim.x * NT) {
+      if (b_lo <= 1) out[r] = 0;
+      if (bs <= bx && bx < be) out[(int64_t)bx * ostride + r] = full[r];
+    }
+    return;
+  }
   for (int64_t r = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
     const uint32_t *row = reinterpret_cast<const uint32_t *>(S + r * kp);
     int32_t run = b_lo > 1 ? out[(int64_t)(b_lo - 1) * ostride + r] : 0;
     if (lane == 0 && b_lo <= 1) out[r] = 0;
-    for (int b = std::max(1, b_lo); b < min(b_hi, nb); ++b) {
+    if (held) {
+      // the squares of word wa + lane + 64 j (one signed 4-byte dot product
+      // each), then each boundary's sum over [wa, T'_b) from them
+      int32_t sq[NRW];
+#pragma unroll
+      for (int j = 0; j < NRW; ++j) {
+        const int32_t w = (int32_t)wa + lane + kWave * j;
+        const int32_t v = w < (int32_t)wz ? (int32_t)row[w] : 0;
+        sq[j] = __builtin_amdgcn_sdot4(v, v, 0, false);
+      }
+      const int32_t base = run;
+      for (int b = bs; b < bx; ++b) {
+        const int32_t w1 = (int32_t)((seq_boundary(sc, b, m) + 3) / 4);
+        int32_t part = 0;
+#pragma unroll
+        for (int j = 0; j < NRW; ++j) part += ((int32_t)wa + lane + kWave * j < w1) ? sq[j] : 0;
+        for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o);
+        run = base + part;
+        if (lane == 0) out[(int64_t)b * ostride + r] = run;
+      }
+      if (bs <= bx && bx < be && lane == 0) out[(int64_t)bx * ostride + r] = full[r];  // bx = R + 1: all m coordinates
+      continue;
+    }
+    for (int b = bs; b < be; ++b) {
       if (b == sc->R + 1) {  // all m coordinates
         if (lane == 0) out[(int64_t)b * ostride + r] = full[r];
         continue;
       }
-      // words of samples [T'_{b-1}, T'_b): T'_{b-1} is a multiple of 4, and
-      // bytes past the last sample are zero
       const int64_t w0 = seq_boundary(sc, b - 1, m) / 4, w1 = (seq_boundary(sc, b, m) + 3) / 4;
       int32_t part = 0;
       for (int64_t w = w0 + lane; w < w1; w += kWave) {
