@@ -1577,8 +1577,8 @@ __global__ __launch_bounds__(NT) void k_select_partial(Slot *__restrict__ slots,
 // the kept set P is exactly the points without a discard flag.  Needs
 // k + 1 <= 64 (the wave selection below).  A tile reads FS_SL * 4 bytes of
 // each point's line of D: the staging is bound by the number of lines a
-// block touches (4 slots: 173 us per launch for the staging alone on the
-// batched-integer workload, 8 slots: 126 us, 16 slots: 117 us), the
+// block touches (per launch over 100,000 points x 1,024 slots, the staging
+// alone: 4 slots 173 us, 8 slots 126 us, 16 slots 117 us), the
 // selections by the vector ALU (111 us without the loads), and the two
 // overlap only across blocks resident on a CU together.  Per launch with
 // both: 4 slots 197 us, 8 slots 174 us, 16 slots 204 us (two 1024-thread
