@@ -26,6 +26,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -89,11 +90,18 @@ struct knn_session_s {
   std::atomic<bool> stop{false};
   std::atomic<int> failed{0};
   std::string fail_msg;
+  // KNN_SESSION_FAIL_UPLOAD=j (tests of the failure path): the upload of
+  // the session's request number j (counted from 0 over all its DBs) fails
+  // as a device copy would, with the batch's earlier requests already in
+  // the ring; -1 (unset): never
+  int64_t fail_upload = -1;
+  std::atomic<int64_t> uploads{0};
 };
 
 namespace knn {
 
-static int upload(DbEngine &D, std::vector<Request *> &batch, std::string &err) {
+static int upload(DbEngine &D, std::vector<Request *> &batch, std::string &err, int64_t fail_at,
+                  std::atomic<int64_t> &uploads) {
   const int64_t m = D.db->m;
   const int elem = D.db->dtype == KNN_U8 ? 1 : 4;
   auto ok = [&](hipError_t e, const char *what) {
@@ -104,6 +112,10 @@ static int upload(DbEngine &D, std::vector<Request *> &batch, std::string &err) 
   // every host source below (the request's query and descriptor, nq_host)
   // stays valid until the single synchronisation at the end of the batch
   for (Request *r : batch) {
+    if (fail_at >= 0 && uploads.fetch_add(1) >= fail_at) {
+      err = "upload query: injected failure (KNN_SESSION_FAIL_UPLOAD)";
+      return KNN_EDEVICE;
+    }
     const int64_t slot = D.submitted % D.qcap;
     QDesc &d = r->dd;
     d = r->d;
@@ -183,9 +195,12 @@ static void db_loop(knn_session_s *S, DbEngine *Dp) {
     }
     if (!batch.empty()) {
       const int64_t before = D.submitted;
-      if (upload(D, batch, err) != KNN_OK) {
-        // the requests that reached the ring are failed there; the rest here
+      if (upload(D, batch, err, S->fail_upload, S->uploads) != KNN_OK) {
+        // the requests that reached the ring are failed there; the rest here.
+        // Copies already queued read the requests' host queries: wait for
+        // them (their own errors aside) before a poll may free a request.
         const int64_t placed = D.submitted - before;
+        (void)hipStreamSynchronize(D.st);
         fail_all(S, D, err);
         std::lock_guard<std::mutex> lk(S->mu);
         for (size_t j = (size_t)placed; j < batch.size(); ++j) {
@@ -249,6 +264,7 @@ int knn_session_create(size_t hbm_budget_bytes, knn_session *out) {
   if (hbm_budget_bytes < ((size_t)1 << 20)) return fail(KNN_EINVAL, "budget below 1 MiB");
   knn_session_s *S = new knn_session_s();
   S->budget = hbm_budget_bytes;
+  if (const char *e = std::getenv("KNN_SESSION_FAIL_UPLOAD")) S->fail_upload = std::atoll(e);
   *out = S;
   return KNN_OK;
 }
@@ -320,12 +336,14 @@ int knn_session_submit(knn_session S, int32_t db_id, const void *host_query, int
   int rc = make_qdesc(db, k, *p, r->d, r->sc);
   if (rc != KNN_OK) return rc;
   if (r->d.kh > kSessionMaxKH) return fail(KNN_EINVAL, "session requests need k + h <= 512");
-  if (S->failed.load()) return fail(KNN_EDEVICE, "session failed: " + S->fail_msg);
   const size_t bytes = (size_t)db->m * (db->dtype == KNN_U8 ? 1 : 4);
   r->q.assign((const uint8_t *)host_query, (const uint8_t *)host_query + bytes);
   r->db_id = db_id;
   {
     std::lock_guard<std::mutex> lk(S->mu);
+    // (checked under the lock that a failure is marked under: a request
+    // queued after fail_all would never be taken or failed)
+    if (S->failed.load()) return fail(KNN_EDEVICE, "session failed: " + S->fail_msg);
     r->ticket = S->next_ticket++;
     *ticket = r->ticket;
     S->dbs[db_id]->pending.push_back(r.get());

@@ -110,6 +110,50 @@ def test_session_errors(P):
     sess.close()
 
 
+def test_session_upload_failure(P, monkeypatch):
+    """A device copy that fails while a batch is uploaded, forced from the
+    host (KNN_SESSION_FAIL_UPLOAD=1: the upload of the session's second
+    request returns a device error, the first one already in the ring, in
+    the same batch or still running from an earlier one).  Every request
+    ends -- the second and later ones with the error (or, submitted after
+    the failure, refused) -- with no ring entry left on a freed request;
+    later submits are refused and the session closes."""
+    from paper_1902_09465_amd import KnnError
+    monkeypatch.setenv("KNN_SESSION_FAIL_UPLOAD", "1")
+    X, Q = gmm_u8(52, n=3000, m=256, n_centres=3, sigma=30.0, nq=6)
+    db = P.KnnDB(dev(X))
+    sess = P.Session(64 << 20)
+    d = sess.add_db(db)
+    tickets, refused = [], 0
+    for i in range(6):
+        try:
+            tickets.append(sess.submit(d, Q[i], 3))
+        except KnnError:
+            refused += 1
+    t0 = time.time()
+    outcome = []
+    for t in tickets:
+        while True:
+            try:
+                r = sess.poll(t, 3)
+            except KnnError as e:
+                assert e.code == -3, e.code  # KNN_EDEVICE
+                outcome.append("error")
+                break
+            if r is not None:
+                outcome.append("ok")
+                break
+            assert time.time() - t0 < 60, "a request never finished"
+            time.sleep(0.001)
+    # only the first request can have been uploaded: every other one fails
+    assert outcome[1:].count("error") == len(outcome) - 1, outcome
+    assert refused + outcome.count("error") >= 5
+    with pytest.raises(KnnError):
+        sess.submit(d, Q[0], 3)
+    sess.close()
+    db.close()
+
+
 def test_session_serving_dbs_full_size(P, orc):
     """The three serving databases at their full sizes (50,000 x 784 u8;
     500,000 x 256 f32; 2,000,000 x 96 f32) resident in one session with a
